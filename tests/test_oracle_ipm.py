@@ -1,0 +1,266 @@
+"""Pins of the oracle's interior-point method, condensed KKT system,
+preconditioner and PCG (paper sections "KKT stationary conditions",
+"Primal-dual interior-point method", "KKT linear systems", "Krylov methods and
+preconditioners") against closed forms, dense linear algebra, an independent
+bound-constrained optimiser (scipy L-BFGS-B) and invariants."""
+import math
+
+import numpy as np
+import pytest
+import scipy.optimize
+
+from oracle import dft3, ipm
+from paper_2502_04217_amd import workload as wl
+
+
+def _barrier(shape, seed, spread=3.0):
+    return wl.random_barrier(shape, seed, spread)
+
+
+def test_pinv_closed_form_and_D():
+    """P^{-1} P = I blockwise (equation "invprecond1"); D = S1 + S2 + 4 S1 S2
+    (proposition "exprbd"); L1 D^{-1} lies in (0, 1) (equation "11block")."""
+    shape = (4, 4, 4)
+    s1, s2 = _barrier(shape, 1, spread=6.0)
+    rng = np.random.default_rng(2)
+    xb, xz = rng.standard_normal(shape), rng.standard_normal(shape)
+    pb, pz = ipm.P_apply(xb, xz, s1, s2)
+    yb, yz = ipm.Pinv_apply(pb, pz, s1, s2)
+    assert np.abs(yb - xb).max() < 1e-9 * np.abs(xb).max()
+    assert np.abs(yz - xz).max() < 1e-9 * np.abs(xz).max()
+    t1, t2 = _barrier(shape, 3, spread=1.0)     # moderate spread: no cancellation
+    L1, L2 = t1 + t2, t1 - t2
+    D = L1 * (1 + L1) - L2 ** 2
+    assert np.allclose(D, t1 + t2 + 4 * t1 * t2, rtol=1e-12)
+    L1 = s1 + s2
+    D = s1 + s2 + 4 * s1 * s2
+    r = L1 / D
+    assert np.all((r > 0) & (r < 1))
+    # stable form of the (1,1) block
+    assert np.allclose(r, (1 / s1 + 1 / s2) / (1 / s1 + 1 / s2 + 4), rtol=1e-12)
+
+
+def test_preconditioned_operator_structure():
+    """P^{-1} K = [[I + L1 D^{-1}(H - I), 0], [-D^{-1} L2 (H - I), I]]
+    (equation "precond1"), checked on the dense 2n x 2n matrices."""
+    shape = (2, 4, 4)
+    n = 32
+    rng = np.random.default_rng(4)
+    obs = (rng.random(shape) > 0.3).astype(np.float64)
+    s1, s2 = _barrier(shape, 5, spread=2.0)
+    cols = []
+    for i in range(2 * n):
+        e = np.zeros(2 * n); e[i] = 1.0
+        qb, qz = ipm.K_apply(e[:n].reshape(shape), e[n:].reshape(shape), s1, s2, obs)
+        yb, yz = ipm.Pinv_apply(qb, qz, s1, s2)
+        cols.append(np.concatenate([yb.ravel(), yz.ravel()]))
+    PK = np.stack(cols, axis=1)
+    A = dft3.dense_A(shape)
+    Hd = A.T @ np.diag(obs.ravel()) @ A
+    L1, L2 = (s1 + s2).ravel(), (s1 - s2).ravel()
+    D = L1 + 4 * s1.ravel() * s2.ravel()
+    I = np.eye(n)
+    assert np.abs(PK[:n, :n] - (I + np.diag(L1 / D) @ (Hd - I))).max() < 1e-12
+    assert np.abs(PK[:n, n:]).max() < 1e-12
+    assert np.abs(PK[n:, n:] - I).max() < 1e-12
+    assert np.abs(PK[n:, :n] - (-np.diag(L2 / D) @ (Hd - I))).max() < 1e-12
+
+
+def test_condensed_step_equals_dense_newton_on_kktmu():
+    """The condensed system with the oracle's right-hand side gives the same
+    (d beta, d z) as a dense Newton step on the full perturbed KKT system
+    (equation "kktmu", all eight blocks).  The Jacobian is formed by central
+    differences, exact for this quadratic residual."""
+    shape = (2, 4, 4)
+    n = 32
+    w = wl.make_workload(shape, n_freq=4, amplitude="normal", snr_db=10.0,
+                         half_width=0, period=2, seed=3)
+    obs = w.observed.astype(np.float64)
+    xi = dft3.xi(w.signal, obs)
+    lam = 0.1 * float(np.abs(xi).max())
+    rng = np.random.default_rng(8)
+    beta = 0.3 * rng.standard_normal(shape)
+    z = np.abs(beta) + rng.uniform(0.1, 1.0, shape)
+    nu1 = rng.uniform(0.1, 1.0, shape) * lam
+    nu2 = rng.uniform(0.1, 1.0, shape) * lam
+    st = ipm.IPMState(beta, z, nu1, nu2)
+    s1, s2 = z + beta, z - beta
+    sigma = 0.1
+    mu = float((s1 * nu1).sum() + (s2 * nu2).sum()) / (2 * n)
+    wvec = np.concatenate([a.ravel() for a in (beta, z, s1, s2, nu1, nu2, nu1, nu2)])
+    F = ipm.kktmu_residual(wvec, xi, lam, obs, sigma * mu)
+    J = np.zeros((8 * n, 8 * n))
+    for i in range(8 * n):
+        e = np.zeros(8 * n); e[i] = 1.0
+        J[:, i] = (ipm.kktmu_residual(wvec + e, xi, lam, obs, sigma * mu)
+                   - ipm.kktmu_residual(wvec - e, xi, lam, obs, sigma * mu)) / 2.0
+    dw = np.linalg.solve(J, -F)
+    Hb = dft3.apply_H(beta, obs)
+    rb, rz = ipm.newton_rhs(st, Hb, xi, lam, sigma, mu)
+    sig1, sig2 = nu1 / s1, nu2 / s2
+    # dense condensed solve
+    A = dft3.dense_A(shape)
+    Hd = A.T @ np.diag(obs.ravel()) @ A
+    L1, L2 = np.diag((sig1 + sig2).ravel()), np.diag((sig1 - sig2).ravel())
+    Kd = np.block([[Hd + L1, L2], [L2, L1]])
+    d = np.linalg.solve(Kd, np.concatenate([rb.ravel(), rz.ravel()]))
+    assert np.abs(d[:n] - dw[:n]).max() < 1e-10
+    assert np.abs(d[n:] - dw[n:2 * n]).max() < 1e-10
+    # dual recovery matches the Newton step's nu blocks
+    _, _, dnu1, dnu2 = ipm.recover_dnu(st, d[:n].reshape(shape), d[n:].reshape(shape),
+                                       sig1, sig2, sigma, mu)
+    assert np.abs(dnu1.ravel() - dw[6 * n:7 * n]).max() < 1e-9
+    assert np.abs(dnu2.ravel() - dw[7 * n:]).max() < 1e-9
+    # and PCG on the matrix-free K reaches the same direction
+    res = ipm.pcg(lambda pb, pz: ipm.K_apply(pb, pz, sig1, sig2, obs),
+                  lambda qb, qz: ipm.Pinv_apply(qb, qz, sig1, sig2), rb, rz, rtol=1e-14, maxit=400)
+    assert np.abs(res.xb.ravel() - d[:n]).max() < 1e-9
+    assert np.abs(res.xz.ravel() - d[n:]).max() < 1e-9
+
+
+def test_no_missing_closed_form_and_one_cg_step():
+    """Nothing missing: H = I, K = P, so PCG converges in one iteration and
+    the LASSO solution is soft(A^T b, lambda)."""
+    shape = (8, 8, 8)
+    w = wl.make_workload(shape, n_freq=20, amplitude="normal", snr_db=15.0,
+                         half_width=-1, period=2, seed=4)
+    assert w.observed.min() == 1
+    lam = ipm.lambda_rule(w.signal, w.observed, 0.1)
+    res = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-11))
+    assert res.converged
+    # exact arithmetic gives one step; at tight tolerances round-off in the
+    # large barrier diagonals can force one more
+    assert max(res.cg_iters) <= 2
+    exact = ipm.soft(dft3.xi(w.signal, w.observed), lam)
+    assert np.abs(res.state.beta - exact).max() < 1e-8 * np.abs(exact).max()
+    s1, s2 = wl.random_barrier(shape, 3, spread=3.0)
+    obs = np.ones(shape)
+    rng = np.random.default_rng(1)
+    out = ipm.pcg(lambda pb, pz: ipm.K_apply(pb, pz, s1, s2, obs),
+                  lambda qb, qz: ipm.Pinv_apply(qb, qz, s1, s2),
+                  rng.standard_normal(shape), rng.standard_normal(shape), rtol=1e-9)
+    assert out.iters == 1 and out.res_hist[1] < 1e-9 * out.res_hist[0]
+
+
+def test_large_lambda_gives_zero():
+    w = wl.grid16(2)
+    lam = 1.01 * float(np.abs(dft3.xi(w.signal, w.observed)).max())
+    res = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-10))
+    assert res.converged
+    assert np.abs(res.state.beta).max() < 1e-8
+
+
+def test_noiseless_planted_closed_form():
+    """Noiseless planted spectrum with the right support S and signs:
+    beta*_S = beta_S - lam (N_S^T N_S)^{-1} sign(beta_S), zero elsewhere,
+    certified by |g_i| <= lam off S (N_S = columns S of M_perp)."""
+    shape = (8, 8, 8)
+    w = wl.make_workload(shape, n_freq=12, amplitude="lognormal", snr_db=np.inf,
+                         half_width=1, period=4, seed=6)
+    btrue = dft3.waves_to_beta(shape, w.wave_k, w.wave_c)
+    A = dft3.dense_A(shape)
+    obs = w.observed.ravel() == 1
+    Mp = A[obs]
+    S = np.nonzero(btrue.ravel())[0]
+    lam = 0.02
+    NS = Mp[:, S]
+    bS = btrue.ravel()[S] - lam * np.linalg.solve(NS.T @ NS, np.sign(btrue.ravel()[S]))
+    assert np.all(np.sign(bS) == np.sign(btrue.ravel()[S]))
+    closed = np.zeros(A.shape[0]); closed[S] = bS
+    g = Mp.T @ (w.signal.ravel()[obs] - Mp @ closed)
+    off = np.setdiff1d(np.arange(A.shape[0]), S)
+    assert np.abs(g[off]).max() < lam           # certificate holds: closed is optimal
+    res = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-11))
+    assert res.converged
+    assert np.linalg.norm(res.state.beta.ravel() - closed) < 1e-7 * np.linalg.norm(closed)
+
+
+def test_matches_independent_bound_constrained_solver():
+    """Same LASSO solved by scipy's L-BFGS-B on the split beta = u - w,
+    u, w >= 0 (a smooth bound-constrained problem)."""
+    shape = (4, 8, 8)
+    w = wl.make_workload(shape, n_freq=10, amplitude="normal", snr_db=12.0,
+                         half_width=1, period=4, seed=9)
+    A = dft3.dense_A(shape)
+    obs = w.observed.ravel() == 1
+    Mp = A[obs]
+    b = w.signal.ravel()[obs]
+    lam = ipm.lambda_rule(w.signal, w.observed, 0.05)
+    n = A.shape[0]
+
+    def f(v):
+        beta = v[:n] - v[n:]
+        r = Mp @ beta - b
+        g = Mp.T @ r
+        return 0.5 * r @ r + lam * v.sum(), np.concatenate([g + lam, -g + lam])
+
+    out = scipy.optimize.minimize(f, np.zeros(2 * n), jac=True, method="L-BFGS-B",
+                                  bounds=[(0, None)] * (2 * n),
+                                  options=dict(maxiter=20000, ftol=1e-16, gtol=1e-13, maxcor=50))
+    ref = out.x[:n] - out.x[n:]
+    res = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-11))
+    assert res.converged
+    assert np.linalg.norm(res.state.beta.ravel() - ref) < 1e-6 * np.linalg.norm(ref)
+    obj = lambda beta: 0.5 * np.sum((Mp @ beta - b) ** 2) + lam * np.abs(beta).sum()
+    assert obj(res.state.beta.ravel()) <= obj(ref) + 1e-9 * abs(obj(ref))
+
+
+def test_grid16_invariants_and_certificate():
+    """On the 16^3 workload: positivity of s and nu at every iterate, mu
+    decreasing, final LASSO optimality conditions and a vanishing duality gap,
+    and the Sigma pattern of the corollary "convergencespeed" (Lambda_1 large
+    everywhere, Sigma_1 small on I+, Sigma_2 small on I-)."""
+    w = wl.grid16(1)
+    lam = ipm.lambda_rule(w.signal, w.observed)
+    seen = []
+
+    def cb(it, st, res):
+        s1, s2 = st.z + st.beta, st.z - st.beta
+        assert s1.min() > 0 and s2.min() > 0 and st.nu1.min() > 0 and st.nu2.min() > 0
+        seen.append(float(((s1 * st.nu1).sum() + (s2 * st.nu2).sum()) / (2 * s1.size)))
+
+    res = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-10), callback=cb)
+    assert res.converged
+    assert all(b < a for a, b in zip(seen, seen[1:]))
+    cert = ipm.lasso_certificate(res.state.beta, w.signal, w.observed, lam)
+    assert cert.natural_residual < 1e-7
+    assert cert.rel_gap < 1e-6
+    assert cert.max_offsupport_ratio <= 1.0 + 1e-6
+    st = res.state
+    s1, s2 = st.z + st.beta, st.z - st.beta
+    sig1, sig2 = st.nu1 / s1, st.nu2 / s2
+    supp = ipm.support(st.beta, 1e-3)
+    pos = supp & (st.beta > 0)
+    neg = supp & (st.beta < 0)
+    assert pos.any() and neg.any()
+    assert (sig1[pos].max() < 1e-3 * (sig1 + sig2)[pos].min())
+    assert (sig2[neg].max() < 1e-3 * (sig1 + sig2)[neg].min())
+    assert (sig1 + sig2).min() > 1e3
+
+
+def test_limit_condition_number_tiny():
+    """Near the end of the IPM, the spectrum of P^{-1}K approaches
+    {1} U spec(Q*) (proposition "boundskappa"), Q* = (M^T M) on the active set."""
+    shape = (4, 4, 4)
+    w = wl.make_workload(shape, n_freq=4, amplitude="normal", snr_db=30.0,
+                         half_width=0, period=2, seed=12)
+    obs = w.observed.astype(np.float64)
+    lam = ipm.lambda_rule(w.signal, w.observed, 0.05)
+    res = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-12))
+    st = res.state
+    s1, s2 = st.z + st.beta, st.z - st.beta
+    sig1, sig2 = st.nu1 / s1, st.nu2 / s2
+    n = obs.size
+    cols = []
+    for i in range(2 * n):
+        e = np.zeros(2 * n); e[i] = 1.0
+        qb, qz = ipm.K_apply(e[:n].reshape(shape), e[n:].reshape(shape), sig1, sig2, obs)
+        yb, yz = ipm.Pinv_apply(qb, qz, sig1, sig2)
+        cols.append(np.concatenate([yb.ravel(), yz.ravel()]))
+    ev = np.sort(np.linalg.eigvals(np.stack(cols, axis=1)).real)
+    A = dft3.dense_A(shape)
+    Hd = A.T @ np.diag(obs.ravel()) @ A
+    act = np.nonzero(ipm.support(st.beta, 1e-6).ravel())[0]
+    q = np.linalg.eigvalsh(Hd[np.ix_(act, act)])
+    expected = np.sort(np.concatenate([np.ones(2 * n - len(act)), q]))
+    assert np.abs(ev - expected).max() < 1e-4
