@@ -1,0 +1,237 @@
+/* csipm — sparse 3D-DFT recovery by a matrix-free primal-dual interior-point
+ * method on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Kuang, Rao, Montoison, Pacaud, Anitescu, "Recovering sparse DFT
+ * from missing signals via interior point method on GPU" (arXiv 2502.04217).
+ * The library solves
+ *     beta* = argmin_beta 1/2 ||b - M_perp beta||^2 + lambda ||beta||_1
+ * (paper, equation "realopt"), where M_perp are the observed rows of the real
+ * orthogonal operator A = IDFT o B^H that maps the real parametrisation beta
+ * of a conjugate-symmetric spectrum to a real 3D signal (section "Problem
+ * formulation", equations "beta", "v", derivation "map").
+ *
+ * Conventions shared by every entry point
+ *  - Grid: N1 x N2 x N3, each a power of two in [4, 1024]; n = N1*N2*N3.
+ *  - Real-space arrays are row-major [N1][N2][N3] (index j3 fastest).
+ *  - beta-space arrays ("external beta layout") are row-major [N1][N2][N3]
+ *    indexed by the frequency k: beta[k] = v_k for self-conjugate k
+ *    (k == -k mod N), and for the canonical member k of each pair {k, -k}
+ *    beta[k] = sqrt2 Re v_k, beta[-k] = sqrt2 Im v_k, with v the unitary
+ *    3D DFT.  k is canonical iff k3 in [1, N3/2), or k3 in {0, N3/2} and
+ *    k2 in [1, N2/2), or k3, k2 in {0, N/2} and k1 in [1, N1/2).
+ *  - All pointers named d_* are device pointers (HIP, the current device);
+ *    all buffers are owned by the caller and must outlive the context.
+ *  - Work is queued on the HIP stream given at creation.  Calls that return
+ *    host scalars (csipm_lambda_rule, csipm_solve, csipm_get_residuals)
+ *    synchronise that stream; all others are asynchronous.
+ *  - Every call returns a csipm_status: 0 success, > 0 success with a
+ *    warning (the result is usable), < 0 failure (no outputs written).
+ *    csipm_last_error gives a message for the last failure on a context.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef CSIPM_H
+#define CSIPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct csipm_ctx csipm_ctx;
+
+typedef enum {
+  CSIPM_OK = 0,
+  CSIPM_NOT_CONVERGED = 1, /* iteration limit reached; iterate usable          */
+  CSIPM_STALLED = 2,       /* step length collapsed; iterate usable            */
+  CSIPM_FELL_BACK = 3,     /* converged, but some Newton systems fell back to
+                              the paper's preconditioner                       */
+  CSIPM_EINVAL = -1,       /* bad argument (null pointer, size, lambda <= 0)   */
+  CSIPM_ENOMEM = -2,       /* workspace too small                              */
+  CSIPM_EHIP = -3,         /* a HIP runtime call failed                        */
+  CSIPM_ENONFINITE = -4,   /* NaN/Inf in an observed sample or an iterate      */
+  CSIPM_EUNSUPPORTED = -5, /* grid size not supported                          */
+  CSIPM_ESTATE = -6        /* call out of order (e.g. solve before lambda)     */
+} csipm_status;
+
+typedef enum { CSIPM_FP64 = 0, CSIPM_FP32 = 1 } csipm_precision;
+typedef enum { CSIPM_PC_PLAIN = 0, CSIPM_PC_LEARNED = 1 } csipm_pc;
+typedef enum {
+  CSIPM_BETA = 0, CSIPM_Z = 1, CSIPM_NU1 = 2, CSIPM_NU2 = 3,
+  CSIPM_XI = 4,       /* M_perp^T b, fixed at creation                        */
+  CSIPM_DIAG_H = 5,   /* diag(M_perp^T M_perp), fixed at creation             */
+  CSIPM_PC_C = 6      /* current learned correction c (1 = paper's P)          */
+} csipm_var;
+
+/* Interior-point options (paper: "Primal-dual interior-point method"; the
+ * barrier strategy is the library's, the paper leaves it to the IPM).       */
+typedef struct {
+  double tol;          /* stop at rel_kkt <= tol (default 1e-6)               */
+  int max_iter;        /* interior-point iterations (default 200)             */
+  int cg_max;          /* PCG iterations per Newton system (default 500)      */
+  double cg_rtol;      /* relative PCG tolerance cap (default 1e-2); the
+                          tolerance used is min(cg_rtol, 0.1 rel_kkt)          */
+  double cg_atol;      /* absolute floor on the preconditioned residual norm
+                          (default 0; 1e-12 with cg_rtol = 0 reproduces the
+                          paper's rule)                                        */
+  double sigma;        /* centring parameter (default 0.1)                    */
+  double tau;          /* fraction to the boundary (default 0.99)             */
+  int precision;       /* csipm_precision of the Krylov solves               */
+  int pc;              /* csipm_pc                                           */
+  int refine_max;      /* FP32: refinement steps per Newton system (def. 8)  */
+  double refine_inner_rtol; /* FP32: inner PCG relative tolerance (def. 1e-2) */
+} csipm_options;
+
+typedef struct {
+  int status;
+  int ipm_iters;
+  int cg_iters_max;         /* largest PCG count of one Newton system          */
+  long long cg_iters_total; /* sum over Newton systems (inner FP32 + FP64)     */
+  int refine_steps_total;
+  int fallbacks;            /* learned -> plain preconditioner restarts        */
+  double rel_kkt;           /* max(|F_beta|_inf, |F_z|_inf, max s.nu)/(1+|xi|_inf) */
+  double res_beta_inf, res_z_inf, compl_max;
+  double mu;
+  double lambda;
+  double xi_inf;
+  double solve_seconds;
+} csipm_info;
+
+/* One record per interior-point iteration (csipm_get_log). */
+typedef struct {
+  int iter, cg_iters, refine_steps, fell_back;
+  double mu, rel_kkt, alpha;
+} csipm_iter_log;
+
+/* Fills `o` with the defaults listed in csipm_options. */
+void csipm_default_options(csipm_options* o);
+
+/* Device workspace bytes needed for a grid (all precisions and the learned
+ * preconditioner included).  Returns 0 for an unsupported grid. */
+size_t csipm_workspace_bytes(int n1, int n2, int n3);
+
+/* Creates a problem (paper: "Matrix-free operators", equation "xi").
+ *   d_signal    : n doubles, real space; values at missing samples ignored
+ *   d_observed  : n bytes, 1 = observed, 0 = missing; at least one observed
+ *   d_workspace : csipm_workspace_bytes(...) bytes, 256-byte aligned
+ *   hip_stream  : hipStream_t to queue all work on (NULL = default stream)
+ * Computes xi = M_perp^T b (zero-filled signal, r2c 3D DFT, real map) and
+ * diag(M_perp^T M_perp).  Errors: EINVAL, EUNSUPPORTED, ENOMEM,
+ * ENONFINITE (non-finite observed sample), EHIP. */
+csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double* d_signal,
+                          const uint8_t* d_observed, void* d_workspace, size_t workspace_bytes,
+                          void* hip_stream);
+
+/* Sets the penalty lambda > 0 (EINVAL otherwise). */
+csipm_status csipm_set_lambda(csipm_ctx* ctx, double lambda);
+/* Sets lambda = frac * ||M_perp^T b||_inf and returns it (frac > 0). */
+csipm_status csipm_lambda_rule(csipm_ctx* ctx, double frac, double* lambda_out);
+
+/* Runs the interior-point method from the standard starting point
+ * (beta = 0, z = ||xi||_inf, nu1 = nu2 = lambda/2).  `info` may be NULL.
+ * Returns OK, NOT_CONVERGED, STALLED or FELL_BACK, or an error. */
+csipm_status csipm_solve(csipm_ctx* ctx, const csipm_options* opts, csipm_info* info);
+
+/* Copies an iterate or a fixed vector to d_dst (n doubles, external beta
+ * layout). */
+csipm_status csipm_get_iterate(csipm_ctx* ctx, int which, double* d_dst);
+
+/* KKT residual parts of the current iterate (one FP64 apply of H). */
+csipm_status csipm_get_residuals(csipm_ctx* ctx, csipm_info* out);
+
+/* Copies up to max_records per-iteration records of the last solve. */
+csipm_status csipm_get_log(csipm_ctx* ctx, csipm_iter_log* host_buf, int max_records, int* n_records);
+
+/* Single operator applies, for parity tests and external Krylov drivers.
+ * Inputs and outputs are device arrays of n values in the precision given
+ * (double for CSIPM_FP64, float for CSIPM_FP32), beta-space ones in the
+ * external beta layout.  Outputs may not alias inputs.
+ *   apply_A    : x = A beta                     (derivation "map")
+ *   apply_At   : beta = A^T x = B DFT(x)          (adjoint of A)
+ *   apply_H    : y = M_perp^T M_perp beta = A^T D A beta
+ *   apply_K    : [qb; qz] = K [pb; pz], K = [[H + L1, L2], [L2, L1]],
+ *                L1 = S1 + S2, L2 = S1 - S2 (equation "condensedkkt"),
+ *                with the barrier diagonals of csipm_set_barrier
+ *   apply_Pinv : [zb; zz] = P_c^{-1} [rb; rz], P_c = [[C + L1, L2], [L2, L1]]
+ *                (equation "invprecond1"; C = I unless a learned correction
+ *                is active) */
+csipm_status csipm_apply_A(csipm_ctx* ctx, const void* d_beta, void* d_x, int precision);
+csipm_status csipm_apply_At(csipm_ctx* ctx, const void* d_x, void* d_beta, int precision);
+csipm_status csipm_apply_H(csipm_ctx* ctx, const void* d_beta, void* d_y, int precision);
+csipm_status csipm_apply_K(csipm_ctx* ctx, const void* d_pb, const void* d_pz, void* d_qb, void* d_qz,
+                           int precision);
+csipm_status csipm_apply_Pinv(csipm_ctx* ctx, const void* d_rb, const void* d_rz, void* d_zb, void* d_zz,
+                              int precision);
+
+/* Sets the barrier diagonals Sigma_1, Sigma_2 (n doubles each, > 0, external
+ * beta layout) used by apply_K / apply_Pinv (paper, equation "defsigma"). */
+csipm_status csipm_set_barrier(csipm_ctx* ctx, const double* d_sigma1, const double* d_sigma2);
+
+/* Learned preconditioner correction (not in the paper): parameters of the
+ * 4-32-32-1 network, float32, flat layout W1[32][4], b1[32], W2[32][32],
+ * b2[32], w3[32], b3 (1249 values).  Used by csipm_solve when
+ * opts.pc = CSIPM_PC_LEARNED. */
+csipm_status csipm_set_pc_params(csipm_ctx* ctx, const float* d_params, int n_params);
+
+#define CSIPM_MLP_PARAMS 1249
+
+/* Network kernels (stateless; queued on hip_stream; no allocation):
+ *   forward  : c[i] = softplus(MLP(feat[i][0..3])) + 1e-6, i < n_rec
+ *   backward : grad += d/dparams sum_i dc[i] c[i]
+ *   loss_grad: loss_out[0] = sum_i w_i (L1_i^2 + L2_i^2)(u_i - c_i p_i)^2 /
+ *              (c_i L1_i + S12_i)^2 and grad = its parameter gradient
+ *              (overwritten), records rec[i] = {u, p, L1, L2, S12, w}
+ *              (6 floats each)
+ *   adam     : one Adam step (beta1 0.9, beta2 0.999, eps 1e-8; t counted
+ *              from 1) on params with moments m, v (1249 floats each)
+ * feat is [n_rec][4] float; d_scratch must hold csipm_mlp_scratch_bytes(n_rec)
+ * bytes (8-byte aligned); per-record work is reduced in a fixed order, so
+ * results are bitwise reproducible. */
+size_t csipm_mlp_scratch_bytes(int n_rec);
+csipm_status csipm_mlp_forward(const float* d_params, const float* d_feat, float* d_c, int n_rec,
+                               void* hip_stream);
+csipm_status csipm_mlp_backward(const float* d_params, const float* d_feat, const float* d_dc, float* d_grad,
+                                int n_rec, void* d_scratch, size_t scratch_bytes, void* hip_stream);
+csipm_status csipm_mlp_loss_grad(const float* d_params, const float* d_feat, const float* d_rec, int n_rec,
+                                 double* d_loss_out, float* d_grad, void* d_scratch, size_t scratch_bytes,
+                                 void* hip_stream);
+csipm_status csipm_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, int t, float lr,
+                            void* hip_stream);
+
+/* Training-record capture during csipm_solve with the paper's
+ * preconditioner.  At every interior-point iteration (up to max_iters), the
+ * first Krylov direction p = P^{-1} r_0 of the Newton solve and q = K p are
+ * reduced to n_per_iter records at coefficients
+ * idx_j = splitmix64(seed + it * n_per_iter + j) mod n, j < n_per_iter:
+ * d_feat gets [max_iters][n_per_iter][4] features, d_rec gets
+ * [max_iters][n_per_iter][6] records {u = (H p_beta)_i, p_beta_i, L1, L2,
+ * 4 S1 S2, w}, with w = (PCG iterations of that Newton system) /
+ * sum_j (p_beta_j^2 + p_z_j^2).  enable = 0 turns capture off.
+ * csipm_captured returns how many iterations were captured by the last solve
+ * and their PCG counts (cg_counts_host may be NULL). */
+csipm_status csipm_capture(csipm_ctx* ctx, int enable, float* d_feat, float* d_rec, int n_per_iter,
+                           int max_iters, unsigned long long seed);
+csipm_status csipm_captured(csipm_ctx* ctx, int* n_iters, int* cg_counts_host, int max_iters);
+
+/* Features of the current iterate and barrier diagonals, [n][4] float,
+ * coefficients in the external beta layout order. */
+csipm_status csipm_features(csipm_ctx* ctx, float* d_feat);
+
+/* Instrumentation: runs `reps` K-applies (apply_K's kernels on the
+ * internal vectors, with the current barrier diagonals) and returns in
+ * ms_out[0..6] the average duration of each of its seven kernels, timed
+ * with HIP events on the context's stream, in launch order: premix,
+ * axis-1 inverse, axis-2 inverse, axis-3 c2r/mask/r2c, axis-2 forward,
+ * axis-1 forward with the K epilogue, postmix.  Synchronises. */
+#define CSIPM_KAPPLY_PASSES 7
+csipm_status csipm_profile_kapply(csipm_ctx* ctx, int precision, int reps, double* ms_out);
+
+csipm_status csipm_destroy(csipm_ctx* ctx);
+const char* csipm_status_string(int status);
+const char* csipm_last_error(const csipm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSIPM_H */

@@ -1,0 +1,872 @@
+// C-ABI of the csipm library: problem set-up, the interior-point driver, the
+// Krylov drivers and single-operator applies.  Host code; all arithmetic on
+// the vectors happens in the kernels of fft.hip, vec.hip and mlp.hip.
+#include "../../include/csipm.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "csipm_internal.h"
+#include "mlp.h"
+#include "vec.h"
+
+using namespace csipm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+bool pow2_in_range(int v) { return v >= 4 && v <= 1024 && (v & (v - 1)) == 0; }
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  size_t cap;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct csipm_ctx {
+  Grid g{};
+  hipStream_t s = nullptr;
+  std::string err;
+
+  // FP64 interior-point state and Newton system (internal layout)
+  double *beta, *z, *nu1, *nu2, *xi, *hb, *sig1, *sig2, *rhb, *rhz, *dxb, *dxz, *diagH;
+  // FP64 Krylov vectors and FFT work array
+  double *rb, *rz, *zb, *zz, *pb, *pz, *qb, *qz, *work;
+  // FP32 Krylov set
+  float *sig1f, *sig2f, *frb, *frz, *fzb, *fzz, *fpb, *fpz, *fqb, *fqz, *fxb, *fxz, *fwork;
+  // learned correction
+  float *pc_c, *feat, *mlp_params;
+  uint32_t* mask;
+  cx<double>* tw64;
+  cx<float>* tw32;
+  Twiddles<double> T64;
+  Twiddles<float> T32;
+  double *partK, *partV, *scal;
+  int* flags;
+  // host side
+  double* hscal = nullptr;   // pinned: S_COUNT doubles then F_COUNT ints
+  int* hflags = nullptr;
+  double lambda = 0.0;
+  bool have_lambda = false;
+  bool have_params = false;
+  double xi_inf = 0.0;
+  long long nobs = 0;
+  std::vector<csipm_iter_log> log;
+  // capture of training records
+  int cap_enable = 0, cap_per_iter = 0, cap_max = 0, cap_count = 0;
+  float *cap_feat = nullptr, *cap_rec = nullptr;
+  unsigned long long cap_seed = 0;
+  std::vector<int> cap_cg;
+  int last_cg = 0;
+};
+
+namespace {
+
+csipm_status fail(csipm_ctx* c, csipm_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+csipm_status hip_check(csipm_ctx* c, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, CSIPM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+  return CSIPM_OK;
+}
+
+// Copies the device scalar and flag blocks to pinned host memory and waits.
+csipm_status sync_scalars(csipm_ctx* c, const char* where) {
+  hipError_t e = hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, c->s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->hflags, c->flags, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, CSIPM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+  return CSIPM_OK;
+}
+
+// partial sums of one K-apply: axis-1 forward blocks plus postmix blocks
+size_t k_partials(int n1, int n2, int n3) {
+  const Grid g{n1, n2, n3, n3 / 2, (long long)n1 * n2 * n3};
+  return (size_t)std::max(axis12_blocks(g, 1, 16), axis12_blocks(g, 1, 8)) + postmix_blocks(g) + 64;
+}
+
+size_t layout(Carver& cv, csipm_ctx* c, int n1, int n2, int n3) {
+  const size_t n = (size_t)n1 * n2 * n3;
+  const size_t ntw = (size_t)n1 + n2 + n3 / 2 + n3;
+  double** d64[] = {&c->beta, &c->z, &c->nu1, &c->nu2, &c->xi, &c->hb, &c->sig1, &c->sig2, &c->rhb, &c->rhz,
+                    &c->dxb, &c->dxz, &c->diagH, &c->rb, &c->rz, &c->zb, &c->zz, &c->pb, &c->pz, &c->qb,
+                    &c->qz, &c->work};
+  for (double** p : d64) *p = cv.take<double>(n);
+  float** f32[] = {&c->sig1f, &c->sig2f, &c->frb, &c->frz, &c->fzb, &c->fzz, &c->fpb, &c->fpz,
+                   &c->fqb,   &c->fqz,   &c->fxb, &c->fxz, &c->fwork, &c->pc_c};
+  for (float** p : f32) *p = cv.take<float>(n);
+  c->feat = cv.take<float>(4 * n);
+  c->mlp_params = cv.take<float>(CSIPM_MLP_PARAMS);
+  c->mask = cv.take<uint32_t>(n / 32);
+  c->tw64 = cv.take<cx<double>>(ntw);
+  c->tw32 = cv.take<cx<float>>(ntw);
+  c->partK = cv.take<double>(k_partials(n1, n2, n3));
+  c->partV = cv.take<double>((size_t)VEC_MAX_BLOCKS * 8);
+  c->scal = cv.take<double>(S_COUNT);
+  c->flags = cv.take<int>(F_COUNT);
+  return cv.off + kAlign;
+}
+
+// ------------------------------------------------------------- operators --
+template <typename T>
+const Twiddles<T>& tw(csipm_ctx* c);
+template <>
+const Twiddles<double>& tw<double>(csipm_ctx* c) { return c->T64; }
+template <>
+const Twiddles<float>& tw<float>(csipm_ctx* c) { return c->T32; }
+
+// out = H in (internal layout), work = FFT scratch; out may equal in.
+template <typename T>
+void op_H(csipm_ctx* c, const T* in, T* out, T* work) {
+  const Grid& g = c->g;
+  launch_premix<T>(g, in, work, nullptr, c->s);
+  launch_axis12<T>(g, 1, +1, in, work, tw<T>(c), EPI_NONE, nullptr, true, nullptr, c->s);
+  launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
+  launch_axis3<T>(g, A3_FULL, work, work, c->mask, tw<T>(c), nullptr, c->s);
+  launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
+  launch_axis12<T>(g, 1, -1, work, out, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
+  launch_postmix<T>(g, out, out, EPI_NONE, nullptr, nullptr, c->s);
+}
+
+// x = A in (real grid, row-major), work = FFT scratch (must differ from x).
+template <typename T>
+void op_A(csipm_ctx* c, const T* in, T* x, T* work) {
+  const Grid& g = c->g;
+  launch_premix<T>(g, in, work, nullptr, c->s);
+  launch_axis12<T>(g, 1, +1, in, work, tw<T>(c), EPI_NONE, nullptr, true, nullptr, c->s);
+  launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
+  launch_axis3<T>(g, A3_C2R, work, x, nullptr, tw<T>(c), nullptr, c->s);
+}
+
+// out = A^T x (internal layout).
+template <typename T>
+void op_At(csipm_ctx* c, const T* x, T* out, T* work) {
+  const Grid& g = c->g;
+  launch_axis3<T>(g, A3_R2C, x, work, nullptr, tw<T>(c), nullptr, c->s);
+  launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
+  launch_axis12<T>(g, 1, -1, work, out, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
+  launch_postmix<T>(g, out, out, EPI_NONE, nullptr, nullptr, c->s);
+}
+
+// q = K p with p.q partials in c->partK; returns the number of partials.
+template <typename T>
+int op_K(csipm_ctx* c, const T* pb, const T* pz, const T* s1, const T* s2, T* qb, T* qz, T* work,
+         const int* skip) {
+  const Grid& g = c->g;
+  const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>));
+  KArgs<T> ka{pb, pz, s1, s2, qb, qz, c->partK};
+  KArgs<T> kb{pb, pz, s1, s2, qb, qz, c->partK + nb5};
+  launch_premix<T>(g, pb, work, skip, c->s);
+  launch_axis12<T>(g, 1, +1, pb, work, tw<T>(c), EPI_NONE, nullptr, true, skip, c->s);
+  launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, skip, c->s);
+  launch_axis3<T>(g, A3_FULL, work, work, c->mask, tw<T>(c), skip, c->s);
+  launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, skip, c->s);
+  launch_axis12<T>(g, 1, -1, work, work, tw<T>(c), EPI_K, &ka, false, skip, c->s);
+  launch_postmix<T>(g, work, nullptr, EPI_K, &kb, skip, c->s);
+  return nb5 + postmix_blocks(g);
+}
+
+// ------------------------------------------------- learned correction --
+// Features of the current iterate into c->feat (internal order).  Uses the
+// FP64 barrier diagonals and max|beta| of the last residual evaluation.
+void compute_features(csipm_ctx* c) {
+  const long long n = c->g.n;
+  mlp_mean_log_l1(c->sig1, c->sig2, n, c->partV, c->scal + S_MISC + 1, c->s);
+  mlp_features(c->sig1, c->sig2, c->beta, c->diagH, c->scal + S_MISC + 1, c->scal + S_RESID + 4, c->feat, n, c->s);
+}
+
+// c = softplus(MLP(features)) + 1e-6 for every coefficient.
+csipm_status learned_correction(csipm_ctx* c) {
+  compute_features(c);
+  mlp_forward(c->mlp_params, c->feat, c->pc_c, c->g.n, c->s);
+  return hip_check(c, "learned_correction");
+}
+
+template <typename T>
+void capture_pair(csipm_ctx* c, const T* pb, const T* pz, const T* qb, const T* qz, const T* s1, const T* s2) {
+  compute_features(c);
+  const size_t off = (size_t)c->cap_count * c->cap_per_iter;
+  mlp_capture<T>(pb, pz, qb, qz, s1, s2, c->feat, c->g.n, c->cap_per_iter,
+                 c->cap_seed + (unsigned long long)c->cap_count * (unsigned long long)c->cap_per_iter,
+                 c->cap_feat + off * 4, c->cap_rec + off * MLP_REC, c->partV, c->s);
+}
+
+// ------------------------------------------------------------------- PCG --
+struct PcgSet {
+  void *rb, *rz, *zb, *zz, *pb, *pz, *qb, *qz, *work;
+};
+
+template <typename T>
+PcgSet pcg_set(csipm_ctx* c);
+template <>
+PcgSet pcg_set<double>(csipm_ctx* c) {
+  return {c->rb, c->rz, c->zb, c->zz, c->pb, c->pz, c->qb, c->qz, c->work};
+}
+template <>
+PcgSet pcg_set<float>(csipm_ctx* c) {
+  return {c->frb, c->frz, c->fzb, c->fzz, c->fpb, c->fpz, c->fqb, c->fqz, c->fwork};
+}
+
+struct PcgOut {
+  int iters = 0;
+  bool converged = false;
+  bool breakdown = false;
+  double res0 = 0.0, res = 0.0;
+};
+
+// Preconditioned CG (Hestenes-Stiefel) on K x = h, x0 = 0, stopping on
+// sqrt(r.P^{-1}r) <= max(atol, eta sqrt(r0.P^{-1}r0)).  Iterations are queued
+// in growing batches; finished iterations turn the rest of a batch into
+// no-ops through the device flag, so the host only synchronises per batch.
+// If `capture` is set, p_0 and q_0 = K p_0 are handed to the capture hook.
+template <typename T>
+csipm_status pcg(csipm_ctx* c, const T* hb, const T* hz, T* xb, T* xz, const T* s1, const T* s2, const float* pcc,
+                 double eta, double atol, int maxit, PcgOut& out, bool capture) {
+  const long long n = c->g.n;
+  PcgSet v = pcg_set<T>(c);
+  T *rb = (T*)v.rb, *rz = (T*)v.rz, *zb = (T*)v.zb, *zz = (T*)v.zz, *pb = (T*)v.pb, *pz = (T*)v.pz,
+    *qb = (T*)v.qb, *qz = (T*)v.qz, *work = (T*)v.work;
+  const int nbv = vec_blocks(n);
+  cg_init<T>(hb, hz, xb, xz, rb, rz, zb, zz, pb, pz, s1, s2, pcc, n, c->partV, c->s);
+  fin_cg_init(c->partV, nbv, c->scal, c->flags, eta, atol, maxit, c->s);
+  const int* skip = c->flags + F_DONE;
+  int chunk = 2;
+  bool first = true;
+  for (;;) {
+    for (int k = 0; k < chunk; ++k) {
+      const int nbk = op_K<T>(c, pb, pz, s1, s2, qb, qz, work, skip);
+      if (first && capture) capture_pair<T>(c, pb, pz, qb, qz, s1, s2);
+      first = false;
+      fin_alpha(c->partK, nbk, c->scal, c->flags, c->s);
+      cg_update<T>(xb, xz, pb, pz, qb, qz, rb, rz, zb, zz, s1, s2, pcc, c->scal, c->flags, n, c->partV, c->s);
+      fin_rz(c->partV, nbv, c->scal, c->flags, c->s);
+      cg_pupdate<T>(pb, pz, zb, zz, c->scal, c->flags, n, c->s);
+    }
+    csipm_status st = sync_scalars(c, "pcg");
+    if (st != CSIPM_OK) return st;
+    if (c->hflags[F_DONE]) break;
+    chunk = std::min(chunk * 2, 16);
+  }
+  out.iters = c->hflags[F_IT];
+  out.breakdown = c->hflags[F_BREAK] != 0;
+  out.res0 = std::sqrt(std::max(c->hscal[S_RZ0], 0.0));
+  out.res = c->hscal[S_RES];
+  out.converged = out.res <= c->hscal[S_TOL];
+  return CSIPM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C-ABI --
+extern "C" {
+
+void csipm_default_options(csipm_options* o) {
+  if (!o) return;
+  o->tol = 1e-6;
+  o->max_iter = 200;
+  o->cg_max = 500;
+  o->cg_rtol = 1e-2;
+  o->cg_atol = 0.0;
+  o->sigma = 0.1;
+  o->tau = 0.99;
+  o->precision = CSIPM_FP64;
+  o->pc = CSIPM_PC_PLAIN;
+  o->refine_max = 8;
+  o->refine_inner_rtol = 1e-2;
+}
+
+size_t csipm_workspace_bytes(int n1, int n2, int n3) {
+  if (!pow2_in_range(n1) || !pow2_in_range(n2) || !pow2_in_range(n3)) return 0;
+  csipm_ctx tmp;
+  Carver cv{nullptr, 0, 0};
+  return layout(cv, &tmp, n1, n2, n3);
+}
+
+csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double* d_signal,
+                          const uint8_t* d_observed, void* d_workspace, size_t workspace_bytes, void* hip_stream) {
+  if (!out) return CSIPM_EINVAL;
+  *out = nullptr;
+  if (!d_signal || !d_observed || !d_workspace) return CSIPM_EINVAL;
+  if (!pow2_in_range(n1) || !pow2_in_range(n2) || !pow2_in_range(n3)) return CSIPM_EUNSUPPORTED;
+  if ((reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0) return CSIPM_EINVAL;
+  const size_t need = csipm_workspace_bytes(n1, n2, n3);
+  if (workspace_bytes < need) return CSIPM_ENOMEM;
+  csipm_ctx* c = new (std::nothrow) csipm_ctx();
+  if (!c) return CSIPM_ENOMEM;
+  c->g = Grid{n1, n2, n3, n3 / 2, (long long)n1 * n2 * n3};
+  c->s = reinterpret_cast<hipStream_t>(hip_stream);
+  Carver cv{reinterpret_cast<char*>(d_workspace), 0, workspace_bytes};
+  layout(cv, c, n1, n2, n3);
+  if (hipHostMalloc((void**)&c->hscal, sizeof(double) * S_COUNT + sizeof(int) * F_COUNT) != hipSuccess) {
+    delete c;
+    return CSIPM_EHIP;
+  }
+  c->hflags = reinterpret_cast<int*>(c->hscal + S_COUNT);
+  const Grid& g = c->g;
+  const long long n = g.n;
+
+  // twiddle tables exp(-2 pi i q / L), from long double, rounded once
+  const int Ls[4] = {n1, n2, n3 / 2, n3};
+  std::vector<cx<double>> h64;
+  std::vector<cx<float>> h32;
+  for (int L : Ls)
+    for (int q = 0; q < L; ++q) {
+      const long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)q / (long double)L;
+      const long double cr = cosl(a), ci = sinl(a);
+      h64.push_back({(double)cr, (double)ci});
+      h32.push_back({(float)cr, (float)ci});
+    }
+  hipError_t e = hipMemcpyAsync(c->tw64, h64.data(), h64.size() * sizeof(cx<double>), hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->tw32, h32.data(), h32.size() * sizeof(cx<float>), hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+  if (e != hipSuccess) {
+    (void)hipHostFree(c->hscal);
+    delete c;
+    return CSIPM_EHIP;
+  }
+  size_t o = 0;
+  c->T64.t1 = c->tw64 + o; c->T32.t1 = c->tw32 + o; o += n1;
+  c->T64.t2 = c->tw64 + o; c->T32.t2 = c->tw32 + o; o += n2;
+  c->T64.tm = c->tw64 + o; c->T32.tm = c->tw32 + o; o += n3 / 2;
+  c->T64.t3 = c->tw64 + o; c->T32.t3 = c->tw32 + o;
+
+  // input checks: finite observed samples, at least one observed
+  check_signal(d_signal, d_observed, n, c->partV, c->scal + S_SIG, c->s);
+  csipm_status st = sync_scalars(c, "create");
+  if (st != CSIPM_OK) { csipm_destroy(c); return st; }
+  if (c->hscal[S_SIG] > 0) { csipm_destroy(c); return CSIPM_ENONFINITE; }
+  c->nobs = (long long)c->hscal[S_SIG + 1];
+  if (c->nobs == 0) { csipm_destroy(c); return CSIPM_EINVAL; }
+
+  launch_pack_mask(g, d_observed, c->mask, c->s);
+  // xi = A^T b_hat (b_hat: zero-filled signal, staged in rb as a real grid)
+  zero_fill(d_signal, d_observed, c->rb, n, c->s);
+  op_At<double>(c, c->rb, c->xi, c->work);
+  absmax(c->xi, n, c->partV, c->scal + S_MISC, c->s);
+  // diag(M_perp^T M_perp) from A^T(mask), through the external layout
+  obs_to_double(d_observed, c->rb, n, c->s);
+  op_At<double>(c, c->rb, c->zb, c->work);
+  launch_to_external<double, double>(g, c->zb, c->zz, c->s);
+  diag_h(c->zz, c->rz, n1, n2, n3, (double)c->nobs / (double)n, c->s);
+  launch_to_internal<double, double>(g, c->rz, c->diagH, c->s);
+  fill<float>(c->pc_c, 1.0f, n, c->s);
+  st = sync_scalars(c, "create");
+  if (st != CSIPM_OK) { csipm_destroy(c); return st; }
+  c->xi_inf = c->hscal[S_MISC];
+  // barrier diagonals default to 1 so apply_K / apply_Pinv are defined
+  fill<double>(c->sig1, 1.0, n, c->s);
+  fill<double>(c->sig2, 1.0, n, c->s);
+  fill<float>(c->sig1f, 1.0f, n, c->s);
+  fill<float>(c->sig2f, 1.0f, n, c->s);
+  st = hip_check(c, "create");
+  if (st != CSIPM_OK) { csipm_destroy(c); return st; }
+  *out = c;
+  return CSIPM_OK;
+}
+
+csipm_status csipm_set_lambda(csipm_ctx* c, double lambda) {
+  if (!c) return CSIPM_EINVAL;
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, CSIPM_EINVAL, "lambda must be finite and > 0");
+  c->lambda = lambda;
+  c->have_lambda = true;
+  return CSIPM_OK;
+}
+
+csipm_status csipm_lambda_rule(csipm_ctx* c, double frac, double* lambda_out) {
+  if (!c) return CSIPM_EINVAL;
+  if (!(frac > 0.0) || !std::isfinite(frac)) return fail(c, CSIPM_EINVAL, "frac must be finite and > 0");
+  if (!(c->xi_inf > 0.0)) return fail(c, CSIPM_EINVAL, "M_perp^T b is zero: every lambda > 0 gives beta = 0");
+  c->lambda = frac * c->xi_inf;
+  c->have_lambda = true;
+  if (lambda_out) *lambda_out = c->lambda;
+  return CSIPM_OK;
+}
+
+namespace {
+
+// Solves the Newton system K [dxb; dxz] = [rhb; rhz] at the current barrier
+// diagonals, in FP64 PCG or FP32 PCG with FP64 iterative refinement.
+csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double eta, const float* pcc, int& cg_iters,
+                          int& refine_steps, bool& converged, bool capture) {
+  const long long n = c->g.n;
+  cg_iters = 0;
+  refine_steps = 0;
+  converged = false;
+  if (o.precision == CSIPM_FP64) {
+    PcgOut po;
+    csipm_status st = pcg<double>(c, c->rhb, c->rhz, c->dxb, c->dxz, c->sig1, c->sig2, pcc, eta, o.cg_atol,
+                                  o.cg_max, po, capture);
+    cg_iters = po.iters;
+    converged = po.converged;
+    return st;
+  }
+  // FP32 inner solves, FP64 residual: d = 0, r = h; repeat { e = K32^{-1} r;
+  // d += e; r = h - K d } until sqrt(r.P^{-1}r) <= max(atol, eta sqrt(h.P^{-1}h)).
+  fill<double>(c->dxb, 0.0, n, c->s);
+  fill<double>(c->dxz, 0.0, n, c->s);
+  pinv_apply<double>(c->rhb, c->rhz, c->zb, c->zz, c->sig1, c->sig2, pcc, n, c->partV, c->scal + S_REF0, c->s);
+  copy2(c->rhb, c->rhz, c->rb, c->rz, n, c->s);
+  csipm_status st = sync_scalars(c, "refine");
+  if (st != CSIPM_OK) return st;
+  const double h0 = std::sqrt(std::max(c->hscal[S_REF0], 0.0));
+  const double target = std::max(o.cg_atol, eta * h0);
+  double rnorm = h0;
+  if (rnorm <= target) {
+    converged = true;
+    return CSIPM_OK;
+  }
+  for (int step = 0; step < std::max(1, o.refine_max); ++step) {
+    cast_d2f(c->rb, c->rz, c->fqb, c->fqz, n, c->s);
+    const double inner = std::max(o.refine_inner_rtol, 0.5 * target / rnorm);
+    PcgOut po;
+    st = pcg<float>(c, c->fqb, c->fqz, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, inner, 0.0, o.cg_max, po,
+                    capture && step == 0);
+    if (st != CSIPM_OK) return st;
+    cg_iters += po.iters;
+    add_f2d(c->dxb, c->dxz, c->fxb, c->fxz, n, c->s);
+    op_K<double>(c, c->dxb, c->dxz, c->sig1, c->sig2, c->qb, c->qz, c->work, nullptr);
+    ref_resid(c->rhb, c->rhz, c->qb, c->qz, c->rb, c->rz, c->sig1, c->sig2, pcc, n, c->partV, c->scal + S_REF,
+              c->s);
+    st = sync_scalars(c, "refine");
+    if (st != CSIPM_OK) return st;
+    ++refine_steps;
+    rnorm = std::sqrt(std::max(c->hscal[S_REF], 0.0));
+    if (rnorm <= target) {
+      converged = true;
+      break;
+    }
+    if (po.iters == 0 || !std::isfinite(rnorm)) break;
+  }
+  return CSIPM_OK;
+}
+
+struct Resid {
+  double fb, fz, cmax, csum, bmax, pmin, nonfinite;
+};
+
+csipm_status residuals(csipm_ctx* c, Resid& r) {
+  op_H<double>(c, c->beta, c->hb, c->work);
+  ipm_resid(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, c->g.n, c->partV, c->scal + S_RESID, c->s);
+  csipm_status st = sync_scalars(c, "residuals");
+  if (st != CSIPM_OK) return st;
+  const double* v = c->hscal + S_RESID;
+  r = Resid{v[0], v[1], v[2], v[3], v[4], v[5], v[6]};
+  return CSIPM_OK;
+}
+
+}  // namespace
+
+csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* info) {
+  if (!c) return CSIPM_EINVAL;
+  if (!c->have_lambda) return fail(c, CSIPM_ESTATE, "lambda not set");
+  csipm_options o;
+  csipm_default_options(&o);
+  if (opts) o = *opts;
+  if (!(o.tol > 0) || o.max_iter < 0 || o.cg_max < 1 || !(o.sigma > 0 && o.sigma < 1) || !(o.tau > 0 && o.tau < 1) ||
+      (o.precision != CSIPM_FP64 && o.precision != CSIPM_FP32) || (o.pc != CSIPM_PC_PLAIN && o.pc != CSIPM_PC_LEARNED))
+    return fail(c, CSIPM_EINVAL, "invalid options");
+  if (o.pc == CSIPM_PC_LEARNED && !c->have_params) return fail(c, CSIPM_ESTATE, "learned preconditioner has no parameters");
+  const auto t0 = std::chrono::steady_clock::now();
+  const long long n = c->g.n;
+  const double lam = c->lambda;
+  c->log.clear();
+  c->cap_count = 0;
+  c->cap_cg.clear();
+  const double z0 = c->xi_inf > 0 ? c->xi_inf : 1.0;
+  ipm_init(c->beta, c->z, c->nu1, c->nu2, n, z0, lam, c->s);
+  csipm_info inf{};
+  inf.lambda = lam;
+  inf.xi_inf = c->xi_inf;
+  csipm_status result = CSIPM_NOT_CONVERGED;
+  int prev_cg = 0;
+  Resid r{};
+  for (int it = 0;; ++it) {
+    csipm_status st = residuals(c, r);
+    if (st != CSIPM_OK) return st;
+    if (r.nonfinite > 0 || !std::isfinite(r.fb)) return fail(c, CSIPM_ENONFINITE, "non-finite interior-point iterate");
+    const double mu = r.csum / (2.0 * (double)n);
+    const double rel = std::max(std::max(r.fb, r.fz), r.cmax) / (1.0 + c->xi_inf);
+    inf.rel_kkt = rel;
+    inf.res_beta_inf = r.fb;
+    inf.res_z_inf = r.fz;
+    inf.compl_max = r.cmax;
+    inf.mu = mu;
+    if (!c->log.empty()) c->log.back().alpha = c->hscal[S_ALPHA_IPM];
+    if (rel <= o.tol) {
+      result = inf.fallbacks > 0 ? CSIPM_FELL_BACK : CSIPM_OK;
+      break;
+    }
+    if (it >= o.max_iter) {
+      result = CSIPM_NOT_CONVERGED;
+      break;
+    }
+    const double smu = o.sigma * mu;
+    const bool need32 = o.precision == CSIPM_FP32;
+    ipm_newton<float>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, lam, smu, c->sig1, c->sig2, c->rhb, c->rhz,
+                      need32 ? c->sig1f : nullptr, need32 ? c->sig2f : nullptr, n, c->s);
+    const double eta = std::min(o.cg_rtol, 0.1 * rel);
+    int cgi = 0, ref = 0;
+    bool conv = false, fell = false;
+    const bool capture = c->cap_enable && o.pc == CSIPM_PC_PLAIN && c->cap_count < c->cap_max;
+    if (o.pc == CSIPM_PC_LEARNED) {
+      st = learned_correction(c);
+      if (st != CSIPM_OK) return st;
+      csipm_options ol = o;
+      const int budget = prev_cg > 0 ? std::min(o.cg_max, std::max(8, (prev_cg * 3) / 2)) : o.cg_max;
+      ol.cg_max = budget;
+      st = newton_solve(c, ol, eta, c->pc_c, cgi, ref, conv, false);
+      if (st != CSIPM_OK) return st;
+      if (!conv) {
+        int cgi2 = 0, ref2 = 0;
+        st = newton_solve(c, o, eta, nullptr, cgi2, ref2, conv, false);
+        if (st != CSIPM_OK) return st;
+        cgi += cgi2;
+        ref += ref2;
+        fell = true;
+        ++inf.fallbacks;
+      }
+    } else {
+      st = newton_solve(c, o, eta, nullptr, cgi, ref, conv, capture);
+      if (st != CSIPM_OK) return st;
+      if (capture) {
+        mlp_scale_weights(c->cap_rec + (size_t)c->cap_count * c->cap_per_iter * MLP_REC, c->cap_per_iter,
+                          (float)cgi, c->s);
+        ++c->cap_count;
+        c->cap_cg.push_back(cgi);
+      }
+    }
+    prev_cg = cgi;
+    inf.cg_iters_total += cgi;
+    inf.cg_iters_max = std::max(inf.cg_iters_max, cgi);
+    inf.refine_steps_total += ref;
+    ipm_step(c->beta, c->z, c->nu1, c->nu2, c->sig1, c->sig2, c->dxb, c->dxz, smu, o.tau, n, c->partV, c->scal,
+             c->s);
+    ipm_update(c->beta, c->z, c->nu1, c->nu2, c->sig1, c->sig2, c->dxb, c->dxz, smu, c->scal, n, c->s);
+    c->log.push_back(csipm_iter_log{it, cgi, ref, fell ? 1 : 0, mu, rel, 0.0});
+    inf.ipm_iters = it + 1;
+    st = hip_check(c, "solve");
+    if (st != CSIPM_OK) return st;
+  }
+  inf.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  inf.status = result;
+  if (info) *info = inf;
+  return result;
+}
+
+csipm_status csipm_get_iterate(csipm_ctx* c, int which, double* d_dst) {
+  if (!c || !d_dst) return CSIPM_EINVAL;
+  const double* src = nullptr;
+  switch (which) {
+    case CSIPM_BETA: src = c->beta; break;
+    case CSIPM_Z: src = c->z; break;
+    case CSIPM_NU1: src = c->nu1; break;
+    case CSIPM_NU2: src = c->nu2; break;
+    case CSIPM_XI: src = c->xi; break;
+    case CSIPM_DIAG_H: src = c->diagH; break;
+    case CSIPM_PC_C:
+      launch_to_external<float, double>(c->g, c->pc_c, d_dst, c->s);
+      return hip_check(c, "get_iterate");
+    default: return fail(c, CSIPM_EINVAL, "unknown variable");
+  }
+  launch_to_external<double, double>(c->g, src, d_dst, c->s);
+  return hip_check(c, "get_iterate");
+}
+
+csipm_status csipm_get_residuals(csipm_ctx* c, csipm_info* out) {
+  if (!c || !out) return CSIPM_EINVAL;
+  if (!c->have_lambda) return fail(c, CSIPM_ESTATE, "lambda not set");
+  Resid r{};
+  csipm_status st = residuals(c, r);
+  if (st != CSIPM_OK) return st;
+  std::memset(out, 0, sizeof(*out));
+  out->res_beta_inf = r.fb;
+  out->res_z_inf = r.fz;
+  out->compl_max = r.cmax;
+  out->mu = r.csum / (2.0 * (double)c->g.n);
+  out->rel_kkt = std::max(std::max(r.fb, r.fz), r.cmax) / (1.0 + c->xi_inf);
+  out->lambda = c->lambda;
+  out->xi_inf = c->xi_inf;
+  return CSIPM_OK;
+}
+
+csipm_status csipm_get_log(csipm_ctx* c, csipm_iter_log* host_buf, int max_records, int* n_records) {
+  if (!c || (!host_buf && max_records > 0)) return CSIPM_EINVAL;
+  const int k = std::min<int>(max_records, (int)c->log.size());
+  for (int i = 0; i < k; ++i) host_buf[i] = c->log[i];
+  if (n_records) *n_records = (int)c->log.size();
+  return CSIPM_OK;
+}
+
+csipm_status csipm_apply_A(csipm_ctx* c, const void* d_beta, void* d_x, int precision) {
+  if (!c || !d_beta || !d_x) return CSIPM_EINVAL;
+  if (precision == CSIPM_FP64) {
+    launch_to_internal<double, double>(c->g, (const double*)d_beta, c->pb, c->s);
+    op_A<double>(c, c->pb, (double*)d_x, c->work);
+  } else if (precision == CSIPM_FP32) {
+    launch_to_internal<float, float>(c->g, (const float*)d_beta, c->fpb, c->s);
+    op_A<float>(c, c->fpb, (float*)d_x, c->fwork);
+  } else {
+    return fail(c, CSIPM_EINVAL, "precision");
+  }
+  return hip_check(c, "apply_A");
+}
+
+csipm_status csipm_apply_At(csipm_ctx* c, const void* d_x, void* d_beta, int precision) {
+  if (!c || !d_beta || !d_x) return CSIPM_EINVAL;
+  if (precision == CSIPM_FP64) {
+    op_At<double>(c, (const double*)d_x, c->qb, c->work);
+    launch_to_external<double, double>(c->g, c->qb, (double*)d_beta, c->s);
+  } else if (precision == CSIPM_FP32) {
+    op_At<float>(c, (const float*)d_x, c->fqb, c->fwork);
+    launch_to_external<float, float>(c->g, c->fqb, (float*)d_beta, c->s);
+  } else {
+    return fail(c, CSIPM_EINVAL, "precision");
+  }
+  return hip_check(c, "apply_At");
+}
+
+csipm_status csipm_apply_H(csipm_ctx* c, const void* d_beta, void* d_y, int precision) {
+  if (!c || !d_beta || !d_y) return CSIPM_EINVAL;
+  if (precision == CSIPM_FP64) {
+    launch_to_internal<double, double>(c->g, (const double*)d_beta, c->pb, c->s);
+    op_H<double>(c, c->pb, c->qb, c->work);
+    launch_to_external<double, double>(c->g, c->qb, (double*)d_y, c->s);
+  } else if (precision == CSIPM_FP32) {
+    launch_to_internal<float, float>(c->g, (const float*)d_beta, c->fpb, c->s);
+    op_H<float>(c, c->fpb, c->fqb, c->fwork);
+    launch_to_external<float, float>(c->g, c->fqb, (float*)d_y, c->s);
+  } else {
+    return fail(c, CSIPM_EINVAL, "precision");
+  }
+  return hip_check(c, "apply_H");
+}
+
+csipm_status csipm_apply_K(csipm_ctx* c, const void* d_pb, const void* d_pz, void* d_qb, void* d_qz, int precision) {
+  if (!c || !d_pb || !d_pz || !d_qb || !d_qz) return CSIPM_EINVAL;
+  if (precision == CSIPM_FP64) {
+    launch_to_internal<double, double>(c->g, (const double*)d_pb, c->pb, c->s);
+    launch_to_internal<double, double>(c->g, (const double*)d_pz, c->pz, c->s);
+    op_K<double>(c, c->pb, c->pz, c->sig1, c->sig2, c->qb, c->qz, c->work, nullptr);
+    launch_to_external<double, double>(c->g, c->qb, (double*)d_qb, c->s);
+    launch_to_external<double, double>(c->g, c->qz, (double*)d_qz, c->s);
+  } else if (precision == CSIPM_FP32) {
+    launch_to_internal<float, float>(c->g, (const float*)d_pb, c->fpb, c->s);
+    launch_to_internal<float, float>(c->g, (const float*)d_pz, c->fpz, c->s);
+    op_K<float>(c, c->fpb, c->fpz, c->sig1f, c->sig2f, c->fqb, c->fqz, c->fwork, nullptr);
+    launch_to_external<float, float>(c->g, c->fqb, (float*)d_qb, c->s);
+    launch_to_external<float, float>(c->g, c->fqz, (float*)d_qz, c->s);
+  } else {
+    return fail(c, CSIPM_EINVAL, "precision");
+  }
+  return hip_check(c, "apply_K");
+}
+
+csipm_status csipm_apply_Pinv(csipm_ctx* c, const void* d_rb, const void* d_rz, void* d_zb, void* d_zz,
+                              int precision) {
+  if (!c || !d_rb || !d_rz || !d_zb || !d_zz) return CSIPM_EINVAL;
+  if (precision == CSIPM_FP64) {
+    launch_to_internal<double, double>(c->g, (const double*)d_rb, c->rb, c->s);
+    launch_to_internal<double, double>(c->g, (const double*)d_rz, c->rz, c->s);
+    pinv_apply<double>(c->rb, c->rz, c->zb, c->zz, c->sig1, c->sig2, c->pc_c, c->g.n, c->partV, nullptr, c->s);
+    launch_to_external<double, double>(c->g, c->zb, (double*)d_zb, c->s);
+    launch_to_external<double, double>(c->g, c->zz, (double*)d_zz, c->s);
+  } else if (precision == CSIPM_FP32) {
+    launch_to_internal<float, float>(c->g, (const float*)d_rb, c->frb, c->s);
+    launch_to_internal<float, float>(c->g, (const float*)d_rz, c->frz, c->s);
+    pinv_apply<float>(c->frb, c->frz, c->fzb, c->fzz, c->sig1f, c->sig2f, c->pc_c, c->g.n, c->partV, nullptr,
+                      c->s);
+    launch_to_external<float, float>(c->g, c->fzb, (float*)d_zb, c->s);
+    launch_to_external<float, float>(c->g, c->fzz, (float*)d_zz, c->s);
+  } else {
+    return fail(c, CSIPM_EINVAL, "precision");
+  }
+  return hip_check(c, "apply_Pinv");
+}
+
+csipm_status csipm_set_barrier(csipm_ctx* c, const double* d_sigma1, const double* d_sigma2) {
+  if (!c || !d_sigma1 || !d_sigma2) return CSIPM_EINVAL;
+  launch_to_internal<double, double>(c->g, d_sigma1, c->sig1, c->s);
+  launch_to_internal<double, double>(c->g, d_sigma2, c->sig2, c->s);
+  launch_to_internal<double, float>(c->g, d_sigma1, c->sig1f, c->s);
+  launch_to_internal<double, float>(c->g, d_sigma2, c->sig2f, c->s);
+  return hip_check(c, "set_barrier");
+}
+
+csipm_status csipm_set_pc_params(csipm_ctx* c, const float* d_params, int n_params) {
+  if (!c || !d_params) return CSIPM_EINVAL;
+  if (n_params != CSIPM_MLP_PARAMS) return fail(c, CSIPM_EINVAL, "expected 1249 parameters");
+  hipError_t e = hipMemcpyAsync(c->mlp_params, d_params, sizeof(float) * MLP_NP, hipMemcpyDeviceToDevice, c->s);
+  if (e != hipSuccess) return fail(c, CSIPM_EHIP, hipGetErrorString(e));
+  c->have_params = true;
+  return CSIPM_OK;
+}
+
+size_t csipm_mlp_scratch_bytes(int n_rec) {
+  if (n_rec < 0) return 0;
+  const size_t nblk = ((size_t)n_rec + 63) / 64;
+  return std::max<size_t>(1, nblk) * (MLP_NP + 1) * sizeof(double);
+}
+
+csipm_status csipm_mlp_forward(const float* d_params, const float* d_feat, float* d_c, int n_rec, void* hip_stream) {
+  if (!d_params || !d_feat || !d_c || n_rec < 0) return CSIPM_EINVAL;
+  if (n_rec == 0) return CSIPM_OK;
+  mlp_forward(d_params, d_feat, d_c, n_rec, reinterpret_cast<hipStream_t>(hip_stream));
+  return hipGetLastError() == hipSuccess ? CSIPM_OK : CSIPM_EHIP;
+}
+
+csipm_status csipm_mlp_backward(const float* d_params, const float* d_feat, const float* d_dc, float* d_grad,
+                                int n_rec, void* d_scratch, size_t scratch_bytes, void* hip_stream) {
+  if (!d_params || !d_feat || !d_dc || !d_grad || !d_scratch || n_rec < 0) return CSIPM_EINVAL;
+  if (scratch_bytes < csipm_mlp_scratch_bytes(n_rec)) return CSIPM_ENOMEM;
+  if (n_rec == 0) return CSIPM_OK;
+  mlp_backward(d_params, d_feat, d_dc, d_grad, n_rec, (double*)d_scratch, reinterpret_cast<hipStream_t>(hip_stream));
+  return hipGetLastError() == hipSuccess ? CSIPM_OK : CSIPM_EHIP;
+}
+
+csipm_status csipm_mlp_loss_grad(const float* d_params, const float* d_feat, const float* d_rec, int n_rec,
+                                 double* d_loss_out, float* d_grad, void* d_scratch, size_t scratch_bytes,
+                                 void* hip_stream) {
+  if (!d_params || !d_feat || !d_rec || !d_loss_out || !d_grad || !d_scratch || n_rec < 1) return CSIPM_EINVAL;
+  if (scratch_bytes < csipm_mlp_scratch_bytes(n_rec)) return CSIPM_ENOMEM;
+  mlp_loss_grad(d_params, d_feat, d_rec, n_rec, d_loss_out, d_grad, (double*)d_scratch,
+                reinterpret_cast<hipStream_t>(hip_stream));
+  return hipGetLastError() == hipSuccess ? CSIPM_OK : CSIPM_EHIP;
+}
+
+csipm_status csipm_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, int t, float lr,
+                            void* hip_stream) {
+  if (!d_params || !d_grad || !d_m || !d_v || t < 1 || !(lr > 0.0f)) return CSIPM_EINVAL;
+  mlp_adam(d_params, d_grad, d_m, d_v, t, lr, reinterpret_cast<hipStream_t>(hip_stream));
+  return hipGetLastError() == hipSuccess ? CSIPM_OK : CSIPM_EHIP;
+}
+
+csipm_status csipm_capture(csipm_ctx* c, int enable, float* d_feat, float* d_rec, int n_per_iter, int max_iters,
+                           unsigned long long seed) {
+  if (!c) return CSIPM_EINVAL;
+  if (!enable) {
+    c->cap_enable = 0;
+    return CSIPM_OK;
+  }
+  if (!d_feat || !d_rec || n_per_iter < 1 || max_iters < 1) return fail(c, CSIPM_EINVAL, "capture buffers");
+  c->cap_enable = 1;
+  c->cap_feat = d_feat;
+  c->cap_rec = d_rec;
+  c->cap_per_iter = n_per_iter;
+  c->cap_max = max_iters;
+  c->cap_seed = seed;
+  c->cap_count = 0;
+  c->cap_cg.clear();
+  return CSIPM_OK;
+}
+
+csipm_status csipm_captured(csipm_ctx* c, int* n_iters, int* cg_counts_host, int max_iters) {
+  if (!c) return CSIPM_EINVAL;
+  if (n_iters) *n_iters = c->cap_count;
+  if (cg_counts_host)
+    for (int i = 0; i < std::min<int>(max_iters, (int)c->cap_cg.size()); ++i) cg_counts_host[i] = c->cap_cg[i];
+  return CSIPM_OK;
+}
+
+csipm_status csipm_features(csipm_ctx* c, float* d_feat) {
+  if (!c || !d_feat) return CSIPM_EINVAL;
+  absmax(c->beta, c->g.n, c->partV, c->scal + S_RESID + 4, c->s);
+  compute_features(c);
+  launch_feat_to_external(c->g, c->feat, d_feat, c->s);
+  return hip_check(c, "features");
+}
+
+csipm_status csipm_profile_kapply(csipm_ctx* c, int precision, int reps, double* ms_out) {
+  if (!c || !ms_out || reps < 1) return CSIPM_EINVAL;
+  if (precision != CSIPM_FP64 && precision != CSIPM_FP32) return fail(c, CSIPM_EINVAL, "precision");
+  const Grid& g = c->g;
+  hipEvent_t ev[CSIPM_KAPPLY_PASSES + 1];
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) return fail(c, CSIPM_EHIP, "hipEventCreate");
+  double acc[CSIPM_KAPPLY_PASSES] = {0};
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    PcgSet v = pcg_set<T>(c);
+    T *pb = (T*)v.pb, *pz = (T*)v.pz, *qb = (T*)v.qb, *qz = (T*)v.qz, *work = (T*)v.work;
+    const T* s1 = std::is_same<T, double>::value ? (const T*)c->sig1 : (const T*)c->sig1f;
+    const T* s2 = std::is_same<T, double>::value ? (const T*)c->sig2 : (const T*)c->sig2f;
+    const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>));
+    KArgs<T> ka{pb, pz, s1, s2, qb, qz, c->partK};
+    KArgs<T> kb{pb, pz, s1, s2, qb, qz, c->partK + nb5};
+    for (int r = 0; r < reps; ++r) {
+      (void)hipEventRecord(ev[0], c->s);
+      launch_premix<T>(g, pb, work, nullptr, c->s);
+      (void)hipEventRecord(ev[1], c->s);
+      launch_axis12<T>(g, 1, +1, pb, work, tw<T>(c), EPI_NONE, nullptr, true, nullptr, c->s);
+      (void)hipEventRecord(ev[2], c->s);
+      launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
+      (void)hipEventRecord(ev[3], c->s);
+      launch_axis3<T>(g, A3_FULL, work, work, c->mask, tw<T>(c), nullptr, c->s);
+      (void)hipEventRecord(ev[4], c->s);
+      launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
+      (void)hipEventRecord(ev[5], c->s);
+      launch_axis12<T>(g, 1, -1, work, work, tw<T>(c), EPI_K, &ka, false, nullptr, c->s);
+      (void)hipEventRecord(ev[6], c->s);
+      launch_postmix<T>(g, work, nullptr, EPI_K, &kb, nullptr, c->s);
+      (void)hipEventRecord(ev[7], c->s);
+      (void)hipEventSynchronize(ev[7]);
+      for (int k = 0; k < CSIPM_KAPPLY_PASSES; ++k) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+        acc[k] += ms;
+      }
+    }
+  };
+  if (precision == CSIPM_FP64) run(double{}); else run(float{});
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  for (int k = 0; k < CSIPM_KAPPLY_PASSES; ++k) ms_out[k] = acc[k] / reps;
+  return hip_check(c, "profile_kapply");
+}
+
+csipm_status csipm_destroy(csipm_ctx* c) {
+  if (!c) return CSIPM_EINVAL;
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  delete c;
+  return CSIPM_OK;
+}
+
+const char* csipm_status_string(int st) {
+  switch (st) {
+    case CSIPM_OK: return "ok";
+    case CSIPM_NOT_CONVERGED: return "not converged (iteration limit)";
+    case CSIPM_STALLED: return "stalled (step length collapsed)";
+    case CSIPM_FELL_BACK: return "converged with preconditioner fallbacks";
+    case CSIPM_EINVAL: return "invalid argument";
+    case CSIPM_ENOMEM: return "workspace too small";
+    case CSIPM_EHIP: return "HIP runtime error";
+    case CSIPM_ENONFINITE: return "non-finite value";
+    case CSIPM_EUNSUPPORTED: return "unsupported grid";
+    case CSIPM_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* csipm_last_error(const csipm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Internal declarations of the csipm HIP library (gfx950).
+//
+// Data layout on the device ("internal layout").  Every beta-indexed vector
+// (beta, z, nu1, nu2, xi, the barrier diagonals, Krylov vectors) is stored as
+// n reals that reinterpret as a complex array P[k1][k2][m], m in [0, N3/2):
+//   m >= 1 : P = (beta[k1,k2,m], beta[-k1,-k2,N3-m])   (sqrt2 Re / sqrt2 Im of
+//            the half-spectrum bin (k1,k2,m))
+//   m == 0 : P = (beta[k1,k2,0], beta[k1,k2,N3/2])      (the two self-paired
+//            planes k3 = 0 and k3 = N3/2, packed as real/imaginary parts)
+// This is a pure permutation of the external row-major beta layout, so all
+// elementwise interior-point arithmetic and every dot product are unchanged;
+// only the FFT passes see the complex structure.  The same n reals also hold
+// the FFT intermediates: after the two inverse complex passes the array is
+// T[j1][j2][m] (packed half-spectrum along axis 3, DC and Nyquist sharing
+// slot 0), and after the axis-3 pass it reinterprets as the real grid
+// x[j1][j2][j3].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace csipm {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
+// multiply by +i (dir > 0) or -i (dir < 0)
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> cmul_i(cx<T> a) {
+  if constexpr (DIR > 0) return {-a.im, a.re};
+  else return {a.im, -a.re};
+}
+
+// exp(DIR * 2 pi i k / 16) for k in [0, 16), as literals (k = 0..15).
+template <typename T>
+__device__ __forceinline__ cx<T> w16(int k, int dir) {
+  constexpr double C1 = 0.92387953251128675613;  // cos(pi/8)
+  constexpr double S1 = 0.38268343236508977173;  // sin(pi/8)
+  constexpr double H = 0.70710678118654752440;   // cos(pi/4)
+  const double c[16] = {1, C1, H, S1, 0, -S1, -H, -C1, -1, -C1, -H, -S1, 0, S1, H, C1};
+  const double s[16] = {0, S1, H, C1, 1, C1, H, S1, 0, -S1, -H, -C1, -1, -C1, -H, -S1};
+  return {T(c[k & 15]), T(dir > 0 ? s[k & 15] : -s[k & 15])};
+}
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+constexpr int bitrev(int x, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+// In-register DFT of size R (power of two, R <= 16) in natural order:
+// out[k] = sum_j v[j] exp(DIR 2 pi i j k / R).  Iterative radix-2 with the
+// bit-reversal done at compile time; trivial twiddles are special-cased.
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft_reg(cx<T>* v) {
+  constexpr int B = ilog2(R);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int j = bitrev(i, B);
+    if (j > i) {
+      cx<T> t = v[i];
+      v[i] = v[j];
+      v[j] = t;
+    }
+  }
+#pragma unroll
+  for (int len = 2; len <= R; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < R; i += len) {
+#pragma unroll
+      for (int k = 0; k < len / 2; ++k) {
+        cx<T> a = v[i + k];
+        cx<T> b = v[i + k + len / 2];
+        if (k == 0) {
+        } else if (4 * k == len) {
+          b = cmul_i<DIR>(b);
+        } else {
+          b = cmul(b, w16<T>(k * (16 / len), DIR));
+        }
+        v[i + k] = cadd(a, b);
+        v[i + k + len / 2] = csub(a, b);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- plans ----
+
+// Twiddle tables for one grid, in both precisions: tw_L[q] = exp(-2 pi i q/L)
+// for L in {N1, N2, M = N3/2, N3}.
+template <typename T>
+struct Twiddles {
+  const cx<T>* t1;   // length N1
+  const cx<T>* t2;   // length N2
+  const cx<T>* tm;   // length M
+  const cx<T>* t3;   // length N3
+};
+
+struct Grid {
+  int n1, n2, n3, m;   // m = n3/2
+  long long n;         // n1*n2*n3 reals = n1*n2*m complex
+};
+
+// Selects what the axis-3 pass does.
+enum Axis3Mode { A3_C2R = 1, A3_R2C = 2, A3_FULL = 3 };
+
+// Epilogue of the last forward pass (axis 1).
+enum EpiMode {
+  EPI_NONE = 0,   // write the transform result (A^T x or H p), m = 0 left raw
+  EPI_K = 1       // q = K p with the barrier diagonals, plus p.q partials
+};
+
+template <typename T>
+struct KArgs {
+  const T* pb;        // p_beta (internal layout)
+  const T* pz;        // p_z
+  const T* sig1;      // Sigma_1
+  const T* sig2;      // Sigma_2
+  T* qb;
+  T* qz;
+  double* partial;    // one double per workgroup
+};
+
+// FFT driver entry points (fft.hip).  All work is queued on `s`.
+// `skip` (nullable device int): when nonzero at launch time the kernel
+// returns at once; lets a batch of Krylov iterations be queued ahead.
+template <typename T>
+void launch_premix(const Grid& g, const T* src, T* work, const int* skip, hipStream_t s);
+template <typename T>
+void launch_axis12(const Grid& g, int axis, int dir, const T* src, T* dst, const Twiddles<T>& tw,
+                   int epi, const KArgs<T>* ka, bool m0_from_dst, const int* skip, hipStream_t s);
+template <typename T>
+void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t* maskbits,
+                  const Twiddles<T>& tw, const int* skip, hipStream_t s);
+template <typename T>
+void launch_postmix(const Grid& g, const T* work, T* out, int epi, const KArgs<T>* ka,
+                    const int* skip, hipStream_t s);
+int axis12_blocks(const Grid& g, int axis, int elem_bytes);
+int postmix_blocks(const Grid& g);
+
+// permutation between the external beta layout and the internal one
+template <typename Te, typename Ti>
+void launch_to_internal(const Grid& g, const Te* ext, Ti* in, hipStream_t s);
+template <typename Ti, typename Te>
+void launch_to_external(const Grid& g, const Ti* in, Te* ext, hipStream_t s);
+void launch_pack_mask(const Grid& g, const uint8_t* obs, uint32_t* bits, hipStream_t s);
+// [n][4] float records, internal coefficient order -> external order
+void launch_feat_to_external(const Grid& g, const float* in, float* ext, hipStream_t s);
+
+}  // namespace csipm

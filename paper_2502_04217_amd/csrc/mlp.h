@@ -1,0 +1,46 @@
+// Learned diagonal correction of the preconditioner: kernel launchers.
+//
+// Network 4 -> 32 -> 32 -> 1 with tanh hidden units and c = softplus(o)+1e-6,
+// float32 parameters in the flat layout W1[32][4], b1[32], W2[32][32], b2[32],
+// w3[32], b3 (1249 values).  Features per coefficient i:
+//   f1 = log L1_i - mean log L1,  f2 = L2_i / L1_i,
+//   f3 = log(|beta_i| / max|beta| + 1e-12),  f4 = diag(M_perp^T M_perp)_i.
+// Training record of a sampled coefficient i of a Krylov direction p with
+// u = H p_beta: {u_i, p_beta_i, L1_i, L2_i, 4 S1_i S2_i, w_i}; its loss is
+//   w (L1^2 + L2^2)(u - c p)^2 / (c L1 + 4 S1 S2)^2,
+// the squared i-th block of P_c^{-1}(K - P_c)p.
+#pragma once
+
+#include "csipm_internal.h"
+
+namespace csipm {
+
+constexpr int MLP_NP = 1249;
+constexpr int MLP_REC = 6;
+constexpr int MLP_BLOCK = 128;   // records per training workgroup
+
+// mean of log(S1 + S2) over n coefficients -> *out (device), via partials
+void mlp_mean_log_l1(const double* s1, const double* s2, long long n, double* partial, double* out, hipStream_t s);
+// feat[i][4] from the iterate (internal order); meanlog and bmax are device scalars
+void mlp_features(const double* s1, const double* s2, const double* beta, const double* diagH,
+                  const double* meanlog, const double* bmax, float* feat, long long n, hipStream_t s);
+void mlp_forward(const float* params, const float* feat, float* c, long long n, hipStream_t s);
+// gradient of sum_i dc_i c_i, accumulated into grad (float, 1249)
+void mlp_backward(const float* params, const float* feat, const float* dc, float* grad, int n, double* scratch,
+                  hipStream_t s);
+// loss (double, device) and gradient (float, overwritten) over n records;
+// scratch holds ceil(n/128) * 1250 doubles
+void mlp_loss_grad(const float* params, const float* feat, const float* rec, int n, double* loss, float* grad,
+                   double* scratch, hipStream_t s);
+void mlp_adam(float* params, const float* grad, float* m, float* v, int t, float lr, hipStream_t s);
+
+// Capture: records at coefficients idx_j = splitmix64(seed + j) mod n,
+// j < npick, from (p, q = K p) and the barrier diagonals; feat_all is the
+// full [n][4] feature array of the iterate.  w_j = 1 / sum_j (pb^2 + pz^2).
+template <typename T>
+void mlp_capture(const T* pb, const T* pz, const T* qb, const T* qz, const T* s1, const T* s2,
+                 const float* feat_all, long long n, int npick, unsigned long long seed, float* out_feat,
+                 float* out_rec, double* partial, hipStream_t s);
+void mlp_scale_weights(float* rec, int npick, float factor, hipStream_t s);
+
+}  // namespace csipm

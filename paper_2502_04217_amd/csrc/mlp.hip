@@ -1,0 +1,342 @@
+// Learned diagonal correction of the preconditioner: feature, inference,
+// training (forward + backward + Adam) and record-capture kernels.  Not in
+// the paper, whose preconditioner P = [[I + L1, L2], [L2, L1]] this corrects
+// (I -> diag(c), c > 0 keeps every 2x2 block positive definite).
+#include "mlp.h"
+
+#include <cmath>
+
+namespace csipm {
+
+namespace {
+
+constexpr int H1 = 32, H2 = 32, NIN = 4;
+constexpr int OW1 = 0, OB1 = OW1 + H1 * NIN, OW2 = OB1 + H1, OB2 = OW2 + H2 * H1, OW3 = OB2 + H2, OB3 = OW3 + H2;
+static_assert(OB3 + 1 == MLP_NP, "parameter layout");
+constexpr int RB = 64;          // records per training workgroup
+constexpr int RP = RB + 1;      // padded LDS row
+
+__device__ __forceinline__ long long gtid() { return blockIdx.x * (long long)blockDim.x + threadIdx.x; }
+__device__ __forceinline__ long long gstride() { return (long long)gridDim.x * blockDim.x; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+__device__ __forceinline__ float sigmoidf(float x) { return 0.5f * (1.0f + tanhf(0.5f * x)); }
+
+__device__ __forceinline__ void load_params(const float* __restrict__ g, float* s) {
+  for (int i = threadIdx.x; i < MLP_NP; i += blockDim.x) s[i] = g[i];
+  __syncthreads();
+}
+
+// forward of one coefficient; returns o (pre-activation of the output)
+__device__ __forceinline__ float fwd1(const float* P, const float x[NIN], float h1[H1], float h2[H2]) {
+#pragma unroll
+  for (int i = 0; i < H1; ++i) {
+    float a = P[OB1 + i];
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) a = fmaf(P[OW1 + i * NIN + j], x[j], a);
+    h1[i] = tanhf(a);
+  }
+  float o = P[OB3];
+#pragma unroll 4
+  for (int i = 0; i < H2; ++i) {
+    float a = P[OB2 + i];
+#pragma unroll
+    for (int j = 0; j < H1; ++j) a = fmaf(P[OW2 + i * H1 + j], h1[j], a);
+    h2[i] = tanhf(a);
+    o = fmaf(P[OW3 + i], h2[i], o);
+  }
+  return o;
+}
+
+__global__ void __launch_bounds__(256)
+k_forward(const float* __restrict__ params, const float* __restrict__ feat, float* __restrict__ c, long long n) {
+  __shared__ float P[MLP_NP];
+  load_params(params, P);
+  for (long long i = gtid(); i < n; i += gstride()) {
+    const float4 f = reinterpret_cast<const float4*>(feat)[i];
+    const float x[NIN] = {f.x, f.y, f.z, f.w};
+    float h1[H1], h2[H2];
+    const float o = fwd1(P, x, h1, h2);
+    c[i] = softplusf(o) + 1e-6f;
+  }
+}
+
+// Per-block gradient partials over RB records.  mode 0: dc given (backward of
+// sum dc*c); mode 1: records, dc from the loss derivative, loss accumulated.
+// scratch[block][0..1248] gradient partials, scratch[block][1249] loss.
+template <int MODE>
+__global__ void __launch_bounds__(RB)
+k_grad_block(const float* __restrict__ params, const float* __restrict__ feat, const float* __restrict__ aux,
+             int n, double* __restrict__ scratch) {
+  __shared__ float P[MLP_NP];
+  __shared__ float xs[NIN][RP], h1s[H1][RP], h2s[H2][RP], d1s[H1][RP], d2s[H2][RP], dos[RP];
+  load_params(params, P);
+  const int r = threadIdx.x;
+  const int idx = blockIdx.x * RB + r;
+  float x[NIN] = {0, 0, 0, 0}, h1[H1], h2[H2];
+  float dout = 0.0f;
+  double e = 0.0;
+  if (idx < n) {
+    const float4 f = reinterpret_cast<const float4*>(feat)[idx];
+    x[0] = f.x; x[1] = f.y; x[2] = f.z; x[3] = f.w;
+    const float o = fwd1(P, x, h1, h2);
+    float dc;
+    if constexpr (MODE == 0) {
+      dc = aux[idx];
+    } else {
+      const float c = softplusf(o) + 1e-6f;
+      const float* rc = aux + (long long)idx * MLP_REC;
+      const double u = rc[0], p = rc[1], L1 = rc[2], L2 = rc[3], S12 = rc[4], w = rc[5];
+      const double D = (double)c * L1 + S12;
+      const double res = u - (double)c * p;
+      const double a = L1 * L1 + L2 * L2;
+      e = w * a * res * res / (D * D);
+      dc = (float)(w * a * (-2.0 * p * res / (D * D) - 2.0 * res * res * L1 / (D * D * D)));
+    }
+    dout = dc * sigmoidf(o);
+  } else {
+#pragma unroll
+    for (int i = 0; i < H1; ++i) h1[i] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < H2; ++i) h2[i] = 0.0f;
+  }
+  // back-propagate to the hidden pre-activations
+  float d2[H2];
+#pragma unroll
+  for (int i = 0; i < H2; ++i) d2[i] = dout * P[OW3 + i] * (1.0f - h2[i] * h2[i]);
+#pragma unroll 4
+  for (int j = 0; j < H1; ++j) {
+    float a = 0.0f;
+#pragma unroll
+    for (int i = 0; i < H2; ++i) a = fmaf(d2[i], P[OW2 + i * H1 + j], a);
+    d1s[j][r] = a * (1.0f - h1[j] * h1[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < NIN; ++j) xs[j][r] = x[j];
+#pragma unroll
+  for (int i = 0; i < H1; ++i) h1s[i][r] = h1[i];
+#pragma unroll
+  for (int i = 0; i < H2; ++i) {
+    h2s[i][r] = h2[i];
+    d2s[i][r] = d2[i];
+  }
+  dos[r] = dout;
+  __syncthreads();
+  double* out = scratch + (long long)blockIdx.x * (MLP_NP + 1);
+  for (int p = r; p < MLP_NP; p += RB) {
+    double g = 0.0;
+    if (p < OB1) {
+      const int i = p / NIN, j = p % NIN;
+      for (int k = 0; k < RB; ++k) g += (double)d1s[i][k] * (double)xs[j][k];
+    } else if (p < OW2) {
+      const int i = p - OB1;
+      for (int k = 0; k < RB; ++k) g += (double)d1s[i][k];
+    } else if (p < OB2) {
+      const int i = (p - OW2) / H1, j = (p - OW2) % H1;
+      for (int k = 0; k < RB; ++k) g += (double)d2s[i][k] * (double)h1s[j][k];
+    } else if (p < OW3) {
+      const int i = p - OB2;
+      for (int k = 0; k < RB; ++k) g += (double)d2s[i][k];
+    } else if (p < OB3) {
+      const int i = p - OW3;
+      for (int k = 0; k < RB; ++k) g += (double)dos[k] * (double)h2s[i][k];
+    } else {
+      for (int k = 0; k < RB; ++k) g += (double)dos[k];
+    }
+    out[p] = g;
+  }
+  e = wave_sum(e);
+  if (r == 0) out[MLP_NP] = e;
+}
+
+// Sums the block partials in block order.  accumulate: grad += (else =).
+__global__ void __launch_bounds__(256)
+k_grad_reduce(const double* __restrict__ scratch, int nblk, float* __restrict__ grad, double* __restrict__ loss,
+              int accumulate) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p <= MLP_NP; p += gridDim.x * blockDim.x) {
+    double g = 0.0;
+    for (int b = 0; b < nblk; ++b) g += scratch[(long long)b * (MLP_NP + 1) + p];
+    if (p < MLP_NP) {
+      grad[p] = accumulate ? (float)((double)grad[p] + g) : (float)g;
+    } else if (loss) {
+      *loss = g;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_adam(float* __restrict__ params, const float* __restrict__ grad, float* __restrict__ m, float* __restrict__ v,
+       float b1t, float b2t, float lr) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MLP_NP) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float g = grad[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * g;
+  const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / (1.0f - b1t);
+  const float vh = vi / (1.0f - b2t);
+  params[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void __launch_bounds__(256)
+k_log_l1(const double* __restrict__ s1, const double* __restrict__ s2, long long n, double* partial) {
+  double a = 0.0;
+  for (long long i = gtid(); i < n; i += gstride()) a += log(s1[i] + s2[i]);
+  __shared__ double red[4];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256)
+k_fin_mean(const double* partial, int nb, double scale, double* out) {
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) a += partial[i];
+  __shared__ double red[4];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (red[0] + red[1] + red[2] + red[3]) * scale;
+}
+
+__global__ void __launch_bounds__(256)
+k_features(const double* __restrict__ s1, const double* __restrict__ s2, const double* __restrict__ beta,
+           const double* __restrict__ diagH, const double* __restrict__ meanlog, const double* __restrict__ bmax,
+           float* __restrict__ feat, long long n) {
+  const double ml = *meanlog;
+  const double bm = *bmax > 0.0 ? *bmax : 1.0;
+  for (long long i = gtid(); i < n; i += gstride()) {
+    const double L1 = s1[i] + s2[i], L2 = s1[i] - s2[i];
+    float4 f;
+    f.x = (float)(log(L1) - ml);
+    f.y = (float)(L2 / L1);
+    f.z = (float)log(fabs(beta[i]) / bm + 1e-12);
+    f.w = (float)diagH[i];
+    reinterpret_cast<float4*>(feat)[i] = f;
+  }
+}
+
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_capture(const T* __restrict__ pb, const T* __restrict__ pz, const T* __restrict__ qb, const T* __restrict__ qz,
+          const T* __restrict__ s1, const T* __restrict__ s2, const float* __restrict__ feat_all, long long n,
+          int npick, unsigned long long seed, float* __restrict__ of, float* __restrict__ orc, double* partial) {
+  double acc = 0.0;
+  for (long long j = gtid(); j < npick; j += gstride()) {
+    const long long i = (long long)(splitmix64(seed + (unsigned long long)j) % (unsigned long long)n);
+    const double b = pb[i], z = pz[i], g1 = s1[i], g2 = s2[i];
+    const double u = (double)qb[i] - g1 * (b + z) - g2 * (b - z);
+    float* rc = orc + j * MLP_REC;
+    rc[0] = (float)u;
+    rc[1] = (float)b;
+    rc[2] = (float)(g1 + g2);
+    rc[3] = (float)(g1 - g2);
+    rc[4] = (float)(4.0 * g1 * g2);
+    rc[5] = 1.0f;
+    reinterpret_cast<float4*>(of)[j] = reinterpret_cast<const float4*>(feat_all)[i];
+    acc += b * b + z * z;
+  }
+  __shared__ double red[4];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256)
+k_set_weights(float* __restrict__ rec, int npick, const double* __restrict__ total) {
+  const double t = *total;
+  const float w = t > 0.0 ? (float)(1.0 / t) : 0.0f;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < npick; j += gridDim.x * blockDim.x) rec[j * MLP_REC + 5] = w;
+}
+
+__global__ void __launch_bounds__(256)
+k_scale_weights(float* __restrict__ rec, int npick, float f) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < npick; j += gridDim.x * blockDim.x) rec[j * MLP_REC + 5] *= f;
+}
+
+int blocks_for(long long n) {
+  long long b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+void mlp_mean_log_l1(const double* s1, const double* s2, long long n, double* partial, double* out, hipStream_t s) {
+  const int nb = blocks_for(n);
+  hipLaunchKernelGGL(k_log_l1, dim3(nb), dim3(256), 0, s, s1, s2, n, partial);
+  hipLaunchKernelGGL(k_fin_mean, dim3(1), dim3(256), 0, s, partial, nb, 1.0 / (double)n, out);
+}
+
+void mlp_features(const double* s1, const double* s2, const double* beta, const double* diagH, const double* meanlog,
+                  const double* bmax, float* feat, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_features, dim3(blocks_for(n)), dim3(256), 0, s, s1, s2, beta, diagH, meanlog, bmax, feat, n);
+}
+
+void mlp_forward(const float* params, const float* feat, float* c, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_forward, dim3(blocks_for(n)), dim3(256), 0, s, params, feat, c, n);
+}
+
+void mlp_backward(const float* params, const float* feat, const float* dc, float* grad, int n, double* scratch,
+                  hipStream_t s) {
+  const int nblk = (n + RB - 1) / RB;
+  hipLaunchKernelGGL((k_grad_block<0>), dim3(nblk), dim3(RB), 0, s, params, feat, dc, n, scratch);
+  hipLaunchKernelGGL(k_grad_reduce, dim3((MLP_NP + 256) / 256), dim3(256), 0, s, scratch, nblk, grad,
+                     (double*)nullptr, 1);
+}
+
+void mlp_loss_grad(const float* params, const float* feat, const float* rec, int n, double* loss, float* grad,
+                   double* scratch, hipStream_t s) {
+  const int nblk = (n + RB - 1) / RB;
+  hipLaunchKernelGGL((k_grad_block<1>), dim3(nblk), dim3(RB), 0, s, params, feat, rec, n, scratch);
+  hipLaunchKernelGGL(k_grad_reduce, dim3((MLP_NP + 256) / 256), dim3(256), 0, s, scratch, nblk, grad, loss, 0);
+}
+
+void mlp_adam(float* params, const float* grad, float* m, float* v, int t, float lr, hipStream_t s) {
+  const float b1t = (float)std::pow(0.9, (double)t);
+  const float b2t = (float)std::pow(0.999, (double)t);
+  hipLaunchKernelGGL(k_adam, dim3((MLP_NP + 255) / 256), dim3(256), 0, s, params, grad, m, v, b1t, b2t, lr);
+}
+
+template <typename T>
+void mlp_capture(const T* pb, const T* pz, const T* qb, const T* qz, const T* s1, const T* s2, const float* feat_all,
+                 long long n, int npick, unsigned long long seed, float* out_feat, float* out_rec, double* partial,
+                 hipStream_t s) {
+  const int nb = blocks_for(npick);
+  hipLaunchKernelGGL((k_capture<T>), dim3(nb), dim3(256), 0, s, pb, pz, qb, qz, s1, s2, feat_all, n, npick, seed,
+                     out_feat, out_rec, partial);
+  double* total = partial + 4096;
+  hipLaunchKernelGGL(k_fin_mean, dim3(1), dim3(256), 0, s, partial, nb, 1.0, total);
+  hipLaunchKernelGGL(k_set_weights, dim3(blocks_for(npick)), dim3(256), 0, s, out_rec, npick, (const double*)total);
+}
+
+void mlp_scale_weights(float* rec, int npick, float factor, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_weights, dim3(blocks_for(npick)), dim3(256), 0, s, rec, npick, factor);
+}
+
+template void mlp_capture<double>(const double*, const double*, const double*, const double*, const double*,
+                                  const double*, const float*, long long, int, unsigned long long, float*, float*,
+                                  double*, hipStream_t);
+template void mlp_capture<float>(const float*, const float*, const float*, const float*, const float*, const float*,
+                                 const float*, long long, int, unsigned long long, float*, float*, double*,
+                                 hipStream_t);
+
+}  // namespace csipm

@@ -1,0 +1,87 @@
+// Krylov / interior-point kernel launchers (vec.hip) and the device scalar
+// slots they share with the host driver.
+#pragma once
+
+#include "csipm_internal.h"
+
+namespace csipm {
+
+constexpr int VEC_MAX_BLOCKS = 4096;   // partial sums per reduced quantity
+
+enum RedOp { RED_SUM = 0, RED_MAX = 1, RED_MIN = 2 };
+template <int NQ>
+struct RedOps {
+  int op[NQ];
+};
+
+// double slots of the device scalar block
+enum ScalarSlot {
+  S_RZ = 0,        // current r.P^{-1}r
+  S_RZ0 = 1,       // initial r.P^{-1}r
+  S_PQ = 2,        // p.Kp
+  S_ALPHA = 3,     // CG step
+  S_BETA = 4,      // CG direction update
+  S_TOL = 5,       // stopping threshold on sqrt(r.P^{-1}r)
+  S_RES = 6,       // sqrt(r.P^{-1}r) now
+  S_AMAX = 8,      // IPM: largest feasible step
+  S_ALPHA_IPM = 9, // IPM: step taken
+  S_RESID = 16,    // IPM residual block, 7 values (k_ipm_resid order)
+  S_REF = 24,      // refinement: r.P^{-1}r of the FP64 residual
+  S_REF0 = 25,     // refinement: rhs.P^{-1}rhs
+  S_SIG = 28,      // signal check: non-finite count, observed count
+  S_MISC = 32,     // free scratch (32 values)
+  S_COUNT = 64
+};
+// int slots of the device flag block
+enum FlagSlot { F_DONE = 0, F_IT = 1, F_MAXIT = 2, F_BREAK = 3, F_COUNT = 8 };
+
+int vec_blocks(long long n);
+
+template <typename T>
+void cg_init(const T* hb, const T* hz, T* xb, T* xz, T* rb, T* rz, T* zb, T* zz, T* pb, T* pz, const T* s1,
+             const T* s2, const float* c, long long n, double* partial, hipStream_t s);
+template <typename T>
+void cg_update(T* xb, T* xz, const T* pb, const T* pz, const T* qb, const T* qz, T* rb, T* rz, T* zb, T* zz,
+               const T* s1, const T* s2, const float* c, const double* scal, const int* flags, long long n,
+               double* partial, hipStream_t s);
+template <typename T>
+void cg_pupdate(T* pb, T* pz, const T* zb, const T* zz, const double* scal, const int* flags, long long n,
+                hipStream_t s);
+void fin_cg_init(const double* partial, int nb, double* scal, int* flags, double eta, double atol, int maxit,
+                 hipStream_t s);
+void fin_alpha(const double* partial, int nb, double* scal, int* flags, hipStream_t s);
+void fin_rz(const double* partial, int nb, double* scal, int* flags, hipStream_t s);
+
+void ipm_init(double* beta, double* z, double* nu1, double* nu2, long long n, double z0, double lam,
+              hipStream_t s);
+void ipm_resid(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
+               const double* xi, double lam, long long n, double* partial, double* out7, hipStream_t s);
+template <typename T>
+void ipm_newton(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
+                const double* xi, double lam, double smu, double* sig1, double* sig2, double* rb, double* rz,
+                T* sig1f, T* sig2f, long long n, hipStream_t s);
+void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* sig1,
+              const double* sig2, const double* db, const double* dz, double smu, double tau, long long n,
+              double* partial, double* scal, hipStream_t s);
+void ipm_update(double* beta, double* z, double* nu1, double* nu2, const double* sig1, const double* sig2,
+                const double* db, const double* dz, double smu, const double* scal, long long n, hipStream_t s);
+
+void cast_d2f(const double* a, const double* b, float* oa, float* ob, long long n, hipStream_t s);
+void cast_f2d(const float* a, const float* b, double* oa, double* ob, long long n, hipStream_t s);
+void copy2(const double* a, const double* b, double* oa, double* ob, long long n, hipStream_t s);
+void add_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s);
+void ref_resid(const double* hb, const double* hz, const double* qb, const double* qz, double* rb, double* rz,
+               const double* s1, const double* s2, const float* c, long long n, double* partial, double* out,
+               hipStream_t s);
+template <typename T>
+void pinv_apply(const T* rb, const T* rz, T* zb, T* zz, const T* s1, const T* s2, const float* c, long long n,
+                double* partial, double* out, hipStream_t s);
+void check_signal(const double* sig, const uint8_t* obs, long long n, double* partial, double* out2, hipStream_t s);
+void zero_fill(const double* sig, const uint8_t* obs, double* out, long long n, hipStream_t s);
+void obs_to_double(const uint8_t* obs, double* out, long long n, hipStream_t s);
+template <typename T>
+void fill(T* a, T v, long long n, hipStream_t s);
+void absmax(const double* a, long long n, double* partial, double* out, hipStream_t s);
+void diag_h(const double* bm_ext, double* out_ext, int n1, int n2, int n3, double mfrac, hipStream_t s);
+
+}  // namespace csipm

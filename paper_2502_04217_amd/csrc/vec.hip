@@ -1,0 +1,623 @@
+// Elementwise kernels of the Krylov solver and the interior-point method,
+// each fused with the reductions it needs (paper: sections "Primal-dual
+// interior-point method", "Condensed KKT system", "Krylov methods and
+// preconditioners").  Every reduction is two-stage and deterministic: a fixed
+// grid writes one partial per workgroup, then a single-workgroup finalize
+// kernel combines the partials in a fixed order and applies the scalar logic
+// (alpha, beta, stopping test) on the device.
+#include "vec.h"
+
+#include <cmath>
+
+namespace csipm {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block (256 threads) reduction of NQ values with per-value op; thread 0
+// writes out[q * stride + blockIdx.x].
+template <int NQ>
+__device__ __forceinline__ void block_reduce_store(double* v, const int* ops, double* out, int stride) {
+  __shared__ double red[NQ][4];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double x = v[q];
+    x = ops[q] == RED_SUM ? wave_sum(x) : ops[q] == RED_MAX ? wave_max(x) : wave_min(x);
+    if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double x = red[q][0];
+      for (int w = 1; w < 4; ++w)
+        x = ops[q] == RED_SUM ? x + red[q][w] : ops[q] == RED_MAX ? fmax(x, red[q][w]) : fmin(x, red[q][w]);
+      out[q * stride + blockIdx.x] = x;
+    }
+  }
+}
+
+__device__ __forceinline__ double block_sum_256(double v) {
+  __shared__ double red[4];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return s;
+}
+
+// P_c^{-1} r for one 2x2 block (equation "invprecond1" with C = diag(c)),
+// coefficients formed in double.
+template <typename T>
+__device__ __forceinline__ void pinv1(T rb, T rz, T s1, T s2, double c, T& zb, T& zz) {
+  const double S1 = (double)s1, S2 = (double)s2;
+  const double L1 = S1 + S2, L2 = S1 - S2;
+  const double inv = 1.0 / (c * L1 + 4.0 * S1 * S2);
+  zb = (T)((L1 * (double)rb - L2 * (double)rz) * inv);
+  zz = (T)((-L2 * (double)rb + (c + L1) * (double)rz) * inv);
+}
+
+__device__ __forceinline__ long long gtid() { return blockIdx.x * (long long)blockDim.x + threadIdx.x; }
+__device__ __forceinline__ long long gstride() { return (long long)gridDim.x * blockDim.x; }
+
+// ------------------------------------------------------------------- PCG --
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_cg_init(const T* __restrict__ hb, const T* __restrict__ hz, T* __restrict__ xb, T* __restrict__ xz,
+          T* __restrict__ rb, T* __restrict__ rz, T* __restrict__ zb, T* __restrict__ zz, T* __restrict__ pb,
+          T* __restrict__ pz, const T* __restrict__ s1, const T* __restrict__ s2, const float* __restrict__ c,
+          long long n, double* partial) {
+  double acc = 0.0;
+  for (long long i = gtid(); i < n; i += gstride()) {
+    const T b = hb[i], z = hz[i];
+    T ub, uz;
+    pinv1<T>(b, z, s1[i], s2[i], c ? (double)c[i] : 1.0, ub, uz);
+    xb[i] = T(0);
+    xz[i] = T(0);
+    rb[i] = b;
+    rz[i] = z;
+    zb[i] = ub;
+    zz[i] = uz;
+    pb[i] = ub;
+    pz[i] = uz;
+    acc += (double)b * (double)ub + (double)z * (double)uz;
+  }
+  const int op = RED_SUM;
+  block_reduce_store<1>(&acc, &op, partial, 0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_cg_update(T* __restrict__ xb, T* __restrict__ xz, const T* __restrict__ pb, const T* __restrict__ pz,
+            const T* __restrict__ qb, const T* __restrict__ qz, T* __restrict__ rb, T* __restrict__ rz,
+            T* __restrict__ zb, T* __restrict__ zz, const T* __restrict__ s1, const T* __restrict__ s2,
+            const float* __restrict__ c, const double* __restrict__ scal, const int* __restrict__ flags,
+            long long n, double* partial) {
+  if (flags[F_DONE]) return;
+  const T a = (T)scal[S_ALPHA];
+  double acc = 0.0;
+  for (long long i = gtid(); i < n; i += gstride()) {
+    xb[i] += a * pb[i];
+    xz[i] += a * pz[i];
+    const T b = rb[i] - a * qb[i];
+    const T z = rz[i] - a * qz[i];
+    rb[i] = b;
+    rz[i] = z;
+    T ub, uz;
+    pinv1<T>(b, z, s1[i], s2[i], c ? (double)c[i] : 1.0, ub, uz);
+    zb[i] = ub;
+    zz[i] = uz;
+    acc += (double)b * (double)ub + (double)z * (double)uz;
+  }
+  const int op = RED_SUM;
+  block_reduce_store<1>(&acc, &op, partial, 0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_cg_pupdate(T* __restrict__ pb, T* __restrict__ pz, const T* __restrict__ zb, const T* __restrict__ zz,
+             const double* __restrict__ scal, const int* __restrict__ flags, long long n) {
+  if (flags[F_DONE]) return;
+  const T be = (T)scal[S_BETA];
+  for (long long i = gtid(); i < n; i += gstride()) {
+    pb[i] = zb[i] + be * pb[i];
+    pz[i] = zz[i] + be * pz[i];
+  }
+}
+
+__device__ __forceinline__ double fin_sum(const double* partial, int nb) {
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) a += partial[i];
+  return block_sum_256(a);
+}
+
+__global__ void __launch_bounds__(256)
+k_fin_cg_init(const double* partial, int nb, double* scal, int* flags, double eta, double atol, int maxit) {
+  const double rz0 = fin_sum(partial, nb);
+  if (threadIdx.x == 0) {
+    scal[S_RZ] = rz0;
+    scal[S_RZ0] = rz0;
+    const double r0 = sqrt(fmax(rz0, 0.0));
+    const double tol = fmax(atol, eta * r0);
+    scal[S_TOL] = tol;
+    scal[S_RES] = r0;
+    flags[F_IT] = 0;
+    flags[F_BREAK] = 0;
+    flags[F_DONE] = (r0 <= tol || maxit <= 0 || !(rz0 == rz0)) ? 1 : 0;
+    flags[F_MAXIT] = maxit;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_fin_alpha(const double* partial, int nb, double* scal, int* flags) {
+  if (flags[F_DONE]) return;
+  const double pq = fin_sum(partial, nb);
+  if (threadIdx.x == 0) {
+    scal[S_PQ] = pq;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      // loss of positive definiteness in floating point: stop the solve
+      scal[S_ALPHA] = 0.0;
+      flags[F_BREAK] = 1;
+      flags[F_DONE] = 1;
+    } else {
+      scal[S_ALPHA] = scal[S_RZ] / pq;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_fin_rz(const double* partial, int nb, double* scal, int* flags) {
+  if (flags[F_DONE]) return;
+  const double rz = fin_sum(partial, nb);
+  if (threadIdx.x == 0) {
+    scal[S_BETA] = rz / scal[S_RZ];
+    scal[S_RZ] = rz;
+    const double r = sqrt(fmax(rz, 0.0));
+    scal[S_RES] = r;
+    const int it = flags[F_IT] + 1;
+    flags[F_IT] = it;
+    flags[F_DONE] = (r <= scal[S_TOL] || it >= flags[F_MAXIT] || !isfinite(rz)) ? 1 : 0;
+  }
+}
+
+// ------------------------------------------------------------------- IPM --
+__global__ void __launch_bounds__(256)
+k_ipm_init(double* __restrict__ beta, double* __restrict__ z, double* __restrict__ nu1, double* __restrict__ nu2,
+           long long n, double z0, double lam) {
+  for (long long i = gtid(); i < n; i += gstride()) {
+    beta[i] = 0.0;
+    z[i] = z0;
+    nu1[i] = 0.5 * lam;
+    nu2[i] = 0.5 * lam;
+  }
+}
+
+// Residual parts of the KKT system (equation "kkt", first two rows) and
+// complementarity: [max|F_b|, max|F_z|, max s.nu, sum s.nu, max|beta|,
+// min(s, nu), count of non-finite values].
+__global__ void __launch_bounds__(256)
+k_ipm_resid(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
+            const double* __restrict__ nu2, const double* __restrict__ hb, const double* __restrict__ xi,
+            double lam, long long n, double* partial, int stride) {
+  double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0};
+  for (long long i = gtid(); i < n; i += gstride()) {
+    const double b = beta[i], zz = z[i], a1 = nu1[i], a2 = nu2[i];
+    const double s1 = zz + b, s2 = zz - b;
+    const double fb = hb[i] - xi[i] - a1 + a2;
+    const double fz = lam - a1 - a2;
+    const double c1 = s1 * a1, c2 = s2 * a2;
+    v[0] = fmax(v[0], fabs(fb));
+    v[1] = fmax(v[1], fabs(fz));
+    v[2] = fmax(v[2], fmax(c1, c2));
+    v[3] += c1 + c2;
+    v[4] = fmax(v[4], fabs(b));
+    v[5] = fmin(v[5], fmin(fmin(s1, s2), fmin(a1, a2)));
+    if (!isfinite(fb) || !isfinite(c1) || !isfinite(c2)) v[6] += 1.0;
+  }
+  const int ops[7] = {RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM};
+  block_reduce_store<7>(v, ops, partial, stride);
+}
+
+// Newton system of one iteration: barrier diagonals and the right-hand side
+//   r_beta = -(H beta - xi) + smu (1/s1 - 1/s2),  r_z = -lam + smu (1/s1 + 1/s2)
+// (derived from equation "kktmu"), smu = sigma * mu.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_ipm_newton(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
+             const double* __restrict__ nu2, const double* __restrict__ hb, const double* __restrict__ xi,
+             double lam, double smu, double* __restrict__ sig1, double* __restrict__ sig2,
+             double* __restrict__ rb, double* __restrict__ rz, T* __restrict__ sig1f, T* __restrict__ sig2f,
+             long long n) {
+  for (long long i = gtid(); i < n; i += gstride()) {
+    const double b = beta[i], zz = z[i];
+    const double s1 = zz + b, s2 = zz - b;
+    const double i1 = 1.0 / s1, i2 = 1.0 / s2;
+    const double g1 = nu1[i] * i1, g2 = nu2[i] * i2;
+    sig1[i] = g1;
+    sig2[i] = g2;
+    rb[i] = -(hb[i] - xi[i]) + smu * (i1 - i2);
+    rz[i] = -lam + smu * (i1 + i2);
+    if (sig1f) {
+      sig1f[i] = (T)g1;
+      sig2f[i] = (T)g2;
+    }
+  }
+}
+
+// Largest step keeping s and nu positive, with
+//   ds1 = db + dz, ds2 = dz - db, dnu_j = smu/s_j - nu_j - Sigma_j ds_j.
+__global__ void __launch_bounds__(256)
+k_ipm_ratio(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
+            const double* __restrict__ nu2, const double* __restrict__ sig1, const double* __restrict__ sig2,
+            const double* __restrict__ db, const double* __restrict__ dz, double smu, long long n,
+            double* partial) {
+  double amax = INFINITY;
+  for (long long i = gtid(); i < n; i += gstride()) {
+    const double b = beta[i], zz = z[i];
+    const double s1 = zz + b, s2 = zz - b;
+    const double ds1 = db[i] + dz[i], ds2 = dz[i] - db[i];
+    const double dn1 = smu / s1 - nu1[i] - sig1[i] * ds1;
+    const double dn2 = smu / s2 - nu2[i] - sig2[i] * ds2;
+    if (ds1 < 0.0) amax = fmin(amax, -s1 / ds1);
+    if (ds2 < 0.0) amax = fmin(amax, -s2 / ds2);
+    if (dn1 < 0.0) amax = fmin(amax, -nu1[i] / dn1);
+    if (dn2 < 0.0) amax = fmin(amax, -nu2[i] / dn2);
+  }
+  const int op = RED_MIN;
+  block_reduce_store<1>(&amax, &op, partial, 0);
+}
+
+__global__ void __launch_bounds__(256)
+k_fin_step(const double* partial, int nb, double tau, double* scal) {
+  double a = INFINITY;
+  for (int i = threadIdx.x; i < nb; i += 256) a = fmin(a, partial[i]);
+  a = wave_min(a);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double amax = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+    scal[S_AMAX] = amax;
+    scal[S_ALPHA_IPM] = fmin(1.0, tau * amax);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_ipm_update(double* __restrict__ beta, double* __restrict__ z, double* __restrict__ nu1, double* __restrict__ nu2,
+             const double* __restrict__ sig1, const double* __restrict__ sig2, const double* __restrict__ db,
+             const double* __restrict__ dz, double smu, const double* __restrict__ scal, long long n) {
+  const double a = scal[S_ALPHA_IPM];
+  for (long long i = gtid(); i < n; i += gstride()) {
+    const double b = beta[i], zz = z[i];
+    const double s1 = zz + b, s2 = zz - b;
+    const double ds1 = db[i] + dz[i], ds2 = dz[i] - db[i];
+    const double dn1 = smu / s1 - nu1[i] - sig1[i] * ds1;
+    const double dn2 = smu / s2 - nu2[i] - sig2[i] * ds2;
+    beta[i] = b + a * db[i];
+    z[i] = zz + a * dz[i];
+    nu1[i] += a * dn1;
+    nu2[i] += a * dn2;
+  }
+}
+
+// Generic multi-value finalize: out[q] = op_q over partial[q*stride + 0..nb).
+template <int NQ>
+__global__ void __launch_bounds__(256)
+k_fin_reduce(const double* partial, int nb, int stride, double* out, RedOps<NQ> ops) {
+  for (int q = 0; q < NQ; ++q) {
+    const int op = ops.op[q];
+    double a = op == RED_SUM ? 0.0 : op == RED_MAX ? -INFINITY : INFINITY;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+      const double x = partial[q * stride + i];
+      a = op == RED_SUM ? a + x : op == RED_MAX ? fmax(a, x) : fmin(a, x);
+    }
+    a = op == RED_SUM ? wave_sum(a) : op == RED_MAX ? wave_max(a) : wave_min(a);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double x = red[0];
+      for (int w = 1; w < 4; ++w) x = op == RED_SUM ? x + red[w] : op == RED_MAX ? fmax(x, red[w]) : fmin(x, red[w]);
+      out[q] = x;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------- mixed precision glue --
+template <typename Ti, typename To>
+__global__ void __launch_bounds__(256)
+k_cast2(const Ti* __restrict__ a, const Ti* __restrict__ b, To* __restrict__ oa, To* __restrict__ ob, long long n) {
+  for (long long i = gtid(); i < n; i += gstride()) {
+    oa[i] = (To)a[i];
+    ob[i] = (To)b[i];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_add_f2d(double* __restrict__ db, double* __restrict__ dz, const float* __restrict__ eb,
+          const float* __restrict__ ez, long long n) {
+  for (long long i = gtid(); i < n; i += gstride()) {
+    db[i] += (double)eb[i];
+    dz[i] += (double)ez[i];
+  }
+}
+
+// r = h - q and partial sums of r.P^{-1}r (FP64 refinement residual).
+__global__ void __launch_bounds__(256)
+k_ref_resid(const double* __restrict__ hb, const double* __restrict__ hz, const double* __restrict__ qb,
+            const double* __restrict__ qz, double* __restrict__ rb, double* __restrict__ rz,
+            const double* __restrict__ s1, const double* __restrict__ s2, const float* __restrict__ c,
+            long long n, double* partial) {
+  double acc = 0.0;
+  for (long long i = gtid(); i < n; i += gstride()) {
+    const double b = hb[i] - qb[i], z = hz[i] - qz[i];
+    rb[i] = b;
+    rz[i] = z;
+    double ub, uz;
+    pinv1<double>(b, z, s1[i], s2[i], c ? (double)c[i] : 1.0, ub, uz);
+    acc += b * ub + z * uz;
+  }
+  const int op = RED_SUM;
+  block_reduce_store<1>(&acc, &op, partial, 0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_pinv(const T* __restrict__ rb, const T* __restrict__ rz, T* __restrict__ zb, T* __restrict__ zz,
+       const T* __restrict__ s1, const T* __restrict__ s2, const float* __restrict__ c, long long n,
+       double* partial) {
+  double acc = 0.0;
+  for (long long i = gtid(); i < n; i += gstride()) {
+    T ub, uz;
+    pinv1<T>(rb[i], rz[i], s1[i], s2[i], c ? (double)c[i] : 1.0, ub, uz);
+    zb[i] = ub;
+    zz[i] = uz;
+    acc += (double)rb[i] * (double)ub + (double)rz[i] * (double)uz;
+  }
+  const int op = RED_SUM;
+  block_reduce_store<1>(&acc, &op, partial, 0);
+}
+
+// Non-finite count over observed samples of the signal.
+__global__ void __launch_bounds__(256)
+k_check_signal(const double* __restrict__ sig, const uint8_t* __restrict__ obs, long long n, double* partial) {
+  double bad = 0.0, nobs = 0.0;
+  for (long long i = gtid(); i < n; i += gstride()) {
+    if (obs[i]) {
+      nobs += 1.0;
+      if (!isfinite(sig[i])) bad += 1.0;
+    }
+  }
+  double v[2] = {bad, nobs};
+  const int ops[2] = {RED_SUM, RED_SUM};
+  block_reduce_store<2>(v, ops, partial, VEC_MAX_BLOCKS);
+}
+
+__global__ void __launch_bounds__(256)
+k_zero_fill(const double* __restrict__ sig, const uint8_t* __restrict__ obs, double* __restrict__ out, long long n) {
+  for (long long i = gtid(); i < n; i += gstride()) out[i] = obs[i] ? sig[i] : 0.0;
+}
+
+__global__ void __launch_bounds__(256)
+k_obs_to_double(const uint8_t* __restrict__ obs, double* __restrict__ out, long long n) {
+  for (long long i = gtid(); i < n; i += gstride()) out[i] = obs[i] ? 1.0 : 0.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fill(T* __restrict__ a, T v, long long n) {
+  for (long long i = gtid(); i < n; i += gstride()) a[i] = v;
+}
+
+
+__global__ void __launch_bounds__(256)
+k_absmax(const double* __restrict__ a, long long n, double* partial) {
+  double v = 0.0;
+  for (long long i = gtid(); i < n; i += gstride()) v = fmax(v, fabs(a[i]));
+  const int op = RED_MAX;
+  block_reduce_store<1>(&v, &op, partial, 0);
+}
+
+// 3D class of a frequency: 0 self-conjugate, 1 canonical, 2 mirror of one.
+__device__ __forceinline__ int cls3(int k1, int k2, int k3, int n1, int n2, int n3) {
+  const bool e1 = k1 == 0 || 2 * k1 == n1, e2 = k2 == 0 || 2 * k2 == n2, e3 = k3 == 0 || 2 * k3 == n3;
+  if (e1 && e2 && e3) return 0;
+  if (k3 >= 1 && 2 * k3 < n3) return 1;
+  if (e3 && k2 >= 1 && 2 * k2 < n2) return 1;
+  if (e3 && e2 && k1 >= 1 && 2 * k1 < n1) return 1;
+  return 2;
+}
+
+// diag(M_perp^T M_perp) in the external beta layout from bm = A^T(mask):
+// column i of A squared is (1/n)(1 + s_i cos(2 theta)), so
+// H_ii = m/n + s_i Re(v_{2k}) / sqrt(n) with v the unitary DFT of the mask
+// and s_i = +1 / -1 / 0 for the sqrt2 Re / sqrt2 Im / self-conjugate entry.
+__global__ void __launch_bounds__(256)
+k_diag_h(const double* __restrict__ bm, double* __restrict__ out, int n1, int n2, int n3, double mfrac,
+         double rsqn) {
+  const long long n = (long long)n1 * n2 * n3;
+  const double rs2 = 0.70710678118654752440;
+  for (long long f = gtid(); f < n; f += gstride()) {
+    const int k3 = (int)(f % n3);
+    const int k2 = (int)((f / n3) % n2);
+    const int k1 = (int)(f / ((long long)n2 * n3));
+    const int ck = cls3(k1, k2, k3, n1, n2, n3);
+    const int q1 = (2 * k1) % n1, q2 = (2 * k2) % n2, q3 = (2 * k3) % n3;
+    const int cq = cls3(q1, q2, q3, n1, n2, n3);
+    double rev;
+    if (cq == 0) {
+      rev = bm[((long long)q1 * n2 + q2) * n3 + q3];
+    } else if (cq == 1) {
+      rev = rs2 * bm[((long long)q1 * n2 + q2) * n3 + q3];
+    } else {
+      const int m1 = (n1 - q1) % n1, m2 = (n2 - q2) % n2, m3 = (n3 - q3) % n3;
+      rev = rs2 * bm[((long long)m1 * n2 + m2) * n3 + m3];
+    }
+    const double sgn = ck == 0 ? 0.0 : (ck == 1 ? 1.0 : -1.0);
+    out[f] = mfrac + sgn * rev * rsqn;
+  }
+}
+
+}  // namespace
+
+int vec_blocks(long long n) {
+  long long b = (n + 1023) / 1024;
+  if (b > VEC_MAX_BLOCKS) b = VEC_MAX_BLOCKS;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+#define VB dim3(vec_blocks(n)), dim3(256), 0, s
+
+template <typename T>
+void cg_init(const T* hb, const T* hz, T* xb, T* xz, T* rb, T* rz, T* zb, T* zz, T* pb, T* pz, const T* s1,
+             const T* s2, const float* c, long long n, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_init<T>), VB, hb, hz, xb, xz, rb, rz, zb, zz, pb, pz, s1, s2, c, n, partial);
+}
+template <typename T>
+void cg_update(T* xb, T* xz, const T* pb, const T* pz, const T* qb, const T* qz, T* rb, T* rz, T* zb, T* zz,
+               const T* s1, const T* s2, const float* c, const double* scal, const int* flags, long long n,
+               double* partial, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_update<T>), VB, xb, xz, pb, pz, qb, qz, rb, rz, zb, zz, s1, s2, c, scal, flags, n,
+                     partial);
+}
+template <typename T>
+void cg_pupdate(T* pb, T* pz, const T* zb, const T* zz, const double* scal, const int* flags, long long n,
+                hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_pupdate<T>), VB, pb, pz, zb, zz, scal, flags, n);
+}
+void fin_cg_init(const double* partial, int nb, double* scal, int* flags, double eta, double atol, int maxit,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_cg_init, dim3(1), dim3(256), 0, s, partial, nb, scal, flags, eta, atol, maxit);
+}
+void fin_alpha(const double* partial, int nb, double* scal, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, s, partial, nb, scal, flags);
+}
+void fin_rz(const double* partial, int nb, double* scal, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(256), 0, s, partial, nb, scal, flags);
+}
+void ipm_init(double* beta, double* z, double* nu1, double* nu2, long long n, double z0, double lam,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_ipm_init, VB, beta, z, nu1, nu2, n, z0, lam);
+}
+void ipm_resid(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
+               const double* xi, double lam, long long n, double* partial, double* out7, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_ipm_resid, VB, beta, z, nu1, nu2, hb, xi, lam, n, partial, VEC_MAX_BLOCKS);
+  RedOps<7> ops{{RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM}};
+  hipLaunchKernelGGL((k_fin_reduce<7>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out7,
+                     ops);
+}
+template <typename T>
+void ipm_newton(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
+                const double* xi, double lam, double smu, double* sig1, double* sig2, double* rb, double* rz,
+                T* sig1f, T* sig2f, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_ipm_newton<T>), VB, beta, z, nu1, nu2, hb, xi, lam, smu, sig1, sig2, rb, rz, sig1f,
+                     sig2f, n);
+}
+void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* sig1,
+              const double* sig2, const double* db, const double* dz, double smu, double tau, long long n,
+              double* partial, double* scal, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_ipm_ratio, VB, beta, z, nu1, nu2, sig1, sig2, db, dz, smu, n, partial);
+  hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(256), 0, s, partial, nb, tau, scal);
+}
+void ipm_update(double* beta, double* z, double* nu1, double* nu2, const double* sig1, const double* sig2,
+                const double* db, const double* dz, double smu, const double* scal, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_ipm_update, VB, beta, z, nu1, nu2, sig1, sig2, db, dz, smu, scal, n);
+}
+void cast_d2f(const double* a, const double* b, float* oa, float* ob, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast2<double, float>), VB, a, b, oa, ob, n);
+}
+void cast_f2d(const float* a, const float* b, double* oa, double* ob, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast2<float, double>), VB, a, b, oa, ob, n);
+}
+void copy2(const double* a, const double* b, double* oa, double* ob, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast2<double, double>), VB, a, b, oa, ob, n);
+}
+void add_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_f2d, VB, db, dz, eb, ez, n);
+}
+void ref_resid(const double* hb, const double* hz, const double* qb, const double* qz, double* rb, double* rz,
+               const double* s1, const double* s2, const float* c, long long n, double* partial, double* out,
+               hipStream_t s) {
+  const int nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_ref_resid, VB, hb, hz, qb, qz, rb, rz, s1, s2, c, n, partial);
+  RedOps<1> ops{{RED_SUM}};
+  hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out, ops);
+}
+template <typename T>
+void pinv_apply(const T* rb, const T* rz, T* zb, T* zz, const T* s1, const T* s2, const float* c, long long n,
+                double* partial, double* out, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  hipLaunchKernelGGL((k_pinv<T>), VB, rb, rz, zb, zz, s1, s2, c, n, partial);
+  if (out) {
+    RedOps<1> ops{{RED_SUM}};
+    hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out,
+                       ops);
+  }
+}
+void check_signal(const double* sig, const uint8_t* obs, long long n, double* partial, double* out2, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_check_signal, VB, sig, obs, n, partial);
+  RedOps<2> ops{{RED_SUM, RED_SUM}};
+  hipLaunchKernelGGL((k_fin_reduce<2>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out2, ops);
+}
+void zero_fill(const double* sig, const uint8_t* obs, double* out, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_fill, VB, sig, obs, out, n);
+}
+void obs_to_double(const uint8_t* obs, double* out, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_obs_to_double, VB, obs, out, n);
+}
+template <typename T>
+void fill(T* a, T v, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_fill<T>), VB, a, v, n);
+}
+void absmax(const double* a, long long n, double* partial, double* out, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_absmax, VB, a, n, partial);
+  RedOps<1> ops{{RED_MAX}};
+  hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out, ops);
+}
+void diag_h(const double* bm_ext, double* out_ext, int n1, int n2, int n3, double mfrac, hipStream_t s) {
+  const long long n = (long long)n1 * n2 * n3;
+  hipLaunchKernelGGL(k_diag_h, VB, bm_ext, out_ext, n1, n2, n3, mfrac, 1.0 / std::sqrt((double)n));
+}
+
+#undef VB
+
+#define CSIPM_VINST(T)                                                                                         \
+  template void cg_init<T>(const T*, const T*, T*, T*, T*, T*, T*, T*, T*, T*, const T*, const T*, const float*, \
+                           long long, double*, hipStream_t);                                                   \
+  template void cg_update<T>(T*, T*, const T*, const T*, const T*, const T*, T*, T*, T*, T*, const T*,         \
+                             const T*, const float*, const double*, const int*, long long, double*,            \
+                             hipStream_t);                                                                     \
+  template void cg_pupdate<T>(T*, T*, const T*, const T*, const double*, const int*, long long, hipStream_t);  \
+  template void ipm_newton<T>(const double*, const double*, const double*, const double*, const double*,      \
+                              const double*, double, double, double*, double*, double*, double*, T*, T*,       \
+                              long long, hipStream_t);                                                         \
+  template void pinv_apply<T>(const T*, const T*, T*, T*, const T*, const T*, const float*, long long,        \
+                              double*, double*, hipStream_t);                                                  \
+  template void fill<T>(T*, T, long long, hipStream_t);
+CSIPM_VINST(double)
+CSIPM_VINST(float)
+#undef CSIPM_VINST
+
+}  // namespace csipm

@@ -1,0 +1,44 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/csipm.h (no compute calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "csipm.h")
+LIB = os.path.join(ROOT, "paper_2502_04217_amd", "libcsipm.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(csipm_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for must in ["csipm_create", "csipm_solve", "csipm_apply_K", "csipm_apply_Pinv", "csipm_get_iterate",
+                 "csipm_get_residuals", "csipm_mlp_loss_grad", "csipm_destroy"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.fail("libcsipm.so not built (run python -m paper_2502_04217_amd.build)")
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_only_calls():
+    """Calls that touch no device: sizes, defaults, status strings."""
+    from paper_2502_04217_amd import csipm
+    assert csipm.workspace_bytes((256, 256, 256)) > 200 * 256 ** 3
+    assert csipm.workspace_bytes((6, 8, 8)) == 0
+    assert csipm.workspace_bytes((2, 8, 8)) == 0
+    o = csipm.default_options()
+    assert o.tol == 1e-6 and o.sigma == 0.1 and o.tau == 0.99
+    assert csipm.lib().csipm_status_string(-5) == b"unsupported grid"
+    assert csipm.lib().csipm_mlp_scratch_bytes(65) == 2 * 1250 * 8

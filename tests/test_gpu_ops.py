@@ -1,0 +1,144 @@
+"""GPU parity of the single-operator applies (A, A^T, H, K, P^{-1}) against
+the CPU oracle, element by element, in FP64 (<= 1e-12 relative) and FP32
+(<= 1e-5 relative), on grids spanning several FFT tiles, the smallest and
+the largest supported axis lengths and non-cubic shapes; plus full-size
+(256^3) checks against independent properties and numpy's FFT synthesis."""
+import numpy as np
+import pytest
+
+from oracle import dft3, ipm
+from paper_2502_04217_amd import workload as wl
+from tests._gpu_common import need_gpu, rel_inf, say
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(4, 4, 4), (8, 16, 32), (16, 16, 16), (32, 8, 64), (64, 64, 64), (4, 4, 1024), (1024, 4, 8),
+          (8, 1024, 4), (128, 32, 16)]
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def _problem(shape, seed=0):
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    rng = np.random.default_rng(seed)
+    sig = rng.standard_normal(shape)
+    obs = (rng.random(shape) > 0.25).astype(np.uint8)
+    return torch, csipm, csipm.Problem(sig, obs), sig, obs
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_operator_parity(shape, prec):
+    torch, csipm, pr, sig, obs = _problem(shape, 1)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    say("operator parity", shape, prec)
+    rng = np.random.default_rng(2)
+    beta = rng.standard_normal(shape)
+    x = rng.standard_normal(shape)
+    pz = rng.standard_normal(shape)
+    if prec == "f32":   # the oracle sees the same rounded inputs
+        beta, x, pz = (a.astype(np.float32).astype(np.float64) for a in (beta, x, pz))
+    obsf = obs.astype(np.float64)
+    tol = TOL[prec]
+    tb = torch.tensor(beta, dtype=dt, device="cuda")
+    tx = torch.tensor(x, dtype=dt, device="cuda")
+    A = pr.apply_A(tb).cpu().numpy()
+    assert rel_inf(A, dft3.apply_A(beta)) <= tol
+    At = pr.apply_At(tx).cpu().numpy()
+    assert rel_inf(At, dft3.apply_At(x)) <= tol
+    H = pr.apply_H(tb).cpu().numpy()
+    assert rel_inf(H, dft3.apply_H(beta, obsf)) <= tol
+    s1, s2 = wl.random_barrier(shape, 3, spread=3.0)
+    pr.set_barrier(torch.tensor(s1, device="cuda"), torch.tensor(s2, device="cuda"))
+    qb, qz = pr.apply_K(tb, torch.tensor(pz, dtype=dt, device="cuda"))
+    rqb, rqz = ipm.K_apply(beta, pz, s1, s2, obsf)
+    assert rel_inf(qb.cpu().numpy(), rqb) <= tol
+    assert rel_inf(qz.cpu().numpy(), rqz) <= tol
+    zb, zz = pr.apply_Pinv(tb, torch.tensor(pz, dtype=dt, device="cuda"))
+    rzb, rzz = ipm.Pinv_apply(beta, pz, s1, s2)
+    assert rel_inf(zb.cpu().numpy(), rzb) <= tol
+    assert rel_inf(zz.cpu().numpy(), rzz) <= tol
+
+
+def test_xi_and_diag_h_at_creation():
+    shape = (16, 32, 8)
+    torch, csipm, pr, sig, obs = _problem(shape, 4)
+    xi = pr.get(csipm.XI).cpu().numpy()
+    assert rel_inf(xi, dft3.xi(sig, obs)) <= 1e-12
+    dh = pr.get(csipm.DIAG_H).cpu().numpy()
+    from oracle import mlp
+    assert rel_inf(dh, mlp.diag_H_closed_form(obs.astype(np.float64))) <= 1e-12
+    assert rel_inf(dh, dft3.diag_H(obs.astype(np.float64))) <= 1e-12
+
+
+def test_full_size_256_properties_and_synthesis():
+    """256^3, the benchmark grid: A applied to the oracle's beta of the
+    planted waves equals numpy's irfftn synthesis of those waves; Parseval,
+    adjoint dot test and H idempotence hold to round-off."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    say("256^3 full-size operator checks")
+    w = wl.grid256(1)
+    pr = csipm.Problem(w.signal, w.observed)
+    beta = dft3.waves_to_beta(w.shape, w.wave_k, w.wave_c)
+    tb = torch.tensor(beta, device="cuda")
+    x = pr.apply_A(tb)
+    assert rel_inf(x.cpu().numpy(), w.clean) <= 1e-12
+    xf = pr.apply_A(tb.float())
+    assert rel_inf(xf.cpu().numpy(), w.clean) <= 1e-5
+    g = torch.Generator(device="cuda").manual_seed(5)
+    b = torch.randn(w.shape, dtype=torch.float64, device="cuda", generator=g)
+    y = torch.randn(w.shape, dtype=torch.float64, device="cuda", generator=g)
+    Ab = pr.apply_A(b)
+    assert abs(float(Ab.norm() / b.norm()) - 1.0) < 1e-13
+    lhs = float((Ab * y).sum())
+    rhs = float((b * pr.apply_At(y)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * float(Ab.norm() * y.norm())
+    Hb = pr.apply_H(b)
+    HHb = pr.apply_H(Hb)
+    assert float((HHb - Hb).abs().max()) <= 1e-12 * float(Hb.abs().max())
+
+
+def test_bitwise_reproducible():
+    torch, csipm, pr, sig, obs = _problem((64, 32, 64), 6)
+    b = torch.randn((64, 32, 64), dtype=torch.float64, device="cuda")
+    s = torch.rand((64, 32, 64), dtype=torch.float64, device="cuda") + 0.1
+    pr.set_barrier(s, s * 2)
+    q1 = pr.apply_K(b, b * 0.5)
+    q2 = pr.apply_K(b, b * 0.5)
+    assert torch.equal(q1[0], q2[0]) and torch.equal(q1[1], q2[1])
+
+
+def test_errors():
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    sig = np.zeros((8, 8, 8))
+    obs = np.ones((8, 8, 8), np.uint8)
+    bad = sig.copy()
+    bad[1, 2, 3] = np.nan
+    with pytest.raises(csipm.CsipmError) as e:
+        csipm.Problem(bad, obs)
+    assert e.value.status == -4
+    bad_missing = bad.copy()
+    o2 = obs.copy()
+    o2[1, 2, 3] = 0
+    csipm.Problem(bad_missing, o2).close()      # NaN at a missing sample is ignored
+    with pytest.raises(csipm.CsipmError) as e:
+        csipm.Problem(sig, np.zeros((8, 8, 8), np.uint8))
+    assert e.value.status == -1
+    with pytest.raises(csipm.CsipmError) as e:
+        csipm.Problem(np.zeros((6, 8, 8)), np.ones((6, 8, 8), np.uint8))
+    assert e.value.status == -5
+    with pytest.raises(csipm.CsipmError) as e:
+        csipm.Problem(np.zeros((2, 8, 8)), np.ones((2, 8, 8), np.uint8))
+    assert e.value.status == -5
+    pr = csipm.Problem(np.random.default_rng(0).standard_normal((8, 8, 8)), obs)
+    with pytest.raises(csipm.CsipmError) as e:
+        pr.solve()
+    assert e.value.status == -6
+    with pytest.raises(csipm.CsipmError) as e:
+        pr.set_lambda(-1.0)
+    assert e.value.status == -1
+    with pytest.raises(csipm.CsipmError) as e:
+        pr.solve(tau=1.5)
+    assert e.value.status in (-1, -6)
