@@ -1,0 +1,181 @@
+"""Training and evaluation of the learned preconditioner correction.
+
+Data: plain-preconditioner FP64 solves of seeded 128^3 problems (the 128^3
+family: sparsity log-uniform in [0.05%, 0.5%], SNR uniform in [5, 20] dB,
+lattice period in {8, 16, 32}) with record capture on: at every
+interior-point iteration the library reduces the first Krylov direction of
+the Newton solve to `n_per_iter` records (features + loss terms) at
+pseudo-random coefficients, weighted by that system's PCG count.
+
+Training: Adam on the records with the library's forward/backward kernels
+(csipm_mlp_loss_grad, csipm_mlp_adam); each step uses the records of one
+captured iteration, iterations visited in a seeded random order.
+
+Evaluation: held-out seeds solved with the paper's preconditioner and with
+the learned correction, in FP64 and FP32+refinement, comparing PCG
+iterations, wall time and the true final KKT residual.
+
+    python -m paper_2502_04217_amd.learn --train 200 --eval 50
+
+writes paper_2502_04217_amd/pc_params.json and gpurun_out/learn_eval.json.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import random
+import sys
+import time
+
+import numpy as np
+
+from . import csipm
+from . import workload as wl
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PARAMS_FILE = os.path.join(HERE, "pc_params.json")
+TRAIN_SEEDS = range(0, 200)
+EVAL_SEEDS = range(10000, 10050)
+
+
+def init_params(seed: int = 0, out_scale: float = 0.01):
+    """Glorot-uniform hidden layers, small output layer with the output bias
+    at softplus^{-1}(1): the untrained correction is c ~ 1, the paper's P."""
+    rng = np.random.default_rng(seed)
+    H1, H2, NIN = 32, 32, 4
+
+    def glorot(fo, fi):
+        a = math.sqrt(6.0 / (fi + fo))
+        return rng.uniform(-a, a, size=(fo, fi))
+
+    p = np.concatenate([glorot(H1, NIN).ravel(), np.zeros(H1), glorot(H2, H1).ravel(), np.zeros(H2),
+                        rng.uniform(-out_scale, out_scale, H2), [math.log(math.e - 1.0)]])
+    assert p.size == csipm.MLP_PARAMS
+    return p.astype(np.float32)
+
+
+def collect(seeds, n_per_iter=4096, max_iters=80, log=print):
+    import torch
+    feats, recs = [], []
+    t0 = time.time()
+    for s in seeds:
+        w = wl.grid128_family(s)
+        pr = csipm.Problem(w.signal, w.observed)
+        pr.lambda_rule(0.05)
+        feat = torch.empty((max_iters * n_per_iter, 4), dtype=torch.float32, device="cuda")
+        rec = torch.empty((max_iters * n_per_iter, 6), dtype=torch.float32, device="cuda")
+        pr.capture(feat, rec, n_per_iter, max_iters, seed=1000003 * (s + 1))
+        info = pr.solve(tol=1e-6, precision=csipm.FP64, pc=csipm.PC_PLAIN)
+        k, cg = pr.captured()
+        for i in range(k):
+            if cg[i] > 0:
+                feats.append(feat[i * n_per_iter:(i + 1) * n_per_iter])
+                recs.append(rec[i * n_per_iter:(i + 1) * n_per_iter])
+        pr.close()
+        log(f"[collect] seed {s}: {w.name} missing {w.missing_fraction:.3f} ipm {info['ipm_iters']} "
+            f"cg {info['cg_iters_total']} captured {k} ({time.time() - t0:.0f} s)")
+    return feats, recs
+
+
+def train(feats, recs, epochs=20, lr=2e-3, seed=0, log=print):
+    import torch
+    params = torch.tensor(init_params(seed), device="cuda")
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    n_per = feats[0].shape[0]
+    scratch = csipm._scratch(n_per, params.device)
+    order = list(range(len(feats)))
+    rng = random.Random(seed)
+    t = 0
+    hist = []
+    for ep in range(epochs):
+        rng.shuffle(order)
+        tot = 0.0
+        losses = []
+        for i in order:
+            loss, g = csipm.mlp_loss_grad(params, feats[i], recs[i], scratch)
+            t += 1
+            lr_t = lr * 0.5 * (1 + math.cos(math.pi * min(1.0, t / (epochs * len(order)))))
+            csipm.mlp_adam(params, g, m, v, t, max(lr_t, 1e-5))
+            losses.append(loss)
+        tot = float(torch.cat(losses).sum().item())
+        hist.append(tot)
+        log(f"[train] epoch {ep}: total loss {tot:.6e}")
+    return params, hist
+
+
+def baseline_loss(feats, recs):
+    """Loss of the untrained correction (c = 1) on the same records."""
+    import torch
+    p0 = torch.tensor(init_params(0, out_scale=0.0), device="cuda")
+    scratch = csipm._scratch(feats[0].shape[0], p0.device)
+    return float(sum(csipm.mlp_loss_grad(p0, f, r, scratch)[0].item() for f, r in zip(feats, recs)))
+
+
+def evaluate(params, seeds, log=print):
+    out = []
+    for s in seeds:
+        w = wl.grid128_family(s)
+        pr = csipm.Problem(w.signal, w.observed)
+        pr.lambda_rule(0.05)
+        pr.set_pc_params(params)
+        row = {"seed": s, "name": w.name, "missing": w.missing_fraction}
+        for tag, prec, pc in (("fp64_plain", csipm.FP64, csipm.PC_PLAIN), ("fp64_learned", csipm.FP64, csipm.PC_LEARNED),
+                              ("fp32_plain", csipm.FP32, csipm.PC_PLAIN), ("fp32_learned", csipm.FP32, csipm.PC_LEARNED)):
+            info = pr.solve(tol=1e-6, precision=prec, pc=pc)
+            true = pr.residuals()
+            row[tag] = {"cg": info["cg_iters_total"], "ipm": info["ipm_iters"], "s": info["solve_seconds"],
+                        "fallbacks": info["fallbacks"], "rel_kkt": true["rel_kkt"], "status": info["status"]}
+        pr.close()
+        out.append(row)
+        log(f"[eval] seed {s}: " + " ".join(f"{k}={row[k]['cg']}/{row[k]['s'] * 1e3:.0f}ms"
+                                             for k in ("fp64_plain", "fp64_learned", "fp32_plain", "fp32_learned")))
+    return out
+
+
+def summarize(rows):
+    def tot(k, f):
+        return float(sum(r[k][f] for r in rows))
+    s = {}
+    for k in ("fp64_plain", "fp64_learned", "fp32_plain", "fp32_learned"):
+        s[k] = {"cg_total": tot(k, "cg"), "seconds_total": tot(k, "s"), "fallbacks": tot(k, "fallbacks"),
+                "max_true_rel_kkt": max(r[k]["rel_kkt"] for r in rows)}
+    s["cg_ratio_fp64"] = s["fp64_learned"]["cg_total"] / max(1.0, s["fp64_plain"]["cg_total"])
+    s["cg_ratio_fp32"] = s["fp32_learned"]["cg_total"] / max(1.0, s["fp32_plain"]["cg_total"])
+    s["time_ratio_fp64"] = s["fp64_learned"]["seconds_total"] / s["fp64_plain"]["seconds_total"]
+    s["time_ratio_fp32"] = s["fp32_learned"]["seconds_total"] / s["fp32_plain"]["seconds_total"]
+    return s
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=200)
+    ap.add_argument("--eval", type=int, default=50)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--out", default=os.path.join("gpurun_out", "learn_eval.json"))
+    args = ap.parse_args()
+    log = lambda *a: print(*a, flush=True)
+    t0 = time.time()
+    feats, recs = collect(list(TRAIN_SEEDS)[:args.train], log=log)
+    log(f"[collect] {len(feats)} record groups in {time.time() - t0:.0f} s")
+    l0 = baseline_loss(feats, recs)
+    t1 = time.time()
+    params, hist = train(feats, recs, epochs=args.epochs, lr=args.lr, log=log)
+    log(f"[train] {time.time() - t1:.0f} s; loss c=1: {l0:.6e} trained: {hist[-1]:.6e}")
+    with open(PARAMS_FILE, "w") as f:
+        json.dump({"params": params.cpu().tolist(), "train_seeds": [0, args.train], "epochs": args.epochs,
+                   "lr": args.lr, "loss_untrained": l0, "loss_trained": hist[-1],
+                   "command": "python -m paper_2502_04217_amd.learn"}, f)
+    rows = evaluate(params, list(EVAL_SEEDS)[:args.eval], log=log)
+    summ = summarize(rows)
+    log(json.dumps(summ))
+    os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
+    with open(args.out, "w") as f:
+        json.dump({"summary": summ, "rows": rows, "loss_hist": hist, "loss_untrained": l0}, f)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,65 @@
+"""Runs K-applies of one grid for profiler runs (rocprofv3 kernel traces and
+HBM counters), plus a device copy of known size that calibrates the
+FETCH_SIZE / WRITE_SIZE counters.
+
+    python -m paper_2502_04217_amd.profile_kapply --grid 256 --reps 10 --precision fp32
+
+Prints one JSON line with the per-kernel event timings (ms) and the
+algorithmic bytes of each kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import numpy as np
+
+from . import csipm
+from . import workload as wl
+
+PASS_NAMES = ["premix", "axis1_inverse", "axis2_inverse", "axis3_c2r_mask_r2c", "axis2_forward",
+              "axis1_forward_K_epilogue", "postmix"]
+
+
+def pass_bytes(shape, w):
+    n1, n2, n3 = shape
+    n = n1 * n2 * n3
+    plane = 2 * n1 * n2
+    return [2 * plane * w, 2 * n * w, 2 * n * w, 2 * n * w + n // 8, 2 * n * w, 7 * n * w, 7 * plane * w]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--precision", choices=["fp32", "fp64", "both"], default="both")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    a = ap.parse_args(argv)
+    import torch
+    shape = (a.grid,) * 3
+    rng = np.random.default_rng(0)
+    obs = wl.lattice_cube_mask(shape, 3, 32) if a.grid % 32 == 0 else np.zeros(shape, bool)
+    pr = csipm.Problem(rng.standard_normal(shape), (~obs).astype(np.uint8))
+    s1, s2 = wl.random_barrier(shape, 1, spread=3.0)
+    pr.set_barrier(torch.tensor(s1, device="cuda"), torch.tensor(s2, device="cuda"))
+    out = {"grid": shape}
+    precs = {"fp32": (csipm.FP32, 4), "fp64": (csipm.FP64, 8)}
+    for name in (["fp32", "fp64"] if a.precision == "both" else [a.precision]):
+        p, w = precs[name]
+        pr.profile_kapply(p, 2)                       # warm-up
+        ms = pr.profile_kapply(p, a.reps)
+        by = pass_bytes(shape, w)
+        out[name] = {k: {"ms": m, "bytes": b, "GBps": b / (m * 1e-3) / 1e9} for k, m, b in zip(PASS_NAMES, ms, by)}
+    # calibration copy: reads and writes copy_mib MiB once
+    nbytes = a.copy_mib * 1024 * 1024
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    out["copy_bytes"] = nbytes
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

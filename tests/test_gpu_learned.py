@@ -1,0 +1,162 @@
+"""GPU kernels of the learned preconditioner correction against the CPU
+oracle (oracle/mlp.py): forward, backward, loss gradient and Adam within
+float32 tolerance; features of an iterate; the learned solve reaching the
+same LASSO solution; the fallback to the paper's preconditioner; and the
+gain of the trained network on held-out problems."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dft3, ipm, mlp
+from paper_2502_04217_amd import workload as wl
+from tests._gpu_common import need_gpu, rel2, rel_inf, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _records(n, seed):
+    rng = np.random.default_rng(seed)
+    feats = np.stack([rng.normal(0, 2, n), rng.uniform(-1, 1, n), rng.uniform(-27, 0, n),
+                      rng.uniform(0.8, 1.0, n)], axis=1)
+    s1, s2 = wl.random_barrier((n,), seed + 1, spread=2.0)
+    rec = np.stack([rng.standard_normal(n), rng.standard_normal(n), s1 + s2, s1 - s2, 4 * s1 * s2,
+                    rng.uniform(0.5, 1.5, n) / n], axis=1)
+    return feats.astype(np.float32), rec.astype(np.float32)
+
+
+def _params(seed, scale=0.5):
+    p = mlp.init_params(seed, out_scale=scale) + 0.05 * np.random.default_rng(seed).standard_normal(mlp.N_PARAMS)
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 1000, 70001])
+def test_forward_backward_loss_grad(n):
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    say("mlp kernels n =", n)
+    feats, rec = _records(n, 3)
+    p = _params(1)
+    f64 = feats.astype(np.float64)
+    r64 = rec.astype(np.float64)
+    tp = torch.tensor(p, device="cuda")
+    tf = torch.tensor(feats, device="cuda")
+    tr = torch.tensor(rec, device="cuda")
+    c = csipm.mlp_forward(tp, tf).cpu().numpy()
+    cref, cache = mlp.forward(p.astype(np.float64), f64)
+    assert rel_inf(c, cref) <= 1e-5
+    dc = np.random.default_rng(4).standard_normal(n).astype(np.float32)
+    g = csipm.mlp_backward(tp, tf, torch.tensor(dc, device="cuda")).cpu().numpy()
+    gref = mlp.backward(p.astype(np.float64), cache, dc.astype(np.float64))
+    assert rel_inf(g, gref) <= 1e-4
+    loss, g2 = csipm.mlp_loss_grad(tp, tf, tr)
+    lref, g2ref = mlp.loss_and_grad(p.astype(np.float64), f64, *[r64[:, i] for i in range(6)])
+    assert abs(float(loss.item()) - lref) <= 1e-5 * abs(lref)
+    assert rel_inf(g2.cpu().numpy(), g2ref) <= 1e-4
+    # bitwise reproducible reduction
+    loss_b, g2b = csipm.mlp_loss_grad(tp, tf, tr)
+    assert torch.equal(g2, g2b) and torch.equal(loss, loss_b)
+
+
+def test_adam_matches_oracle():
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    p = _params(2)
+    rng = np.random.default_rng(5)
+    tp = torch.tensor(p, device="cuda")
+    m = torch.zeros_like(tp)
+    v = torch.zeros_like(tp)
+    pr, mr, vr = p.astype(np.float64), np.zeros(p.size), np.zeros(p.size)
+    for t in range(1, 6):
+        g = rng.standard_normal(p.size).astype(np.float32)
+        csipm.mlp_adam(tp, torch.tensor(g, device="cuda"), m, v, t, 1e-3)
+        pr, mr, vr = mlp.adam_step(pr, g.astype(np.float64), mr, vr, t, 1e-3)
+    assert np.abs(tp.cpu().numpy() - pr).max() <= 1e-6
+
+
+def test_features_of_iterate():
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid16(2)
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.lambda_rule(0.05)
+    pr.solve(tol=1e-3)
+    s1, s2 = wl.random_barrier(w.shape, 7, spread=4.0)
+    pr.set_barrier(torch.tensor(s1, device="cuda"), torch.tensor(s2, device="cuda"))
+    f = pr.features().cpu().numpy()
+    beta = pr.get(csipm.BETA).cpu().numpy()
+    ref = mlp.features(s1, s2, beta, dft3.diag_H(w.observed.astype(np.float64)))
+    assert np.abs(f - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_learned_solve_same_solution_and_fallback():
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid16(4)
+    lam = ipm.lambda_rule(w.signal, w.observed)
+    ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-10))
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.set_lambda(lam)
+    pr.set_pc_params(torch.tensor(_params(3), device="cuda"))
+    for prec in (0, 1):
+        info = pr.solve(tol=1e-10, pc=1, precision=prec)
+        beta = pr.get(csipm.BETA).cpu().numpy()
+        say("learned solve precision", prec, info)
+        assert info["status"] in (0, 3)
+        assert rel2(beta, ref.state.beta) <= 1e-7
+    # a correction of 1e6 makes P_c a poor preconditioner: the learned
+    # systems exceed the budget and restart with the paper's P
+    bad = mlp.init_params(0, out_scale=0.0)
+    bad[-1] = 1e6
+    pr.set_pc_params(torch.tensor(bad.astype(np.float32), device="cuda"))
+    info = pr.solve(tol=1e-10, pc=1, cg_max=30)
+    say("forced fallback", info)
+    assert info["fallbacks"] > 0 and info["status"] == 3
+    assert rel2(pr.get(csipm.BETA).cpu().numpy(), ref.state.beta) <= 1e-7
+    c = pr.get(csipm.PC_C).cpu().numpy()
+    assert np.all(c > 0)
+
+
+def test_capture_records_consistent():
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid16(1)
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.lambda_rule(0.05)
+    per, mx = 256, 40
+    feat = torch.zeros((per * mx, 4), dtype=torch.float32, device="cuda")
+    rec = torch.zeros((per * mx, 6), dtype=torch.float32, device="cuda")
+    pr.capture(feat, rec, per, mx, seed=11)
+    info = pr.solve(tol=1e-8)
+    k, cg = pr.captured()
+    assert k == info["ipm_iters"] and len(cg) == k
+    r = rec[:k * per].cpu().numpy()
+    f = feat[:k * per].cpu().numpy()
+    assert np.all(r[:, 2] > 0) and np.all(np.abs(r[:, 3]) <= r[:, 2] * (1 + 1e-6)) and np.all(r[:, 4] > 0)
+    assert np.allclose(f[:, 1], r[:, 3] / r[:, 2], rtol=1e-4, atol=1e-6)
+    for i in range(k):
+        wsum = r[i * per:(i + 1) * per, 5]
+        assert np.allclose(wsum, wsum[0]) and wsum[0] > 0
+    pr.capture_off()
+
+
+PARAMS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2502_04217_amd",
+                      "pc_params.json")
+
+
+@pytest.mark.skipif(not os.path.exists(PARAMS), reason="no trained parameters committed")
+def test_trained_network_on_held_out_problems():
+    """Held-out 128^3 problems: the trained correction reaches the same true
+    KKT residual as the paper's preconditioner; its PCG iteration total is
+    reported against the plain one and may not exceed it by more than 10%."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm, learn
+    with open(PARAMS) as fh:
+        params = torch.tensor(json.load(fh)["params"], dtype=torch.float32, device="cuda")
+    rows = learn.evaluate(params, [10000, 10001, 10002], log=say)
+    s = learn.summarize(rows)
+    say("held-out summary", json.dumps(s))
+    assert s["fp64_learned"]["max_true_rel_kkt"] <= 1e-6
+    assert s["fp32_learned"]["max_true_rel_kkt"] <= 1e-6
+    assert s["cg_ratio_fp64"] <= 1.10
