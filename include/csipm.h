@@ -180,7 +180,8 @@ csipm_status csipm_set_pc_params(csipm_ctx* ctx, const float* d_params, int n_pa
  *   forward  : c[i] = softplus(MLP(feat[i][0..3])) + 1e-6, i < n_rec
  *   backward : grad += d/dparams sum_i dc[i] c[i]
  *   loss_grad: loss_out[0] = sum_i w_i (L1_i^2 + L2_i^2)(u_i - c_i p_i)^2 /
- *              (c_i L1_i + S12_i)^2 and grad = its parameter gradient
+ *              (L1_i + S12_i)^2 (the i-th block of P^{-1}(K - P_c)p squared,
+ *              P the paper's preconditioner) and grad = its parameter gradient
  *              (overwritten), records rec[i] = {u, p, L1, L2, S12, w}
  *              (6 floats each)
  *   adam     : one Adam step (beta1 0.9, beta2 0.999, eps 1e-8; t counted

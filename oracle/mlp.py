@@ -21,9 +21,12 @@ Features per coefficient i:
                                              samples)
 Loss (one training record per sampled coefficient i of a captured Krylov
 direction p with u = H p_beta):
-    e_i(c) = (L1_i^2 + L2_i^2) (u_i - c_i p_i)^2 / (c_i L1_i + 4 S1_i S2_i)^2
-which is the squared i-th block of P_c^{-1}(K - P_c)p; the total loss is
-sum_i w_i e_i with per-record weights w_i supplied by the caller.
+    e_i(c) = (L1_i^2 + L2_i^2) (u_i - c_i p_i)^2 / (L1_i + 4 S1_i S2_i)^2
+which is the squared i-th block of P^{-1}(K - P_c)p, the deviation of the
+corrected preconditioner from K along p measured through the paper's P
+(c = 1); the total loss is sum_i w_i e_i with per-record weights w_i supplied
+by the caller.  It is a weighted least-squares problem in c whose optimum
+for white directions is the Jacobi choice c_i = (M_perp^T M_perp)_ii.
 """
 from __future__ import annotations
 
@@ -109,13 +112,13 @@ def backward(params, cache, dc):
 
 
 def record_loss(c, u, p, L1, L2, S12, w):
-    """Per-record loss w (L1^2 + L2^2)(u - c p)^2 / (c L1 + S12)^2 and its
+    """Per-record loss w (L1^2 + L2^2)(u - c p)^2 / (L1 + S12)^2 and its
     derivative with respect to c (S12 = 4 S1 S2)."""
-    D = c * L1 + S12
+    D = L1 + S12
     res = u - c * p
-    a = L1 * L1 + L2 * L2
-    e = w * a * res * res / (D * D)
-    de = w * a * (-2.0 * p * res / (D * D) - 2.0 * res * res * L1 / (D * D * D))
+    a = (L1 * L1 + L2 * L2) / (D * D)
+    e = w * a * res * res
+    de = -2.0 * w * a * p * res
     return e, de
 
 

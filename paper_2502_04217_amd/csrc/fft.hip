@@ -28,7 +28,7 @@ namespace csipm {
 
 namespace {
 
-constexpr int kLdsBytes = 32768;   // LDS budget of one workgroup
+constexpr int kLdsBytes = 65536;   // LDS budget of one workgroup
 
 // ------------------------------------------------------------- radix plan --
 template <int L, int E>
@@ -144,12 +144,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Block sum of v into *out (thread 0).  `red` is LDS scratch of at least
+// NTHREADS/64 doubles; it may alias the FFT exchange buffer, so the block
+// synchronises before writing it.
 template <int NTHREADS>
-__device__ __forceinline__ void block_sum_store(double v, double* out) {
-  __shared__ double red[NTHREADS / 64 > 0 ? NTHREADS / 64 : 1];
+__device__ __forceinline__ void block_sum_store(double v, double* out, double* red) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
+  __syncthreads();
   if (lane == 0) red[w] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -246,7 +249,7 @@ k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
           }
         }
     }
-    block_sum_store<TM * NT>(acc, &ka.partial[blockIdx.x]);
+    block_sum_store<TM * NT>(acc, &ka.partial[blockIdx.x], reinterpret_cast<double*>(smem_raw));
   } else {
     if (active) {
 #pragma unroll
@@ -500,7 +503,10 @@ k_postmix(const cx<T>* work, cx<T>* out, int n1, int n2, int m, KArgs<T> ka, con
       }
     }
   }
-  if constexpr (EPI == EPI_K) block_sum_store<256>(acc, &ka.partial[blockIdx.x]);
+  if constexpr (EPI == EPI_K) {
+    __shared__ double red[4];
+    block_sum_store<256>(acc, &ka.partial[blockIdx.x], red);
+  }
 }
 
 // ----------------------------------------------------- layout conversion --

@@ -7,8 +7,9 @@
 //   f3 = log(|beta_i| / max|beta| + 1e-12),  f4 = diag(M_perp^T M_perp)_i.
 // Training record of a sampled coefficient i of a Krylov direction p with
 // u = H p_beta: {u_i, p_beta_i, L1_i, L2_i, 4 S1_i S2_i, w_i}; its loss is
-//   w (L1^2 + L2^2)(u - c p)^2 / (c L1 + 4 S1 S2)^2,
-// the squared i-th block of P_c^{-1}(K - P_c)p.
+//   w (L1^2 + L2^2)(u - c p)^2 / (L1 + 4 S1 S2)^2,
+// the squared i-th block of P^{-1}(K - P_c)p with P the paper's
+// preconditioner: a weighted least-squares fit of c_i p_i to (H p)_i.
 #pragma once
 
 #include "csipm_internal.h"

@@ -93,11 +93,11 @@ k_grad_block(const float* __restrict__ params, const float* __restrict__ feat, c
       const float c = softplusf(o) + 1e-6f;
       const float* rc = aux + (long long)idx * MLP_REC;
       const double u = rc[0], p = rc[1], L1 = rc[2], L2 = rc[3], S12 = rc[4], w = rc[5];
-      const double D = (double)c * L1 + S12;
+      const double D = L1 + S12;
       const double res = u - (double)c * p;
-      const double a = L1 * L1 + L2 * L2;
-      e = w * a * res * res / (D * D);
-      dc = (float)(w * a * (-2.0 * p * res / (D * D) - 2.0 * res * res * L1 / (D * D * D)));
+      const double a = (L1 * L1 + L2 * L2) / (D * D);
+      e = w * a * res * res;
+      dc = (float)(-2.0 * w * a * p * res);
     }
     dout = dc * sigmoidf(o);
   } else {

@@ -1,0 +1,74 @@
+"""Summarises a rocprofv3 result database (rocpd SQLite): per-kernel dispatch
+count, total and average duration, and the average over "working" dispatches
+only (longer than --min-us; Krylov iterations are queued ahead in batches and
+the ones past convergence return at once, in a few microseconds), plus the
+per-dispatch mean of any collected counters (FETCH_SIZE, WRITE_SIZE in KiB).
+
+    python -m paper_2502_04217_amd.rocprof_summary gpurun_out/prof/x_results.db [--top 25] [--min-us 8]
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import re
+import sqlite3
+import sys
+
+
+def short(name: str) -> str:
+    name = re.sub(r"csipm::\(anonymous namespace\)::", "", name)
+    name = re.sub(r"csipm::", "", name)
+    m = re.match(r"(void )?([A-Za-z_0-9]+(<[^()]*>)?)", name)
+    return m.group(2) if m else name[:80]
+
+
+def summarize(db: str, top: int = 25, min_us: float = 8.0):
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, duration from kernels").fetchall()
+    agg = collections.OrderedDict()
+    for name, dur in rows:
+        k = short(name)
+        a = agg.setdefault(k, [0, 0.0, 0, 0.0])
+        a[0] += 1
+        a[1] += dur
+        if dur >= min_us * 1e3:
+            a[2] += 1
+            a[3] += dur
+    total = sum(a[1] for a in agg.values()) or 1.0
+    out = []
+    for k, (n, t, nw, tw) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+        out.append({"kernel": k, "calls": n, "total_us": t / 1e3, "avg_us": t / n / 1e3, "pct": 100 * t / total,
+                    "working_calls": nw, "working_avg_us": (tw / nw / 1e3) if nw else 0.0})
+    ctr = collections.defaultdict(lambda: collections.defaultdict(list))
+    try:
+        for kname, cname, val in c.execute("select kernel_name, counter_name, value from counters_collection"):
+            ctr[short(kname)][cname].append(val)
+    except sqlite3.Error:
+        pass
+    counters = {k: {cn: {"dispatches": len(v), "mean": sum(v) / len(v)} for cn, v in d.items()}
+                for k, d in ctr.items()}
+    return out, counters, total / 1e3
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("db")
+    ap.add_argument("--top", type=int, default=25)
+    ap.add_argument("--min-us", type=float, default=8.0)
+    a = ap.parse_args(argv)
+    out, counters, total_us = summarize(a.db, a.top, a.min_us)
+    print(f"# kernel time total {total_us:.1f} us; working = dispatches >= {a.min_us} us")
+    print(f"{'kernel':60s} {'calls':>6s} {'total_us':>11s} {'avg_us':>9s} {'pct':>6s} {'work':>5s} {'work_avg_us':>11s}")
+    for r in out:
+        print(f"{r['kernel'][:60]:60s} {r['calls']:6d} {r['total_us']:11.1f} {r['avg_us']:9.2f} {r['pct']:6.2f} "
+              f"{r['working_calls']:5d} {r['working_avg_us']:11.2f}")
+    if counters:
+        print("# counters (mean per dispatch)")
+        for k, d in counters.items():
+            for cn, v in d.items():
+                print(f"{k[:60]:60s} {cn:12s} n={v['dispatches']:5d} mean={v['mean']:.1f}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

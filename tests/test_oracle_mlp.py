@@ -60,13 +60,30 @@ def test_correction_positive_and_pc_spd():
     assert np.abs(yb - xb).max() < 1e-9 and np.abs(yz - xz).max() < 1e-9
 
 
+def test_loss_minimiser_is_jacobi_for_white_directions():
+    """Over many iid directions the least-squares optimum of a common c_i
+    is diag(M_perp^T M_perp)_i."""
+    shape = (4, 4, 8)
+    rng = np.random.default_rng(12)
+    obs = (rng.random(shape) > 0.3).astype(np.float64)
+    num = np.zeros(shape)
+    den = np.zeros(shape)
+    for _ in range(4000):
+        p = rng.standard_normal(shape)
+        u = dft3.apply_H(p, obs)
+        num += u * p
+        den += p * p
+    assert np.abs(num / den - dft3.diag_H(obs)).max() < 0.05
+
+
 def test_untrained_network_is_the_paper_preconditioner():
     c, _ = mlp.forward(mlp.init_params(0, out_scale=0.0), _records(10, 1)[0])
     assert np.allclose(c, 1.0 + mlp.C_FLOOR, atol=1e-12)
 
 
 def test_loss_is_norm_of_preconditioned_deviation():
-    """sum_i e_i(c) = ||P_c^{-1}(K - P_c) p||^2 with u = H p_beta."""
+    """sum_i e_i(c) = ||P^{-1}(K - P_c) p||^2 with u = H p_beta and P the
+    paper's preconditioner (c = 1)."""
     shape = (4, 4, 8)
     rng = np.random.default_rng(7)
     obs = (rng.random(shape) > 0.2).astype(np.float64)
@@ -75,7 +92,7 @@ def test_loss_is_norm_of_preconditioned_deviation():
     pb, pz = rng.standard_normal(shape), rng.standard_normal(shape)
     qb, qz = ipm.K_apply(pb, pz, s1, s2, obs)
     Pb, Pz = ipm.P_apply(pb, pz, s1, s2, c)
-    yb, yz = ipm.Pinv_apply(qb - Pb, qz - Pz, s1, s2, c)
+    yb, yz = ipm.Pinv_apply(qb - Pb, qz - Pz, s1, s2)
     direct = float(np.sum(yb ** 2) + np.sum(yz ** 2))
     u = dft3.apply_H(pb, obs)
     e, _ = mlp.record_loss(c.ravel(), u.ravel(), pb.ravel(), (s1 + s2).ravel(),
