@@ -80,7 +80,9 @@ typedef struct {
   int precision;       /* csipm_precision of the Krylov solves               */
   int pc;              /* csipm_pc                                           */
   int refine_max;      /* FP32: refinement steps per Newton system (def. 8)  */
-  double refine_inner_rtol; /* FP32: inner PCG relative tolerance (def. 1e-2) */
+  double refine_inner_rtol; /* FP32: tightest relative tolerance asked of one inner
+                               PCG solve (default 1e-5); each inner solve aims at
+                               half the remaining reduction, at most 1e-2     */
 } csipm_options;
 
 typedef struct {
@@ -218,6 +220,12 @@ csipm_status csipm_captured(csipm_ctx* ctx, int* n_iters, int* cg_counts_host, i
 /* Features of the current iterate and barrier diagonals, [n][4] float,
  * coefficients in the external beta layout order. */
 csipm_status csipm_features(csipm_ctx* ctx, float* d_feat);
+
+/* The correction c the solver would apply at the current iterate
+ * (n doubles, external beta layout): the network is evaluated on the
+ * iterate's features where L1/(L1 + 4 S1 S2) >= 1e-3 (there c can act on
+ * P_c^{-1}), and c = 1 elsewhere.  Needs parameters (ESTATE otherwise). */
+csipm_status csipm_pc_correction(csipm_ctx* ctx, double* d_c);
 
 /* Instrumentation: runs `reps` K-applies (apply_K's kernels on the
  * internal vectors, with the current barrier diagonals) and returns in

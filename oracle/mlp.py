@@ -150,6 +150,22 @@ def features(sig1, sig2, beta, diagH):
     return np.stack([f1, f2, f3, f4], axis=1)
 
 
+PC_RELEVANCE = 1e-3
+
+
+def correction(params, beta, z, nu1, nu2, diagH, rmin=PC_RELEVANCE):
+    """The correction the solver applies at an interior-point iterate:
+    c = softplus(MLP(features)) + 1e-6 where the correction can act on
+    P_c^{-1}, i.e. where L1 / (L1 + 4 S1 S2) >= rmin; c = 1 elsewhere (there
+    every entry of P_c^{-1} moves by less than rmin relative with c)."""
+    s1, s2 = z + beta, z - beta
+    sig1, sig2 = nu1 / s1, nu2 / s2
+    c, _ = forward(params, features(sig1, sig2, beta, diagH))
+    L1 = (sig1 + sig2).ravel()
+    act = L1 >= rmin * (L1 + 4.0 * (sig1 * sig2).ravel())
+    return np.where(act, c, 1.0).reshape(beta.shape), act.reshape(beta.shape)
+
+
 def diag_H_closed_form(observed):
     """diag(M_perp^T M_perp) from one DFT of the mask: the square of column i
     of A is (1/n)(1 +- cos(2 theta)) for the sqrt2 Re / sqrt2 Im coordinates

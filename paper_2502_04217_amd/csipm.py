@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "csipm_capture": (I, [P, I, P, P, I, I, C.c_ulonglong]),
         "csipm_captured": (I, [P, C.POINTER(I), P, I]),
         "csipm_features": (I, [P, P]),
+        "csipm_pc_correction": (I, [P, P]),
         "csipm_profile_kapply": (I, [P, I, I, C.POINTER(D)]),
         "csipm_destroy": (I, [P]),
         "csipm_status_string": (C.c_char_p, [I]),
@@ -273,6 +274,11 @@ class Problem:
         out = (C.c_double * 7)()
         self._check(lib().csipm_profile_kapply(self._ctx, precision, reps, out), "profile_kapply")
         return list(out)
+
+    def pc_correction(self):
+        out = self._vec()
+        self._check(lib().csipm_pc_correction(self._ctx, _ptr(out)), "pc_correction")
+        return out
 
     def features(self):
         import torch

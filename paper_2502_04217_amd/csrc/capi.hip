@@ -22,6 +22,8 @@ using namespace csipm;
 namespace {
 
 constexpr size_t kAlign = 256;
+// the learned correction is evaluated where L1 / (L1 + 4 S1 S2) >= this
+constexpr double kPcRelevance = 1e-3;
 
 bool pow2_in_range(int v) { return v >= 4 && v <= 1024 && (v & (v - 1)) == 0; }
 
@@ -121,7 +123,7 @@ size_t layout(Carver& cv, csipm_ctx* c, int n1, int n2, int n3) {
   c->mask = cv.take<uint32_t>(n / 32);
   c->tw64 = cv.take<cx<double>>(ntw);
   c->tw32 = cv.take<cx<float>>(ntw);
-  c->partK = cv.take<double>(k_partials(n1, n2, n3));
+  c->partK = cv.take<double>(2 * k_partials(n1, n2, n3));   // up to two quantities
   c->partV = cv.take<double>((size_t)VEC_MAX_BLOCKS * 8);
   c->scal = cv.take<double>(S_COUNT);
   c->flags = cv.take<int>(F_COUNT);
@@ -169,14 +171,18 @@ void op_At(csipm_ctx* c, const T* x, T* out, T* work) {
   launch_postmix<T>(g, out, out, EPI_NONE, nullptr, nullptr, c->s);
 }
 
+size_t k_partials(int n1, int n2, int n3);
+
 // q = K p with p.q partials in c->partK; returns the number of partials.
 template <typename T>
 int op_K(csipm_ctx* c, const T* pb, const T* pz, const T* s1, const T* s2, T* qb, T* qz, T* work,
          const int* skip) {
   const Grid& g = c->g;
   const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>));
-  KArgs<T> ka{pb, pz, s1, s2, qb, qz, c->partK};
-  KArgs<T> kb{pb, pz, s1, s2, qb, qz, c->partK + nb5};
+  const int ps = (int)k_partials(g.n1, g.n2, g.n3);
+  EpiArgs<T> ka{KArgs<T>{pb, pz, s1, s2, qb, qz}, RArgs{}, c->partK, ps};
+  EpiArgs<T> kb = ka;
+  kb.partial = c->partK + nb5;
   launch_premix<T>(g, pb, work, skip, c->s);
   launch_axis12<T>(g, 1, +1, pb, work, tw<T>(c), EPI_NONE, nullptr, true, skip, c->s);
   launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, skip, c->s);
@@ -187,19 +193,43 @@ int op_K(csipm_ctx* c, const T* pb, const T* pz, const T* s1, const T* s2, T* qb
   return nb5 + postmix_blocks(g);
 }
 
+// FP64 refinement residual r = h - K d, fused into the K-apply: writes the
+// FP32 start of the next inner PCG (r32, z32 = P_c^{-1} r, p32) and sums
+// r.P_c^{-1}r -> scal[S_REF], r32.z32 -> scal[S_REFRZ].
+void op_Kr(csipm_ctx* c, const float* pcc) {
+  const Grid& g = c->g;
+  const int nb5 = axis12_blocks(g, 1, 16);
+  const int ps = (int)k_partials(g.n1, g.n2, g.n3);
+  RArgs ra{c->dxb, c->dxz, c->sig1, c->sig2, c->rhb, c->rhz, pcc, c->frb, c->frz, c->fzb, c->fzz, c->fpb, c->fpz};
+  EpiArgs<double> ea{KArgs<double>{}, ra, c->partK, ps};
+  EpiArgs<double> eb = ea;
+  eb.partial = c->partK + nb5;
+  double* work = c->work;
+  launch_premix<double>(g, c->dxb, work, nullptr, c->s);
+  launch_axis12<double>(g, 1, +1, c->dxb, work, c->T64, EPI_NONE, nullptr, true, nullptr, c->s);
+  launch_axis12<double>(g, 2, +1, work, work, c->T64, EPI_NONE, nullptr, false, nullptr, c->s);
+  launch_axis3<double>(g, A3_FULL, work, work, c->mask, c->T64, nullptr, c->s);
+  launch_axis12<double>(g, 2, -1, work, work, c->T64, EPI_NONE, nullptr, false, nullptr, c->s);
+  launch_axis12<double>(g, 1, -1, work, work, c->T64, EPI_R, &ea, false, nullptr, c->s);
+  launch_postmix<double>(g, work, nullptr, EPI_R, &eb, nullptr, c->s);
+  fin_two(c->partK, nb5 + postmix_blocks(g), ps, c->scal, S_REF, S_REFRZ, c->s);
+}
+
 // ------------------------------------------------- learned correction --
-// Features of the current iterate into c->feat (internal order).  Uses the
-// FP64 barrier diagonals and max|beta| of the last residual evaluation.
+// Features of the current iterate into c->feat (internal order) from the
+// FP64 barrier diagonals in sig1/sig2 and max|beta| of the last residual.
 void compute_features(csipm_ctx* c) {
   const long long n = c->g.n;
   mlp_mean_log_l1(c->sig1, c->sig2, n, c->partV, c->scal + S_MISC + 1, c->s);
   mlp_features(c->sig1, c->sig2, c->beta, c->diagH, c->scal + S_MISC + 1, c->scal + S_RESID + 4, c->feat, n, c->s);
 }
 
-// c = softplus(MLP(features)) + 1e-6 for every coefficient.
+// c = softplus(MLP(features)) + 1e-6 where it can act on P_c^{-1}, c = 1
+// elsewhere; features formed from the interior-point state (before the
+// Newton system is built).
 csipm_status learned_correction(csipm_ctx* c) {
-  compute_features(c);
-  mlp_forward(c->mlp_params, c->feat, c->pc_c, c->g.n, c->s);
+  mlp_correction_state(c->beta, c->z, c->nu1, c->nu2, c->diagH, c->scal + S_RESID + 4, c->mlp_params, c->pc_c,
+                       c->g.n, c->partV, c->scal + S_MISC + 1, kPcRelevance, c->s);
   return hip_check(c, "learned_correction");
 }
 
@@ -236,10 +266,14 @@ struct PcgOut {
 };
 
 // Preconditioned CG (Hestenes-Stiefel) on K x = h, x0 = 0, stopping on
-// sqrt(r.P^{-1}r) <= max(atol, eta sqrt(r0.P^{-1}r0)).  Iterations are queued
-// in growing batches; finished iterations turn the rest of a batch into
-// no-ops through the device flag, so the host only synchronises per batch.
-// If `capture` is set, p_0 and q_0 = K p_0 are handed to the capture hook.
+// sqrt(r.P^{-1}r) <= max(atol, eta sqrt(r0.P^{-1}r0)).  When hb is set the
+// solve starts from h (kernel k_cg_init); otherwise r, z = P^{-1}r and p = z
+// are already in the precision-T Krylov vectors and the start has been
+// finalised (k_fin_cg_init) by the caller.  x0 = 0 is never stored: the
+// first update writes x = alpha p.  Iterations are queued in growing
+// batches; finished iterations turn the rest of a batch into no-ops through
+// the device flag, so the host only synchronises once per batch.  If
+// `capture` is set, p_0 and q_0 = K p_0 go to the capture hook.
 template <typename T>
 csipm_status pcg(csipm_ctx* c, const T* hb, const T* hz, T* xb, T* xz, const T* s1, const T* s2, const float* pcc,
                  double eta, double atol, int maxit, PcgOut& out, bool capture) {
@@ -248,8 +282,10 @@ csipm_status pcg(csipm_ctx* c, const T* hb, const T* hz, T* xb, T* xz, const T* 
   T *rb = (T*)v.rb, *rz = (T*)v.rz, *zb = (T*)v.zb, *zz = (T*)v.zz, *pb = (T*)v.pb, *pz = (T*)v.pz,
     *qb = (T*)v.qb, *qz = (T*)v.qz, *work = (T*)v.work;
   const int nbv = vec_blocks(n);
-  cg_init<T>(hb, hz, xb, xz, rb, rz, zb, zz, pb, pz, s1, s2, pcc, n, c->partV, c->s);
-  fin_cg_init(c->partV, nbv, c->scal, c->flags, eta, atol, maxit, c->s);
+  if (hb) {
+    cg_init<T>(hb, hz, xb, xz, rb, rz, zb, zz, pb, pz, s1, s2, pcc, n, c->partV, c->s);
+    fin_cg_init(c->partV, nbv, c->scal, c->flags, eta, atol, maxit, c->s);
+  }
   const int* skip = c->flags + F_DONE;
   int chunk = 2;
   bool first = true;
@@ -257,9 +293,10 @@ csipm_status pcg(csipm_ctx* c, const T* hb, const T* hz, T* xb, T* xz, const T* 
     for (int k = 0; k < chunk; ++k) {
       const int nbk = op_K<T>(c, pb, pz, s1, s2, qb, qz, work, skip);
       if (first && capture) capture_pair<T>(c, pb, pz, qb, qz, s1, s2);
-      first = false;
       fin_alpha(c->partK, nbk, c->scal, c->flags, c->s);
-      cg_update<T>(xb, xz, pb, pz, qb, qz, rb, rz, zb, zz, s1, s2, pcc, c->scal, c->flags, n, c->partV, c->s);
+      cg_update<T>(xb, xz, pb, pz, qb, qz, rb, rz, zb, zz, s1, s2, pcc, c->scal, c->flags, n, c->partV, first,
+                   c->s);
+      first = false;
       fin_rz(c->partV, nbv, c->scal, c->flags, c->s);
       cg_pupdate<T>(pb, pz, zb, zz, c->scal, c->flags, n, c->s);
     }
@@ -293,7 +330,7 @@ void csipm_default_options(csipm_options* o) {
   o->precision = CSIPM_FP64;
   o->pc = CSIPM_PC_PLAIN;
   o->refine_max = 8;
-  o->refine_inner_rtol = 1e-2;
+  o->refine_inner_rtol = 1e-5;
 }
 
 size_t csipm_workspace_bytes(int n1, int n2, int n3) {
@@ -406,17 +443,23 @@ csipm_status csipm_lambda_rule(csipm_ctx* c, double frac, double* lambda_out) {
 
 namespace {
 
-// Solves the Newton system K [dxb; dxz] = [rhb; rhz] at the current barrier
-// diagonals, in FP64 PCG or FP32 PCG with FP64 iterative refinement.
-csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double eta, const float* pcc, int& cg_iters,
-                          int& refine_steps, bool& converged, bool capture) {
+// Builds and solves the Newton system of the current iterate (target
+// smu = sigma mu): K [dxb; dxz] = h with the barrier diagonals Sigma_j =
+// nu_j / s_j, either by FP64 PCG or by FP32 PCG inside FP64 iterative
+// refinement.  The system build is fused with the PCG start (newton_init).
+csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, double eta, const float* pcc,
+                          int& cg_iters, int& refine_steps, bool& converged, bool capture) {
   const long long n = c->g.n;
+  const int nbv = vec_blocks(n);
   cg_iters = 0;
   refine_steps = 0;
   converged = false;
   if (o.precision == CSIPM_FP64) {
+    newton_init<double>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, smu, c->sig1, c->sig2, nullptr,
+                        nullptr, nullptr, nullptr, pcc, c->rb, c->rz, c->zb, c->zz, c->pb, c->pz, n, c->partV, c->s);
+    fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, eta, o.cg_atol, o.cg_max, -1, -1, c->s);
     PcgOut po;
-    csipm_status st = pcg<double>(c, c->rhb, c->rhz, c->dxb, c->dxz, c->sig1, c->sig2, pcc, eta, o.cg_atol,
+    csipm_status st = pcg<double>(c, nullptr, nullptr, c->dxb, c->dxz, c->sig1, c->sig2, pcc, eta, o.cg_atol,
                                   o.cg_max, po, capture);
     cg_iters = po.iters;
     converged = po.converged;
@@ -424,40 +467,40 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double eta, cons
   }
   // FP32 inner solves, FP64 residual: d = 0, r = h; repeat { e = K32^{-1} r;
   // d += e; r = h - K d } until sqrt(r.P^{-1}r) <= max(atol, eta sqrt(h.P^{-1}h)).
-  fill<double>(c->dxb, 0.0, n, c->s);
-  fill<double>(c->dxz, 0.0, n, c->s);
-  pinv_apply<double>(c->rhb, c->rhz, c->zb, c->zz, c->sig1, c->sig2, pcc, n, c->partV, c->scal + S_REF0, c->s);
-  copy2(c->rhb, c->rhz, c->rb, c->rz, n, c->s);
-  csipm_status st = sync_scalars(c, "refine");
-  if (st != CSIPM_OK) return st;
-  const double h0 = std::sqrt(std::max(c->hscal[S_REF0], 0.0));
-  const double target = std::max(o.cg_atol, eta * h0);
-  double rnorm = h0;
-  if (rnorm <= target) {
-    converged = true;
-    return CSIPM_OK;
-  }
+  // The first inner solve starts from h (built in FP32 by newton_init, which
+  // also sums h.P^{-1}h); later ones start from the FP32 residual written by
+  // the fused FP64 residual pass.
+  newton_init<float>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, smu, c->sig1, c->sig2, c->rhb, c->rhz,
+                     c->sig1f, c->sig2f, pcc, c->frb, c->frz, c->fzb, c->fzz, c->fpb, c->fpz, n, c->partV, c->s);
+  // inner tolerance: half the remaining reduction, at most 1e-2, at least
+  // refine_inner_rtol (what FP32 PCG can still reach)
+  double inner = std::max(o.refine_inner_rtol, std::min(1e-2, 0.5 * eta));
+  fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, inner, 0.0, o.cg_max, S_REF0, -1, c->s);
+  double target = 0.0, rnorm = 0.0;
   for (int step = 0; step < std::max(1, o.refine_max); ++step) {
-    cast_d2f(c->rb, c->rz, c->fqb, c->fqz, n, c->s);
-    const double inner = std::max(o.refine_inner_rtol, 0.5 * target / rnorm);
+    if (step > 0) fin_cg_start(nullptr, 0, 0, c->scal, c->flags, inner, 0.0, o.cg_max, -1, S_REFRZ, c->s);
     PcgOut po;
-    st = pcg<float>(c, c->fqb, c->fqz, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, inner, 0.0, o.cg_max, po,
-                    capture && step == 0);
+    csipm_status st = pcg<float>(c, nullptr, nullptr, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, inner, 0.0, o.cg_max,
+                                 po, capture && step == 0);
     if (st != CSIPM_OK) return st;
     cg_iters += po.iters;
-    add_f2d(c->dxb, c->dxz, c->fxb, c->fxz, n, c->s);
-    op_K<double>(c, c->dxb, c->dxz, c->sig1, c->sig2, c->qb, c->qz, c->work, nullptr);
-    ref_resid(c->rhb, c->rhz, c->qb, c->qz, c->rb, c->rz, c->sig1, c->sig2, pcc, n, c->partV, c->scal + S_REF,
-              c->s);
+    if (step == 0)
+      set_f2d(c->dxb, c->dxz, c->fxb, c->fxz, n, c->s);
+    else
+      add_f2d(c->dxb, c->dxz, c->fxb, c->fxz, n, c->s);
+    op_Kr(c, pcc);
     st = sync_scalars(c, "refine");
     if (st != CSIPM_OK) return st;
     ++refine_steps;
+    const double h0 = std::sqrt(std::max(c->hscal[S_REF0], 0.0));
+    target = std::max(o.cg_atol, eta * h0);
     rnorm = std::sqrt(std::max(c->hscal[S_REF], 0.0));
     if (rnorm <= target) {
       converged = true;
       break;
     }
     if (po.iters == 0 || !std::isfinite(rnorm)) break;
+    inner = std::max(o.refine_inner_rtol, std::min(1e-2, 0.5 * target / rnorm));
   }
   return CSIPM_OK;
 }
@@ -523,9 +566,6 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       break;
     }
     const double smu = o.sigma * mu;
-    const bool need32 = o.precision == CSIPM_FP32;
-    ipm_newton<float>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, lam, smu, c->sig1, c->sig2, c->rhb, c->rhz,
-                      need32 ? c->sig1f : nullptr, need32 ? c->sig2f : nullptr, n, c->s);
     const double eta = std::min(o.cg_rtol, 0.1 * rel);
     int cgi = 0, ref = 0;
     bool conv = false, fell = false;
@@ -536,11 +576,11 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       csipm_options ol = o;
       const int budget = prev_cg > 0 ? std::min(o.cg_max, std::max(8, (prev_cg * 3) / 2)) : o.cg_max;
       ol.cg_max = budget;
-      st = newton_solve(c, ol, eta, c->pc_c, cgi, ref, conv, false);
+      st = newton_solve(c, ol, smu, eta, c->pc_c, cgi, ref, conv, false);
       if (st != CSIPM_OK) return st;
       if (!conv) {
         int cgi2 = 0, ref2 = 0;
-        st = newton_solve(c, o, eta, nullptr, cgi2, ref2, conv, false);
+        st = newton_solve(c, o, smu, eta, nullptr, cgi2, ref2, conv, false);
         if (st != CSIPM_OK) return st;
         cgi += cgi2;
         ref += ref2;
@@ -548,7 +588,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
         ++inf.fallbacks;
       }
     } else {
-      st = newton_solve(c, o, eta, nullptr, cgi, ref, conv, capture);
+      st = newton_solve(c, o, smu, eta, nullptr, cgi, ref, conv, capture);
       if (st != CSIPM_OK) return st;
       if (capture) {
         mlp_scale_weights(c->cap_rec + (size_t)c->cap_count * c->cap_per_iter * MLP_REC, c->cap_per_iter,
@@ -789,6 +829,16 @@ csipm_status csipm_captured(csipm_ctx* c, int* n_iters, int* cg_counts_host, int
   return CSIPM_OK;
 }
 
+csipm_status csipm_pc_correction(csipm_ctx* c, double* d_c) {
+  if (!c || !d_c) return CSIPM_EINVAL;
+  if (!c->have_params) return fail(c, CSIPM_ESTATE, "learned preconditioner has no parameters");
+  absmax(c->beta, c->g.n, c->partV, c->scal + S_RESID + 4, c->s);
+  csipm_status st = learned_correction(c);
+  if (st != CSIPM_OK) return st;
+  launch_to_external<float, double>(c->g, c->pc_c, d_c, c->s);
+  return hip_check(c, "pc_correction");
+}
+
 csipm_status csipm_features(csipm_ctx* c, float* d_feat) {
   if (!c || !d_feat) return CSIPM_EINVAL;
   absmax(c->beta, c->g.n, c->partV, c->scal + S_RESID + 4, c->s);
@@ -812,8 +862,10 @@ csipm_status csipm_profile_kapply(csipm_ctx* c, int precision, int reps, double*
     const T* s1 = std::is_same<T, double>::value ? (const T*)c->sig1 : (const T*)c->sig1f;
     const T* s2 = std::is_same<T, double>::value ? (const T*)c->sig2 : (const T*)c->sig2f;
     const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>));
-    KArgs<T> ka{pb, pz, s1, s2, qb, qz, c->partK};
-    KArgs<T> kb{pb, pz, s1, s2, qb, qz, c->partK + nb5};
+    const int ps = (int)k_partials(g.n1, g.n2, g.n3);
+    EpiArgs<T> ka{KArgs<T>{pb, pz, s1, s2, qb, qz}, RArgs{}, c->partK, ps};
+    EpiArgs<T> kb = ka;
+    kb.partial = c->partK + nb5;
     for (int r = 0; r < reps; ++r) {
       (void)hipEventRecord(ev[0], c->s);
       launch_premix<T>(g, pb, work, nullptr, c->s);

@@ -120,10 +120,11 @@ struct Grid {
 // Selects what the axis-3 pass does.
 enum Axis3Mode { A3_C2R = 1, A3_R2C = 2, A3_FULL = 3 };
 
-// Epilogue of the last forward pass (axis 1).
+// Epilogue of the last forward pass (axis 1) and of the m = 0 postmix pass.
 enum EpiMode {
   EPI_NONE = 0,   // write the transform result (A^T x or H p), m = 0 left raw
-  EPI_K = 1       // q = K p with the barrier diagonals, plus p.q partials
+  EPI_K = 1,      // q = K p with the barrier diagonals, plus p.q partials
+  EPI_R = 2       // FP64 only: r = h - K d, FP32 restart vectors, two dots
 };
 
 template <typename T>
@@ -134,8 +135,53 @@ struct KArgs {
   const T* sig2;      // Sigma_2
   T* qb;
   T* qz;
-  double* partial;    // one double per workgroup
 };
+
+struct RArgs {
+  const double* db;   // d_beta, d_z: the current correction (K input)
+  const double* dz;
+  const double* sig1;
+  const double* sig2;
+  const double* hb;   // right-hand side
+  const double* hz;
+  const float* c;     // learned correction or null (c = 1)
+  float* frb;         // FP32 restart of the inner PCG: r, z = P_c^{-1} r, p = z
+  float* frz;
+  float* fzb;
+  float* fzz;
+  float* fpb;
+  float* fpz;
+};
+
+// Epilogue arguments: quantity q of block b goes to partial[q * pstride + b].
+template <typename T>
+struct EpiArgs {
+  KArgs<T> k;
+  RArgs r;
+  double* partial;
+  int pstride;
+};
+
+// One element of q = K p in Sigma form:
+//   q_b = h + S1 (p_b + p_z) + S2 (p_b - p_z),  q_z = S1 (p_b + p_z) - S2 (p_b - p_z)
+template <typename T>
+__device__ __forceinline__ void k_block(T h, T pb, T pz, T s1, T s2, T& qb, T& qz) {
+  const T a = pb + pz, d = pb - pz;
+  qb = h + s1 * a + s2 * d;
+  qz = s1 * a - s2 * d;
+}
+
+// One 2x2 block of P_c^{-1} (equation "invprecond1" with C = diag(c)):
+//   [zb; zz] = [[L1, -L2], [-L2, c + L1]] [rb; rz] / (c L1 + 4 S1 S2),
+// coefficients formed in double.
+template <typename T>
+__device__ __forceinline__ void pinv_block(T rb, T rz, T s1, T s2, double c, T& zb, T& zz) {
+  const double S1 = (double)s1, S2 = (double)s2;
+  const double L1 = S1 + S2, L2 = S1 - S2;
+  const double inv = 1.0 / (c * L1 + 4.0 * S1 * S2);
+  zb = (T)((L1 * (double)rb - L2 * (double)rz) * inv);
+  zz = (T)((-L2 * (double)rb + (c + L1) * (double)rz) * inv);
+}
 
 // FFT driver entry points (fft.hip).  All work is queued on `s`.
 // `skip` (nullable device int): when nonzero at launch time the kernel
@@ -144,12 +190,12 @@ template <typename T>
 void launch_premix(const Grid& g, const T* src, T* work, const int* skip, hipStream_t s);
 template <typename T>
 void launch_axis12(const Grid& g, int axis, int dir, const T* src, T* dst, const Twiddles<T>& tw,
-                   int epi, const KArgs<T>* ka, bool m0_from_dst, const int* skip, hipStream_t s);
+                   int epi, const EpiArgs<T>* ea, bool m0_from_dst, const int* skip, hipStream_t s);
 template <typename T>
 void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t* maskbits,
                   const Twiddles<T>& tw, const int* skip, hipStream_t s);
 template <typename T>
-void launch_postmix(const Grid& g, const T* work, T* out, int epi, const KArgs<T>* ka,
+void launch_postmix(const Grid& g, const T* work, T* out, int epi, const EpiArgs<T>* ea,
                     const int* skip, hipStream_t s);
 int axis12_blocks(const Grid& g, int axis, int elem_bytes);
 int postmix_blocks(const Grid& g);

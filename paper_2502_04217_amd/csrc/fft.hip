@@ -23,6 +23,7 @@
 #include "csipm_internal.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace csipm {
 
@@ -144,23 +145,90 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block sum of v into *out (thread 0).  `red` is LDS scratch of at least
-// NTHREADS/64 doubles; it may alias the FFT exchange buffer, so the block
-// synchronises before writing it.
-template <int NTHREADS>
-__device__ __forceinline__ void block_sum_store(double v, double* out, double* red) {
-  v = wave_sum(v);
+// Block sums of NQ values; thread 0 writes out[q * stride + blockIdx.x].
+// `red` is LDS scratch of at least NQ * NTHREADS/64 doubles; it may alias the
+// FFT exchange buffer, so the block synchronises before writing it.
+template <int NTHREADS, int NQ>
+__device__ __forceinline__ void block_sums_store(const double* v, double* out, int stride, double* red) {
+  constexpr int NW = NTHREADS / 64;
+  double w[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) w[q] = wave_sum(v[q]);
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int wv = threadIdx.x >> 6;
   __syncthreads();
-  if (lane == 0) red[w] = v;
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) red[q * NW + wv] = w[q];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < NTHREADS / 64; ++i) s += red[i];
-    *out = s;
-  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double a = 0.0;
+      for (int i = 0; i < NW; ++i) a += red[q * NW + i];
+      out[q * stride + blockIdx.x] = a;
+    }
 }
+
+// ------------------------------------------------------------ epilogues --
+// Applied to each output element h = (H p)[idx] of the last forward pass
+// (m >= 1 there, the m = 0 plane in the postmix pass).
+struct EpiNone {
+  static constexpr int NRED = 0;
+  double* partial = nullptr;
+  int pstride = 0;
+};
+
+// q = K p (equation "condensedkkt" in Sigma form) and p.q
+template <typename T>
+struct EpiK {
+  static constexpr int NRED = 1;
+  KArgs<T> a;
+  double* partial;
+  int pstride;
+  __device__ __forceinline__ void operator()(long long idx, cx<T> h, double* acc) const {
+    const cx<T> pb = reinterpret_cast<const cx<T>*>(a.pb)[idx];
+    const cx<T> pz = reinterpret_cast<const cx<T>*>(a.pz)[idx];
+    const cx<T> s1 = reinterpret_cast<const cx<T>*>(a.sig1)[idx];
+    const cx<T> s2 = reinterpret_cast<const cx<T>*>(a.sig2)[idx];
+    cx<T> qb, qz;
+    k_block<T>(h.re, pb.re, pz.re, s1.re, s2.re, qb.re, qz.re);
+    k_block<T>(h.im, pb.im, pz.im, s1.im, s2.im, qb.im, qz.im);
+    reinterpret_cast<cx<T>*>(a.qb)[idx] = qb;
+    reinterpret_cast<cx<T>*>(a.qz)[idx] = qz;
+    acc[0] += (double)pb.re * (double)qb.re + (double)pb.im * (double)qb.im + (double)pz.re * (double)qz.re +
+              (double)pz.im * (double)qz.im;
+  }
+};
+
+// FP64 refinement residual r = h - K d, the FP32 start of the next inner
+// PCG (r32, z32 = P_c^{-1} r, p32 = z32) and the sums r.P_c^{-1}r, r32.z32.
+struct EpiR {
+  static constexpr int NRED = 2;
+  RArgs a;
+  double* partial;
+  int pstride;
+  __device__ __forceinline__ void one(long long i, double h, double& acc0, double& acc1) const {
+    double qb, qz;
+    k_block<double>(h, a.db[i], a.dz[i], a.sig1[i], a.sig2[i], qb, qz);
+    const double rb = a.hb[i] - qb, rz = a.hz[i] - qz;
+    double zb, zz;
+    pinv_block(rb, rz, a.sig1[i], a.sig2[i], a.c ? (double)a.c[i] : 1.0, zb, zz);
+    const float fb = (float)rb, fz = (float)rz, gb = (float)zb, gz = (float)zz;
+    a.frb[i] = fb;
+    a.frz[i] = fz;
+    a.fzb[i] = gb;
+    a.fzz[i] = gz;
+    a.fpb[i] = gb;
+    a.fpz[i] = gz;
+    acc0 += rb * zb + rz * zz;
+    acc1 += (double)fb * (double)gb + (double)fz * (double)gz;
+  }
+  __device__ __forceinline__ void operator()(long long idx, cx<double> h, double* acc) const {
+    one(2 * idx, h.re, acc[0], acc[1]);
+    one(2 * idx + 1, h.im, acc[0], acc[1]);
+  }
+};
 
 // --------------------------------------------------- strided pencil pass --
 // Complex FFT along axis 1 or 2 over the array [N1][N2][M].  Pencil q has
@@ -182,11 +250,13 @@ constexpr int strided_tm(int L) {
 }
 template <typename T, int L>
 constexpr int strided_e() { return L < 16 ? L : 16; }
+template <typename T, int L>
+constexpr int strided_threads() { return strided_tm<T>(L) * (L / strided_e<T, L>()); }
 
-template <typename T, int L, int DIR, int EPI>
-__global__ void __launch_bounds__(1024)
+template <typename T, int L, int DIR, class Epi>
+__global__ void __launch_bounds__((strided_threads<T, L>()))
 k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
-         const cx<T>* __restrict__ tw, int m, int m0_from_dst, KArgs<T> ka, const int* skip) {
+         const cx<T>* __restrict__ tw, int m, int m0_from_dst, Epi epi, const int* skip) {
   if (skip && *skip) return;
   constexpr int E = strided_e<T, L>();
   constexpr int TM = strided_tm<T>(L);
@@ -214,42 +284,23 @@ k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
   fft_stages<T, L, E, DIR, 0>(v, t, lds, lidx, tw);
 
   constexpr int rl = radix_of<L, E, Radix<L, E>::NSTAGES - 1>();
-  if constexpr (EPI == EPI_K) {
-    double acc = 0.0;
+  if constexpr (Epi::NRED > 0) {
+    double acc[Epi::NRED];
+#pragma unroll
+    for (int q = 0; q < Epi::NRED; ++q) acc[q] = 0.0;
     if (active) {
 #pragma unroll
       for (int i = 0; i < E / rl; ++i)
 #pragma unroll
         for (int q = 0; q < rl; ++q) {
-          const int e = last_elem<T, L, E>(t, i, q);
-          const long long idx = base + (long long)e * geo.estride;
-          const cx<T> h = v[i * rl + q];
-          if (is_m0) {
-            dst[idx] = h;   // finished by the postmix pass
-          } else {
-            const cx<T> pb = reinterpret_cast<const cx<T>*>(ka.pb)[idx];
-            const cx<T> pz = reinterpret_cast<const cx<T>*>(ka.pz)[idx];
-            const cx<T> s1 = reinterpret_cast<const cx<T>*>(ka.sig1)[idx];
-            const cx<T> s2 = reinterpret_cast<const cx<T>*>(ka.sig2)[idx];
-            cx<T> qb, qz;
-            {
-              const T a = pb.re + pz.re, d = pb.re - pz.re;
-              qb.re = h.re + s1.re * a + s2.re * d;
-              qz.re = s1.re * a - s2.re * d;
-            }
-            {
-              const T a = pb.im + pz.im, d = pb.im - pz.im;
-              qb.im = h.im + s1.im * a + s2.im * d;
-              qz.im = s1.im * a - s2.im * d;
-            }
-            reinterpret_cast<cx<T>*>(ka.qb)[idx] = qb;
-            reinterpret_cast<cx<T>*>(ka.qz)[idx] = qz;
-            acc += (double)pb.re * (double)qb.re + (double)pb.im * (double)qb.im +
-                   (double)pz.re * (double)qz.re + (double)pz.im * (double)qz.im;
-          }
+          const long long idx = base + (long long)last_elem<T, L, E>(t, i, q) * geo.estride;
+          if (is_m0)
+            dst[idx] = v[i * rl + q];   // finished by the postmix pass
+          else
+            epi(idx, v[i * rl + q], acc);
         }
     }
-    block_sum_store<TM * NT>(acc, &ka.partial[blockIdx.x], reinterpret_cast<double*>(smem_raw));
+    block_sums_store<TM * NT, Epi::NRED>(acc, epi.partial, epi.pstride, reinterpret_cast<double*>(smem_raw));
   } else {
     if (active) {
 #pragma unroll
@@ -448,12 +499,14 @@ __global__ void k_premix(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
   dst[ib] = cscale(csub(a, ib_), r);
 }
 
-template <typename T, int EPI>
+template <typename T, class Epi>
 __global__ void __launch_bounds__(256)
-k_postmix(const cx<T>* work, cx<T>* out, int n1, int n2, int m, KArgs<T> ka, const int* skip) {
+k_postmix(const cx<T>* work, cx<T>* out, int n1, int n2, int m, Epi epi, const int* skip) {
   if (skip && *skip) return;
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  double acc = 0.0;
+  double acc[Epi::NRED > 0 ? Epi::NRED : 1];
+#pragma unroll
+  for (int q = 0; q < (Epi::NRED > 0 ? Epi::NRED : 1); ++q) acc[q] = 0.0;
   if (id < n1 * n2) {
     const int k1 = id / n2, k2 = id % n2;
     const int c = cls2(k1, k2, n1, n2);
@@ -474,38 +527,18 @@ k_postmix(const cx<T>* work, cx<T>* out, int n1, int n2, int m, KArgs<T> ka, con
         hb = cscale(cmul_i<1>(csub(b, a)), r);
         cnt = 2;
       }
-      for (int s = 0; s < cnt; ++s) {
-        const long long idx = s == 0 ? ia : ib;
-        const cx<T> h = s == 0 ? ha : hb;
-        if constexpr (EPI == EPI_K) {
-          const cx<T> pb = reinterpret_cast<const cx<T>*>(ka.pb)[idx];
-          const cx<T> pz = reinterpret_cast<const cx<T>*>(ka.pz)[idx];
-          const cx<T> s1 = reinterpret_cast<const cx<T>*>(ka.sig1)[idx];
-          const cx<T> s2 = reinterpret_cast<const cx<T>*>(ka.sig2)[idx];
-          cx<T> qb, qz;
-          {
-            const T a = pb.re + pz.re, d = pb.re - pz.re;
-            qb.re = h.re + s1.re * a + s2.re * d;
-            qz.re = s1.re * a - s2.re * d;
-          }
-          {
-            const T a = pb.im + pz.im, d = pb.im - pz.im;
-            qb.im = h.im + s1.im * a + s2.im * d;
-            qz.im = s1.im * a - s2.im * d;
-          }
-          reinterpret_cast<cx<T>*>(ka.qb)[idx] = qb;
-          reinterpret_cast<cx<T>*>(ka.qz)[idx] = qz;
-          acc += (double)pb.re * (double)qb.re + (double)pb.im * (double)qb.im +
-                 (double)pz.re * (double)qz.re + (double)pz.im * (double)qz.im;
-        } else {
-          out[idx] = h;
-        }
+      if constexpr (Epi::NRED > 0) {
+        epi(ia, ha, acc);
+        if (cnt == 2) epi(ib, hb, acc);
+      } else {
+        out[ia] = ha;
+        if (cnt == 2) out[ib] = hb;
       }
     }
   }
-  if constexpr (EPI == EPI_K) {
-    __shared__ double red[4];
-    block_sum_store<256>(acc, &ka.partial[blockIdx.x], red);
+  if constexpr (Epi::NRED > 0) {
+    __shared__ double red[4 * Epi::NRED];
+    block_sums_store<256, Epi::NRED>(acc, epi.partial, epi.pstride, red);
   }
 }
 
@@ -570,16 +603,16 @@ int grid_for(long long n, int block) {
   return (int)g;
 }
 
-template <typename T, int DIR, int EPI>
+template <typename T, int DIR, class Epi>
 void launch_axis12_L(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* tw,
-                     int m, int m0, KArgs<T> ka, const int* skip, hipStream_t s) {
+                     int m, int m0, Epi epi, const int* skip, hipStream_t s) {
 #define CSIPM_A12(LL)                                                                          \
   case LL: {                                                                                   \
     constexpr int TM = strided_tm<T>(LL);                                                      \
     constexpr int NT = LL / strided_e<T, LL>();                                                \
     const size_t shm = (size_t)TM * LL * sizeof(cx<T>);                                        \
-    hipLaunchKernelGGL((k_axis12<T, LL, DIR, EPI>), grid, dim3(TM * NT), shm, s, src, dst, geo, \
-                       tw, m, m0, ka, skip);                                                   \
+    hipLaunchKernelGGL((k_axis12<T, LL, DIR, Epi>), grid, dim3(TM * NT), shm, s, src, dst, geo, \
+                       tw, m, m0, epi, skip);                                                  \
     break;                                                                                     \
   }
   switch (L) {
@@ -651,21 +684,22 @@ void launch_premix(const Grid& g, const T* src, T* work, const int* skip, hipStr
 
 template <typename T>
 void launch_axis12(const Grid& g, int axis, int dir, const T* src, T* dst, const Twiddles<T>& tw, int epi,
-                   const KArgs<T>* ka, bool m0_from_dst, const int* skip, hipStream_t s) {
+                   const EpiArgs<T>* ea, bool m0_from_dst, const int* skip, hipStream_t s) {
   const int L = axis == 1 ? g.n1 : g.n2;
   const cx<T>* twp = axis == 1 ? tw.t1 : tw.t2;
   StridedGeom<T> geo = geom<T>(g, axis);
   dim3 grid(axis12_blocks(g, axis, (int)sizeof(cx<T>)));
-  KArgs<T> k{};
-  if (ka) k = *ka;
   const cx<T>* cs = reinterpret_cast<const cx<T>*>(src);
   cx<T>* cd = reinterpret_cast<cx<T>*>(dst);
   if (dir > 0) {
-    launch_axis12_L<T, +1, EPI_NONE>(L, grid, cs, cd, geo, twp, g.m, m0_from_dst ? 1 : 0, k, skip, s);
+    launch_axis12_L<T, +1>(L, grid, cs, cd, geo, twp, g.m, m0_from_dst ? 1 : 0, EpiNone{}, skip, s);
   } else if (epi == EPI_K) {
-    launch_axis12_L<T, -1, EPI_K>(L, grid, cs, cd, geo, twp, g.m, 0, k, skip, s);
+    launch_axis12_L<T, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiK<T>{ea->k, ea->partial, ea->pstride}, skip, s);
+  } else if (epi == EPI_R) {
+    if constexpr (std::is_same<T, double>::value)
+      launch_axis12_L<T, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiR{ea->r, ea->partial, ea->pstride}, skip, s);
   } else {
-    launch_axis12_L<T, -1, EPI_NONE>(L, grid, cs, cd, geo, twp, g.m, 0, k, skip, s);
+    launch_axis12_L<T, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiNone{}, skip, s);
   }
 }
 
@@ -714,17 +748,21 @@ void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t*
 }
 
 template <typename T>
-void launch_postmix(const Grid& g, const T* work, T* out, int epi, const KArgs<T>* ka, const int* skip,
+void launch_postmix(const Grid& g, const T* work, T* out, int epi, const EpiArgs<T>* ea, const int* skip,
                     hipStream_t s) {
-  KArgs<T> k{};
-  if (ka) k = *ka;
   dim3 grid(postmix_blocks(g));
-  if (epi == EPI_K)
-    hipLaunchKernelGGL((k_postmix<T, EPI_K>), grid, dim3(256), 0, s, reinterpret_cast<const cx<T>*>(work),
-                       reinterpret_cast<cx<T>*>(out), g.n1, g.n2, g.m, k, skip);
-  else
-    hipLaunchKernelGGL((k_postmix<T, EPI_NONE>), grid, dim3(256), 0, s, reinterpret_cast<const cx<T>*>(work),
-                       reinterpret_cast<cx<T>*>(out), g.n1, g.n2, g.m, k, skip);
+  const cx<T>* w = reinterpret_cast<const cx<T>*>(work);
+  cx<T>* o = reinterpret_cast<cx<T>*>(out);
+  if (epi == EPI_K) {
+    hipLaunchKernelGGL((k_postmix<T, EpiK<T>>), grid, dim3(256), 0, s, w, o, g.n1, g.n2, g.m,
+                       EpiK<T>{ea->k, ea->partial, ea->pstride}, skip);
+  } else if (epi == EPI_R) {
+    if constexpr (std::is_same<T, double>::value)
+      hipLaunchKernelGGL((k_postmix<T, EpiR>), grid, dim3(256), 0, s, w, o, g.n1, g.n2, g.m,
+                         EpiR{ea->r, ea->partial, ea->pstride}, skip);
+  } else {
+    hipLaunchKernelGGL((k_postmix<T, EpiNone>), grid, dim3(256), 0, s, w, o, g.n1, g.n2, g.m, EpiNone{}, skip);
+  }
 }
 
 template <typename Te, typename Ti>
@@ -749,11 +787,11 @@ void launch_pack_mask(const Grid& g, const uint8_t* obs, uint32_t* bits, hipStre
 
 #define CSIPM_INST(T)                                                                                          \
   template void launch_premix<T>(const Grid&, const T*, T*, const int*, hipStream_t);                          \
-  template void launch_axis12<T>(const Grid&, int, int, const T*, T*, const Twiddles<T>&, int, const KArgs<T>*, \
-                                 bool, const int*, hipStream_t);                                               \
+  template void launch_axis12<T>(const Grid&, int, int, const T*, T*, const Twiddles<T>&, int,                 \
+                                 const EpiArgs<T>*, bool, const int*, hipStream_t);                            \
   template void launch_axis3<T>(const Grid&, int, const T*, T*, const uint32_t*, const Twiddles<T>&,           \
                                 const int*, hipStream_t);                                                      \
-  template void launch_postmix<T>(const Grid&, const T*, T*, int, const KArgs<T>*, const int*, hipStream_t);  \
+  template void launch_postmix<T>(const Grid&, const T*, T*, int, const EpiArgs<T>*, const int*, hipStream_t); \
   template void launch_to_internal<double, T>(const Grid&, const double*, T*, hipStream_t);                   \
   template void launch_to_internal<float, T>(const Grid&, const float*, T*, hipStream_t);                     \
   template void launch_to_external<T, double>(const Grid&, const T*, double*, hipStream_t);                   \

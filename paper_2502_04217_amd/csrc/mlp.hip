@@ -25,8 +25,25 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
-__device__ __forceinline__ float sigmoidf(float x) { return 0.5f * (1.0f + tanhf(0.5f * x)); }
+// tanh in float32 to ~2e-7 relative: an odd polynomial (least-squares fit
+// of tanh(x)/x in x^2 on [0, 0.55]) below 0.55, 1 - 2/(exp(2|x|) + 1) above.
+__device__ __forceinline__ float tanh_fast(float x) {
+  const float ax = fabsf(x);
+  if (ax < 0.55f) {
+    const float t = x * x;
+    float p = -0.0063321318888434315f;
+    p = fmaf(p, t, 0.021107190038856506f);
+    p = fmaf(p, t, -0.05385906545947602f);
+    p = fmaf(p, t, 0.13332620512105214f);
+    p = fmaf(p, t, -0.33333316330560286f);
+    p = fmaf(p, t, 0.9999999993472424f);
+    return x * p;
+  }
+  const float e = __expf(2.0f * ax);
+  return copysignf(1.0f - __fdividef(2.0f, e + 1.0f), x);
+}
+__device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(__expf(-fabsf(x))); }
+__device__ __forceinline__ float sigmoidf(float x) { return 0.5f * (1.0f + tanh_fast(0.5f * x)); }
 
 __device__ __forceinline__ void load_params(const float* __restrict__ g, float* s) {
   for (int i = threadIdx.x; i < MLP_NP; i += blockDim.x) s[i] = g[i];
@@ -40,7 +57,7 @@ __device__ __forceinline__ float fwd1(const float* P, const float x[NIN], float 
     float a = P[OB1 + i];
 #pragma unroll
     for (int j = 0; j < NIN; ++j) a = fmaf(P[OW1 + i * NIN + j], x[j], a);
-    h1[i] = tanhf(a);
+    h1[i] = tanh_fast(a);
   }
   float o = P[OB3];
 #pragma unroll 4
@@ -48,16 +65,14 @@ __device__ __forceinline__ float fwd1(const float* P, const float x[NIN], float 
     float a = P[OB2 + i];
 #pragma unroll
     for (int j = 0; j < H1; ++j) a = fmaf(P[OW2 + i * H1 + j], h1[j], a);
-    h2[i] = tanhf(a);
+    h2[i] = tanh_fast(a);
     o = fmaf(P[OW3 + i], h2[i], o);
   }
   return o;
 }
 
 __global__ void __launch_bounds__(256)
-k_forward(const float* __restrict__ params, const float* __restrict__ feat, float* __restrict__ c, long long n) {
-  __shared__ float P[MLP_NP];
-  load_params(params, P);
+k_forward(const float* __restrict__ P, const float* __restrict__ feat, float* __restrict__ c, long long n) {
   for (long long i = gtid(); i < n; i += gstride()) {
     const float4 f = reinterpret_cast<const float4*>(feat)[i];
     const float x[NIN] = {f.x, f.y, f.z, f.w};
@@ -225,6 +240,69 @@ k_features(const double* __restrict__ s1, const double* __restrict__ s2, const d
   }
 }
 
+
+// The same two steps computed from the interior-point state, with
+// Sigma_j = nu_j / s_j, s1 = z + beta, s2 = z - beta formed on the fly.
+__global__ void __launch_bounds__(256)
+k_log_l1_state(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
+               const double* __restrict__ nu2, long long n, double* partial) {
+  double a = 0.0;
+  for (long long i = gtid(); i < n; i += gstride())
+    a += log(nu1[i] / (z[i] + beta[i]) + nu2[i] / (z[i] - beta[i]));
+  __shared__ double red[4];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256)
+k_features_state(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
+                 const double* __restrict__ nu2, const double* __restrict__ diagH,
+                 const double* __restrict__ meanlog, const double* __restrict__ bmax, float* __restrict__ feat,
+                 long long n) {
+  const double ml = *meanlog;
+  const double bm = *bmax > 0.0 ? *bmax : 1.0;
+  for (long long i = gtid(); i < n; i += gstride()) {
+    const double b = beta[i];
+    const double g1 = nu1[i] / (z[i] + b), g2 = nu2[i] / (z[i] - b);
+    const double L1 = g1 + g2, L2 = g1 - g2;
+    float4 f;
+    f.x = (float)(log(L1) - ml);
+    f.y = (float)(L2 / L1);
+    f.z = (float)log(fabs(b) / bm + 1e-12);
+    f.w = (float)diagH[i];
+    reinterpret_cast<float4*>(feat)[i] = f;
+  }
+}
+
+
+// Correction of the interior-point state in one pass: Sigma_j = nu_j / s_j,
+// the four features, and c = softplus(MLP) + 1e-6 only where c can act on
+// P_c^{-1}, i.e. where L1 / (L1 + 4 S1 S2) >= rmin; elsewhere c = 1 (the
+// paper's P, from which P_c^{-1} then differs by less than rmin relative).
+__global__ void __launch_bounds__(256)
+k_correction_state(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
+                   const double* __restrict__ nu2, const double* __restrict__ diagH,
+                   const double* __restrict__ meanlog, const double* __restrict__ bmax,
+                   const float* __restrict__ P, float* __restrict__ c, long long n, double rmin) {
+  const double ml = *meanlog;
+  const double bm = *bmax > 0.0 ? *bmax : 1.0;
+  for (long long i = gtid(); i < n; i += gstride()) {
+    const double b = beta[i];
+    const double g1 = nu1[i] / (z[i] + b), g2 = nu2[i] / (z[i] - b);
+    const double L1 = g1 + g2;
+    float ci = 1.0f;
+    if (L1 >= rmin * (L1 + 4.0 * g1 * g2)) {
+      const float x[NIN] = {(float)(log(L1) - ml), (float)((g1 - g2) / L1), (float)log(fabs(b) / bm + 1e-12),
+                            (float)diagH[i]};
+      float h1[H1], h2[H2];
+      ci = softplusf(fwd1(P, x, h1, h2)) + 1e-6f;
+    }
+    c[i] = ci;
+  }
+}
+
 __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
   x += 0x9E3779B97F4A7C15ull;
   x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -289,6 +367,26 @@ void mlp_mean_log_l1(const double* s1, const double* s2, long long n, double* pa
 void mlp_features(const double* s1, const double* s2, const double* beta, const double* diagH, const double* meanlog,
                   const double* bmax, float* feat, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_features, dim3(blocks_for(n)), dim3(256), 0, s, s1, s2, beta, diagH, meanlog, bmax, feat, n);
+}
+
+void mlp_features_state(const double* beta, const double* z, const double* nu1, const double* nu2,
+                        const double* diagH, const double* bmax, float* feat, long long n, double* partial,
+                        double* meanlog, hipStream_t s) {
+  const int nb = blocks_for(n);
+  hipLaunchKernelGGL(k_log_l1_state, dim3(nb), dim3(256), 0, s, beta, z, nu1, nu2, n, partial);
+  hipLaunchKernelGGL(k_fin_mean, dim3(1), dim3(256), 0, s, partial, nb, 1.0 / (double)n, meanlog);
+  hipLaunchKernelGGL(k_features_state, dim3(nb), dim3(256), 0, s, beta, z, nu1, nu2, diagH, (const double*)meanlog,
+                     bmax, feat, n);
+}
+
+void mlp_correction_state(const double* beta, const double* z, const double* nu1, const double* nu2,
+                          const double* diagH, const double* bmax, const float* params, float* c, long long n,
+                          double* partial, double* meanlog, double rmin, hipStream_t s) {
+  const int nb = blocks_for(n);
+  hipLaunchKernelGGL(k_log_l1_state, dim3(nb), dim3(256), 0, s, beta, z, nu1, nu2, n, partial);
+  hipLaunchKernelGGL(k_fin_mean, dim3(1), dim3(256), 0, s, partial, nb, 1.0 / (double)n, meanlog);
+  hipLaunchKernelGGL(k_correction_state, dim3(nb), dim3(256), 0, s, beta, z, nu1, nu2, diagH,
+                     (const double*)meanlog, bmax, params, c, n, rmin);
 }
 
 void mlp_forward(const float* params, const float* feat, float* c, long long n, hipStream_t s) {

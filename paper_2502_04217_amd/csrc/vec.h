@@ -6,7 +6,7 @@
 
 namespace csipm {
 
-constexpr int VEC_MAX_BLOCKS = 4096;   // partial sums per reduced quantity
+constexpr int VEC_MAX_BLOCKS = 2048;   // partial sums per reduced quantity
 
 enum RedOp { RED_SUM = 0, RED_MAX = 1, RED_MIN = 2 };
 template <int NQ>
@@ -28,6 +28,7 @@ enum ScalarSlot {
   S_RESID = 16,    // IPM residual block, 7 values (k_ipm_resid order)
   S_REF = 24,      // refinement: r.P^{-1}r of the FP64 residual
   S_REF0 = 25,     // refinement: rhs.P^{-1}rhs
+  S_REFRZ = 26,    // refinement: r32.P^{-1}r32, start of the next inner PCG
   S_SIG = 28,      // signal check: non-finite count, observed count
   S_MISC = 32,     // free scratch (32 values)
   S_COUNT = 64
@@ -43,12 +44,23 @@ void cg_init(const T* hb, const T* hz, T* xb, T* xz, T* rb, T* rz, T* zb, T* zz,
 template <typename T>
 void cg_update(T* xb, T* xz, const T* pb, const T* pz, const T* qb, const T* qz, T* rb, T* rz, T* zb, T* zz,
                const T* s1, const T* s2, const float* c, const double* scal, const int* flags, long long n,
-               double* partial, hipStream_t s);
+               double* partial, bool first, hipStream_t s);
 template <typename T>
 void cg_pupdate(T* pb, T* pz, const T* zb, const T* zz, const double* scal, const int* flags, long long n,
                 hipStream_t s);
 void fin_cg_init(const double* partial, int nb, double* scal, int* flags, double eta, double atol, int maxit,
                  hipStream_t s);
+// rz0 from partial quantity 0 (or scal[from_slot] when >= 0); quantity 1
+// (at partial + stride) summed into scal[ref_slot] when ref_slot >= 0
+void fin_cg_start(const double* partial, int nb, int stride, double* scal, int* flags, double eta, double atol,
+                  int maxit, int ref_slot, int from_slot, hipStream_t s);
+void fin_two(const double* partial, int nb, int stride, double* scal, int s0, int s1, hipStream_t s);
+template <typename TC>
+void newton_init(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
+                 const double* xi, double lam, double smu, double* sig1, double* sig2, double* hb_out,
+                 double* hz_out, TC* sig1c, TC* sig2c, const float* c, TC* rb, TC* rz, TC* zb, TC* zz, TC* pb,
+                 TC* pz, long long n, double* partial, hipStream_t s);
+void set_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s);
 void fin_alpha(const double* partial, int nb, double* scal, int* flags, hipStream_t s);
 void fin_rz(const double* partial, int nb, double* scal, int* flags, hipStream_t s);
 

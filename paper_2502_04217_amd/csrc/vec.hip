@@ -8,6 +8,7 @@
 #include "vec.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace csipm {
 
@@ -62,15 +63,9 @@ __device__ __forceinline__ double block_sum_256(double v) {
   return s;
 }
 
-// P_c^{-1} r for one 2x2 block (equation "invprecond1" with C = diag(c)),
-// coefficients formed in double.
 template <typename T>
 __device__ __forceinline__ void pinv1(T rb, T rz, T s1, T s2, double c, T& zb, T& zz) {
-  const double S1 = (double)s1, S2 = (double)s2;
-  const double L1 = S1 + S2, L2 = S1 - S2;
-  const double inv = 1.0 / (c * L1 + 4.0 * S1 * S2);
-  zb = (T)((L1 * (double)rb - L2 * (double)rz) * inv);
-  zz = (T)((-L2 * (double)rb + (c + L1) * (double)rz) * inv);
+  pinv_block<T>(rb, rz, s1, s2, c, zb, zz);
 }
 
 __device__ __forceinline__ long long gtid() { return blockIdx.x * (long long)blockDim.x + threadIdx.x; }
@@ -102,19 +97,34 @@ k_cg_init(const T* __restrict__ hb, const T* __restrict__ hz, T* __restrict__ xb
   block_reduce_store<1>(&acc, &op, partial, 0);
 }
 
+// x += alpha p (x = alpha p on the first iteration: x0 = 0 is never stored),
+// r -= alpha q, z = P_c^{-1} r, partial r.z.  A first iteration of a solve
+// that finished at initialisation writes x = 0 and nothing else.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_cg_update(T* __restrict__ xb, T* __restrict__ xz, const T* __restrict__ pb, const T* __restrict__ pz,
             const T* __restrict__ qb, const T* __restrict__ qz, T* __restrict__ rb, T* __restrict__ rz,
             T* __restrict__ zb, T* __restrict__ zz, const T* __restrict__ s1, const T* __restrict__ s2,
             const float* __restrict__ c, const double* __restrict__ scal, const int* __restrict__ flags,
-            long long n, double* partial) {
-  if (flags[F_DONE]) return;
+            long long n, double* partial, int first) {
+  if (flags[F_DONE]) {
+    if (first)
+      for (long long i = gtid(); i < n; i += gstride()) {
+        xb[i] = T(0);
+        xz[i] = T(0);
+      }
+    return;
+  }
   const T a = (T)scal[S_ALPHA];
   double acc = 0.0;
   for (long long i = gtid(); i < n; i += gstride()) {
-    xb[i] += a * pb[i];
-    xz[i] += a * pz[i];
+    if (first) {
+      xb[i] = a * pb[i];
+      xz[i] = a * pz[i];
+    } else {
+      xb[i] += a * pb[i];
+      xz[i] += a * pz[i];
+    }
     const T b = rb[i] - a * qb[i];
     const T z = rz[i] - a * qz[i];
     rb[i] = b;
@@ -147,10 +157,17 @@ __device__ __forceinline__ double fin_sum(const double* partial, int nb) {
   return block_sum_256(a);
 }
 
+// Starts a PCG solve: rz0 from the partials (quantity 0) or, when
+// from_slot >= 0, from scal[from_slot]; with ref_slot >= 0 the second
+// quantity of the partials is summed into scal[ref_slot].
 __global__ void __launch_bounds__(256)
-k_fin_cg_init(const double* partial, int nb, double* scal, int* flags, double eta, double atol, int maxit) {
-  const double rz0 = fin_sum(partial, nb);
+k_fin_cg_init(const double* partial, int nb, int stride, double* scal, int* flags, double eta, double atol,
+              int maxit, int ref_slot, int from_slot) {
+  const double rzp = from_slot >= 0 ? 0.0 : fin_sum(partial, nb);
+  const double ref = ref_slot >= 0 ? fin_sum(partial + stride, nb) : 0.0;
   if (threadIdx.x == 0) {
+    const double rz0 = from_slot >= 0 ? scal[from_slot] : rzp;
+    if (ref_slot >= 0) scal[ref_slot] = ref;
     scal[S_RZ] = rz0;
     scal[S_RZ0] = rz0;
     const double r0 = sqrt(fmax(rz0, 0.0));
@@ -161,6 +178,17 @@ k_fin_cg_init(const double* partial, int nb, double* scal, int* flags, double et
     flags[F_BREAK] = 0;
     flags[F_DONE] = (r0 <= tol || maxit <= 0 || !(rz0 == rz0)) ? 1 : 0;
     flags[F_MAXIT] = maxit;
+  }
+}
+
+// Two sums of the refinement-residual epilogue into scal[s0], scal[s1].
+__global__ void __launch_bounds__(256)
+k_fin_two(const double* partial, int nb, int stride, double* scal, int s0, int s1) {
+  const double a = fin_sum(partial, nb);
+  const double b = fin_sum(partial + stride, nb);
+  if (threadIdx.x == 0) {
+    scal[s0] = a;
+    scal[s1] = b;
   }
 }
 
@@ -260,6 +288,59 @@ k_ipm_newton(const double* __restrict__ beta, const double* __restrict__ z, cons
   }
 }
 
+// Newton system and PCG start in one pass: Sigma_j = nu_j / s_j (FP64, and
+// in TC when sig1c is set), the right-hand side h (written only when hb_out
+// is set), r = h, z = P_c^{-1} r, p = z in the Krylov precision TC, and the
+// partial sums r.z (in TC) and h.P_c^{-1}h (in FP64).  x0 = 0 is implicit.
+template <typename TC>
+__global__ void __launch_bounds__(256)
+k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
+              const double* __restrict__ nu2, const double* __restrict__ hb, const double* __restrict__ xi,
+              double lam, double smu, double* __restrict__ sig1, double* __restrict__ sig2,
+              double* __restrict__ hb_out, double* __restrict__ hz_out, TC* __restrict__ sig1c,
+              TC* __restrict__ sig2c, const float* __restrict__ c, TC* __restrict__ rb, TC* __restrict__ rz,
+              TC* __restrict__ zb, TC* __restrict__ zz, TC* __restrict__ pb, TC* __restrict__ pz, long long n,
+              double* partial) {
+  double acc[2] = {0.0, 0.0};
+  for (long long i = gtid(); i < n; i += gstride()) {
+    const double b = beta[i], zv = z[i];
+    const double s1 = zv + b, s2 = zv - b;
+    const double i1 = 1.0 / s1, i2 = 1.0 / s2;
+    const double g1 = nu1[i] * i1, g2 = nu2[i] * i2;
+    const double h1 = -(hb[i] - xi[i]) + smu * (i1 - i2);
+    const double h2 = -lam + smu * (i1 + i2);
+    sig1[i] = g1;
+    sig2[i] = g2;
+    if (hb_out) {
+      hb_out[i] = h1;
+      hz_out[i] = h2;
+    }
+    const double cc = c ? (double)c[i] : 1.0;
+    double u1, u2;
+    pinv_block<double>(h1, h2, g1, g2, cc, u1, u2);
+    acc[1] += h1 * u1 + h2 * u2;
+    const TC r1 = (TC)h1, r2 = (TC)h2;
+    TC w1, w2;
+    if constexpr (std::is_same<TC, double>::value) {
+      w1 = u1;
+      w2 = u2;
+    } else {
+      pinv_block<TC>(r1, r2, (TC)g1, (TC)g2, cc, w1, w2);
+      sig1c[i] = (TC)g1;
+      sig2c[i] = (TC)g2;
+    }
+    rb[i] = r1;
+    rz[i] = r2;
+    zb[i] = w1;
+    zz[i] = w2;
+    pb[i] = w1;
+    pz[i] = w2;
+    acc[0] += (double)r1 * (double)w1 + (double)r2 * (double)w2;
+  }
+  const int ops[2] = {RED_SUM, RED_SUM};
+  block_reduce_store<2>(acc, ops, partial, VEC_MAX_BLOCKS);
+}
+
 // Largest step keeping s and nu positive, with
 //   ds1 = db + dz, ds2 = dz - db, dnu_j = smu/s_j - nu_j - Sigma_j ds_j.
 __global__ void __launch_bounds__(256)
@@ -316,28 +397,35 @@ k_ipm_update(double* __restrict__ beta, double* __restrict__ z, double* __restri
   }
 }
 
-// Generic multi-value finalize: out[q] = op_q over partial[q*stride + 0..nb).
+// Generic multi-value finalize: out[q] = op_q over partial[q*stride + 0..nb);
+// all quantities are reduced in one sweep.
 template <int NQ>
 __global__ void __launch_bounds__(256)
 k_fin_reduce(const double* partial, int nb, int stride, double* out, RedOps<NQ> ops) {
-  for (int q = 0; q < NQ; ++q) {
-    const int op = ops.op[q];
-    double a = op == RED_SUM ? 0.0 : op == RED_MAX ? -INFINITY : INFINITY;
-    for (int i = threadIdx.x; i < nb; i += 256) {
+  double a[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) a[q] = ops.op[q] == RED_SUM ? 0.0 : ops.op[q] == RED_MAX ? -INFINITY : INFINITY;
+  for (int i = threadIdx.x; i < nb; i += 256)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
       const double x = partial[q * stride + i];
-      a = op == RED_SUM ? a + x : op == RED_MAX ? fmax(a, x) : fmin(a, x);
+      a[q] = ops.op[q] == RED_SUM ? a[q] + x : ops.op[q] == RED_MAX ? fmax(a[q], x) : fmin(a[q], x);
     }
-    a = op == RED_SUM ? wave_sum(a) : op == RED_MAX ? wave_max(a) : wave_min(a);
-    __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double x = red[0];
-      for (int w = 1; w < 4; ++w) x = op == RED_SUM ? x + red[w] : op == RED_MAX ? fmax(x, red[w]) : fmin(x, red[w]);
+  __shared__ double red[NQ][4];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double x = ops.op[q] == RED_SUM ? wave_sum(a[q]) : ops.op[q] == RED_MAX ? wave_max(a[q]) : wave_min(a[q]);
+    if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double x = red[q][0];
+      for (int w = 1; w < 4; ++w)
+        x = ops.op[q] == RED_SUM ? x + red[q][w] : ops.op[q] == RED_MAX ? fmax(x, red[q][w]) : fmin(x, red[q][w]);
       out[q] = x;
     }
-    __syncthreads();
-  }
 }
 
 // ------------------------------------------------- mixed precision glue --
@@ -347,6 +435,15 @@ k_cast2(const Ti* __restrict__ a, const Ti* __restrict__ b, To* __restrict__ oa,
   for (long long i = gtid(); i < n; i += gstride()) {
     oa[i] = (To)a[i];
     ob[i] = (To)b[i];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_set_f2d(double* __restrict__ db, double* __restrict__ dz, const float* __restrict__ eb,
+          const float* __restrict__ ez, long long n) {
+  for (long long i = gtid(); i < n; i += gstride()) {
+    db[i] = (double)eb[i];
+    dz[i] = (double)ez[i];
   }
 }
 
@@ -494,9 +591,9 @@ void cg_init(const T* hb, const T* hz, T* xb, T* xz, T* rb, T* rz, T* zb, T* zz,
 template <typename T>
 void cg_update(T* xb, T* xz, const T* pb, const T* pz, const T* qb, const T* qz, T* rb, T* rz, T* zb, T* zz,
                const T* s1, const T* s2, const float* c, const double* scal, const int* flags, long long n,
-               double* partial, hipStream_t s) {
+               double* partial, bool first, hipStream_t s) {
   hipLaunchKernelGGL((k_cg_update<T>), VB, xb, xz, pb, pz, qb, qz, rb, rz, zb, zz, s1, s2, c, scal, flags, n,
-                     partial);
+                     partial, first ? 1 : 0);
 }
 template <typename T>
 void cg_pupdate(T* pb, T* pz, const T* zb, const T* zz, const double* scal, const int* flags, long long n,
@@ -505,7 +602,26 @@ void cg_pupdate(T* pb, T* pz, const T* zb, const T* zz, const double* scal, cons
 }
 void fin_cg_init(const double* partial, int nb, double* scal, int* flags, double eta, double atol, int maxit,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_cg_init, dim3(1), dim3(256), 0, s, partial, nb, scal, flags, eta, atol, maxit);
+  hipLaunchKernelGGL(k_fin_cg_init, dim3(1), dim3(256), 0, s, partial, nb, 0, scal, flags, eta, atol, maxit, -1, -1);
+}
+void fin_cg_start(const double* partial, int nb, int stride, double* scal, int* flags, double eta, double atol,
+                  int maxit, int ref_slot, int from_slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_cg_init, dim3(1), dim3(256), 0, s, partial, nb, stride, scal, flags, eta, atol, maxit,
+                     ref_slot, from_slot);
+}
+void fin_two(const double* partial, int nb, int stride, double* scal, int s0, int s1, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_two, dim3(1), dim3(256), 0, s, partial, nb, stride, scal, s0, s1);
+}
+template <typename TC>
+void newton_init(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
+                 const double* xi, double lam, double smu, double* sig1, double* sig2, double* hb_out,
+                 double* hz_out, TC* sig1c, TC* sig2c, const float* c, TC* rb, TC* rz, TC* zb, TC* zz, TC* pb,
+                 TC* pz, long long n, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL((k_newton_init<TC>), VB, beta, z, nu1, nu2, hb, xi, lam, smu, sig1, sig2, hb_out, hz_out,
+                     sig1c, sig2c, c, rb, rz, zb, zz, pb, pz, n, partial);
+}
+void set_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_f2d, VB, db, dz, eb, ez, n);
 }
 void fin_alpha(const double* partial, int nb, double* scal, int* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, s, partial, nb, scal, flags);
@@ -607,8 +723,11 @@ void diag_h(const double* bm_ext, double* out_ext, int n1, int n2, int n3, doubl
   template void cg_init<T>(const T*, const T*, T*, T*, T*, T*, T*, T*, T*, T*, const T*, const T*, const float*, \
                            long long, double*, hipStream_t);                                                   \
   template void cg_update<T>(T*, T*, const T*, const T*, const T*, const T*, T*, T*, T*, T*, const T*,         \
-                             const T*, const float*, const double*, const int*, long long, double*,            \
+                             const T*, const float*, const double*, const int*, long long, double*, bool,      \
                              hipStream_t);                                                                     \
+  template void newton_init<T>(const double*, const double*, const double*, const double*, const double*,     \
+                               const double*, double, double, double*, double*, double*, double*, T*, T*,      \
+                               const float*, T*, T*, T*, T*, T*, T*, long long, double*, hipStream_t);         \
   template void cg_pupdate<T>(T*, T*, const T*, const T*, const double*, const int*, long long, hipStream_t);  \
   template void ipm_newton<T>(const double*, const double*, const double*, const double*, const double*,      \
                               const double*, double, double, double*, double*, double*, double*, T*, T*,       \

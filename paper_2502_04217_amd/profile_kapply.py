@@ -51,13 +51,15 @@ def main(argv=None):
         ms = pr.profile_kapply(p, a.reps)
         by = pass_bytes(shape, w)
         out[name] = {k: {"ms": m, "bytes": b, "GBps": b / (m * 1e-3) / 1e9} for k, m, b in zip(PASS_NAMES, ms, by)}
-    # calibration copy: reads and writes copy_mib MiB once
+    # counter calibration: a fill that writes copy_mib MiB and a sum that
+    # reads them once (FETCH_SIZE / WRITE_SIZE of these two kernels against
+    # the known byte counts give the scale factors)
     nbytes = a.copy_mib * 1024 * 1024
     x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    y = torch.empty_like(x)
-    y.copy_(x)
+    s = x.sum()
     torch.cuda.synchronize()
-    out["copy_bytes"] = nbytes
+    out["calibration_bytes"] = nbytes
+    out["calibration_sum"] = float(s)
     print(json.dumps(out), flush=True)
 
 

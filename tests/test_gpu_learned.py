@@ -90,6 +90,25 @@ def test_features_of_iterate():
     assert np.abs(f - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
+def test_correction_of_iterate_matches_oracle():
+    """c at an iterate: network where L1/(L1 + 4 S1 S2) >= 1e-3, 1 elsewhere."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid16(3)
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.lambda_rule(0.05)
+    p = _params(5)
+    pr.set_pc_params(torch.tensor(p, device="cuda"))
+    for tol in (1e-1, 1e-4):
+        pr.solve(tol=tol)
+        st = [pr.get(v).cpu().numpy() for v in (csipm.BETA, csipm.Z, csipm.NU1, csipm.NU2)]
+        c = pr.pc_correction().cpu().numpy()
+        ref, act = mlp.correction(p.astype(np.float64), *st, dft3.diag_H(w.observed.astype(np.float64)))
+        say("correction active fraction", act.mean())
+        assert np.abs(c - ref).max() <= 1e-5 * np.abs(ref).max()
+        assert np.all(c[~act] == 1.0)
+
+
 def test_learned_solve_same_solution_and_fallback():
     torch = need_gpu()
     from paper_2502_04217_amd import csipm
