@@ -29,7 +29,8 @@ namespace csipm {
 
 namespace {
 
-constexpr int kLdsBytes = 65536;   // LDS budget of one workgroup
+constexpr int kLdsBytes = 65536;     // LDS budget of one workgroup
+constexpr int kLdsBytesAxis1 = 131072;  // axis-1 passes: wider tiles for longer contiguous runs
 
 // ------------------------------------------------------------- radix plan --
 template <int L, int E>
@@ -242,24 +243,25 @@ struct StridedGeom {
 };
 
 template <typename T>
-constexpr int strided_tm(int L) {
-  int tm = kLdsBytes / (L * int(sizeof(cx<T>)));
+constexpr int strided_tm(int L, int axis) {
+  int tm = (axis == 1 ? kLdsBytesAxis1 : kLdsBytes) / (L * int(sizeof(cx<T>)));
   if (tm > 64) tm = 64;
   if (tm < 1) tm = 1;
+  while (tm * (L < 16 ? 1 : L / 16) > 1024) tm >>= 1;   // at most 1024 threads
   return tm;
 }
 template <typename T, int L>
 constexpr int strided_e() { return L < 16 ? L : 16; }
-template <typename T, int L>
-constexpr int strided_threads() { return strided_tm<T>(L) * (L / strided_e<T, L>()); }
+template <typename T, int L, int AX>
+constexpr int strided_threads() { return strided_tm<T>(L, AX) * (L / strided_e<T, L>()); }
 
-template <typename T, int L, int DIR, class Epi>
-__global__ void __launch_bounds__((strided_threads<T, L>()))
+template <typename T, int L, int AX, int DIR, class Epi>
+__global__ void __launch_bounds__((strided_threads<T, L, AX>()))
 k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
          const cx<T>* __restrict__ tw, int m, int m0_from_dst, Epi epi, const int* skip) {
   if (skip && *skip) return;
   constexpr int E = strided_e<T, L>();
-  constexpr int TM = strided_tm<T>(L);
+  constexpr int TM = strided_tm<T>(L, AX);
   constexpr int NT = L / E;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -603,17 +605,19 @@ int grid_for(long long n, int block) {
   return (int)g;
 }
 
-template <typename T, int DIR, class Epi>
+template <typename T, int AX, int DIR, class Epi>
 void launch_axis12_L(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* tw,
                      int m, int m0, Epi epi, const int* skip, hipStream_t s) {
-#define CSIPM_A12(LL)                                                                          \
-  case LL: {                                                                                   \
-    constexpr int TM = strided_tm<T>(LL);                                                      \
-    constexpr int NT = LL / strided_e<T, LL>();                                                \
-    const size_t shm = (size_t)TM * LL * sizeof(cx<T>);                                        \
-    hipLaunchKernelGGL((k_axis12<T, LL, DIR, Epi>), grid, dim3(TM * NT), shm, s, src, dst, geo, \
-                       tw, m, m0, epi, skip);                                                  \
-    break;                                                                                     \
+#define CSIPM_A12(LL)                                                                               \
+  case LL: {                                                                                        \
+    constexpr int TM = strided_tm<T>(LL, AX);                                                       \
+    constexpr int NT = LL / strided_e<T, LL>();                                                     \
+    const size_t shm = (size_t)TM * LL * sizeof(cx<T>);                                             \
+    auto kern = k_axis12<T, LL, AX, DIR, Epi>;                                                      \
+    if (shm > 65536) (void)hipFuncSetAttribute((const void*)kern,                                   \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); \
+    hipLaunchKernelGGL(kern, grid, dim3(TM * NT), shm, s, src, dst, geo, tw, m, m0, epi, skip);      \
+    break;                                                                                          \
   }
   switch (L) {
     CSIPM_A12(4)
@@ -632,19 +636,12 @@ void launch_axis12_L(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom
 }
 
 template <typename T>
-int tm_for(int L) {
-  switch (L) {
-    case 4: return strided_tm<T>(4);
-    case 8: return strided_tm<T>(8);
-    case 16: return strided_tm<T>(16);
-    case 32: return strided_tm<T>(32);
-    case 64: return strided_tm<T>(64);
-    case 128: return strided_tm<T>(128);
-    case 256: return strided_tm<T>(256);
-    case 512: return strided_tm<T>(512);
-    case 1024: return strided_tm<T>(1024);
-  }
-  return 1;
+int tm_for(int L, int axis) {
+  int tm = (axis == 1 ? kLdsBytesAxis1 : kLdsBytes) / (L * int(sizeof(cx<T>)));
+  if (tm > 64) tm = 64;
+  if (tm < 1) tm = 1;
+  while (tm * (L < 16 ? 1 : L / 16) > 1024) tm >>= 1;
+  return tm;
 }
 
 template <typename T>
@@ -669,7 +666,7 @@ StridedGeom<T> geom(const Grid& g, int axis) {
 int axis12_blocks(const Grid& g, int axis, int elem_bytes) {
   const int L = axis == 1 ? g.n1 : g.n2;
   const int batch = axis == 1 ? g.n2 * g.m : g.n1 * g.m;
-  const int tm = elem_bytes == 16 ? tm_for<double>(L) : tm_for<float>(L);
+  const int tm = elem_bytes == 16 ? tm_for<double>(L, axis) : tm_for<float>(L, axis);
   return (batch + tm - 1) / tm;
 }
 
@@ -691,15 +688,22 @@ void launch_axis12(const Grid& g, int axis, int dir, const T* src, T* dst, const
   dim3 grid(axis12_blocks(g, axis, (int)sizeof(cx<T>)));
   const cx<T>* cs = reinterpret_cast<const cx<T>*>(src);
   cx<T>* cd = reinterpret_cast<cx<T>*>(dst);
-  if (dir > 0) {
-    launch_axis12_L<T, +1>(L, grid, cs, cd, geo, twp, g.m, m0_from_dst ? 1 : 0, EpiNone{}, skip, s);
-  } else if (epi == EPI_K) {
-    launch_axis12_L<T, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiK<T>{ea->k, ea->partial, ea->pstride}, skip, s);
-  } else if (epi == EPI_R) {
-    if constexpr (std::is_same<T, double>::value)
-      launch_axis12_L<T, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiR{ea->r, ea->partial, ea->pstride}, skip, s);
+  if (axis == 1) {
+    if (dir > 0) {
+      launch_axis12_L<T, 1, +1>(L, grid, cs, cd, geo, twp, g.m, m0_from_dst ? 1 : 0, EpiNone{}, skip, s);
+    } else if (epi == EPI_K) {
+      launch_axis12_L<T, 1, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiK<T>{ea->k, ea->partial, ea->pstride}, skip, s);
+    } else if (epi == EPI_R) {
+      if constexpr (std::is_same<T, double>::value)
+        launch_axis12_L<T, 1, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiR{ea->r, ea->partial, ea->pstride}, skip, s);
+    } else {
+      launch_axis12_L<T, 1, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiNone{}, skip, s);
+    }
   } else {
-    launch_axis12_L<T, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiNone{}, skip, s);
+    if (dir > 0)
+      launch_axis12_L<T, 2, +1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiNone{}, skip, s);
+    else
+      launch_axis12_L<T, 2, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiNone{}, skip, s);
   }
 }
 

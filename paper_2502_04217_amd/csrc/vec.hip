@@ -71,6 +71,14 @@ __device__ __forceinline__ void pinv1(T rb, T rz, T s1, T s2, double c, T& zb, T
 __device__ __forceinline__ long long gtid() { return blockIdx.x * (long long)blockDim.x + threadIdx.x; }
 __device__ __forceinline__ long long gstride() { return (long long)gridDim.x * blockDim.x; }
 
+// Elementwise loops visit pairs of neighbouring elements (n is even) from
+// pointers known to be 2-element aligned, so each lane moves 16 bytes per
+// FP64 array per access.
+#define CSIPM_PAIRS(n)                                                      \
+  for (long long j_ = gtid(); j_ < (n) / 2; j_ += gstride())                \
+    _Pragma("unroll") for (long long i = 2 * j_; i < 2 * j_ + 2; ++i)
+#define CSIPM_ALIGN(p) p = (decltype(p))__builtin_assume_aligned(p, 2 * sizeof(*(p)))
+
 // ------------------------------------------------------------------- PCG --
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -107,9 +115,22 @@ k_cg_update(T* __restrict__ xb, T* __restrict__ xz, const T* __restrict__ pb, co
             T* __restrict__ zb, T* __restrict__ zz, const T* __restrict__ s1, const T* __restrict__ s2,
             const float* __restrict__ c, const double* __restrict__ scal, const int* __restrict__ flags,
             long long n, double* partial, int first) {
+  CSIPM_ALIGN(xb);
+  CSIPM_ALIGN(xz);
+  CSIPM_ALIGN(pb);
+  CSIPM_ALIGN(pz);
+  CSIPM_ALIGN(qb);
+  CSIPM_ALIGN(qz);
+  CSIPM_ALIGN(rb);
+  CSIPM_ALIGN(rz);
+  CSIPM_ALIGN(zb);
+  CSIPM_ALIGN(zz);
+  CSIPM_ALIGN(s1);
+  CSIPM_ALIGN(s2);
+
   if (flags[F_DONE]) {
     if (first)
-      for (long long i = gtid(); i < n; i += gstride()) {
+      CSIPM_PAIRS(n) {
         xb[i] = T(0);
         xz[i] = T(0);
       }
@@ -117,23 +138,39 @@ k_cg_update(T* __restrict__ xb, T* __restrict__ xz, const T* __restrict__ pb, co
   }
   const T a = (T)scal[S_ALPHA];
   double acc = 0.0;
-  for (long long i = gtid(); i < n; i += gstride()) {
+  using V = cx<T>;
+  const V *PB = (const V*)pb, *PZ = (const V*)pz, *QB = (const V*)qb, *QZ = (const V*)qz, *S1 = (const V*)s1,
+          *S2 = (const V*)s2;
+  V *XB = (V*)xb, *XZ = (V*)xz, *RB = (V*)rb, *RZ = (V*)rz, *ZB = (V*)zb, *ZZ = (V*)zz;
+  const float2* C2 = (const float2*)c;
+  for (long long j = gtid(); j < n / 2; j += gstride()) {
+    const V p1 = PB[j], p2 = PZ[j];
+    V x1, x2;
     if (first) {
-      xb[i] = a * pb[i];
-      xz[i] = a * pz[i];
+      x1 = {a * p1.re, a * p1.im};
+      x2 = {a * p2.re, a * p2.im};
     } else {
-      xb[i] += a * pb[i];
-      xz[i] += a * pz[i];
+      x1 = XB[j];
+      x2 = XZ[j];
+      x1 = {x1.re + a * p1.re, x1.im + a * p1.im};
+      x2 = {x2.re + a * p2.re, x2.im + a * p2.im};
     }
-    const T b = rb[i] - a * qb[i];
-    const T z = rz[i] - a * qz[i];
-    rb[i] = b;
-    rz[i] = z;
-    T ub, uz;
-    pinv1<T>(b, z, s1[i], s2[i], c ? (double)c[i] : 1.0, ub, uz);
-    zb[i] = ub;
-    zz[i] = uz;
-    acc += (double)b * (double)ub + (double)z * (double)uz;
+    XB[j] = x1;
+    XZ[j] = x2;
+    const V q1 = QB[j], q2 = QZ[j], r1 = RB[j], r2 = RZ[j];
+    const V b = {r1.re - a * q1.re, r1.im - a * q1.im};
+    const V z = {r2.re - a * q2.re, r2.im - a * q2.im};
+    RB[j] = b;
+    RZ[j] = z;
+    const V g1 = S1[j], g2 = S2[j];
+    const float2 cc = C2 ? C2[j] : make_float2(1.0f, 1.0f);
+    V ub, uz;
+    pinv1<T>(b.re, z.re, g1.re, g2.re, (double)cc.x, ub.re, uz.re);
+    pinv1<T>(b.im, z.im, g1.im, g2.im, (double)cc.y, ub.im, uz.im);
+    ZB[j] = ub;
+    ZZ[j] = uz;
+    acc += (double)b.re * (double)ub.re + (double)z.re * (double)uz.re + (double)b.im * (double)ub.im +
+           (double)z.im * (double)uz.im;
   }
   const int op = RED_SUM;
   block_reduce_store<1>(&acc, &op, partial, 0);
@@ -143,9 +180,14 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_cg_pupdate(T* __restrict__ pb, T* __restrict__ pz, const T* __restrict__ zb, const T* __restrict__ zz,
              const double* __restrict__ scal, const int* __restrict__ flags, long long n) {
+  CSIPM_ALIGN(pb);
+  CSIPM_ALIGN(pz);
+  CSIPM_ALIGN(zb);
+  CSIPM_ALIGN(zz);
+
   if (flags[F_DONE]) return;
   const T be = (T)scal[S_BETA];
-  for (long long i = gtid(); i < n; i += gstride()) {
+  CSIPM_PAIRS(n) {
     pb[i] = zb[i] + be * pb[i];
     pz[i] = zz[i] + be * pz[i];
   }
@@ -243,8 +285,15 @@ __global__ void __launch_bounds__(256)
 k_ipm_resid(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
             const double* __restrict__ nu2, const double* __restrict__ hb, const double* __restrict__ xi,
             double lam, long long n, double* partial, int stride) {
+  CSIPM_ALIGN(beta);
+  CSIPM_ALIGN(z);
+  CSIPM_ALIGN(nu1);
+  CSIPM_ALIGN(nu2);
+  CSIPM_ALIGN(hb);
+  CSIPM_ALIGN(xi);
+
   double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0};
-  for (long long i = gtid(); i < n; i += gstride()) {
+  CSIPM_PAIRS(n) {
     const double b = beta[i], zz = z[i], a1 = nu1[i], a2 = nu2[i];
     const double s1 = zz + b, s2 = zz - b;
     const double fb = hb[i] - xi[i] - a1 + a2;
@@ -301,41 +350,73 @@ k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, con
               TC* __restrict__ sig2c, const float* __restrict__ c, TC* __restrict__ rb, TC* __restrict__ rz,
               TC* __restrict__ zb, TC* __restrict__ zz, TC* __restrict__ pb, TC* __restrict__ pz, long long n,
               double* partial) {
+  CSIPM_ALIGN(beta);
+  CSIPM_ALIGN(z);
+  CSIPM_ALIGN(nu1);
+  CSIPM_ALIGN(nu2);
+  CSIPM_ALIGN(hb);
+  CSIPM_ALIGN(xi);
+  CSIPM_ALIGN(sig1);
+  CSIPM_ALIGN(sig2);
+  CSIPM_ALIGN(rb);
+  CSIPM_ALIGN(rz);
+  CSIPM_ALIGN(zb);
+  CSIPM_ALIGN(zz);
+  CSIPM_ALIGN(pb);
+  CSIPM_ALIGN(pz);
+
   double acc[2] = {0.0, 0.0};
-  for (long long i = gtid(); i < n; i += gstride()) {
-    const double b = beta[i], zv = z[i];
-    const double s1 = zv + b, s2 = zv - b;
-    const double i1 = 1.0 / s1, i2 = 1.0 / s2;
-    const double g1 = nu1[i] * i1, g2 = nu2[i] * i2;
-    const double h1 = -(hb[i] - xi[i]) + smu * (i1 - i2);
-    const double h2 = -lam + smu * (i1 + i2);
-    sig1[i] = g1;
-    sig2[i] = g2;
+  using D2 = cx<double>;
+  using V = cx<TC>;
+  const D2 *BE = (const D2*)beta, *ZV = (const D2*)z, *N1 = (const D2*)nu1, *N2 = (const D2*)nu2,
+           *HB = (const D2*)hb, *XI = (const D2*)xi;
+  const float2* C2 = (const float2*)c;
+  for (long long j = gtid(); j < n / 2; j += gstride()) {
+    const D2 b2 = BE[j], z2 = ZV[j], a1 = N1[j], a2 = N2[j], hh = HB[j], x2 = XI[j];
+    const float2 cc = C2 ? C2[j] : make_float2(1.0f, 1.0f);
+    const double bb[2] = {b2.re, b2.im}, zz2[2] = {z2.re, z2.im}, n1[2] = {a1.re, a1.im},
+                 n2[2] = {a2.re, a2.im}, hv[2] = {hh.re, hh.im}, xv[2] = {x2.re, x2.im},
+                 cv[2] = {(double)cc.x, (double)cc.y};
+    double g1o[2], g2o[2], h1o[2], h2o[2];
+    TC r1o[2], r2o[2], w1o[2], w2o[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const double s1 = zz2[k] + bb[k], s2 = zz2[k] - bb[k];
+      const double i1 = 1.0 / s1, i2 = 1.0 / s2;
+      const double g1 = n1[k] * i1, g2 = n2[k] * i2;
+      const double h1 = -(hv[k] - xv[k]) + smu * (i1 - i2);
+      const double h2 = -lam + smu * (i1 + i2);
+      double u1, u2;
+      pinv_block<double>(h1, h2, g1, g2, cv[k], u1, u2);
+      acc[1] += h1 * u1 + h2 * u2;
+      const TC r1 = (TC)h1, r2 = (TC)h2;
+      TC w1, w2;
+      if constexpr (std::is_same<TC, double>::value) {
+        w1 = u1;
+        w2 = u2;
+      } else {
+        pinv_block<TC>(r1, r2, (TC)g1, (TC)g2, cv[k], w1, w2);
+      }
+      acc[0] += (double)r1 * (double)w1 + (double)r2 * (double)w2;
+      g1o[k] = g1; g2o[k] = g2; h1o[k] = h1; h2o[k] = h2;
+      r1o[k] = r1; r2o[k] = r2; w1o[k] = w1; w2o[k] = w2;
+    }
+    ((D2*)sig1)[j] = {g1o[0], g1o[1]};
+    ((D2*)sig2)[j] = {g2o[0], g2o[1]};
     if (hb_out) {
-      hb_out[i] = h1;
-      hz_out[i] = h2;
+      ((D2*)hb_out)[j] = {h1o[0], h1o[1]};
+      ((D2*)hz_out)[j] = {h2o[0], h2o[1]};
     }
-    const double cc = c ? (double)c[i] : 1.0;
-    double u1, u2;
-    pinv_block<double>(h1, h2, g1, g2, cc, u1, u2);
-    acc[1] += h1 * u1 + h2 * u2;
-    const TC r1 = (TC)h1, r2 = (TC)h2;
-    TC w1, w2;
-    if constexpr (std::is_same<TC, double>::value) {
-      w1 = u1;
-      w2 = u2;
-    } else {
-      pinv_block<TC>(r1, r2, (TC)g1, (TC)g2, cc, w1, w2);
-      sig1c[i] = (TC)g1;
-      sig2c[i] = (TC)g2;
+    if constexpr (!std::is_same<TC, double>::value) {
+      ((V*)sig1c)[j] = {(TC)g1o[0], (TC)g1o[1]};
+      ((V*)sig2c)[j] = {(TC)g2o[0], (TC)g2o[1]};
     }
-    rb[i] = r1;
-    rz[i] = r2;
-    zb[i] = w1;
-    zz[i] = w2;
-    pb[i] = w1;
-    pz[i] = w2;
-    acc[0] += (double)r1 * (double)w1 + (double)r2 * (double)w2;
+    ((V*)rb)[j] = {r1o[0], r1o[1]};
+    ((V*)rz)[j] = {r2o[0], r2o[1]};
+    ((V*)zb)[j] = {w1o[0], w1o[1]};
+    ((V*)zz)[j] = {w2o[0], w2o[1]};
+    ((V*)pb)[j] = {w1o[0], w1o[1]};
+    ((V*)pz)[j] = {w2o[0], w2o[1]};
   }
   const int ops[2] = {RED_SUM, RED_SUM};
   block_reduce_store<2>(acc, ops, partial, VEC_MAX_BLOCKS);
@@ -348,17 +429,33 @@ k_ipm_ratio(const double* __restrict__ beta, const double* __restrict__ z, const
             const double* __restrict__ nu2, const double* __restrict__ sig1, const double* __restrict__ sig2,
             const double* __restrict__ db, const double* __restrict__ dz, double smu, long long n,
             double* partial) {
+  CSIPM_ALIGN(beta);
+  CSIPM_ALIGN(z);
+  CSIPM_ALIGN(nu1);
+  CSIPM_ALIGN(nu2);
+  CSIPM_ALIGN(sig1);
+  CSIPM_ALIGN(sig2);
+  CSIPM_ALIGN(db);
+  CSIPM_ALIGN(dz);
+
   double amax = INFINITY;
-  for (long long i = gtid(); i < n; i += gstride()) {
-    const double b = beta[i], zz = z[i];
-    const double s1 = zz + b, s2 = zz - b;
-    const double ds1 = db[i] + dz[i], ds2 = dz[i] - db[i];
-    const double dn1 = smu / s1 - nu1[i] - sig1[i] * ds1;
-    const double dn2 = smu / s2 - nu2[i] - sig2[i] * ds2;
-    if (ds1 < 0.0) amax = fmin(amax, -s1 / ds1);
-    if (ds2 < 0.0) amax = fmin(amax, -s2 / ds2);
-    if (dn1 < 0.0) amax = fmin(amax, -nu1[i] / dn1);
-    if (dn2 < 0.0) amax = fmin(amax, -nu2[i] / dn2);
+  using D2 = cx<double>;
+  for (long long j = gtid(); j < n / 2; j += gstride()) {
+    const D2 b2 = ((const D2*)beta)[j], z2 = ((const D2*)z)[j], a1 = ((const D2*)nu1)[j], a2 = ((const D2*)nu2)[j],
+             g1 = ((const D2*)sig1)[j], g2 = ((const D2*)sig2)[j], d1 = ((const D2*)db)[j], d2 = ((const D2*)dz)[j];
+    const double bb[2] = {b2.re, b2.im}, zv[2] = {z2.re, z2.im}, n1[2] = {a1.re, a1.im}, n2[2] = {a2.re, a2.im},
+                 s1v[2] = {g1.re, g1.im}, s2v[2] = {g2.re, g2.im}, dbv[2] = {d1.re, d1.im}, dzv[2] = {d2.re, d2.im};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const double s1 = zv[k] + bb[k], s2 = zv[k] - bb[k];
+      const double ds1 = dbv[k] + dzv[k], ds2 = dzv[k] - dbv[k];
+      const double dn1 = smu / s1 - n1[k] - s1v[k] * ds1;
+      const double dn2 = smu / s2 - n2[k] - s2v[k] * ds2;
+      if (ds1 < 0.0) amax = fmin(amax, -s1 / ds1);
+      if (ds2 < 0.0) amax = fmin(amax, -s2 / ds2);
+      if (dn1 < 0.0) amax = fmin(amax, -n1[k] / dn1);
+      if (dn2 < 0.0) amax = fmin(amax, -n2[k] / dn2);
+    }
   }
   const int op = RED_MIN;
   block_reduce_store<1>(&amax, &op, partial, 0);
@@ -383,8 +480,17 @@ __global__ void __launch_bounds__(256)
 k_ipm_update(double* __restrict__ beta, double* __restrict__ z, double* __restrict__ nu1, double* __restrict__ nu2,
              const double* __restrict__ sig1, const double* __restrict__ sig2, const double* __restrict__ db,
              const double* __restrict__ dz, double smu, const double* __restrict__ scal, long long n) {
+  CSIPM_ALIGN(beta);
+  CSIPM_ALIGN(z);
+  CSIPM_ALIGN(nu1);
+  CSIPM_ALIGN(nu2);
+  CSIPM_ALIGN(sig1);
+  CSIPM_ALIGN(sig2);
+  CSIPM_ALIGN(db);
+  CSIPM_ALIGN(dz);
+
   const double a = scal[S_ALPHA_IPM];
-  for (long long i = gtid(); i < n; i += gstride()) {
+  CSIPM_PAIRS(n) {
     const double b = beta[i], zz = z[i];
     const double s1 = zz + b, s2 = zz - b;
     const double ds1 = db[i] + dz[i], ds2 = dz[i] - db[i];
@@ -441,7 +547,12 @@ k_cast2(const Ti* __restrict__ a, const Ti* __restrict__ b, To* __restrict__ oa,
 __global__ void __launch_bounds__(256)
 k_set_f2d(double* __restrict__ db, double* __restrict__ dz, const float* __restrict__ eb,
           const float* __restrict__ ez, long long n) {
-  for (long long i = gtid(); i < n; i += gstride()) {
+  CSIPM_ALIGN(db);
+  CSIPM_ALIGN(dz);
+  CSIPM_ALIGN(eb);
+  CSIPM_ALIGN(ez);
+
+  CSIPM_PAIRS(n) {
     db[i] = (double)eb[i];
     dz[i] = (double)ez[i];
   }
@@ -450,7 +561,12 @@ k_set_f2d(double* __restrict__ db, double* __restrict__ dz, const float* __restr
 __global__ void __launch_bounds__(256)
 k_add_f2d(double* __restrict__ db, double* __restrict__ dz, const float* __restrict__ eb,
           const float* __restrict__ ez, long long n) {
-  for (long long i = gtid(); i < n; i += gstride()) {
+  CSIPM_ALIGN(db);
+  CSIPM_ALIGN(dz);
+  CSIPM_ALIGN(eb);
+  CSIPM_ALIGN(ez);
+
+  CSIPM_PAIRS(n) {
     db[i] += (double)eb[i];
     dz[i] += (double)ez[i];
   }

@@ -60,6 +60,16 @@ def main(argv=None):
     torch.cuda.synchronize()
     out["calibration_bytes"] = nbytes
     out["calibration_sum"] = float(s)
+    # achievable device-to-device copy bandwidth (read + write), for context
+    y = torch.empty_like(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    y.copy_(x)
+    e0.record()
+    for _ in range(5):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    out["copy_GBps"] = 2 * nbytes * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     print(json.dumps(out), flush=True)
 
 

@@ -50,12 +50,50 @@ def summarize(db: str, top: int = 25, min_us: float = 8.0):
     return out, counters, total / 1e3
 
 
+def calibrated_traffic(fetch_db: str, write_db: str, calib_bytes: int):
+    """Per-kernel HBM bytes per dispatch from a FETCH_SIZE run and a
+    WRITE_SIZE run (KiB per dispatch), each scaled by what the counter reads
+    for a kernel of known traffic in the same run: the reduction (torch sum,
+    reads calib_bytes) for FETCH_SIZE and the fill (writes calib_bytes) for
+    WRITE_SIZE.  Returns ({kernel: (fetch_bytes, write_bytes)}, factors)."""
+    def per_dispatch(db, counter):
+        c = sqlite3.connect(db)
+        rows = c.execute("select kernel_name, value from counters_collection where counter_name = ?",
+                         (counter,)).fetchall()
+        d = collections.defaultdict(list)
+        for k, v in rows:
+            d[k].append(v)
+        return d
+    f = per_dispatch(fetch_db, "FETCH_SIZE")
+    w = per_dispatch(write_db, "WRITE_SIZE")
+    red = [max(v) for k, v in f.items() if "reduce_kernel" in k]
+    fill = [max(v) for k, v in w.items() if "FillFunctor" in k]
+    ff = calib_bytes / 1024.0 / max(red) if red else 1.0
+    fw = calib_bytes / 1024.0 / max(fill) if fill else 1.0
+    out = {}
+    for k in set(f) | set(w):
+        fe = sum(f.get(k, [0])) / max(1, len(f.get(k, [1]))) * 1024.0 * ff
+        wr = sum(w.get(k, [0])) / max(1, len(w.get(k, [1]))) * 1024.0 * fw
+        out[short(k)] = (fe, wr)
+    return out, (ff, fw)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("db")
     ap.add_argument("--top", type=int, default=25)
     ap.add_argument("--min-us", type=float, default=8.0)
+    ap.add_argument("--fetch-db")
+    ap.add_argument("--write-db")
+    ap.add_argument("--calib-bytes", type=int, default=1 << 30)
     a = ap.parse_args(argv)
+    if a.fetch_db and a.write_db:
+        tr, (ff, fw) = calibrated_traffic(a.fetch_db, a.write_db, a.calib_bytes)
+        print(f"# calibrated HBM traffic per dispatch (FETCH_SIZE x {ff:.4f}, WRITE_SIZE x {fw:.4f})")
+        for k in sorted(tr):
+            fe, wr = tr[k]
+            if fe + wr > 1e6:
+                print(f"{k[:60]:60s} read {fe / 1e6:10.2f} MB  write {wr / 1e6:10.2f} MB")
     out, counters, total_us = summarize(a.db, a.top, a.min_us)
     print(f"# kernel time total {total_us:.1f} us; working = dispatches >= {a.min_us} us")
     print(f"{'kernel':60s} {'calls':>6s} {'total_us':>11s} {'avg_us':>9s} {'pct':>6s} {'work':>5s} {'work_avg_us':>11s}")
