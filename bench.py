@@ -12,9 +12,16 @@ resident in HBM and the problem created (xi, diag H) outside the timed region.
 
 The chosen form (FP32 Krylov with FP64 refinement, learned preconditioner
 correction when trained parameters are present) gives `value`; the plain FP64
-form is timed alongside.  `roofline` covers the K-apply kernel that dominates
-the step; `cpu_baseline` times the CPU oracle on one K-apply of the same
-problem and scales it by the number of operator applies of the FP64 solve.
+form is timed alongside.  One more solve of each form runs with per-kernel
+event timing (csipm_timing); `roofline` covers the HBM-bound kernel with the
+largest share of the chosen form's solve time (`dominant` says whether it is
+also the largest overall), with its algorithmic bytes per launch over its
+average launch time.  `traffic` is the calibrated rocprofv3 counter total of
+that kernel from a committed profile record taken on the current kernel
+sources (null otherwise).  `kapply` times the seven K-apply kernels alone
+(the matvec rate).  `cpu_baseline` times the CPU oracle on one K-apply of the
+same problem and scales it by the number of operator applies of the FP64
+solve.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--grid 256]
 """
@@ -47,6 +54,94 @@ def pass_bytes(shape, w):
     n = n1 * n2 * n3
     plane = 2 * n1 * n2
     return [2 * plane * w, 2 * n * w, 2 * n * w, 2 * n * w + n // 8, 2 * n * w, 7 * n * w, 7 * plane * w]
+
+
+def kernel_bytes(name, shape, learned):
+    """Algorithmic HBM bytes of one working launch of a timed kernel (names
+    of csipm_timing_report), or None for the small finalize kernels and the
+    correction inference, which is bound by arithmetic, not bytes.  FFT
+    passes move the n-real work array once each way; the epilogues add the
+    vectors they read and write; elementwise kernels count each FP64 array
+    as 8n bytes and each FP32 array as 4n."""
+    n1, n2, n3 = shape
+    n = n1 * n2 * n3
+    plane = 2 * n1 * n2
+    base, _, prec = name.partition(".")
+    w = 8 if prec == "f64" else 4
+    c = 4 if learned else 0   # FP32 correction read by P_c^{-1}
+    table = {
+        "premix": 2 * plane * w,
+        "axis1_inv": 2 * n * w, "axis2_inv": 2 * n * w, "axis2_fwd": 2 * n * w, "axis1_fwd": 2 * n * w,
+        "axis3": 2 * n * w + n // 8,
+        "postmix": 2 * plane * w,
+        "axis1_fwd_K": 7 * n * w,
+        "postmix_K": 7 * plane * w,
+        # T, d (2), Sigma (2), h (2) in FP64, c; H d_beta out
+        "axis1_fwd_R": (64 + c) * n,
+        "postmix_R": (64 + c) * plane,
+        # h, d, Sigma (2 each), H d_beta in FP64, c; r32, z32, p32 (2 each, FP32) out
+        "ref_restart+fin": (56 + c + 24) * n,
+        # x, p, q, r, Sigma (2 each) in, x, r, z out (the first update of a solve skips reading x)
+        "cg_update": 16 * n * w + c * n,
+        "cg_pupdate": 6 * n * w,
+        # beta, z, nu1, nu2, H beta, xi in; Sigma, PCG start (and h, FP32 Sigma) out
+        "newton_init": (112 + c) * n,
+        "newton_init_noh": (96 + c) * n,   # FP32 system taken without refinement: h not stored
+        "ipm_ratio+fin": 48 * n,
+        "ipm_advance+fin": 112 * n,
+        "ipm_resid+fin": 48 * n,
+        "set_f2d": 24 * n,
+        "add_f2d": 40 * n,
+        "log_l1+fin": 32 * n,
+    }
+    return table.get(base)
+
+
+def kernel_breakdown(pr, opts, shape, learned, info):
+    """One extra solve with per-kernel event timing; returns the per-kernel
+    records (ms per solve) with algorithmic bytes attached."""
+    pr.timing(True)
+    pr.solve(**opts)
+    rep = pr.timing_report(8.0)
+    pr.timing(False)
+    # launches of cg_update that start a PCG solve read no x: 2nw fewer bytes
+    starts = int(info["refine_steps_total"]) if opts["precision"] == 1 else int(info["ipm_iters"])
+    out = []
+    for r in rep:
+        b = kernel_bytes(r["name"], shape, learned)
+        if b is not None and r["name"].startswith("cg_update"):
+            n = shape[0] * shape[1] * shape[2]
+            w = 8 if r["name"].endswith("f64") else 4
+            tot = b * r["working_calls"] - 2 * n * w * min(starts, r["working_calls"])
+            b = tot / max(1, r["working_calls"])
+        r["bytes_per_launch"] = b
+        out.append(r)
+    out.sort(key=lambda r: -r["total_ms"])
+    return out
+
+
+PROFILE_RECORDS = os.path.join(ROOT, "profiles")
+
+
+def traffic_record(kernel, grid):
+    """Calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per launch of
+    `kernel` at `grid`^3 from a committed profile summary, when it was taken
+    on the current kernel sources; None otherwise."""
+    if not os.path.isdir(PROFILE_RECORDS):
+        return None
+    from paper_2502_04217_amd.build import source_digest
+    digest = source_digest()
+    for f in sorted(os.listdir(PROFILE_RECORDS)):
+        if not f.endswith((".md", ".txt")):
+            continue
+        with open(os.path.join(PROFILE_RECORDS, f)) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record: "):
+                    continue
+                rec = json.loads(line[len("traffic-record: "):])
+                if rec.get("kernel") == kernel and rec.get("grid") == grid and rec.get("source_sha256") == digest:
+                    return rec
+    return None
 
 
 def load_params(torch):
@@ -154,17 +249,26 @@ def main():
     print(f"[bench] plain FP64: {plain_s * 1e3:.1f} ms/solve {infos64[-1]}", file=sys.stderr, flush=True)
     rel_diff = float((beta_chosen - beta64).norm() / beta64.norm())
 
+    # per-kernel event timing of one more solve of each form; the dominant
+    # kernel of the chosen form is the roofline kernel
+    n = int(np.prod(w.shape))
+    kern = kernel_breakdown(pr, chosen, w.shape, learned, infos[-1])
+    kern64 = kernel_breakdown(pr, plain, w.shape, False, infos64[-1])
+    top = next(r for r in kern if r["bytes_per_launch"] is not None)
+    dominant_is_top = top is kern[0]
+
     # per-kernel timing of the K-apply at the last Newton system's barrier diagonals
     prof = {}
     for name, prec, wsz in (("fp32", csipm.FP32, 4), ("fp64", csipm.FP64, 8)):
         ms = pr.profile_kapply(prec, args.profile_reps)
         by = pass_bytes(w.shape, wsz)
         prof[name] = {"ms": ms, "bytes": by}
-    dom = "fp32" if chosen["precision"] == csipm.FP32 else "fp64"
-    ms = prof[dom]["ms"]
-    k = int(np.argmax(ms))
-    achieved = prof[dom]["bytes"][k] / (ms[k] * 1e-3) / 1e9
-    n = int(np.prod(w.shape))
+    k_bytes = top["bytes_per_launch"] * top["working_calls"]
+    achieved = k_bytes / (top["total_ms"] * 1e-3) / 1e9
+    rec = traffic_record(top["name"], w.shape[0])
+    traffic = None
+    if rec is not None:
+        traffic = rec["read_bytes"] + rec["write_bytes"]
     kapply = {}
     for name, wsz in (("fp32", 4), ("fp64", 8)):
         t = sum(prof[name]["ms"]) * 1e-3
@@ -204,9 +308,13 @@ def main():
                        "cg_iters_total": infos64[-1]["cg_iters_total"], "rel_kkt": infos64[-1]["rel_kkt"]},
         "setup_seconds": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBPS, "traffic": None,
-                     "kernel": f"{PASS_NAMES[k]} ({dom})", "kernel_ms": ms[k],
-                     "bytes_per_launch": prof[dom]["bytes"][k]},
+                     "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic,
+                     "kernel": top["name"], "dominant": dominant_is_top,
+                     "launches": top["calls"], "working_launches": top["working_calls"],
+                     "avg_ms": top["total_ms"] / max(1, top["calls"]),
+                     "bytes_per_launch": top["bytes_per_launch"]},
+        "kernels_ms_per_solve": {r["name"]: round(r["total_ms"], 3) for r in kern[:10]},
+        "kernels_ms_per_solve_fp64": {r["name"]: round(r["total_ms"], 3) for r in kern64[:8]},
         "kapply": kapply,
         "cpu_baseline": cpu,
     }

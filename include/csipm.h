@@ -83,6 +83,14 @@ typedef struct {
   double refine_inner_rtol; /* FP32: tightest relative tolerance asked of one inner
                                PCG solve (default 1e-5); each inner solve aims at
                                half the remaining reduction, at most 1e-2     */
+  double refine_trust; /* FP32: Newton systems whose tolerance min(cg_rtol,
+                          0.1 rel_kkt) is at least this (default 1e-4) take
+                          the FP32 solution (inner tolerance half of it)
+                          without an FP64 residual pass; the residual of the
+                          iterate then carries FP32-level error until it is
+                          recomputed in FP64, which happens before every
+                          stopping test and before the first system below
+                          the threshold.  0 = always refine.               */
 } csipm_options;
 
 typedef struct {
@@ -235,6 +243,31 @@ csipm_status csipm_pc_correction(csipm_ctx* ctx, double* d_c);
  * axis-1 forward with the K epilogue, postmix.  Synchronises. */
 #define CSIPM_KAPPLY_PASSES 7
 csipm_status csipm_profile_kapply(csipm_ctx* ctx, int precision, int reps, double* ms_out);
+
+/* Instrumentation: per-kernel timing of everything the context launches.
+ * csipm_timing(ctx, 1) clears earlier records and starts recording a HIP
+ * event pair around each kernel launch (launchers that also queue a
+ * one-workgroup finalize kernel are timed as one record, named "...+fin");
+ * csipm_timing(ctx, 0) stops.  csipm_timing_report synchronises the stream
+ * and aggregates the records by kernel name: calls, total duration, and the
+ * calls (and their duration) that took at least min_us microseconds, which
+ * separates real work from the launches of a queued Krylov batch that
+ * return at once after convergence.  Up to max_records entries are written
+ * to out (host memory); *n_records receives the number of distinct names.
+ * At most 1,000,000 launches are recorded; later ones are counted in
+ * `dropped` of the first entry.  Recording adds host work per launch and is
+ * meant for measurement runs only. */
+typedef struct {
+  char name[48];
+  int calls;
+  int working_calls;
+  double total_ms;
+  double working_ms;
+  long long dropped;
+} csipm_kernel_time;
+csipm_status csipm_timing(csipm_ctx* ctx, int enable);
+csipm_status csipm_timing_report(csipm_ctx* ctx, double min_us, csipm_kernel_time* out, int max_records,
+                                 int* n_records);
 
 csipm_status csipm_destroy(csipm_ctx* ctx);
 const char* csipm_status_string(int status);

@@ -22,6 +22,19 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-function"]
 
 
+def source_digest() -> str:
+    """SHA-256 over the kernel sources (csrc/*.hip, csrc/*.h) and the public
+    header: identifies the code a profile or counter record was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    files = [os.path.join(SRC, f) for f in sorted(os.listdir(SRC)) if f.endswith((".hip", ".h"))]
+    files.append(os.path.join(os.path.dirname(HERE), "include", "csipm.h"))
+    for path in files:
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):

@@ -33,7 +33,8 @@ class CsipmError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("cg_max", C.c_int), ("cg_rtol", C.c_double),
                 ("cg_atol", C.c_double), ("sigma", C.c_double), ("tau", C.c_double), ("precision", C.c_int),
-                ("pc", C.c_int), ("refine_max", C.c_int), ("refine_inner_rtol", C.c_double)]
+                ("pc", C.c_int), ("refine_max", C.c_int), ("refine_inner_rtol", C.c_double),
+                ("refine_trust", C.c_double)]
 
 
 class Info(C.Structure):
@@ -47,6 +48,11 @@ class Info(C.Structure):
         d = {f: getattr(self, f) for f, _ in self._fields_}
         d["lambda"] = d.pop("lambda_")
         return d
+
+
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("calls", C.c_int), ("working_calls", C.c_int), ("total_ms", C.c_double),
+                ("working_ms", C.c_double), ("dropped", C.c_longlong)]
 
 
 class IterLog(C.Structure):
@@ -86,6 +92,8 @@ def load_library(path: str = LIB_PATH):
         "csipm_features": (I, [P, P]),
         "csipm_pc_correction": (I, [P, P]),
         "csipm_profile_kapply": (I, [P, I, I, C.POINTER(D)]),
+        "csipm_timing": (I, [P, I]),
+        "csipm_timing_report": (I, [P, D, C.POINTER(KernelTime), I, C.POINTER(I)]),
         "csipm_destroy": (I, [P]),
         "csipm_status_string": (C.c_char_p, [I]),
         "csipm_last_error": (C.c_char_p, [P]),
@@ -274,6 +282,20 @@ class Problem:
         out = (C.c_double * 7)()
         self._check(lib().csipm_profile_kapply(self._ctx, precision, reps, out), "profile_kapply")
         return list(out)
+
+    def timing(self, enable: bool):
+        """Start (clearing earlier records) or stop per-kernel event timing."""
+        self._check(lib().csipm_timing(self._ctx, 1 if enable else 0), "timing")
+
+    def timing_report(self, min_us: float = 8.0) -> list:
+        """Per-kernel aggregates of the recorded launches: name, calls,
+        working_calls (those lasting >= min_us), total_ms, working_ms."""
+        n = C.c_int(0)
+        self._check(lib().csipm_timing_report(self._ctx, min_us, None, 0, C.byref(n)), "timing_report")
+        buf = (KernelTime * max(1, n.value))()
+        self._check(lib().csipm_timing_report(self._ctx, min_us, buf, n.value, C.byref(n)), "timing_report")
+        return [{"name": r.name.decode(), "calls": r.calls, "working_calls": r.working_calls,
+                 "total_ms": r.total_ms, "working_ms": r.working_ms, "dropped": r.dropped} for r in buf[:n.value]]
 
     def pc_correction(self):
         out = self._vec()

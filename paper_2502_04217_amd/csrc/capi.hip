@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -77,6 +78,11 @@ struct csipm_ctx {
   unsigned long long cap_seed = 0;
   std::vector<int> cap_cg;
   int last_cg = 0;
+  // kernel timing: an event pair per launch while kt_on
+  bool kt_on = false;
+  std::vector<hipEvent_t> kt_ev;
+  std::vector<std::pair<const char*, size_t>> kt_rec;
+  long long kt_dropped = 0;
 };
 
 namespace {
@@ -91,6 +97,41 @@ csipm_status hip_check(csipm_ctx* c, const char* where) {
   if (e != hipSuccess) return fail(c, CSIPM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
   return CSIPM_OK;
 }
+
+// Kernel timing.  KT(c, name, launch) brackets one launcher call with a pair
+// of events on the context's stream when timing is enabled.
+constexpr size_t kMaxTimed = 1000000;
+
+size_t kt_begin(csipm_ctx* c, const char* name) {
+  if (!c->kt_on) return SIZE_MAX;
+  if (c->kt_rec.size() >= kMaxTimed) {
+    ++c->kt_dropped;
+    return SIZE_MAX;
+  }
+  const size_t e = 2 * c->kt_rec.size();
+  while (c->kt_ev.size() < e + 2) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) {
+      ++c->kt_dropped;
+      return SIZE_MAX;
+    }
+    c->kt_ev.push_back(ev);
+  }
+  hipEventRecord(c->kt_ev[e], c->s);
+  c->kt_rec.emplace_back(name, e);
+  return e;
+}
+void kt_end(csipm_ctx* c, size_t e) {
+  if (e != SIZE_MAX) hipEventRecord(c->kt_ev[e + 1], c->s);
+}
+#define KT(c, name, launch)                 \
+  do {                                      \
+    const size_t kt_e_ = kt_begin(c, name); \
+    launch;                                 \
+    kt_end(c, kt_e_);                       \
+  } while (0)
+// kernel name with the precision of T
+#define PN(T, s) (sizeof(T) == 8 ? s ".f64" : s ".f32")
 
 // Copies the device scalar and flag blocks to pinned host memory and waits.
 csipm_status sync_scalars(csipm_ctx* c, const char* where) {
@@ -142,13 +183,13 @@ const Twiddles<float>& tw<float>(csipm_ctx* c) { return c->T32; }
 template <typename T>
 void op_H(csipm_ctx* c, const T* in, T* out, T* work) {
   const Grid& g = c->g;
-  launch_premix<T>(g, in, work, nullptr, c->s);
-  launch_axis12<T>(g, 1, +1, in, work, tw<T>(c), EPI_NONE, nullptr, true, nullptr, c->s);
-  launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
-  launch_axis3<T>(g, A3_FULL, work, work, c->mask, tw<T>(c), nullptr, c->s);
-  launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
-  launch_axis12<T>(g, 1, -1, work, out, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
-  launch_postmix<T>(g, out, out, EPI_NONE, nullptr, nullptr, c->s);
+  KT(c, PN(T, "premix"), launch_premix<T>(g, in, work, nullptr, c->s));
+  KT(c, PN(T, "axis1_inv"), launch_axis12<T>(g, 1, +1, in, work, tw<T>(c), EPI_NONE, nullptr, true, nullptr, c->s));
+  KT(c, PN(T, "axis2_inv"), launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s));
+  KT(c, PN(T, "axis3"), launch_axis3<T>(g, A3_FULL, work, work, c->mask, tw<T>(c), nullptr, c->s));
+  KT(c, PN(T, "axis2_fwd"), launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s));
+  KT(c, PN(T, "axis1_fwd"), launch_axis12<T>(g, 1, -1, work, out, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s));
+  KT(c, PN(T, "postmix"), launch_postmix<T>(g, out, out, EPI_NONE, nullptr, nullptr, c->s));
 }
 
 // x = A in (real grid, row-major), work = FFT scratch (must differ from x).
@@ -183,36 +224,37 @@ int op_K(csipm_ctx* c, const T* pb, const T* pz, const T* s1, const T* s2, T* qb
   EpiArgs<T> ka{KArgs<T>{pb, pz, s1, s2, qb, qz}, RArgs{}, c->partK, ps};
   EpiArgs<T> kb = ka;
   kb.partial = c->partK + nb5;
-  launch_premix<T>(g, pb, work, skip, c->s);
-  launch_axis12<T>(g, 1, +1, pb, work, tw<T>(c), EPI_NONE, nullptr, true, skip, c->s);
-  launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, skip, c->s);
-  launch_axis3<T>(g, A3_FULL, work, work, c->mask, tw<T>(c), skip, c->s);
-  launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, skip, c->s);
-  launch_axis12<T>(g, 1, -1, work, work, tw<T>(c), EPI_K, &ka, false, skip, c->s);
-  launch_postmix<T>(g, work, nullptr, EPI_K, &kb, skip, c->s);
+  KT(c, PN(T, "premix"), launch_premix<T>(g, pb, work, skip, c->s));
+  KT(c, PN(T, "axis1_inv"), launch_axis12<T>(g, 1, +1, pb, work, tw<T>(c), EPI_NONE, nullptr, true, skip, c->s));
+  KT(c, PN(T, "axis2_inv"), launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, skip, c->s));
+  KT(c, PN(T, "axis3"), launch_axis3<T>(g, A3_FULL, work, work, c->mask, tw<T>(c), skip, c->s));
+  KT(c, PN(T, "axis2_fwd"), launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, skip, c->s));
+  KT(c, PN(T, "axis1_fwd_K"), launch_axis12<T>(g, 1, -1, work, work, tw<T>(c), EPI_K, &ka, false, skip, c->s));
+  KT(c, PN(T, "postmix_K"), launch_postmix<T>(g, work, nullptr, EPI_K, &kb, skip, c->s));
   return nb5 + postmix_blocks(g);
 }
 
-// FP64 refinement residual r = h - K d, fused into the K-apply: writes the
-// FP32 start of the next inner PCG (r32, z32 = P_c^{-1} r, p32) and sums
-// r.P_c^{-1}r -> scal[S_REF], r32.z32 -> scal[S_REFRZ].
+// FP64 refinement residual r = h - K d, fused into the K-apply of d: writes
+// H d_beta (into rb) and sums r.P_c^{-1}r -> scal[S_REF].
 void op_Kr(csipm_ctx* c, const float* pcc) {
   const Grid& g = c->g;
   const int nb5 = axis12_blocks(g, 1, 16);
   const int ps = (int)k_partials(g.n1, g.n2, g.n3);
-  RArgs ra{c->dxb, c->dxz, c->sig1, c->sig2, c->rhb, c->rhz, pcc, c->frb, c->frz, c->fzb, c->fzz, c->fpb, c->fpz};
+  // H d_beta goes to rb: the FP64 Krylov vectors are idle in the FP32 form
+  RArgs ra{c->dxb, c->dxz, c->sig1, c->sig2, c->rhb, c->rhz, pcc, c->rb};
   EpiArgs<double> ea{KArgs<double>{}, ra, c->partK, ps};
   EpiArgs<double> eb = ea;
   eb.partial = c->partK + nb5;
   double* work = c->work;
-  launch_premix<double>(g, c->dxb, work, nullptr, c->s);
-  launch_axis12<double>(g, 1, +1, c->dxb, work, c->T64, EPI_NONE, nullptr, true, nullptr, c->s);
-  launch_axis12<double>(g, 2, +1, work, work, c->T64, EPI_NONE, nullptr, false, nullptr, c->s);
-  launch_axis3<double>(g, A3_FULL, work, work, c->mask, c->T64, nullptr, c->s);
-  launch_axis12<double>(g, 2, -1, work, work, c->T64, EPI_NONE, nullptr, false, nullptr, c->s);
-  launch_axis12<double>(g, 1, -1, work, work, c->T64, EPI_R, &ea, false, nullptr, c->s);
-  launch_postmix<double>(g, work, nullptr, EPI_R, &eb, nullptr, c->s);
-  fin_two(c->partK, nb5 + postmix_blocks(g), ps, c->scal, S_REF, S_REFRZ, c->s);
+  KT(c, "premix.f64", launch_premix<double>(g, c->dxb, work, nullptr, c->s));
+  KT(c, "axis1_inv.f64",
+     launch_axis12<double>(g, 1, +1, c->dxb, work, c->T64, EPI_NONE, nullptr, true, nullptr, c->s));
+  KT(c, "axis2_inv.f64", launch_axis12<double>(g, 2, +1, work, work, c->T64, EPI_NONE, nullptr, false, nullptr, c->s));
+  KT(c, "axis3.f64", launch_axis3<double>(g, A3_FULL, work, work, c->mask, c->T64, nullptr, c->s));
+  KT(c, "axis2_fwd.f64", launch_axis12<double>(g, 2, -1, work, work, c->T64, EPI_NONE, nullptr, false, nullptr, c->s));
+  KT(c, "axis1_fwd_R.f64", launch_axis12<double>(g, 1, -1, work, work, c->T64, EPI_R, &ea, false, nullptr, c->s));
+  KT(c, "postmix_R.f64", launch_postmix<double>(g, work, nullptr, EPI_R, &eb, nullptr, c->s));
+  KT(c, "fin_sum", fin_sum(c->partK, nb5 + postmix_blocks(g), c->scal + S_REF, c->s));
 }
 
 // ------------------------------------------------- learned correction --
@@ -228,8 +270,11 @@ void compute_features(csipm_ctx* c) {
 // elsewhere; features formed from the interior-point state (before the
 // Newton system is built).
 csipm_status learned_correction(csipm_ctx* c) {
-  mlp_correction_state(c->beta, c->z, c->nu1, c->nu2, c->diagH, c->scal + S_RESID + 4, c->mlp_params, c->pc_c,
-                       c->g.n, c->partV, c->scal + S_MISC + 1, kPcRelevance, c->s);
+  KT(c, "log_l1+fin",
+     mlp_mean_log_l1_state(c->beta, c->z, c->nu1, c->nu2, c->g.n, c->partV, c->scal + S_MISC + 1, c->s));
+  KT(c, "correction",
+     mlp_correction_state(c->beta, c->z, c->nu1, c->nu2, c->diagH, c->scal + S_MISC + 1, c->scal + S_RESID + 4,
+                          c->mlp_params, c->pc_c, c->g.n, kPcRelevance, c->s));
   return hip_check(c, "learned_correction");
 }
 
@@ -266,39 +311,34 @@ struct PcgOut {
 };
 
 // Preconditioned CG (Hestenes-Stiefel) on K x = h, x0 = 0, stopping on
-// sqrt(r.P^{-1}r) <= max(atol, eta sqrt(r0.P^{-1}r0)).  When hb is set the
-// solve starts from h (kernel k_cg_init); otherwise r, z = P^{-1}r and p = z
-// are already in the precision-T Krylov vectors and the start has been
-// finalised (k_fin_cg_init) by the caller.  x0 = 0 is never stored: the
-// first update writes x = alpha p.  Iterations are queued in growing
+// sqrt(r.P^{-1}r) <= max(atol, eta sqrt(r0.P^{-1}r0)).  The caller has put
+// r = h, z = P^{-1}r and p = z into the precision-T Krylov vectors and
+// finalised the start (k_fin_cg_init).  x0 = 0 is never stored: the first
+// update writes x = alpha p.  On return r holds the recursive residual of x.  Iterations are queued in growing
 // batches; finished iterations turn the rest of a batch into no-ops through
 // the device flag, so the host only synchronises once per batch.  If
 // `capture` is set, p_0 and q_0 = K p_0 go to the capture hook.
 template <typename T>
-csipm_status pcg(csipm_ctx* c, const T* hb, const T* hz, T* xb, T* xz, const T* s1, const T* s2, const float* pcc,
-                 double eta, double atol, int maxit, PcgOut& out, bool capture) {
+csipm_status pcg(csipm_ctx* c, T* xb, T* xz, const T* s1, const T* s2, const float* pcc, PcgOut& out,
+                 bool capture) {
   const long long n = c->g.n;
   PcgSet v = pcg_set<T>(c);
   T *rb = (T*)v.rb, *rz = (T*)v.rz, *zb = (T*)v.zb, *zz = (T*)v.zz, *pb = (T*)v.pb, *pz = (T*)v.pz,
     *qb = (T*)v.qb, *qz = (T*)v.qz, *work = (T*)v.work;
   const int nbv = vec_blocks(n);
-  if (hb) {
-    cg_init<T>(hb, hz, xb, xz, rb, rz, zb, zz, pb, pz, s1, s2, pcc, n, c->partV, c->s);
-    fin_cg_init(c->partV, nbv, c->scal, c->flags, eta, atol, maxit, c->s);
-  }
   const int* skip = c->flags + F_DONE;
   int chunk = 2;
   bool first = true;
   for (;;) {
     for (int k = 0; k < chunk; ++k) {
       const int nbk = op_K<T>(c, pb, pz, s1, s2, qb, qz, work, skip);
-      if (first && capture) capture_pair<T>(c, pb, pz, qb, qz, s1, s2);
-      fin_alpha(c->partK, nbk, c->scal, c->flags, c->s);
-      cg_update<T>(xb, xz, pb, pz, qb, qz, rb, rz, zb, zz, s1, s2, pcc, c->scal, c->flags, n, c->partV, first,
-                   c->s);
+      if (first && capture) KT(c, "capture", capture_pair<T>(c, pb, pz, qb, qz, s1, s2));
+      KT(c, "fin_alpha", fin_alpha(c->partK, nbk, c->scal, c->flags, c->s));
+      KT(c, PN(T, "cg_update"), cg_update<T>(xb, xz, pb, pz, qb, qz, rb, rz, zb, zz, s1, s2, pcc, c->scal, c->flags,
+                                            n, c->partV, first, c->s));
       first = false;
-      fin_rz(c->partV, nbv, c->scal, c->flags, c->s);
-      cg_pupdate<T>(pb, pz, zb, zz, c->scal, c->flags, n, c->s);
+      KT(c, "fin_rz", fin_rz(c->partV, nbv, c->scal, c->flags, c->s));
+      KT(c, PN(T, "cg_pupdate"), cg_pupdate<T>(pb, pz, zb, zz, c->scal, c->flags, n, c->s));
     }
     csipm_status st = sync_scalars(c, "pcg");
     if (st != CSIPM_OK) return st;
@@ -331,6 +371,7 @@ void csipm_default_options(csipm_options* o) {
   o->pc = CSIPM_PC_PLAIN;
   o->refine_max = 8;
   o->refine_inner_rtol = 1e-5;
+  o->refine_trust = 1e-4;
 }
 
 size_t csipm_workspace_bytes(int n1, int n2, int n3) {
@@ -447,20 +488,30 @@ namespace {
 // smu = sigma mu): K [dxb; dxz] = h with the barrier diagonals Sigma_j =
 // nu_j / s_j, either by FP64 PCG or by FP32 PCG inside FP64 iterative
 // refinement.  The system build is fused with the PCG start (newton_init).
+// Where the iterate update finds H d_beta after a Newton solve.
+enum HdSource {
+  HD_RRES64,   // recovered from the FP64 PCG residual (rb, rz)
+  HD_DIRECT,   // written by the FP64 refinement residual pass (rb)
+  HD_RRES32    // recovered from the FP32 PCG residual (frb, frz): FP32-level accuracy
+};
+
 csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, double eta, const float* pcc,
-                          int& cg_iters, int& refine_steps, bool& converged, bool capture) {
+                          int& cg_iters, int& refine_steps, bool& converged, bool capture, HdSource& src) {
   const long long n = c->g.n;
   const int nbv = vec_blocks(n);
   cg_iters = 0;
   refine_steps = 0;
   converged = false;
+  src = HD_RRES64;
   if (o.precision == CSIPM_FP64) {
-    newton_init<double>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, smu, c->sig1, c->sig2, nullptr,
-                        nullptr, nullptr, nullptr, pcc, c->rb, c->rz, c->zb, c->zz, c->pb, c->pz, n, c->partV, c->s);
-    fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, eta, o.cg_atol, o.cg_max, -1, -1, c->s);
+    KT(c, "newton_init.f64",
+       newton_init<double>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, smu, c->sig1, c->sig2, nullptr,
+                           nullptr, nullptr, nullptr, pcc, c->rb, c->rz, c->zb, c->zz, c->pb, c->pz, n, c->partV,
+                           c->s));
+    KT(c, "fin_cg_start",
+       fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, eta, o.cg_atol, o.cg_max, -1, -1, c->s));
     PcgOut po;
-    csipm_status st = pcg<double>(c, nullptr, nullptr, c->dxb, c->dxz, c->sig1, c->sig2, pcc, eta, o.cg_atol,
-                                  o.cg_max, po, capture);
+    csipm_status st = pcg<double>(c, c->dxb, c->dxz, c->sig1, c->sig2, pcc, po, capture);
     cg_iters = po.iters;
     converged = po.converged;
     return st;
@@ -468,26 +519,45 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
   // FP32 inner solves, FP64 residual: d = 0, r = h; repeat { e = K32^{-1} r;
   // d += e; r = h - K d } until sqrt(r.P^{-1}r) <= max(atol, eta sqrt(h.P^{-1}h)).
   // The first inner solve starts from h (built in FP32 by newton_init, which
-  // also sums h.P^{-1}h); later ones start from the FP32 residual written by
-  // the fused FP64 residual pass.
-  newton_init<float>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, smu, c->sig1, c->sig2, c->rhb, c->rhz,
-                     c->sig1f, c->sig2f, pcc, c->frb, c->frz, c->fzb, c->fzz, c->fpb, c->fpz, n, c->partV, c->s);
+  // also sums h.P^{-1}h); later ones start from the FP32 residual (built
+  // from the fused FP64 residual pass by ref_restart).  A system whose
+  // tolerance is loose enough for FP32 (eta >= refine_trust) takes the FP32
+  // solution to half its tolerance without the FP64 residual pass.
+  const bool trusted = o.refine_trust > 0.0 && eta >= o.refine_trust;
+  KT(c, trusted ? "newton_init_noh.f32" : "newton_init.f32",
+     newton_init<float>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, smu, c->sig1, c->sig2,
+                        trusted ? nullptr : c->rhb, trusted ? nullptr : c->rhz, c->sig1f, c->sig2f, pcc, c->frb,
+                        c->frz, c->fzb, c->fzz, c->fpb, c->fpz, n, c->partV, c->s));
   // inner tolerance: half the remaining reduction, at most 1e-2, at least
   // refine_inner_rtol (what FP32 PCG can still reach)
   double inner = std::max(o.refine_inner_rtol, std::min(1e-2, 0.5 * eta));
-  fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, inner, 0.0, o.cg_max, S_REF0, -1, c->s);
+  if (trusted) {
+    KT(c, "fin_cg_start",
+       fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, inner, 0.0, o.cg_max, -1, -1, c->s));
+    PcgOut po;
+    csipm_status st = pcg<float>(c, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, po, capture);
+    if (st != CSIPM_OK) return st;
+    cg_iters = po.iters;
+    converged = po.converged;
+    KT(c, "set_f2d", set_f2d(c->dxb, c->dxz, c->fxb, c->fxz, n, c->s));
+    src = HD_RRES32;
+    return CSIPM_OK;
+  }
+  src = HD_DIRECT;
+  KT(c, "fin_cg_start",
+     fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, inner, 0.0, o.cg_max, S_REF0, -1, c->s));
   double target = 0.0, rnorm = 0.0;
   for (int step = 0; step < std::max(1, o.refine_max); ++step) {
-    if (step > 0) fin_cg_start(nullptr, 0, 0, c->scal, c->flags, inner, 0.0, o.cg_max, -1, S_REFRZ, c->s);
+    if (step > 0)
+      KT(c, "fin_cg_start", fin_cg_start(nullptr, 0, 0, c->scal, c->flags, inner, 0.0, o.cg_max, -1, S_REFRZ, c->s));
     PcgOut po;
-    csipm_status st = pcg<float>(c, nullptr, nullptr, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, inner, 0.0, o.cg_max,
-                                 po, capture && step == 0);
+    csipm_status st = pcg<float>(c, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, po, capture && step == 0);
     if (st != CSIPM_OK) return st;
     cg_iters += po.iters;
     if (step == 0)
-      set_f2d(c->dxb, c->dxz, c->fxb, c->fxz, n, c->s);
+      KT(c, "set_f2d", set_f2d(c->dxb, c->dxz, c->fxb, c->fxz, n, c->s));
     else
-      add_f2d(c->dxb, c->dxz, c->fxb, c->fxz, n, c->s);
+      KT(c, "add_f2d", add_f2d(c->dxb, c->dxz, c->fxb, c->fxz, n, c->s));
     op_Kr(c, pcc);
     st = sync_scalars(c, "refine");
     if (st != CSIPM_OK) return st;
@@ -499,8 +569,12 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
       converged = true;
       break;
     }
-    if (po.iters == 0 || !std::isfinite(rnorm)) break;
+    if (po.iters == 0 || !std::isfinite(rnorm) || step + 1 >= std::max(1, o.refine_max)) break;
     inner = std::max(o.refine_inner_rtol, std::min(1e-2, 0.5 * target / rnorm));
+    // FP32 start of the next inner solve: r32, z32 = p32 = P_c^{-1} r, r32.z32 -> S_REFRZ
+    KT(c, "ref_restart+fin",
+       ref_restart(c->rhb, c->rhz, c->dxb, c->dxz, c->rb, c->sig1, c->sig2, pcc, c->frb, c->frz, c->fzb, c->fzz,
+                   c->fpb, c->fpz, n, c->partV, c->scal + S_REFRZ, c->s));
   }
   return CSIPM_OK;
 }
@@ -509,15 +583,28 @@ struct Resid {
   double fb, fz, cmax, csum, bmax, pmin, nonfinite;
 };
 
+// Residual parts last reduced into scal[S_RESID..] (after a sync).
+Resid read_resid(const csipm_ctx* c) {
+  const double* v = c->hscal + S_RESID;
+  return Resid{v[0], v[1], v[2], v[3], v[4], v[5], v[6]};
+}
+
+// Residual parts with H beta recomputed by a full H-apply.
 csipm_status residuals(csipm_ctx* c, Resid& r) {
   op_H<double>(c, c->beta, c->hb, c->work);
-  ipm_resid(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, c->g.n, c->partV, c->scal + S_RESID, c->s);
+  KT(c, "ipm_resid+fin", ipm_resid(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, c->g.n, c->partV,
+                                    c->scal + S_RESID, c->s));
   csipm_status st = sync_scalars(c, "residuals");
   if (st != CSIPM_OK) return st;
-  const double* v = c->hscal + S_RESID;
-  r = Resid{v[0], v[1], v[2], v[3], v[4], v[5], v[6]};
+  r = read_resid(c);
   return CSIPM_OK;
 }
+
+// H beta is carried from iteration to iteration (k_ipm_advance); it is
+// recomputed by a full H-apply before a stopping decision, at least every
+// kExactEvery iterations, and before the first FP32 Newton system that is
+// refined after unrefined ones, so carried error never accumulates far.
+constexpr int kExactEvery = 16;
 
 }  // namespace
 
@@ -528,7 +615,8 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   csipm_default_options(&o);
   if (opts) o = *opts;
   if (!(o.tol > 0) || o.max_iter < 0 || o.cg_max < 1 || !(o.sigma > 0 && o.sigma < 1) || !(o.tau > 0 && o.tau < 1) ||
-      (o.precision != CSIPM_FP64 && o.precision != CSIPM_FP32) || (o.pc != CSIPM_PC_PLAIN && o.pc != CSIPM_PC_LEARNED))
+      (o.precision != CSIPM_FP64 && o.precision != CSIPM_FP32) || (o.pc != CSIPM_PC_PLAIN && o.pc != CSIPM_PC_LEARNED) ||
+      !(o.refine_trust >= 0.0 && o.refine_trust <= 1.0) || !(o.refine_inner_rtol > 0.0))
     return fail(c, CSIPM_EINVAL, "invalid options");
   if (o.pc == CSIPM_PC_LEARNED && !c->have_params) return fail(c, CSIPM_ESTATE, "learned preconditioner has no parameters");
   const auto t0 = std::chrono::steady_clock::now();
@@ -538,19 +626,36 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   c->cap_count = 0;
   c->cap_cg.clear();
   const double z0 = c->xi_inf > 0 ? c->xi_inf : 1.0;
-  ipm_init(c->beta, c->z, c->nu1, c->nu2, n, z0, lam, c->s);
+  // the start beta = 0 has H beta = 0 exactly
+  KT(c, "ipm_init", ipm_init(c->beta, c->z, c->nu1, c->nu2, c->hb, n, z0, lam, c->s));
+  KT(c, "ipm_resid+fin",
+     ipm_resid(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, lam, n, c->partV, c->scal + S_RESID, c->s));
+  csipm_status st = sync_scalars(c, "solve start");
+  if (st != CSIPM_OK) return st;
+  Resid r = read_resid(c);
+  bool exact = true;
+  bool approx = false;   // carried H beta holds FP32-level error (an unrefined FP32 step)
+  int carried = 0;
   csipm_info inf{};
   inf.lambda = lam;
   inf.xi_inf = c->xi_inf;
   csipm_status result = CSIPM_NOT_CONVERGED;
   int prev_cg = 0;
-  Resid r{};
   for (int it = 0;; ++it) {
-    csipm_status st = residuals(c, r);
-    if (st != CSIPM_OK) return st;
+    auto rel_of = [&](const Resid& q) { return std::max(std::max(q.fb, q.fz), q.cmax) / (1.0 + c->xi_inf); };
+    double rel = rel_of(r);
+    const bool leaving_trust = approx && !(std::min(o.cg_rtol, 0.1 * rel) >= o.refine_trust);
+    if (!exact &&
+        (rel <= o.tol || it >= o.max_iter || carried >= kExactEvery || leaving_trust || !std::isfinite(rel))) {
+      st = residuals(c, r);
+      if (st != CSIPM_OK) return st;
+      exact = true;
+      approx = false;
+      carried = 0;
+      rel = rel_of(r);
+    }
     if (r.nonfinite > 0 || !std::isfinite(r.fb)) return fail(c, CSIPM_ENONFINITE, "non-finite interior-point iterate");
     const double mu = r.csum / (2.0 * (double)n);
-    const double rel = std::max(std::max(r.fb, r.fz), r.cmax) / (1.0 + c->xi_inf);
     inf.rel_kkt = rel;
     inf.res_beta_inf = r.fb;
     inf.res_z_inf = r.fz;
@@ -569,6 +674,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     const double eta = std::min(o.cg_rtol, 0.1 * rel);
     int cgi = 0, ref = 0;
     bool conv = false, fell = false;
+    HdSource src = HD_RRES64;
     const bool capture = c->cap_enable && o.pc == CSIPM_PC_PLAIN && c->cap_count < c->cap_max;
     if (o.pc == CSIPM_PC_LEARNED) {
       st = learned_correction(c);
@@ -576,11 +682,11 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       csipm_options ol = o;
       const int budget = prev_cg > 0 ? std::min(o.cg_max, std::max(8, (prev_cg * 3) / 2)) : o.cg_max;
       ol.cg_max = budget;
-      st = newton_solve(c, ol, smu, eta, c->pc_c, cgi, ref, conv, false);
+      st = newton_solve(c, ol, smu, eta, c->pc_c, cgi, ref, conv, false, src);
       if (st != CSIPM_OK) return st;
       if (!conv) {
         int cgi2 = 0, ref2 = 0;
-        st = newton_solve(c, o, smu, eta, nullptr, cgi2, ref2, conv, false);
+        st = newton_solve(c, o, smu, eta, nullptr, cgi2, ref2, conv, false, src);
         if (st != CSIPM_OK) return st;
         cgi += cgi2;
         ref += ref2;
@@ -588,7 +694,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
         ++inf.fallbacks;
       }
     } else {
-      st = newton_solve(c, o, smu, eta, nullptr, cgi, ref, conv, capture);
+      st = newton_solve(c, o, smu, eta, nullptr, cgi, ref, conv, capture, src);
       if (st != CSIPM_OK) return st;
       if (capture) {
         mlp_scale_weights(c->cap_rec + (size_t)c->cap_count * c->cap_per_iter * MLP_REC, c->cap_per_iter,
@@ -601,13 +707,19 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     inf.cg_iters_total += cgi;
     inf.cg_iters_max = std::max(inf.cg_iters_max, cgi);
     inf.refine_steps_total += ref;
-    ipm_step(c->beta, c->z, c->nu1, c->nu2, c->sig1, c->sig2, c->dxb, c->dxz, smu, o.tau, n, c->partV, c->scal,
-             c->s);
-    ipm_update(c->beta, c->z, c->nu1, c->nu2, c->sig1, c->sig2, c->dxb, c->dxz, smu, c->scal, n, c->s);
+    KT(c, "ipm_ratio+fin",
+       ipm_step(c->beta, c->z, c->nu1, c->nu2, c->dxb, c->dxz, smu, o.tau, n, c->partV, c->scal, c->s));
+    KT(c, "ipm_advance+fin",
+       ipm_advance(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->dxb, c->dxz, src == HD_DIRECT ? c->rb : nullptr,
+                   c->rb, src == HD_RRES32 ? c->frb : nullptr, lam, smu, c->scal, n, c->partV, c->s));
+    st = sync_scalars(c, "advance");
+    if (st != CSIPM_OK) return st;
+    r = read_resid(c);
+    exact = false;
+    approx = approx || src == HD_RRES32;
+    ++carried;
     c->log.push_back(csipm_iter_log{it, cgi, ref, fell ? 1 : 0, mu, rel, 0.0});
     inf.ipm_iters = it + 1;
-    st = hip_check(c, "solve");
-    if (st != CSIPM_OK) return st;
   }
   inf.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   inf.status = result;
@@ -896,8 +1008,49 @@ csipm_status csipm_profile_kapply(csipm_ctx* c, int precision, int reps, double*
   return hip_check(c, "profile_kapply");
 }
 
+csipm_status csipm_timing(csipm_ctx* c, int enable) {
+  if (!c) return CSIPM_EINVAL;
+  if (enable) {
+    c->kt_rec.clear();
+    c->kt_dropped = 0;
+  }
+  c->kt_on = enable != 0;
+  return CSIPM_OK;
+}
+
+csipm_status csipm_timing_report(csipm_ctx* c, double min_us, csipm_kernel_time* out, int max_records,
+                                 int* n_records) {
+  if (!c || (!out && max_records > 0)) return CSIPM_EINVAL;
+  hipError_t e = hipStreamSynchronize(c->s);
+  if (e != hipSuccess) return fail(c, CSIPM_EHIP, std::string("timing_report: ") + hipGetErrorString(e));
+  std::vector<csipm_kernel_time> agg;
+  for (const auto& rec : c->kt_rec) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, c->kt_ev[rec.second], c->kt_ev[rec.second + 1]);
+    if (e != hipSuccess) return fail(c, CSIPM_EHIP, std::string("timing_report: ") + hipGetErrorString(e));
+    size_t k = 0;
+    while (k < agg.size() && std::strcmp(agg[k].name, rec.first) != 0) ++k;
+    if (k == agg.size()) {
+      csipm_kernel_time t{};
+      std::snprintf(t.name, sizeof(t.name), "%s", rec.first);
+      agg.push_back(t);
+    }
+    agg[k].calls += 1;
+    agg[k].total_ms += ms;
+    if (ms * 1e3 >= min_us) {
+      agg[k].working_calls += 1;
+      agg[k].working_ms += ms;
+    }
+  }
+  if (!agg.empty()) agg[0].dropped = c->kt_dropped;
+  for (int i = 0; i < std::min<int>(max_records, (int)agg.size()); ++i) out[i] = agg[i];
+  if (n_records) *n_records = (int)agg.size();
+  return CSIPM_OK;
+}
+
 csipm_status csipm_destroy(csipm_ctx* c) {
   if (!c) return CSIPM_EINVAL;
+  for (hipEvent_t ev : c->kt_ev) (void)hipEventDestroy(ev);
   if (c->hscal) (void)hipHostFree(c->hscal);
   delete c;
   return CSIPM_OK;

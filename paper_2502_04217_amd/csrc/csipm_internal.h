@@ -124,7 +124,7 @@ enum Axis3Mode { A3_C2R = 1, A3_R2C = 2, A3_FULL = 3 };
 enum EpiMode {
   EPI_NONE = 0,   // write the transform result (A^T x or H p), m = 0 left raw
   EPI_K = 1,      // q = K p with the barrier diagonals, plus p.q partials
-  EPI_R = 2       // FP64 only: r = h - K d, FP32 restart vectors, two dots
+  EPI_R = 2       // FP64 only: H d_beta out and r.P^{-1}r of r = h - K d
 };
 
 template <typename T>
@@ -145,12 +145,7 @@ struct RArgs {
   const double* hb;   // right-hand side
   const double* hz;
   const float* c;     // learned correction or null (c = 1)
-  float* frb;         // FP32 restart of the inner PCG: r, z = P_c^{-1} r, p = z
-  float* frz;
-  float* fzb;
-  float* fzz;
-  float* fpb;
-  float* fpz;
+  double* hd;         // out: H d_beta, the transform output
 };
 
 // Epilogue arguments: quantity q of block b goes to partial[q * pstride + b].

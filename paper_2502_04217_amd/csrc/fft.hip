@@ -202,32 +202,31 @@ struct EpiK {
   }
 };
 
-// FP64 refinement residual r = h - K d, the FP32 start of the next inner
-// PCG (r32, z32 = P_c^{-1} r, p32 = z32) and the sums r.P_c^{-1}r, r32.z32.
+// FP64 refinement residual r = h - K d: writes H d_beta (the transform output
+// itself) and sums r.P_c^{-1}r.  A further inner solve, when one is needed,
+// builds its FP32 start from H d_beta elementwise (k_ref_restart).
 struct EpiR {
-  static constexpr int NRED = 2;
+  static constexpr int NRED = 1;
   RArgs a;
   double* partial;
   int pstride;
-  __device__ __forceinline__ void one(long long i, double h, double& acc0, double& acc1) const {
-    double qb, qz;
-    k_block<double>(h, a.db[i], a.dz[i], a.sig1[i], a.sig2[i], qb, qz);
-    const double rb = a.hb[i] - qb, rz = a.hz[i] - qz;
-    double zb, zz;
-    pinv_block(rb, rz, a.sig1[i], a.sig2[i], a.c ? (double)a.c[i] : 1.0, zb, zz);
-    const float fb = (float)rb, fz = (float)rz, gb = (float)zb, gz = (float)zz;
-    a.frb[i] = fb;
-    a.frz[i] = fz;
-    a.fzb[i] = gb;
-    a.fzz[i] = gz;
-    a.fpb[i] = gb;
-    a.fpz[i] = gz;
-    acc0 += rb * zb + rz * zz;
-    acc1 += (double)fb * (double)gb + (double)fz * (double)gz;
-  }
   __device__ __forceinline__ void operator()(long long idx, cx<double> h, double* acc) const {
-    one(2 * idx, h.re, acc[0], acc[1]);
-    one(2 * idx + 1, h.im, acc[0], acc[1]);
+    using D2 = cx<double>;
+    const D2 db = reinterpret_cast<const D2*>(a.db)[idx], dz = reinterpret_cast<const D2*>(a.dz)[idx];
+    const D2 s1 = reinterpret_cast<const D2*>(a.sig1)[idx], s2 = reinterpret_cast<const D2*>(a.sig2)[idx];
+    const D2 hb = reinterpret_cast<const D2*>(a.hb)[idx], hz = reinterpret_cast<const D2*>(a.hz)[idx];
+    const float2 c = a.c ? reinterpret_cast<const float2*>(a.c)[idx] : make_float2(1.0f, 1.0f);
+    reinterpret_cast<D2*>(a.hd)[idx] = h;
+    const double hv[2] = {h.re, h.im}, dbv[2] = {db.re, db.im}, dzv[2] = {dz.re, dz.im}, g1[2] = {s1.re, s1.im},
+                 g2[2] = {s2.re, s2.im}, rhb[2] = {hb.re, hb.im}, rhz[2] = {hz.re, hz.im}, cv[2] = {c.x, c.y};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      double qb, qz, zb, zz;
+      k_block<double>(hv[k], dbv[k], dzv[k], g1[k], g2[k], qb, qz);
+      const double rb = rhb[k] - qb, rz = rhz[k] - qz;
+      pinv_block(rb, rz, g1[k], g2[k], cv[k], zb, zz);
+      acc[0] += rb * zb + rz * zz;
+    }
   }
 };
 
@@ -724,6 +723,14 @@ void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t*
     constexpr int NT = LL / a3_e<T>(LL);                                                           \
     const size_t shm = (size_t)PP * a3_pad<T>(LL) * sizeof(cx<T>);                                 \
     dim3 grid((np + PP - 1) / PP), block(PP * NT);                                                 \
+    if (shm > 65536) {                                                                             \
+      (void)hipFuncSetAttribute((const void*)k_axis3<T, LL, A3_FULL>,                              \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);            \
+      (void)hipFuncSetAttribute((const void*)k_axis3<T, LL, A3_C2R>,                               \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);            \
+      (void)hipFuncSetAttribute((const void*)k_axis3<T, LL, A3_R2C>,                               \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);            \
+    }                                                                                              \
     if (mode == A3_FULL)                                                                           \
       hipLaunchKernelGGL((k_axis3<T, LL, A3_FULL>), grid, block, shm, s, cs, cd, maskbits, tw.tm, \
                          tw.t3, np, sc_c2r, sc_dc, sc_ac, skip);                                         \

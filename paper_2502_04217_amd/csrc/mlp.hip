@@ -40,7 +40,7 @@ __device__ __forceinline__ float tanh_fast(float x) {
     return x * p;
   }
   const float e = __expf(2.0f * ax);
-  return copysignf(1.0f - __fdividef(2.0f, e + 1.0f), x);
+  return copysignf(1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f), x);
 }
 __device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(__expf(-fabsf(x))); }
 __device__ __forceinline__ float sigmoidf(float x) { return 0.5f * (1.0f + tanh_fast(0.5f * x)); }
@@ -71,14 +71,125 @@ __device__ __forceinline__ float fwd1(const float* P, const float x[NIN], float 
   return o;
 }
 
-__global__ void __launch_bounds__(256)
+// ------------------------------------------------ inference on MFMA --
+// Inference runs the two dense layers on the matrix cores
+// (v_mfma_f32_16x16x4_f32, FP32 in, FP32 accumulate) with coefficients along
+// the 16 columns and neurons along the rows.  Register layout of that MFMA
+// for lane l (g = l / 16, q = l % 16): A is 16x4 with lane l holding A[q][g],
+// B is 4x16 with lane l holding B[g][q], D is 16x16 with lane l holding
+// D[4g + r][q] in register r.  Layer 1 (K = 4 features) is one MFMA per 16
+// neurons.  A layer output lands in lane (g, q) as neurons 16t + 4g + r of
+// coefficient q, which is already a valid B operand for the next layer if the
+// contraction index of k-step (t, r) is taken as g <-> neuron 16t + 4g + r;
+// the A operand (weights) is permuted to match, so no data moves between
+// layers.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+struct MfmaNet {
+  float w1[2];      // W1[16t + q][g]
+  float w2[2][8];   // output rows 16m + q, k-step s = 4t + r: W2[16m + q][16t + 4g + r]
+  float b1[2][4];   // [t][r]: b1[16t + 4g + r]
+  float b2[2][4];
+  float w3[2][4];
+  float b3;
+};
+
+__device__ __forceinline__ void load_net(const float* __restrict__ P, MfmaNet& w) {
+  const int l = threadIdx.x & 63, g = l >> 4, q = l & 15;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    w.w1[t] = P[OW1 + (16 * t + q) * NIN + g];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      w.b1[t][r] = P[OB1 + 16 * t + 4 * g + r];
+      w.b2[t][r] = P[OB2 + 16 * t + 4 * g + r];
+      w.w3[t][r] = P[OW3 + 16 * t + 4 * g + r];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) w.w2[m][s] = P[OW2 + (16 * m + q) * H1 + 16 * (s >> 2) + 4 * g + (s & 3)];
+  w.b3 = P[OB3];
+}
+
+// tanh without branches: sign(x) (1 - e) / (1 + e), e = exp(-2|x|), with the
+// hardware exp2 and reciprocal; absolute error ~2e-7 (what the weighted sums
+// of the next layer see).
+__device__ __forceinline__ float tanh_exp(float x) {
+  const float e = __builtin_amdgcn_exp2f(fabsf(x) * -2.8853900817779268f);
+  return copysignf((1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e), x);
+}
+
+// Output pre-activation o for the 16 coefficients of one tile: lane (g, q)
+// brings feature g of coefficient q and receives o of coefficient q.
+__device__ __forceinline__ float net_tile(const MfmaNet& w, float xb) {
+  f4_t h1[2], h2[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const f4_t c = {w.b1[t][0], w.b1[t][1], w.b1[t][2], w.b1[t][3]};
+    h1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w1[t], xb, c, 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h1[t][r] = tanh_exp(h1[t][r]);
+#pragma unroll
+  for (int m = 0; m < 2; ++m) h2[m] = f4_t{w.b2[m][0], w.b2[m][1], w.b2[m][2], w.b2[m][3]};
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+      h2[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w2[m][s], h1[s >> 2][s & 3], h2[m], 0, 0, 0);
+  float o = 0.0f;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o = fmaf(w.w3[m][r], tanh_exp(h2[m][r]), o);
+  o += __shfl_xor(o, 16, 64);
+  o += __shfl_xor(o, 32, 64);
+  return o + w.b3;
+}
+
+// o for a chunk of 64 coefficients, lane l holding the four features of
+// coefficient l; tiles (16 coefficients) with no bit set in `act` are
+// skipped.  `lds` is this wave's 256-float staging area.
+__device__ __forceinline__ float net_chunk(const MfmaNet& w, float* lds, const float x[NIN], unsigned long long act) {
+  const int l = threadIdx.x & 63, g = l >> 4, q = l & 15;
+  reinterpret_cast<float4*>(lds)[l] = make_float4(x[0], x[1], x[2], x[3]);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  float mine = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (((act >> (16 * t)) & 0xFFFFull) == 0) continue;
+    const float o = net_tile(w, lds[(16 * t + q) * NIN + g]);
+    if (g == t) mine = o;
+  }
+  __builtin_amdgcn_wave_barrier();
+  return mine;
+}
+
+constexpr int kNetWaves = 4;   // waves per inference workgroup
+
+__global__ void __launch_bounds__(64 * kNetWaves)
 k_forward(const float* __restrict__ P, const float* __restrict__ feat, float* __restrict__ c, long long n) {
-  for (long long i = gtid(); i < n; i += gstride()) {
-    const float4 f = reinterpret_cast<const float4*>(feat)[i];
-    const float x[NIN] = {f.x, f.y, f.z, f.w};
-    float h1[H1], h2[H2];
-    const float o = fwd1(P, x, h1, h2);
-    c[i] = softplusf(o) + 1e-6f;
+  __shared__ float lds[kNetWaves][64 * NIN];
+  MfmaNet w;
+  load_net(P, w);
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long long nch = (n + 63) / 64;
+  for (long long ch = blockIdx.x * (long long)kNetWaves + wv; ch < nch; ch += (long long)gridDim.x * kNetWaves) {
+    const long long i = ch * 64 + l;
+    float x[NIN] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (i < n) {
+      const float4 f = reinterpret_cast<const float4*>(feat)[i];
+      x[0] = f.x; x[1] = f.y; x[2] = f.z; x[3] = f.w;
+    }
+    const unsigned long long act = __ballot(i < n);
+    const float o = net_chunk(w, lds[wv], x, act);
+    if (i < n) c[i] = softplusf(o) + 1e-6f;
   }
 }
 
@@ -281,25 +392,38 @@ k_features_state(const double* __restrict__ beta, const double* __restrict__ z, 
 // the four features, and c = softplus(MLP) + 1e-6 only where c can act on
 // P_c^{-1}, i.e. where L1 / (L1 + 4 S1 S2) >= rmin; elsewhere c = 1 (the
 // paper's P, from which P_c^{-1} then differs by less than rmin relative).
-__global__ void __launch_bounds__(256)
+// The network runs on the matrix cores for every 16-coefficient tile that
+// holds an active coefficient.
+__global__ void __launch_bounds__(64 * kNetWaves)
 k_correction_state(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
                    const double* __restrict__ nu2, const double* __restrict__ diagH,
                    const double* __restrict__ meanlog, const double* __restrict__ bmax,
                    const float* __restrict__ P, float* __restrict__ c, long long n, double rmin) {
+  __shared__ float lds[kNetWaves][64 * NIN];
+  MfmaNet w;
+  load_net(P, w);
   const double ml = *meanlog;
   const double bm = *bmax > 0.0 ? *bmax : 1.0;
-  for (long long i = gtid(); i < n; i += gstride()) {
-    const double b = beta[i];
-    const double g1 = nu1[i] / (z[i] + b), g2 = nu2[i] / (z[i] - b);
-    const double L1 = g1 + g2;
-    float ci = 1.0f;
-    if (L1 >= rmin * (L1 + 4.0 * g1 * g2)) {
-      const float x[NIN] = {(float)(log(L1) - ml), (float)((g1 - g2) / L1), (float)log(fabs(b) / bm + 1e-12),
-                            (float)diagH[i]};
-      float h1[H1], h2[H2];
-      ci = softplusf(fwd1(P, x, h1, h2)) + 1e-6f;
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long long nch = (n + 63) / 64;
+  for (long long ch = blockIdx.x * (long long)kNetWaves + wv; ch < nch; ch += (long long)gridDim.x * kNetWaves) {
+    const long long i = ch * 64 + l;
+    float x[NIN] = {0.0f, 0.0f, 0.0f, 0.0f};
+    bool act = false;
+    if (i < n) {
+      const double b = beta[i];
+      const double g1 = nu1[i] / (z[i] + b), g2 = nu2[i] / (z[i] - b);
+      const double L1 = g1 + g2;
+      act = L1 >= rmin * (L1 + 4.0 * g1 * g2);
+      x[0] = (float)(log(L1) - ml);
+      x[1] = (float)((g1 - g2) / L1);
+      x[2] = (float)log(fabs(b) / bm + 1e-12);
+      x[3] = (float)diagH[i];
     }
-    c[i] = ci;
+    const unsigned long long am = __ballot(act);
+    float o = 0.0f;
+    if (am) o = net_chunk(w, lds[wv], x, am);
+    if (i < n) c[i] = act ? softplusf(o) + 1e-6f : 1.0f;
   }
 }
 
@@ -349,6 +473,15 @@ k_scale_weights(float* __restrict__ rec, int npick, float f) {
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < npick; j += gridDim.x * blockDim.x) rec[j * MLP_REC + 5] *= f;
 }
 
+// inference grid: one 64-coefficient chunk per wave and round, at most
+// 2560 workgroups (10 per compute unit)
+int net_blocks(long long n) {
+  long long b = ((n + 63) / 64 + kNetWaves - 1) / kNetWaves;
+  if (b > 2560) b = 2560;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
 int blocks_for(long long n) {
   long long b = (n + 255) / 256;
   if (b > 4096) b = 4096;
@@ -379,18 +512,22 @@ void mlp_features_state(const double* beta, const double* z, const double* nu1, 
                      bmax, feat, n);
 }
 
-void mlp_correction_state(const double* beta, const double* z, const double* nu1, const double* nu2,
-                          const double* diagH, const double* bmax, const float* params, float* c, long long n,
-                          double* partial, double* meanlog, double rmin, hipStream_t s) {
+void mlp_mean_log_l1_state(const double* beta, const double* z, const double* nu1, const double* nu2, long long n,
+                           double* partial, double* meanlog, hipStream_t s) {
   const int nb = blocks_for(n);
   hipLaunchKernelGGL(k_log_l1_state, dim3(nb), dim3(256), 0, s, beta, z, nu1, nu2, n, partial);
   hipLaunchKernelGGL(k_fin_mean, dim3(1), dim3(256), 0, s, partial, nb, 1.0 / (double)n, meanlog);
-  hipLaunchKernelGGL(k_correction_state, dim3(nb), dim3(256), 0, s, beta, z, nu1, nu2, diagH,
-                     (const double*)meanlog, bmax, params, c, n, rmin);
+}
+
+void mlp_correction_state(const double* beta, const double* z, const double* nu1, const double* nu2,
+                          const double* diagH, const double* meanlog, const double* bmax, const float* params,
+                          float* c, long long n, double rmin, hipStream_t s) {
+  hipLaunchKernelGGL(k_correction_state, dim3(net_blocks(n)), dim3(64 * kNetWaves), 0, s, beta, z, nu1, nu2, diagH,
+                     meanlog, bmax, params, c, n, rmin);
 }
 
 void mlp_forward(const float* params, const float* feat, float* c, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_forward, dim3(blocks_for(n)), dim3(256), 0, s, params, feat, c, n);
+  hipLaunchKernelGGL(k_forward, dim3(net_blocks(n)), dim3(64 * kNetWaves), 0, s, params, feat, c, n);
 }
 
 void mlp_backward(const float* params, const float* feat, const float* dc, float* grad, int n, double* scratch,

@@ -39,22 +39,16 @@ enum FlagSlot { F_DONE = 0, F_IT = 1, F_MAXIT = 2, F_BREAK = 3, F_COUNT = 8 };
 int vec_blocks(long long n);
 
 template <typename T>
-void cg_init(const T* hb, const T* hz, T* xb, T* xz, T* rb, T* rz, T* zb, T* zz, T* pb, T* pz, const T* s1,
-             const T* s2, const float* c, long long n, double* partial, hipStream_t s);
-template <typename T>
 void cg_update(T* xb, T* xz, const T* pb, const T* pz, const T* qb, const T* qz, T* rb, T* rz, T* zb, T* zz,
                const T* s1, const T* s2, const float* c, const double* scal, const int* flags, long long n,
                double* partial, bool first, hipStream_t s);
 template <typename T>
 void cg_pupdate(T* pb, T* pz, const T* zb, const T* zz, const double* scal, const int* flags, long long n,
                 hipStream_t s);
-void fin_cg_init(const double* partial, int nb, double* scal, int* flags, double eta, double atol, int maxit,
-                 hipStream_t s);
 // rz0 from partial quantity 0 (or scal[from_slot] when >= 0); quantity 1
 // (at partial + stride) summed into scal[ref_slot] when ref_slot >= 0
 void fin_cg_start(const double* partial, int nb, int stride, double* scal, int* flags, double eta, double atol,
                   int maxit, int ref_slot, int from_slot, hipStream_t s);
-void fin_two(const double* partial, int nb, int stride, double* scal, int s0, int s1, hipStream_t s);
 template <typename TC>
 void newton_init(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
                  const double* xi, double lam, double smu, double* sig1, double* sig2, double* hb_out,
@@ -64,27 +58,30 @@ void set_f2d(double* db, double* dz, const float* eb, const float* ez, long long
 void fin_alpha(const double* partial, int nb, double* scal, int* flags, hipStream_t s);
 void fin_rz(const double* partial, int nb, double* scal, int* flags, hipStream_t s);
 
-void ipm_init(double* beta, double* z, double* nu1, double* nu2, long long n, double z0, double lam,
+// beta = 0, z = z0, nu = lam/2, and H beta = 0
+void ipm_init(double* beta, double* z, double* nu1, double* nu2, double* hbeta, long long n, double z0, double lam,
               hipStream_t s);
+// residual parts of the iterate from a given H beta -> out7 (k_ipm_resid order)
 void ipm_resid(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
                const double* xi, double lam, long long n, double* partial, double* out7, hipStream_t s);
-template <typename T>
-void ipm_newton(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
-                const double* xi, double lam, double smu, double* sig1, double* sig2, double* rb, double* rz,
-                T* sig1f, T* sig2f, long long n, hipStream_t s);
-void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* sig1,
-              const double* sig2, const double* db, const double* dz, double smu, double tau, long long n,
-              double* partial, double* scal, hipStream_t s);
-void ipm_update(double* beta, double* z, double* nu1, double* nu2, const double* sig1, const double* sig2,
-                const double* db, const double* dz, double smu, const double* scal, long long n, hipStream_t s);
+// step length: scal[S_AMAX] and scal[S_ALPHA_IPM] = min(1, tau * S_AMAX)
+void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* db,
+              const double* dz, double smu, double tau, long long n, double* partial, double* scal, hipStream_t s);
+// iterate update with H beta carried along (H d_beta from hd when set, else
+// from the Krylov residual: rres32 when set, else rres), and the new residual
+// parts -> scal[S_RESID..]
+void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* xi,
+                 const double* db, const double* dz, const double* hd, const double* rres, const float* rres32,
+                 double lam, double smu, double* scal, long long n, double* partial, hipStream_t s);
 
-void cast_d2f(const double* a, const double* b, float* oa, float* ob, long long n, hipStream_t s);
-void cast_f2d(const float* a, const float* b, double* oa, double* ob, long long n, hipStream_t s);
-void copy2(const double* a, const double* b, double* oa, double* ob, long long n, hipStream_t s);
 void add_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s);
-void ref_resid(const double* hb, const double* hz, const double* qb, const double* qz, double* rb, double* rz,
-               const double* s1, const double* s2, const float* c, long long n, double* partial, double* out,
-               hipStream_t s);
+// FP32 restart of a further inner solve from H d_beta (hd): r32, z32 = p32 =
+// P_c^{-1} r and the sum r32.z32 -> *out (device)
+void ref_restart(const double* hb, const double* hz, const double* db, const double* dz, const double* hd,
+                 const double* s1, const double* s2, const float* c, float* frb, float* frz, float* fzb, float* fzz,
+                 float* fpb, float* fpz, long long n, double* partial, double* out, hipStream_t s);
+// *out = sum of partial[0..nb)
+void fin_sum(const double* partial, int nb, double* out, hipStream_t s);
 template <typename T>
 void pinv_apply(const T* rb, const T* rz, T* zb, T* zz, const T* s1, const T* s2, const float* c, long long n,
                 double* partial, double* out, hipStream_t s);

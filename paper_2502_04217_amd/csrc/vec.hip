@@ -80,31 +80,6 @@ __device__ __forceinline__ long long gstride() { return (long long)gridDim.x * b
 #define CSIPM_ALIGN(p) p = (decltype(p))__builtin_assume_aligned(p, 2 * sizeof(*(p)))
 
 // ------------------------------------------------------------------- PCG --
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_cg_init(const T* __restrict__ hb, const T* __restrict__ hz, T* __restrict__ xb, T* __restrict__ xz,
-          T* __restrict__ rb, T* __restrict__ rz, T* __restrict__ zb, T* __restrict__ zz, T* __restrict__ pb,
-          T* __restrict__ pz, const T* __restrict__ s1, const T* __restrict__ s2, const float* __restrict__ c,
-          long long n, double* partial) {
-  double acc = 0.0;
-  for (long long i = gtid(); i < n; i += gstride()) {
-    const T b = hb[i], z = hz[i];
-    T ub, uz;
-    pinv1<T>(b, z, s1[i], s2[i], c ? (double)c[i] : 1.0, ub, uz);
-    xb[i] = T(0);
-    xz[i] = T(0);
-    rb[i] = b;
-    rz[i] = z;
-    zb[i] = ub;
-    zz[i] = uz;
-    pb[i] = ub;
-    pz[i] = uz;
-    acc += (double)b * (double)ub + (double)z * (double)uz;
-  }
-  const int op = RED_SUM;
-  block_reduce_store<1>(&acc, &op, partial, 0);
-}
-
 // x += alpha p (x = alpha p on the first iteration: x0 = 0 is never stored),
 // r -= alpha q, z = P_c^{-1} r, partial r.z.  A first iteration of a solve
 // that finished at initialisation writes x = 0 and nothing else.
@@ -223,17 +198,6 @@ k_fin_cg_init(const double* partial, int nb, int stride, double* scal, int* flag
   }
 }
 
-// Two sums of the refinement-residual epilogue into scal[s0], scal[s1].
-__global__ void __launch_bounds__(256)
-k_fin_two(const double* partial, int nb, int stride, double* scal, int s0, int s1) {
-  const double a = fin_sum(partial, nb);
-  const double b = fin_sum(partial + stride, nb);
-  if (threadIdx.x == 0) {
-    scal[s0] = a;
-    scal[s1] = b;
-  }
-}
-
 __global__ void __launch_bounds__(256)
 k_fin_alpha(const double* partial, int nb, double* scal, int* flags) {
   if (flags[F_DONE]) return;
@@ -269,9 +233,10 @@ k_fin_rz(const double* partial, int nb, double* scal, int* flags) {
 // ------------------------------------------------------------------- IPM --
 __global__ void __launch_bounds__(256)
 k_ipm_init(double* __restrict__ beta, double* __restrict__ z, double* __restrict__ nu1, double* __restrict__ nu2,
-           long long n, double z0, double lam) {
+           double* __restrict__ hbeta, long long n, double z0, double lam) {
   for (long long i = gtid(); i < n; i += gstride()) {
     beta[i] = 0.0;
+    hbeta[i] = 0.0;
     z[i] = z0;
     nu1[i] = 0.5 * lam;
     nu2[i] = 0.5 * lam;
@@ -309,32 +274,6 @@ k_ipm_resid(const double* __restrict__ beta, const double* __restrict__ z, const
   }
   const int ops[7] = {RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM};
   block_reduce_store<7>(v, ops, partial, stride);
-}
-
-// Newton system of one iteration: barrier diagonals and the right-hand side
-//   r_beta = -(H beta - xi) + smu (1/s1 - 1/s2),  r_z = -lam + smu (1/s1 + 1/s2)
-// (derived from equation "kktmu"), smu = sigma * mu.
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_ipm_newton(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
-             const double* __restrict__ nu2, const double* __restrict__ hb, const double* __restrict__ xi,
-             double lam, double smu, double* __restrict__ sig1, double* __restrict__ sig2,
-             double* __restrict__ rb, double* __restrict__ rz, T* __restrict__ sig1f, T* __restrict__ sig2f,
-             long long n) {
-  for (long long i = gtid(); i < n; i += gstride()) {
-    const double b = beta[i], zz = z[i];
-    const double s1 = zz + b, s2 = zz - b;
-    const double i1 = 1.0 / s1, i2 = 1.0 / s2;
-    const double g1 = nu1[i] * i1, g2 = nu2[i] * i2;
-    sig1[i] = g1;
-    sig2[i] = g2;
-    rb[i] = -(hb[i] - xi[i]) + smu * (i1 - i2);
-    rz[i] = -lam + smu * (i1 + i2);
-    if (sig1f) {
-      sig1f[i] = (T)g1;
-      sig2f[i] = (T)g2;
-    }
-  }
 }
 
 // Newton system and PCG start in one pass: Sigma_j = nu_j / s_j (FP64, and
@@ -422,39 +361,48 @@ k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, con
   block_reduce_store<2>(acc, ops, partial, VEC_MAX_BLOCKS);
 }
 
-// Largest step keeping s and nu positive, with
+// Search direction of the multipliers at one coefficient, with the barrier
+// diagonals re-formed from the state exactly as the Newton build forms them:
+//   s1 = z + beta, s2 = z - beta, Sigma_j = nu_j / s_j,
 //   ds1 = db + dz, ds2 = dz - db, dnu_j = smu/s_j - nu_j - Sigma_j ds_j.
+struct IpmDir {
+  double s1, s2, i1, i2, g1, g2, ds1, ds2, dn1, dn2;
+};
+__device__ __forceinline__ IpmDir ipm_dir(double b, double zz, double a1, double a2, double d1, double d2,
+                                          double smu) {
+  IpmDir o;
+  o.s1 = zz + b;
+  o.s2 = zz - b;
+  o.i1 = 1.0 / o.s1;
+  o.i2 = 1.0 / o.s2;
+  o.g1 = a1 * o.i1;
+  o.g2 = a2 * o.i2;
+  o.ds1 = d1 + d2;
+  o.ds2 = d2 - d1;
+  o.dn1 = smu * o.i1 - a1 - o.g1 * o.ds1;
+  o.dn2 = smu * o.i2 - a2 - o.g2 * o.ds2;
+  return o;
+}
+
+// Largest step keeping s and nu positive along (db, dz, dnu1, dnu2).
 __global__ void __launch_bounds__(256)
 k_ipm_ratio(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
-            const double* __restrict__ nu2, const double* __restrict__ sig1, const double* __restrict__ sig2,
-            const double* __restrict__ db, const double* __restrict__ dz, double smu, long long n,
-            double* partial) {
-  CSIPM_ALIGN(beta);
-  CSIPM_ALIGN(z);
-  CSIPM_ALIGN(nu1);
-  CSIPM_ALIGN(nu2);
-  CSIPM_ALIGN(sig1);
-  CSIPM_ALIGN(sig2);
-  CSIPM_ALIGN(db);
-  CSIPM_ALIGN(dz);
-
+            const double* __restrict__ nu2, const double* __restrict__ db, const double* __restrict__ dz,
+            double smu, long long n, double* partial) {
   double amax = INFINITY;
   using D2 = cx<double>;
   for (long long j = gtid(); j < n / 2; j += gstride()) {
     const D2 b2 = ((const D2*)beta)[j], z2 = ((const D2*)z)[j], a1 = ((const D2*)nu1)[j], a2 = ((const D2*)nu2)[j],
-             g1 = ((const D2*)sig1)[j], g2 = ((const D2*)sig2)[j], d1 = ((const D2*)db)[j], d2 = ((const D2*)dz)[j];
+             d1 = ((const D2*)db)[j], d2 = ((const D2*)dz)[j];
     const double bb[2] = {b2.re, b2.im}, zv[2] = {z2.re, z2.im}, n1[2] = {a1.re, a1.im}, n2[2] = {a2.re, a2.im},
-                 s1v[2] = {g1.re, g1.im}, s2v[2] = {g2.re, g2.im}, dbv[2] = {d1.re, d1.im}, dzv[2] = {d2.re, d2.im};
+                 dbv[2] = {d1.re, d1.im}, dzv[2] = {d2.re, d2.im};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const double s1 = zv[k] + bb[k], s2 = zv[k] - bb[k];
-      const double ds1 = dbv[k] + dzv[k], ds2 = dzv[k] - dbv[k];
-      const double dn1 = smu / s1 - n1[k] - s1v[k] * ds1;
-      const double dn2 = smu / s2 - n2[k] - s2v[k] * ds2;
-      if (ds1 < 0.0) amax = fmin(amax, -s1 / ds1);
-      if (ds2 < 0.0) amax = fmin(amax, -s2 / ds2);
-      if (dn1 < 0.0) amax = fmin(amax, -n1[k] / dn1);
-      if (dn2 < 0.0) amax = fmin(amax, -n2[k] / dn2);
+      const IpmDir d = ipm_dir(bb[k], zv[k], n1[k], n2[k], dbv[k], dzv[k], smu);
+      if (d.ds1 < 0.0) amax = fmin(amax, -d.s1 / d.ds1);
+      if (d.ds2 < 0.0) amax = fmin(amax, -d.s2 / d.ds2);
+      if (d.dn1 < 0.0) amax = fmin(amax, -n1[k] / d.dn1);
+      if (d.dn2 < 0.0) amax = fmin(amax, -n2[k] / d.dn2);
     }
   }
   const int op = RED_MIN;
@@ -476,31 +424,73 @@ k_fin_step(const double* partial, int nb, double tau, double* scal) {
   }
 }
 
+// Step of the interior-point iterate by alpha = scal[S_ALPHA_IPM], with H beta
+// carried along instead of recomputed: H beta += alpha H d_beta, where H d_beta
+// is either given (hd, from the FP64 residual pass of the refinement) or
+// recovered from the Krylov residual r = h - K d of the Newton system (rres in
+// FP64, or rres32 from an FP32 solve taken without refinement),
+//   H d_beta = h_beta - r_beta - Sigma_1 (d_beta + d_z) - Sigma_2 (d_beta - d_z)
+// (the beta row of K in Sigma form).  The same pass reduces the residual parts
+// of the new iterate in k_ipm_resid's order.
 __global__ void __launch_bounds__(256)
-k_ipm_update(double* __restrict__ beta, double* __restrict__ z, double* __restrict__ nu1, double* __restrict__ nu2,
-             const double* __restrict__ sig1, const double* __restrict__ sig2, const double* __restrict__ db,
-             const double* __restrict__ dz, double smu, const double* __restrict__ scal, long long n) {
-  CSIPM_ALIGN(beta);
-  CSIPM_ALIGN(z);
-  CSIPM_ALIGN(nu1);
-  CSIPM_ALIGN(nu2);
-  CSIPM_ALIGN(sig1);
-  CSIPM_ALIGN(sig2);
-  CSIPM_ALIGN(db);
-  CSIPM_ALIGN(dz);
-
+k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restrict__ nu1, double* __restrict__ nu2,
+              double* __restrict__ hbeta, const double* __restrict__ xi, const double* __restrict__ db,
+              const double* __restrict__ dz, const double* __restrict__ hd, const double* __restrict__ rres,
+              const float* __restrict__ rres32, double lam, double smu, const double* __restrict__ scal, long long n,
+              double* partial, int stride) {
   const double a = scal[S_ALPHA_IPM];
-  CSIPM_PAIRS(n) {
-    const double b = beta[i], zz = z[i];
-    const double s1 = zz + b, s2 = zz - b;
-    const double ds1 = db[i] + dz[i], ds2 = dz[i] - db[i];
-    const double dn1 = smu / s1 - nu1[i] - sig1[i] * ds1;
-    const double dn2 = smu / s2 - nu2[i] - sig2[i] * ds2;
-    beta[i] = b + a * db[i];
-    z[i] = zz + a * dz[i];
-    nu1[i] += a * dn1;
-    nu2[i] += a * dn2;
+  double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0};
+  using D2 = cx<double>;
+  D2 *BE = (D2*)beta, *ZV = (D2*)z, *N1 = (D2*)nu1, *N2 = (D2*)nu2, *HBV = (D2*)hbeta;
+  const D2 *XI = (const D2*)xi, *DB = (const D2*)db, *DZ = (const D2*)dz, *W = (const D2*)(hd ? hd : rres);
+  const float2* W32 = (const float2*)rres32;
+  for (long long j = gtid(); j < n / 2; j += gstride()) {
+    const D2 b2 = BE[j], z2 = ZV[j], a1 = N1[j], a2 = N2[j], h2 = HBV[j], x2 = XI[j], d1 = DB[j], d2 = DZ[j];
+    D2 w2;
+    if (W32) {
+      const float2 f = W32[j];
+      w2 = {(double)f.x, (double)f.y};
+    } else {
+      w2 = W[j];
+    }
+    const double bb[2] = {b2.re, b2.im}, zv[2] = {z2.re, z2.im}, n1[2] = {a1.re, a1.im}, n2[2] = {a2.re, a2.im},
+                 hv[2] = {h2.re, h2.im}, xv[2] = {x2.re, x2.im}, dbv[2] = {d1.re, d1.im},
+                 dzv[2] = {d2.re, d2.im}, wv[2] = {w2.re, w2.im};
+    double bo[2], zo[2], n1o[2], n2o[2], ho[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const IpmDir d = ipm_dir(bb[k], zv[k], n1[k], n2[k], dbv[k], dzv[k], smu);
+      double u;
+      if (hd) {
+        u = wv[k];
+      } else {
+        const double hrhs = -(hv[k] - xv[k]) + smu * (d.i1 - d.i2);
+        u = (hrhs - wv[k]) - (d.g1 * (dbv[k] + dzv[k]) + d.g2 * (dbv[k] - dzv[k]));
+      }
+      const double b = bb[k] + a * dbv[k], zz = zv[k] + a * dzv[k];
+      const double m1 = n1[k] + a * d.dn1, m2 = n2[k] + a * d.dn2;
+      const double hb = hv[k] + a * u;
+      bo[k] = b; zo[k] = zz; n1o[k] = m1; n2o[k] = m2; ho[k] = hb;
+      const double s1 = zz + b, s2 = zz - b;
+      const double fb = hb - xv[k] - m1 + m2;
+      const double fz = lam - m1 - m2;
+      const double c1 = s1 * m1, c2 = s2 * m2;
+      v[0] = fmax(v[0], fabs(fb));
+      v[1] = fmax(v[1], fabs(fz));
+      v[2] = fmax(v[2], fmax(c1, c2));
+      v[3] += c1 + c2;
+      v[4] = fmax(v[4], fabs(b));
+      v[5] = fmin(v[5], fmin(fmin(s1, s2), fmin(m1, m2)));
+      if (!isfinite(fb) || !isfinite(c1) || !isfinite(c2)) v[6] += 1.0;
+    }
+    BE[j] = {bo[0], bo[1]};
+    ZV[j] = {zo[0], zo[1]};
+    N1[j] = {n1o[0], n1o[1]};
+    N2[j] = {n2o[0], n2o[1]};
+    HBV[j] = {ho[0], ho[1]};
   }
+  const int ops[7] = {RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM};
+  block_reduce_store<7>(v, ops, partial, stride);
 }
 
 // Generic multi-value finalize: out[q] = op_q over partial[q*stride + 0..nb);
@@ -535,15 +525,6 @@ k_fin_reduce(const double* partial, int nb, int stride, double* out, RedOps<NQ> 
 }
 
 // ------------------------------------------------- mixed precision glue --
-template <typename Ti, typename To>
-__global__ void __launch_bounds__(256)
-k_cast2(const Ti* __restrict__ a, const Ti* __restrict__ b, To* __restrict__ oa, To* __restrict__ ob, long long n) {
-  for (long long i = gtid(); i < n; i += gstride()) {
-    oa[i] = (To)a[i];
-    ob[i] = (To)b[i];
-  }
-}
-
 __global__ void __launch_bounds__(256)
 k_set_f2d(double* __restrict__ db, double* __restrict__ dz, const float* __restrict__ eb,
           const float* __restrict__ ez, long long n) {
@@ -572,20 +553,43 @@ k_add_f2d(double* __restrict__ db, double* __restrict__ dz, const float* __restr
   }
 }
 
-// r = h - q and partial sums of r.P^{-1}r (FP64 refinement residual).
+// FP32 start of a further inner solve of the refinement, elementwise from
+// the residual pass's H d_beta: r = h - K d (FP64, K in Sigma form), r32 = r,
+// z32 = p32 = P_c^{-1} r (formed in FP64), partial sums of r32.z32.
 __global__ void __launch_bounds__(256)
-k_ref_resid(const double* __restrict__ hb, const double* __restrict__ hz, const double* __restrict__ qb,
-            const double* __restrict__ qz, double* __restrict__ rb, double* __restrict__ rz,
-            const double* __restrict__ s1, const double* __restrict__ s2, const float* __restrict__ c,
-            long long n, double* partial) {
+k_ref_restart(const double* __restrict__ hb, const double* __restrict__ hz, const double* __restrict__ db,
+              const double* __restrict__ dz, const double* __restrict__ hd, const double* __restrict__ s1,
+              const double* __restrict__ s2, const float* __restrict__ c, float* __restrict__ frb,
+              float* __restrict__ frz, float* __restrict__ fzb, float* __restrict__ fzz, float* __restrict__ fpb,
+              float* __restrict__ fpz, long long n, double* partial) {
+  CSIPM_ALIGN(hb);
+  CSIPM_ALIGN(hz);
+  CSIPM_ALIGN(db);
+  CSIPM_ALIGN(dz);
+  CSIPM_ALIGN(hd);
+  CSIPM_ALIGN(s1);
+  CSIPM_ALIGN(s2);
+  CSIPM_ALIGN(frb);
+  CSIPM_ALIGN(frz);
+  CSIPM_ALIGN(fzb);
+  CSIPM_ALIGN(fzz);
+  CSIPM_ALIGN(fpb);
+  CSIPM_ALIGN(fpz);
+
   double acc = 0.0;
-  for (long long i = gtid(); i < n; i += gstride()) {
-    const double b = hb[i] - qb[i], z = hz[i] - qz[i];
-    rb[i] = b;
-    rz[i] = z;
-    double ub, uz;
-    pinv1<double>(b, z, s1[i], s2[i], c ? (double)c[i] : 1.0, ub, uz);
-    acc += b * ub + z * uz;
+  CSIPM_PAIRS(n) {
+    double qb, qz, zb, zz;
+    k_block<double>(hd[i], db[i], dz[i], s1[i], s2[i], qb, qz);
+    const double rb = hb[i] - qb, rz = hz[i] - qz;
+    pinv_block<double>(rb, rz, s1[i], s2[i], c ? (double)c[i] : 1.0, zb, zz);
+    const float fb = (float)rb, fz = (float)rz, gb = (float)zb, gz = (float)zz;
+    frb[i] = fb;
+    frz[i] = fz;
+    fzb[i] = gb;
+    fzz[i] = gz;
+    fpb[i] = gb;
+    fpz[i] = gz;
+    acc += (double)fb * (double)gb + (double)fz * (double)gz;
   }
   const int op = RED_SUM;
   block_reduce_store<1>(&acc, &op, partial, 0);
@@ -700,11 +704,6 @@ int vec_blocks(long long n) {
 #define VB dim3(vec_blocks(n)), dim3(256), 0, s
 
 template <typename T>
-void cg_init(const T* hb, const T* hz, T* xb, T* xz, T* rb, T* rz, T* zb, T* zz, T* pb, T* pz, const T* s1,
-             const T* s2, const float* c, long long n, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_init<T>), VB, hb, hz, xb, xz, rb, rz, zb, zz, pb, pz, s1, s2, c, n, partial);
-}
-template <typename T>
 void cg_update(T* xb, T* xz, const T* pb, const T* pz, const T* qb, const T* qz, T* rb, T* rz, T* zb, T* zz,
                const T* s1, const T* s2, const float* c, const double* scal, const int* flags, long long n,
                double* partial, bool first, hipStream_t s) {
@@ -716,17 +715,10 @@ void cg_pupdate(T* pb, T* pz, const T* zb, const T* zz, const double* scal, cons
                 hipStream_t s) {
   hipLaunchKernelGGL((k_cg_pupdate<T>), VB, pb, pz, zb, zz, scal, flags, n);
 }
-void fin_cg_init(const double* partial, int nb, double* scal, int* flags, double eta, double atol, int maxit,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_cg_init, dim3(1), dim3(256), 0, s, partial, nb, 0, scal, flags, eta, atol, maxit, -1, -1);
-}
 void fin_cg_start(const double* partial, int nb, int stride, double* scal, int* flags, double eta, double atol,
                   int maxit, int ref_slot, int from_slot, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_cg_init, dim3(1), dim3(256), 0, s, partial, nb, stride, scal, flags, eta, atol, maxit,
                      ref_slot, from_slot);
-}
-void fin_two(const double* partial, int nb, int stride, double* scal, int s0, int s1, hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_two, dim3(1), dim3(256), 0, s, partial, nb, stride, scal, s0, s1);
 }
 template <typename TC>
 void newton_init(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
@@ -745,9 +737,9 @@ void fin_alpha(const double* partial, int nb, double* scal, int* flags, hipStrea
 void fin_rz(const double* partial, int nb, double* scal, int* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(256), 0, s, partial, nb, scal, flags);
 }
-void ipm_init(double* beta, double* z, double* nu1, double* nu2, long long n, double z0, double lam,
+void ipm_init(double* beta, double* z, double* nu1, double* nu2, double* hbeta, long long n, double z0, double lam,
               hipStream_t s) {
-  hipLaunchKernelGGL(k_ipm_init, VB, beta, z, nu1, nu2, n, z0, lam);
+  hipLaunchKernelGGL(k_ipm_init, VB, beta, z, nu1, nu2, hbeta, n, z0, lam);
 }
 void ipm_resid(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
                const double* xi, double lam, long long n, double* partial, double* out7, hipStream_t s) {
@@ -757,41 +749,33 @@ void ipm_resid(const double* beta, const double* z, const double* nu1, const dou
   hipLaunchKernelGGL((k_fin_reduce<7>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out7,
                      ops);
 }
-template <typename T>
-void ipm_newton(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
-                const double* xi, double lam, double smu, double* sig1, double* sig2, double* rb, double* rz,
-                T* sig1f, T* sig2f, long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_ipm_newton<T>), VB, beta, z, nu1, nu2, hb, xi, lam, smu, sig1, sig2, rb, rz, sig1f,
-                     sig2f, n);
-}
-void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* sig1,
-              const double* sig2, const double* db, const double* dz, double smu, double tau, long long n,
-              double* partial, double* scal, hipStream_t s) {
+void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* db,
+              const double* dz, double smu, double tau, long long n, double* partial, double* scal, hipStream_t s) {
   const int nb = vec_blocks(n);
-  hipLaunchKernelGGL(k_ipm_ratio, VB, beta, z, nu1, nu2, sig1, sig2, db, dz, smu, n, partial);
+  hipLaunchKernelGGL(k_ipm_ratio, VB, beta, z, nu1, nu2, db, dz, smu, n, partial);
   hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(256), 0, s, partial, nb, tau, scal);
 }
-void ipm_update(double* beta, double* z, double* nu1, double* nu2, const double* sig1, const double* sig2,
-                const double* db, const double* dz, double smu, const double* scal, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_ipm_update, VB, beta, z, nu1, nu2, sig1, sig2, db, dz, smu, scal, n);
-}
-void cast_d2f(const double* a, const double* b, float* oa, float* ob, long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_cast2<double, float>), VB, a, b, oa, ob, n);
-}
-void cast_f2d(const float* a, const float* b, double* oa, double* ob, long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_cast2<float, double>), VB, a, b, oa, ob, n);
-}
-void copy2(const double* a, const double* b, double* oa, double* ob, long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_cast2<double, double>), VB, a, b, oa, ob, n);
+void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* xi,
+                 const double* db, const double* dz, const double* hd, const double* rres, const float* rres32,
+                 double lam, double smu, double* scal, long long n, double* partial, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_ipm_advance, VB, beta, z, nu1, nu2, hbeta, xi, db, dz, hd, rres, rres32, lam, smu, scal, n,
+                     partial, VEC_MAX_BLOCKS);
+  RedOps<7> ops{{RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM}};
+  hipLaunchKernelGGL((k_fin_reduce<7>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, scal + S_RESID,
+                     ops);
 }
 void add_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_add_f2d, VB, db, dz, eb, ez, n);
 }
-void ref_resid(const double* hb, const double* hz, const double* qb, const double* qz, double* rb, double* rz,
-               const double* s1, const double* s2, const float* c, long long n, double* partial, double* out,
-               hipStream_t s) {
+void ref_restart(const double* hb, const double* hz, const double* db, const double* dz, const double* hd,
+                 const double* s1, const double* s2, const float* c, float* frb, float* frz, float* fzb, float* fzz,
+                 float* fpb, float* fpz, long long n, double* partial, double* out, hipStream_t s) {
   const int nb = vec_blocks(n);
-  hipLaunchKernelGGL(k_ref_resid, VB, hb, hz, qb, qz, rb, rz, s1, s2, c, n, partial);
+  hipLaunchKernelGGL(k_ref_restart, VB, hb, hz, db, dz, hd, s1, s2, c, frb, frz, fzb, fzz, fpb, fpz, n, partial);
+  fin_sum(partial, nb, out, s);
+}
+void fin_sum(const double* partial, int nb, double* out, hipStream_t s) {
   RedOps<1> ops{{RED_SUM}};
   hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out, ops);
 }
@@ -836,8 +820,6 @@ void diag_h(const double* bm_ext, double* out_ext, int n1, int n2, int n3, doubl
 #undef VB
 
 #define CSIPM_VINST(T)                                                                                         \
-  template void cg_init<T>(const T*, const T*, T*, T*, T*, T*, T*, T*, T*, T*, const T*, const T*, const float*, \
-                           long long, double*, hipStream_t);                                                   \
   template void cg_update<T>(T*, T*, const T*, const T*, const T*, const T*, T*, T*, T*, T*, const T*,         \
                              const T*, const float*, const double*, const int*, long long, double*, bool,      \
                              hipStream_t);                                                                     \
@@ -845,9 +827,6 @@ void diag_h(const double* bm_ext, double* out_ext, int n1, int n2, int n3, doubl
                                const double*, double, double, double*, double*, double*, double*, T*, T*,      \
                                const float*, T*, T*, T*, T*, T*, T*, long long, double*, hipStream_t);         \
   template void cg_pupdate<T>(T*, T*, const T*, const T*, const double*, const int*, long long, hipStream_t);  \
-  template void ipm_newton<T>(const double*, const double*, const double*, const double*, const double*,      \
-                              const double*, double, double, double*, double*, double*, double*, T*, T*,       \
-                              long long, hipStream_t);                                                         \
   template void pinv_apply<T>(const T*, const T*, T*, T*, const T*, const T*, const float*, long long,        \
                               double*, double*, hipStream_t);                                                  \
   template void fill<T>(T*, T, long long, hipStream_t);

@@ -86,6 +86,9 @@ def main(argv=None):
     ap.add_argument("--fetch-db")
     ap.add_argument("--write-db")
     ap.add_argument("--calib-bytes", type=int, default=1 << 30)
+    ap.add_argument("--record", nargs=3, metavar=("KERNEL", "NAME", "GRID"),
+                    help="print a traffic-record line for the rocprof kernel KERNEL (short name), timed as NAME "
+                         "by csipm_timing, at GRID^3, stamped with the current kernel-source digest")
     a = ap.parse_args(argv)
     if a.fetch_db and a.write_db:
         tr, (ff, fw) = calibrated_traffic(a.fetch_db, a.write_db, a.calib_bytes)
@@ -94,6 +97,15 @@ def main(argv=None):
             fe, wr = tr[k]
             if fe + wr > 1e6:
                 print(f"{k[:60]:60s} read {fe / 1e6:10.2f} MB  write {wr / 1e6:10.2f} MB")
+        if a.record:
+            import json
+            from .build import source_digest
+            kern, name, grid = a.record
+            fe, wr = tr[kern]
+            print("traffic-record: " + json.dumps({"kernel": name, "rocprof_kernel": kern, "grid": int(grid),
+                                                   "read_bytes": round(fe), "write_bytes": round(wr),
+                                                   "fetch_factor": round(ff, 4), "write_factor": round(fw, 4),
+                                                   "source_sha256": source_digest()}))
     out, counters, total_us = summarize(a.db, a.top, a.min_us)
     print(f"# kernel time total {total_us:.1f} us; working = dispatches >= {a.min_us} us")
     print(f"{'kernel':60s} {'calls':>6s} {'total_us':>11s} {'avg_us':>9s} {'pct':>6s} {'work':>5s} {'work_avg_us':>11s}")

@@ -55,13 +55,20 @@ def test_grid16_parity(seed, precision):
     assert ok
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_grid64_parity(precision):
+@pytest.mark.parametrize("precision,trust", [(0, 1e-4), (1, 1e-4), (1, 0.0)])
+def test_grid64_parity(precision, trust):
+    """trust = 0: every FP32 Newton system is refined in FP64; 1e-4 (default):
+    systems with tolerance >= 1e-4 take the FP32 solution unrefined."""
     w = wl.grid64(1)
     lam = ipm.lambda_rule(w.signal, w.observed)
-    say("grid64 parity precision", precision)
+    say("grid64 parity precision", precision, "trust", trust)
     ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=PARITY_TOL))
-    pr, info, beta = _gpu_solve(w, lam, tol=PARITY_TOL, precision=precision)
+    pr, info, beta = _gpu_solve(w, lam, tol=PARITY_TOL, precision=precision, refine_trust=trust)
+    if precision == 1:
+        log = pr.log()
+        unrefined = [r["iter"] for r in log if r["refine_steps"] == 0]
+        say("  unrefined FP32 systems", unrefined)
+        assert (len(unrefined) > 0) == (trust > 0)
     say("  gpu", info["status_name"], info["ipm_iters"], info["cg_iters_total"], info["rel_kkt"],
         "oracle", ref.iters, sum(ref.cg_iters))
     assert info["status"] == 0
@@ -145,3 +152,28 @@ def test_grid256_certificate_fp64_and_fp32():
     say("  certificate", cert.natural_residual, cert.rel_gap, cert.max_offsupport_ratio)
     assert cert.max_offsupport_ratio <= 1.0 + 1e-4
     assert cert.rel_gap <= 1e-4
+
+
+def test_kernel_timing_records():
+    """csipm_timing: one record per launch of the solve, aggregated by kernel
+    name; counts follow the solve's iteration structure; nothing is recorded
+    once timing is off."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid16(2)
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.lambda_rule(0.05)
+    pr.timing(True)
+    info = pr.solve(tol=1e-6, precision=1)
+    rep = pr.timing_report(0.0)
+    pr.timing(False)
+    by = {r["name"]: r for r in rep}
+    say("timing", info, sorted((r["name"], r["calls"]) for r in rep))
+    k = info["ipm_iters"]
+    assert sum(by.get(nm, {"calls": 0})["calls"] for nm in ("newton_init.f32", "newton_init_noh.f32")) == k
+    assert by["ipm_ratio+fin"]["calls"] == k and by["ipm_advance+fin"]["calls"] == k
+    assert by.get("axis1_fwd_R.f64", {"calls": 0})["calls"] == info["refine_steps_total"]
+    assert by["axis1_fwd_K.f32"]["calls"] >= info["cg_iters_total"]
+    assert all(r["total_ms"] > 0 and r["working_calls"] == r["calls"] for r in rep)
+    pr.solve(tol=1e-6, precision=1)
+    assert pr.timing_report(0.0) == rep
