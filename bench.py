@@ -86,9 +86,13 @@ def kernel_bytes(name, shape, learned):
         "cg_pupdate": 6 * n * w,
         # beta, z, nu1, nu2, H beta, xi in; Sigma, PCG start (and h, FP32 Sigma) out
         "newton_init": (112 + c) * n,
-        "newton_init_noh": (96 + c) * n,   # FP32 system taken without refinement: h not stored
+        "newton_init_noh": (80 + c) * n,   # FP32 system taken without refinement: no FP64 h, Sigma
+        # beta, z, nu1, nu2 and the direction (FP64, or FP32 after an unrefined FP32 solve)
         "ipm_ratio+fin": 48 * n,
+        "ipm_ratio_d32+fin": 40 * n,
+        # beta, z, nu1, nu2, H beta, xi, direction, H d_beta source (beta part) in; state and H beta out
         "ipm_advance+fin": 112 * n,
+        "ipm_advance_d32+fin": 100 * n,
         "ipm_resid+fin": 48 * n,
         "set_f2d": 24 * n,
         "add_f2d": 40 * n,
@@ -247,6 +251,15 @@ def main():
     plain_s = (time.perf_counter() - t0) / args.steps
     beta64 = pr.get(csipm.BETA)
     print(f"[bench] plain FP64: {plain_s * 1e3:.1f} ms/solve {infos64[-1]}", file=sys.stderr, flush=True)
+
+    # the FP32 form with the paper's preconditioner: what the learned correction adds or saves
+    fp32_plain = dict(tol=1e-6, precision=csipm.FP32, pc=csipm.PC_PLAIN)
+    pr.solve(**fp32_plain)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos32 = [pr.solve(**fp32_plain) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    fp32_plain_s = (time.perf_counter() - t0) / args.steps
     rel_diff = float((beta_chosen - beta64).norm() / beta64.norm())
 
     # per-kernel event timing of one more solve of each form; the dominant
@@ -277,6 +290,26 @@ def main():
                         "minimum_GBps": (6 * n * wsz + n // 8) / t / 1e9,
                         "per_kernel_ms": dict(zip(PASS_NAMES, [round(v, 5) for v in prof[name]["ms"]]))}
 
+    # learned-correction inference on every coefficient (the network's two
+    # dense layers on the matrix cores): 2 (4*32 + 32*32) MFMA flops per coefficient
+    corr = None
+    if learned:
+        feat = torch.randn((n, 4), dtype=torch.float32, device="cuda")
+        csipm.mlp_forward(params, feat)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            csipm.mlp_forward(params, feat)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = 2 * (4 * 32 + 32 * 32) * n / (ms * 1e-3) / 1e12
+        corr = {"kernel": "k_forward, all n coefficients", "ms": ms, "bound": "alu",
+                "mfma_tflops": tf, "mfma_peak_fp32": 157.3, "mfma_frac": tf / 157.3,
+                "note": "bound by the VALU tanh (exp2 + reciprocal per neuron), not by the matrix cores"}
+        del feat
+
     cpu = None
     if not args.no_cpu_baseline:
         sig1, sig2 = wl.random_barrier(w.shape, 1, spread=3.0)
@@ -306,6 +339,9 @@ def main():
                   "rel_kkt": last["rel_kkt"], "rel_diff_vs_fp64": rel_diff},
         "plain_fp64": {"seconds": plain_s, "ipm_iters": infos64[-1]["ipm_iters"],
                        "cg_iters_total": infos64[-1]["cg_iters_total"], "rel_kkt": infos64[-1]["rel_kkt"]},
+        "fp32_plain_pc": {"seconds": fp32_plain_s, "ipm_iters": infos32[-1]["ipm_iters"],
+                          "cg_iters_total": infos32[-1]["cg_iters_total"], "rel_kkt": infos32[-1]["rel_kkt"]},
+        "correction_inference": corr,
         "setup_seconds": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic,

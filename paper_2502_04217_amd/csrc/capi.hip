@@ -146,7 +146,7 @@ csipm_status sync_scalars(csipm_ctx* c, const char* where) {
 // partial sums of one K-apply: axis-1 forward blocks plus postmix blocks
 size_t k_partials(int n1, int n2, int n3) {
   const Grid g{n1, n2, n3, n3 / 2, (long long)n1 * n2 * n3};
-  return (size_t)std::max(axis12_blocks(g, 1, 16), axis12_blocks(g, 1, 8)) + postmix_blocks(g) + 64;
+  return (size_t)std::max(axis12_blocks(g, 1, 16, -1), axis12_blocks(g, 1, 8, -1)) + postmix_blocks(g) + 64;
 }
 
 size_t layout(Carver& cv, csipm_ctx* c, int n1, int n2, int n3) {
@@ -219,7 +219,7 @@ template <typename T>
 int op_K(csipm_ctx* c, const T* pb, const T* pz, const T* s1, const T* s2, T* qb, T* qz, T* work,
          const int* skip) {
   const Grid& g = c->g;
-  const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>));
+  const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>), -1);
   const int ps = (int)k_partials(g.n1, g.n2, g.n3);
   EpiArgs<T> ka{KArgs<T>{pb, pz, s1, s2, qb, qz}, RArgs{}, c->partK, ps};
   EpiArgs<T> kb = ka;
@@ -238,7 +238,7 @@ int op_K(csipm_ctx* c, const T* pb, const T* pz, const T* s1, const T* s2, T* qb
 // H d_beta (into rb) and sums r.P_c^{-1}r -> scal[S_REF].
 void op_Kr(csipm_ctx* c, const float* pcc) {
   const Grid& g = c->g;
-  const int nb5 = axis12_blocks(g, 1, 16);
+  const int nb5 = axis12_blocks(g, 1, 16, -1);
   const int ps = (int)k_partials(g.n1, g.n2, g.n3);
   // H d_beta goes to rb: the FP64 Krylov vectors are idle in the FP32 form
   RArgs ra{c->dxb, c->dxz, c->sig1, c->sig2, c->rhb, c->rhz, pcc, c->rb};
@@ -268,13 +268,21 @@ void compute_features(csipm_ctx* c) {
 
 // c = softplus(MLP(features)) + 1e-6 where it can act on P_c^{-1}, c = 1
 // elsewhere; features formed from the interior-point state (before the
-// Newton system is built).
-csipm_status learned_correction(csipm_ctx* c) {
-  KT(c, "log_l1+fin",
-     mlp_mean_log_l1_state(c->beta, c->z, c->nu1, c->nu2, c->g.n, c->partV, c->scal + S_MISC + 1, c->s));
+// Newton system is built).  With have_logsum the centring sum of log(S1+S2)
+// is already in scal[S_RESID + 7] (reduced with the residual of this
+// iterate); otherwise it is computed here.
+csipm_status learned_correction(csipm_ctx* c, bool have_logsum) {
+  const double* ml = c->scal + S_RESID + 7;
+  double mscale = 1.0 / (double)c->g.n;
+  if (!have_logsum) {
+    KT(c, "log_l1+fin",
+       mlp_mean_log_l1_state(c->beta, c->z, c->nu1, c->nu2, c->g.n, c->partV, c->scal + S_MISC + 1, c->s));
+    ml = c->scal + S_MISC + 1;
+    mscale = 1.0;
+  }
   KT(c, "correction",
-     mlp_correction_state(c->beta, c->z, c->nu1, c->nu2, c->diagH, c->scal + S_MISC + 1, c->scal + S_RESID + 4,
-                          c->mlp_params, c->pc_c, c->g.n, kPcRelevance, c->s));
+     mlp_correction_state(c->beta, c->z, c->nu1, c->nu2, c->diagH, ml, mscale, c->scal + S_RESID + 4, c->mlp_params,
+                          c->pc_c, c->g.n, kPcRelevance, c->s));
   return hip_check(c, "learned_correction");
 }
 
@@ -524,9 +532,13 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
   // tolerance is loose enough for FP32 (eta >= refine_trust) takes the FP32
   // solution to half its tolerance without the FP64 residual pass.
   const bool trusted = o.refine_trust > 0.0 && eta >= o.refine_trust;
+  // (an unrefined system stores no FP64 Sigma or h: nothing reads them,
+  // except the features of a capture)
   KT(c, trusted ? "newton_init_noh.f32" : "newton_init.f32",
-     newton_init<float>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, smu, c->sig1, c->sig2,
-                        trusted ? nullptr : c->rhb, trusted ? nullptr : c->rhz, c->sig1f, c->sig2f, pcc, c->frb,
+     newton_init<float>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, smu,
+                        trusted && !capture ? nullptr : c->sig1, trusted && !capture ? nullptr : c->sig2,
+                        trusted ? nullptr : c->rhb, trusted ? nullptr : c->rhz,
+                        c->sig1f, c->sig2f, pcc, c->frb,
                         c->frz, c->fzb, c->fzz, c->fpb, c->fpz, n, c->partV, c->s));
   // inner tolerance: half the remaining reduction, at most 1e-2, at least
   // refine_inner_rtol (what FP32 PCG can still reach)
@@ -539,8 +551,7 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
     if (st != CSIPM_OK) return st;
     cg_iters = po.iters;
     converged = po.converged;
-    KT(c, "set_f2d", set_f2d(c->dxb, c->dxz, c->fxb, c->fxz, n, c->s));
-    src = HD_RRES32;
+    src = HD_RRES32;   // the step is read from the FP32 solution itself
     return CSIPM_OK;
   }
   src = HD_DIRECT;
@@ -589,11 +600,12 @@ Resid read_resid(const csipm_ctx* c) {
   return Resid{v[0], v[1], v[2], v[3], v[4], v[5], v[6]};
 }
 
-// Residual parts with H beta recomputed by a full H-apply.
-csipm_status residuals(csipm_ctx* c, Resid& r) {
+// Residual parts with H beta recomputed by a full H-apply (and the sum of
+// log(S1 + S2) into scal[S_RESID + 7] when logsum).
+csipm_status residuals(csipm_ctx* c, Resid& r, bool logsum) {
   op_H<double>(c, c->beta, c->hb, c->work);
   KT(c, "ipm_resid+fin", ipm_resid(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, c->g.n, c->partV,
-                                    c->scal + S_RESID, c->s));
+                                    c->scal + S_RESID, logsum, c->s));
   csipm_status st = sync_scalars(c, "residuals");
   if (st != CSIPM_OK) return st;
   r = read_resid(c);
@@ -626,10 +638,11 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   c->cap_count = 0;
   c->cap_cg.clear();
   const double z0 = c->xi_inf > 0 ? c->xi_inf : 1.0;
+  const bool learned = o.pc == CSIPM_PC_LEARNED;
   // the start beta = 0 has H beta = 0 exactly
   KT(c, "ipm_init", ipm_init(c->beta, c->z, c->nu1, c->nu2, c->hb, n, z0, lam, c->s));
   KT(c, "ipm_resid+fin",
-     ipm_resid(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, lam, n, c->partV, c->scal + S_RESID, c->s));
+     ipm_resid(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, lam, n, c->partV, c->scal + S_RESID, learned, c->s));
   csipm_status st = sync_scalars(c, "solve start");
   if (st != CSIPM_OK) return st;
   Resid r = read_resid(c);
@@ -647,7 +660,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     const bool leaving_trust = approx && !(std::min(o.cg_rtol, 0.1 * rel) >= o.refine_trust);
     if (!exact &&
         (rel <= o.tol || it >= o.max_iter || carried >= kExactEvery || leaving_trust || !std::isfinite(rel))) {
-      st = residuals(c, r);
+      st = residuals(c, r, learned);
       if (st != CSIPM_OK) return st;
       exact = true;
       approx = false;
@@ -677,7 +690,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     HdSource src = HD_RRES64;
     const bool capture = c->cap_enable && o.pc == CSIPM_PC_PLAIN && c->cap_count < c->cap_max;
     if (o.pc == CSIPM_PC_LEARNED) {
-      st = learned_correction(c);
+      st = learned_correction(c, true);
       if (st != CSIPM_OK) return st;
       csipm_options ol = o;
       const int budget = prev_cg > 0 ? std::min(o.cg_max, std::max(8, (prev_cg * 3) / 2)) : o.cg_max;
@@ -703,15 +716,19 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
         c->cap_cg.push_back(cgi);
       }
     }
+    // an FP32 solution taken without refinement is read in FP32 (d = x32 exactly)
+    const float* d32b = src == HD_RRES32 ? c->fxb : nullptr;
+    const float* d32z = src == HD_RRES32 ? c->fxz : nullptr;
     prev_cg = cgi;
     inf.cg_iters_total += cgi;
     inf.cg_iters_max = std::max(inf.cg_iters_max, cgi);
     inf.refine_steps_total += ref;
-    KT(c, "ipm_ratio+fin",
-       ipm_step(c->beta, c->z, c->nu1, c->nu2, c->dxb, c->dxz, smu, o.tau, n, c->partV, c->scal, c->s));
-    KT(c, "ipm_advance+fin",
-       ipm_advance(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->dxb, c->dxz, src == HD_DIRECT ? c->rb : nullptr,
-                   c->rb, src == HD_RRES32 ? c->frb : nullptr, lam, smu, c->scal, n, c->partV, c->s));
+    KT(c, d32b ? "ipm_ratio_d32+fin" : "ipm_ratio+fin",
+       ipm_step(c->beta, c->z, c->nu1, c->nu2, c->dxb, c->dxz, d32b, d32z, smu, o.tau, n, c->partV, c->scal, c->s));
+    KT(c, d32b ? "ipm_advance_d32+fin" : "ipm_advance+fin",
+       ipm_advance(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->dxb, c->dxz, d32b, d32z,
+                   src == HD_DIRECT ? c->rb : nullptr, c->rb, src == HD_RRES32 ? c->frb : nullptr, lam, smu, c->scal, n,
+                   c->partV, learned, c->s));
     st = sync_scalars(c, "advance");
     if (st != CSIPM_OK) return st;
     r = read_resid(c);
@@ -750,7 +767,7 @@ csipm_status csipm_get_residuals(csipm_ctx* c, csipm_info* out) {
   if (!c || !out) return CSIPM_EINVAL;
   if (!c->have_lambda) return fail(c, CSIPM_ESTATE, "lambda not set");
   Resid r{};
-  csipm_status st = residuals(c, r);
+  csipm_status st = residuals(c, r, false);
   if (st != CSIPM_OK) return st;
   std::memset(out, 0, sizeof(*out));
   out->res_beta_inf = r.fb;
@@ -945,7 +962,7 @@ csipm_status csipm_pc_correction(csipm_ctx* c, double* d_c) {
   if (!c || !d_c) return CSIPM_EINVAL;
   if (!c->have_params) return fail(c, CSIPM_ESTATE, "learned preconditioner has no parameters");
   absmax(c->beta, c->g.n, c->partV, c->scal + S_RESID + 4, c->s);
-  csipm_status st = learned_correction(c);
+  csipm_status st = learned_correction(c, false);
   if (st != CSIPM_OK) return st;
   launch_to_external<float, double>(c->g, c->pc_c, d_c, c->s);
   return hip_check(c, "pc_correction");
@@ -973,7 +990,7 @@ csipm_status csipm_profile_kapply(csipm_ctx* c, int precision, int reps, double*
     T *pb = (T*)v.pb, *pz = (T*)v.pz, *qb = (T*)v.qb, *qz = (T*)v.qz, *work = (T*)v.work;
     const T* s1 = std::is_same<T, double>::value ? (const T*)c->sig1 : (const T*)c->sig1f;
     const T* s2 = std::is_same<T, double>::value ? (const T*)c->sig2 : (const T*)c->sig2f;
-    const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>));
+    const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>), -1);
     const int ps = (int)k_partials(g.n1, g.n2, g.n3);
     EpiArgs<T> ka{KArgs<T>{pb, pz, s1, s2, qb, qz}, RArgs{}, c->partK, ps};
     EpiArgs<T> kb = ka;

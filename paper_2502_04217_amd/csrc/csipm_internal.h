@@ -192,7 +192,9 @@ void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t*
 template <typename T>
 void launch_postmix(const Grid& g, const T* work, T* out, int epi, const EpiArgs<T>* ea,
                     const int* skip, hipStream_t s);
-int axis12_blocks(const Grid& g, int axis, int elem_bytes);
+// workgroups of a strided pass (axis 1 or 2, complex size elem_bytes, dir +1
+// inverse / -1 forward); for the axis-1 forward pass also its partial count
+int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir);
 int postmix_blocks(const Grid& g);
 
 // permutation between the external beta layout and the internal one

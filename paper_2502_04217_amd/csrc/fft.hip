@@ -29,8 +29,7 @@ namespace csipm {
 
 namespace {
 
-constexpr int kLdsBytes = 65536;     // LDS budget of one workgroup
-constexpr int kLdsBytesAxis1 = 131072;  // axis-1 passes: wider tiles for longer contiguous runs
+constexpr int kLdsBytes = 65536;     // LDS budget of an axis-3 workgroup
 
 // ------------------------------------------------------------- radix plan --
 template <int L, int E>
@@ -241,26 +240,39 @@ struct StridedGeom {
   int batch;
 };
 
-template <typename T>
-constexpr int strided_tm(int L, int axis) {
-  int tm = (axis == 1 ? kLdsBytesAxis1 : kLdsBytes) / (L * int(sizeof(cx<T>)));
+// Tile shape of the strided (axis-1/2) passes per complex size w in bytes,
+// pencil length L, axis and direction: elements per thread E and pencils
+// per workgroup TM (LDS = TM L w, at most 1024 threads).  Chosen from
+// measurements at 256^3: 8 elements per thread for the FP64 axis-2 passes
+// and the FP32 axis-1 forward pass, 16 otherwise; 128 KB tiles for axis 1
+// except the FP64 inverse pass (64 KB), 64 KB for axis 2.
+constexpr int strided_e(int w, int L, int axis, int dir) {
+  const int e = ((w == 16 && axis == 2) || (w == 8 && axis == 1 && dir < 0)) ? 8 : 16;
+  return L < e ? L : e;
+}
+constexpr int strided_lds(int w, int axis, int dir) {
+  return axis == 2 ? 65536 : (w == 16 && dir > 0 ? 65536 : 131072);
+}
+constexpr int strided_tm(int w, int L, int axis, int dir) {
+  int tm = strided_lds(w, axis, dir) / (L * w);
   if (tm > 64) tm = 64;
   if (tm < 1) tm = 1;
-  while (tm * (L < 16 ? 1 : L / 16) > 1024) tm >>= 1;   // at most 1024 threads
+  while (tm * (L / strided_e(w, L, axis, dir)) > 1024) tm >>= 1;
   return tm;
 }
-template <typename T, int L>
-constexpr int strided_e() { return L < 16 ? L : 16; }
-template <typename T, int L, int AX>
-constexpr int strided_threads() { return strided_tm<T>(L, AX) * (L / strided_e<T, L>()); }
+template <typename T, int L, int AX, int DIR>
+constexpr int strided_threads() {
+  constexpr int w = int(sizeof(cx<T>));
+  return strided_tm(w, L, AX, DIR) * (L / strided_e(w, L, AX, DIR));
+}
 
 template <typename T, int L, int AX, int DIR, class Epi>
-__global__ void __launch_bounds__((strided_threads<T, L, AX>()))
+__global__ void __launch_bounds__((strided_threads<T, L, AX, DIR>()))
 k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
          const cx<T>* __restrict__ tw, int m, int m0_from_dst, Epi epi, const int* skip) {
   if (skip && *skip) return;
-  constexpr int E = strided_e<T, L>();
-  constexpr int TM = strided_tm<T>(L, AX);
+  constexpr int E = strided_e(int(sizeof(cx<T>)), L, AX, DIR);
+  constexpr int TM = strided_tm(int(sizeof(cx<T>)), L, AX, DIR);
   constexpr int NT = L / E;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -317,7 +329,7 @@ k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
 
 // ------------------------------------------------------ axis-3 (c2r/r2c) --
 template <typename T>
-constexpr int a3_e(int L) { return L < 16 ? L : 16; }
+constexpr int a3_e(int L) { return L < 8 ? L : 8; }   // 8 elements per thread (measured best)
 template <typename T>
 constexpr int a3_pad(int L) { return L + (L >= 16 ? L / 16 : 1); }
 template <typename T>
@@ -609,8 +621,8 @@ void launch_axis12_L(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom
                      int m, int m0, Epi epi, const int* skip, hipStream_t s) {
 #define CSIPM_A12(LL)                                                                               \
   case LL: {                                                                                        \
-    constexpr int TM = strided_tm<T>(LL, AX);                                                       \
-    constexpr int NT = LL / strided_e<T, LL>();                                                     \
+    constexpr int TM = strided_tm(int(sizeof(cx<T>)), LL, AX, DIR);                                \
+    constexpr int NT = LL / strided_e(int(sizeof(cx<T>)), LL, AX, DIR);                             \
     const size_t shm = (size_t)TM * LL * sizeof(cx<T>);                                             \
     auto kern = k_axis12<T, LL, AX, DIR, Epi>;                                                      \
     if (shm > 65536) (void)hipFuncSetAttribute((const void*)kern,                                   \
@@ -635,15 +647,6 @@ void launch_axis12_L(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom
 }
 
 template <typename T>
-int tm_for(int L, int axis) {
-  int tm = (axis == 1 ? kLdsBytesAxis1 : kLdsBytes) / (L * int(sizeof(cx<T>)));
-  if (tm > 64) tm = 64;
-  if (tm < 1) tm = 1;
-  while (tm * (L < 16 ? 1 : L / 16) > 1024) tm >>= 1;
-  return tm;
-}
-
-template <typename T>
 StridedGeom<T> geom(const Grid& g, int axis) {
   StridedGeom<T> geo;
   if (axis == 1) {
@@ -662,10 +665,10 @@ StridedGeom<T> geom(const Grid& g, int axis) {
 
 }  // namespace
 
-int axis12_blocks(const Grid& g, int axis, int elem_bytes) {
+int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir) {
   const int L = axis == 1 ? g.n1 : g.n2;
   const int batch = axis == 1 ? g.n2 * g.m : g.n1 * g.m;
-  const int tm = elem_bytes == 16 ? tm_for<double>(L, axis) : tm_for<float>(L, axis);
+  const int tm = strided_tm(elem_bytes, L, axis, dir);
   return (batch + tm - 1) / tm;
 }
 
@@ -684,7 +687,7 @@ void launch_axis12(const Grid& g, int axis, int dir, const T* src, T* dst, const
   const int L = axis == 1 ? g.n1 : g.n2;
   const cx<T>* twp = axis == 1 ? tw.t1 : tw.t2;
   StridedGeom<T> geo = geom<T>(g, axis);
-  dim3 grid(axis12_blocks(g, axis, (int)sizeof(cx<T>)));
+  dim3 grid(axis12_blocks(g, axis, (int)sizeof(cx<T>), dir));
   const cx<T>* cs = reinterpret_cast<const cx<T>*>(src);
   cx<T>* cd = reinterpret_cast<cx<T>*>(dst);
   if (axis == 1) {

@@ -33,11 +33,11 @@ void mlp_features_state(const double* beta, const double* z, const double* nu1, 
 void mlp_mean_log_l1_state(const double* beta, const double* z, const double* nu1, const double* nu2, long long n,
                            double* partial, double* meanlog, hipStream_t s);
 // c of the interior-point state, network evaluated (on the matrix cores) only
-// where L1 / (L1 + 4 S1 S2) >= rmin (c = 1 elsewhere); meanlog and bmax are
-// device scalars
+// where L1 / (L1 + 4 S1 S2) >= rmin (c = 1 elsewhere); the centring of the
+// first feature is *meanlog * mscale, and meanlog, bmax are device scalars
 void mlp_correction_state(const double* beta, const double* z, const double* nu1, const double* nu2,
-                          const double* diagH, const double* meanlog, const double* bmax, const float* params,
-                          float* c, long long n, double rmin, hipStream_t s);
+                          const double* diagH, const double* meanlog, double mscale, const double* bmax,
+                          const float* params, float* c, long long n, double rmin, hipStream_t s);
 // c = softplus(MLP(feat)) + 1e-6 for n records (matrix-core inference)
 void mlp_forward(const float* params, const float* feat, float* c, long long n, hipStream_t s);
 // gradient of sum_i dc_i c_i, accumulated into grad (float, 1249)

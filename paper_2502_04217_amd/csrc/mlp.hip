@@ -113,63 +113,75 @@ __device__ __forceinline__ void load_net(const float* __restrict__ P, MfmaNet& w
   w.b3 = P[OB3];
 }
 
-// tanh without branches: sign(x) (1 - e) / (1 + e), e = exp(-2|x|), with the
-// hardware exp2 and reciprocal; absolute error ~2e-7 (what the weighted sums
-// of the next layer see).
+// tanh without branches: 2 / (1 + exp(-2x)) - 1 with the hardware exp2 and
+// reciprocal (exp overflowing to +inf for large negative x gives -1); absolute
+// error ~2e-7, which is what the weighted sums of the next layer see.
 __device__ __forceinline__ float tanh_exp(float x) {
-  const float e = __builtin_amdgcn_exp2f(fabsf(x) * -2.8853900817779268f);
-  return copysignf((1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e), x);
+  const float e = __builtin_amdgcn_exp2f(x * -2.8853900817779268f);
+  return fmaf(2.0f, __builtin_amdgcn_rcpf(1.0f + e), -1.0f);
 }
 
-// Output pre-activation o for the 16 coefficients of one tile: lane (g, q)
-// brings feature g of coefficient q and receives o of coefficient q.
-__device__ __forceinline__ float net_tile(const MfmaNet& w, float xb) {
-  f4_t h1[2], h2[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const f4_t c = {w.b1[t][0], w.b1[t][1], w.b1[t][2], w.b1[t][3]};
-    h1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w1[t], xb, c, 0, 0, 0);
-  }
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) h1[t][r] = tanh_exp(h1[t][r]);
-#pragma unroll
-  for (int m = 0; m < 2; ++m) h2[m] = f4_t{w.b2[m][0], w.b2[m][1], w.b2[m][2], w.b2[m][3]};
-#pragma unroll
-  for (int s = 0; s < 8; ++s)
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-      h2[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w2[m][s], h1[s >> 2][s & 3], h2[m], 0, 0, 0);
-  float o = 0.0f;
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) o = fmaf(w.w3[m][r], tanh_exp(h2[m][r]), o);
-  o += __shfl_xor(o, 16, 64);
-  o += __shfl_xor(o, 32, 64);
-  return o + w.b3;
-}
-
-// o for a chunk of 64 coefficients, lane l holding the four features of
-// coefficient l; tiles (16 coefficients) with no bit set in `act` are
-// skipped.  `lds` is this wave's 256-float staging area.
-__device__ __forceinline__ float net_chunk(const MfmaNet& w, float* lds, const float x[NIN], unsigned long long act) {
+// Output pre-activation o for a chunk of 64 coefficients, lane l holding the
+// four features of coefficient l.  The chunk is four tiles of 16
+// coefficients; lane (g, q) takes feature g of coefficient 16t + q of tile t
+// (staged through `lds`, this wave's 256 floats) and receives o of
+// coefficient l.  The four tiles go through each layer together, so the
+// matrix core sees eight independent accumulation chains in the 32x32 layer
+// while the VALU works on the tanh of the other tiles.
+template <int TB>
+__device__ __forceinline__ float net_chunk(const MfmaNet& w, float* lds, const float x[NIN]) {
   const int l = threadIdx.x & 63, g = l >> 4, q = l & 15;
   reinterpret_cast<float4*>(lds)[l] = make_float4(x[0], x[1], x[2], x[3]);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  float mine = 0.0f;
+  float xb[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    if (((act >> (16 * t)) & 0xFFFFull) == 0) continue;
-    const float o = net_tile(w, lds[(16 * t + q) * NIN + g]);
-    if (g == t) mine = o;
-  }
+  for (int t = 0; t < 4; ++t) xb[t] = lds[(16 * t + q) * NIN + g];
   __builtin_amdgcn_wave_barrier();
-  return mine;
+  float o[4];
+#pragma unroll
+  for (int t0 = 0; t0 < 4; t0 += TB) {
+    f4_t h1[TB][2], h2[TB][2];
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+        h1[t][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+            w.w1[m], xb[t0 + t], f4_t{w.b1[m][0], w.b1[m][1], w.b1[m][2], w.b1[m][3]}, 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h1[t][m][r] = tanh_exp(h1[t][m][r]);
+        h2[t][m] = f4_t{w.b2[m][0], w.b2[m][1], w.b2[m][2], w.b2[m][3]};
+      }
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+          h2[t][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w2[m][s], h1[t][s >> 2][s & 3], h2[t][m], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+      float a = 0.0f;
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a = fmaf(w.w3[m][r], tanh_exp(h2[t][m][r]), a);
+      a += __shfl_xor(a, 16, 64);
+      a += __shfl_xor(a, 32, 64);
+      o[t0 + t] = a;
+    }
+  }
+  const float mine = g == 0 ? o[0] : g == 1 ? o[1] : g == 2 ? o[2] : o[3];
+  return mine + w.b3;
 }
+
+// tiles that go through a layer together (register use against overlap)
+constexpr int kNetTiles = 2;
 
 constexpr int kNetWaves = 4;   // waves per inference workgroup
 
@@ -187,8 +199,7 @@ k_forward(const float* __restrict__ P, const float* __restrict__ feat, float* __
       const float4 f = reinterpret_cast<const float4*>(feat)[i];
       x[0] = f.x; x[1] = f.y; x[2] = f.z; x[3] = f.w;
     }
-    const unsigned long long act = __ballot(i < n);
-    const float o = net_chunk(w, lds[wv], x, act);
+    const float o = net_chunk<kNetTiles>(w, lds[wv], x);
     if (i < n) c[i] = softplusf(o) + 1e-6f;
   }
 }
@@ -392,18 +403,18 @@ k_features_state(const double* __restrict__ beta, const double* __restrict__ z, 
 // the four features, and c = softplus(MLP) + 1e-6 only where c can act on
 // P_c^{-1}, i.e. where L1 / (L1 + 4 S1 S2) >= rmin; elsewhere c = 1 (the
 // paper's P, from which P_c^{-1} then differs by less than rmin relative).
-// The network runs on the matrix cores for every 16-coefficient tile that
+// The network runs on the matrix cores for every 64-coefficient chunk that
 // holds an active coefficient.
 __global__ void __launch_bounds__(64 * kNetWaves)
 k_correction_state(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
                    const double* __restrict__ nu2, const double* __restrict__ diagH,
-                   const double* __restrict__ meanlog, const double* __restrict__ bmax,
+                   const double* __restrict__ meanlog, double mscale, const double* __restrict__ bmax,
                    const float* __restrict__ P, float* __restrict__ c, long long n, double rmin) {
   __shared__ float lds[kNetWaves][64 * NIN];
   MfmaNet w;
   load_net(P, w);
-  const double ml = *meanlog;
-  const double bm = *bmax > 0.0 ? *bmax : 1.0;
+  const double ml = *meanlog * mscale;
+  const double ibm = *bmax > 0.0 ? 1.0 / *bmax : 1.0;
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long long nch = (n + 63) / 64;
   for (long long ch = blockIdx.x * (long long)kNetWaves + wv; ch < nch; ch += (long long)gridDim.x * kNetWaves) {
@@ -411,18 +422,24 @@ k_correction_state(const double* __restrict__ beta, const double* __restrict__ z
     float x[NIN] = {0.0f, 0.0f, 0.0f, 0.0f};
     bool act = false;
     if (i < n) {
-      const double b = beta[i];
-      const double g1 = nu1[i] / (z[i] + b), g2 = nu2[i] / (z[i] - b);
-      const double L1 = g1 + g2;
-      act = L1 >= rmin * (L1 + 4.0 * g1 * g2);
-      x[0] = (float)(log(L1) - ml);
-      x[1] = (float)((g1 - g2) / L1);
-      x[2] = (float)log(fabs(b) / bm + 1e-12);
+      // slacks in FP64 (z and |beta| nearly cancel late in the solve); the
+      // gate L1 / (L1 + 4 S1 S2) >= rmin multiplied through by s1 s2 > 0:
+      // (nu1 s2 + nu2 s1) >= rmin (nu1 s2 + nu2 s1 + 4 nu1 nu2), no division
+      const double b = beta[i], a1 = nu1[i], a2 = nu2[i];
+      const double s1 = z[i] + b, s2 = z[i] - b;
+      const double num = a1 * s2 + a2 * s1;
+      act = num >= rmin * (num + 4.0 * a1 * a2);
+      // features in FP32 from the FP64 slacks
+      const float g1 = (float)a1 * __builtin_amdgcn_rcpf((float)s1);
+      const float g2 = (float)a2 * __builtin_amdgcn_rcpf((float)s2);
+      const float L1 = g1 + g2;
+      x[0] = __logf(L1) - (float)ml;
+      x[1] = (g1 - g2) * __builtin_amdgcn_rcpf(L1);
+      x[2] = __logf((float)(fabs(b) * ibm) + 1e-12f);
       x[3] = (float)diagH[i];
     }
-    const unsigned long long am = __ballot(act);
     float o = 0.0f;
-    if (am) o = net_chunk(w, lds[wv], x, am);
+    if (__ballot(act)) o = net_chunk<kNetTiles>(w, lds[wv], x);   // chunks without an active coefficient skip the network
     if (i < n) c[i] = act ? softplusf(o) + 1e-6f : 1.0f;
   }
 }
@@ -520,10 +537,10 @@ void mlp_mean_log_l1_state(const double* beta, const double* z, const double* nu
 }
 
 void mlp_correction_state(const double* beta, const double* z, const double* nu1, const double* nu2,
-                          const double* diagH, const double* meanlog, const double* bmax, const float* params,
-                          float* c, long long n, double rmin, hipStream_t s) {
+                          const double* diagH, const double* meanlog, double mscale, const double* bmax,
+                          const float* params, float* c, long long n, double rmin, hipStream_t s) {
   hipLaunchKernelGGL(k_correction_state, dim3(net_blocks(n)), dim3(64 * kNetWaves), 0, s, beta, z, nu1, nu2, diagH,
-                     meanlog, bmax, params, c, n, rmin);
+                     meanlog, mscale, bmax, params, c, n, rmin);
 }
 
 void mlp_forward(const float* params, const float* feat, float* c, long long n, hipStream_t s) {

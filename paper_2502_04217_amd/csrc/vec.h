@@ -25,7 +25,7 @@ enum ScalarSlot {
   S_RES = 6,       // sqrt(r.P^{-1}r) now
   S_AMAX = 8,      // IPM: largest feasible step
   S_ALPHA_IPM = 9, // IPM: step taken
-  S_RESID = 16,    // IPM residual block, 7 values (k_ipm_resid order)
+  S_RESID = 16,    // IPM residual block, 8 values (k_ipm_resid order)
   S_REF = 24,      // refinement: r.P^{-1}r of the FP64 residual
   S_REF0 = 25,     // refinement: rhs.P^{-1}rhs
   S_REFRZ = 26,    // refinement: r32.P^{-1}r32, start of the next inner PCG
@@ -61,18 +61,22 @@ void fin_rz(const double* partial, int nb, double* scal, int* flags, hipStream_t
 // beta = 0, z = z0, nu = lam/2, and H beta = 0
 void ipm_init(double* beta, double* z, double* nu1, double* nu2, double* hbeta, long long n, double z0, double lam,
               hipStream_t s);
-// residual parts of the iterate from a given H beta -> out7 (k_ipm_resid order)
+// residual parts of the iterate from a given H beta -> out8 (k_ipm_resid order;
+// out8[7] = sum log(S1 + S2) when logsum)
 void ipm_resid(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
-               const double* xi, double lam, long long n, double* partial, double* out7, hipStream_t s);
+               const double* xi, double lam, long long n, double* partial, double* out8, bool logsum, hipStream_t s);
 // step length: scal[S_AMAX] and scal[S_ALPHA_IPM] = min(1, tau * S_AMAX)
+// (the direction is read from db32/dz32 when set, else from db/dz)
 void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* db,
-              const double* dz, double smu, double tau, long long n, double* partial, double* scal, hipStream_t s);
+              const double* dz, const float* db32, const float* dz32, double smu, double tau, long long n,
+              double* partial, double* scal, hipStream_t s);
 // iterate update with H beta carried along (H d_beta from hd when set, else
 // from the Krylov residual: rres32 when set, else rres), and the new residual
 // parts -> scal[S_RESID..]
 void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* xi,
-                 const double* db, const double* dz, const double* hd, const double* rres, const float* rres32,
-                 double lam, double smu, double* scal, long long n, double* partial, hipStream_t s);
+                 const double* db, const double* dz, const float* db32, const float* dz32, const double* hd,
+                 const double* rres, const float* rres32, double lam, double smu, double* scal, long long n,
+                 double* partial, bool logsum, hipStream_t s);
 
 void add_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s);
 // FP32 restart of a further inner solve from H d_beta (hd): r32, z32 = p32 =

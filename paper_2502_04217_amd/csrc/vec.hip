@@ -245,11 +245,27 @@ k_ipm_init(double* __restrict__ beta, double* __restrict__ z, double* __restrict
 
 // Residual parts of the KKT system (equation "kkt", first two rows) and
 // complementarity: [max|F_b|, max|F_z|, max s.nu, sum s.nu, max|beta|,
-// min(s, nu), count of non-finite values].
+// min(s, nu), count of non-finite values, sum log(S1 + S2) (when logsum is
+// set: the centring of the learned correction's first feature)].
+constexpr int NRESID = 8;
+#define CSIPM_RESID_OPS {RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM, RED_SUM}
+
+__device__ __forceinline__ void resid_accumulate(double* v, double b, double s1, double s2, double a1, double a2,
+                                                 double fb, double fz, int logsum) {
+  const double c1 = s1 * a1, c2 = s2 * a2;
+  v[0] = fmax(v[0], fabs(fb));
+  v[1] = fmax(v[1], fabs(fz));
+  v[2] = fmax(v[2], fmax(c1, c2));
+  v[3] += c1 + c2;
+  v[4] = fmax(v[4], fabs(b));
+  v[5] = fmin(v[5], fmin(fmin(s1, s2), fmin(a1, a2)));
+  if (!isfinite(fb) || !isfinite(c1) || !isfinite(c2)) v[6] += 1.0;
+  if (logsum) v[7] += log(a1 / s1 + a2 / s2);
+}
 __global__ void __launch_bounds__(256)
 k_ipm_resid(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
             const double* __restrict__ nu2, const double* __restrict__ hb, const double* __restrict__ xi,
-            double lam, long long n, double* partial, int stride) {
+            double lam, long long n, double* partial, int stride, int logsum) {
   CSIPM_ALIGN(beta);
   CSIPM_ALIGN(z);
   CSIPM_ALIGN(nu1);
@@ -257,28 +273,21 @@ k_ipm_resid(const double* __restrict__ beta, const double* __restrict__ z, const
   CSIPM_ALIGN(hb);
   CSIPM_ALIGN(xi);
 
-  double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0};
+  double v[NRESID] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0};
   CSIPM_PAIRS(n) {
     const double b = beta[i], zz = z[i], a1 = nu1[i], a2 = nu2[i];
     const double s1 = zz + b, s2 = zz - b;
     const double fb = hb[i] - xi[i] - a1 + a2;
     const double fz = lam - a1 - a2;
-    const double c1 = s1 * a1, c2 = s2 * a2;
-    v[0] = fmax(v[0], fabs(fb));
-    v[1] = fmax(v[1], fabs(fz));
-    v[2] = fmax(v[2], fmax(c1, c2));
-    v[3] += c1 + c2;
-    v[4] = fmax(v[4], fabs(b));
-    v[5] = fmin(v[5], fmin(fmin(s1, s2), fmin(a1, a2)));
-    if (!isfinite(fb) || !isfinite(c1) || !isfinite(c2)) v[6] += 1.0;
+    resid_accumulate(v, b, s1, s2, a1, a2, fb, fz, logsum);
   }
-  const int ops[7] = {RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM};
-  block_reduce_store<7>(v, ops, partial, stride);
+  const int ops[NRESID] = CSIPM_RESID_OPS;
+  block_reduce_store<NRESID>(v, ops, partial, stride);
 }
 
-// Newton system and PCG start in one pass: Sigma_j = nu_j / s_j (FP64, and
-// in TC when sig1c is set), the right-hand side h (written only when hb_out
-// is set), r = h, z = P_c^{-1} r, p = z in the Krylov precision TC, and the
+// Newton system and PCG start in one pass: Sigma_j = nu_j / s_j (FP64 when
+// sig1 is set, and in TC when sig1c is set), the right-hand side h (written
+// only when hb_out is set), r = h, z = P_c^{-1} r, p = z in the Krylov precision TC, and the
 // partial sums r.z (in TC) and h.P_c^{-1}h (in FP64).  x0 = 0 is implicit.
 template <typename TC>
 __global__ void __launch_bounds__(256)
@@ -340,8 +349,10 @@ k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, con
       g1o[k] = g1; g2o[k] = g2; h1o[k] = h1; h2o[k] = h2;
       r1o[k] = r1; r2o[k] = r2; w1o[k] = w1; w2o[k] = w2;
     }
-    ((D2*)sig1)[j] = {g1o[0], g1o[1]};
-    ((D2*)sig2)[j] = {g2o[0], g2o[1]};
+    if (sig1) {
+      ((D2*)sig1)[j] = {g1o[0], g1o[1]};
+      ((D2*)sig2)[j] = {g2o[0], g2o[1]};
+    }
     if (hb_out) {
       ((D2*)hb_out)[j] = {h1o[0], h1o[1]};
       ((D2*)hz_out)[j] = {h2o[0], h2o[1]};
@@ -384,16 +395,27 @@ __device__ __forceinline__ IpmDir ipm_dir(double b, double zz, double a1, double
   return o;
 }
 
+// Pair j of a Newton direction: from its FP32 copy when one is given (an
+// FP32 solution taken without refinement), else from the FP64 array.
+__device__ __forceinline__ cx<double> ld_dir(const cx<double>* d64, const float* d32, long long j) {
+  if (d32) {
+    const float2 f = reinterpret_cast<const float2*>(d32)[j];
+    return {(double)f.x, (double)f.y};
+  }
+  return d64[j];
+}
+
 // Largest step keeping s and nu positive along (db, dz, dnu1, dnu2).
 __global__ void __launch_bounds__(256)
 k_ipm_ratio(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
             const double* __restrict__ nu2, const double* __restrict__ db, const double* __restrict__ dz,
-            double smu, long long n, double* partial) {
+            const float* __restrict__ db32, const float* __restrict__ dz32, double smu, long long n,
+            double* partial) {
   double amax = INFINITY;
   using D2 = cx<double>;
   for (long long j = gtid(); j < n / 2; j += gstride()) {
     const D2 b2 = ((const D2*)beta)[j], z2 = ((const D2*)z)[j], a1 = ((const D2*)nu1)[j], a2 = ((const D2*)nu2)[j],
-             d1 = ((const D2*)db)[j], d2 = ((const D2*)dz)[j];
+             d1 = ld_dir((const D2*)db, db32, j), d2 = ld_dir((const D2*)dz, dz32, j);
     const double bb[2] = {b2.re, b2.im}, zv[2] = {z2.re, z2.im}, n1[2] = {a1.re, a1.im}, n2[2] = {a2.re, a2.im},
                  dbv[2] = {d1.re, d1.im}, dzv[2] = {d2.re, d2.im};
 #pragma unroll
@@ -436,16 +458,18 @@ __global__ void __launch_bounds__(256)
 k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restrict__ nu1, double* __restrict__ nu2,
               double* __restrict__ hbeta, const double* __restrict__ xi, const double* __restrict__ db,
               const double* __restrict__ dz, const double* __restrict__ hd, const double* __restrict__ rres,
-              const float* __restrict__ rres32, double lam, double smu, const double* __restrict__ scal, long long n,
-              double* partial, int stride) {
+              const float* __restrict__ rres32, const float* __restrict__ db32, const float* __restrict__ dz32,
+              double lam, double smu, const double* __restrict__ scal, long long n, double* partial, int stride,
+              int logsum) {
   const double a = scal[S_ALPHA_IPM];
-  double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0};
+  double v[NRESID] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0};
   using D2 = cx<double>;
   D2 *BE = (D2*)beta, *ZV = (D2*)z, *N1 = (D2*)nu1, *N2 = (D2*)nu2, *HBV = (D2*)hbeta;
   const D2 *XI = (const D2*)xi, *DB = (const D2*)db, *DZ = (const D2*)dz, *W = (const D2*)(hd ? hd : rres);
   const float2* W32 = (const float2*)rres32;
   for (long long j = gtid(); j < n / 2; j += gstride()) {
-    const D2 b2 = BE[j], z2 = ZV[j], a1 = N1[j], a2 = N2[j], h2 = HBV[j], x2 = XI[j], d1 = DB[j], d2 = DZ[j];
+    const D2 b2 = BE[j], z2 = ZV[j], a1 = N1[j], a2 = N2[j], h2 = HBV[j], x2 = XI[j];
+    const D2 d1 = ld_dir(DB, db32, j), d2 = ld_dir(DZ, dz32, j);
     D2 w2;
     if (W32) {
       const float2 f = W32[j];
@@ -471,17 +495,7 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
       const double m1 = n1[k] + a * d.dn1, m2 = n2[k] + a * d.dn2;
       const double hb = hv[k] + a * u;
       bo[k] = b; zo[k] = zz; n1o[k] = m1; n2o[k] = m2; ho[k] = hb;
-      const double s1 = zz + b, s2 = zz - b;
-      const double fb = hb - xv[k] - m1 + m2;
-      const double fz = lam - m1 - m2;
-      const double c1 = s1 * m1, c2 = s2 * m2;
-      v[0] = fmax(v[0], fabs(fb));
-      v[1] = fmax(v[1], fabs(fz));
-      v[2] = fmax(v[2], fmax(c1, c2));
-      v[3] += c1 + c2;
-      v[4] = fmax(v[4], fabs(b));
-      v[5] = fmin(v[5], fmin(fmin(s1, s2), fmin(m1, m2)));
-      if (!isfinite(fb) || !isfinite(c1) || !isfinite(c2)) v[6] += 1.0;
+      resid_accumulate(v, b, zz + b, zz - b, m1, m2, hb - xv[k] - m1 + m2, lam - m1 - m2, logsum);
     }
     BE[j] = {bo[0], bo[1]};
     ZV[j] = {zo[0], zo[1]};
@@ -489,8 +503,8 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
     N2[j] = {n2o[0], n2o[1]};
     HBV[j] = {ho[0], ho[1]};
   }
-  const int ops[7] = {RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM};
-  block_reduce_store<7>(v, ops, partial, stride);
+  const int ops[NRESID] = CSIPM_RESID_OPS;
+  block_reduce_store<NRESID>(v, ops, partial, stride);
 }
 
 // Generic multi-value finalize: out[q] = op_q over partial[q*stride + 0..nb);
@@ -741,29 +755,31 @@ void ipm_init(double* beta, double* z, double* nu1, double* nu2, double* hbeta, 
               hipStream_t s) {
   hipLaunchKernelGGL(k_ipm_init, VB, beta, z, nu1, nu2, hbeta, n, z0, lam);
 }
+static const RedOps<NRESID> kResidRedOps{CSIPM_RESID_OPS};
+
 void ipm_resid(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
-               const double* xi, double lam, long long n, double* partial, double* out7, hipStream_t s) {
+               const double* xi, double lam, long long n, double* partial, double* out8, bool logsum, hipStream_t s) {
   const int nb = vec_blocks(n);
-  hipLaunchKernelGGL(k_ipm_resid, VB, beta, z, nu1, nu2, hb, xi, lam, n, partial, VEC_MAX_BLOCKS);
-  RedOps<7> ops{{RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM}};
-  hipLaunchKernelGGL((k_fin_reduce<7>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out7,
-                     ops);
+  hipLaunchKernelGGL(k_ipm_resid, VB, beta, z, nu1, nu2, hb, xi, lam, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0);
+  hipLaunchKernelGGL((k_fin_reduce<8>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out8,
+                     kResidRedOps);
 }
 void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* db,
-              const double* dz, double smu, double tau, long long n, double* partial, double* scal, hipStream_t s) {
+              const double* dz, const float* db32, const float* dz32, double smu, double tau, long long n,
+              double* partial, double* scal, hipStream_t s) {
   const int nb = vec_blocks(n);
-  hipLaunchKernelGGL(k_ipm_ratio, VB, beta, z, nu1, nu2, db, dz, smu, n, partial);
+  hipLaunchKernelGGL(k_ipm_ratio, VB, beta, z, nu1, nu2, db, dz, db32, dz32, smu, n, partial);
   hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(256), 0, s, partial, nb, tau, scal);
 }
 void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* xi,
-                 const double* db, const double* dz, const double* hd, const double* rres, const float* rres32,
-                 double lam, double smu, double* scal, long long n, double* partial, hipStream_t s) {
+                 const double* db, const double* dz, const float* db32, const float* dz32, const double* hd,
+                 const double* rres, const float* rres32, double lam, double smu, double* scal, long long n,
+                 double* partial, bool logsum, hipStream_t s) {
   const int nb = vec_blocks(n);
-  hipLaunchKernelGGL(k_ipm_advance, VB, beta, z, nu1, nu2, hbeta, xi, db, dz, hd, rres, rres32, lam, smu, scal, n,
-                     partial, VEC_MAX_BLOCKS);
-  RedOps<7> ops{{RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM}};
-  hipLaunchKernelGGL((k_fin_reduce<7>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, scal + S_RESID,
-                     ops);
+  hipLaunchKernelGGL(k_ipm_advance, VB, beta, z, nu1, nu2, hbeta, xi, db, dz, hd, rres, rres32, db32, dz32, lam, smu,
+                     scal, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0);
+  hipLaunchKernelGGL((k_fin_reduce<8>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, scal + S_RESID,
+                     kResidRedOps);
 }
 void add_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_add_f2d, VB, db, dz, eb, ez, n);

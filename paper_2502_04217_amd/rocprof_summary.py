@@ -50,12 +50,15 @@ def summarize(db: str, top: int = 25, min_us: float = 8.0):
     return out, counters, total / 1e3
 
 
-def calibrated_traffic(fetch_db: str, write_db: str, calib_bytes: int):
-    """Per-kernel HBM bytes per dispatch from a FETCH_SIZE run and a
+def calibrated_traffic(fetch_db: str, write_db: str, calib_bytes: int, working_frac: float = 0.1):
+    """Per-kernel HBM bytes per working dispatch from a FETCH_SIZE run and a
     WRITE_SIZE run (KiB per dispatch), each scaled by what the counter reads
     for a kernel of known traffic in the same run: the reduction (torch sum,
     reads calib_bytes) for FETCH_SIZE and the fill (writes calib_bytes) for
-    WRITE_SIZE.  Returns ({kernel: (fetch_bytes, write_bytes)}, factors)."""
+    WRITE_SIZE.  A dispatch counts as working when its counter reaches
+    working_frac of that kernel's largest dispatch (the Krylov launches queued
+    past convergence return at once and read only a flag).
+    Returns ({kernel: (fetch_bytes, write_bytes)}, factors)."""
     def per_dispatch(db, counter):
         c = sqlite3.connect(db)
         rows = c.execute("select kernel_name, value from counters_collection where counter_name = ?",
@@ -70,11 +73,15 @@ def calibrated_traffic(fetch_db: str, write_db: str, calib_bytes: int):
     fill = [max(v) for k, v in w.items() if "FillFunctor" in k]
     ff = calib_bytes / 1024.0 / max(red) if red else 1.0
     fw = calib_bytes / 1024.0 / max(fill) if fill else 1.0
+    def working_mean(v):
+        if not v:
+            return 0.0
+        top = max(v)
+        keep = [x for x in v if x >= working_frac * top]
+        return sum(keep) / len(keep)
     out = {}
     for k in set(f) | set(w):
-        fe = sum(f.get(k, [0])) / max(1, len(f.get(k, [1]))) * 1024.0 * ff
-        wr = sum(w.get(k, [0])) / max(1, len(w.get(k, [1]))) * 1024.0 * fw
-        out[short(k)] = (fe, wr)
+        out[short(k)] = (working_mean(f.get(k, [])) * 1024.0 * ff, working_mean(w.get(k, [])) * 1024.0 * fw)
     return out, (ff, fw)
 
 
@@ -92,7 +99,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.fetch_db and a.write_db:
         tr, (ff, fw) = calibrated_traffic(a.fetch_db, a.write_db, a.calib_bytes)
-        print(f"# calibrated HBM traffic per dispatch (FETCH_SIZE x {ff:.4f}, WRITE_SIZE x {fw:.4f})")
+        print(f"# calibrated HBM traffic per working dispatch (FETCH_SIZE x {ff:.4f}, WRITE_SIZE x {fw:.4f})")
         for k in sorted(tr):
             fe, wr = tr[k]
             if fe + wr > 1e6:

@@ -114,12 +114,12 @@ def test_learned_solve_same_solution_and_fallback():
     from paper_2502_04217_amd import csipm
     w = wl.grid16(4)
     lam = ipm.lambda_rule(w.signal, w.observed)
-    ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-10))
+    ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-12))
     pr = csipm.Problem(w.signal, w.observed)
     pr.set_lambda(lam)
     pr.set_pc_params(torch.tensor(_params(3), device="cuda"))
     for prec in (0, 1):
-        info = pr.solve(tol=1e-10, pc=1, precision=prec)
+        info = pr.solve(tol=1e-12, pc=1, precision=prec)
         beta = pr.get(csipm.BETA).cpu().numpy()
         say("learned solve precision", prec, info)
         assert info["status"] in (0, 3)
@@ -129,7 +129,7 @@ def test_learned_solve_same_solution_and_fallback():
     bad = mlp.init_params(0, out_scale=0.0)
     bad[-1] = 1e6
     pr.set_pc_params(torch.tensor(bad.astype(np.float32), device="cuda"))
-    info = pr.solve(tol=1e-10, pc=1, cg_max=30)
+    info = pr.solve(tol=1e-12, pc=1, cg_max=30)
     say("forced fallback", info)
     assert info["fallbacks"] > 0 and info["status"] == 3
     assert rel2(pr.get(csipm.BETA).cpu().numpy(), ref.state.beta) <= 1e-7

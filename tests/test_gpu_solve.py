@@ -1,5 +1,6 @@
 """GPU interior-point solves against the CPU oracle: final beta within 1e-7
-relative, identical support above 1e-6 max|beta|, on the 16^3 (5 seeds) and
+relative (both sides stopped at rel_kkt 1e-12), identical support above
+1e-6 max|beta|, on the 16^3 (5 seeds) and
 64^3 workloads, in FP64 and FP32-with-refinement; closed forms (nothing
 missing -> soft threshold, lambda >= ||xi||_inf -> 0); the LASSO certificate
 at 256^3 computed by the oracle from the GPU solution."""
@@ -12,7 +13,12 @@ from tests._gpu_common import need_gpu, rel2, say
 
 pytestmark = pytest.mark.gpu
 
-PARITY_TOL = 1e-10     # both sides stop at rel_kkt <= 1e-10 before comparing
+# Both sides stop at rel_kkt <= 1e-12 before comparing.  Coordinates next to
+# the support (|g_i| close to lambda) approach their limit only like
+# mu / (lambda - |g_i|), so two runs stopped at 1e-10 can still differ by
+# ~2e-7 (16^3 seed 2: the oracle at 1e-10 is 1.7e-7 from its own 1e-14
+# solution); at 1e-12 every workload here is within 1e-10 of it.
+PARITY_TOL = 1e-12
 
 
 def _supports_match(bg, bo, rel=1e-6):
@@ -170,8 +176,12 @@ def test_kernel_timing_records():
     by = {r["name"]: r for r in rep}
     say("timing", info, sorted((r["name"], r["calls"]) for r in rep))
     k = info["ipm_iters"]
-    assert sum(by.get(nm, {"calls": 0})["calls"] for nm in ("newton_init.f32", "newton_init_noh.f32")) == k
-    assert by["ipm_ratio+fin"]["calls"] == k and by["ipm_advance+fin"]["calls"] == k
+    calls = lambda *names: sum(by.get(nm, {"calls": 0})["calls"] for nm in names)
+    assert calls("newton_init.f32", "newton_init_noh.f32") == k
+    assert calls("ipm_ratio+fin", "ipm_ratio_d32+fin") == k
+    assert calls("ipm_advance+fin", "ipm_advance_d32+fin") == k
+    unrefined = sum(1 for r in pr.log() if r["refine_steps"] == 0)
+    assert calls("ipm_advance_d32+fin") == unrefined == calls("newton_init_noh.f32")
     assert by.get("axis1_fwd_R.f64", {"calls": 0})["calls"] == info["refine_steps_total"]
     assert by["axis1_fwd_K.f32"]["calls"] >= info["cg_iters_total"]
     assert all(r["total_ms"] > 0 and r["working_calls"] == r["calls"] for r in rep)
