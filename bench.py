@@ -240,6 +240,7 @@ def main():
         infos.append(pr.solve(**chosen))
     torch.cuda.synchronize()
     chosen_s = (time.perf_counter() - t0) / args.steps
+    chosen_log = pr.log()
     beta_chosen = pr.get(csipm.BETA)
     print(f"[bench] chosen form: {chosen_s * 1e3:.1f} ms/solve {infos[-1]}", file=sys.stderr, flush=True)
 
@@ -260,6 +261,7 @@ def main():
     infos32 = [pr.solve(**fp32_plain) for _ in range(args.steps)]
     torch.cuda.synchronize()
     fp32_plain_s = (time.perf_counter() - t0) / args.steps
+    fp32_plain_log = pr.log()
     rel_diff = float((beta_chosen - beta64).norm() / beta64.norm())
 
     # per-kernel event timing of one more solve of each form; the dominant
@@ -335,11 +337,14 @@ def main():
                    "form": ("fp32+refine+learned-pc" if learned else "fp32+refine+plain-pc (no trained params)"),
                    "tol_rel_kkt": 1e-6, "n": n},
         "solve": {"ipm_iters": last["ipm_iters"], "cg_iters_total": last["cg_iters_total"],
+                  "cg_per_iter": [r["cg_iters"] for r in chosen_log],
+                  "learned_per_iter": [r["learned"] for r in chosen_log],
                   "refine_steps": last["refine_steps_total"], "fallbacks": last["fallbacks"],
                   "rel_kkt": last["rel_kkt"], "rel_diff_vs_fp64": rel_diff},
         "plain_fp64": {"seconds": plain_s, "ipm_iters": infos64[-1]["ipm_iters"],
                        "cg_iters_total": infos64[-1]["cg_iters_total"], "rel_kkt": infos64[-1]["rel_kkt"]},
         "fp32_plain_pc": {"seconds": fp32_plain_s, "ipm_iters": infos32[-1]["ipm_iters"],
+                          "cg_per_iter": [r["cg_iters"] for r in fp32_plain_log],
                           "cg_iters_total": infos32[-1]["cg_iters_total"], "rel_kkt": infos32[-1]["rel_kkt"]},
         "correction_inference": corr,
         "setup_seconds": setup_s,

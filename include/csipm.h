@@ -91,6 +91,12 @@ typedef struct {
                           recomputed in FP64, which happens before every
                           stopping test and before the first system below
                           the threshold.  0 = always refine.               */
+  int pc_min_cg;       /* learned correction: applied to a Newton system only
+                          when the previous system took at least this many
+                          PCG iterations (default 2; the first system and
+                          systems after a one-iteration solve use the paper's
+                          P, which already makes them one-iteration solves);
+                          0 = every system                                   */
 } csipm_options;
 
 typedef struct {
@@ -111,6 +117,7 @@ typedef struct {
 /* One record per interior-point iteration (csipm_get_log). */
 typedef struct {
   int iter, cg_iters, refine_steps, fell_back;
+  int learned;   /* 1 when the learned correction was applied to this system */
   double mu, rel_kkt, alpha;
 } csipm_iter_log;
 

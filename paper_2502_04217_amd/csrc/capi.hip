@@ -380,6 +380,7 @@ void csipm_default_options(csipm_options* o) {
   o->refine_max = 8;
   o->refine_inner_rtol = 1e-5;
   o->refine_trust = 1e-4;
+  o->pc_min_cg = 2;
 }
 
 size_t csipm_workspace_bytes(int n1, int n2, int n3) {
@@ -628,7 +629,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   if (opts) o = *opts;
   if (!(o.tol > 0) || o.max_iter < 0 || o.cg_max < 1 || !(o.sigma > 0 && o.sigma < 1) || !(o.tau > 0 && o.tau < 1) ||
       (o.precision != CSIPM_FP64 && o.precision != CSIPM_FP32) || (o.pc != CSIPM_PC_PLAIN && o.pc != CSIPM_PC_LEARNED) ||
-      !(o.refine_trust >= 0.0 && o.refine_trust <= 1.0) || !(o.refine_inner_rtol > 0.0))
+      !(o.refine_trust >= 0.0 && o.refine_trust <= 1.0) || !(o.refine_inner_rtol > 0.0) || o.pc_min_cg < 0)
     return fail(c, CSIPM_EINVAL, "invalid options");
   if (o.pc == CSIPM_PC_LEARNED && !c->have_params) return fail(c, CSIPM_ESTATE, "learned preconditioner has no parameters");
   const auto t0 = std::chrono::steady_clock::now();
@@ -689,7 +690,11 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     bool conv = false, fell = false;
     HdSource src = HD_RRES64;
     const bool capture = c->cap_enable && o.pc == CSIPM_PC_PLAIN && c->cap_count < c->cap_max;
-    if (o.pc == CSIPM_PC_LEARNED) {
+    // the correction is applied once a Newton system has needed more than
+    // pc_min_cg - 1 PCG iterations: a system the paper's P solves in one
+    // iteration leaves nothing to gain
+    const bool use_learned = o.pc == CSIPM_PC_LEARNED && prev_cg >= o.pc_min_cg;
+    if (use_learned) {
       st = learned_correction(c, true);
       if (st != CSIPM_OK) return st;
       csipm_options ol = o;
@@ -735,7 +740,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     exact = false;
     approx = approx || src == HD_RRES32;
     ++carried;
-    c->log.push_back(csipm_iter_log{it, cgi, ref, fell ? 1 : 0, mu, rel, 0.0});
+    c->log.push_back(csipm_iter_log{it, cgi, ref, fell ? 1 : 0, use_learned ? 1 : 0, mu, rel, 0.0});
     inf.ipm_iters = it + 1;
   }
   inf.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

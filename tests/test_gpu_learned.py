@@ -119,17 +119,22 @@ def test_learned_solve_same_solution_and_fallback():
     pr.set_lambda(lam)
     pr.set_pc_params(torch.tensor(_params(3), device="cuda"))
     for prec in (0, 1):
-        info = pr.solve(tol=1e-12, pc=1, precision=prec)
-        beta = pr.get(csipm.BETA).cpu().numpy()
-        say("learned solve precision", prec, info)
-        assert info["status"] in (0, 3)
-        assert rel2(beta, ref.state.beta) <= 1e-7
+        for min_cg in (0, 2):
+            info = pr.solve(tol=1e-12, pc=1, precision=prec, pc_min_cg=min_cg)
+            beta = pr.get(csipm.BETA).cpu().numpy()
+            log = pr.log()
+            say("learned solve precision", prec, "pc_min_cg", min_cg, info)
+            assert info["status"] in (0, 3)
+            assert rel2(beta, ref.state.beta) <= 1e-7
+            # the correction is applied exactly where the previous system needed >= pc_min_cg iterations
+            prev = [0] + [r["cg_iters"] for r in log[:-1]]
+            assert [r["learned"] for r in log] == [int(p >= min_cg) for p in prev]
     # a correction of 1e6 makes P_c a poor preconditioner: the learned
     # systems exceed the budget and restart with the paper's P
     bad = mlp.init_params(0, out_scale=0.0)
     bad[-1] = 1e6
     pr.set_pc_params(torch.tensor(bad.astype(np.float32), device="cuda"))
-    info = pr.solve(tol=1e-12, pc=1, cg_max=30)
+    info = pr.solve(tol=1e-12, pc=1, cg_max=30, pc_min_cg=0)
     say("forced fallback", info)
     assert info["fallbacks"] > 0 and info["status"] == 3
     assert rel2(pr.get(csipm.BETA).cpu().numpy(), ref.state.beta) <= 1e-7
