@@ -44,7 +44,8 @@ typedef struct csipm_ctx csipm_ctx;
 typedef enum {
   CSIPM_OK = 0,
   CSIPM_NOT_CONVERGED = 1, /* iteration limit reached; iterate usable          */
-  CSIPM_STALLED = 2,       /* step length collapsed; iterate usable            */
+  CSIPM_STALLED = 2,       /* rel_kkt rose above 10x its best value (the
+                              precision floor was reached); iterate usable   */
   CSIPM_FELL_BACK = 3,     /* converged, but some Newton systems fell back to
                               the paper's preconditioner                       */
   CSIPM_EINVAL = -1,       /* bad argument (null pointer, size, lambda <= 0)   */

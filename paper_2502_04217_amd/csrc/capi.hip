@@ -235,7 +235,8 @@ int op_K(csipm_ctx* c, const T* pb, const T* pz, const T* s1, const T* s2, T* qb
 }
 
 // FP64 refinement residual r = h - K d, fused into the K-apply of d: writes
-// H d_beta (into rb) and sums r.P_c^{-1}r -> scal[S_REF].
+// H d_beta (into rb), sums r.P_c^{-1}r -> scal[S_REF] and max |r| ->
+// scal[S_REFINF].
 void op_Kr(csipm_ctx* c, const float* pcc) {
   const Grid& g = c->g;
   const int nb5 = axis12_blocks(g, 1, 16, -1);
@@ -255,6 +256,7 @@ void op_Kr(csipm_ctx* c, const float* pcc) {
   KT(c, "axis1_fwd_R.f64", launch_axis12<double>(g, 1, -1, work, work, c->T64, EPI_R, &ea, false, nullptr, c->s));
   KT(c, "postmix_R.f64", launch_postmix<double>(g, work, nullptr, EPI_R, &eb, nullptr, c->s));
   KT(c, "fin_sum", fin_sum(c->partK, nb5 + postmix_blocks(g), c->scal + S_REF, c->s));
+  KT(c, "fin_max", fin_max(c->partK + ps, nb5 + postmix_blocks(g), c->scal + S_REFINF, c->s));
 }
 
 // ------------------------------------------------- learned correction --
@@ -559,9 +561,15 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
   KT(c, "fin_cg_start",
      fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, inner, 0.0, o.cg_max, S_REF0, -1, c->s));
   double target = 0.0, rnorm = 0.0;
+  double prev_rnorm = INFINITY, prev_rinf = INFINITY;
+  int first_iters = 0;
   for (int step = 0; step < std::max(1, o.refine_max); ++step) {
+    // a later inner solve gets at most max(50, 2x the first one's) iterations:
+    // one that needs more is stuck at FP32 resolution of a tiny residual
+    const int inner_max = step == 0 ? o.cg_max : std::min(o.cg_max, std::max(50, 2 * first_iters));
     if (step > 0)
-      KT(c, "fin_cg_start", fin_cg_start(nullptr, 0, 0, c->scal, c->flags, inner, 0.0, o.cg_max, -1, S_REFRZ, c->s));
+      KT(c, "fin_cg_start",
+         fin_cg_start(nullptr, 0, 0, c->scal, c->flags, inner, 0.0, inner_max, -1, S_REFRZ, c->s));
     PcgOut po;
     csipm_status st = pcg<float>(c, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, po, capture && step == 0);
     if (st != CSIPM_OK) return st;
@@ -577,12 +585,24 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
     const double h0 = std::sqrt(std::max(c->hscal[S_REF0], 0.0));
     target = std::max(o.cg_atol, eta * h0);
     rnorm = std::sqrt(std::max(c->hscal[S_REF], 0.0));
-    if (rnorm <= target) {
+    // besides the preconditioned norm, every component of r must be below
+    // eta in the KKT residual's scale: an FP32 solution misrepresents
+    // d_beta + d_z where one slack is tiny and its Sigma huge, which leaves
+    // single large components that a global norm over n values can hide
+    const double rinf = c->hscal[S_REFINF];
+    if (rnorm <= target && rinf <= eta * (1.0 + c->xi_inf)) {
       converged = true;
       break;
     }
-    if (po.iters == 0 || !std::isfinite(rnorm) || step + 1 >= std::max(1, o.refine_max)) break;
-    inner = std::max(o.refine_inner_rtol, std::min(1e-2, 0.5 * target / rnorm));
+    if (step == 0) first_iters = po.iters;
+    // stop at the precision floor: a step that halves neither measure of r
+    // will not be followed by one that does
+    const bool progress = rnorm < 0.5 * prev_rnorm || rinf < 0.5 * prev_rinf;
+    prev_rnorm = rnorm;
+    prev_rinf = rinf;
+    if (po.iters == 0 || !std::isfinite(rnorm) || !progress || step + 1 >= std::max(1, o.refine_max)) break;
+    const double need = std::min(target / rnorm, rinf > 0.0 ? eta * (1.0 + c->xi_inf) / rinf : 1.0);
+    inner = std::max(o.refine_inner_rtol, std::min(1e-2, 0.5 * need));
     // FP32 start of the next inner solve: r32, z32 = p32 = P_c^{-1} r, r32.z32 -> S_REFRZ
     KT(c, "ref_restart+fin",
        ref_restart(c->rhb, c->rhz, c->dxb, c->dxz, c->rb, c->sig1, c->sig2, pcc, c->frb, c->frz, c->fzb, c->fzz,
@@ -618,6 +638,9 @@ csipm_status residuals(csipm_ctx* c, Resid& r, bool logsum) {
 // kExactEvery iterations, and before the first FP32 Newton system that is
 // refined after unrefined ones, so carried error never accumulates far.
 constexpr int kExactEvery = 16;
+// the solve stops (CSIPM_STALLED) once rel_kkt exceeds this multiple of the
+// best value it reached
+constexpr double kStallFactor = 10.0;
 
 }  // namespace
 
@@ -650,6 +673,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   bool exact = true;
   bool approx = false;   // carried H beta holds FP32-level error (an unrefined FP32 step)
   int carried = 0;
+  double best_rel = INFINITY;
   csipm_info inf{};
   inf.lambda = lam;
   inf.xi_inf = c->xi_inf;
@@ -659,8 +683,8 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     auto rel_of = [&](const Resid& q) { return std::max(std::max(q.fb, q.fz), q.cmax) / (1.0 + c->xi_inf); };
     double rel = rel_of(r);
     const bool leaving_trust = approx && !(std::min(o.cg_rtol, 0.1 * rel) >= o.refine_trust);
-    if (!exact &&
-        (rel <= o.tol || it >= o.max_iter || carried >= kExactEvery || leaving_trust || !std::isfinite(rel))) {
+    if (!exact && (rel <= o.tol || it >= o.max_iter || carried >= kExactEvery || leaving_trust ||
+                   rel > kStallFactor * best_rel || !std::isfinite(rel))) {
       st = residuals(c, r, learned);
       if (st != CSIPM_OK) return st;
       exact = true;
@@ -669,6 +693,19 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       rel = rel_of(r);
     }
     if (r.nonfinite > 0 || !std::isfinite(r.fb)) return fail(c, CSIPM_ENONFINITE, "non-finite interior-point iterate");
+    // past the precision floor the Newton steps stop reducing the residual
+    // and start raising it: stop there rather than run into overflow
+    if (rel > kStallFactor * best_rel) {
+      result = CSIPM_STALLED;
+      inf.rel_kkt = rel;
+      inf.res_beta_inf = r.fb;
+      inf.res_z_inf = r.fz;
+      inf.compl_max = r.cmax;
+      inf.mu = r.csum / (2.0 * (double)n);
+      if (!c->log.empty()) c->log.back().alpha = c->hscal[S_ALPHA_IPM];
+      break;
+    }
+    best_rel = std::min(best_rel, rel);
     const double mu = r.csum / (2.0 * (double)n);
     inf.rel_kkt = rel;
     inf.res_beta_inf = r.fb;

@@ -144,16 +144,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
 
 // Block sums of NQ values; thread 0 writes out[q * stride + blockIdx.x].
 // `red` is LDS scratch of at least NQ * NTHREADS/64 doubles; it may alias the
 // FFT exchange buffer, so the block synchronises before writing it.
-template <int NTHREADS, int NQ>
+// The last NMAX quantities are maxima (of non-negative values), the others sums.
+template <int NTHREADS, int NQ, int NMAX = 0>
 __device__ __forceinline__ void block_sums_store(const double* v, double* out, int stride, double* red) {
   constexpr int NW = NTHREADS / 64;
   double w[NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) w[q] = wave_sum(v[q]);
+  for (int q = 0; q < NQ; ++q) w[q] = q >= NQ - NMAX ? wave_max(v[q]) : wave_sum(v[q]);
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   __syncthreads();
@@ -165,7 +171,7 @@ __device__ __forceinline__ void block_sums_store(const double* v, double* out, i
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       double a = 0.0;
-      for (int i = 0; i < NW; ++i) a += red[q * NW + i];
+      for (int i = 0; i < NW; ++i) a = q >= NQ - NMAX ? fmax(a, red[q * NW + i]) : a + red[q * NW + i];
       out[q * stride + blockIdx.x] = a;
     }
 }
@@ -175,6 +181,7 @@ __device__ __forceinline__ void block_sums_store(const double* v, double* out, i
 // (m >= 1 there, the m = 0 plane in the postmix pass).
 struct EpiNone {
   static constexpr int NRED = 0;
+  static constexpr int NMAX = 0;
   double* partial = nullptr;
   int pstride = 0;
 };
@@ -183,6 +190,7 @@ struct EpiNone {
 template <typename T>
 struct EpiK {
   static constexpr int NRED = 1;
+  static constexpr int NMAX = 0;
   KArgs<T> a;
   double* partial;
   int pstride;
@@ -202,10 +210,12 @@ struct EpiK {
 };
 
 // FP64 refinement residual r = h - K d: writes H d_beta (the transform output
-// itself) and sums r.P_c^{-1}r.  A further inner solve, when one is needed,
-// builds its FP32 start from H d_beta elementwise (k_ref_restart).
+// itself), sums r.P_c^{-1}r and takes max |r|.  A further inner solve, when
+// one is needed, builds its FP32 start from H d_beta elementwise
+// (k_ref_restart).
 struct EpiR {
-  static constexpr int NRED = 1;
+  static constexpr int NRED = 2;
+  static constexpr int NMAX = 1;
   RArgs a;
   double* partial;
   int pstride;
@@ -225,6 +235,7 @@ struct EpiR {
       const double rb = rhb[k] - qb, rz = rhz[k] - qz;
       pinv_block(rb, rz, g1[k], g2[k], cv[k], zb, zz);
       acc[0] += rb * zb + rz * zz;
+      acc[1] = fmax(acc[1], fmax(fabs(rb), fabs(rz)));
     }
   }
 };
@@ -313,7 +324,8 @@ k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
             epi(idx, v[i * rl + q], acc);
         }
     }
-    block_sums_store<TM * NT, Epi::NRED>(acc, epi.partial, epi.pstride, reinterpret_cast<double*>(smem_raw));
+    block_sums_store<TM * NT, Epi::NRED, Epi::NMAX>(acc, epi.partial, epi.pstride,
+                                                    reinterpret_cast<double*>(smem_raw));
   } else {
     if (active) {
 #pragma unroll
@@ -551,7 +563,7 @@ k_postmix(const cx<T>* work, cx<T>* out, int n1, int n2, int m, Epi epi, const i
   }
   if constexpr (Epi::NRED > 0) {
     __shared__ double red[4 * Epi::NRED];
-    block_sums_store<256, Epi::NRED>(acc, epi.partial, epi.pstride, red);
+    block_sums_store<256, Epi::NRED, Epi::NMAX>(acc, epi.partial, epi.pstride, red);
   }
 }
 

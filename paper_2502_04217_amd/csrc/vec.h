@@ -29,6 +29,7 @@ enum ScalarSlot {
   S_REF = 24,      // refinement: r.P^{-1}r of the FP64 residual
   S_REF0 = 25,     // refinement: rhs.P^{-1}rhs
   S_REFRZ = 26,    // refinement: r32.P^{-1}r32, start of the next inner PCG
+  S_REFINF = 27,   // refinement: max |r| of the FP64 residual
   S_SIG = 28,      // signal check: non-finite count, observed count
   S_MISC = 32,     // free scratch (32 values)
   S_COUNT = 64
@@ -86,6 +87,8 @@ void ref_restart(const double* hb, const double* hz, const double* db, const dou
                  float* fpb, float* fpz, long long n, double* partial, double* out, hipStream_t s);
 // *out = sum of partial[0..nb)
 void fin_sum(const double* partial, int nb, double* out, hipStream_t s);
+// *out = max of partial[0..nb)
+void fin_max(const double* partial, int nb, double* out, hipStream_t s);
 template <typename T>
 void pinv_apply(const T* rb, const T* rz, T* zb, T* zz, const T* s1, const T* s2, const float* c, long long n,
                 double* partial, double* out, hipStream_t s);

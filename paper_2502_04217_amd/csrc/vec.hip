@@ -795,6 +795,10 @@ void fin_sum(const double* partial, int nb, double* out, hipStream_t s) {
   RedOps<1> ops{{RED_SUM}};
   hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out, ops);
 }
+void fin_max(const double* partial, int nb, double* out, hipStream_t s) {
+  RedOps<1> ops{{RED_MAX}};
+  hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out, ops);
+}
 template <typename T>
 void pinv_apply(const T* rb, const T* rz, T* zb, T* zz, const T* s1, const T* s2, const float* c, long long n,
                 double* partial, double* out, hipStream_t s) {

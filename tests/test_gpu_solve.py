@@ -1,5 +1,5 @@
 """GPU interior-point solves against the CPU oracle: final beta within 1e-7
-relative (both sides stopped at rel_kkt 1e-12), identical support above
+relative (both sides stopped at rel_kkt 1e-11), identical support above
 1e-6 max|beta|, on the 16^3 (5 seeds) and
 64^3 workloads, in FP64 and FP32-with-refinement; closed forms (nothing
 missing -> soft threshold, lambda >= ||xi||_inf -> 0); the LASSO certificate
@@ -13,12 +13,13 @@ from tests._gpu_common import need_gpu, rel2, say
 
 pytestmark = pytest.mark.gpu
 
-# Both sides stop at rel_kkt <= 1e-12 before comparing.  Coordinates next to
+# Both sides stop at rel_kkt <= 1e-11 before comparing.  Coordinates next to
 # the support (|g_i| close to lambda) approach their limit only like
 # mu / (lambda - |g_i|), so two runs stopped at 1e-10 can still differ by
 # ~2e-7 (16^3 seed 2: the oracle at 1e-10 is 1.7e-7 from its own 1e-14
-# solution); at 1e-12 every workload here is within 1e-10 of it.
-PARITY_TOL = 1e-12
+# solution); at 1e-11 every workload here is within 1e-9 of it, and the FP32
+# form stays above its precision floor (mu ~ 1e-14 on 64^3).
+PARITY_TOL = 1e-11
 
 
 def _supports_match(bg, bo, rel=1e-6):
@@ -127,6 +128,19 @@ def test_large_lambda_zero():
     assert np.abs(beta).max() < 1e-8
 
 
+def test_precision_floor_stops_cleanly():
+    """A tolerance below what the FP32 form can reach (64^3, 1e-14) ends with
+    OK or STALLED and a usable iterate, never with overflow."""
+    w = wl.grid64(1)
+    lam = ipm.lambda_rule(w.signal, w.observed)
+    ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=PARITY_TOL))
+    pr, info, beta = _gpu_solve(w, lam, tol=1e-14, precision=1)
+    say("  floor", info["status_name"], info["ipm_iters"], info["rel_kkt"])
+    assert info["status"] in (0, 2)
+    assert info["rel_kkt"] <= 1e-9
+    assert rel2(beta, ref.state.beta) <= 1e-6
+
+
 def test_iteration_limit_status():
     w = wl.grid16(1)
     lam = ipm.lambda_rule(w.signal, w.observed)
@@ -187,3 +201,31 @@ def test_kernel_timing_records():
     assert all(r["total_ms"] > 0 and r["working_calls"] == r["calls"] for r in rep)
     pr.solve(tol=1e-6, precision=1)
     assert pr.timing_report(0.0) == rep
+
+
+def test_grid512_fp32_tracks_fp64():
+    """512^3 (the full-size workload): the FP32 form with the paper's P
+    follows the FP64 form iteration by iteration and converges with it.
+    Regression: a refinement test on the preconditioned norm alone let FP32
+    solutions through whose d_beta + d_z was misrepresented where one slack
+    is tiny; the single large residual components then grew rel_kkt from
+    7e-6 back to 1e-1 and the solve never converged."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid512(1)
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.lambda_rule(0.05)
+    i64 = pr.solve(tol=1e-6, precision=0, max_iter=30)
+    log64 = pr.log()
+    b64 = pr.get(csipm.BETA)
+    i32 = pr.solve(tol=1e-6, precision=1, pc=0, max_iter=30)
+    log32 = pr.log()
+    b32 = pr.get(csipm.BETA)
+    say("512^3 fp64", i64["ipm_iters"], i64["rel_kkt"], "fp32", i32["ipm_iters"], i32["rel_kkt"])
+    assert i64["status"] == 0 and i32["status"] == 0
+    assert i32["ipm_iters"] <= i64["ipm_iters"] + 1
+    for a, b in zip(log32, log64):
+        assert abs(a["rel_kkt"] - b["rel_kkt"]) <= 0.05 * b["rel_kkt"]
+    assert float((b32 - b64).norm() / b64.norm()) <= 1e-4
+    del pr
+    torch.cuda.empty_cache()
