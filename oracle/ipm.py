@@ -30,9 +30,13 @@ implementation"):
   * stop when rel_kkt = max(||F_beta||_inf, ||F_z||_inf, max_i s_i nu_i)
     / (1 + ||xi||_inf) <= tol, where F_beta = H beta - xi - nu1 + nu2 and
     F_z = lambda e - nu1 - nu2 are the first two rows of "kkt";
-  * K is solved by textbook PCG with the paper's preconditioner
+  * K is solved by textbook PCG (or, as an option, preconditioned CR) with
+    the paper's preconditioner
     P = [[I + L1, L2], [L2, L1]] (section "Krylov methods and
-    preconditioners"), x0 = 0, stopping on the preconditioned residual norm
+    preconditioners"; as an option its scaled-identity relative
+    [[rho I + L1, L2], [L2, L1]], the variant the paper attributes to earlier
+    work, with rho tied to the observed fraction), x0 = 0, stopping on the
+    preconditioned residual norm
     sqrt(r^T P^{-1} r) <= max(cg_atol, eta sqrt(r0^T P^{-1} r0)),
     eta = min(cg_rtol, 0.1 rel_kkt).
 """
@@ -126,6 +130,49 @@ def pcg(apply_K, apply_Pinv, rb, rz, *, atol=0.0, rtol=1e-10, maxit=500):
     return PCGResult(xb, xz, it, hist, hist[-1] <= tol)
 
 
+def pcr(apply_K, apply_Pinv, rb, rz, *, atol=0.0, rtol=1e-10, maxit=500):
+    """Preconditioned conjugate residuals (the CR method of Hestenes and
+    Stiefel, which section "Krylov methods and preconditioners" lists beside
+    CG) on the 2n-vector blocks, x0 = 0.  With z = P^{-1} r and w = K z,
+    each step takes alpha = (z.w) / (q.P^{-1}q) along p, where q = K p, and
+    the next direction p = z + beta p with beta = (z.w)_new / (z.w)_old
+    (q = w + beta q follows without a second product).  The iterates
+    minimise ||b - K x|| in the P^{-1} norm over the Krylov space.  Stops on
+    the same preconditioned residual norm as pcg."""
+    xb = np.zeros_like(rb)
+    xz = np.zeros_like(rz)
+    rb = rb.copy()
+    rz = rz.copy()
+    zb, zz = apply_Pinv(rb, rz)
+    rho = float(np.sum(rb * zb) + np.sum(rz * zz))
+    hist = [math.sqrt(max(rho, 0.0))]
+    tol = max(atol, rtol * hist[0])
+    it = 0
+    zw_old = None
+    pb = pz = qb = qz = None
+    while hist[-1] > tol and it < maxit:
+        wb, wz = apply_K(zb, zz)
+        zw = float(np.sum(zb * wb) + np.sum(zz * wz))
+        if zw_old is None:
+            pb, pz, qb, qz = zb.copy(), zz.copy(), wb, wz
+        else:
+            beta = zw / zw_old
+            pb, pz = zb + beta * pb, zz + beta * pz
+            qb, qz = wb + beta * qb, wz + beta * qz
+        ub, uz = apply_Pinv(qb, qz)
+        alpha = zw / float(np.sum(qb * ub) + np.sum(qz * uz))
+        xb += alpha * pb
+        xz += alpha * pz
+        rb -= alpha * qb
+        rz -= alpha * qz
+        zb, zz = apply_Pinv(rb, rz)
+        zw_old = zw
+        rho = float(np.sum(rb * zb) + np.sum(rz * zz))
+        it += 1
+        hist.append(math.sqrt(max(rho, 0.0)))
+    return PCGResult(xb, xz, it, hist, hist[-1] <= tol)
+
+
 # ---------------------------------------------------------------------- IPM --
 
 @dataclasses.dataclass
@@ -137,6 +184,8 @@ class IPMOptions:
     cg_max: int = 500
     cg_rtol: float = 1e-2
     cg_atol: float = 0.0
+    krylov: str = "cg"              # "cg" (pcg) or "cr" (pcr)
+    pc_rho: float | None = None     # C = rho I: the scaled-identity variant of P
 
 
 @dataclasses.dataclass
@@ -233,9 +282,10 @@ def ipm_solve(signal, observed, lam, opts: IPMOptions | None = None,
         sig2 = st.nu2 / s2
         rb, rz = newton_rhs(st, Hb, xi, lam, opts.sigma, mu)
         eta = min(opts.cg_rtol, 0.1 * rel)
-        res = pcg(lambda pb, pz: K_apply(pb, pz, sig1, sig2, observed),
-                  lambda qb, qz: Pinv_apply(qb, qz, sig1, sig2),
-                  rb, rz, atol=opts.cg_atol, rtol=eta, maxit=opts.cg_max)
+        solver = pcr if opts.krylov == "cr" else pcg
+        res = solver(lambda pb, pz: K_apply(pb, pz, sig1, sig2, observed),
+                     lambda qb, qz: Pinv_apply(qb, qz, sig1, sig2, opts.pc_rho),
+                     rb, rz, atol=opts.cg_atol, rtol=eta, maxit=opts.cg_max)
         db, dz = res.xb, res.xz
         ds1, ds2, dnu1, dnu2 = recover_dnu(st, db, dz, sig1, sig2, opts.sigma, mu)
         amax = min(max_step(s1, ds1), max_step(s2, ds2),

@@ -264,3 +264,80 @@ def test_limit_condition_number_tiny():
     q = np.linalg.eigvalsh(Hd[np.ix_(act, act)])
     expected = np.sort(np.concatenate([np.ones(2 * n - len(act)), q]))
     assert np.abs(ev - expected).max() < 1e-4
+
+
+# ------------------------------------------------- CR and the scaled P --
+
+def _dense_system(m, seed):
+    """A random SPD 2m x 2m K with the block structure [[G + L1, L2], [L2, L1]]
+    (G a random PSD matrix standing in for H) and random barrier diagonals."""
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((m, m // 2))
+    G = B @ B.T / m
+    s1 = np.exp(rng.uniform(-2, 2, m))
+    s2 = np.exp(rng.uniform(-2, 2, m))
+    L1, L2 = s1 + s2, s1 - s2
+    K = np.block([[G + np.diag(L1), np.diag(L2)], [np.diag(L2), np.diag(L1)]])
+    applyK = lambda pb, pz: (G @ pb + L1 * pb + L2 * pz, L2 * pb + L1 * pz)
+    return K, applyK, s1, s2, rng
+
+
+def test_pcr_solves_dense_system_and_is_exact_for_K_equal_P():
+    m = 24
+    K, applyK, s1, s2, rng = _dense_system(m, 5)
+    b = rng.standard_normal(2 * m)
+    pinv = lambda rb, rz: ipm.Pinv_apply(rb, rz, s1, s2)
+    out = ipm.pcr(applyK, pinv, b[:m], b[m:], rtol=1e-13, maxit=200)
+    x = np.linalg.solve(K, b)
+    assert out.converged
+    assert np.abs(np.concatenate([out.xb, out.xz]) - x).max() < 1e-10 * np.abs(x).max()
+    # K = P (G = I): one step
+    applyP = lambda pb, pz: ipm.P_apply(pb, pz, s1, s2)
+    one = ipm.pcr(applyP, pinv, b[:m], b[m:], rtol=1e-10)
+    assert one.iters == 1
+
+
+def test_pcr_iterates_minimise_preconditioned_residual_over_krylov_space():
+    """x_k = argmin over K_k(P^{-1}K, P^{-1}b) of (b - Kx)^T P^{-1} (b - Kx),
+    computed by a dense weighted least-squares solve on the Krylov basis."""
+    m = 20
+    K, applyK, s1, s2, rng = _dense_system(m, 9)
+    b = rng.standard_normal(2 * m)
+    Pinv = np.zeros((2 * m, 2 * m))
+    for j in range(2 * m):
+        e = np.zeros(2 * m)
+        e[j] = 1.0
+        zb, zz = ipm.Pinv_apply(e[:m], e[m:], s1, s2)
+        Pinv[:, j] = np.concatenate([zb, zz])
+    pinv = lambda rb, rz: ipm.Pinv_apply(rb, rz, s1, s2)
+    res_prev = math.inf
+    for k in (1, 2, 3, 5):
+        out = ipm.pcr(applyK, pinv, b[:m], b[m:], rtol=0.0, maxit=k)
+        xk = np.concatenate([out.xb, out.xz])
+        V = [Pinv @ b]
+        for _ in range(k - 1):
+            V.append(Pinv @ (K @ V[-1]))
+        V = np.array(V).T
+        KV = K @ V
+        y = np.linalg.solve(KV.T @ Pinv @ KV, KV.T @ Pinv @ b)
+        assert np.abs(xk - V @ y).max() < 1e-8 * np.abs(V @ y).max()
+        r = b - K @ xk
+        res = float(r @ Pinv @ r)
+        assert res <= res_prev * (1 + 1e-12)
+        res_prev = res
+
+
+def test_cr_and_scaled_preconditioner_reach_the_lasso_solution():
+    """The Krylov method and the preconditioner change only how each Newton
+    system is solved: CR, and the scaled-identity P with rho = m/n, reach the
+    solution of the plain PCG solve."""
+    w = wl.grid16(4)
+    lam = ipm.lambda_rule(w.signal, w.observed)
+    ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-11))
+    rho = float(w.observed.mean())
+    for opts in (ipm.IPMOptions(tol=1e-11, krylov="cr"), ipm.IPMOptions(tol=1e-11, pc_rho=rho),
+                 ipm.IPMOptions(tol=1e-11, krylov="cr", pc_rho=rho)):
+        res = ipm.ipm_solve(w.signal, w.observed, lam, opts)
+        assert res.converged
+        err = np.linalg.norm(res.state.beta - ref.state.beta) / np.linalg.norm(ref.state.beta)
+        assert err < 1e-8, (opts, err)
