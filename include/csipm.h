@@ -57,7 +57,15 @@ typedef enum {
 } csipm_status;
 
 typedef enum { CSIPM_FP64 = 0, CSIPM_FP32 = 1 } csipm_precision;
-typedef enum { CSIPM_PC_PLAIN = 0, CSIPM_PC_LEARNED = 1 } csipm_pc;
+/* Preconditioner of the Newton systems (sec. "Krylov methods and
+ * preconditioners"): the paper's P = [[I + L1, L2], [L2, L1]]; P with the
+ * learned diagonal correction C = diag(c) in place of I; or the scaled
+ * identity rho I in place of I (the variant the paper compares P with). */
+typedef enum { CSIPM_PC_PLAIN = 0, CSIPM_PC_LEARNED = 1, CSIPM_PC_SCALED = 2 } csipm_pc;
+/* Krylov method of the Newton systems: CG, or conjugate residuals (CR,
+ * which the same section lists beside CG): alpha = (z.Kz)/(q.P^{-1}q), one
+ * K-apply per iteration, residual minimised in the P^{-1} norm. */
+typedef enum { CSIPM_KRYLOV_CG = 0, CSIPM_KRYLOV_CR = 1 } csipm_krylov;
 typedef enum {
   CSIPM_BETA = 0, CSIPM_Z = 1, CSIPM_NU1 = 2, CSIPM_NU2 = 3,
   CSIPM_XI = 4,       /* M_perp^T b, fixed at creation                        */
@@ -98,6 +106,11 @@ typedef struct {
                           systems after a one-iteration solve use the paper's
                           P, which already makes them one-iteration solves);
                           0 = every system                                   */
+  int krylov;          /* csipm_krylov (default CG); the learned
+                          correction's training capture needs CG             */
+  double pc_rho;       /* CSIPM_PC_SCALED: rho (default 0 = m/n, the
+                          observed fraction: H = M_perp^T M_perp has mean
+                          diagonal m/n)                                      */
 } csipm_options;
 
 typedef struct {

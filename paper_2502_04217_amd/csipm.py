@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libcsipm.so")
 MLP_PARAMS = 1249
 
 FP64, FP32 = 0, 1
-PC_PLAIN, PC_LEARNED = 0, 1
+PC_PLAIN, PC_LEARNED, PC_SCALED = 0, 1, 2
+KRYLOV_CG, KRYLOV_CR = 0, 1
 BETA, Z, NU1, NU2, XI, DIAG_H, PC_C = range(7)
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "STALLED", 3: "FELL_BACK", -1: "EINVAL", -2: "ENOMEM",
@@ -34,7 +35,8 @@ class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("cg_max", C.c_int), ("cg_rtol", C.c_double),
                 ("cg_atol", C.c_double), ("sigma", C.c_double), ("tau", C.c_double), ("precision", C.c_int),
                 ("pc", C.c_int), ("refine_max", C.c_int), ("refine_inner_rtol", C.c_double),
-                ("refine_trust", C.c_double), ("pc_min_cg", C.c_int)]
+                ("refine_trust", C.c_double), ("pc_min_cg", C.c_int), ("krylov", C.c_int),
+                ("pc_rho", C.c_double)]
 
 
 class Info(C.Structure):

@@ -54,6 +54,7 @@ struct csipm_ctx {
   double *rb, *rz, *zb, *zz, *pb, *pz, *qb, *qz, *work;
   // FP32 Krylov set
   float *sig1f, *sig2f, *frb, *frz, *fzb, *fzz, *fpb, *fpz, *fqb, *fqz, *fxb, *fxz, *fwork;
+  float *fwb, *fwz;   // FP32 w = K z of conjugate residuals
   // learned correction
   float *pc_c, *feat, *mlp_params;
   uint32_t* mask;
@@ -156,8 +157,8 @@ size_t layout(Carver& cv, csipm_ctx* c, int n1, int n2, int n3) {
                     &c->dxb, &c->dxz, &c->diagH, &c->rb, &c->rz, &c->zb, &c->zz, &c->pb, &c->pz, &c->qb,
                     &c->qz, &c->work};
   for (double** p : d64) *p = cv.take<double>(n);
-  float** f32[] = {&c->sig1f, &c->sig2f, &c->frb, &c->frz, &c->fzb, &c->fzz, &c->fpb, &c->fpz,
-                   &c->fqb,   &c->fqz,   &c->fxb, &c->fxz, &c->fwork, &c->pc_c};
+  float** f32[] = {&c->sig1f, &c->sig2f, &c->frb, &c->frz, &c->fzb,   &c->fzz,  &c->fpb, &c->fpz,
+                   &c->fqb,   &c->fqz,   &c->fxb, &c->fxz, &c->fwork, &c->pc_c, &c->fwb, &c->fwz};
   for (float** p : f32) *p = cv.take<float>(n);
   c->feat = cv.take<float>(4 * n);
   c->mlp_params = cv.take<float>(CSIPM_MLP_PARAMS);
@@ -299,18 +300,19 @@ void capture_pair(csipm_ctx* c, const T* pb, const T* pz, const T* qb, const T* 
 
 // ------------------------------------------------------------------- PCG --
 struct PcgSet {
-  void *rb, *rz, *zb, *zz, *pb, *pz, *qb, *qz, *work;
+  void *rb, *rz, *zb, *zz, *pb, *pz, *qb, *qz, *work, *wb, *wz;
 };
 
 template <typename T>
 PcgSet pcg_set(csipm_ctx* c);
 template <>
 PcgSet pcg_set<double>(csipm_ctx* c) {
-  return {c->rb, c->rz, c->zb, c->zz, c->pb, c->pz, c->qb, c->qz, c->work};
+  // w of conjugate residuals: the FP64 right-hand side copy is idle in the FP64 form
+  return {c->rb, c->rz, c->zb, c->zz, c->pb, c->pz, c->qb, c->qz, c->work, c->rhb, c->rhz};
 }
 template <>
 PcgSet pcg_set<float>(csipm_ctx* c) {
-  return {c->frb, c->frz, c->fzb, c->fzz, c->fpb, c->fpz, c->fqb, c->fqz, c->fwork};
+  return {c->frb, c->frz, c->fzb, c->fzz, c->fpb, c->fpz, c->fqb, c->fqz, c->fwork, c->fwb, c->fwz};
 }
 
 struct PcgOut {
@@ -363,6 +365,54 @@ csipm_status pcg(csipm_ctx* c, T* xb, T* xz, const T* s1, const T* s2, const flo
   return CSIPM_OK;
 }
 
+// Preconditioned conjugate residuals on K x = h from the same start as pcg
+// (r = h and z = P^{-1}r in the Krylov vectors, finalised by
+// k_fin_cg_init); stops on the same sqrt(r.P^{-1}r) test.  Per iteration:
+// w = K z (with z.w), then p = z + beta p and q = w + beta q (with
+// q.P^{-1}q), then the update of x, r and z = P^{-1}r that CG uses.
+template <typename T>
+csipm_status pcr(csipm_ctx* c, T* xb, T* xz, const T* s1, const T* s2, const float* pcc, PcgOut& out) {
+  const long long n = c->g.n;
+  PcgSet v = pcg_set<T>(c);
+  T *rb = (T*)v.rb, *rz = (T*)v.rz, *zb = (T*)v.zb, *zz = (T*)v.zz, *pb = (T*)v.pb, *pz = (T*)v.pz,
+    *qb = (T*)v.qb, *qz = (T*)v.qz, *work = (T*)v.work, *wb = (T*)v.wb, *wz = (T*)v.wz;
+  const int nbv = vec_blocks(n);
+  const int* skip = c->flags + F_DONE;
+  int chunk = 2;
+  bool first = true;
+  for (;;) {
+    for (int k = 0; k < chunk; ++k) {
+      const int nbk = op_K<T>(c, zb, zz, s1, s2, wb, wz, work, skip);
+      KT(c, "fin_cr_zw", fin_cr_zw(c->partK, nbk, c->scal, c->flags, first, c->s));
+      KT(c, PN(T, "cr_dir"),
+         cr_dir<T>(pb, pz, qb, qz, zb, zz, wb, wz, s1, s2, pcc, c->scal, c->flags, n, c->partV, first, c->s));
+      KT(c, "fin_alpha", fin_alpha(c->partV, nbv, c->scal, c->flags, c->s));
+      KT(c, PN(T, "cg_update"), cg_update<T>(xb, xz, pb, pz, qb, qz, rb, rz, zb, zz, s1, s2, pcc, c->scal, c->flags,
+                                            n, c->partV, first, c->s));
+      first = false;
+      KT(c, "fin_rz", fin_rz(c->partV, nbv, c->scal, c->flags, c->s));
+    }
+    csipm_status st = sync_scalars(c, "pcr");
+    if (st != CSIPM_OK) return st;
+    if (c->hflags[F_DONE]) break;
+    chunk = std::min(chunk * 2, 16);
+  }
+  out.iters = c->hflags[F_IT];
+  out.breakdown = c->hflags[F_BREAK] != 0;
+  out.res0 = std::sqrt(std::max(c->hscal[S_RZ0], 0.0));
+  out.res = c->hscal[S_RES];
+  out.converged = out.res <= c->hscal[S_TOL];
+  return CSIPM_OK;
+}
+
+// The Newton systems' Krylov method (options.krylov); capture needs CG.
+template <typename T>
+csipm_status krylov(csipm_ctx* c, int method, T* xb, T* xz, const T* s1, const T* s2, const float* pcc, PcgOut& out,
+                    bool capture) {
+  if (method == CSIPM_KRYLOV_CR) return pcr<T>(c, xb, xz, s1, s2, pcc, out);
+  return pcg<T>(c, xb, xz, s1, s2, pcc, out, capture);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- C-ABI --
@@ -383,6 +433,8 @@ void csipm_default_options(csipm_options* o) {
   o->refine_inner_rtol = 1e-5;
   o->refine_trust = 1e-4;
   o->pc_min_cg = 2;
+  o->krylov = CSIPM_KRYLOV_CG;
+  o->pc_rho = 0.0;
 }
 
 size_t csipm_workspace_bytes(int n1, int n2, int n3) {
@@ -522,7 +574,7 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
     KT(c, "fin_cg_start",
        fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, eta, o.cg_atol, o.cg_max, -1, -1, c->s));
     PcgOut po;
-    csipm_status st = pcg<double>(c, c->dxb, c->dxz, c->sig1, c->sig2, pcc, po, capture);
+    csipm_status st = krylov<double>(c, o.krylov, c->dxb, c->dxz, c->sig1, c->sig2, pcc, po, capture);
     cg_iters = po.iters;
     converged = po.converged;
     return st;
@@ -550,7 +602,7 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
     KT(c, "fin_cg_start",
        fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, inner, 0.0, o.cg_max, -1, -1, c->s));
     PcgOut po;
-    csipm_status st = pcg<float>(c, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, po, capture);
+    csipm_status st = krylov<float>(c, o.krylov, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, po, capture);
     if (st != CSIPM_OK) return st;
     cg_iters = po.iters;
     converged = po.converged;
@@ -571,7 +623,7 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
       KT(c, "fin_cg_start",
          fin_cg_start(nullptr, 0, 0, c->scal, c->flags, inner, 0.0, inner_max, -1, S_REFRZ, c->s));
     PcgOut po;
-    csipm_status st = pcg<float>(c, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, po, capture && step == 0);
+    csipm_status st = krylov<float>(c, o.krylov, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, po, capture && step == 0);
     if (st != CSIPM_OK) return st;
     cg_iters += po.iters;
     if (step == 0)
@@ -651,7 +703,9 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   csipm_default_options(&o);
   if (opts) o = *opts;
   if (!(o.tol > 0) || o.max_iter < 0 || o.cg_max < 1 || !(o.sigma > 0 && o.sigma < 1) || !(o.tau > 0 && o.tau < 1) ||
-      (o.precision != CSIPM_FP64 && o.precision != CSIPM_FP32) || (o.pc != CSIPM_PC_PLAIN && o.pc != CSIPM_PC_LEARNED) ||
+      (o.precision != CSIPM_FP64 && o.precision != CSIPM_FP32) ||
+      (o.pc != CSIPM_PC_PLAIN && o.pc != CSIPM_PC_LEARNED && o.pc != CSIPM_PC_SCALED) ||
+      (o.krylov != CSIPM_KRYLOV_CG && o.krylov != CSIPM_KRYLOV_CR) || !(o.pc_rho >= 0.0) ||
       !(o.refine_trust >= 0.0 && o.refine_trust <= 1.0) || !(o.refine_inner_rtol > 0.0) || o.pc_min_cg < 0)
     return fail(c, CSIPM_EINVAL, "invalid options");
   if (o.pc == CSIPM_PC_LEARNED && !c->have_params) return fail(c, CSIPM_ESTATE, "learned preconditioner has no parameters");
@@ -663,6 +717,13 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   c->cap_cg.clear();
   const double z0 = c->xi_inf > 0 ? c->xi_inf : 1.0;
   const bool learned = o.pc == CSIPM_PC_LEARNED;
+  // scaled identity: c = rho everywhere, rho = m/n unless given
+  const float* pc_fixed = nullptr;
+  if (o.pc == CSIPM_PC_SCALED) {
+    const double rho = o.pc_rho > 0.0 ? o.pc_rho : (double)c->nobs / (double)n;
+    KT(c, "fill", fill<float>(c->pc_c, (float)rho, n, c->s));
+    pc_fixed = c->pc_c;
+  }
   // the start beta = 0 has H beta = 0 exactly
   KT(c, "ipm_init", ipm_init(c->beta, c->z, c->nu1, c->nu2, c->hb, n, z0, lam, c->s));
   KT(c, "ipm_resid+fin",
@@ -726,7 +787,8 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     int cgi = 0, ref = 0;
     bool conv = false, fell = false;
     HdSource src = HD_RRES64;
-    const bool capture = c->cap_enable && o.pc == CSIPM_PC_PLAIN && c->cap_count < c->cap_max;
+    const bool capture =
+        c->cap_enable && o.pc == CSIPM_PC_PLAIN && o.krylov == CSIPM_KRYLOV_CG && c->cap_count < c->cap_max;
     // the correction is applied once a Newton system has needed more than
     // pc_min_cg - 1 PCG iterations: a system the paper's P solves in one
     // iteration leaves nothing to gain
@@ -749,7 +811,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
         ++inf.fallbacks;
       }
     } else {
-      st = newton_solve(c, o, smu, eta, nullptr, cgi, ref, conv, capture, src);
+      st = newton_solve(c, o, smu, eta, pc_fixed, cgi, ref, conv, capture, src);
       if (st != CSIPM_OK) return st;
       if (capture) {
         mlp_scale_weights(c->cap_rec + (size_t)c->cap_count * c->cap_per_iter * MLP_REC, c->cap_per_iter,

@@ -23,6 +23,7 @@ enum ScalarSlot {
   S_BETA = 4,      // CG direction update
   S_TOL = 5,       // stopping threshold on sqrt(r.P^{-1}r)
   S_RES = 6,       // sqrt(r.P^{-1}r) now
+  S_ZW = 7,        // conjugate residuals: z.K z of the current iterate
   S_AMAX = 8,      // IPM: largest feasible step
   S_ALPHA_IPM = 9, // IPM: step taken
   S_RESID = 16,    // IPM residual block, 8 values (k_ipm_resid order)
@@ -46,6 +47,13 @@ void cg_update(T* xb, T* xz, const T* pb, const T* pz, const T* qb, const T* qz,
 template <typename T>
 void cg_pupdate(T* pb, T* pz, const T* zb, const T* zz, const double* scal, const int* flags, long long n,
                 hipStream_t s);
+// conjugate residuals: p = z + beta p, q = w + beta q (p = z, q = w first),
+// partial q.P_c^{-1}q; and the finalize after w = K z (beta, alpha's numerator)
+template <typename T>
+void cr_dir(T* pb, T* pz, T* qb, T* qz, const T* zb, const T* zz, const T* wb, const T* wz, const T* s1, const T* s2,
+            const float* c, const double* scal, const int* flags, long long n, double* partial, bool first,
+            hipStream_t s);
+void fin_cr_zw(const double* partial, int nb, double* scal, int* flags, bool first, hipStream_t s);
 // rz0 from partial quantity 0 (or scal[from_slot] when >= 0); quantity 1
 // (at partial + stride) summed into scal[ref_slot] when ref_slot >= 0
 void fin_cg_start(const double* partial, int nb, int stride, double* scal, int* flags, double eta, double atol,

@@ -168,6 +168,46 @@ k_cg_pupdate(T* __restrict__ pb, T* __restrict__ pz, const T* __restrict__ zb, c
   }
 }
 
+// Conjugate residuals, direction step: p = z + beta p and q = w + beta q
+// (p = z, q = w on the first iteration), where w = K z came from the
+// K-apply; partial sums of q.P_c^{-1}q, the denominator of alpha.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_cr_dir(T* __restrict__ pb, T* __restrict__ pz, T* __restrict__ qb, T* __restrict__ qz,
+         const T* __restrict__ zb, const T* __restrict__ zz, const T* __restrict__ wb, const T* __restrict__ wz,
+         const T* __restrict__ s1, const T* __restrict__ s2, const float* __restrict__ c,
+         const double* __restrict__ scal, const int* __restrict__ flags, long long n, double* partial, int first) {
+  CSIPM_ALIGN(pb);
+  CSIPM_ALIGN(pz);
+  CSIPM_ALIGN(qb);
+  CSIPM_ALIGN(qz);
+  CSIPM_ALIGN(zb);
+  CSIPM_ALIGN(zz);
+  CSIPM_ALIGN(wb);
+  CSIPM_ALIGN(wz);
+  CSIPM_ALIGN(s1);
+  CSIPM_ALIGN(s2);
+
+  if (flags[F_DONE]) return;
+  const T be = first ? T(0) : (T)scal[S_BETA];
+  double acc = 0.0;
+  CSIPM_PAIRS(n) {
+    const T p1 = first ? zb[i] : zb[i] + be * pb[i];
+    const T p2 = first ? zz[i] : zz[i] + be * pz[i];
+    const T q1 = first ? wb[i] : wb[i] + be * qb[i];
+    const T q2 = first ? wz[i] : wz[i] + be * qz[i];
+    pb[i] = p1;
+    pz[i] = p2;
+    qb[i] = q1;
+    qz[i] = q2;
+    T u1, u2;
+    pinv1<T>(q1, q2, s1[i], s2[i], c ? (double)c[i] : 1.0, u1, u2);
+    acc += (double)q1 * (double)u1 + (double)q2 * (double)u2;
+  }
+  const int op = RED_SUM;
+  block_reduce_store<1>(&acc, &op, partial, 0);
+}
+
 __device__ __forceinline__ double fin_sum(const double* partial, int nb) {
   double a = 0.0;
   for (int i = threadIdx.x; i < nb; i += 256) a += partial[i];
@@ -227,6 +267,25 @@ k_fin_rz(const double* partial, int nb, double* scal, int* flags) {
     const int it = flags[F_IT] + 1;
     flags[F_IT] = it;
     flags[F_DONE] = (r <= scal[S_TOL] || it >= flags[F_MAXIT] || !isfinite(rz)) ? 1 : 0;
+  }
+}
+
+// Conjugate residuals, after w = K z: beta = (z.w) / (z.w)_previous (not on
+// the first iteration), and S_RZ = z.w, the numerator of alpha.  A
+// non-positive or non-finite z.w ends the solve.
+__global__ void __launch_bounds__(256)
+k_fin_cr_zw(const double* partial, int nb, double* scal, int* flags, int first) {
+  if (flags[F_DONE]) return;
+  const double zw = fin_sum(partial, nb);
+  if (threadIdx.x == 0) {
+    if (!(zw > 0.0) || !isfinite(zw)) {
+      flags[F_BREAK] = 1;
+      flags[F_DONE] = 1;
+      return;
+    }
+    if (!first) scal[S_BETA] = zw / scal[S_ZW];
+    scal[S_ZW] = zw;
+    scal[S_RZ] = zw;
   }
 }
 
@@ -748,6 +807,16 @@ void set_f2d(double* db, double* dz, const float* eb, const float* ez, long long
 void fin_alpha(const double* partial, int nb, double* scal, int* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, s, partial, nb, scal, flags);
 }
+template <typename T>
+void cr_dir(T* pb, T* pz, T* qb, T* qz, const T* zb, const T* zz, const T* wb, const T* wz, const T* s1, const T* s2,
+            const float* c, const double* scal, const int* flags, long long n, double* partial, bool first,
+            hipStream_t s) {
+  hipLaunchKernelGGL((k_cr_dir<T>), VB, pb, pz, qb, qz, zb, zz, wb, wz, s1, s2, c, scal, flags, n, partial,
+                     first ? 1 : 0);
+}
+void fin_cr_zw(const double* partial, int nb, double* scal, int* flags, bool first, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_cr_zw, dim3(1), dim3(256), 0, s, partial, nb, scal, flags, first ? 1 : 0);
+}
 void fin_rz(const double* partial, int nb, double* scal, int* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(256), 0, s, partial, nb, scal, flags);
 }
@@ -847,6 +916,8 @@ void diag_h(const double* bm_ext, double* out_ext, int n1, int n2, int n3, doubl
                                const double*, double, double, double*, double*, double*, double*, T*, T*,      \
                                const float*, T*, T*, T*, T*, T*, T*, long long, double*, hipStream_t);         \
   template void cg_pupdate<T>(T*, T*, const T*, const T*, const double*, const int*, long long, hipStream_t);  \
+  template void cr_dir<T>(T*, T*, T*, T*, const T*, const T*, const T*, const T*, const T*, const T*,         \
+                          const float*, const double*, const int*, long long, double*, bool, hipStream_t);   \
   template void pinv_apply<T>(const T*, const T*, T*, T*, const T*, const T*, const float*, long long,        \
                               double*, double*, hipStream_t);                                                  \
   template void fill<T>(T*, T, long long, hipStream_t);

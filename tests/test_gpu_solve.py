@@ -229,3 +229,27 @@ def test_grid512_fp32_tracks_fp64():
     assert float((b32 - b64).norm() / b64.norm()) <= 1e-4
     del pr
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("krylov,scaled", [(1, False), (0, True), (1, True)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cr_and_scaled_pc_parity(krylov, scaled, precision):
+    """Conjugate residuals and the scaled-identity preconditioner (rho = m/n)
+    against the oracle's pcr / pc_rho: same LASSO solution; in FP64 the same
+    Krylov iteration counts over the first interior-point iterations."""
+    from paper_2502_04217_amd import csipm
+    w = wl.grid64(1)
+    lam = ipm.lambda_rule(w.signal, w.observed)
+    rho = float(w.observed.mean()) if scaled else None
+    ref = ipm.ipm_solve(w.signal, w.observed, lam,
+                        ipm.IPMOptions(tol=PARITY_TOL, krylov="cr" if krylov else "cg", pc_rho=rho))
+    assert ref.converged
+    pr, info, beta = _gpu_solve(w, lam, tol=PARITY_TOL, precision=precision, krylov=krylov,
+                                pc=csipm.PC_SCALED if scaled else csipm.PC_PLAIN)
+    say("  cr/scaled", krylov, scaled, precision, info["status_name"], info["ipm_iters"], info["cg_iters_total"],
+        "oracle", ref.iters, sum(ref.cg_iters))
+    assert info["status"] == 0
+    assert rel2(beta, ref.state.beta) <= 1e-7
+    if precision == 0:
+        for a, b in zip(pr.log()[:6], ref.log[:6]):
+            assert a["cg_iters"] == b["cg"]
