@@ -342,12 +342,16 @@ k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
 // ------------------------------------------------------ axis-3 (c2r/r2c) --
 template <typename T>
 constexpr int a3_e(int L) { return L < 8 ? L : 8; }   // 8 elements per thread (measured best)
+// one wave per workgroup: the pass synchronises between its many LDS
+// stages, and at 256^3 the single-wave group is the fastest tile measured
+// (4 pencils of 128 at 8 elements per thread)
+constexpr int kA3Threads = 64;
 template <typename T>
 constexpr int a3_pad(int L) { return L + (L >= 16 ? L / 16 : 1); }
 template <typename T>
 constexpr int a3_pp(int L) {
   int nt = L / a3_e<T>(L);
-  int pp = 256 / nt;
+  int pp = kA3Threads / nt;
   if (pp < 1) pp = 1;
   int lim = kLdsBytes / (a3_pad<T>(L) * int(sizeof(cx<T>)));
   while (pp > lim && pp > 1) pp >>= 1;
@@ -356,7 +360,7 @@ constexpr int a3_pp(int L) {
 
 // L = M = N3/2 complex values per pencil; pencil = (j1, j2).
 template <typename T, int L, int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kA3Threads)
 k_axis3(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask,
         const cx<T>* __restrict__ twm, const cx<T>* __restrict__ tw3, int npencils, T sc_c2r,
         T sc_r2c_dc, T sc_r2c, const int* skip) {
@@ -364,6 +368,7 @@ k_axis3(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask,
   constexpr int E = a3_e<T>(L);
   constexpr int NT = L / E;
   constexpr int PP = a3_pp<T>(L);
+  static_assert(PP * NT <= kA3Threads, "axis-3 workgroup exceeds its launch bound");
   constexpr int LP = a3_pad<T>(L);
   constexpr int N3 = 2 * L;
   extern __shared__ __align__(16) unsigned char smem_raw[];
