@@ -11,7 +11,10 @@
  * formulation", equations "beta", "v", derivation "map").
  *
  * Conventions shared by every entry point
- *  - Grid: N1 x N2 x N3, each a power of two in [4, 1024]; n = N1*N2*N3.
+ *  - Grid: N1 x N2 x N3, each a power of two in [4, 1024] or one of the
+ *    extents with odd factors 12, 20, 24, 28, 40, 48, 56, 70, 96, 192, 384,
+ *    560 (the FFT passes have radix-3, -5 and -7 stages); n = N1*N2*N3.
+ *    Other extents return CSIPM_EUNSUPPORTED.
  *  - Real-space arrays are row-major [N1][N2][N3] (index j3 fastest).
  *  - beta-space arrays ("external beta layout") are row-major [N1][N2][N3]
  *    indexed by the frequency k: beta[k] = v_k for self-conjugate k
@@ -44,8 +47,11 @@ typedef struct csipm_ctx csipm_ctx;
 typedef enum {
   CSIPM_OK = 0,
   CSIPM_NOT_CONVERGED = 1, /* iteration limit reached; iterate usable          */
-  CSIPM_STALLED = 2,       /* rel_kkt rose above 10x its best value (the
-                              precision floor was reached); iterate usable   */
+  CSIPM_STALLED = 2,       /* the precision floor was reached: a step along
+                              a Newton direction that missed its tolerance
+                              raised rel_kkt (the iterate before that step
+                              is returned), or rel_kkt rose above 10x its
+                              best value; iterate usable                     */
   CSIPM_FELL_BACK = 3,     /* converged, but some Newton systems fell back to
                               the paper's preconditioner                       */
   CSIPM_EINVAL = -1,       /* bad argument (null pointer, size, lambda <= 0)   */

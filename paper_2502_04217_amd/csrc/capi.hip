@@ -26,7 +26,6 @@ constexpr size_t kAlign = 256;
 // the learned correction is evaluated where L1 / (L1 + 4 S1 S2) >= this
 constexpr double kPcRelevance = 1e-3;
 
-bool pow2_in_range(int v) { return v >= 4 && v <= 1024 && (v & (v - 1)) == 0; }
 
 struct Carver {
   char* base;
@@ -50,6 +49,9 @@ struct csipm_ctx {
 
   // FP64 interior-point state and Newton system (internal layout)
   double *beta, *z, *nu1, *nu2, *xi, *hb, *sig1, *sig2, *rhb, *rhz, *dxb, *dxz, *diagH;
+  // copy of (beta, z, nu1, nu2) taken before a step along a direction that
+  // missed its tolerance, restored if that step raised rel_kkt
+  double *snap;
   // FP64 Krylov vectors and FFT work array
   double *rb, *rz, *zb, *zz, *pb, *pz, *qb, *qz, *work;
   // FP32 Krylov set
@@ -157,12 +159,13 @@ size_t layout(Carver& cv, csipm_ctx* c, int n1, int n2, int n3) {
                     &c->dxb, &c->dxz, &c->diagH, &c->rb, &c->rz, &c->zb, &c->zz, &c->pb, &c->pz, &c->qb,
                     &c->qz, &c->work};
   for (double** p : d64) *p = cv.take<double>(n);
+  c->snap = cv.take<double>(4 * n);
   float** f32[] = {&c->sig1f, &c->sig2f, &c->frb, &c->frz, &c->fzb,   &c->fzz,  &c->fpb, &c->fpz,
                    &c->fqb,   &c->fqz,   &c->fxb, &c->fxz, &c->fwork, &c->pc_c, &c->fwb, &c->fwz};
   for (float** p : f32) *p = cv.take<float>(n);
   c->feat = cv.take<float>(4 * n);
   c->mlp_params = cv.take<float>(CSIPM_MLP_PARAMS);
-  c->mask = cv.take<uint32_t>(n / 32);
+  c->mask = cv.take<uint32_t>((n + 31) / 32);
   c->tw64 = cv.take<cx<double>>(ntw);
   c->tw32 = cv.take<cx<float>>(ntw);
   c->partK = cv.take<double>(2 * k_partials(n1, n2, n3));   // up to two quantities
@@ -438,7 +441,7 @@ void csipm_default_options(csipm_options* o) {
 }
 
 size_t csipm_workspace_bytes(int n1, int n2, int n3) {
-  if (!pow2_in_range(n1) || !pow2_in_range(n2) || !pow2_in_range(n3)) return 0;
+  if (!fft_extent_supported(n1) || !fft_extent_supported(n2) || !fft_extent_supported(n3)) return 0;
   csipm_ctx tmp;
   Carver cv{nullptr, 0, 0};
   return layout(cv, &tmp, n1, n2, n3);
@@ -449,7 +452,7 @@ csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double*
   if (!out) return CSIPM_EINVAL;
   *out = nullptr;
   if (!d_signal || !d_observed || !d_workspace) return CSIPM_EINVAL;
-  if (!pow2_in_range(n1) || !pow2_in_range(n2) || !pow2_in_range(n3)) return CSIPM_EUNSUPPORTED;
+  if (!fft_extent_supported(n1) || !fft_extent_supported(n2) || !fft_extent_supported(n3)) return CSIPM_EUNSUPPORTED;
   if ((reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0) return CSIPM_EINVAL;
   const size_t need = csipm_workspace_bytes(n1, n2, n3);
   if (workspace_bytes < need) return CSIPM_ENOMEM;
@@ -663,6 +666,18 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
   return CSIPM_OK;
 }
 
+// (beta, z, nu1, nu2) <-> snap
+void save_state(csipm_ctx* c) {
+  const size_t b = sizeof(double) * (size_t)c->g.n;
+  const double* src[4] = {c->beta, c->z, c->nu1, c->nu2};
+  for (int i = 0; i < 4; ++i) (void)hipMemcpyAsync(c->snap + i * c->g.n, src[i], b, hipMemcpyDeviceToDevice, c->s);
+}
+void restore_state(csipm_ctx* c) {
+  const size_t b = sizeof(double) * (size_t)c->g.n;
+  double* dst[4] = {c->beta, c->z, c->nu1, c->nu2};
+  for (int i = 0; i < 4; ++i) (void)hipMemcpyAsync(dst[i], c->snap + i * c->g.n, b, hipMemcpyDeviceToDevice, c->s);
+}
+
 struct Resid {
   double fb, fz, cmax, csum, bmax, pmin, nonfinite;
 };
@@ -735,6 +750,8 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   bool approx = false;   // carried H beta holds FP32-level error (an unrefined FP32 step)
   int carried = 0;
   double best_rel = INFINITY;
+  bool have_snap = false;
+  double snap_rel = INFINITY;
   csipm_info inf{};
   inf.lambda = lam;
   inf.xi_inf = c->xi_inf;
@@ -744,7 +761,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     auto rel_of = [&](const Resid& q) { return std::max(std::max(q.fb, q.fz), q.cmax) / (1.0 + c->xi_inf); };
     double rel = rel_of(r);
     const bool leaving_trust = approx && !(std::min(o.cg_rtol, 0.1 * rel) >= o.refine_trust);
-    if (!exact && (rel <= o.tol || it >= o.max_iter || carried >= kExactEvery || leaving_trust ||
+    if (!exact && (rel <= o.tol || it >= o.max_iter || carried >= kExactEvery || leaving_trust || have_snap ||
                    rel > kStallFactor * best_rel || !std::isfinite(rel))) {
       st = residuals(c, r, learned);
       if (st != CSIPM_OK) return st;
@@ -753,6 +770,23 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       carried = 0;
       rel = rel_of(r);
     }
+    // a step along an inexact direction (the Newton solve stopped at its
+    // precision floor or budget) that raised rel_kkt is undone, and the solve
+    // ends there with the better iterate
+    if (have_snap && !(rel <= snap_rel)) {
+      restore_state(c);
+      st = residuals(c, r, learned);
+      if (st != CSIPM_OK) return st;
+      rel = rel_of(r);
+      result = CSIPM_STALLED;
+      inf.rel_kkt = rel;
+      inf.res_beta_inf = r.fb;
+      inf.res_z_inf = r.fz;
+      inf.compl_max = r.cmax;
+      inf.mu = r.csum / (2.0 * (double)n);
+      break;
+    }
+    have_snap = false;
     if (r.nonfinite > 0 || !std::isfinite(r.fb)) return fail(c, CSIPM_ENONFINITE, "non-finite interior-point iterate");
     // past the precision floor the Newton steps stop reducing the residual
     // and start raising it: stop there rather than run into overflow
@@ -819,6 +853,11 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
         ++c->cap_count;
         c->cap_cg.push_back(cgi);
       }
+    }
+    if (!conv) {
+      save_state(c);
+      have_snap = true;
+      snap_rel = rel;
     }
     // an FP32 solution taken without refinement is read in FP32 (d = x32 exactly)
     const float* d32b = src == HD_RRES32 ? c->fxb : nullptr;

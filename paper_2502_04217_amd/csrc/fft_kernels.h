@@ -1,0 +1,677 @@
+// Pencil-FFT kernel templates shared by the FFT drivers: fft.hip
+// instantiates them for power-of-two pencil lengths, fft_mixed.hip for
+// lengths with odd factors 3, 5 and 7 (the non-power-of-two grids of the
+// paper's synthetic size table, and small grids that exercise each radix).
+//
+// Each pencil FFT is a Stockham sequence of radix-r stages: the first stage
+// reads its inputs straight from global memory into registers, intermediate
+// stages exchange through LDS, and the last stage writes from registers to
+// global memory (or into an epilogue).  A stage of radix r has L/r
+// butterflies; the NT threads of a pencil take butterflies j = t + i*NT.
+// When NT divides L/r every thread has the same number of butterflies;
+// otherwise (an odd radix that does not divide the per-thread element count)
+// the stage is guarded, and the spare register slots of the last round go
+// unused.
+#pragma once
+
+#include "csipm_internal.h"
+
+#include <type_traits>
+
+namespace csipm {
+namespace fftk {
+
+constexpr int kLdsBytes = 65536;     // LDS budget of an axis-3 workgroup
+
+// ------------------------------------------------------------- radix plan --
+constexpr int odd_part(int x) {
+  while (x > 0 && x % 2 == 0) x /= 2;
+  return x;
+}
+constexpr int smallest_odd_factor(int x) {
+  for (int p = 3; p <= x; p += 2)
+    if (x % p == 0) return p;
+  return x;
+}
+// k-th odd prime factor of F (ascending, with multiplicity)
+constexpr int odd_factor(int F, int k) {
+  int p = smallest_odd_factor(F);
+  for (int i = 0; i < k; ++i) {
+    F /= p;
+    p = smallest_odd_factor(F);
+  }
+  return p;
+}
+constexpr int odd_factor_count(int F) {
+  int c = 0;
+  while (F > 1) {
+    F /= smallest_odd_factor(F);
+    ++c;
+  }
+  return c;
+}
+
+// Stage plan of a length-L pencil with E elements per thread (NT = L/E
+// threads).  The power-of-two part of L is split into stages of radix P2
+// (the power-of-two part of E; 4 when E is odd) and one remainder stage;
+// the odd prime factors of L follow as stages of their own.
+template <int L, int E>
+struct Radix {
+  static_assert(L % E == 0, "elements per thread must divide the pencil length");
+  static constexpr int NT = L / E;
+  static constexpr int LP = L / odd_part(L);
+  static constexpr int P2 = (E / odd_part(E)) > 1 ? E / odd_part(E) : (LP < 4 ? LP : 4);
+  static constexpr int nfull() {
+    int c = 0, r = LP;
+    while (P2 > 1 && r >= P2) { r /= P2; ++c; }
+    return c;
+  }
+  static constexpr int NFULL = nfull();
+  static constexpr int rem() {
+    int r = LP;
+    for (int i = 0; i < NFULL; ++i) r /= P2;
+    return r;
+  }
+  static constexpr int REM = rem();
+  static constexpr int NPOW = NFULL + (REM > 1 ? 1 : 0);
+  static constexpr int NSTAGES = NPOW + odd_factor_count(odd_part(L));
+  static constexpr int radix(int s) {
+    return s < NFULL ? P2 : (s < NPOW ? REM : odd_factor(odd_part(L), s - NPOW));
+  }
+  static constexpr int ns(int s) {
+    int v = 1;
+    for (int i = 0; i < s; ++i) v *= radix(i);
+    return v;
+  }
+  // butterflies per thread in stage s, and whether every one is real
+  static constexpr int nb(int s) { return (L / radix(s) + NT - 1) / NT; }
+  static constexpr bool exact(int s) { return (L / radix(s)) % NT == 0; }
+  static constexpr int vmax() {
+    int m = 0;
+    for (int s = 0; s < NSTAGES; ++s) m = nb(s) * radix(s) > m ? nb(s) * radix(s) : m;
+    return m;
+  }
+  static constexpr int VMAX = vmax();   // register slots per thread
+};
+
+// cos and sin of 2 pi m / R for the odd radices (folded to literals once
+// the butterfly loops are unrolled)
+__host__ __device__ constexpr double root_cos(int R, int m) {
+  const int k = m % R;
+  const int a = 2 * k <= R ? k : R - k;
+  if (a == 0) return 1.0;
+  if (R == 3) return -0.5;
+  if (R == 5) return a == 1 ? 0.30901699437494742410 : -0.80901699437494742410;
+  return a == 1 ? 0.62348980185873353053 : (a == 2 ? -0.22252093395631440429 : -0.90096886790241912624);
+}
+__host__ __device__ constexpr double root_sin(int R, int m) {
+  const int k = m % R;
+  const bool neg = 2 * k > R;
+  const int a = neg ? R - k : k;
+  double v = 0.0;
+  if (a != 0) {
+    if (R == 3) v = 0.86602540378443864676;
+    else if (R == 5) v = a == 1 ? 0.95105651629515357212 : 0.58778525229247312917;
+    else v = a == 1 ? 0.78183148246802980871 : (a == 2 ? 0.97492791218182360702 : 0.43388373911755812048);
+  }
+  return neg ? -v : v;
+}
+
+// In-register DFT of odd size R in natural order, out[k] = sum_j v[j]
+// exp(DIR 2 pi i j k / R), from the conjugate-pair split: with a_j = v_j +
+// v_{R-j} and b_j = v_j - v_{R-j} (j = 1..(R-1)/2),
+//   out[k] = v_0 + sum_j a_j cos(2 pi jk/R) + DIR i sum_j b_j sin(2 pi jk/R),
+// and out[R-k] the same with the sine sum negated.
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft_odd(cx<T>* v) {
+  static_assert(R == 3 || R == 5 || R == 7, "odd radices 3, 5 and 7");
+  constexpr int H = (R - 1) / 2;
+  cx<T> a[H], b[H];
+#pragma unroll
+  for (int j = 1; j <= H; ++j) {
+    a[j - 1] = cadd(v[j], v[R - j]);
+    b[j - 1] = csub(v[j], v[R - j]);
+  }
+  cx<T> out[R];
+  out[0] = v[0];
+#pragma unroll
+  for (int j = 0; j < H; ++j) out[0] = cadd(out[0], a[j]);
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    cx<T> x = v[0], y = {T(0), T(0)};
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      const T c = T(root_cos(R, j * k)), s = T(root_sin(R, j * k));
+      x = {x.re + a[j - 1].re * c, x.im + a[j - 1].im * c};
+      y = {y.re + b[j - 1].re * s, y.im + b[j - 1].im * s};
+    }
+    const cx<T> iy = cmul_i<DIR>(y);
+    out[k] = cadd(x, iy);
+    out[R - k] = csub(x, iy);
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) v[k] = out[k];
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft_any(cx<T>* v) {
+  if constexpr ((R & (R - 1)) == 0) dft_reg<R, DIR, T>(v);
+  else dft_odd<R, DIR, T>(v);
+}
+
+template <typename T, typename Tw>
+__device__ __forceinline__ cx<T> twiddle(const Tw* tw, int idx, int dir) {
+  cx<T> w = tw[idx];
+  if (dir > 0) w.im = -w.im;
+  return w;
+}
+
+// Calls f(slot, element) for the inputs of stage S (element j + q L/r of
+// butterfly j), which are also the outputs of the last stage; slot i*r + q
+// of the register block holds value q of the thread's i-th butterfly.
+template <int L, int E, int S, class F>
+__device__ __forceinline__ void for_stage_io(int t, F f) {
+  using RP = Radix<L, E>;
+  constexpr int r = RP::radix(S);
+  constexpr int NB = RP::nb(S);
+  constexpr bool EX = RP::exact(S);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int j = t + i * RP::NT;
+    if (EX || j < L / r) {
+#pragma unroll
+      for (int q = 0; q < r; ++q) f(i * r + q, j + q * (L / r));
+    }
+  }
+}
+
+// Applies stage S of a length-L Stockham FFT to the register block v.
+template <typename T, int L, int E, int DIR, int S>
+__device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* tw) {
+  using RP = Radix<L, E>;
+  constexpr int r = RP::radix(S);
+  constexpr int Ns = RP::ns(S);
+  constexpr int NT = RP::NT;
+  constexpr int NB = RP::nb(S);
+  constexpr bool EX = RP::exact(S);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int j = t + i * NT;
+    if (EX || j < L / r) {
+      if constexpr (Ns > 1) {
+        const int jm = j % Ns;
+#pragma unroll
+        for (int q = 1; q < r; ++q) {
+          v[i * r + q] = cmul(v[i * r + q], twiddle<T>(tw, jm * q * (L / (Ns * r)), DIR));
+        }
+      }
+      dft_any<r, DIR, T>(&v[i * r]);
+    }
+  }
+}
+
+// Writes stage S outputs to LDS (Stockham destination index) and reads
+// stage S+1 inputs back.  `lidx(e)` maps a pencil element to its LDS slot.
+template <typename T, int L, int E, int S, class LIdx>
+__device__ __forceinline__ void stage_exchange(cx<T>* v, int t, cx<T>* lds, LIdx lidx) {
+  using RP = Radix<L, E>;
+  constexpr int r = RP::radix(S);
+  constexpr int Ns = RP::ns(S);
+  constexpr int NT = RP::NT;
+  constexpr int NB = RP::nb(S);
+  constexpr bool EX = RP::exact(S);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int j = t + i * NT;
+    if (EX || j < L / r) {
+      const int base = (j / Ns) * Ns * r + (j % Ns);
+#pragma unroll
+      for (int q = 0; q < r; ++q) lds[lidx(base + q * Ns)] = v[i * r + q];
+    }
+  }
+  __syncthreads();
+  for_stage_io<L, E, S + 1>(t, [&](int slot, int e) { v[slot] = lds[lidx(e)]; });
+}
+
+// Runs all stages; inputs in the first-stage pattern, outputs left in
+// registers in the last-stage pattern (both as for_stage_io lists them).
+template <typename T, int L, int E, int DIR, int S, class LIdx>
+__device__ __forceinline__ void fft_stages(cx<T>* v, int t, cx<T>* lds, LIdx lidx, const cx<T>* tw) {
+  using RP = Radix<L, E>;
+  stage_compute<T, L, E, DIR, S>(v, t, tw);
+  if constexpr (S + 1 < RP::NSTAGES) {
+    stage_exchange<T, L, E, S>(v, t, lds, lidx);
+    fft_stages<T, L, E, DIR, S + 1>(v, t, lds, lidx, tw);
+  }
+}
+
+template <int L, int E>
+constexpr int last_stage() { return Radix<L, E>::NSTAGES - 1; }
+
+// Elements per thread of a pencil with odd factors: the odd part times up
+// to 4 when the odd part is at most 7 (12, 20 or 28 values), else the odd
+// part alone; the thread count per pencil L/E is then a power of two.
+constexpr int mixed_e(int L) {
+  const int F = odd_part(L), P = L / F;
+  const int q = F <= 7 ? (P < 4 ? P : 4) : 1;
+  return F * q;
+}
+
+// ------------------------------------------------------- block reduction --
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block sums of NQ values; thread 0 writes out[q * stride + blockIdx.x].
+// `red` is LDS scratch of at least NQ * NTHREADS/64 doubles; it may alias the
+// FFT exchange buffer, so the block synchronises before writing it.
+// The last NMAX quantities are maxima (of non-negative values), the others sums.
+template <int NTHREADS, int NQ, int NMAX = 0>
+__device__ __forceinline__ void block_sums_store(const double* v, double* out, int stride, double* red) {
+  static_assert(NTHREADS % 64 == 0, "block reductions need whole waves");
+  constexpr int NW = NTHREADS / 64;
+  double w[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) w[q] = q >= NQ - NMAX ? wave_max(v[q]) : wave_sum(v[q]);
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) red[q * NW + wv] = w[q];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double a = 0.0;
+      for (int i = 0; i < NW; ++i) a = q >= NQ - NMAX ? fmax(a, red[q * NW + i]) : a + red[q * NW + i];
+      out[q * stride + blockIdx.x] = a;
+    }
+}
+
+// ------------------------------------------------------------ epilogues --
+// Applied to each output element h = (H p)[idx] of the last forward pass
+// (m >= 1 there, the m = 0 plane in the postmix pass).
+struct EpiNone {
+  static constexpr int NRED = 0;
+  static constexpr int NMAX = 0;
+  double* partial = nullptr;
+  int pstride = 0;
+};
+
+// q = K p (equation "condensedkkt" in Sigma form) and p.q
+template <typename T>
+struct EpiK {
+  static constexpr int NRED = 1;
+  static constexpr int NMAX = 0;
+  KArgs<T> a;
+  double* partial;
+  int pstride;
+  __device__ __forceinline__ void operator()(long long idx, cx<T> h, double* acc) const {
+    const cx<T> pb = reinterpret_cast<const cx<T>*>(a.pb)[idx];
+    const cx<T> pz = reinterpret_cast<const cx<T>*>(a.pz)[idx];
+    const cx<T> s1 = reinterpret_cast<const cx<T>*>(a.sig1)[idx];
+    const cx<T> s2 = reinterpret_cast<const cx<T>*>(a.sig2)[idx];
+    cx<T> qb, qz;
+    k_block<T>(h.re, pb.re, pz.re, s1.re, s2.re, qb.re, qz.re);
+    k_block<T>(h.im, pb.im, pz.im, s1.im, s2.im, qb.im, qz.im);
+    reinterpret_cast<cx<T>*>(a.qb)[idx] = qb;
+    reinterpret_cast<cx<T>*>(a.qz)[idx] = qz;
+    acc[0] += (double)pb.re * (double)qb.re + (double)pb.im * (double)qb.im + (double)pz.re * (double)qz.re +
+              (double)pz.im * (double)qz.im;
+  }
+};
+
+// FP64 refinement residual r = h - K d: writes H d_beta (the transform output
+// itself), sums r.P_c^{-1}r and takes max |r|.  A further inner solve, when
+// one is needed, builds its FP32 start from H d_beta elementwise
+// (k_ref_restart).
+struct EpiR {
+  static constexpr int NRED = 2;
+  static constexpr int NMAX = 1;
+  RArgs a;
+  double* partial;
+  int pstride;
+  __device__ __forceinline__ void operator()(long long idx, cx<double> h, double* acc) const {
+    using D2 = cx<double>;
+    const D2 db = reinterpret_cast<const D2*>(a.db)[idx], dz = reinterpret_cast<const D2*>(a.dz)[idx];
+    const D2 s1 = reinterpret_cast<const D2*>(a.sig1)[idx], s2 = reinterpret_cast<const D2*>(a.sig2)[idx];
+    const D2 hb = reinterpret_cast<const D2*>(a.hb)[idx], hz = reinterpret_cast<const D2*>(a.hz)[idx];
+    const float2 c = a.c ? reinterpret_cast<const float2*>(a.c)[idx] : make_float2(1.0f, 1.0f);
+    reinterpret_cast<D2*>(a.hd)[idx] = h;
+    const double hv[2] = {h.re, h.im}, dbv[2] = {db.re, db.im}, dzv[2] = {dz.re, dz.im}, g1[2] = {s1.re, s1.im},
+                 g2[2] = {s2.re, s2.im}, rhb[2] = {hb.re, hb.im}, rhz[2] = {hz.re, hz.im}, cv[2] = {c.x, c.y};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      double qb, qz, zb, zz;
+      k_block<double>(hv[k], dbv[k], dzv[k], g1[k], g2[k], qb, qz);
+      const double rb = rhb[k] - qb, rz = rhz[k] - qz;
+      pinv_block(rb, rz, g1[k], g2[k], cv[k], zb, zz);
+      acc[0] += rb * zb + rz * zz;
+      acc[1] = fmax(acc[1], fmax(fabs(rb), fabs(rz)));
+    }
+  }
+};
+
+// --------------------------------------------------- strided pencil pass --
+// Complex FFT along axis 1 or 2 over the array [N1][N2][M].  Pencil q has
+// base offset (q / inner) * outer + q % inner and element stride estride.
+template <typename T>
+struct StridedGeom {
+  int inner;
+  long long outer;
+  long long estride;
+  int batch;
+};
+
+// Tile shape of the strided (axis-1/2) passes per complex size w in bytes,
+// pencil length L, axis and direction: elements per thread E and pencils
+// per workgroup TM (LDS = TM L w, at most 1024 threads, TM a power of two).
+// Power-of-two pencils, chosen from measurements at 256^3: 8 elements per
+// thread for the FP64 axis-2 passes and the FP32 axis-1 forward pass, 16
+// otherwise; 128 KB tiles for axis 1 except the FP64 inverse pass (64 KB),
+// 64 KB for axis 2.  Pencils with odd factors take mixed_e elements.
+constexpr int strided_e(int w, int L, int axis, int dir) {
+  if (odd_part(L) != 1) return mixed_e(L);
+  const int e = ((w == 16 && axis == 2) || (w == 8 && axis == 1 && dir < 0)) ? 8 : 16;
+  return L < e ? L : e;
+}
+constexpr int strided_lds(int w, int axis, int dir) {
+  return axis == 2 ? 65536 : (w == 16 && dir > 0 ? 65536 : 131072);
+}
+constexpr int strided_tm(int w, int L, int axis, int dir) {
+  int tm = strided_lds(w, axis, dir) / (L * w);
+  if (tm > 64) tm = 64;
+  if (tm < 1) tm = 1;
+  int p = 1;
+  while (2 * p <= tm) p *= 2;
+  tm = p;
+  while (tm * (L / strided_e(w, L, axis, dir)) > 1024) tm >>= 1;
+  return tm;
+}
+template <typename T, int L, int AX, int DIR>
+constexpr int strided_threads() {
+  constexpr int w = int(sizeof(cx<T>));
+  return strided_tm(w, L, AX, DIR) * (L / strided_e(w, L, AX, DIR));
+}
+
+template <typename T, int L, int AX, int DIR, class Epi>
+__global__ void __launch_bounds__((strided_threads<T, L, AX, DIR>()))
+k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
+         const cx<T>* __restrict__ tw, int m, int m0_from_dst, Epi epi, const int* skip) {
+  if (skip && *skip) return;
+  constexpr int E = strided_e(int(sizeof(cx<T>)), L, AX, DIR);
+  constexpr int TM = strided_tm(int(sizeof(cx<T>)), L, AX, DIR);
+  constexpr int NT = L / E;
+  constexpr int VM = Radix<L, E>::VMAX;
+  constexpr int SL = last_stage<L, E>();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int p = threadIdx.x % TM;
+  const int t = threadIdx.x / TM;
+  const int qpen = blockIdx.x * TM + p;
+  const bool active = qpen < geo.batch;
+  const long long base = active ? (long long)(qpen / geo.inner) * geo.outer + (qpen % geo.inner) : 0;
+  const bool is_m0 = (qpen % m) == 0;
+  const cx<T>* in = (m0_from_dst && is_m0) ? dst : src;
+
+  cx<T> v[VM];
+  for_stage_io<L, E, 0>(t, [&](int s, int e) {
+    v[s] = active ? in[base + (long long)e * geo.estride] : cx<T>{T(0), T(0)};
+  });
+  auto lidx = [p](int e) { return e * TM + p; };
+  fft_stages<T, L, E, DIR, 0>(v, t, lds, lidx, tw);
+
+  if constexpr (Epi::NRED > 0) {
+    double acc[Epi::NRED];
+#pragma unroll
+    for (int q = 0; q < Epi::NRED; ++q) acc[q] = 0.0;
+    if (active) {
+      for_stage_io<L, E, SL>(t, [&](int s, int e) {
+        const long long idx = base + (long long)e * geo.estride;
+        if (is_m0)
+          dst[idx] = v[s];   // finished by the postmix pass
+        else
+          epi(idx, v[s], acc);
+      });
+    }
+    block_sums_store<TM * NT, Epi::NRED, Epi::NMAX>(acc, epi.partial, epi.pstride,
+                                                    reinterpret_cast<double*>(smem_raw));
+  } else {
+    if (active) {
+      for_stage_io<L, E, SL>(t, [&](int s, int e) { dst[base + (long long)e * geo.estride] = v[s]; });
+    }
+  }
+}
+
+template <typename T, int L, int AX, int DIR, class Epi>
+void launch_axis12_at(dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* tw, int m,
+                      int m0, Epi epi, const int* skip, hipStream_t s) {
+  constexpr int TM = strided_tm(int(sizeof(cx<T>)), L, AX, DIR);
+  constexpr int NT = L / strided_e(int(sizeof(cx<T>)), L, AX, DIR);
+  static_assert((TM * NT) % 64 == 0 && TM * NT <= 1024, "strided tile must be whole waves");
+  const size_t shm = (size_t)TM * L * sizeof(cx<T>);
+  auto kern = k_axis12<T, L, AX, DIR, Epi>;
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(kern, grid, dim3(TM * NT), shm, s, src, dst, geo, tw, m, m0, epi, skip);
+}
+
+// ------------------------------------------------------ axis-3 (c2r/r2c) --
+template <typename T>
+constexpr int a3_e(int L) {   // 8 elements per thread for power-of-two pencils (measured best)
+  return odd_part(L) != 1 ? mixed_e(L) : (L < 8 ? L : 8);
+}
+// one wave per workgroup: the pass synchronises between its many LDS
+// stages, and at 256^3 the single-wave group is the fastest tile measured
+// (4 pencils of 128 at 8 elements per thread)
+constexpr int kA3Threads = 64;
+template <typename T>
+constexpr int a3_pad(int L) { return L + (L >= 16 ? L / 16 : 1); }
+template <typename T>
+constexpr int a3_pp(int L) {
+  int nt = L / a3_e<T>(L);
+  int pp = kA3Threads / nt;
+  if (pp < 1) pp = 1;
+  int lim = kLdsBytes / (a3_pad<T>(L) * int(sizeof(cx<T>)));
+  while (pp > lim && pp > 1) pp >>= 1;
+  return pp;
+}
+
+// L = M = N3/2 complex values per pencil; pencil = (j1, j2).
+template <typename T, int L, int MODE>
+__global__ void __launch_bounds__(kA3Threads)
+k_axis3(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask,
+        const cx<T>* __restrict__ twm, const cx<T>* __restrict__ tw3, int npencils, T sc_c2r,
+        T sc_r2c_dc, T sc_r2c, const int* skip) {
+  if (skip && *skip) return;
+  constexpr int E = a3_e<T>(L);
+  constexpr int NT = L / E;
+  constexpr int PP = a3_pp<T>(L);
+  static_assert(PP * NT <= kA3Threads, "axis-3 workgroup exceeds its launch bound");
+  constexpr int LP = a3_pad<T>(L);
+  constexpr int N3 = 2 * L;
+  constexpr int VM = Radix<L, E>::VMAX;
+  constexpr int SL = last_stage<L, E>();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* ldsall = reinterpret_cast<cx<T>*>(smem_raw);
+  const int p = threadIdx.x / NT;
+  const int t = threadIdx.x % NT;
+  const int pen = blockIdx.x * PP + p;
+  const bool active = pen < npencils;
+  const long long base = (long long)pen * L;
+  cx<T>* lds = ldsall + p * LP;
+  auto lidx = [](int e) { return e + (e >> 4); };
+  const T rs2 = T(0.70710678118654752440);
+
+  cx<T> v[VM];
+  if constexpr (MODE & A3_C2R) {
+    // stage the packed half-spectrum through LDS: Z_e needs X_e and X_{L-e}
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int e = t + q * NT;
+      lds[lidx(e)] = active ? src[base + e] : cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    for_stage_io<L, E, 0>(t, [&](int s, int e) {
+      cx<T> z;
+      if (e == 0) {
+        const cx<T> x0 = lds[lidx(0)];   // (DC, Nyquist)
+        z = {x0.re + x0.im, x0.re - x0.im};
+      } else {
+        const cx<T> a = cscale(lds[lidx(e)], rs2);
+        const cx<T> b = cconj(cscale(lds[lidx(L - e)], rs2));
+        const cx<T> sm = cadd(a, b);
+        const cx<T> d = csub(a, b);
+        cx<T> w = tw3[e];          // exp(-2 pi i e / N3)
+        w.im = -w.im;              // exp(+2 pi i e / N3)
+        const cx<T> id = cmul_i<1>(cmul(w, d));
+        z = cadd(sm, id);
+      }
+      v[s] = z;
+    });
+    fft_stages<T, L, E, +1, 0>(v, t, lds, lidx, twm);
+    // z_e = x[2e] + i x[2e+1]
+    for_stage_io<L, E, SL>(t, [&](int s, int e) {
+      cx<T> z = cscale(v[s], sc_c2r);
+      if constexpr (MODE == A3_FULL) {
+        const long long bit = (long long)pen * N3 + 2 * e;
+        const uint32_t wd = active ? mask[bit >> 5] : 0u;
+        const int sh = (int)(bit & 31);
+        if (!((wd >> sh) & 1u)) z.re = T(0);
+        if (!((wd >> (sh + 1)) & 1u)) z.im = T(0);
+      }
+      v[s] = z;
+    });
+    if constexpr (MODE == A3_C2R) {
+      if (active) for_stage_io<L, E, SL>(t, [&](int s, int e) { dst[base + e] = v[s]; });
+      return;
+    } else {
+      // re-order to the first-stage pattern of the forward transform
+      __syncthreads();
+      for_stage_io<L, E, SL>(t, [&](int s, int e) { lds[lidx(e)] = v[s]; });
+      __syncthreads();
+      for_stage_io<L, E, 0>(t, [&](int s, int e) { v[s] = lds[lidx(e)]; });
+    }
+  } else {
+    for_stage_io<L, E, 0>(t, [&](int s, int e) { v[s] = active ? src[base + e] : cx<T>{T(0), T(0)}; });
+  }
+
+  // forward half-length FFT of z' and the r2c post-processing
+  fft_stages<T, L, E, -1, 0>(v, t, lds, lidx, twm);
+  __syncthreads();
+  for_stage_io<L, E, SL>(t, [&](int s, int e) { lds[lidx(e)] = v[s]; });
+  __syncthreads();
+  if (!active) return;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int e = t + q * NT;
+    cx<T> xo;
+    if (e == 0) {
+      const cx<T> z0 = lds[lidx(0)];
+      xo = {(z0.re + z0.im) * sc_r2c_dc, (z0.re - z0.im) * sc_r2c_dc};
+    } else {
+      const cx<T> a = lds[lidx(e)];
+      const cx<T> b = cconj(lds[lidx(L - e)]);
+      const cx<T> ev = cscale(cadd(a, b), T(0.5));
+      const cx<T> od = cscale(csub(a, b), T(0.5));
+      const cx<T> w = tw3[e];        // exp(-2 pi i e / N3)
+      const cx<T> t2 = cmul_i<-1>(cmul(w, od));
+      xo = cscale(cadd(ev, t2), sc_r2c);
+    }
+    dst[base + e] = xo;
+  }
+}
+
+template <typename T, int L>
+void launch_axis3_at(int mode, int np, const cx<T>* cs, cx<T>* cd, const uint32_t* maskbits,
+                     const cx<T>* twm, const cx<T>* tw3, T sc_c2r, T sc_dc, T sc_ac, const int* skip,
+                     hipStream_t s) {
+  constexpr int PP = a3_pp<T>(L);
+  constexpr int NT = L / a3_e<T>(L);
+  const size_t shm = (size_t)PP * a3_pad<T>(L) * sizeof(cx<T>);
+  dim3 grid((np + PP - 1) / PP), block(PP * NT);
+  if (shm > 65536) {
+    (void)hipFuncSetAttribute((const void*)k_axis3<T, L, A3_FULL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shm);
+    (void)hipFuncSetAttribute((const void*)k_axis3<T, L, A3_C2R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shm);
+    (void)hipFuncSetAttribute((const void*)k_axis3<T, L, A3_R2C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shm);
+  }
+  if (mode == A3_FULL)
+    hipLaunchKernelGGL((k_axis3<T, L, A3_FULL>), grid, block, shm, s, cs, cd, maskbits, twm, tw3, np, sc_c2r,
+                       sc_dc, sc_ac, skip);
+  else if (mode == A3_C2R)
+    hipLaunchKernelGGL((k_axis3<T, L, A3_C2R>), grid, block, shm, s, cs, cd, maskbits, twm, tw3, np, sc_c2r,
+                       sc_dc, sc_ac, skip);
+  else
+    hipLaunchKernelGGL((k_axis3<T, L, A3_R2C>), grid, block, shm, s, cs, cd, maskbits, twm, tw3, np, sc_c2r,
+                       sc_dc, sc_ac, skip);
+}
+
+// ------------------------------------------------------- length dispatch --
+// Grid extents with odd factors that have kernels (each as an axis-1/2
+// pencil length N, and N/2 as the axis-3 half length): small grids that
+// exercise radix 3, 5 and 7, and the non-power-of-two sizes of the paper's
+// synthetic table (96, 192, 384, 560).
+#define CSIPM_MIXED_LENGTHS(X) X(12) X(20) X(24) X(28) X(40) X(48) X(56) X(70) X(96) X(192) X(384) X(560)
+
+// Launch a strided or axis-3 pass at a pencil length with odd factors;
+// false when the length has no kernels.  Instantiated for FP64 in
+// fft_mixed_f64.hip and for FP32 in fft_mixed_f32.hip.
+template <typename T, int AX, int DIR, class Epi>
+bool launch_axis12_mixed(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* tw,
+                         int m, int m0, Epi epi, const int* skip, hipStream_t s) {
+#define CSIPM_A12(LL)                                                                     \
+  case LL:                                                                                \
+    launch_axis12_at<T, LL, AX, DIR, Epi>(grid, src, dst, geo, tw, m, m0, epi, skip, s); \
+    return true;
+  switch (L) {
+    CSIPM_MIXED_LENGTHS(CSIPM_A12)
+    default:
+      return false;
+  }
+#undef CSIPM_A12
+}
+
+template <typename T>
+bool launch_axis3_mixed(int L, int mode, int np, const cx<T>* cs, cx<T>* cd, const uint32_t* maskbits,
+                        const cx<T>* twm, const cx<T>* tw3, T sc_c2r, T sc_dc, T sc_ac, const int* skip,
+                        hipStream_t s) {
+#define CSIPM_A3(NN)                                                                                     \
+  case NN / 2:                                                                                           \
+    launch_axis3_at<T, NN / 2>(mode, np, cs, cd, maskbits, twm, tw3, sc_c2r, sc_dc, sc_ac, skip, s); \
+    return true;
+  switch (L) {
+    CSIPM_MIXED_LENGTHS(CSIPM_A3)
+    default:
+      return false;
+  }
+#undef CSIPM_A3
+}
+
+// The instances used: PREFIX is empty where they are compiled and `extern`
+// where they are only called.
+#define CSIPM_MIXED_INST12(PREFIX, T, AX, DIR, EPI)                                                           \
+  PREFIX template bool launch_axis12_mixed<T, AX, DIR, EPI>(int, dim3, const cx<T>*, cx<T>*, StridedGeom<T>, \
+                                                            const cx<T>*, int, int, EPI, const int*, hipStream_t);
+#define CSIPM_MIXED_INSTANCES(PREFIX, T)                                                                   \
+  CSIPM_MIXED_INST12(PREFIX, T, 1, +1, EpiNone)                                                            \
+  CSIPM_MIXED_INST12(PREFIX, T, 1, -1, EpiNone)                                                            \
+  CSIPM_MIXED_INST12(PREFIX, T, 1, -1, EpiK<T>)                                                            \
+  CSIPM_MIXED_INST12(PREFIX, T, 2, +1, EpiNone)                                                            \
+  CSIPM_MIXED_INST12(PREFIX, T, 2, -1, EpiNone)                                                            \
+  PREFIX template bool launch_axis3_mixed<T>(int, int, int, const cx<T>*, cx<T>*, const uint32_t*, const cx<T>*, \
+                                             const cx<T>*, T, T, T, const int*, hipStream_t);
+
+}  // namespace fftk
+}  // namespace csipm

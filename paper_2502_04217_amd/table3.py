@@ -1,8 +1,8 @@
 """Time-to-solve on the paper's artificial test problem (section "Synthetic
-Dataset", table "tab:cpu_gpu_comparison_artificial") at the power-of-two grid
-sizes of that table, for a table beside it.
+Dataset", table "tab:cpu_gpu_comparison_artificial") at the grid sizes of
+that table, for a table beside it.
 
-    python -m paper_2502_04217_amd.table3 [--sizes 8 16 32 64 128 256 512] [--tol 1e-8] [--reps 3]
+    python -m paper_2502_04217_amd.table3 [--sizes 8 16 32 64 96 128 192 256 384 512 560] [--tol 1e-8] [--reps 3]
 
 Each size: the workload of workload.paper_synthetic, lambda = 0.05 ||M^T b||_inf,
 solved to rel_kkt <= tol (the paper stops at a primal-dual residual of 1e-8)
@@ -25,13 +25,14 @@ from . import csipm
 from . import workload as wl
 
 # GPU seconds of the paper's table for the same grid sizes (GH200)
-PAPER_GPU_S = {8: 0.63, 16: 0.72, 32: 0.68, 64: 0.71, 128: 1.07, 256: 5.88, 512: 104.55}
+PAPER_GPU_S = {8: 0.63, 16: 0.72, 32: 0.68, 64: 0.71, 96: 0.79, 128: 1.07, 192: 3.22, 256: 5.88, 384: 20.66,
+               512: 104.55, 560: 159.66}
 PARAMS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "pc_params.json")
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--sizes", type=int, nargs="+", default=[8, 16, 32, 64, 128, 256, 512])
+    ap.add_argument("--sizes", type=int, nargs="+", default=[8, 16, 32, 64, 96, 128, 192, 256, 384, 512, 560])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--reps", type=int, default=3)
     a = ap.parse_args(argv)

@@ -217,16 +217,38 @@ def grid512(seed: int = 1) -> Workload:
                          name=f"grid512-s{seed}")
 
 
+def paper_mask_params(N: int):
+    """(period, half-width) of the lattice-cube mask of paper_synthetic at
+    extent N: period 32 with half-width 8 (15.0 % missing) where 32 divides N,
+    period 16 with half-width 4 (17.8 %) at N = 16 and period 8 with
+    half-width 2 (24.4 %) at N = 8; otherwise the divisor P of N in [32, 128]
+    and half-width h whose missing fraction ((2h+1)/P)^3 is closest to 15 %
+    (N = 560: P = 70, h = 18, 14.8 %)."""
+    if N % 32 == 0:
+        return 32, 8
+    if N < 32:
+        return (16, 4) if N >= 16 else (8, 2)
+    best = None
+    for P in range(32, 129):
+        if N % P:
+            continue
+        for h in range(P // 2):
+            d = abs(((2 * h + 1) / P) ** 3 - 0.15)
+            if best is None or d < best[0]:
+                best = (d, P, h)
+    if best is None:
+        raise ValueError(f"no lattice period in [32, 128] divides {N}")
+    return best[1], best[2]
+
+
 def paper_synthetic(n_side: int, seed: int = 1) -> Workload:
     """The paper's artificial test problem (section "Synthetic Dataset"):
     x_ijk = f1(i) f2(j) f3(k) with f_a(t) = cos(2 pi a t / N) + 2 sin(2 pi a t / N)
     for a = 1, 2, 3 along the three axes, plus iid U[0, 1] noise on every
     sample.  The paper's "~15 %" missing samples come in an unspecified
-    pattern; here they are lattice cubes as in the other workloads: period 32
-    with half-width 8 (15.0 % missing) from N = 32 up, period 16 with
-    half-width 4 (17.8 %) at N = 16, period 8 with half-width 2 (24.4 %) at
-    N = 8.  The planted spectrum is the product formula itself, so wave_k and
-    wave_c are empty."""
+    pattern; here they are lattice cubes as in the other workloads, with the
+    period and half-width of paper_mask_params.  The planted spectrum is the
+    product formula itself, so wave_k and wave_c are empty."""
     N = int(n_side)
     if N < 8 or N % 8 != 0:
         raise ValueError("paper_synthetic needs N >= 8, a multiple of 8")
@@ -236,7 +258,7 @@ def paper_synthetic(n_side: int, seed: int = 1) -> Workload:
     clean = f[0][:, None, None] * f[1][None, :, None] * f[2][None, None, :]
     rng = np.random.default_rng(seed)
     noisy = clean + rng.uniform(0.0, 1.0, shape)
-    period, half = (32, 8) if N >= 32 else ((16, 4) if N >= 16 else (8, 2))
+    period, half = paper_mask_params(N)
     observed = (~lattice_cube_mask(shape, half, period)).astype(np.uint8)
     signal = np.where(observed == 1, noisy, 0.0)
     return Workload(shape=shape, signal=signal, observed=observed, clean=clean,

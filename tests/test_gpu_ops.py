@@ -14,6 +14,11 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = [(4, 4, 4), (8, 16, 32), (16, 16, 16), (32, 8, 64), (64, 64, 64), (4, 4, 1024), (1024, 4, 8),
           (8, 1024, 4), (128, 32, 16)]
+# extents with odd factors 3, 5 and 7: each small one once on every axis,
+# each of the paper's non-power-of-two sizes once on every axis, and 96^3
+_MIXED = [12, 20, 24, 28, 40, 48, 56, 70]
+MIXED_SHAPES = [(_MIXED[i], _MIXED[(i + 1) % 8], _MIXED[(i + 2) % 8]) for i in range(8)] + \
+    [s for N in (96, 192, 384, 560) for s in ((N, 4, 8), (8, N, 4), (4, 8, N))] + [(96, 96, 96)]
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
@@ -26,7 +31,7 @@ def _problem(shape, seed=0):
     return torch, csipm, csipm.Problem(sig, obs), sig, obs
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + MIXED_SHAPES)
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_operator_parity(shape, prec):
     torch, csipm, pr, sig, obs = _problem(shape, 1)
@@ -87,6 +92,38 @@ def test_full_size_256_properties_and_synthesis():
     xf = pr.apply_A(tb.float())
     assert rel_inf(xf.cpu().numpy(), w.clean) <= 1e-5
     g = torch.Generator(device="cuda").manual_seed(5)
+    b = torch.randn(w.shape, dtype=torch.float64, device="cuda", generator=g)
+    y = torch.randn(w.shape, dtype=torch.float64, device="cuda", generator=g)
+    Ab = pr.apply_A(b)
+    assert abs(float(Ab.norm() / b.norm()) - 1.0) < 1e-13
+    lhs = float((Ab * y).sum())
+    rhs = float((b * pr.apply_At(y)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * float(Ab.norm() * y.norm())
+    Hb = pr.apply_H(b)
+    HHb = pr.apply_H(Hb)
+    assert float((HHb - Hb).abs().max()) <= 1e-12 * float(Hb.abs().max())
+
+
+def test_full_size_560_properties_and_synthesis():
+    """560^3, the largest grid of the paper's size table (odd factors 5 and
+    7 on every axis): A applied to the oracle's beta of 32 planted waves
+    equals numpy's irfftn synthesis; Parseval, adjoint dot test and H
+    idempotence hold to round-off."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    say("560^3 full-size operator checks")
+    w = wl.make_workload((560, 560, 560), n_freq=64, amplitude="normal", snr_db=float("inf"), half_width=-1,
+                         period=1, dropout=0.15, seed=4)
+    pr = csipm.Problem(w.signal, w.observed)
+    beta = dft3.waves_to_beta(w.shape, w.wave_k, w.wave_c)
+    tb = torch.tensor(beta, device="cuda")
+    del beta
+    x = pr.apply_A(tb)
+    assert rel_inf(x.cpu().numpy(), w.clean) <= 1e-12
+    xf = pr.apply_A(tb.float())
+    assert rel_inf(xf.cpu().numpy(), w.clean) <= 1e-5
+    del x, xf, tb
+    g = torch.Generator(device="cuda").manual_seed(7)
     b = torch.randn(w.shape, dtype=torch.float64, device="cuda", generator=g)
     y = torch.randn(w.shape, dtype=torch.float64, device="cuda", generator=g)
     Ab = pr.apply_A(b)

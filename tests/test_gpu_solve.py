@@ -97,6 +97,51 @@ def test_grid64_parity(precision, trust):
     assert abs(info["rel_kkt"] - rel) <= 1e-3 * rel + 1e-15
 
 
+@pytest.mark.parametrize("shape,half,period,dropout", [((24, 20, 28), 0, 4, 0.03), ((12, 70, 40), -1, 1, 0.08)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mixed_grid_parity(shape, half, period, dropout, precision):
+    """Grids with odd factors 3, 5 and 7 (odd-radix FFT stages on every
+    axis): the same parity bar as the power-of-two grids."""
+    w = wl.make_workload(shape, n_freq=24, amplitude="normal", snr_db=20.0, half_width=half, period=period,
+                         dropout=dropout, seed=2)
+    lam = ipm.lambda_rule(w.signal, w.observed)
+    say("mixed-grid parity", shape, "precision", precision)
+    ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=PARITY_TOL))
+    assert ref.converged
+    pr, info, beta = _gpu_solve(w, lam, tol=PARITY_TOL, precision=precision)
+    say("  gpu", info["status_name"], info["ipm_iters"], info["cg_iters_total"], info["rel_kkt"],
+        "oracle", ref.iters, sum(ref.cg_iters))
+    assert info["status"] == 0
+    err = rel2(beta, ref.state.beta)
+    say("  rel err vs oracle", err)
+    assert err <= 1e-7
+    ok, amb = _supports_match(beta, ref.state.beta)
+    assert ok
+
+
+def test_paper_synthetic_96_certificate():
+    """96^3, the first non-power-of-two size of the paper's synthetic table,
+    at the table's tolerance (1e-8): the oracle certifies the FP64 solution
+    and the FP32+refinement solution matches it."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.paper_synthetic(96)
+    pr = csipm.Problem(w.signal, w.observed)
+    lam = pr.lambda_rule(0.05)
+    say("96^3 paper synthetic, FP64 and FP32+refine")
+    i64 = pr.solve(tol=1e-8, precision=0)
+    b64 = pr.get(csipm.BETA).cpu().numpy()
+    i32 = pr.solve(tol=1e-8, precision=1)
+    b32 = pr.get(csipm.BETA).cpu().numpy()
+    say("  ", i64, i32)
+    assert i64["status"] == 0 and i32["status"] == 0
+    assert rel2(b32, b64) <= 1e-5
+    cert = ipm.lasso_certificate(b64, w.signal, w.observed, lam)
+    say("  certificate", cert.natural_residual, cert.rel_gap, cert.max_offsupport_ratio)
+    assert cert.max_offsupport_ratio <= 1.0 + 1e-6
+    assert cert.rel_gap <= 1e-6
+
+
 def test_first_iterations_track_oracle():
     """Same algorithm and constants: the per-iteration CG counts and mu agree
     with the oracle's over the first iterations (basis-independent CG)."""
@@ -136,6 +181,8 @@ def test_precision_floor_stops_cleanly():
     ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=PARITY_TOL))
     pr, info, beta = _gpu_solve(w, lam, tol=1e-14, precision=1)
     say("  floor", info["status_name"], info["ipm_iters"], info["rel_kkt"])
+    for rec in pr.log():
+        say("   ", rec)
     assert info["status"] in (0, 2)
     assert info["rel_kkt"] <= 1e-9
     assert rel2(beta, ref.state.beta) <= 1e-6

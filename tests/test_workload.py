@@ -24,3 +24,17 @@ def test_paper_synthetic(N, frac):
     # the clean signal is a product of three real waves: 8 nonzero DFT bins
     spec = np.fft.fftn(w.clean)
     assert int((np.abs(spec) > 1e-8 * np.abs(spec).max()).sum()) == 8
+
+
+@pytest.mark.parametrize("N,period,half", [(96, 32, 8), (192, 32, 8), (384, 32, 8), (560, 70, 18), (40, 40, 10)])
+def test_paper_mask_params(N, period, half):
+    """The 15 % lattice at the non-power-of-two extents of the paper's table:
+    a period that divides N, and a missing fraction within 1 % of 15 %."""
+    assert wl.paper_mask_params(N) == (period, half)
+    assert N % period == 0
+    assert abs(((2 * half + 1) / period) ** 3 - 0.15) < 1e-2
+
+
+def test_paper_synthetic_mixed_extent():
+    w = wl.paper_synthetic(40, seed=1)
+    assert abs(w.missing_fraction - (21 / 40) ** 3) < 1e-12
