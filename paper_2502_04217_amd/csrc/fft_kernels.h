@@ -200,9 +200,22 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* tw) 
     if (EX || j < L / r) {
       if constexpr (Ns > 1) {
         const int jm = j % Ns;
+        if constexpr (odd_part(L) > 1) {
+          // lengths with odd factors: one table load per butterfly, the
+          // higher twiddles w^q as powers of w (at most 6 products)
+          const cx<T> w1 = twiddle<T>(tw, jm * (L / (Ns * r)), DIR);
+          cx<T> wq = w1;
+          v[i * r + 1] = cmul(v[i * r + 1], w1);
 #pragma unroll
-        for (int q = 1; q < r; ++q) {
-          v[i * r + q] = cmul(v[i * r + q], twiddle<T>(tw, jm * q * (L / (Ns * r)), DIR));
+          for (int q = 2; q < r; ++q) {
+            wq = cmul(wq, w1);
+            v[i * r + q] = cmul(v[i * r + q], wq);
+          }
+        } else {
+#pragma unroll
+          for (int q = 1; q < r; ++q) {
+            v[i * r + q] = cmul(v[i * r + q], twiddle<T>(tw, jm * q * (L / (Ns * r)), DIR));
+          }
         }
       }
       dft_any<r, DIR, T>(&v[i * r]);
@@ -249,14 +262,16 @@ __device__ __forceinline__ void fft_stages(cx<T>* v, int t, cx<T>* lds, LIdx lid
 template <int L, int E>
 constexpr int last_stage() { return Radix<L, E>::NSTAGES - 1; }
 
-// Elements per thread of a pencil with odd factors: the odd part times up
-// to 4 when the odd part is at most 7 (12, 20 or 28 values), else the odd
-// part alone; the thread count per pencil L/E is then a power of two.
+// Elements per thread of a pencil with odd factors: the odd part (its
+// smallest prime factor when the odd part exceeds 7) times up to 4: 12, 20
+// or 28 values for odd parts 3, 5, 7; 20 for odd part 35 (70, 280, 560),
+// whose largest radix-7 stage is then the only guarded one.
 constexpr int mixed_e(int L) {
   const int F = odd_part(L), P = L / F;
-  const int q = F <= 7 ? (P < 4 ? P : 4) : 1;
-  return F * q;
+  const int f = F <= 7 ? F : smallest_odd_factor(F);
+  return f * (P < 4 ? P : 4);
 }
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 
 // ------------------------------------------------------- block reduction --
 __device__ __forceinline__ double wave_sum(double v) {
@@ -387,14 +402,21 @@ constexpr int strided_e(int w, int L, int axis, int dir) {
 constexpr int strided_lds(int w, int axis, int dir) {
   return axis == 2 ? 65536 : (w == 16 && dir > 0 ? 65536 : 131072);
 }
+// TM is the power of two that the LDS budget gives (at most 64), raised
+// until each access is a run of at least 128 contiguous bytes (a whole
+// cache line) and the workgroup is whole waves (block reductions), within
+// 160 KB of LDS and 1024 threads.
 constexpr int strided_tm(int w, int L, int axis, int dir) {
+  const int nt = L / strided_e(w, L, axis, dir);
   int tm = strided_lds(w, axis, dir) / (L * w);
   if (tm > 64) tm = 64;
   if (tm < 1) tm = 1;
   int p = 1;
   while (2 * p <= tm) p *= 2;
   tm = p;
-  while (tm * (L / strided_e(w, L, axis, dir)) > 1024) tm >>= 1;
+  while (tm * w < 128 && 2 * tm * L * w <= 163840 && 2 * tm * nt <= 1024) tm *= 2;
+  while ((tm * nt) % 64 != 0 && 2 * tm * L * w <= 163840 && 2 * tm * nt <= 1024) tm *= 2;
+  while (tm * nt > 1024) tm >>= 1;
   return tm;
 }
 template <typename T, int L, int AX, int DIR>
@@ -458,6 +480,7 @@ void launch_axis12_at(dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> ge
   constexpr int TM = strided_tm(int(sizeof(cx<T>)), L, AX, DIR);
   constexpr int NT = L / strided_e(int(sizeof(cx<T>)), L, AX, DIR);
   static_assert((TM * NT) % 64 == 0 && TM * NT <= 1024, "strided tile must be whole waves");
+  static_assert((size_t)TM * L * sizeof(cx<T>) <= 163840, "strided tile exceeds the LDS of a CU");
   const size_t shm = (size_t)TM * L * sizeof(cx<T>);
   auto kern = k_axis12<T, L, AX, DIR, Epi>;
   if (shm > 65536)
@@ -466,9 +489,18 @@ void launch_axis12_at(dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> ge
 }
 
 // ------------------------------------------------------ axis-3 (c2r/r2c) --
+// Elements per thread of the axis-3 pass, the measured best per length:
+// 8 for power-of-two pencils; for odd parts above 7 the smallest odd factor
+// times up to 2 (10 at L = 280: 12 % and 17 % faster than 20 or 35 in FP32
+// and FP64 at 256 x 256 x 560); mixed_e otherwise.
 template <typename T>
-constexpr int a3_e(int L) {   // 8 elements per thread for power-of-two pencils (measured best)
-  return odd_part(L) != 1 ? mixed_e(L) : (L < 8 ? L : 8);
+constexpr int a3_e(int L) {
+  if (odd_part(L) == 1) return L < 8 ? L : 8;
+  if (odd_part(L) > 7) {
+    const int P = L / odd_part(L);
+    return smallest_odd_factor(odd_part(L)) * (P < 2 ? P : 2);
+  }
+  return mixed_e(L);
 }
 // one wave per workgroup: the pass synchronises between its many LDS
 // stages, and at 256^3 the single-wave group is the fastest tile measured
@@ -566,14 +598,20 @@ k_axis3(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask,
   }
 
   // forward half-length FFT of z' and the r2c post-processing
-  fft_stages<T, L, E, -1, 0>(v, t, lds, lidx, twm);
+  int tf = t;
+  if constexpr (MODE == A3_FULL && odd_part(L) > 1) {
+    // the forward half recomputes its indices instead of keeping those of
+    // the inverse half live across it
+    asm volatile("" : "+v"(tf));
+  }
+  fft_stages<T, L, E, -1, 0>(v, tf, lds, lidx, twm);
   __syncthreads();
-  for_stage_io<L, E, SL>(t, [&](int s, int e) { lds[lidx(e)] = v[s]; });
+  for_stage_io<L, E, SL>(tf, [&](int s, int e) { lds[lidx(e)] = v[s]; });
   __syncthreads();
   if (!active) return;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
-    const int e = t + q * NT;
+    const int e = tf + q * NT;
     cx<T> xo;
     if (e == 0) {
       const cx<T> z0 = lds[lidx(0)];
