@@ -13,8 +13,9 @@
  * Conventions shared by every entry point
  *  - Grid: N1 x N2 x N3, each a power of two in [4, 1024] or one of the
  *    extents with odd factors 12, 20, 24, 28, 40, 48, 56, 70, 96, 192, 384,
- *    560 (the FFT passes have radix-3, -5 and -7 stages); n = N1*N2*N3.
- *    Other extents return CSIPM_EUNSUPPORTED.
+ *    560 (the FFT passes have radix-3, -5 and -7 stages); N1 and N2 may
+ *    also be 1 or 2, so a 2D problem is the grid 1 x N2 x N3 and a 1D one
+ *    1 x 1 x N3; n = N1*N2*N3.  Other extents return CSIPM_EUNSUPPORTED.
  *  - Real-space arrays are row-major [N1][N2][N3] (index j3 fastest).
  *  - beta-space arrays ("external beta layout") are row-major [N1][N2][N3]
  *    indexed by the frequency k: beta[k] = v_k for self-conjugate k

@@ -441,7 +441,7 @@ void csipm_default_options(csipm_options* o) {
 }
 
 size_t csipm_workspace_bytes(int n1, int n2, int n3) {
-  if (!fft_extent_supported(n1) || !fft_extent_supported(n2) || !fft_extent_supported(n3)) return 0;
+  if (!fft_extent_supported(n1, 1) || !fft_extent_supported(n2, 2) || !fft_extent_supported(n3, 3)) return 0;
   csipm_ctx tmp;
   Carver cv{nullptr, 0, 0};
   return layout(cv, &tmp, n1, n2, n3);
@@ -452,7 +452,7 @@ csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double*
   if (!out) return CSIPM_EINVAL;
   *out = nullptr;
   if (!d_signal || !d_observed || !d_workspace) return CSIPM_EINVAL;
-  if (!fft_extent_supported(n1) || !fft_extent_supported(n2) || !fft_extent_supported(n3)) return CSIPM_EUNSUPPORTED;
+  if (!fft_extent_supported(n1, 1) || !fft_extent_supported(n2, 2) || !fft_extent_supported(n3, 3)) return CSIPM_EUNSUPPORTED;
   if ((reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0) return CSIPM_EINVAL;
   const size_t need = csipm_workspace_bytes(n1, n2, n3);
   if (workspace_bytes < need) return CSIPM_ENOMEM;

@@ -195,10 +195,11 @@ void launch_postmix(const Grid& g, const T* work, T* out, int epi, const EpiArgs
 // workgroups of a strided pass (axis 1 or 2, complex size elem_bytes, dir +1
 // inverse / -1 forward); for the axis-1 forward pass also its partial count
 int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir);
-// whether the FFT passes have kernels for a grid extent N (axes 1 and 2 at
-// length N, axis 3 at N/2): powers of two in [4, 1024] and the extents with
-// odd factors that fft_mixed.hip instantiates
-bool fft_extent_supported(int N);
+// whether the FFT passes have kernels for extent N on `axis` (1, 2: pencils
+// of length N; 3: half length N/2): powers of two in [4, 1024], the extents
+// with odd factors that fft_mixed_f64/f32.hip instantiate, and on axes 1
+// and 2 also 1 and 2 (2D and 1D grids)
+bool fft_extent_supported(int N, int axis);
 int postmix_blocks(const Grid& g);
 
 // permutation between the external beta layout and the internal one

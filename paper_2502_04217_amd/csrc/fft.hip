@@ -184,6 +184,8 @@ void launch_axis12_L(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom
     launch_axis12_at<T, LL, AX, DIR, Epi>(grid, src, dst, geo, tw, m, m0, epi, skip, s); \
     break;
   switch (L) {
+    CSIPM_A12(1)
+    CSIPM_A12(2)
     CSIPM_A12(4)
     CSIPM_A12(8)
     CSIPM_A12(16)
@@ -226,7 +228,8 @@ int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir) {
   return (batch + tm - 1) / tm;
 }
 
-bool fft_extent_supported(int N) {
+bool fft_extent_supported(int N, int axis) {
+  if (axis != 3 && (N == 1 || N == 2)) return true;
   if (N >= 4 && N <= 1024 && (N & (N - 1)) == 0) return true;
 #define CSIPM_IS(NN) if (N == NN) return true;
   CSIPM_MIXED_LENGTHS(CSIPM_IS)

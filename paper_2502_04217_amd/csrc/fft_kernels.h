@@ -74,9 +74,10 @@ struct Radix {
   }
   static constexpr int REM = rem();
   static constexpr int NPOW = NFULL + (REM > 1 ? 1 : 0);
-  static constexpr int NSTAGES = NPOW + odd_factor_count(odd_part(L));
+  // a length-1 pencil (a 2D or 1D grid) has one identity stage of radix 1
+  static constexpr int NSTAGES = L == 1 ? 1 : NPOW + odd_factor_count(odd_part(L));
   static constexpr int radix(int s) {
-    return s < NFULL ? P2 : (s < NPOW ? REM : odd_factor(odd_part(L), s - NPOW));
+    return L == 1 ? 1 : (s < NFULL ? P2 : (s < NPOW ? REM : odd_factor(odd_part(L), s - NPOW)));
   }
   static constexpr int ns(int s) {
     int v = 1;

@@ -37,7 +37,8 @@ def test_host_only_calls():
     from paper_2502_04217_amd import csipm
     assert csipm.workspace_bytes((256, 256, 256)) > 200 * 256 ** 3
     assert csipm.workspace_bytes((6, 8, 8)) == 0
-    assert csipm.workspace_bytes((2, 8, 8)) == 0
+    assert csipm.workspace_bytes((8, 8, 2)) == 0
+    assert csipm.workspace_bytes((1, 8, 8)) > 0
     o = csipm.default_options()
     assert o.tol == 1e-6 and o.sigma == 0.1 and o.tau == 0.99
     assert csipm.lib().csipm_status_string(-5) == b"unsupported grid"

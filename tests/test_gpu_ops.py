@@ -19,6 +19,8 @@ SHAPES = [(4, 4, 4), (8, 16, 32), (16, 16, 16), (32, 8, 64), (64, 64, 64), (4, 4
 _MIXED = [12, 20, 24, 28, 40, 48, 56, 70]
 MIXED_SHAPES = [(_MIXED[i], _MIXED[(i + 1) % 8], _MIXED[(i + 2) % 8]) for i in range(8)] + \
     [s for N in (96, 192, 384, 560) for s in ((N, 4, 8), (8, N, 4), (4, 8, N))] + [(96, 96, 96)]
+# 2D (N1 = 1) and 1D (N1 = N2 = 1) grids, and extent 2 on the strided axes
+LOWDIM_SHAPES = [(1, 64, 64), (1, 1, 256), (2, 96, 40), (1, 560, 12), (64, 1, 32), (2, 2, 8), (1, 1, 4)]
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
@@ -31,7 +33,7 @@ def _problem(shape, seed=0):
     return torch, csipm, csipm.Problem(sig, obs), sig, obs
 
 
-@pytest.mark.parametrize("shape", SHAPES + MIXED_SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + MIXED_SHAPES + LOWDIM_SHAPES)
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_operator_parity(shape, prec):
     torch, csipm, pr, sig, obs = _problem(shape, 1)
@@ -167,7 +169,10 @@ def test_errors():
         csipm.Problem(np.zeros((6, 8, 8)), np.ones((6, 8, 8), np.uint8))
     assert e.value.status == -5
     with pytest.raises(csipm.CsipmError) as e:
-        csipm.Problem(np.zeros((2, 8, 8)), np.ones((2, 8, 8), np.uint8))
+        csipm.Problem(np.zeros((8, 8, 2)), np.ones((8, 8, 2), np.uint8))
+    assert e.value.status == -5
+    with pytest.raises(csipm.CsipmError) as e:
+        csipm.Problem(np.zeros((8, 18, 8)), np.ones((8, 18, 8), np.uint8))
     assert e.value.status == -5
     pr = csipm.Problem(np.random.default_rng(0).standard_normal((8, 8, 8)), obs)
     with pytest.raises(csipm.CsipmError) as e:

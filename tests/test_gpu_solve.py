@@ -97,11 +97,13 @@ def test_grid64_parity(precision, trust):
     assert abs(info["rel_kkt"] - rel) <= 1e-3 * rel + 1e-15
 
 
-@pytest.mark.parametrize("shape,half,period,dropout", [((24, 20, 28), 0, 4, 0.03), ((12, 70, 40), -1, 1, 0.08)])
+@pytest.mark.parametrize("shape,half,period,dropout", [((24, 20, 28), 0, 4, 0.03), ((12, 70, 40), -1, 1, 0.08),
+                                                       ((1, 64, 96), -1, 1, 0.1), ((1, 1, 512), -1, 1, 0.15)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_mixed_grid_parity(shape, half, period, dropout, precision):
     """Grids with odd factors 3, 5 and 7 (odd-radix FFT stages on every
-    axis): the same parity bar as the power-of-two grids."""
+    axis), a 2D grid (1 x 64 x 96) and a 1D one (1 x 1 x 512): the same
+    parity bar as the 3D power-of-two grids."""
     w = wl.make_workload(shape, n_freq=24, amplitude="normal", snr_db=20.0, half_width=half, period=period,
                          dropout=dropout, seed=2)
     lam = ipm.lambda_rule(w.signal, w.observed)
