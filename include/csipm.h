@@ -118,6 +118,16 @@ typedef struct {
   double pc_rho;       /* CSIPM_PC_SCALED: rho (default 0 = m/n, the
                           observed fraction: H = M_perp^T M_perp has mean
                           diagonal m/n)                                      */
+  double pc_max_relevant; /* learned correction: applied only when at most
+                          this fraction of the coefficients are relevant,
+                          L1 / (L1 + 4 S1 S2) >= 1e-3 at the current
+                          iterate (default 0.5).  Early iterates have every
+                          coefficient relevant and need one or two PCG
+                          iterations with the paper's P, so evaluating the
+                          network on all n coefficients cannot pay; late
+                          iterates have the relevant set near the support,
+                          where the network runs on few chunks.  1 = no
+                          limit.                                              */
 } csipm_options;
 
 typedef struct {
@@ -140,6 +150,9 @@ typedef struct {
   int iter, cg_iters, refine_steps, fell_back;
   int learned;   /* 1 when the learned correction was applied to this system */
   double mu, rel_kkt, alpha;
+  double relevant; /* learned form: fraction of coefficients where the
+                      correction can matter at this iterate (see
+                      pc_max_relevant); -1 in the other forms            */
 } csipm_iter_log;
 
 /* Fills `o` with the defaults listed in csipm_options. */

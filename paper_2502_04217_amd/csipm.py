@@ -36,7 +36,7 @@ class Options(C.Structure):
                 ("cg_atol", C.c_double), ("sigma", C.c_double), ("tau", C.c_double), ("precision", C.c_int),
                 ("pc", C.c_int), ("refine_max", C.c_int), ("refine_inner_rtol", C.c_double),
                 ("refine_trust", C.c_double), ("pc_min_cg", C.c_int), ("krylov", C.c_int),
-                ("pc_rho", C.c_double)]
+                ("pc_rho", C.c_double), ("pc_max_relevant", C.c_double)]
 
 
 class Info(C.Structure):
@@ -59,7 +59,8 @@ class KernelTime(C.Structure):
 
 class IterLog(C.Structure):
     _fields_ = [("iter", C.c_int), ("cg_iters", C.c_int), ("refine_steps", C.c_int), ("fell_back", C.c_int),
-                ("learned", C.c_int), ("mu", C.c_double), ("rel_kkt", C.c_double), ("alpha", C.c_double)]
+                ("learned", C.c_int), ("mu", C.c_double), ("rel_kkt", C.c_double), ("alpha", C.c_double),
+                ("relevant", C.c_double)]
 
 
 def load_library(path: str = LIB_PATH):

@@ -23,8 +23,6 @@ using namespace csipm;
 namespace {
 
 constexpr size_t kAlign = 256;
-// the learned correction is evaluated where L1 / (L1 + 4 S1 S2) >= this
-constexpr double kPcRelevance = 1e-3;
 
 
 struct Carver {
@@ -169,7 +167,7 @@ size_t layout(Carver& cv, csipm_ctx* c, int n1, int n2, int n3) {
   c->tw64 = cv.take<cx<double>>(ntw);
   c->tw32 = cv.take<cx<float>>(ntw);
   c->partK = cv.take<double>(2 * k_partials(n1, n2, n3));   // up to two quantities
-  c->partV = cv.take<double>((size_t)VEC_MAX_BLOCKS * 8);
+  c->partV = cv.take<double>((size_t)VEC_MAX_BLOCKS * 16);
   c->scal = cv.take<double>(S_COUNT);
   c->flags = cv.take<int>(F_COUNT);
   return cv.off + kAlign;
@@ -438,6 +436,7 @@ void csipm_default_options(csipm_options* o) {
   o->pc_min_cg = 2;
   o->krylov = CSIPM_KRYLOV_CG;
   o->pc_rho = 0.0;
+  o->pc_max_relevant = 0.5;
 }
 
 size_t csipm_workspace_bytes(int n1, int n2, int n3) {
@@ -680,12 +679,13 @@ void restore_state(csipm_ctx* c) {
 
 struct Resid {
   double fb, fz, cmax, csum, bmax, pmin, nonfinite;
+  double relevant;   // coefficients where the learned correction can matter (when reduced)
 };
 
 // Residual parts last reduced into scal[S_RESID..] (after a sync).
 Resid read_resid(const csipm_ctx* c) {
   const double* v = c->hscal + S_RESID;
-  return Resid{v[0], v[1], v[2], v[3], v[4], v[5], v[6]};
+  return Resid{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[8]};
 }
 
 // Residual parts with H beta recomputed by a full H-apply (and the sum of
@@ -721,6 +721,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       (o.precision != CSIPM_FP64 && o.precision != CSIPM_FP32) ||
       (o.pc != CSIPM_PC_PLAIN && o.pc != CSIPM_PC_LEARNED && o.pc != CSIPM_PC_SCALED) ||
       (o.krylov != CSIPM_KRYLOV_CG && o.krylov != CSIPM_KRYLOV_CR) || !(o.pc_rho >= 0.0) ||
+      !(o.pc_max_relevant >= 0.0 && o.pc_max_relevant <= 1.0) ||
       !(o.refine_trust >= 0.0 && o.refine_trust <= 1.0) || !(o.refine_inner_rtol > 0.0) || o.pc_min_cg < 0)
     return fail(c, CSIPM_EINVAL, "invalid options");
   if (o.pc == CSIPM_PC_LEARNED && !c->have_params) return fail(c, CSIPM_ESTATE, "learned preconditioner has no parameters");
@@ -824,9 +825,12 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     const bool capture =
         c->cap_enable && o.pc == CSIPM_PC_PLAIN && o.krylov == CSIPM_KRYLOV_CG && c->cap_count < c->cap_max;
     // the correction is applied once a Newton system has needed more than
-    // pc_min_cg - 1 PCG iterations: a system the paper's P solves in one
-    // iteration leaves nothing to gain
-    const bool use_learned = o.pc == CSIPM_PC_LEARNED && prev_cg >= o.pc_min_cg;
+    // pc_min_cg - 1 PCG iterations (a system the paper's P solves in one
+    // iteration leaves nothing to gain) and while at most pc_max_relevant of
+    // the coefficients are relevant (reduced with the residual of the
+    // iterate)
+    const double relevant = learned ? r.relevant / (double)n : -1.0;
+    const bool use_learned = learned && prev_cg >= o.pc_min_cg && relevant <= o.pc_max_relevant;
     if (use_learned) {
       st = learned_correction(c, true);
       if (st != CSIPM_OK) return st;
@@ -878,7 +882,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     exact = false;
     approx = approx || src == HD_RRES32;
     ++carried;
-    c->log.push_back(csipm_iter_log{it, cgi, ref, fell ? 1 : 0, use_learned ? 1 : 0, mu, rel, 0.0});
+    c->log.push_back(csipm_iter_log{it, cgi, ref, fell ? 1 : 0, use_learned ? 1 : 0, mu, rel, 0.0, relevant});
     inf.ipm_iters = it + 1;
   }
   inf.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

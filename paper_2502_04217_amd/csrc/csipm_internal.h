@@ -127,6 +127,10 @@ enum EpiMode {
   EPI_R = 2       // FP64 only: H d_beta out and r.P^{-1}r of r = h - K d
 };
 
+// the learned correction is evaluated where L1 / (L1 + 4 S1 S2) >= this
+// (elsewhere the 2x2 block of P_c does not depend on c to this precision)
+constexpr double kPcRelevance = 1e-3;
+
 template <typename T>
 struct KArgs {
   const T* pb;        // p_beta (internal layout)

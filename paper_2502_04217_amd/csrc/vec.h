@@ -26,11 +26,11 @@ enum ScalarSlot {
   S_ZW = 7,        // conjugate residuals: z.K z of the current iterate
   S_AMAX = 8,      // IPM: largest feasible step
   S_ALPHA_IPM = 9, // IPM: step taken
-  S_RESID = 16,    // IPM residual block, 8 values (k_ipm_resid order)
-  S_REF = 24,      // refinement: r.P^{-1}r of the FP64 residual
-  S_REF0 = 25,     // refinement: rhs.P^{-1}rhs
-  S_REFRZ = 26,    // refinement: r32.P^{-1}r32, start of the next inner PCG
-  S_REFINF = 27,   // refinement: max |r| of the FP64 residual
+  S_REF = 10,      // refinement: r.P^{-1}r of the FP64 residual
+  S_REF0 = 11,     // refinement: rhs.P^{-1}rhs
+  S_REFRZ = 12,    // refinement: r32.P^{-1}r32, start of the next inner PCG
+  S_REFINF = 13,   // refinement: max |r| of the FP64 residual
+  S_RESID = 16,    // IPM residual block, 9 values (k_ipm_resid order)
   S_SIG = 28,      // signal check: non-finite count, observed count
   S_MISC = 32,     // free scratch (32 values)
   S_COUNT = 64

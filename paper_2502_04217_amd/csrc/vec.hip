@@ -306,8 +306,8 @@ k_ipm_init(double* __restrict__ beta, double* __restrict__ z, double* __restrict
 // complementarity: [max|F_b|, max|F_z|, max s.nu, sum s.nu, max|beta|,
 // min(s, nu), count of non-finite values, sum log(S1 + S2) (when logsum is
 // set: the centring of the learned correction's first feature)].
-constexpr int NRESID = 8;
-#define CSIPM_RESID_OPS {RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM, RED_SUM}
+constexpr int NRESID = 9;
+#define CSIPM_RESID_OPS {RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM, RED_SUM, RED_SUM}
 
 __device__ __forceinline__ void resid_accumulate(double* v, double b, double s1, double s2, double a1, double a2,
                                                  double fb, double fz, int logsum) {
@@ -319,7 +319,13 @@ __device__ __forceinline__ void resid_accumulate(double* v, double b, double s1,
   v[4] = fmax(v[4], fabs(b));
   v[5] = fmin(v[5], fmin(fmin(s1, s2), fmin(a1, a2)));
   if (!isfinite(fb) || !isfinite(c1) || !isfinite(c2)) v[6] += 1.0;
-  if (logsum) v[7] += log(a1 / s1 + a2 / s2);
+  if (logsum) {
+    v[7] += log(a1 / s1 + a2 / s2);
+    // coefficients where the learned correction can matter: L1 / (L1 +
+    // 4 S1 S2) >= kPcRelevance, multiplied through by s1 s2 > 0
+    const double num = a1 * s2 + a2 * s1;
+    v[8] += num >= kPcRelevance * (num + 4.0 * a1 * a2) ? 1.0 : 0.0;
+  }
 }
 __global__ void __launch_bounds__(256)
 k_ipm_resid(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
@@ -332,7 +338,7 @@ k_ipm_resid(const double* __restrict__ beta, const double* __restrict__ z, const
   CSIPM_ALIGN(hb);
   CSIPM_ALIGN(xi);
 
-  double v[NRESID] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0};
+  double v[NRESID] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0};
   CSIPM_PAIRS(n) {
     const double b = beta[i], zz = z[i], a1 = nu1[i], a2 = nu2[i];
     const double s1 = zz + b, s2 = zz - b;
@@ -521,7 +527,7 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
               double lam, double smu, const double* __restrict__ scal, long long n, double* partial, int stride,
               int logsum) {
   const double a = scal[S_ALPHA_IPM];
-  double v[NRESID] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0};
+  double v[NRESID] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0};
   using D2 = cx<double>;
   D2 *BE = (D2*)beta, *ZV = (D2*)z, *N1 = (D2*)nu1, *N2 = (D2*)nu2, *HBV = (D2*)hbeta;
   const D2 *XI = (const D2*)xi, *DB = (const D2*)db, *DZ = (const D2*)dz, *W = (const D2*)(hd ? hd : rres);
@@ -830,7 +836,7 @@ void ipm_resid(const double* beta, const double* z, const double* nu1, const dou
                const double* xi, double lam, long long n, double* partial, double* out8, bool logsum, hipStream_t s) {
   const int nb = vec_blocks(n);
   hipLaunchKernelGGL(k_ipm_resid, VB, beta, z, nu1, nu2, hb, xi, lam, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0);
-  hipLaunchKernelGGL((k_fin_reduce<8>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out8,
+  hipLaunchKernelGGL((k_fin_reduce<NRESID>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out8,
                      kResidRedOps);
 }
 void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* db,
@@ -847,7 +853,7 @@ void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbet
   const int nb = vec_blocks(n);
   hipLaunchKernelGGL(k_ipm_advance, VB, beta, z, nu1, nu2, hbeta, xi, db, dz, hd, rres, rres32, db32, dz32, lam, smu,
                      scal, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0);
-  hipLaunchKernelGGL((k_fin_reduce<8>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, scal + S_RESID,
+  hipLaunchKernelGGL((k_fin_reduce<NRESID>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, scal + S_RESID,
                      kResidRedOps);
 }
 void add_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s) {

@@ -119,22 +119,38 @@ def test_learned_solve_same_solution_and_fallback():
     pr.set_lambda(lam)
     pr.set_pc_params(torch.tensor(_params(3), device="cuda"))
     for prec in (0, 1):
-        for min_cg in (0, 2):
-            info = pr.solve(tol=1e-11, pc=1, precision=prec, pc_min_cg=min_cg)
+        for min_cg, max_rel in ((0, 1.0), (2, 1.0), (2, 0.5)):
+            info = pr.solve(tol=1e-11, pc=1, precision=prec, pc_min_cg=min_cg, pc_max_relevant=max_rel)
             beta = pr.get(csipm.BETA).cpu().numpy()
             log = pr.log()
-            say("learned solve precision", prec, "pc_min_cg", min_cg, info)
+            say("learned solve precision", prec, "pc_min_cg", min_cg, "pc_max_relevant", max_rel, info)
+            say("  relevant", [round(r["relevant"], 4) for r in log])
             assert info["status"] in (0, 3)
             assert rel2(beta, ref.state.beta) <= 1e-7
-            # the correction is applied exactly where the previous system needed >= pc_min_cg iterations
+            # the correction is applied exactly where the previous system needed
+            # >= pc_min_cg iterations and at most max_rel of the coefficients are relevant
             prev = [0] + [r["cg_iters"] for r in log[:-1]]
-            assert [r["learned"] for r in log] == [int(p >= min_cg) for p in prev]
+            assert all(0.0 <= r["relevant"] <= 1.0 for r in log)
+            assert [r["learned"] for r in log] == [int(p >= min_cg and r["relevant"] <= max_rel)
+                                                   for p, r in zip(prev, log)]
+    # the logged relevant fraction of iterate m equals L1 / (L1 + 4 S1 S2) >= 1e-3
+    # counted on the host from that iterate (a solve stopped after m iterations)
+    for m in (2, 6):
+        pr.solve(tol=1e-11, pc=1, precision=0, pc_min_cg=0, pc_max_relevant=1.0, max_iter=m)
+        b, z, n1, n2 = (pr.get(v).cpu().numpy() for v in (csipm.BETA, csipm.Z, csipm.NU1, csipm.NU2))
+        s1, s2 = z + b, z - b
+        num = n1 * s2 + n2 * s1
+        frac = float(np.mean(num >= 1e-3 * (num + 4 * n1 * n2)))
+        pr.solve(tol=1e-11, pc=1, precision=0, pc_min_cg=0, pc_max_relevant=1.0, max_iter=m + 1)
+        logged = pr.log()[m]["relevant"]
+        say("  iterate", m, "relevant fraction host", frac, "logged", logged)
+        assert abs(logged - frac) <= 2.0 / b.size
     # a correction of 1e6 makes P_c a poor preconditioner: the learned
     # systems exceed the budget and restart with the paper's P
     bad = mlp.init_params(0, out_scale=0.0)
     bad[-1] = 1e6
     pr.set_pc_params(torch.tensor(bad.astype(np.float32), device="cuda"))
-    info = pr.solve(tol=1e-11, pc=1, cg_max=30, pc_min_cg=0)
+    info = pr.solve(tol=1e-11, pc=1, cg_max=30, pc_min_cg=0, pc_max_relevant=1.0)
     say("forced fallback", info)
     assert info["fallbacks"] > 0 and info["status"] == 3
     assert rel2(pr.get(csipm.BETA).cpu().numpy(), ref.state.beta) <= 1e-7
