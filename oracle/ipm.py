@@ -173,6 +173,63 @@ def pcr(apply_K, apply_Pinv, rb, rz, *, atol=0.0, rtol=1e-10, maxit=500):
     return PCGResult(xb, xz, it, hist, hist[-1] <= tol)
 
 
+def pcar(apply_K, apply_Pinv, rb, rz, *, atol=0.0, rtol=1e-10, maxit=500):
+    """Preconditioned conjugate A-residuals (CAr, the third Krylov method that
+    section "Krylov methods and preconditioners" lists for SPD systems, from
+    the MinAres work it cites), x0 = 0.  With the split P = L L^T and the
+    symmetric operator A = L^{-1} K L^{-T}, CAr is CG in the inner product
+    <a, b> = a^T A^3 b: it minimises ||A r~|| = ||K z||_{P^{-1}} (z = P^{-1} r,
+    the preconditioned A-residual) over the Krylov space.  Vectors, with
+    w = K z and u = P^{-1} w:
+      alpha = (u.s) / (t.P^{-1}t), where s = K u, and t = K v, v = P^{-1} q,
+      q = K p along the direction p;
+      x += alpha p,  r -= alpha q,  w -= alpha t,  then z, u, s anew;
+      beta = (u.s)_new / (u.s)_old;  p = z + beta p, q = w + beta q,
+      t = s + beta t  (v = P^{-1} q follows).
+    One K product per step (s = K u).  Stops on the same preconditioned
+    residual norm sqrt(r.P^{-1}r) as pcg, or when the A-residual has vanished
+    in floating point (u.s or t.P^{-1}t no longer positive)."""
+    xb = np.zeros_like(rb)
+    xz = np.zeros_like(rz)
+    rb = rb.copy()
+    rz = rz.copy()
+    zb, zz = apply_Pinv(rb, rz)
+    rho = float(np.sum(rb * zb) + np.sum(rz * zz))
+    hist = [math.sqrt(max(rho, 0.0))]
+    tol = max(atol, rtol * hist[0])
+    it = 0
+    wb, wz = apply_K(zb, zz)
+    ub, uz = apply_Pinv(wb, wz)
+    sb, sz = apply_K(ub, uz)
+    pb, pz, qb, qz, tb, tz = zb.copy(), zz.copy(), wb.copy(), wz.copy(), sb.copy(), sz.copy()
+    us = float(np.sum(ub * sb) + np.sum(uz * sz))
+    while hist[-1] > tol and it < maxit:
+        yb, yz = apply_Pinv(tb, tz)
+        den = float(np.sum(tb * yb) + np.sum(tz * yz))
+        if not (den > 0.0 and us > 0.0):
+            break           # the A-residual vanished in floating point: nothing left to minimise
+        alpha = us / den
+        xb += alpha * pb
+        xz += alpha * pz
+        rb -= alpha * qb
+        rz -= alpha * qz
+        wb -= alpha * tb
+        wz -= alpha * tz
+        zb, zz = apply_Pinv(rb, rz)
+        ub, uz = apply_Pinv(wb, wz)
+        sb, sz = apply_K(ub, uz)
+        us_new = float(np.sum(ub * sb) + np.sum(uz * sz))
+        beta = us_new / us
+        us = us_new
+        pb, pz = zb + beta * pb, zz + beta * pz
+        qb, qz = wb + beta * qb, wz + beta * qz
+        tb, tz = sb + beta * tb, sz + beta * tz
+        rho = float(np.sum(rb * zb) + np.sum(rz * zz))
+        it += 1
+        hist.append(math.sqrt(max(rho, 0.0)))
+    return PCGResult(xb, xz, it, hist, hist[-1] <= tol)
+
+
 # ---------------------------------------------------------------------- IPM --
 
 @dataclasses.dataclass
@@ -184,7 +241,7 @@ class IPMOptions:
     cg_max: int = 500
     cg_rtol: float = 1e-2
     cg_atol: float = 0.0
-    krylov: str = "cg"              # "cg" (pcg) or "cr" (pcr)
+    krylov: str = "cg"              # "cg" (pcg), "cr" (pcr) or "car" (pcar)
     pc_rho: float | None = None     # C = rho I: the scaled-identity variant of P
 
 
@@ -282,7 +339,7 @@ def ipm_solve(signal, observed, lam, opts: IPMOptions | None = None,
         sig2 = st.nu2 / s2
         rb, rz = newton_rhs(st, Hb, xi, lam, opts.sigma, mu)
         eta = min(opts.cg_rtol, 0.1 * rel)
-        solver = pcr if opts.krylov == "cr" else pcg
+        solver = {"cg": pcg, "cr": pcr, "car": pcar}[opts.krylov]
         res = solver(lambda pb, pz: K_apply(pb, pz, sig1, sig2, observed),
                      lambda qb, qz: Pinv_apply(qb, qz, sig1, sig2, opts.pc_rho),
                      rb, rz, atol=opts.cg_atol, rtol=eta, maxit=opts.cg_max)

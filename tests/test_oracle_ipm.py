@@ -327,10 +327,57 @@ def test_pcr_iterates_minimise_preconditioned_residual_over_krylov_space():
         res_prev = res
 
 
+def test_pcar_solves_dense_system_and_is_exact_for_K_equal_P():
+    m = 24
+    K, applyK, s1, s2, rng = _dense_system(m, 6)
+    b = rng.standard_normal(2 * m)
+    pinv = lambda rb, rz: ipm.Pinv_apply(rb, rz, s1, s2)
+    out = ipm.pcar(applyK, pinv, b[:m], b[m:], rtol=1e-12, maxit=300)
+    x = np.linalg.solve(K, b)
+    assert out.converged
+    assert np.abs(np.concatenate([out.xb, out.xz]) - x).max() < 1e-9 * np.abs(x).max()
+    applyP = lambda pb, pz: ipm.P_apply(pb, pz, s1, s2)
+    one = ipm.pcar(applyP, pinv, b[:m], b[m:], rtol=1e-10)
+    assert one.iters == 1
+
+
+def test_pcar_iterates_minimise_preconditioned_A_residual_over_krylov_space():
+    """x_k = argmin over K_k(P^{-1}K, P^{-1}b) of ||K P^{-1}(b - Kx)||_{P^{-1}}
+    (dense weighted least squares on the Krylov basis); that norm decreases
+    monotonically, and so does the preconditioned residual."""
+    m = 20
+    K, applyK, s1, s2, rng = _dense_system(m, 10)
+    b = rng.standard_normal(2 * m)
+    Pinv = np.zeros((2 * m, 2 * m))
+    for j in range(2 * m):
+        e = np.zeros(2 * m)
+        e[j] = 1.0
+        zb, zz = ipm.Pinv_apply(e[:m], e[m:], s1, s2)
+        Pinv[:, j] = np.concatenate([zb, zz])
+    pinv = lambda rb, rz: ipm.Pinv_apply(rb, rz, s1, s2)
+    W = K @ Pinv                     # r -> K P^{-1} r, the A-residual
+    prev_a = prev_r = math.inf
+    for k in (1, 2, 3, 5, 8):
+        out = ipm.pcar(applyK, pinv, b[:m], b[m:], rtol=0.0, maxit=k)
+        xk = np.concatenate([out.xb, out.xz])
+        V = [Pinv @ b]
+        for _ in range(k - 1):
+            V.append(Pinv @ (K @ V[-1]))
+        V = np.linalg.qr(np.array(V).T)[0]       # orthonormal basis of the same space
+        G = W @ K @ V
+        y = np.linalg.solve(G.T @ Pinv @ G, G.T @ Pinv @ (W @ b))
+        assert np.abs(xk - V @ y).max() < 1e-7 * np.abs(V @ y).max()
+        r = b - K @ xk
+        a = float((W @ r) @ Pinv @ (W @ r))
+        res = float(r @ Pinv @ r)
+        assert a <= prev_a * (1 + 1e-12) and res <= prev_r * (1 + 1e-12)
+        prev_a, prev_r = a, res
+
+
 def test_cr_and_scaled_preconditioner_reach_the_lasso_solution():
     """The Krylov method and the preconditioner change only how each Newton
-    system is solved: CR, and the scaled-identity P with rho = m/n, reach the
-    solution of the plain PCG solve."""
+    system is solved: CR, CAr, and the scaled-identity P with rho = m/n,
+    reach the solution of the plain PCG solve."""
     w = wl.grid16(4)
     lam = ipm.lambda_rule(w.signal, w.observed)
     ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-11))
@@ -341,3 +388,11 @@ def test_cr_and_scaled_preconditioner_reach_the_lasso_solution():
         assert res.converged
         err = np.linalg.norm(res.state.beta - ref.state.beta) / np.linalg.norm(ref.state.beta)
         assert err < 1e-8, (opts, err)
+    # CAr minimises ||K z||_{P^{-1}}, which reaches its floating-point floor
+    # near a 1e-9 relative residual on these systems: compared at 1e-9, where
+    # it takes the same interior-point and Krylov steps as CG
+    cg9 = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-9))
+    car9 = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-9, krylov="car"))
+    assert car9.converged and car9.iters == cg9.iters
+    err = np.linalg.norm(car9.state.beta - cg9.state.beta) / np.linalg.norm(cg9.state.beta)
+    assert err < 1e-8, err
