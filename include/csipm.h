@@ -69,10 +69,15 @@ typedef enum { CSIPM_FP64 = 0, CSIPM_FP32 = 1 } csipm_precision;
  * learned diagonal correction C = diag(c) in place of I; or the scaled
  * identity rho I in place of I (the variant the paper compares P with). */
 typedef enum { CSIPM_PC_PLAIN = 0, CSIPM_PC_LEARNED = 1, CSIPM_PC_SCALED = 2 } csipm_pc;
-/* Krylov method of the Newton systems: CG, or conjugate residuals (CR,
- * which the same section lists beside CG): alpha = (z.Kz)/(q.P^{-1}q), one
- * K-apply per iteration, residual minimised in the P^{-1} norm. */
-typedef enum { CSIPM_KRYLOV_CG = 0, CSIPM_KRYLOV_CR = 1 } csipm_krylov;
+/* Krylov method of the Newton systems (section "Krylov methods and
+ * preconditioners" lists CG, CR and CAr for SPD systems): CG; conjugate
+ * residuals (CR): alpha = (z.Kz)/(q.P^{-1}q), one K-apply per iteration,
+ * residual minimised in the P^{-1} norm; conjugate A-residuals (CAr): CR
+ * applied to the A-residual K z, ||K z|| minimised in the P^{-1} norm, one
+ * K-apply per iteration after two at the start.  CAr's residual stops
+ * decreasing near 1e-9 relative on ill-conditioned systems (late FP64
+ * interior-point iterations at tight tolerances). */
+typedef enum { CSIPM_KRYLOV_CG = 0, CSIPM_KRYLOV_CR = 1, CSIPM_KRYLOV_CAR = 2 } csipm_krylov;
 typedef enum {
   CSIPM_BETA = 0, CSIPM_Z = 1, CSIPM_NU1 = 2, CSIPM_NU2 = 3,
   CSIPM_XI = 4,       /* M_perp^T b, fixed at creation                        */

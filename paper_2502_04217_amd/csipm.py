@@ -18,7 +18,7 @@ MLP_PARAMS = 1249
 
 FP64, FP32 = 0, 1
 PC_PLAIN, PC_LEARNED, PC_SCALED = 0, 1, 2
-KRYLOV_CG, KRYLOV_CR = 0, 1
+KRYLOV_CG, KRYLOV_CR, KRYLOV_CAR = 0, 1, 2
 BETA, Z, NU1, NU2, XI, DIAG_H, PC_C = range(7)
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "STALLED", 3: "FELL_BACK", -1: "EINVAL", -2: "ENOMEM",

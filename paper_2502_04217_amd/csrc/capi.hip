@@ -55,6 +55,8 @@ struct csipm_ctx {
   // FP32 Krylov set
   float *sig1f, *sig2f, *frb, *frz, *fzb, *fzz, *fpb, *fpz, *fqb, *fqz, *fxb, *fxz, *fwork;
   float *fwb, *fwz;   // FP32 w = K z of conjugate residuals
+  double *yb64, *yz64; // CAr: y = P^{-1} K v (FP64)
+  float *fyb, *fyz;    // CAr: y (FP32)
   // learned correction
   float *pc_c, *feat, *mlp_params;
   uint32_t* mask;
@@ -155,11 +157,12 @@ size_t layout(Carver& cv, csipm_ctx* c, int n1, int n2, int n3) {
   const size_t ntw = (size_t)n1 + n2 + n3 / 2 + n3;
   double** d64[] = {&c->beta, &c->z, &c->nu1, &c->nu2, &c->xi, &c->hb, &c->sig1, &c->sig2, &c->rhb, &c->rhz,
                     &c->dxb, &c->dxz, &c->diagH, &c->rb, &c->rz, &c->zb, &c->zz, &c->pb, &c->pz, &c->qb,
-                    &c->qz, &c->work};
+                    &c->qz, &c->work, &c->yb64, &c->yz64};
   for (double** p : d64) *p = cv.take<double>(n);
   c->snap = cv.take<double>(4 * n);
   float** f32[] = {&c->sig1f, &c->sig2f, &c->frb, &c->frz, &c->fzb,   &c->fzz,  &c->fpb, &c->fpz,
-                   &c->fqb,   &c->fqz,   &c->fxb, &c->fxz, &c->fwork, &c->pc_c, &c->fwb, &c->fwz};
+                   &c->fqb,   &c->fqz,   &c->fxb, &c->fxz, &c->fwork, &c->pc_c, &c->fwb, &c->fwz,
+                   &c->fyb,   &c->fyz};
   for (float** p : f32) *p = cv.take<float>(n);
   c->feat = cv.take<float>(4 * n);
   c->mlp_params = cv.take<float>(CSIPM_MLP_PARAMS);
@@ -301,7 +304,7 @@ void capture_pair(csipm_ctx* c, const T* pb, const T* pz, const T* qb, const T* 
 
 // ------------------------------------------------------------------- PCG --
 struct PcgSet {
-  void *rb, *rz, *zb, *zz, *pb, *pz, *qb, *qz, *work, *wb, *wz;
+  void *rb, *rz, *zb, *zz, *pb, *pz, *qb, *qz, *work, *wb, *wz, *yb, *yz;
 };
 
 template <typename T>
@@ -309,11 +312,11 @@ PcgSet pcg_set(csipm_ctx* c);
 template <>
 PcgSet pcg_set<double>(csipm_ctx* c) {
   // w of conjugate residuals: the FP64 right-hand side copy is idle in the FP64 form
-  return {c->rb, c->rz, c->zb, c->zz, c->pb, c->pz, c->qb, c->qz, c->work, c->rhb, c->rhz};
+  return {c->rb, c->rz, c->zb, c->zz, c->pb, c->pz, c->qb, c->qz, c->work, c->rhb, c->rhz, c->yb64, c->yz64};
 }
 template <>
 PcgSet pcg_set<float>(csipm_ctx* c) {
-  return {c->frb, c->frz, c->fzb, c->fzz, c->fpb, c->fpz, c->fqb, c->fqz, c->fwork, c->fwb, c->fwz};
+  return {c->frb, c->frz, c->fzb, c->fzz, c->fpb, c->fpz, c->fqb, c->fqz, c->fwork, c->fwb, c->fwz, c->fyb, c->fyz};
 }
 
 struct PcgOut {
@@ -406,11 +409,63 @@ csipm_status pcr(csipm_ctx* c, T* xb, T* xz, const T* s1, const T* s2, const flo
   return CSIPM_OK;
 }
 
+// Preconditioned conjugate A-residuals on K x = h, x0 = 0: the caller has
+// put z = P^{-1}h into the Krylov set (and r = h, which CAr overwrites with
+// u).  Start: w = K z, u = P^{-1} w.  Each iteration: s = K u (partial u.s),
+// beta and alpha's numerator u.s (fin_cr_zw), the direction step
+// (car_dir: p, v = P^{-1}Kp, y = P^{-1}Kv; partial y.Py = t.P^{-1}t),
+// alpha, the update (car_update: x, z, u; partial z.Pz = r.P^{-1}r) and the
+// stopping test on sqrt(r.P^{-1}r) (fin_rz).  Vectors: u in r's place
+// (r = P z is written back at the end), v in q's, s in w's, y in its own.
+template <typename T>
+csipm_status pcar(csipm_ctx* c, T* xb, T* xz, const T* s1, const T* s2, const float* pcc, PcgOut& out) {
+  const long long n = c->g.n;
+  PcgSet v = pcg_set<T>(c);
+  T *ub = (T*)v.rb, *uz = (T*)v.rz, *zb = (T*)v.zb, *zz = (T*)v.zz, *pb = (T*)v.pb, *pz = (T*)v.pz,
+    *vb = (T*)v.qb, *vz = (T*)v.qz, *work = (T*)v.work, *sb = (T*)v.wb, *sz = (T*)v.wz, *yb = (T*)v.yb,
+    *yz = (T*)v.yz;
+  const int nbv = vec_blocks(n);
+  const int* skip = c->flags + F_DONE;
+  // w = K z into s's buffer, then u = P^{-1} w (skipped when the solve is
+  // already done at initialisation: the first update then writes x = 0)
+  (void)op_K<T>(c, zb, zz, s1, s2, sb, sz, work, skip);
+  KT(c, PN(T, "pinv"), pinv_apply<T>(sb, sz, ub, uz, s1, s2, pcc, n, c->partV, nullptr, c->s));
+  int chunk = 2;
+  bool first = true;
+  for (;;) {
+    for (int k = 0; k < chunk; ++k) {
+      const int nbk = op_K<T>(c, ub, uz, s1, s2, sb, sz, work, skip);
+      KT(c, "fin_cr_zw", fin_cr_zw(c->partK, nbk, c->scal, c->flags, first, c->s));
+      KT(c, PN(T, "car_dir"), car_dir<T>(pb, pz, vb, vz, yb, yz, zb, zz, ub, uz, sb, sz, s1, s2, pcc, c->scal,
+                                         c->flags, n, c->partV, first, c->s));
+      KT(c, "fin_alpha", fin_alpha(c->partV, nbv, c->scal, c->flags, c->s));
+      KT(c, PN(T, "car_update"), car_update<T>(xb, xz, pb, pz, zb, zz, vb, vz, ub, uz, yb, yz, s1, s2, pcc,
+                                               c->scal, c->flags, n, c->partV, first, c->s));
+      first = false;
+      KT(c, "fin_rz", fin_rz(c->partV, nbv, c->scal, c->flags, c->s));
+    }
+    csipm_status st = sync_scalars(c, "pcar");
+    if (st != CSIPM_OK) return st;
+    if (c->hflags[F_DONE]) break;
+    chunk = std::min(chunk * 2, 16);
+  }
+  // the residual r = P z back into r's place (u is no longer needed): the
+  // interior-point update recovers H d_beta from it
+  KT(c, PN(T, "p_apply"), p_apply<T>(zb, zz, s1, s2, pcc, ub, uz, n, c->s));
+  out.iters = c->hflags[F_IT];
+  out.breakdown = c->hflags[F_BREAK] != 0;
+  out.res0 = std::sqrt(std::max(c->hscal[S_RZ0], 0.0));
+  out.res = c->hscal[S_RES];
+  out.converged = out.res <= c->hscal[S_TOL];
+  return CSIPM_OK;
+}
+
 // The Newton systems' Krylov method (options.krylov); capture needs CG.
 template <typename T>
 csipm_status krylov(csipm_ctx* c, int method, T* xb, T* xz, const T* s1, const T* s2, const float* pcc, PcgOut& out,
                     bool capture) {
   if (method == CSIPM_KRYLOV_CR) return pcr<T>(c, xb, xz, s1, s2, pcc, out);
+  if (method == CSIPM_KRYLOV_CAR) return pcar<T>(c, xb, xz, s1, s2, pcc, out);
   return pcg<T>(c, xb, xz, s1, s2, pcc, out, capture);
 }
 
@@ -720,7 +775,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   if (!(o.tol > 0) || o.max_iter < 0 || o.cg_max < 1 || !(o.sigma > 0 && o.sigma < 1) || !(o.tau > 0 && o.tau < 1) ||
       (o.precision != CSIPM_FP64 && o.precision != CSIPM_FP32) ||
       (o.pc != CSIPM_PC_PLAIN && o.pc != CSIPM_PC_LEARNED && o.pc != CSIPM_PC_SCALED) ||
-      (o.krylov != CSIPM_KRYLOV_CG && o.krylov != CSIPM_KRYLOV_CR) || !(o.pc_rho >= 0.0) ||
+      (o.krylov != CSIPM_KRYLOV_CG && o.krylov != CSIPM_KRYLOV_CR && o.krylov != CSIPM_KRYLOV_CAR) || !(o.pc_rho >= 0.0) ||
       !(o.pc_max_relevant >= 0.0 && o.pc_max_relevant <= 1.0) ||
       !(o.refine_trust >= 0.0 && o.refine_trust <= 1.0) || !(o.refine_inner_rtol > 0.0) || o.pc_min_cg < 0)
     return fail(c, CSIPM_EINVAL, "invalid options");

@@ -182,6 +182,15 @@ __device__ __forceinline__ void pinv_block(T rb, T rz, T s1, T s2, double c, T& 
   zz = (T)((-L2 * (double)rb + (c + L1) * (double)rz) * inv);
 }
 
+// One 2x2 block of P_c itself (equation "precond1" with C = diag(c)):
+//   [qb; qz] = [[c + L1, L2], [L2, L1]] [zb; zz], in double.
+template <typename T>
+__device__ __forceinline__ void p_block(T zb, T zz, T s1, T s2, double c, double& qb, double& qz) {
+  const double L1 = (double)s1 + (double)s2, L2 = (double)s1 - (double)s2;
+  qb = (c + L1) * (double)zb + L2 * (double)zz;
+  qz = L2 * (double)zb + L1 * (double)zz;
+}
+
 // FFT driver entry points (fft.hip).  All work is queued on `s`.
 // `skip` (nullable device int): when nonzero at launch time the kernel
 // returns at once; lets a batch of Krylov iterations be queued ahead.

@@ -54,6 +54,21 @@ void cr_dir(T* pb, T* pz, T* qb, T* qz, const T* zb, const T* zz, const T* wb, c
             const float* c, const double* scal, const int* flags, long long n, double* partial, bool first,
             hipStream_t s);
 void fin_cr_zw(const double* partial, int nb, double* scal, int* flags, bool first, hipStream_t s);
+// r = P_c z (elementwise 2x2 blocks)
+template <typename T>
+void p_apply(const T* zb, const T* zz, const T* s1, const T* s2, const float* c, T* rb, T* rz, long long n,
+             hipStream_t s);
+// conjugate A-residuals: direction step (p, v = P^{-1}Kp, y = P^{-1}Kv from
+// s = K u; partial y.P y) and update (x, z = P^{-1}r, u = P^{-1}Kz; partial
+// z.P z)
+template <typename T>
+void car_dir(T* pb, T* pz, T* vb, T* vz, T* yb, T* yz, const T* zb, const T* zz, const T* ub, const T* uz,
+             const T* sb, const T* sz, const T* s1, const T* s2, const float* c, const double* scal,
+             const int* flags, long long n, double* partial, bool first, hipStream_t s);
+template <typename T>
+void car_update(T* xb, T* xz, const T* pb, const T* pz, T* zb, T* zz, const T* vb, const T* vz, T* ub, T* uz,
+                const T* yb, const T* yz, const T* s1, const T* s2, const float* c, const double* scal,
+                const int* flags, long long n, double* partial, bool first, hipStream_t s);
 // rz0 from partial quantity 0 (or scal[from_slot] when >= 0); quantity 1
 // (at partial + stride) summed into scal[ref_slot] when ref_slot >= 0
 void fin_cg_start(const double* partial, int nb, int stride, double* scal, int* flags, double eta, double atol,

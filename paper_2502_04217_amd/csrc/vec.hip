@@ -208,6 +208,132 @@ k_cr_dir(T* __restrict__ pb, T* __restrict__ pz, T* __restrict__ qb, T* __restri
   block_reduce_store<1>(&acc, &op, partial, 0);
 }
 
+// Conjugate A-residuals (CAr), in the P_c^{-1} space: z = P^{-1} r,
+// u = P^{-1} K z, v = P^{-1} K p and y = P^{-1} K v are kept, r = P z and
+// the other K images are implied.  Direction step after s = K u:
+// p = z + beta p, v = u + beta v, y = P^{-1}s + beta y (p = z, v = u,
+// y = P^{-1}s first); partial sums of y.(P y), the denominator of alpha.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_car_dir(T* __restrict__ pb, T* __restrict__ pz, T* __restrict__ vb, T* __restrict__ vz, T* __restrict__ yb,
+          T* __restrict__ yz, const T* __restrict__ zb, const T* __restrict__ zz, const T* __restrict__ ub,
+          const T* __restrict__ uz, const T* __restrict__ sb, const T* __restrict__ sz, const T* __restrict__ s1,
+          const T* __restrict__ s2, const float* __restrict__ c, const double* __restrict__ scal,
+          const int* __restrict__ flags, long long n, double* partial, int first) {
+  CSIPM_ALIGN(pb);
+  CSIPM_ALIGN(pz);
+  CSIPM_ALIGN(vb);
+  CSIPM_ALIGN(vz);
+  CSIPM_ALIGN(yb);
+  CSIPM_ALIGN(yz);
+  CSIPM_ALIGN(zb);
+  CSIPM_ALIGN(zz);
+  CSIPM_ALIGN(ub);
+  CSIPM_ALIGN(uz);
+  CSIPM_ALIGN(sb);
+  CSIPM_ALIGN(sz);
+  CSIPM_ALIGN(s1);
+  CSIPM_ALIGN(s2);
+
+  if (flags[F_DONE]) return;
+  const T be = first ? T(0) : (T)scal[S_BETA];
+  double acc = 0.0;
+  CSIPM_PAIRS(n) {
+    const double cc = c ? (double)c[i] : 1.0;
+    T h1, h2;
+    pinv1<T>(sb[i], sz[i], s1[i], s2[i], cc, h1, h2);
+    const T p1 = first ? zb[i] : zb[i] + be * pb[i];
+    const T p2 = first ? zz[i] : zz[i] + be * pz[i];
+    const T v1 = first ? ub[i] : ub[i] + be * vb[i];
+    const T v2 = first ? uz[i] : uz[i] + be * vz[i];
+    const T y1 = first ? h1 : h1 + be * yb[i];
+    const T y2 = first ? h2 : h2 + be * yz[i];
+    pb[i] = p1;
+    pz[i] = p2;
+    vb[i] = v1;
+    vz[i] = v2;
+    yb[i] = y1;
+    yz[i] = y2;
+    double t1, t2;
+    p_block<T>(y1, y2, s1[i], s2[i], cc, t1, t2);
+    acc += (double)y1 * t1 + (double)y2 * t2;
+  }
+  const int op = RED_SUM;
+  block_reduce_store<1>(&acc, &op, partial, 0);
+}
+
+// CAr update: x += alpha p (x = alpha p first), z -= alpha v, u -= alpha y;
+// partial sums of z.(P z) = r.P^{-1}r, the stopping norm.  A first
+// iteration of a solve that finished at initialisation writes x = 0.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_car_update(T* __restrict__ xb, T* __restrict__ xz, const T* __restrict__ pb, const T* __restrict__ pz,
+             T* __restrict__ zb, T* __restrict__ zz, const T* __restrict__ vb, const T* __restrict__ vz,
+             T* __restrict__ ub, T* __restrict__ uz, const T* __restrict__ yb, const T* __restrict__ yz,
+             const T* __restrict__ s1, const T* __restrict__ s2, const float* __restrict__ c,
+             const double* __restrict__ scal, const int* __restrict__ flags, long long n, double* partial,
+             int first) {
+  CSIPM_ALIGN(xb);
+  CSIPM_ALIGN(xz);
+  CSIPM_ALIGN(pb);
+  CSIPM_ALIGN(pz);
+  CSIPM_ALIGN(zb);
+  CSIPM_ALIGN(zz);
+  CSIPM_ALIGN(vb);
+  CSIPM_ALIGN(vz);
+  CSIPM_ALIGN(ub);
+  CSIPM_ALIGN(uz);
+  CSIPM_ALIGN(yb);
+  CSIPM_ALIGN(yz);
+  CSIPM_ALIGN(s1);
+  CSIPM_ALIGN(s2);
+
+  if (flags[F_DONE]) {
+    if (first)
+      CSIPM_PAIRS(n) {
+        xb[i] = T(0);
+        xz[i] = T(0);
+      }
+    return;
+  }
+  const T a = (T)scal[S_ALPHA];
+  double acc = 0.0;
+  CSIPM_PAIRS(n) {
+    xb[i] = first ? a * pb[i] : xb[i] + a * pb[i];
+    xz[i] = first ? a * pz[i] : xz[i] + a * pz[i];
+    const T z1 = zb[i] - a * vb[i], z2 = zz[i] - a * vz[i];
+    zb[i] = z1;
+    zz[i] = z2;
+    ub[i] = ub[i] - a * yb[i];
+    uz[i] = uz[i] - a * yz[i];
+    double r1, r2;
+    p_block<T>(z1, z2, s1[i], s2[i], c ? (double)c[i] : 1.0, r1, r2);
+    acc += (double)z1 * r1 + (double)z2 * r2;
+  }
+  const int op = RED_SUM;
+  block_reduce_store<1>(&acc, &op, partial, 0);
+}
+
+// r = P_c z: the residual of a CAr solve, which keeps only z = P^{-1} r,
+// for the interior-point update that recovers H d_beta from it.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_p_apply(const T* __restrict__ zb, const T* __restrict__ zz, const T* __restrict__ s1, const T* __restrict__ s2,
+          const float* __restrict__ c, T* __restrict__ rb, T* __restrict__ rz, long long n) {
+  CSIPM_ALIGN(zb);
+  CSIPM_ALIGN(zz);
+  CSIPM_ALIGN(s1);
+  CSIPM_ALIGN(s2);
+  CSIPM_ALIGN(rb);
+  CSIPM_ALIGN(rz);
+  CSIPM_PAIRS(n) {
+    double r1, r2;
+    p_block<T>(zb[i], zz[i], s1[i], s2[i], c ? (double)c[i] : 1.0, r1, r2);
+    rb[i] = (T)r1;
+    rz[i] = (T)r2;
+  }
+}
+
 __device__ __forceinline__ double fin_sum(const double* partial, int nb) {
   double a = 0.0;
   for (int i = threadIdx.x; i < nb; i += 256) a += partial[i];
@@ -820,6 +946,25 @@ void cr_dir(T* pb, T* pz, T* qb, T* qz, const T* zb, const T* zz, const T* wb, c
   hipLaunchKernelGGL((k_cr_dir<T>), VB, pb, pz, qb, qz, zb, zz, wb, wz, s1, s2, c, scal, flags, n, partial,
                      first ? 1 : 0);
 }
+template <typename T>
+void car_dir(T* pb, T* pz, T* vb, T* vz, T* yb, T* yz, const T* zb, const T* zz, const T* ub, const T* uz,
+             const T* sb, const T* sz, const T* s1, const T* s2, const float* c, const double* scal,
+             const int* flags, long long n, double* partial, bool first, hipStream_t s) {
+  hipLaunchKernelGGL((k_car_dir<T>), VB, pb, pz, vb, vz, yb, yz, zb, zz, ub, uz, sb, sz, s1, s2, c, scal, flags, n,
+                     partial, first ? 1 : 0);
+}
+template <typename T>
+void car_update(T* xb, T* xz, const T* pb, const T* pz, T* zb, T* zz, const T* vb, const T* vz, T* ub, T* uz,
+                const T* yb, const T* yz, const T* s1, const T* s2, const float* c, const double* scal,
+                const int* flags, long long n, double* partial, bool first, hipStream_t s) {
+  hipLaunchKernelGGL((k_car_update<T>), VB, xb, xz, pb, pz, zb, zz, vb, vz, ub, uz, yb, yz, s1, s2, c, scal, flags,
+                     n, partial, first ? 1 : 0);
+}
+template <typename T>
+void p_apply(const T* zb, const T* zz, const T* s1, const T* s2, const float* c, T* rb, T* rz, long long n,
+             hipStream_t s) {
+  hipLaunchKernelGGL((k_p_apply<T>), VB, zb, zz, s1, s2, c, rb, rz, n);
+}
 void fin_cr_zw(const double* partial, int nb, double* scal, int* flags, bool first, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_cr_zw, dim3(1), dim3(256), 0, s, partial, nb, scal, flags, first ? 1 : 0);
 }
@@ -924,6 +1069,14 @@ void diag_h(const double* bm_ext, double* out_ext, int n1, int n2, int n3, doubl
   template void cg_pupdate<T>(T*, T*, const T*, const T*, const double*, const int*, long long, hipStream_t);  \
   template void cr_dir<T>(T*, T*, T*, T*, const T*, const T*, const T*, const T*, const T*, const T*,         \
                           const float*, const double*, const int*, long long, double*, bool, hipStream_t);   \
+  template void car_dir<T>(T*, T*, T*, T*, T*, T*, const T*, const T*, const T*, const T*, const T*, const T*,  \
+                           const T*, const T*, const float*, const double*, const int*, long long, double*,    \
+                           bool, hipStream_t);                                                                 \
+  template void car_update<T>(T*, T*, const T*, const T*, T*, T*, const T*, const T*, T*, T*, const T*,      \
+                              const T*, const T*, const T*, const float*, const double*, const int*, long long, \
+                              double*, bool, hipStream_t);                                                     \
+  template void p_apply<T>(const T*, const T*, const T*, const T*, const float*, T*, T*, long long,           \
+                           hipStream_t);                                                                       \
   template void pinv_apply<T>(const T*, const T*, T*, T*, const T*, const T*, const float*, long long,        \
                               double*, double*, hipStream_t);                                                  \
   template void fill<T>(T*, T, long long, hipStream_t);

@@ -302,3 +302,33 @@ def test_cr_and_scaled_pc_parity(krylov, scaled, precision):
     if precision == 0:
         for a, b in zip(pr.log()[:6], ref.log[:6]):
             assert a["cg_iters"] == b["cg"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("grid,tol", [("grid16", 1e-9), ("grid64", 1e-7)])
+def test_car_parity(grid, tol, precision):
+    """Conjugate A-residuals against the oracle's pcar, both stopped at the
+    same tolerance: the residual of CAr stops decreasing near 1e-9 relative
+    on late interior-point systems (at 64^3 the oracle's CAr solve breaks
+    down below 1e-7).  FP64 follows the oracle's iterates (same Krylov
+    counts over the first iterations, beta within 1e-7); FP32 with
+    refinement stops at a different iterate of the same path, within 1e-7 at
+    1e-9 and 1e-5 at 1e-7 (near-support coordinates converge like mu)."""
+    from paper_2502_04217_amd import csipm
+    w = wl.grid16(4) if grid == "grid16" else wl.grid64(1)
+    lam = ipm.lambda_rule(w.signal, w.observed)
+    ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=tol, krylov="car"))
+    assert ref.converged
+    pr, info, beta = _gpu_solve(w, lam, tol=tol, precision=precision, krylov=csipm.KRYLOV_CAR)
+    say("  car", grid, precision, info["status_name"], info["ipm_iters"], info["cg_iters_total"],
+        [r["cg_iters"] for r in pr.log()], "oracle", ref.iters, ref.cg_iters)
+    assert info["status"] == 0
+    bar = 1e-7 if (precision == 0 or tol <= 1e-9) else 1e-5
+    err = rel2(beta, ref.state.beta)
+    say("  rel err vs oracle", err)
+    assert err <= bar
+    if precision == 0:
+        ok, amb = _supports_match(beta, ref.state.beta)
+        assert ok
+        for a, b in zip(pr.log()[:6], ref.log[:6]):
+            assert a["cg_iters"] == b["cg"]
