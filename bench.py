@@ -264,6 +264,20 @@ def main():
     fp32_plain_log = pr.log()
     rel_diff = float((beta_chosen - beta64).norm() / beta64.norm())
 
+    # the other Krylov methods and preconditioner of the paper's list, FP64
+    alternatives = {}
+    for name, f in (("cr_fp64", dict(krylov=csipm.KRYLOV_CR)), ("car_fp64", dict(krylov=csipm.KRYLOV_CAR)),
+                    ("scaled_pc_fp64", dict(pc=csipm.PC_SCALED))):
+        alt = dict(plain, **f)
+        pr.solve(**alt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ia = [pr.solve(**alt) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        alternatives[name] = {"seconds": (time.perf_counter() - t0) / args.steps, "ipm_iters": ia[-1]["ipm_iters"],
+                              "krylov_iters_total": ia[-1]["cg_iters_total"], "rel_kkt": ia[-1]["rel_kkt"],
+                              "status": ia[-1]["status_name"]}
+
     # per-kernel event timing of one more solve of each form; the dominant
     # kernel of the chosen form is the roofline kernel
     n = int(np.prod(w.shape))
@@ -345,7 +359,9 @@ def main():
                        "cg_iters_total": infos64[-1]["cg_iters_total"], "rel_kkt": infos64[-1]["rel_kkt"]},
         "fp32_plain_pc": {"seconds": fp32_plain_s, "ipm_iters": infos32[-1]["ipm_iters"],
                           "cg_per_iter": [r["cg_iters"] for r in fp32_plain_log],
-                          "cg_iters_total": infos32[-1]["cg_iters_total"], "rel_kkt": infos32[-1]["rel_kkt"]},
+                          "cg_iters_total": infos32[-1]["cg_iters_total"], "rel_kkt": infos32[-1]["rel_kkt"],
+                          "refine_steps": infos32[-1]["refine_steps_total"]},
+        "alternatives_fp64": alternatives,
         "correction_inference": corr,
         "setup_seconds": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
