@@ -15,7 +15,10 @@
  *    extents with odd factors 12, 20, 24, 28, 40, 48, 56, 70, 96, 192, 384,
  *    560 (the FFT passes have radix-3, -5 and -7 stages); N1 and N2 may
  *    also be 1 or 2, so a 2D problem is the grid 1 x N2 x N3 and a 1D one
- *    1 x 1 x N3; n = N1*N2*N3.  Other extents return CSIPM_EUNSUPPORTED.
+ *    1 x 1 x N3, or odd: 3, 5, 7, 9, 15, 21, 35, 45 (the odd-N case of the
+ *    parametrisation, section "Problem formulation": no Nyquist index on
+ *    that axis); N3 is even.  n = N1*N2*N3.  Other extents return
+ *    CSIPM_EUNSUPPORTED.
  *  - Real-space arrays are row-major [N1][N2][N3] (index j3 fastest).
  *  - beta-space arrays ("external beta layout") are row-major [N1][N2][N3]
  *    indexed by the frequency k: beta[k] = v_k for self-conjugate k

@@ -9,8 +9,10 @@ Paper, section "Problem formulation":
     each conjugate pair (v_k, v_{-k}) by (sqrt2 Re v_k, sqrt2 Im v_k)
     (equation "beta"), B is unitary, and A = C^H B^H is real orthogonal
     (derivation "map").
-The paper writes the 1D case and says 2D/3D mappings are analogous.  Reading
-used here (3D, every N_d even or 1):
+The paper writes the 1D case and says 2D/3D mappings are analogous; it
+notes that for odd n the subspace F has no Nyquist bin.  Reading used here
+(3D, every N_d even, odd or 1; for odd N_d the sets {0, N_d/2} below are
+just {0}):
   * k = (k1,k2,k3), -k = ((N_d - k_d) mod N_d)_d;
   * k is self-conjugate iff k == -k; then beta[k] = v_k (real);
   * otherwise k is canonical iff  k3 in [1, N3/2)

@@ -211,7 +211,7 @@ int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir);
 // whether the FFT passes have kernels for extent N on `axis` (1, 2: pencils
 // of length N; 3: half length N/2): powers of two in [4, 1024], the extents
 // with odd factors that fft_mixed_f64/f32.hip instantiate, and on axes 1
-// and 2 also 1 and 2 (2D and 1D grids)
+// and 2 also 1 and 2 (2D and 1D grids) and the odd extents 3-45
 bool fft_extent_supported(int N, int axis);
 int postmix_blocks(const Grid& g);
 

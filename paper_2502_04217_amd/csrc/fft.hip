@@ -230,6 +230,9 @@ int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir) {
 
 bool fft_extent_supported(int N, int axis) {
   if (axis != 3 && (N == 1 || N == 2)) return true;
+#define CSIPM_IS_ODD(NN) if (axis != 3 && N == NN) return true;
+  CSIPM_ODD_LENGTHS(CSIPM_IS_ODD)
+#undef CSIPM_IS_ODD
   if (N >= 4 && N <= 1024 && (N & (N - 1)) == 0) return true;
 #define CSIPM_IS(NN) if (N == NN) return true;
   CSIPM_MIXED_LENGTHS(CSIPM_IS)

@@ -663,6 +663,10 @@ void launch_axis3_at(int mode, int np, const cx<T>* cs, cx<T>* cd, const uint32_
 // exercise radix 3, 5 and 7, and the non-power-of-two sizes of the paper's
 // synthetic table (96, 192, 384, 560).
 #define CSIPM_MIXED_LENGTHS(X) X(12) X(20) X(24) X(28) X(40) X(48) X(56) X(70) X(96) X(192) X(384) X(560)
+// Odd extents, on axes 1 and 2 only (the odd-N case of the parametrisation:
+// no Nyquist index on that axis); axis 3 keeps an even extent for its
+// half-length transform.
+#define CSIPM_ODD_LENGTHS(X) X(3) X(5) X(7) X(9) X(15) X(21) X(35) X(45)
 
 // Launch a strided or axis-3 pass at a pencil length with odd factors;
 // false when the length has no kernels.  Instantiated for FP64 in
@@ -676,6 +680,7 @@ bool launch_axis12_mixed(int L, dim3 grid, const cx<T>* src, cx<T>* dst, Strided
     return true;
   switch (L) {
     CSIPM_MIXED_LENGTHS(CSIPM_A12)
+    CSIPM_ODD_LENGTHS(CSIPM_A12)
     default:
       return false;
   }

@@ -21,6 +21,8 @@ MIXED_SHAPES = [(_MIXED[i], _MIXED[(i + 1) % 8], _MIXED[(i + 2) % 8]) for i in r
     [s for N in (96, 192, 384, 560) for s in ((N, 4, 8), (8, N, 4), (4, 8, N))] + [(96, 96, 96)]
 # 2D (N1 = 1) and 1D (N1 = N2 = 1) grids, and extent 2 on the strided axes
 LOWDIM_SHAPES = [(1, 64, 64), (1, 1, 256), (2, 96, 40), (1, 560, 12), (64, 1, 32), (2, 2, 8), (1, 1, 4)]
+# odd extents on axes 1 and 2 (no Nyquist index there)
+ODD_SHAPES = [(3, 5, 8), (7, 9, 12), (15, 21, 16), (35, 45, 20), (45, 35, 64), (1, 21, 28), (5, 1, 40), (9, 7, 96)]
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
@@ -33,7 +35,7 @@ def _problem(shape, seed=0):
     return torch, csipm, csipm.Problem(sig, obs), sig, obs
 
 
-@pytest.mark.parametrize("shape", SHAPES + MIXED_SHAPES + LOWDIM_SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + MIXED_SHAPES + LOWDIM_SHAPES + ODD_SHAPES)
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_operator_parity(shape, prec):
     torch, csipm, pr, sig, obs = _problem(shape, 1)
@@ -173,6 +175,9 @@ def test_errors():
     assert e.value.status == -5
     with pytest.raises(csipm.CsipmError) as e:
         csipm.Problem(np.zeros((8, 18, 8)), np.ones((8, 18, 8), np.uint8))
+    assert e.value.status == -5
+    with pytest.raises(csipm.CsipmError) as e:     # odd N3
+        csipm.Problem(np.zeros((8, 8, 15)), np.ones((8, 8, 15), np.uint8))
     assert e.value.status == -5
     pr = csipm.Problem(np.random.default_rng(0).standard_normal((8, 8, 8)), obs)
     with pytest.raises(csipm.CsipmError) as e:

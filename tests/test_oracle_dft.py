@@ -11,7 +11,8 @@ from oracle import dft3, mlp
 from paper_2502_04217_amd import workload as wl
 
 
-@pytest.mark.parametrize("shape", [(4, 6, 8), (2, 4, 4), (1, 1, 8), (8, 2, 2), (6, 10, 14)])
+@pytest.mark.parametrize("shape", [(4, 6, 8), (2, 4, 4), (1, 1, 8), (8, 2, 2), (6, 10, 14), (3, 5, 8), (5, 7, 4),
+                                   (3, 3, 3)])
 def test_A_real_orthogonal(shape):
     A = dft3.dense_A(shape)
     n = A.shape[0]
@@ -21,7 +22,7 @@ def test_A_real_orthogonal(shape):
     assert np.abs(dft3.idft3(dft3.beta_to_spectrum(beta)).imag).max() < 1e-14
 
 
-@pytest.mark.parametrize("shape", [(4, 6, 8), (6, 4, 2), (1, 1, 10)])
+@pytest.mark.parametrize("shape", [(4, 6, 8), (6, 4, 2), (1, 1, 10), (3, 5, 8), (7, 1, 9)])
 def test_exactly_one_of_pair_canonical(shape):
     sc, can, mir = dft3.classes(shape)
     n = int(np.prod(shape))
@@ -74,7 +75,7 @@ def test_synthesised_waves_match_A():
     assert np.abs(dft3.dft3(x) - np.fft.fftn(x, norm="ortho")).max() < 1e-13
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 8), (4, 16, 8), (12, 10, 14)])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (4, 16, 8), (12, 10, 14), (15, 7, 6)])
 def test_parseval_adjoint_projection(shape):
     rng = np.random.default_rng(11)
     beta = rng.standard_normal(shape)
@@ -119,7 +120,7 @@ def test_xi_equals_dense_Mperp_transpose_b():
     assert np.abs(dft3.xi(w.signal, w.observed).ravel() - Mp.T @ b).max() < 1e-13
 
 
-@pytest.mark.parametrize("shape", [(4, 6, 8), (8, 8, 4), (6, 10, 14)])
+@pytest.mark.parametrize("shape", [(4, 6, 8), (8, 8, 4), (6, 10, 14), (3, 5, 8), (9, 7, 6)])
 def test_diag_H_closed_form(shape):
     rng = np.random.default_rng(9)
     obs = (rng.random(shape) > 0.25).astype(np.float64)
