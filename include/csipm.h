@@ -192,6 +192,18 @@ csipm_status csipm_lambda_rule(csipm_ctx* ctx, double frac, double* lambda_out);
  * Returns OK, NOT_CONVERGED, STALLED or FELL_BACK, or an error. */
 csipm_status csipm_solve(csipm_ctx* ctx, const csipm_options* opts, csipm_info* info);
 
+/* Solves `count` independent problems concurrently (the "next" item of
+ * batches of small problems: one 16^3-64^3 problem leaves most of the GPU
+ * idle).  Each context's csipm_solve runs on one of up to `max_threads`
+ * host threads (<= 0: min(count, 8)), on the device and stream the context
+ * was created with; kernels of different contexts overlap when their
+ * streams differ.  The contexts must be distinct.  statuses[i] receives
+ * context i's status and infos[i] its info (infos may be NULL).  Returns
+ * EINVAL for a bad argument (nothing run), else the first negative status
+ * in context order, else OK. */
+csipm_status csipm_solve_batch(csipm_ctx* const* ctxs, int count, const csipm_options* opts, csipm_info* infos,
+                               int* statuses, int max_threads);
+
 /* Copies an iterate or a fixed vector to d_dst (n doubles, external beta
  * layout). */
 csipm_status csipm_get_iterate(csipm_ctx* ctx, int which, double* d_dst);

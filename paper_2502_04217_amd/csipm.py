@@ -137,6 +137,27 @@ def default_options(**kw) -> Options:
     return o
 
 
+def solve_batch(problems, opts: Options | None = None, max_threads: int = 0, **kw) -> list:
+    """csipm_solve_batch: solves distinct problems concurrently (each on its
+    own host thread and on the stream its Problem was created with); returns
+    one info dict per problem."""
+    o = opts if opts is not None else default_options(**kw)
+    k = len(problems)
+    ctxs = (C.c_void_p * k)(*[p._ctx.value for p in problems])
+    infos = (Info * k)()
+    sts = (C.c_int * k)()
+    st = lib().csipm_solve_batch(ctxs, k, C.byref(o), infos, sts, int(max_threads))
+    if st < 0:
+        raise CsipmError(st, "solve_batch")
+    out = []
+    for i in range(k):
+        d = infos[i].as_dict()
+        d["status"] = sts[i]
+        d["status_name"] = STATUS.get(sts[i], "?")
+        out.append(d)
+    return out
+
+
 def workspace_bytes(shape) -> int:
     return int(lib().csipm_workspace_bytes(*[int(s) for s in shape]))
 
@@ -144,7 +165,10 @@ def workspace_bytes(shape) -> int:
 class Problem:
     """One recovery problem on the current HIP device (csipm_create)."""
 
-    def __init__(self, signal, observed, device="cuda"):
+    def __init__(self, signal, observed, device="cuda", stream=None):
+        """`stream` (a torch.cuda.Stream, optional): the stream every call of
+        this problem queues on (default: the current stream); problems on
+        distinct streams overlap in solve_batch."""
         import torch
         self.shape = tuple(int(s) for s in signal.shape)
         self.n = int(np.prod(self.shape))
@@ -159,8 +183,12 @@ class Problem:
         off = (-base) % 256
         self._ws_ptr = C.c_void_p(base + off)
         self._ctx = C.c_void_p()
+        self.stream = stream
+        if stream is not None:
+            torch.cuda.current_stream(self.device).synchronize()   # inputs copied before the context reads them
+        handle = C.c_void_p(stream.cuda_stream) if stream is not None else _stream()
         st = lib().csipm_create(C.byref(self._ctx), *self.shape, _ptr(self.signal), _ptr(self.observed),
-                                self._ws_ptr, nbytes, _stream())
+                                self._ws_ptr, nbytes, handle)
         if st != 0:
             raise CsipmError(st, "csipm_create")
 
@@ -206,6 +234,8 @@ class Problem:
     def get(self, which: int):
         out = self._vec()
         self._check(lib().csipm_get_iterate(self._ctx, which, _ptr(out)), "get_iterate")
+        if self.stream is not None:
+            self.stream.synchronize()
         return out
 
     def residuals(self) -> dict:

@@ -4,6 +4,7 @@
 #include "../../include/csipm.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdint>
@@ -11,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -43,6 +45,7 @@ struct Carver {
 struct csipm_ctx {
   Grid g{};
   hipStream_t s = nullptr;
+  int device = 0;       // the HIP device current at creation
   std::string err;
 
   // FP64 interior-point state and Newton system (internal layout)
@@ -514,6 +517,10 @@ csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double*
   if (!c) return CSIPM_ENOMEM;
   c->g = Grid{n1, n2, n3, n3 / 2, (long long)n1 * n2 * n3};
   c->s = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return CSIPM_EHIP;
+  }
   Carver cv{reinterpret_cast<char*>(d_workspace), 0, workspace_bytes};
   layout(cv, c, n1, n2, n3);
   if (hipHostMalloc((void**)&c->hscal, sizeof(double) * S_COUNT + sizeof(int) * F_COUNT) != hipSuccess) {
@@ -944,6 +951,35 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   inf.status = result;
   if (info) *info = inf;
   return result;
+}
+
+csipm_status csipm_solve_batch(csipm_ctx* const* ctxs, int count, const csipm_options* opts, csipm_info* infos,
+                               int* statuses, int max_threads) {
+  if (count < 0 || (count > 0 && (!ctxs || !statuses))) return CSIPM_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    if (!ctxs[i]) return CSIPM_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return CSIPM_EINVAL;
+  }
+  const int nt = std::max(1, std::min(count, max_threads > 0 ? max_threads : 8));
+  std::atomic<int> next{0};
+  auto worker = [&]() {
+    for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1)) {
+      if (hipSetDevice(ctxs[i]->device) != hipSuccess) {
+        statuses[i] = fail(ctxs[i], CSIPM_EHIP, "solve_batch: hipSetDevice");
+        continue;
+      }
+      statuses[i] = csipm_solve(ctxs[i], opts, infos ? infos + i : nullptr);
+    }
+  };
+  std::vector<std::thread> pool;
+  pool.reserve(nt > 1 ? nt - 1 : 0);
+  for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+  for (int i = 0; i < count; ++i)
+    if (statuses[i] < 0) return static_cast<csipm_status>(statuses[i]);
+  return CSIPM_OK;
 }
 
 csipm_status csipm_get_iterate(csipm_ctx* c, int which, double* d_dst) {

@@ -334,3 +334,28 @@ def test_car_parity(grid, tol, precision):
         assert ok
         for a, b in zip(pr.log()[:6], ref.log[:6]):
             assert a["cg_iters"] == b["cg"]
+
+
+def test_solve_batch_matches_sequential():
+    """csipm_solve_batch on 12 independent problems (16^3 and the paper's
+    32^3 problem), each on its own stream: every solution equals its
+    sequential solve bit for bit, with the same iteration counts."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    probs = []
+    for seed in range(12):
+        w = wl.grid16(seed % 5 + 1) if seed % 2 else wl.paper_synthetic(32, seed)
+        pr = csipm.Problem(w.signal, w.observed, stream=torch.cuda.Stream())
+        pr.lambda_rule(0.05)
+        probs.append(pr)
+    seq = []
+    for pr in probs:
+        info = pr.solve(tol=1e-8)
+        seq.append((info, pr.get(csipm.BETA).cpu()))
+    infos = csipm.solve_batch(probs, tol=1e-8, max_threads=4)
+    for pr, (i0, b0), i1 in zip(probs, seq, infos):
+        assert i1["status"] == 0 and i0["status"] == 0
+        assert i1["ipm_iters"] == i0["ipm_iters"] and i1["cg_iters_total"] == i0["cg_iters_total"]
+        assert torch.equal(pr.get(csipm.BETA).cpu(), b0)
+    with pytest.raises(csipm.CsipmError):
+        csipm.solve_batch([probs[0], probs[0]], tol=1e-8)
