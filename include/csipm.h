@@ -108,7 +108,7 @@ typedef struct {
                                PCG solve (default 1e-5); each inner solve aims at
                                half the remaining reduction, at most 1e-2     */
   double refine_trust; /* FP32: Newton systems whose tolerance min(cg_rtol,
-                          0.1 rel_kkt) is at least this (default 1e-4) take
+                          0.1 rel_kkt) is at least this (default 1e-5) take
                           the FP32 solution (inner tolerance half of it)
                           without an FP64 residual pass; the residual of the
                           iterate then carries FP32-level error until it is

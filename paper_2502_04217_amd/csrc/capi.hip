@@ -490,7 +490,7 @@ void csipm_default_options(csipm_options* o) {
   o->pc = CSIPM_PC_PLAIN;
   o->refine_max = 8;
   o->refine_inner_rtol = 1e-5;
-  o->refine_trust = 1e-4;
+  o->refine_trust = 1e-5;
   o->pc_min_cg = 2;
   o->krylov = CSIPM_KRYLOV_CG;
   o->pc_rho = 0.0;
