@@ -64,7 +64,8 @@ constexpr int bitrev(int x, int bits) {
   return r;
 }
 
-// In-register DFT of size R (power of two, R <= 16) in natural order:
+// In-register DFT of size R (power of two, R <= 16; odd sizes 3, 5 and 7
+// are dft_odd in fft_kernels.h) in natural order:
 // out[k] = sum_j v[j] exp(DIR 2 pi i j k / R).  Iterative radix-2 with the
 // bit-reversal done at compile time; trivial twiddles are special-cased.
 template <int R, int DIR, typename T>

@@ -15,7 +15,7 @@
 //              q = K p and the p.q partial sums
 //   postmix  : m = 0 plane, spectrum -> real parametrisation, K epilogue
 // The pencil FFT kernels (Stockham stages, fft_kernels.h) are instantiated
-// here for power-of-two lengths and in fft_mixed.hip for lengths with odd
+// here for power-of-two lengths and in fft_mixed_f64/f32.hip for lengths with odd
 // factors.  Strided passes map consecutive lanes to consecutive pencils, so
 // every global access is a run of TM contiguous complex numbers.
 #include "fft_kernels.h"

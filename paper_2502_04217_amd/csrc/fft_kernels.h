@@ -1,7 +1,8 @@
 // Pencil-FFT kernel templates shared by the FFT drivers: fft.hip
-// instantiates them for power-of-two pencil lengths, fft_mixed.hip for
-// lengths with odd factors 3, 5 and 7 (the non-power-of-two grids of the
-// paper's synthetic size table, and small grids that exercise each radix).
+// instantiates them for power-of-two pencil lengths, fft_mixed_f64.hip and
+// fft_mixed_f32.hip for lengths with odd factors 3, 5 and 7 (the
+// non-power-of-two grids of the paper's synthetic size table, small grids
+// that exercise each radix, and odd extents on axes 1 and 2).
 //
 // Each pencil FFT is a Stockham sequence of radix-r stages: the first stage
 // reads its inputs straight from global memory into registers, intermediate
