@@ -16,8 +16,10 @@ the learned correction, in FP64 and FP32+refinement, comparing PCG
 iterations, wall time and the true final KKT residual.
 
     python -m paper_2502_04217_amd.learn --train 200 --eval 50
+    python -m paper_2502_04217_amd.learn --eval-only --eval 50
 
-writes paper_2502_04217_amd/pc_params.json and gpurun_out/learn_eval.json.
+writes paper_2502_04217_amd/pc_params.json (not with --eval-only) and
+gpurun_out/learn_eval.json.
 """
 from __future__ import annotations
 
@@ -156,8 +158,20 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--out", default=os.path.join("gpurun_out", "learn_eval.json"))
+    ap.add_argument("--eval-only", action="store_true", help="evaluate the stored parameters, no training")
     args = ap.parse_args()
     log = lambda *a: print(*a, flush=True)
+    if args.eval_only:
+        import torch
+        with open(PARAMS_FILE) as f:
+            params = torch.tensor(json.load(f)["params"], dtype=torch.float32, device="cuda")
+        rows = evaluate(params, list(EVAL_SEEDS)[:args.eval], log=log)
+        summ = summarize(rows)
+        log(json.dumps(summ))
+        os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
+        with open(args.out, "w") as f:
+            json.dump({"summary": summ, "rows": rows}, f)
+        return 0
     t0 = time.time()
     feats, recs = collect(list(TRAIN_SEEDS)[:args.train], log=log)
     log(f"[collect] {len(feats)} record groups in {time.time() - t0:.0f} s")
