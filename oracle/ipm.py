@@ -27,6 +27,11 @@ implementation"):
     d s2 = dz - dbeta;
   * one common step length alpha = min(1, tau * max step keeping s, nu > 0),
     tau = 0.99;
+  * as an option (mehrotra), Mehrotra's predictor-corrector: an affine
+    direction (sigma = 0), its step to the boundary alpha_a (at most 1) and
+    mu_a = (s + alpha_a ds).(nu + alpha_a dnu)/(2n); sigma = (mu_a/mu)^3,
+    at least 0.1 tol (1 + ||xi||_inf) / mu; then the corrector, a second
+    solve with the same K whose complementarity rows carry - ds_a dnu_a;
   * stop when rel_kkt = max(||F_beta||_inf, ||F_z||_inf, max_i s_i nu_i)
     / (1 + ||xi||_inf) <= tol, where F_beta = H beta - xi - nu1 + nu2 and
     F_z = lambda e - nu1 - nu2 are the first two rows of "kkt";
@@ -242,6 +247,7 @@ class IPMOptions:
     cg_rtol: float = 1e-2
     cg_atol: float = 0.0
     krylov: str = "cg"              # "cg" (pcg), "cr" (pcr) or "car" (pcar)
+    mehrotra: bool = False          # predictor-corrector steps (see ipm_solve)
     pc_rho: float | None = None     # C = rho I: the scaled-identity variant of P
 
 
@@ -290,23 +296,37 @@ def initial_state(xi, lam):
                     np.full_like(xi, lam / 2.0), np.full_like(xi, lam / 2.0))
 
 
-def newton_rhs(st: IPMState, Hb, xi, lam, sigma, mu):
+def newton_rhs(st: IPMState, Hb, xi, lam, sigma, mu, corr=None):
+    """Condensed right-hand side.  `corr` = (c1, c2): the complementarity rows
+    of "kktmu" read s_j d nu_j + nu_j d s_j = sigma mu - s_j nu_j - c_j (the
+    corrector of a predictor-corrector step, c_j = d s_j d nu_j of the
+    predictor), i.e. sigma mu / s_j becomes (sigma mu - c_j) / s_j."""
     s1 = st.z + st.beta
     s2 = st.z - st.beta
     t = sigma * mu
-    rb = -(Hb - xi) + t * (1.0 / s1 - 1.0 / s2)
-    rz = -lam + t * (1.0 / s1 + 1.0 / s2)
+    if corr is None:
+        rb = -(Hb - xi) + t * (1.0 / s1 - 1.0 / s2)
+        rz = -lam + t * (1.0 / s1 + 1.0 / s2)
+    else:
+        u1 = (t - corr[0]) / s1
+        u2 = (t - corr[1]) / s2
+        rb = -(Hb - xi) + u1 - u2
+        rz = -lam + u1 + u2
     return rb, rz
 
 
-def recover_dnu(st: IPMState, db, dz, sig1, sig2, sigma, mu):
+def recover_dnu(st: IPMState, db, dz, sig1, sig2, sigma, mu, corr=None):
     s1 = st.z + st.beta
     s2 = st.z - st.beta
     t = sigma * mu
     ds1 = db + dz
     ds2 = dz - db
-    dnu1 = t / s1 - st.nu1 - sig1 * ds1
-    dnu2 = t / s2 - st.nu2 - sig2 * ds2
+    if corr is None:
+        dnu1 = t / s1 - st.nu1 - sig1 * ds1
+        dnu2 = t / s2 - st.nu2 - sig2 * ds2
+    else:
+        dnu1 = (t - corr[0]) / s1 - st.nu1 - sig1 * ds1
+        dnu2 = (t - corr[1]) / s2 - st.nu2 - sig2 * ds2
     return ds1, ds2, dnu1, dnu2
 
 
@@ -337,21 +357,38 @@ def ipm_solve(signal, observed, lam, opts: IPMOptions | None = None,
             break
         sig1 = st.nu1 / s1
         sig2 = st.nu2 / s2
-        rb, rz = newton_rhs(st, Hb, xi, lam, opts.sigma, mu)
         eta = min(opts.cg_rtol, 0.1 * rel)
         solver = {"cg": pcg, "cr": pcr, "car": pcar}[opts.krylov]
-        res = solver(lambda pb, pz: K_apply(pb, pz, sig1, sig2, observed),
-                     lambda qb, qz: Pinv_apply(qb, qz, sig1, sig2, opts.pc_rho),
-                     rb, rz, atol=opts.cg_atol, rtol=eta, maxit=opts.cg_max)
+
+        def newton(rb, rz):
+            return solver(lambda pb, pz: K_apply(pb, pz, sig1, sig2, observed),
+                          lambda qb, qz: Pinv_apply(qb, qz, sig1, sig2, opts.pc_rho),
+                          rb, rz, atol=opts.cg_atol, rtol=eta, maxit=opts.cg_max)
+        sigma, corr, iters = opts.sigma, None, 0
+        if opts.mehrotra:
+            # predictor: the affine-scaling direction (sigma = 0), its full
+            # step to the boundary (capped at 1) and the duality measure there
+            ra = newton(*newton_rhs(st, Hb, xi, lam, 0.0, mu))
+            iters += ra.iters
+            da1, da2, dna1, dna2 = recover_dnu(st, ra.xb, ra.xz, sig1, sig2, 0.0, mu)
+            aa = min(1.0, max_step(s1, da1), max_step(s2, da2), max_step(st.nu1, dna1), max_step(st.nu2, dna2))
+            mu_aff = float(np.sum((s1 + aa * da1) * (st.nu1 + aa * dna1)) +
+                           np.sum((s2 + aa * da2) * (st.nu2 + aa * dna2))) / (2 * xi.size)
+            # centring sigma = (mu_aff / mu)^3, never aiming below the
+            # complementarity the tolerance needs (0.1 tol (1 + |xi|_inf))
+            sigma = min(1.0, max((mu_aff / mu) ** 3, 0.1 * opts.tol * (1.0 + xinorm) / mu))
+            corr = (da1 * dna1, da2 * dna2)
+        res = newton(*newton_rhs(st, Hb, xi, lam, sigma, mu, corr))
+        iters += res.iters
         db, dz = res.xb, res.xz
-        ds1, ds2, dnu1, dnu2 = recover_dnu(st, db, dz, sig1, sig2, opts.sigma, mu)
+        ds1, ds2, dnu1, dnu2 = recover_dnu(st, db, dz, sig1, sig2, sigma, mu, corr)
         amax = min(max_step(s1, ds1), max_step(s2, ds2),
                    max_step(st.nu1, dnu1), max_step(st.nu2, dnu2))
         alpha = min(1.0, opts.tau * amax)
         st = IPMState(st.beta + alpha * db, st.z + alpha * dz,
                       st.nu1 + alpha * dnu1, st.nu2 + alpha * dnu2)
-        cg_counts.append(res.iters)
-        log.append(dict(it=it, mu=mu, rel_kkt=rel, alpha=alpha, cg=res.iters))
+        cg_counts.append(iters)
+        log.append(dict(it=it, mu=mu, rel_kkt=rel, alpha=alpha, cg=iters, sigma=sigma))
         if callback is not None:
             callback(it, st, res)
     return IPMResult(st, len(cg_counts), cg_counts, rel, mu, rel <= opts.tol, log)

@@ -118,6 +118,72 @@ def test_condensed_step_equals_dense_newton_on_kktmu():
     assert np.abs(res.xz.ravel() - d[n:]).max() < 1e-9
 
 
+def test_predictor_corrector_steps_equal_dense_newton():
+    """Mehrotra's two directions against dense Newton solves of "kktmu": the
+    affine one with target 0, the corrector with target sigma mu and the
+    complementarity rows shifted by d s_a * d nu_a of the affine step."""
+    shape = (2, 4, 4)
+    n = 32
+    w = wl.make_workload(shape, n_freq=4, amplitude="normal", snr_db=10.0,
+                         half_width=0, period=2, seed=5)
+    obs = w.observed.astype(np.float64)
+    xi = dft3.xi(w.signal, obs)
+    lam = 0.1 * float(np.abs(xi).max())
+    rng = np.random.default_rng(3)
+    beta = 0.3 * rng.standard_normal(shape)
+    z = np.abs(beta) + rng.uniform(0.1, 1.0, shape)
+    nu1 = rng.uniform(0.1, 1.0, shape) * lam
+    nu2 = rng.uniform(0.1, 1.0, shape) * lam
+    st = ipm.IPMState(beta, z, nu1, nu2)
+    s1, s2 = z + beta, z - beta
+    mu = float((s1 * nu1).sum() + (s2 * nu2).sum()) / (2 * n)
+    wvec = np.concatenate([a.ravel() for a in (beta, z, s1, s2, nu1, nu2, nu1, nu2)])
+
+    def jac(target):
+        J = np.zeros((8 * n, 8 * n))
+        for i in range(8 * n):
+            e = np.zeros(8 * n); e[i] = 1.0
+            J[:, i] = (ipm.kktmu_residual(wvec + e, xi, lam, obs, target)
+                       - ipm.kktmu_residual(wvec - e, xi, lam, obs, target)) / 2.0
+        return J
+    A = dft3.dense_A(shape)
+    Hd = A.T @ np.diag(obs.ravel()) @ A
+    sig1, sig2 = nu1 / s1, nu2 / s2
+    L1, L2 = np.diag((sig1 + sig2).ravel()), np.diag((sig1 - sig2).ravel())
+    Kd = np.block([[Hd + L1, L2], [L2, L1]])
+    Hb = dft3.apply_H(beta, obs)
+    # affine direction
+    Fa = ipm.kktmu_residual(wvec, xi, lam, obs, 0.0)
+    dwa = np.linalg.solve(jac(0.0), -Fa)
+    da = np.linalg.solve(Kd, np.concatenate([a.ravel() for a in ipm.newton_rhs(st, Hb, xi, lam, 0.0, mu)]))
+    assert np.abs(da - dwa[:2 * n]).max() < 1e-10
+    ds1a, ds2a, dn1a, dn2a = ipm.recover_dnu(st, da[:n].reshape(shape), da[n:].reshape(shape), sig1, sig2, 0.0, mu)
+    # corrector with sigma = 0.2
+    sigma = 0.2
+    corr = (ds1a * dn1a, ds2a * dn2a)
+    F = ipm.kktmu_residual(wvec, xi, lam, obs, sigma * mu)
+    F[6 * n:7 * n] += corr[0].ravel()
+    F[7 * n:] += corr[1].ravel()
+    dw = np.linalg.solve(jac(sigma * mu), -F)
+    d = np.linalg.solve(Kd, np.concatenate([a.ravel() for a in ipm.newton_rhs(st, Hb, xi, lam, sigma, mu, corr)]))
+    assert np.abs(d[:n] - dw[:n]).max() < 1e-10
+    assert np.abs(d[n:] - dw[n:2 * n]).max() < 1e-10
+    _, _, dnu1, dnu2 = ipm.recover_dnu(st, d[:n].reshape(shape), d[n:].reshape(shape), sig1, sig2, sigma, mu, corr)
+    assert np.abs(dnu1.ravel() - dw[6 * n:7 * n]).max() < 1e-9
+    assert np.abs(dnu2.ravel() - dw[7 * n:]).max() < 1e-9
+
+
+def test_predictor_corrector_reaches_the_lasso_solution_in_fewer_iterations():
+    for seed in (1, 4):
+        w = wl.grid16(seed)
+        lam = ipm.lambda_rule(w.signal, w.observed)
+        ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-11))
+        mpc = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-11, mehrotra=True))
+        assert mpc.converged and mpc.iters < ref.iters
+        err = np.linalg.norm(mpc.state.beta - ref.state.beta) / np.linalg.norm(ref.state.beta)
+        assert err < 1e-8, err
+
+
 def test_no_missing_closed_form_and_one_cg_step():
     """Nothing missing: H = I, K = P, so PCG converges in one iteration and
     the LASSO solution is soft(A^T b, lambda)."""
