@@ -264,10 +264,11 @@ def main():
     fp32_plain_log = pr.log()
     rel_diff = float((beta_chosen - beta64).norm() / beta64.norm())
 
-    # the other Krylov methods and preconditioner of the paper's list, FP64
+    # the other Krylov methods and preconditioner of the paper's list, and
+    # predictor-corrector steps, FP64
     alternatives = {}
     for name, f in (("cr_fp64", dict(krylov=csipm.KRYLOV_CR)), ("car_fp64", dict(krylov=csipm.KRYLOV_CAR)),
-                    ("scaled_pc_fp64", dict(pc=csipm.PC_SCALED))):
+                    ("scaled_pc_fp64", dict(pc=csipm.PC_SCALED)), ("mehrotra_fp64", dict(mehrotra=1))):
         alt = dict(plain, **f)
         pr.solve(**alt)
         torch.cuda.synchronize()

@@ -136,6 +136,16 @@ typedef struct {
                           iterates have the relevant set near the support,
                           where the network runs on few chunks.  1 = no
                           limit.                                              */
+  int mehrotra;        /* 1: Mehrotra predictor-corrector steps (default 0):
+                          an affine direction (target 0) and its step to the
+                          boundary give mu_a and sigma = (mu_a/mu)^3 (at
+                          least 0.1 tol (1 + |xi|_inf) / mu); a second solve
+                          with the same K, whose complementarity rows carry
+                          the affine ds * dnu, gives the step.  Fewer
+                          interior-point iterations, two Krylov solves each.
+                          Not from the paper, which leaves the barrier update
+                          to its solver; Mehrotra's scheme on the condensed K
+                          (eq. condensedkkt) with the rows of eq. kktmu. */
 } csipm_options;
 
 typedef struct {

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cfloat>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -59,6 +60,7 @@ struct csipm_ctx {
   float *sig1f, *sig2f, *frb, *frz, *fzb, *fzz, *fpb, *fpz, *fqb, *fqz, *fxb, *fxz, *fwork;
   float *fwb, *fwz;   // FP32 w = K z of conjugate residuals
   double *yb64, *yz64; // CAr: y = P^{-1} K v (FP64)
+  double *dab, *daz;   // predictor-corrector: the affine direction
   float *fyb, *fyz;    // CAr: y (FP32)
   // learned correction
   float *pc_c, *feat, *mlp_params;
@@ -160,7 +162,7 @@ size_t layout(Carver& cv, csipm_ctx* c, int n1, int n2, int n3) {
   const size_t ntw = (size_t)n1 + n2 + n3 / 2 + n3;
   double** d64[] = {&c->beta, &c->z, &c->nu1, &c->nu2, &c->xi, &c->hb, &c->sig1, &c->sig2, &c->rhb, &c->rhz,
                     &c->dxb, &c->dxz, &c->diagH, &c->rb, &c->rz, &c->zb, &c->zz, &c->pb, &c->pz, &c->qb,
-                    &c->qz, &c->work, &c->yb64, &c->yz64};
+                    &c->qz, &c->work, &c->yb64, &c->yz64, &c->dab, &c->daz};
   for (double** p : d64) *p = cv.take<double>(n);
   c->snap = cv.take<double>(4 * n);
   float** f32[] = {&c->sig1f, &c->sig2f, &c->frb, &c->frz, &c->fzb,   &c->fzz,  &c->fpb, &c->fpz,
@@ -495,6 +497,7 @@ void csipm_default_options(csipm_options* o) {
   o->krylov = CSIPM_KRYLOV_CG;
   o->pc_rho = 0.0;
   o->pc_max_relevant = 0.5;
+  o->mehrotra = 0;
 }
 
 size_t csipm_workspace_bytes(int n1, int n2, int n3) {
@@ -623,7 +626,8 @@ enum HdSource {
 };
 
 csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, double eta, const float* pcc,
-                          int& cg_iters, int& refine_steps, bool& converged, bool capture, HdSource& src) {
+                          int& cg_iters, int& refine_steps, bool& converged, bool capture, HdSource& src,
+                          const double* dab = nullptr, const double* daz = nullptr) {
   const long long n = c->g.n;
   const int nbv = vec_blocks(n);
   cg_iters = 0;
@@ -634,7 +638,7 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
     KT(c, "newton_init.f64",
        newton_init<double>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, smu, c->sig1, c->sig2, nullptr,
                            nullptr, nullptr, nullptr, pcc, c->rb, c->rz, c->zb, c->zz, c->pb, c->pz, n, c->partV,
-                           c->s));
+                           c->s, dab, daz));
     KT(c, "fin_cg_start",
        fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, eta, o.cg_atol, o.cg_max, -1, -1, c->s));
     PcgOut po;
@@ -658,7 +662,7 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
                         trusted && !capture ? nullptr : c->sig1, trusted && !capture ? nullptr : c->sig2,
                         trusted ? nullptr : c->rhb, trusted ? nullptr : c->rhz,
                         c->sig1f, c->sig2f, pcc, c->frb,
-                        c->frz, c->fzb, c->fzz, c->fpb, c->fpz, n, c->partV, c->s));
+                        c->frz, c->fzb, c->fzz, c->fpb, c->fpz, n, c->partV, c->s, dab, daz));
   // inner tolerance: half the remaining reduction, at most 1e-2, at least
   // refine_inner_rtol (what FP32 PCG can still reach)
   double inner = std::max(o.refine_inner_rtol, std::min(1e-2, 0.5 * eta));
@@ -727,6 +731,13 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
   return CSIPM_OK;
 }
 
+// two FP64 n-arrays copied on the context's stream
+void copy_pair(double* db, double* dz, const double* sb, const double* sz, long long n, hipStream_t s) {
+  const size_t b = sizeof(double) * (size_t)n;
+  (void)hipMemcpyAsync(db, sb, b, hipMemcpyDeviceToDevice, s);
+  (void)hipMemcpyAsync(dz, sz, b, hipMemcpyDeviceToDevice, s);
+}
+
 // (beta, z, nu1, nu2) <-> snap
 void save_state(csipm_ctx* c) {
   const size_t b = sizeof(double) * (size_t)c->g.n;
@@ -742,12 +753,13 @@ void restore_state(csipm_ctx* c) {
 struct Resid {
   double fb, fz, cmax, csum, bmax, pmin, nonfinite;
   double relevant;   // coefficients where the learned correction can matter (when reduced)
+  double dscale;     // after a carried update from rres: max (S1 + S2)(|d_beta| + |d_z|)
 };
 
 // Residual parts last reduced into scal[S_RESID..] (after a sync).
 Resid read_resid(const csipm_ctx* c) {
   const double* v = c->hscal + S_RESID;
-  return Resid{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[8]};
+  return Resid{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[8], v[9]};
 }
 
 // Residual parts with H beta recomputed by a full H-apply (and the sum of
@@ -767,6 +779,12 @@ csipm_status residuals(csipm_ctx* c, Resid& r, bool logsum) {
 // kExactEvery iterations, and before the first FP32 Newton system that is
 // refined after unrefined ones, so carried error never accumulates far.
 constexpr int kExactEvery = 16;
+// H beta recovered from an FP64 Krylov residual (h - r minus the Sigma terms
+// of d) carries rounding of order eps (S1 + S2)(|d_beta| + |d_z|), which
+// grows as the slacks close; H beta is also recomputed once the accumulated
+// bound exceeds this fraction of the KKT residual, so that the Newton
+// right-hand side stays accurate far inside the Krylov tolerance
+constexpr double kCarryFrac = 0.01;
 // the solve stops (CSIPM_STALLED) once rel_kkt exceeds this multiple of the
 // best value it reached
 constexpr double kStallFactor = 10.0;
@@ -783,7 +801,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       (o.precision != CSIPM_FP64 && o.precision != CSIPM_FP32) ||
       (o.pc != CSIPM_PC_PLAIN && o.pc != CSIPM_PC_LEARNED && o.pc != CSIPM_PC_SCALED) ||
       (o.krylov != CSIPM_KRYLOV_CG && o.krylov != CSIPM_KRYLOV_CR && o.krylov != CSIPM_KRYLOV_CAR) || !(o.pc_rho >= 0.0) ||
-      !(o.pc_max_relevant >= 0.0 && o.pc_max_relevant <= 1.0) ||
+      !(o.pc_max_relevant >= 0.0 && o.pc_max_relevant <= 1.0) || (o.mehrotra != 0 && o.mehrotra != 1) ||
       !(o.refine_trust >= 0.0 && o.refine_trust <= 1.0) || !(o.refine_inner_rtol > 0.0) || o.pc_min_cg < 0)
     return fail(c, CSIPM_EINVAL, "invalid options");
   if (o.pc == CSIPM_PC_LEARNED && !c->have_params) return fail(c, CSIPM_ESTATE, "learned preconditioner has no parameters");
@@ -812,6 +830,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   bool exact = true;
   bool approx = false;   // carried H beta holds FP32-level error (an unrefined FP32 step)
   int carried = 0;
+  double carry_err = 0.0;   // bound on the error of the carried H beta (max norm)
   double best_rel = INFINITY;
   bool have_snap = false;
   double snap_rel = INFINITY;
@@ -825,12 +844,14 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     double rel = rel_of(r);
     const bool leaving_trust = approx && !(std::min(o.cg_rtol, 0.1 * rel) >= o.refine_trust);
     if (!exact && (rel <= o.tol || it >= o.max_iter || carried >= kExactEvery || leaving_trust || have_snap ||
-                   rel > kStallFactor * best_rel || !std::isfinite(rel))) {
+                   carry_err > kCarryFrac * rel * (1.0 + c->xi_inf) || rel > kStallFactor * best_rel ||
+                   !std::isfinite(rel))) {
       st = residuals(c, r, learned);
       if (st != CSIPM_OK) return st;
       exact = true;
       approx = false;
       carried = 0;
+      carry_err = 0.0;
       rel = rel_of(r);
     }
     // a step along an inexact direction (the Newton solve stopped at its
@@ -879,7 +900,6 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       result = CSIPM_NOT_CONVERGED;
       break;
     }
-    const double smu = o.sigma * mu;
     const double eta = std::min(o.cg_rtol, 0.1 * rel);
     int cgi = 0, ref = 0;
     bool conv = false, fell = false;
@@ -896,30 +916,76 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     if (use_learned) {
       st = learned_correction(c, true);
       if (st != CSIPM_OK) return st;
-      csipm_options ol = o;
-      const int budget = prev_cg > 0 ? std::min(o.cg_max, std::max(8, (prev_cg * 3) / 2)) : o.cg_max;
-      ol.cg_max = budget;
-      st = newton_solve(c, ol, smu, eta, c->pc_c, cgi, ref, conv, false, src);
-      if (st != CSIPM_OK) return st;
-      if (!conv) {
-        int cgi2 = 0, ref2 = 0;
-        st = newton_solve(c, o, smu, eta, nullptr, cgi2, ref2, conv, false, src);
-        if (st != CSIPM_OK) return st;
-        cgi += cgi2;
-        ref += ref2;
-        fell = true;
-        ++inf.fallbacks;
-      }
-    } else {
-      st = newton_solve(c, o, smu, eta, pc_fixed, cgi, ref, conv, capture, src);
-      if (st != CSIPM_OK) return st;
-      if (capture) {
-        mlp_scale_weights(c->cap_rec + (size_t)c->cap_count * c->cap_per_iter * MLP_REC, c->cap_per_iter,
-                          (float)cgi, c->s);
-        ++c->cap_count;
-        c->cap_cg.push_back(cgi);
-      }
     }
+    // one Newton system at target tmu (with the corrector terms of the affine
+    // direction when dab is set): the learned correction within a budget and
+    // the paper's P as its fallback, or the plain / scaled P
+    auto solve_system = [&](double tmu, const double* dab, const double* daz, bool cap) -> csipm_status {
+      int a = 0, b = 0;
+      csipm_status e;
+      if (use_learned) {
+        csipm_options ol = o;
+        const int budget = prev_cg > 0 ? std::min(o.cg_max, std::max(8, (prev_cg * 3) / 2)) : o.cg_max;
+        ol.cg_max = budget;
+        e = newton_solve(c, ol, tmu, eta, c->pc_c, a, b, conv, false, src, dab, daz);
+        if (e != CSIPM_OK) return e;
+        cgi += a;
+        ref += b;
+        if (!conv) {
+          e = newton_solve(c, o, tmu, eta, nullptr, a, b, conv, false, src, dab, daz);
+          if (e != CSIPM_OK) return e;
+          cgi += a;
+          ref += b;
+          fell = true;
+          ++inf.fallbacks;
+        }
+      } else {
+        e = newton_solve(c, o, tmu, eta, pc_fixed, a, b, conv, cap, src, dab, daz);
+        if (e != CSIPM_OK) return e;
+        cgi += a;
+        ref += b;
+      }
+      return CSIPM_OK;
+    };
+    double smu = o.sigma * mu;
+    const double* dab = nullptr;
+    const double* daz = nullptr;
+    bool pred_conv = true;
+    if (o.mehrotra) {
+      // predictor: the affine direction (target 0), its step to the
+      // boundary (at most 1) and the duality measure there,
+      //   mu_a = ((1 - alpha) s.nu + alpha^2 ds.dnu) / 2n;
+      // centring sigma = (mu_a / mu)^3, never aiming below the
+      // complementarity the tolerance needs
+      st = solve_system(0.0, nullptr, nullptr, false);
+      if (st != CSIPM_OK) return st;
+      pred_conv = conv;
+      if (src == HD_RRES32)
+        KT(c, "set_f2d", set_f2d(c->dab, c->daz, c->fxb, c->fxz, n, c->s));
+      else
+        KT(c, "copy_dir", copy_pair(c->dab, c->daz, c->dxb, c->dxz, n, c->s));
+      KT(c, "ipm_ratio_aff+fin", ipm_step(c->beta, c->z, c->nu1, c->nu2, c->dab, c->daz, nullptr, nullptr, 0.0, 1.0,
+                                          n, c->partV, c->scal, c->s, nullptr, nullptr, c->scal + S_DSDN));
+      st = sync_scalars(c, "predictor");
+      if (st != CSIPM_OK) return st;
+      const double aa = std::min(1.0, c->hscal[S_AMAX]);
+      const double nn = 2.0 * (double)n;
+      const double mu_aff = std::max(0.0, ((1.0 - aa) * nn * mu + aa * aa * c->hscal[S_DSDN]) / nn);
+      double sigma = std::pow(mu_aff / mu, 3.0);
+      sigma = std::min(1.0, std::max(sigma, 0.1 * o.tol * (1.0 + c->xi_inf) / mu));
+      smu = sigma * mu;
+      dab = c->dab;
+      daz = c->daz;
+    }
+    st = solve_system(smu, dab, daz, capture && !o.mehrotra);
+    if (st != CSIPM_OK) return st;
+    if (capture && !o.mehrotra && !use_learned) {
+      mlp_scale_weights(c->cap_rec + (size_t)c->cap_count * c->cap_per_iter * MLP_REC, c->cap_per_iter,
+                        (float)cgi, c->s);
+      ++c->cap_count;
+      c->cap_cg.push_back(cgi);
+    }
+    conv = conv && pred_conv;
     if (!conv) {
       save_state(c);
       have_snap = true;
@@ -933,16 +999,18 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     inf.cg_iters_max = std::max(inf.cg_iters_max, cgi);
     inf.refine_steps_total += ref;
     KT(c, d32b ? "ipm_ratio_d32+fin" : "ipm_ratio+fin",
-       ipm_step(c->beta, c->z, c->nu1, c->nu2, c->dxb, c->dxz, d32b, d32z, smu, o.tau, n, c->partV, c->scal, c->s));
+       ipm_step(c->beta, c->z, c->nu1, c->nu2, c->dxb, c->dxz, d32b, d32z, smu, o.tau, n, c->partV, c->scal, c->s,
+                dab, daz));
     KT(c, d32b ? "ipm_advance_d32+fin" : "ipm_advance+fin",
        ipm_advance(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->dxb, c->dxz, d32b, d32z,
                    src == HD_DIRECT ? c->rb : nullptr, c->rb, src == HD_RRES32 ? c->frb : nullptr, lam, smu, c->scal, n,
-                   c->partV, learned, c->s));
+                   c->partV, learned, c->s, dab, daz));
     st = sync_scalars(c, "advance");
     if (st != CSIPM_OK) return st;
     r = read_resid(c);
     exact = false;
     approx = approx || src == HD_RRES32;
+    if (src == HD_RRES64) carry_err += 2.0 * DBL_EPSILON * c->hscal[S_ALPHA_IPM] * r.dscale;
     ++carried;
     c->log.push_back(csipm_iter_log{it, cgi, ref, fell ? 1 : 0, use_learned ? 1 : 0, mu, rel, 0.0, relevant});
     inf.ipm_iters = it + 1;

@@ -30,7 +30,8 @@ enum ScalarSlot {
   S_REF0 = 11,     // refinement: rhs.P^{-1}rhs
   S_REFRZ = 12,    // refinement: r32.P^{-1}r32, start of the next inner PCG
   S_REFINF = 13,   // refinement: max |r| of the FP64 residual
-  S_RESID = 16,    // IPM residual block, 9 values (k_ipm_resid order)
+  S_DSDN = 14,     // predictor-corrector: sum ds.dnu of the affine direction
+  S_RESID = 16,    // IPM residual block, 10 values (k_ipm_resid order)
   S_SIG = 28,      // signal check: non-finite count, observed count
   S_MISC = 32,     // free scratch (32 values)
   S_COUNT = 64
@@ -77,7 +78,8 @@ template <typename TC>
 void newton_init(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
                  const double* xi, double lam, double smu, double* sig1, double* sig2, double* hb_out,
                  double* hz_out, TC* sig1c, TC* sig2c, const float* c, TC* rb, TC* rz, TC* zb, TC* zz, TC* pb,
-                 TC* pz, long long n, double* partial, hipStream_t s);
+                 TC* pz, long long n, double* partial, hipStream_t s, const double* dab = nullptr,
+                 const double* daz = nullptr);
 void set_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s);
 void fin_alpha(const double* partial, int nb, double* scal, int* flags, hipStream_t s);
 void fin_rz(const double* partial, int nb, double* scal, int* flags, hipStream_t s);
@@ -91,16 +93,22 @@ void ipm_resid(const double* beta, const double* z, const double* nu1, const dou
                const double* xi, double lam, long long n, double* partial, double* out8, bool logsum, hipStream_t s);
 // step length: scal[S_AMAX] and scal[S_ALPHA_IPM] = min(1, tau * S_AMAX)
 // (the direction is read from db32/dz32 when set, else from db/dz)
+// (dab, daz: the affine direction of a predictor-corrector step, for the
+// corrector's dnu; dsdn: where to put sum ds.dnu of this direction)
 void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* db,
               const double* dz, const float* db32, const float* dz32, double smu, double tau, long long n,
-              double* partial, double* scal, hipStream_t s);
+              double* partial, double* scal, hipStream_t s, const double* dab = nullptr, const double* daz = nullptr,
+              double* dsdn = nullptr);
 // iterate update with H beta carried along (H d_beta from hd when set, else
 // from the Krylov residual: rres32 when set, else rres), and the new residual
-// parts -> scal[S_RESID..]
+// parts -> scal[S_RESID..]; with rres, scal[S_RESID + 9] = max (S1 + S2)
+// (|d_beta| + |d_z|), which times the FP64 epsilon bounds the rounding error
+// of the recovered H d_beta
 void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* xi,
                  const double* db, const double* dz, const float* db32, const float* dz32, const double* hd,
                  const double* rres, const float* rres32, double lam, double smu, double* scal, long long n,
-                 double* partial, bool logsum, hipStream_t s);
+                 double* partial, bool logsum, hipStream_t s, const double* dab = nullptr,
+                 const double* daz = nullptr);
 
 void add_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s);
 // FP32 restart of a further inner solve from H d_beta (hd): r32, z32 = p32 =

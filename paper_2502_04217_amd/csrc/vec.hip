@@ -432,8 +432,9 @@ k_ipm_init(double* __restrict__ beta, double* __restrict__ z, double* __restrict
 // complementarity: [max|F_b|, max|F_z|, max s.nu, sum s.nu, max|beta|,
 // min(s, nu), count of non-finite values, sum log(S1 + S2) (when logsum is
 // set: the centring of the learned correction's first feature)].
-constexpr int NRESID = 9;
-#define CSIPM_RESID_OPS {RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM, RED_SUM, RED_SUM}
+constexpr int NRESID = 10;
+#define CSIPM_RESID_OPS \
+  {RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM, RED_SUM, RED_SUM, RED_MAX}
 
 __device__ __forceinline__ void resid_accumulate(double* v, double b, double s1, double s2, double a1, double a2,
                                                  double fb, double fz, int logsum) {
@@ -464,7 +465,7 @@ k_ipm_resid(const double* __restrict__ beta, const double* __restrict__ z, const
   CSIPM_ALIGN(hb);
   CSIPM_ALIGN(xi);
 
-  double v[NRESID] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0};
+  double v[NRESID] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0, 0.0};
   CSIPM_PAIRS(n) {
     const double b = beta[i], zz = z[i], a1 = nu1[i], a2 = nu2[i];
     const double s1 = zz + b, s2 = zz - b;
@@ -474,6 +475,45 @@ k_ipm_resid(const double* __restrict__ beta, const double* __restrict__ z, const
   }
   const int ops[NRESID] = CSIPM_RESID_OPS;
   block_reduce_store<NRESID>(v, ops, partial, stride);
+}
+
+// Search direction of the multipliers at one coefficient, with the barrier
+// diagonals re-formed from the state exactly as the Newton build forms them:
+//   s1 = z + beta, s2 = z - beta, Sigma_j = nu_j / s_j,
+//   ds1 = db + dz, ds2 = dz - db, dnu_j = smu/s_j - nu_j - Sigma_j ds_j.
+// With a predictor-corrector step the complementarity rows carry the
+// second-order term c_j = ds_j dnu_j of the affine direction (ca = c1, c2),
+// and smu / s_j becomes (smu - c_j) / s_j.
+struct IpmDir {
+  double s1, s2, i1, i2, g1, g2, ds1, ds2, dn1, dn2;
+};
+__device__ __forceinline__ IpmDir ipm_dir(double b, double zz, double a1, double a2, double d1, double d2,
+                                          double smu, double c1 = 0.0, double c2 = 0.0, bool corr = false) {
+  IpmDir o;
+  o.s1 = zz + b;
+  o.s2 = zz - b;
+  o.i1 = 1.0 / o.s1;
+  o.i2 = 1.0 / o.s2;
+  o.g1 = a1 * o.i1;
+  o.g2 = a2 * o.i2;
+  o.ds1 = d1 + d2;
+  o.ds2 = d2 - d1;
+  if (corr) {
+    o.dn1 = (smu - c1) * o.i1 - a1 - o.g1 * o.ds1;
+    o.dn2 = (smu - c2) * o.i2 - a2 - o.g2 * o.ds2;
+  } else {
+    o.dn1 = smu * o.i1 - a1 - o.g1 * o.ds1;
+    o.dn2 = smu * o.i2 - a2 - o.g2 * o.ds2;
+  }
+  return o;
+}
+// Second-order terms c_j = ds_j dnu_j of the affine direction (da1, da2) at
+// one coefficient (dnu_j = -nu_j - Sigma_j ds_j: target 0).
+__device__ __forceinline__ void corr_terms(double b, double zz, double a1, double a2, double da1, double da2,
+                                           double& c1, double& c2) {
+  const IpmDir d = ipm_dir(b, zz, a1, a2, da1, da2, 0.0);
+  c1 = d.ds1 * d.dn1;
+  c2 = d.ds2 * d.dn2;
 }
 
 // Newton system and PCG start in one pass: Sigma_j = nu_j / s_j (FP64 when
@@ -488,7 +528,7 @@ k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, con
               double* __restrict__ hb_out, double* __restrict__ hz_out, TC* __restrict__ sig1c,
               TC* __restrict__ sig2c, const float* __restrict__ c, TC* __restrict__ rb, TC* __restrict__ rz,
               TC* __restrict__ zb, TC* __restrict__ zz, TC* __restrict__ pb, TC* __restrict__ pz, long long n,
-              double* partial) {
+              double* partial, const double* __restrict__ dab, const double* __restrict__ daz) {
   CSIPM_ALIGN(beta);
   CSIPM_ALIGN(z);
   CSIPM_ALIGN(nu1);
@@ -523,8 +563,18 @@ k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, con
       const double s1 = zz2[k] + bb[k], s2 = zz2[k] - bb[k];
       const double i1 = 1.0 / s1, i2 = 1.0 / s2;
       const double g1 = n1[k] * i1, g2 = n2[k] * i2;
-      const double h1 = -(hv[k] - xv[k]) + smu * (i1 - i2);
-      const double h2 = -lam + smu * (i1 + i2);
+      double h1, h2;
+      if (dab) {   // corrector of a predictor-corrector step
+        double c1, c2;
+        corr_terms(bb[k], zz2[k], n1[k], n2[k], k ? dab[2 * j + 1] : dab[2 * j], k ? daz[2 * j + 1] : daz[2 * j],
+                   c1, c2);
+        const double u1 = (smu - c1) * i1, u2 = (smu - c2) * i2;
+        h1 = -(hv[k] - xv[k]) + (u1 - u2);
+        h2 = -lam + (u1 + u2);
+      } else {
+        h1 = -(hv[k] - xv[k]) + smu * (i1 - i2);
+        h2 = -lam + smu * (i1 + i2);
+      }
       double u1, u2;
       pinv_block<double>(h1, h2, g1, g2, cv[k], u1, u2);
       acc[1] += h1 * u1 + h2 * u2;
@@ -563,29 +613,6 @@ k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, con
   block_reduce_store<2>(acc, ops, partial, VEC_MAX_BLOCKS);
 }
 
-// Search direction of the multipliers at one coefficient, with the barrier
-// diagonals re-formed from the state exactly as the Newton build forms them:
-//   s1 = z + beta, s2 = z - beta, Sigma_j = nu_j / s_j,
-//   ds1 = db + dz, ds2 = dz - db, dnu_j = smu/s_j - nu_j - Sigma_j ds_j.
-struct IpmDir {
-  double s1, s2, i1, i2, g1, g2, ds1, ds2, dn1, dn2;
-};
-__device__ __forceinline__ IpmDir ipm_dir(double b, double zz, double a1, double a2, double d1, double d2,
-                                          double smu) {
-  IpmDir o;
-  o.s1 = zz + b;
-  o.s2 = zz - b;
-  o.i1 = 1.0 / o.s1;
-  o.i2 = 1.0 / o.s2;
-  o.g1 = a1 * o.i1;
-  o.g2 = a2 * o.i2;
-  o.ds1 = d1 + d2;
-  o.ds2 = d2 - d1;
-  o.dn1 = smu * o.i1 - a1 - o.g1 * o.ds1;
-  o.dn2 = smu * o.i2 - a2 - o.g2 * o.ds2;
-  return o;
-}
-
 // Pair j of a Newton direction: from its FP32 copy when one is given (an
 // FP32 solution taken without refinement), else from the FP64 array.
 __device__ __forceinline__ cx<double> ld_dir(const cx<double>* d64, const float* d32, long long j) {
@@ -596,30 +623,46 @@ __device__ __forceinline__ cx<double> ld_dir(const cx<double>* d64, const float*
   return d64[j];
 }
 
-// Largest step keeping s and nu positive along (db, dz, dnu1, dnu2).
+// Largest step keeping s and nu positive along (db, dz, dnu1, dnu2); with
+// dab set (a corrector) dnu carries the affine direction's second-order
+// terms; with dsdn set, also sum ds.dnu (quantity 1 of the partials: for the
+// affine direction, mu at its step alpha is ((1 - alpha) s.nu + alpha^2
+// ds.dnu) / 2n).
 __global__ void __launch_bounds__(256)
 k_ipm_ratio(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
             const double* __restrict__ nu2, const double* __restrict__ db, const double* __restrict__ dz,
             const float* __restrict__ db32, const float* __restrict__ dz32, double smu, long long n,
-            double* partial) {
-  double amax = INFINITY;
+            double* partial, const double* __restrict__ dab, const double* __restrict__ daz, int dsdn) {
+  double v[2] = {INFINITY, 0.0};
   using D2 = cx<double>;
   for (long long j = gtid(); j < n / 2; j += gstride()) {
     const D2 b2 = ((const D2*)beta)[j], z2 = ((const D2*)z)[j], a1 = ((const D2*)nu1)[j], a2 = ((const D2*)nu2)[j],
              d1 = ld_dir((const D2*)db, db32, j), d2 = ld_dir((const D2*)dz, dz32, j);
     const double bb[2] = {b2.re, b2.im}, zv[2] = {z2.re, z2.im}, n1[2] = {a1.re, a1.im}, n2[2] = {a2.re, a2.im},
                  dbv[2] = {d1.re, d1.im}, dzv[2] = {d2.re, d2.im};
+    double c1[2] = {0.0, 0.0}, c2[2] = {0.0, 0.0};
+    if (dab) {
+      const D2 e1 = ((const D2*)dab)[j], e2 = ((const D2*)daz)[j];
+      corr_terms(bb[0], zv[0], n1[0], n2[0], e1.re, e2.re, c1[0], c2[0]);
+      corr_terms(bb[1], zv[1], n1[1], n2[1], e1.im, e2.im, c1[1], c2[1]);
+    }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const IpmDir d = ipm_dir(bb[k], zv[k], n1[k], n2[k], dbv[k], dzv[k], smu);
-      if (d.ds1 < 0.0) amax = fmin(amax, -d.s1 / d.ds1);
-      if (d.ds2 < 0.0) amax = fmin(amax, -d.s2 / d.ds2);
-      if (d.dn1 < 0.0) amax = fmin(amax, -n1[k] / d.dn1);
-      if (d.dn2 < 0.0) amax = fmin(amax, -n2[k] / d.dn2);
+      const IpmDir d = ipm_dir(bb[k], zv[k], n1[k], n2[k], dbv[k], dzv[k], smu, c1[k], c2[k], dab != nullptr);
+      if (d.ds1 < 0.0) v[0] = fmin(v[0], -d.s1 / d.ds1);
+      if (d.ds2 < 0.0) v[0] = fmin(v[0], -d.s2 / d.ds2);
+      if (d.dn1 < 0.0) v[0] = fmin(v[0], -n1[k] / d.dn1);
+      if (d.dn2 < 0.0) v[0] = fmin(v[0], -n2[k] / d.dn2);
+      if (dsdn) v[1] += d.ds1 * d.dn1 + d.ds2 * d.dn2;
     }
   }
-  const int op = RED_MIN;
-  block_reduce_store<1>(&amax, &op, partial, 0);
+  if (dsdn) {
+    const int ops[2] = {RED_MIN, RED_SUM};
+    block_reduce_store<2>(v, ops, partial, VEC_MAX_BLOCKS);
+  } else {
+    const int op = RED_MIN;
+    block_reduce_store<1>(v, &op, partial, 0);
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -651,9 +694,9 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
               const double* __restrict__ dz, const double* __restrict__ hd, const double* __restrict__ rres,
               const float* __restrict__ rres32, const float* __restrict__ db32, const float* __restrict__ dz32,
               double lam, double smu, const double* __restrict__ scal, long long n, double* partial, int stride,
-              int logsum) {
+              int logsum, const double* __restrict__ dab, const double* __restrict__ daz) {
   const double a = scal[S_ALPHA_IPM];
-  double v[NRESID] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0};
+  double v[NRESID] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0, 0.0};
   using D2 = cx<double>;
   D2 *BE = (D2*)beta, *ZV = (D2*)z, *N1 = (D2*)nu1, *N2 = (D2*)nu2, *HBV = (D2*)hbeta;
   const D2 *XI = (const D2*)xi, *DB = (const D2*)db, *DZ = (const D2*)dz, *W = (const D2*)(hd ? hd : rres);
@@ -672,15 +715,25 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
                  hv[2] = {h2.re, h2.im}, xv[2] = {x2.re, x2.im}, dbv[2] = {d1.re, d1.im},
                  dzv[2] = {d2.re, d2.im}, wv[2] = {w2.re, w2.im};
     double bo[2], zo[2], n1o[2], n2o[2], ho[2];
+    double c1[2] = {0.0, 0.0}, c2[2] = {0.0, 0.0};
+    if (dab) {
+      const D2 e1 = ((const D2*)dab)[j], e2 = ((const D2*)daz)[j];
+      corr_terms(bb[0], zv[0], n1[0], n2[0], e1.re, e2.re, c1[0], c2[0]);
+      corr_terms(bb[1], zv[1], n1[1], n2[1], e1.im, e2.im, c1[1], c2[1]);
+    }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const IpmDir d = ipm_dir(bb[k], zv[k], n1[k], n2[k], dbv[k], dzv[k], smu);
+      const IpmDir d = ipm_dir(bb[k], zv[k], n1[k], n2[k], dbv[k], dzv[k], smu, c1[k], c2[k], dab != nullptr);
       double u;
       if (hd) {
         u = wv[k];
       } else {
-        const double hrhs = -(hv[k] - xv[k]) + smu * (d.i1 - d.i2);
+        const double hrhs = dab ? -(hv[k] - xv[k]) + ((smu - c1[k]) * d.i1 - (smu - c2[k]) * d.i2)
+                                : -(hv[k] - xv[k]) + smu * (d.i1 - d.i2);
         u = (hrhs - wv[k]) - (d.g1 * (dbv[k] + dzv[k]) + d.g2 * (dbv[k] - dzv[k]));
+        // rounding of the Sigma terms, here and in the Krylov recurrence
+        // that produced r, scales like eps (S1 + S2)(|d_beta| + |d_z|)
+        v[9] = fmax(v[9], (d.g1 + d.g2) * (fabs(dbv[k]) + fabs(dzv[k])));
       }
       const double b = bb[k] + a * dbv[k], zz = zv[k] + a * dzv[k];
       const double m1 = n1[k] + a * d.dn1, m2 = n2[k] + a * d.dn2;
@@ -929,9 +982,9 @@ template <typename TC>
 void newton_init(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
                  const double* xi, double lam, double smu, double* sig1, double* sig2, double* hb_out,
                  double* hz_out, TC* sig1c, TC* sig2c, const float* c, TC* rb, TC* rz, TC* zb, TC* zz, TC* pb,
-                 TC* pz, long long n, double* partial, hipStream_t s) {
+                 TC* pz, long long n, double* partial, hipStream_t s, const double* dab, const double* daz) {
   hipLaunchKernelGGL((k_newton_init<TC>), VB, beta, z, nu1, nu2, hb, xi, lam, smu, sig1, sig2, hb_out, hz_out,
-                     sig1c, sig2c, c, rb, rz, zb, zz, pb, pz, n, partial);
+                     sig1c, sig2c, c, rb, rz, zb, zz, pb, pz, n, partial, dab, daz);
 }
 void set_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_set_f2d, VB, db, dz, eb, ez, n);
@@ -986,18 +1039,24 @@ void ipm_resid(const double* beta, const double* z, const double* nu1, const dou
 }
 void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* db,
               const double* dz, const float* db32, const float* dz32, double smu, double tau, long long n,
-              double* partial, double* scal, hipStream_t s) {
+              double* partial, double* scal, hipStream_t s, const double* dab, const double* daz, double* dsdn) {
   const int nb = vec_blocks(n);
-  hipLaunchKernelGGL(k_ipm_ratio, VB, beta, z, nu1, nu2, db, dz, db32, dz32, smu, n, partial);
+  hipLaunchKernelGGL(k_ipm_ratio, VB, beta, z, nu1, nu2, db, dz, db32, dz32, smu, n, partial, dab, daz,
+                     dsdn ? 1 : 0);
   hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(256), 0, s, partial, nb, tau, scal);
+  if (dsdn) {
+    RedOps<1> ops{{RED_SUM}};
+    hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(256), 0, s, partial + VEC_MAX_BLOCKS, nb, VEC_MAX_BLOCKS,
+                       dsdn, ops);
+  }
 }
 void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* xi,
                  const double* db, const double* dz, const float* db32, const float* dz32, const double* hd,
                  const double* rres, const float* rres32, double lam, double smu, double* scal, long long n,
-                 double* partial, bool logsum, hipStream_t s) {
+                 double* partial, bool logsum, hipStream_t s, const double* dab, const double* daz) {
   const int nb = vec_blocks(n);
   hipLaunchKernelGGL(k_ipm_advance, VB, beta, z, nu1, nu2, hbeta, xi, db, dz, hd, rres, rres32, db32, dz32, lam, smu,
-                     scal, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0);
+                     scal, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0, dab, daz);
   hipLaunchKernelGGL((k_fin_reduce<NRESID>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, scal + S_RESID,
                      kResidRedOps);
 }
@@ -1065,7 +1124,8 @@ void diag_h(const double* bm_ext, double* out_ext, int n1, int n2, int n3, doubl
                              hipStream_t);                                                                     \
   template void newton_init<T>(const double*, const double*, const double*, const double*, const double*,     \
                                const double*, double, double, double*, double*, double*, double*, T*, T*,      \
-                               const float*, T*, T*, T*, T*, T*, T*, long long, double*, hipStream_t);         \
+                               const float*, T*, T*, T*, T*, T*, T*, long long, double*, hipStream_t,          \
+                               const double*, const double*);                                                  \
   template void cg_pupdate<T>(T*, T*, const T*, const T*, const double*, const int*, long long, hipStream_t);  \
   template void cr_dir<T>(T*, T*, T*, T*, const T*, const T*, const T*, const T*, const T*, const T*,         \
                           const float*, const double*, const int*, long long, double*, bool, hipStream_t);   \

@@ -359,3 +359,34 @@ def test_solve_batch_matches_sequential():
         assert torch.equal(pr.get(csipm.BETA).cpu(), b0)
     with pytest.raises(csipm.CsipmError):
         csipm.solve_batch([probs[0], probs[0]], tol=1e-8)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("grid", ["grid16-1", "grid16-4", "grid64"])
+def test_predictor_corrector_parity(grid, precision):
+    """Mehrotra predictor-corrector steps against the oracle's (IPMOptions
+    mehrotra): same LASSO solution and support at rel_kkt 1e-11; in FP64 the
+    same interior-point iteration count and Krylov counts over the first
+    iterations; fewer interior-point iterations than the standard method."""
+    w = wl.grid64(1) if grid == "grid64" else wl.grid16(int(grid[-1]))
+    lam = ipm.lambda_rule(w.signal, w.observed)
+    ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=PARITY_TOL, mehrotra=True))
+    assert ref.converged
+    pr, info, beta = _gpu_solve(w, lam, tol=PARITY_TOL, precision=precision, mehrotra=1)
+    log = pr.log()
+    say("  mehrotra", grid, precision, info["status_name"], info["ipm_iters"], info["cg_iters_total"],
+        [r["cg_iters"] for r in log], "oracle", ref.iters, ref.cg_iters)
+    say("  rel_kkt", ["%.2e" % r["rel_kkt"] for r in log], info["rel_kkt"])
+    say("  oracle ", ["%.2e" % r["rel_kkt"] for r in ref.log])
+    assert info["status"] == 0
+    err = rel2(beta, ref.state.beta)
+    say("  rel err vs oracle", err)
+    assert err <= 1e-7
+    ok, amb = _supports_match(beta, ref.state.beta)
+    assert ok
+    std = pr.solve(tol=PARITY_TOL, precision=precision)
+    assert info["ipm_iters"] < std["ipm_iters"]
+    if precision == 0:
+        assert info["ipm_iters"] == ref.iters
+        for a, b in zip(log[:4], ref.log[:4]):
+            assert a["cg_iters"] == b["cg"]
