@@ -76,6 +76,12 @@ def kernel_bytes(name, shape, learned):
         "postmix": 2 * plane * w,
         "axis1_fwd_K": 7 * n * w,
         "postmix_K": 7 * plane * w,
+        # the K-apply of a CG direction with p <- z + beta p fused in: z read and
+        # p written back by the passes that first read p
+        "premix_P": 4 * plane * w,
+        "axis1_inv_P": 4 * n * w,
+        "axis1_fwd_KP": 9 * n * w,
+        "postmix_KP": 9 * plane * w,
         # T, d (2), Sigma (2), h (2) in FP64, c; H d_beta out
         "axis1_fwd_R": (64 + c) * n,
         "postmix_R": (64 + c) * plane,
@@ -83,17 +89,17 @@ def kernel_bytes(name, shape, learned):
         "ref_restart+fin": (56 + c + 24) * n,
         # x, p, q, r, Sigma (2 each) in, x, r, z out (the first update of a solve skips reading x)
         "cg_update": 16 * n * w + c * n,
-        "cg_pupdate": 6 * n * w,
-        # beta, z, nu1, nu2, H beta, xi in; Sigma, PCG start (and h, FP32 Sigma) out
-        "newton_init": (112 + c) * n,
-        "newton_init_noh": (80 + c) * n,   # FP32 system taken without refinement: no FP64 h, Sigma
+        # beta, z, nu1, nu2, G = H beta - xi in; Sigma, CG start r, p (and h, FP32 Sigma) out
+        "newton_init": (96 + c) * n,
+        "newton_init_noh": (64 + c) * n,   # FP32 system taken without refinement: no FP64 h, Sigma
         # beta, z, nu1, nu2 and the direction (FP64, or FP32 after an unrefined FP32 solve)
         "ipm_ratio+fin": 48 * n,
         "ipm_ratio_d32+fin": 40 * n,
-        # beta, z, nu1, nu2, H beta, xi, direction, H d_beta source (beta part) in; state and H beta out
-        "ipm_advance+fin": 112 * n,
-        "ipm_advance_d32+fin": 100 * n,
-        "ipm_resid+fin": 48 * n,
+        # beta, z, nu1, nu2, G, direction, H d_beta source (beta part) in; state and G out
+        "ipm_advance+fin": 104 * n,
+        "ipm_advance_d32+fin": 92 * n,
+        # beta, z, nu1, nu2, H beta, xi in, G = H beta - xi out (after a full H-apply)
+        "ipm_resid+fin": 56 * n,
         "set_f2d": 24 * n,
         "add_f2d": 40 * n,
         "log_l1+fin": 32 * n,

@@ -49,7 +49,8 @@ struct csipm_ctx {
   int device = 0;       // the HIP device current at creation
   std::string err;
 
-  // FP64 interior-point state and Newton system (internal layout)
+  // FP64 interior-point state and Newton system (internal layout); hb
+  // holds G = H beta - xi, the data part of the first KKT row
   double *beta, *z, *nu1, *nu2, *xi, *hb, *sig1, *sig2, *rhb, *rhz, *dxb, *dxz, *diagH;
   // copy of (beta, z, nu1, nu2) taken before a step along a direction that
   // missed its tolerance, restored if that step raised rel_kkt
@@ -227,20 +228,23 @@ size_t k_partials(int n1, int n2, int n3);
 // q = K p with p.q partials in c->partK; returns the number of partials.
 template <typename T>
 int op_K(csipm_ctx* c, const T* pb, const T* pz, const T* s1, const T* s2, T* qb, T* qz, T* work,
-         const int* skip) {
+         const int* skip, const PUpd<T>* u = nullptr) {
   const Grid& g = c->g;
   const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>), -1);
   const int ps = (int)k_partials(g.n1, g.n2, g.n3);
-  EpiArgs<T> ka{KArgs<T>{pb, pz, s1, s2, qb, qz}, RArgs{}, c->partK, ps};
+  EpiArgs<T> ka{KArgs<T>{pb, pz, s1, s2, qb, qz, u ? *u : PUpd<T>{}}, RArgs{}, c->partK, ps};
   EpiArgs<T> kb = ka;
   kb.partial = c->partK + nb5;
-  KT(c, PN(T, "premix"), launch_premix<T>(g, pb, work, skip, c->s));
-  KT(c, PN(T, "axis1_inv"), launch_axis12<T>(g, 1, +1, pb, work, tw<T>(c), EPI_NONE, nullptr, true, skip, c->s));
+  // (the passes that apply the direction update are timed under their own names)
+  KT(c, u ? PN(T, "premix_P") : PN(T, "premix"), launch_premix<T>(g, pb, work, skip, c->s, u));
+  KT(c, u ? PN(T, "axis1_inv_P") : PN(T, "axis1_inv"),
+     launch_axis12<T>(g, 1, +1, pb, work, tw<T>(c), EPI_NONE, u ? &ka : nullptr, true, skip, c->s));
   KT(c, PN(T, "axis2_inv"), launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, skip, c->s));
   KT(c, PN(T, "axis3"), launch_axis3<T>(g, A3_FULL, work, work, c->mask, tw<T>(c), skip, c->s));
   KT(c, PN(T, "axis2_fwd"), launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, skip, c->s));
-  KT(c, PN(T, "axis1_fwd_K"), launch_axis12<T>(g, 1, -1, work, work, tw<T>(c), EPI_K, &ka, false, skip, c->s));
-  KT(c, PN(T, "postmix_K"), launch_postmix<T>(g, work, nullptr, EPI_K, &kb, skip, c->s));
+  KT(c, u ? PN(T, "axis1_fwd_KP") : PN(T, "axis1_fwd_K"),
+     launch_axis12<T>(g, 1, -1, work, work, tw<T>(c), EPI_K, &ka, false, skip, c->s));
+  KT(c, u ? PN(T, "postmix_KP") : PN(T, "postmix_K"), launch_postmix<T>(g, work, nullptr, EPI_K, &kb, skip, c->s));
   return nb5 + postmix_blocks(g);
 }
 
@@ -350,16 +354,18 @@ csipm_status pcg(csipm_ctx* c, T* xb, T* xz, const T* s1, const T* s2, const flo
   const int* skip = c->flags + F_DONE;
   int chunk = 2;
   bool first = true;
+  // after the first iteration, p <- z + beta p is applied by the K-apply of
+  // the new p as it reads p (PUpd), not by a separate pass
+  const PUpd<T> upd{pb, pz, zb, zz, c->scal + S_BETA};
   for (;;) {
     for (int k = 0; k < chunk; ++k) {
-      const int nbk = op_K<T>(c, pb, pz, s1, s2, qb, qz, work, skip);
+      const int nbk = op_K<T>(c, pb, pz, s1, s2, qb, qz, work, skip, first ? nullptr : &upd);
       if (first && capture) KT(c, "capture", capture_pair<T>(c, pb, pz, qb, qz, s1, s2));
       KT(c, "fin_alpha", fin_alpha(c->partK, nbk, c->scal, c->flags, c->s));
       KT(c, PN(T, "cg_update"), cg_update<T>(xb, xz, pb, pz, qb, qz, rb, rz, zb, zz, s1, s2, pcc, c->scal, c->flags,
                                             n, c->partV, first, c->s));
       first = false;
       KT(c, "fin_rz", fin_rz(c->partV, nbv, c->scal, c->flags, c->s));
-      KT(c, PN(T, "cg_pupdate"), cg_pupdate<T>(pb, pz, zb, zz, c->scal, c->flags, n, c->s));
     }
     csipm_status st = sync_scalars(c, "pcg");
     if (st != CSIPM_OK) return st;
@@ -634,11 +640,13 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
   refine_steps = 0;
   converged = false;
   src = HD_RRES64;
+  // CG starts from p = z and overwrites z before reading it
+  const bool cg = o.krylov == CSIPM_KRYLOV_CG;
   if (o.precision == CSIPM_FP64) {
     KT(c, "newton_init.f64",
-       newton_init<double>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, smu, c->sig1, c->sig2, nullptr,
-                           nullptr, nullptr, nullptr, pcc, c->rb, c->rz, c->zb, c->zz, c->pb, c->pz, n, c->partV,
-                           c->s, dab, daz));
+       newton_init<double>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->lambda, smu, c->sig1, c->sig2, nullptr,
+                           nullptr, nullptr, nullptr, pcc, c->rb, c->rz, cg ? nullptr : c->zb, c->zz, c->pb, c->pz,
+                           n, c->partV, c->s, dab, daz));
     KT(c, "fin_cg_start",
        fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, eta, o.cg_atol, o.cg_max, -1, -1, c->s));
     PcgOut po;
@@ -658,11 +666,11 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
   // (an unrefined system stores no FP64 Sigma or h: nothing reads them,
   // except the features of a capture)
   KT(c, trusted ? "newton_init_noh.f32" : "newton_init.f32",
-     newton_init<float>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, smu,
+     newton_init<float>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->lambda, smu,
                         trusted && !capture ? nullptr : c->sig1, trusted && !capture ? nullptr : c->sig2,
                         trusted ? nullptr : c->rhb, trusted ? nullptr : c->rhz,
                         c->sig1f, c->sig2f, pcc, c->frb,
-                        c->frz, c->fzb, c->fzz, c->fpb, c->fpz, n, c->partV, c->s, dab, daz));
+                        c->frz, cg ? nullptr : c->fzb, c->fzz, c->fpb, c->fpz, n, c->partV, c->s, dab, daz));
   // inner tolerance: half the remaining reduction, at most 1e-2, at least
   // refine_inner_rtol (what FP32 PCG can still reach)
   double inner = std::max(o.refine_inner_rtol, std::min(1e-2, 0.5 * eta));
@@ -725,8 +733,8 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
     inner = std::max(o.refine_inner_rtol, std::min(1e-2, 0.5 * need));
     // FP32 start of the next inner solve: r32, z32 = p32 = P_c^{-1} r, r32.z32 -> S_REFRZ
     KT(c, "ref_restart+fin",
-       ref_restart(c->rhb, c->rhz, c->dxb, c->dxz, c->rb, c->sig1, c->sig2, pcc, c->frb, c->frz, c->fzb, c->fzz,
-                   c->fpb, c->fpz, n, c->partV, c->scal + S_REFRZ, c->s));
+       ref_restart(c->rhb, c->rhz, c->dxb, c->dxz, c->rb, c->sig1, c->sig2, pcc, c->frb, c->frz,
+                   cg ? nullptr : c->fzb, c->fzz, c->fpb, c->fpz, n, c->partV, c->scal + S_REFRZ, c->s));
   }
   return CSIPM_OK;
 }
@@ -762,8 +770,8 @@ Resid read_resid(const csipm_ctx* c) {
   return Resid{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[8], v[9]};
 }
 
-// Residual parts with H beta recomputed by a full H-apply (and the sum of
-// log(S1 + S2) into scal[S_RESID + 7] when logsum).
+// Residual parts with G = H beta - xi recomputed by a full H-apply (and the
+// sum of log(S1 + S2) into scal[S_RESID + 7] when logsum).
 csipm_status residuals(csipm_ctx* c, Resid& r, bool logsum) {
   op_H<double>(c, c->beta, c->hb, c->work);
   KT(c, "ipm_resid+fin", ipm_resid(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->lambda, c->g.n, c->partV,
@@ -774,7 +782,8 @@ csipm_status residuals(csipm_ctx* c, Resid& r, bool logsum) {
   return CSIPM_OK;
 }
 
-// H beta is carried from iteration to iteration (k_ipm_advance); it is
+// G = H beta - xi is carried from iteration to iteration (k_ipm_advance: G +=
+// alpha H d_beta); it is
 // recomputed by a full H-apply before a stopping decision, at least every
 // kExactEvery iterations, and before the first FP32 Newton system that is
 // refined after unrefined ones, so carried error never accumulates far.
@@ -820,10 +829,10 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     KT(c, "fill", fill<float>(c->pc_c, (float)rho, n, c->s));
     pc_fixed = c->pc_c;
   }
-  // the start beta = 0 has H beta = 0 exactly
-  KT(c, "ipm_init", ipm_init(c->beta, c->z, c->nu1, c->nu2, c->hb, n, z0, lam, c->s));
+  // the start beta = 0 has H beta = 0 exactly: G = -xi
+  KT(c, "ipm_init", ipm_init(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, n, z0, lam, c->s));
   KT(c, "ipm_resid+fin",
-     ipm_resid(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, lam, n, c->partV, c->scal + S_RESID, learned, c->s));
+     ipm_resid(c->beta, c->z, c->nu1, c->nu2, c->hb, nullptr, lam, n, c->partV, c->scal + S_RESID, learned, c->s));
   csipm_status st = sync_scalars(c, "solve start");
   if (st != CSIPM_OK) return st;
   Resid r = read_resid(c);
@@ -1002,7 +1011,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
        ipm_step(c->beta, c->z, c->nu1, c->nu2, c->dxb, c->dxz, d32b, d32z, smu, o.tau, n, c->partV, c->scal, c->s,
                 dab, daz));
     KT(c, d32b ? "ipm_advance_d32+fin" : "ipm_advance+fin",
-       ipm_advance(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, c->dxb, c->dxz, d32b, d32z,
+       ipm_advance(c->beta, c->z, c->nu1, c->nu2, c->hb, c->dxb, c->dxz, d32b, d32z,
                    src == HD_DIRECT ? c->rb : nullptr, c->rb, src == HD_RRES32 ? c->frb : nullptr, lam, smu, c->scal, n,
                    c->partV, learned, c->s, dab, daz));
     st = sync_scalars(c, "advance");

@@ -132,6 +132,19 @@ enum EpiMode {
 // (elsewhere the 2x2 block of P_c does not depend on c to this precision)
 constexpr double kPcRelevance = 1e-3;
 
+// CG direction update p <- z + beta p fused into the K-apply of the new p
+// (zb null: none).  The passes that first read p apply it and write p back:
+// the premix (m = 0) and the axis-1 inverse pass (m >= 1) to p_beta, the K
+// epilogues to p_z.  Every element is updated exactly once.
+template <typename T>
+struct PUpd {
+  T* pb;
+  T* pz;
+  const T* zb;
+  const T* zz;
+  const double* beta;   // device scalar
+};
+
 template <typename T>
 struct KArgs {
   const T* pb;        // p_beta (internal layout)
@@ -140,6 +153,7 @@ struct KArgs {
   const T* sig2;      // Sigma_2
   T* qb;
   T* qz;
+  PUpd<T> u;          // fused direction update (u.zb null: none)
 };
 
 struct RArgs {
@@ -196,7 +210,10 @@ __device__ __forceinline__ void p_block(T zb, T zz, T s1, T s2, double c, double
 // `skip` (nullable device int): when nonzero at launch time the kernel
 // returns at once; lets a batch of Krylov iterations be queued ahead.
 template <typename T>
-void launch_premix(const Grid& g, const T* src, T* work, const int* skip, hipStream_t s);
+void launch_premix(const Grid& g, const T* src, T* work, const int* skip, hipStream_t s,
+                   const PUpd<T>* u = nullptr);
+// (the axis-1 inverse pass applies the direction update ea->k.u when ea is
+// set and ea->k.u.zb is not null)
 template <typename T>
 void launch_axis12(const Grid& g, int axis, int dir, const T* src, T* dst, const Twiddles<T>& tw,
                    int epi, const EpiArgs<T>* ea, bool m0_from_dst, const int* skip, hipStream_t s);

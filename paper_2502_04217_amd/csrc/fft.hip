@@ -47,24 +47,36 @@ __device__ __forceinline__ int cls2(int k1, int k2, int n1, int n2) {
   return 2;
 }
 
+// (pw, z, beta: the fused CG direction update of the m = 0 column, src = pw;
+// z null: none)
 template <typename T>
-__global__ void k_premix(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n1, int n2, int m,
-                         const int* skip) {
+__global__ void k_premix(const cx<T>* src, cx<T>* __restrict__ dst, int n1, int n2, int m, const int* skip,
+                         cx<T>* pw, const cx<T>* __restrict__ z, const double* __restrict__ beta) {
   if (skip && *skip) return;
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= n1 * n2) return;
   const int k1 = id / n2, k2 = id % n2;
   const int c = cls2(k1, k2, n1, n2);
   if (c == 2) return;
+  const T be = z ? (T)*beta : T(0);
+  auto load = [&](long long i) {
+    cx<T> x = src[i];
+    if (z) {
+      const cx<T> zv = z[i];
+      x = {zv.re + be * x.re, zv.im + be * x.im};
+      pw[i] = x;
+    }
+    return x;
+  };
   const long long ia = ((long long)k1 * n2 + k2) * m;
   if (c == 0) {
-    dst[ia] = src[ia];
+    dst[ia] = load(ia);
     return;
   }
   const int q1 = (n1 - k1) % n1, q2 = (n2 - k2) % n2;
   const long long ib = ((long long)q1 * n2 + q2) * m;
   const T r = T(0.70710678118654752440);
-  const cx<T> a = src[ia], b = src[ib];
+  const cx<T> a = load(ia), b = load(ib);
   // U[k] = (W[k] + i W[-k]) / sqrt2,  U[-k] = (W[k] - i W[-k]) / sqrt2
   const cx<T> ib_ = cmul_i<1>(b);
   dst[ia] = cscale(cadd(a, ib_), r);
@@ -243,10 +255,13 @@ bool fft_extent_supported(int N, int axis) {
 int postmix_blocks(const Grid& g) { return (g.n1 * g.n2 + 255) / 256; }
 
 template <typename T>
-void launch_premix(const Grid& g, const T* src, T* work, const int* skip, hipStream_t s) {
+void launch_premix(const Grid& g, const T* src, T* work, const int* skip, hipStream_t s, const PUpd<T>* u) {
   const int tot = g.n1 * g.n2;
+  const bool up = u && u->zb;
   hipLaunchKernelGGL((k_premix<T>), dim3((tot + 255) / 256), dim3(256), 0, s,
-                     reinterpret_cast<const cx<T>*>(src), reinterpret_cast<cx<T>*>(work), g.n1, g.n2, g.m, skip);
+                     reinterpret_cast<const cx<T>*>(src), reinterpret_cast<cx<T>*>(work), g.n1, g.n2, g.m, skip,
+                     up ? reinterpret_cast<cx<T>*>(u->pb) : nullptr,
+                     up ? reinterpret_cast<const cx<T>*>(u->zb) : nullptr, up ? u->beta : nullptr);
 }
 
 template <typename T>
@@ -260,7 +275,10 @@ void launch_axis12(const Grid& g, int axis, int dir, const T* src, T* dst, const
   cx<T>* cd = reinterpret_cast<cx<T>*>(dst);
   if (axis == 1) {
     if (dir > 0) {
-      launch_axis12_L<T, 1, +1>(L, grid, cs, cd, geo, twp, g.m, m0_from_dst ? 1 : 0, EpiNone{}, skip, s);
+      const bool up = ea && ea->k.u.zb;
+      EpiP<T> pro{up ? reinterpret_cast<cx<T>*>(ea->k.u.pb) : nullptr,
+                  up ? reinterpret_cast<const cx<T>*>(ea->k.u.zb) : nullptr, up ? ea->k.u.beta : nullptr};
+      launch_axis12_L<T, 1, +1>(L, grid, cs, cd, geo, twp, g.m, m0_from_dst ? 1 : 0, pro, skip, s);
     } else if (epi == EPI_K) {
       launch_axis12_L<T, 1, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiK<T>{ea->k, ea->partial, ea->pstride}, skip, s);
     } else if (epi == EPI_R) {
@@ -348,7 +366,7 @@ void launch_pack_mask(const Grid& g, const uint8_t* obs, uint32_t* bits, hipStre
 }
 
 #define CSIPM_INST(T)                                                                                          \
-  template void launch_premix<T>(const Grid&, const T*, T*, const int*, hipStream_t);                          \
+  template void launch_premix<T>(const Grid&, const T*, T*, const int*, hipStream_t, const PUpd<T>*);          \
   template void launch_axis12<T>(const Grid&, int, int, const T*, T*, const Twiddles<T>&, int,                 \
                                  const EpiArgs<T>*, bool, const int*, hipStream_t);                            \
   template void launch_axis3<T>(const Grid&, int, const T*, T*, const uint32_t*, const Twiddles<T>&,           \

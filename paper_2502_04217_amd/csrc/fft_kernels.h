@@ -320,6 +320,22 @@ __device__ __forceinline__ void block_sums_store(const double* v, double* out, i
 struct EpiNone {
   static constexpr int NRED = 0;
   static constexpr int NMAX = 0;
+  static constexpr bool PRO = false;
+  double* partial = nullptr;
+  int pstride = 0;
+};
+
+// Plain output with the fused CG direction update on input (axis-1 inverse
+// pass of K p): p <- z + beta p as p is loaded, written back to p, except in
+// the m = 0 column that the premix already updated.  z null: no update.
+template <typename T>
+struct EpiP {
+  static constexpr int NRED = 0;
+  static constexpr int NMAX = 0;
+  static constexpr bool PRO = true;
+  cx<T>* p;
+  const cx<T>* z;
+  const double* beta;
   double* partial = nullptr;
   int pstride = 0;
 };
@@ -329,12 +345,19 @@ template <typename T>
 struct EpiK {
   static constexpr int NRED = 1;
   static constexpr int NMAX = 0;
+  static constexpr bool PRO = false;
   KArgs<T> a;
   double* partial;
   int pstride;
   __device__ __forceinline__ void operator()(long long idx, cx<T> h, double* acc) const {
     const cx<T> pb = reinterpret_cast<const cx<T>*>(a.pb)[idx];
-    const cx<T> pz = reinterpret_cast<const cx<T>*>(a.pz)[idx];
+    cx<T> pz = reinterpret_cast<const cx<T>*>(a.pz)[idx];
+    if (a.u.zb) {   // fused direction update of p_z (p_beta was updated on input)
+      const T be = (T)*a.u.beta;
+      const cx<T> zz = reinterpret_cast<const cx<T>*>(a.u.zz)[idx];
+      pz = {zz.re + be * pz.re, zz.im + be * pz.im};
+      reinterpret_cast<cx<T>*>(a.u.pz)[idx] = pz;
+    }
     const cx<T> s1 = reinterpret_cast<const cx<T>*>(a.sig1)[idx];
     const cx<T> s2 = reinterpret_cast<const cx<T>*>(a.sig2)[idx];
     cx<T> qb, qz;
@@ -354,6 +377,7 @@ struct EpiK {
 struct EpiR {
   static constexpr int NRED = 2;
   static constexpr int NMAX = 1;
+  static constexpr bool PRO = false;
   RArgs a;
   double* partial;
   int pstride;
@@ -448,8 +472,23 @@ k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
   const cx<T>* in = (m0_from_dst && is_m0) ? dst : src;
 
   cx<T> v[VM];
+  bool upd = false;
+  T be = T(0);
+  if constexpr (Epi::PRO) {
+    upd = epi.z != nullptr && !(m0_from_dst && is_m0);
+    if (upd) be = (T)*epi.beta;
+  }
   for_stage_io<L, E, 0>(t, [&](int s, int e) {
-    v[s] = active ? in[base + (long long)e * geo.estride] : cx<T>{T(0), T(0)};
+    const long long idx = base + (long long)e * geo.estride;
+    cx<T> x = active ? in[idx] : cx<T>{T(0), T(0)};
+    if constexpr (Epi::PRO) {
+      if (upd && active) {
+        const cx<T> zv = epi.z[idx];
+        x = {zv.re + be * x.re, zv.im + be * x.im};
+        epi.p[idx] = x;
+      }
+    }
+    v[s] = x;
   });
   auto lidx = [p](int e) { return e * TM + p; };
   fft_stages<T, L, E, DIR, 0>(v, t, lds, lidx, tw);
@@ -710,7 +749,7 @@ bool launch_axis3_mixed(int L, int mode, int np, const cx<T>* cs, cx<T>* cd, con
   PREFIX template bool launch_axis12_mixed<T, AX, DIR, EPI>(int, dim3, const cx<T>*, cx<T>*, StridedGeom<T>, \
                                                             const cx<T>*, int, int, EPI, const int*, hipStream_t);
 #define CSIPM_MIXED_INSTANCES(PREFIX, T)                                                                   \
-  CSIPM_MIXED_INST12(PREFIX, T, 1, +1, EpiNone)                                                            \
+  CSIPM_MIXED_INST12(PREFIX, T, 1, +1, EpiP<T>)                                                            \
   CSIPM_MIXED_INST12(PREFIX, T, 1, -1, EpiNone)                                                            \
   CSIPM_MIXED_INST12(PREFIX, T, 1, -1, EpiK<T>)                                                            \
   CSIPM_MIXED_INST12(PREFIX, T, 2, +1, EpiNone)                                                            \

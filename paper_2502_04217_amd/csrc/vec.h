@@ -45,9 +45,6 @@ template <typename T>
 void cg_update(T* xb, T* xz, const T* pb, const T* pz, const T* qb, const T* qz, T* rb, T* rz, T* zb, T* zz,
                const T* s1, const T* s2, const float* c, const double* scal, const int* flags, long long n,
                double* partial, bool first, hipStream_t s);
-template <typename T>
-void cg_pupdate(T* pb, T* pz, const T* zb, const T* zz, const double* scal, const int* flags, long long n,
-                hipStream_t s);
 // conjugate residuals: p = z + beta p, q = w + beta q (p = z, q = w first),
 // partial q.P_c^{-1}q; and the finalize after w = K z (beta, alpha's numerator)
 template <typename T>
@@ -74,9 +71,15 @@ void car_update(T* xb, T* xz, const T* pb, const T* pz, T* zb, T* zz, const T* v
 // (at partial + stride) summed into scal[ref_slot] when ref_slot >= 0
 void fin_cg_start(const double* partial, int nb, int stride, double* scal, int* flags, double eta, double atol,
                   int maxit, int ref_slot, int from_slot, hipStream_t s);
+// The interior-point iteration carries G = H beta - xi (the "hb" arrays
+// below), the data part of the first KKT residual row.
+//
+// Newton system of the iterate: Sigma, h, r = h and p = z = P_c^{-1} r (z
+// skipped when zb is null: CG never reads it before its first update), the
+// sums r.z and h.P^{-1}h
 template <typename TC>
 void newton_init(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
-                 const double* xi, double lam, double smu, double* sig1, double* sig2, double* hb_out,
+                 double lam, double smu, double* sig1, double* sig2, double* hb_out,
                  double* hz_out, TC* sig1c, TC* sig2c, const float* c, TC* rb, TC* rz, TC* zb, TC* zz, TC* pb,
                  TC* pz, long long n, double* partial, hipStream_t s, const double* dab = nullptr,
                  const double* daz = nullptr);
@@ -84,12 +87,13 @@ void set_f2d(double* db, double* dz, const float* eb, const float* ez, long long
 void fin_alpha(const double* partial, int nb, double* scal, int* flags, hipStream_t s);
 void fin_rz(const double* partial, int nb, double* scal, int* flags, hipStream_t s);
 
-// beta = 0, z = z0, nu = lam/2, and H beta = 0
-void ipm_init(double* beta, double* z, double* nu1, double* nu2, double* hbeta, long long n, double z0, double lam,
-              hipStream_t s);
-// residual parts of the iterate from a given H beta -> out8 (k_ipm_resid order;
-// out8[7] = sum log(S1 + S2) when logsum)
-void ipm_resid(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
+// beta = 0, z = z0, nu = lam/2, and G = -xi (H beta = 0)
+void ipm_init(double* beta, double* z, double* nu1, double* nu2, double* g, const double* xi, long long n, double z0,
+              double lam, hipStream_t s);
+// residual parts of the iterate -> out8 (k_ipm_resid order; out8[7] = sum
+// log(S1 + S2) when logsum).  hb holds G, or H beta when xi is set, which is
+// then replaced in place by G = H beta - xi.
+void ipm_resid(const double* beta, const double* z, const double* nu1, const double* nu2, double* hb,
                const double* xi, double lam, long long n, double* partial, double* out8, bool logsum, hipStream_t s);
 // step length: scal[S_AMAX] and scal[S_ALPHA_IPM] = min(1, tau * S_AMAX)
 // (the direction is read from db32/dz32 when set, else from db/dz)
@@ -104,15 +108,15 @@ void ipm_step(const double* beta, const double* z, const double* nu1, const doub
 // parts -> scal[S_RESID..]; with rres, scal[S_RESID + 9] = max (S1 + S2)
 // (|d_beta| + |d_z|), which times the FP64 epsilon bounds the rounding error
 // of the recovered H d_beta
-void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* xi,
-                 const double* db, const double* dz, const float* db32, const float* dz32, const double* hd,
+void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* db, const double* dz, const float* db32, const float* dz32, const double* hd,
                  const double* rres, const float* rres32, double lam, double smu, double* scal, long long n,
                  double* partial, bool logsum, hipStream_t s, const double* dab = nullptr,
                  const double* daz = nullptr);
 
 void add_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s);
 // FP32 restart of a further inner solve from H d_beta (hd): r32, z32 = p32 =
-// P_c^{-1} r and the sum r32.z32 -> *out (device)
+// P_c^{-1} r (z32 skipped when fzb is null) and the sum r32.z32 -> *out
+// (device)
 void ref_restart(const double* hb, const double* hz, const double* db, const double* dz, const double* hd,
                  const double* s1, const double* s2, const float* c, float* frb, float* frz, float* fzb, float* fzz,
                  float* fpb, float* fpz, long long n, double* partial, double* out, hipStream_t s);

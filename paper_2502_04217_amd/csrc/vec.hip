@@ -151,23 +151,6 @@ k_cg_update(T* __restrict__ xb, T* __restrict__ xz, const T* __restrict__ pb, co
   block_reduce_store<1>(&acc, &op, partial, 0);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_cg_pupdate(T* __restrict__ pb, T* __restrict__ pz, const T* __restrict__ zb, const T* __restrict__ zz,
-             const double* __restrict__ scal, const int* __restrict__ flags, long long n) {
-  CSIPM_ALIGN(pb);
-  CSIPM_ALIGN(pz);
-  CSIPM_ALIGN(zb);
-  CSIPM_ALIGN(zz);
-
-  if (flags[F_DONE]) return;
-  const T be = (T)scal[S_BETA];
-  CSIPM_PAIRS(n) {
-    pb[i] = zb[i] + be * pb[i];
-    pz[i] = zz[i] + be * pz[i];
-  }
-}
-
 // Conjugate residuals, direction step: p = z + beta p and q = w + beta q
 // (p = z, q = w on the first iteration), where w = K z came from the
 // K-apply; partial sums of q.P_c^{-1}q, the denominator of alpha.
@@ -418,10 +401,10 @@ k_fin_cr_zw(const double* partial, int nb, double* scal, int* flags, int first) 
 // ------------------------------------------------------------------- IPM --
 __global__ void __launch_bounds__(256)
 k_ipm_init(double* __restrict__ beta, double* __restrict__ z, double* __restrict__ nu1, double* __restrict__ nu2,
-           double* __restrict__ hbeta, long long n, double z0, double lam) {
+           double* __restrict__ g, const double* __restrict__ xi, long long n, double z0, double lam) {
   for (long long i = gtid(); i < n; i += gstride()) {
     beta[i] = 0.0;
-    hbeta[i] = 0.0;
+    g[i] = -xi[i];
     z[i] = z0;
     nu1[i] = 0.5 * lam;
     nu2[i] = 0.5 * lam;
@@ -456,7 +439,7 @@ __device__ __forceinline__ void resid_accumulate(double* v, double b, double s1,
 }
 __global__ void __launch_bounds__(256)
 k_ipm_resid(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
-            const double* __restrict__ nu2, const double* __restrict__ hb, const double* __restrict__ xi,
+            const double* __restrict__ nu2, double* __restrict__ hb, const double* __restrict__ xi,
             double lam, long long n, double* partial, int stride, int logsum) {
   CSIPM_ALIGN(beta);
   CSIPM_ALIGN(z);
@@ -469,7 +452,12 @@ k_ipm_resid(const double* __restrict__ beta, const double* __restrict__ z, const
   CSIPM_PAIRS(n) {
     const double b = beta[i], zz = z[i], a1 = nu1[i], a2 = nu2[i];
     const double s1 = zz + b, s2 = zz - b;
-    const double fb = hb[i] - xi[i] - a1 + a2;
+    double g = hb[i];
+    if (xi) {   // hb holds H beta: keep G = H beta - xi from here on
+      g -= xi[i];
+      hb[i] = g;
+    }
+    const double fb = g - a1 + a2;
     const double fz = lam - a1 - a2;
     resid_accumulate(v, b, s1, s2, a1, a2, fb, fz, logsum);
   }
@@ -523,9 +511,8 @@ __device__ __forceinline__ void corr_terms(double b, double zz, double a1, doubl
 template <typename TC>
 __global__ void __launch_bounds__(256)
 k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
-              const double* __restrict__ nu2, const double* __restrict__ hb, const double* __restrict__ xi,
-              double lam, double smu, double* __restrict__ sig1, double* __restrict__ sig2,
-              double* __restrict__ hb_out, double* __restrict__ hz_out, TC* __restrict__ sig1c,
+              const double* __restrict__ nu2, const double* __restrict__ hb, double lam, double smu,
+              double* __restrict__ sig1, double* __restrict__ sig2, double* __restrict__ hb_out, double* __restrict__ hz_out, TC* __restrict__ sig1c,
               TC* __restrict__ sig2c, const float* __restrict__ c, TC* __restrict__ rb, TC* __restrict__ rz,
               TC* __restrict__ zb, TC* __restrict__ zz, TC* __restrict__ pb, TC* __restrict__ pz, long long n,
               double* partial, const double* __restrict__ dab, const double* __restrict__ daz) {
@@ -534,7 +521,6 @@ k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, con
   CSIPM_ALIGN(nu1);
   CSIPM_ALIGN(nu2);
   CSIPM_ALIGN(hb);
-  CSIPM_ALIGN(xi);
   CSIPM_ALIGN(sig1);
   CSIPM_ALIGN(sig2);
   CSIPM_ALIGN(rb);
@@ -548,14 +534,13 @@ k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, con
   using D2 = cx<double>;
   using V = cx<TC>;
   const D2 *BE = (const D2*)beta, *ZV = (const D2*)z, *N1 = (const D2*)nu1, *N2 = (const D2*)nu2,
-           *HB = (const D2*)hb, *XI = (const D2*)xi;
+           *HB = (const D2*)hb;
   const float2* C2 = (const float2*)c;
   for (long long j = gtid(); j < n / 2; j += gstride()) {
-    const D2 b2 = BE[j], z2 = ZV[j], a1 = N1[j], a2 = N2[j], hh = HB[j], x2 = XI[j];
+    const D2 b2 = BE[j], z2 = ZV[j], a1 = N1[j], a2 = N2[j], hh = HB[j];
     const float2 cc = C2 ? C2[j] : make_float2(1.0f, 1.0f);
     const double bb[2] = {b2.re, b2.im}, zz2[2] = {z2.re, z2.im}, n1[2] = {a1.re, a1.im},
-                 n2[2] = {a2.re, a2.im}, hv[2] = {hh.re, hh.im}, xv[2] = {x2.re, x2.im},
-                 cv[2] = {(double)cc.x, (double)cc.y};
+                 n2[2] = {a2.re, a2.im}, hv[2] = {hh.re, hh.im}, cv[2] = {(double)cc.x, (double)cc.y};
     double g1o[2], g2o[2], h1o[2], h2o[2];
     TC r1o[2], r2o[2], w1o[2], w2o[2];
 #pragma unroll
@@ -569,10 +554,10 @@ k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, con
         corr_terms(bb[k], zz2[k], n1[k], n2[k], k ? dab[2 * j + 1] : dab[2 * j], k ? daz[2 * j + 1] : daz[2 * j],
                    c1, c2);
         const double u1 = (smu - c1) * i1, u2 = (smu - c2) * i2;
-        h1 = -(hv[k] - xv[k]) + (u1 - u2);
+        h1 = -hv[k] + (u1 - u2);
         h2 = -lam + (u1 + u2);
       } else {
-        h1 = -(hv[k] - xv[k]) + smu * (i1 - i2);
+        h1 = -hv[k] + smu * (i1 - i2);
         h2 = -lam + smu * (i1 + i2);
       }
       double u1, u2;
@@ -604,8 +589,10 @@ k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, con
     }
     ((V*)rb)[j] = {r1o[0], r1o[1]};
     ((V*)rz)[j] = {r2o[0], r2o[1]};
-    ((V*)zb)[j] = {w1o[0], w1o[1]};
-    ((V*)zz)[j] = {w2o[0], w2o[1]};
+    if (zb) {
+      ((V*)zb)[j] = {w1o[0], w1o[1]};
+      ((V*)zz)[j] = {w2o[0], w2o[1]};
+    }
     ((V*)pb)[j] = {w1o[0], w1o[1]};
     ((V*)pz)[j] = {w2o[0], w2o[1]};
   }
@@ -690,7 +677,7 @@ k_fin_step(const double* partial, int nb, double tau, double* scal) {
 // of the new iterate in k_ipm_resid's order.
 __global__ void __launch_bounds__(256)
 k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restrict__ nu1, double* __restrict__ nu2,
-              double* __restrict__ hbeta, const double* __restrict__ xi, const double* __restrict__ db,
+              double* __restrict__ hbeta, const double* __restrict__ db,
               const double* __restrict__ dz, const double* __restrict__ hd, const double* __restrict__ rres,
               const float* __restrict__ rres32, const float* __restrict__ db32, const float* __restrict__ dz32,
               double lam, double smu, const double* __restrict__ scal, long long n, double* partial, int stride,
@@ -699,10 +686,10 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
   double v[NRESID] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0, 0.0};
   using D2 = cx<double>;
   D2 *BE = (D2*)beta, *ZV = (D2*)z, *N1 = (D2*)nu1, *N2 = (D2*)nu2, *HBV = (D2*)hbeta;
-  const D2 *XI = (const D2*)xi, *DB = (const D2*)db, *DZ = (const D2*)dz, *W = (const D2*)(hd ? hd : rres);
+  const D2 *DB = (const D2*)db, *DZ = (const D2*)dz, *W = (const D2*)(hd ? hd : rres);
   const float2* W32 = (const float2*)rres32;
   for (long long j = gtid(); j < n / 2; j += gstride()) {
-    const D2 b2 = BE[j], z2 = ZV[j], a1 = N1[j], a2 = N2[j], h2 = HBV[j], x2 = XI[j];
+    const D2 b2 = BE[j], z2 = ZV[j], a1 = N1[j], a2 = N2[j], h2 = HBV[j];
     const D2 d1 = ld_dir(DB, db32, j), d2 = ld_dir(DZ, dz32, j);
     D2 w2;
     if (W32) {
@@ -712,7 +699,7 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
       w2 = W[j];
     }
     const double bb[2] = {b2.re, b2.im}, zv[2] = {z2.re, z2.im}, n1[2] = {a1.re, a1.im}, n2[2] = {a2.re, a2.im},
-                 hv[2] = {h2.re, h2.im}, xv[2] = {x2.re, x2.im}, dbv[2] = {d1.re, d1.im},
+                 hv[2] = {h2.re, h2.im}, dbv[2] = {d1.re, d1.im},
                  dzv[2] = {d2.re, d2.im}, wv[2] = {w2.re, w2.im};
     double bo[2], zo[2], n1o[2], n2o[2], ho[2];
     double c1[2] = {0.0, 0.0}, c2[2] = {0.0, 0.0};
@@ -728,8 +715,7 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
       if (hd) {
         u = wv[k];
       } else {
-        const double hrhs = dab ? -(hv[k] - xv[k]) + ((smu - c1[k]) * d.i1 - (smu - c2[k]) * d.i2)
-                                : -(hv[k] - xv[k]) + smu * (d.i1 - d.i2);
+        const double hrhs = dab ? -hv[k] + ((smu - c1[k]) * d.i1 - (smu - c2[k]) * d.i2) : -hv[k] + smu * (d.i1 - d.i2);
         u = (hrhs - wv[k]) - (d.g1 * (dbv[k] + dzv[k]) + d.g2 * (dbv[k] - dzv[k]));
         // rounding of the Sigma terms, here and in the Krylov recurrence
         // that produced r, scales like eps (S1 + S2)(|d_beta| + |d_z|)
@@ -739,7 +725,7 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
       const double m1 = n1[k] + a * d.dn1, m2 = n2[k] + a * d.dn2;
       const double hb = hv[k] + a * u;
       bo[k] = b; zo[k] = zz; n1o[k] = m1; n2o[k] = m2; ho[k] = hb;
-      resid_accumulate(v, b, zz + b, zz - b, m1, m2, hb - xv[k] - m1 + m2, lam - m1 - m2, logsum);
+      resid_accumulate(v, b, zz + b, zz - b, m1, m2, hb - m1 + m2, lam - m1 - m2, logsum);
     }
     BE[j] = {bo[0], bo[1]};
     ZV[j] = {zo[0], zo[1]};
@@ -753,33 +739,38 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
 
 // Generic multi-value finalize: out[q] = op_q over partial[q*stride + 0..nb);
 // all quantities are reduced in one sweep.
+// one block of kFinThreads: at most two partials per thread and quantity for
+// the VEC_MAX_BLOCKS partials of a vector pass, loaded before they are combined
+constexpr int kFinThreads = 1024;
 template <int NQ>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kFinThreads)
 k_fin_reduce(const double* partial, int nb, int stride, double* out, RedOps<NQ> ops) {
   double a[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) a[q] = ops.op[q] == RED_SUM ? 0.0 : ops.op[q] == RED_MAX ? -INFINITY : INFINITY;
-  for (int i = threadIdx.x; i < nb; i += 256)
+  for (int i = threadIdx.x; i < nb; i += kFinThreads) {
+    double x[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const double x = partial[q * stride + i];
-      a[q] = ops.op[q] == RED_SUM ? a[q] + x : ops.op[q] == RED_MAX ? fmax(a[q], x) : fmin(a[q], x);
-    }
-  __shared__ double red[NQ][4];
+    for (int q = 0; q < NQ; ++q) x[q] = partial[q * stride + i];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      a[q] = ops.op[q] == RED_SUM ? a[q] + x[q] : ops.op[q] == RED_MAX ? fmax(a[q], x[q]) : fmin(a[q], x[q]);
+  }
+  constexpr int W = kFinThreads / 64;
+  __shared__ double red[NQ][W];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const double x = ops.op[q] == RED_SUM ? wave_sum(a[q]) : ops.op[q] == RED_MAX ? wave_max(a[q]) : wave_min(a[q]);
     if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = x;
   }
   __syncthreads();
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      double x = red[q][0];
-      for (int w = 1; w < 4; ++w)
-        x = ops.op[q] == RED_SUM ? x + red[q][w] : ops.op[q] == RED_MAX ? fmax(x, red[q][w]) : fmin(x, red[q][w]);
-      out[q] = x;
-    }
+  if (threadIdx.x < NQ) {
+    const int q = threadIdx.x;
+    double x = red[q][0];
+    for (int w = 1; w < W; ++w)
+      x = ops.op[q] == RED_SUM ? x + red[q][w] : ops.op[q] == RED_MAX ? fmax(x, red[q][w]) : fmin(x, red[q][w]);
+    out[q] = x;
+  }
 }
 
 // ------------------------------------------------- mixed precision glue --
@@ -843,8 +834,10 @@ k_ref_restart(const double* __restrict__ hb, const double* __restrict__ hz, cons
     const float fb = (float)rb, fz = (float)rz, gb = (float)zb, gz = (float)zz;
     frb[i] = fb;
     frz[i] = fz;
-    fzb[i] = gb;
-    fzz[i] = gz;
+    if (fzb) {
+      fzb[i] = gb;
+      fzz[i] = gz;
+    }
     fpb[i] = gb;
     fpz[i] = gz;
     acc += (double)fb * (double)gb + (double)fz * (double)gz;
@@ -968,11 +961,6 @@ void cg_update(T* xb, T* xz, const T* pb, const T* pz, const T* qb, const T* qz,
   hipLaunchKernelGGL((k_cg_update<T>), VB, xb, xz, pb, pz, qb, qz, rb, rz, zb, zz, s1, s2, c, scal, flags, n,
                      partial, first ? 1 : 0);
 }
-template <typename T>
-void cg_pupdate(T* pb, T* pz, const T* zb, const T* zz, const double* scal, const int* flags, long long n,
-                hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_pupdate<T>), VB, pb, pz, zb, zz, scal, flags, n);
-}
 void fin_cg_start(const double* partial, int nb, int stride, double* scal, int* flags, double eta, double atol,
                   int maxit, int ref_slot, int from_slot, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_cg_init, dim3(1), dim3(256), 0, s, partial, nb, stride, scal, flags, eta, atol, maxit,
@@ -980,10 +968,10 @@ void fin_cg_start(const double* partial, int nb, int stride, double* scal, int* 
 }
 template <typename TC>
 void newton_init(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
-                 const double* xi, double lam, double smu, double* sig1, double* sig2, double* hb_out,
+                 double lam, double smu, double* sig1, double* sig2, double* hb_out,
                  double* hz_out, TC* sig1c, TC* sig2c, const float* c, TC* rb, TC* rz, TC* zb, TC* zz, TC* pb,
                  TC* pz, long long n, double* partial, hipStream_t s, const double* dab, const double* daz) {
-  hipLaunchKernelGGL((k_newton_init<TC>), VB, beta, z, nu1, nu2, hb, xi, lam, smu, sig1, sig2, hb_out, hz_out,
+  hipLaunchKernelGGL((k_newton_init<TC>), VB, beta, z, nu1, nu2, hb, lam, smu, sig1, sig2, hb_out, hz_out,
                      sig1c, sig2c, c, rb, rz, zb, zz, pb, pz, n, partial, dab, daz);
 }
 void set_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s) {
@@ -1024,17 +1012,17 @@ void fin_cr_zw(const double* partial, int nb, double* scal, int* flags, bool fir
 void fin_rz(const double* partial, int nb, double* scal, int* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(256), 0, s, partial, nb, scal, flags);
 }
-void ipm_init(double* beta, double* z, double* nu1, double* nu2, double* hbeta, long long n, double z0, double lam,
-              hipStream_t s) {
-  hipLaunchKernelGGL(k_ipm_init, VB, beta, z, nu1, nu2, hbeta, n, z0, lam);
+void ipm_init(double* beta, double* z, double* nu1, double* nu2, double* g, const double* xi, long long n, double z0,
+              double lam, hipStream_t s) {
+  hipLaunchKernelGGL(k_ipm_init, VB, beta, z, nu1, nu2, g, xi, n, z0, lam);
 }
 static const RedOps<NRESID> kResidRedOps{CSIPM_RESID_OPS};
 
-void ipm_resid(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
+void ipm_resid(const double* beta, const double* z, const double* nu1, const double* nu2, double* hb,
                const double* xi, double lam, long long n, double* partial, double* out8, bool logsum, hipStream_t s) {
   const int nb = vec_blocks(n);
   hipLaunchKernelGGL(k_ipm_resid, VB, beta, z, nu1, nu2, hb, xi, lam, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0);
-  hipLaunchKernelGGL((k_fin_reduce<NRESID>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out8,
+  hipLaunchKernelGGL((k_fin_reduce<NRESID>), dim3(1), dim3(kFinThreads), 0, s, partial, nb, VEC_MAX_BLOCKS, out8,
                      kResidRedOps);
 }
 void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* db,
@@ -1046,18 +1034,17 @@ void ipm_step(const double* beta, const double* z, const double* nu1, const doub
   hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(256), 0, s, partial, nb, tau, scal);
   if (dsdn) {
     RedOps<1> ops{{RED_SUM}};
-    hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(256), 0, s, partial + VEC_MAX_BLOCKS, nb, VEC_MAX_BLOCKS,
+    hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(kFinThreads), 0, s, partial + VEC_MAX_BLOCKS, nb, VEC_MAX_BLOCKS,
                        dsdn, ops);
   }
 }
-void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* xi,
-                 const double* db, const double* dz, const float* db32, const float* dz32, const double* hd,
+void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* db, const double* dz, const float* db32, const float* dz32, const double* hd,
                  const double* rres, const float* rres32, double lam, double smu, double* scal, long long n,
                  double* partial, bool logsum, hipStream_t s, const double* dab, const double* daz) {
   const int nb = vec_blocks(n);
-  hipLaunchKernelGGL(k_ipm_advance, VB, beta, z, nu1, nu2, hbeta, xi, db, dz, hd, rres, rres32, db32, dz32, lam, smu,
+  hipLaunchKernelGGL(k_ipm_advance, VB, beta, z, nu1, nu2, hbeta, db, dz, hd, rres, rres32, db32, dz32, lam, smu,
                      scal, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0, dab, daz);
-  hipLaunchKernelGGL((k_fin_reduce<NRESID>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, scal + S_RESID,
+  hipLaunchKernelGGL((k_fin_reduce<NRESID>), dim3(1), dim3(kFinThreads), 0, s, partial, nb, VEC_MAX_BLOCKS, scal + S_RESID,
                      kResidRedOps);
 }
 void add_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s) {
@@ -1072,11 +1059,11 @@ void ref_restart(const double* hb, const double* hz, const double* db, const dou
 }
 void fin_sum(const double* partial, int nb, double* out, hipStream_t s) {
   RedOps<1> ops{{RED_SUM}};
-  hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out, ops);
+  hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(kFinThreads), 0, s, partial, nb, VEC_MAX_BLOCKS, out, ops);
 }
 void fin_max(const double* partial, int nb, double* out, hipStream_t s) {
   RedOps<1> ops{{RED_MAX}};
-  hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out, ops);
+  hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(kFinThreads), 0, s, partial, nb, VEC_MAX_BLOCKS, out, ops);
 }
 template <typename T>
 void pinv_apply(const T* rb, const T* rz, T* zb, T* zz, const T* s1, const T* s2, const float* c, long long n,
@@ -1085,7 +1072,7 @@ void pinv_apply(const T* rb, const T* rz, T* zb, T* zz, const T* s1, const T* s2
   hipLaunchKernelGGL((k_pinv<T>), VB, rb, rz, zb, zz, s1, s2, c, n, partial);
   if (out) {
     RedOps<1> ops{{RED_SUM}};
-    hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out,
+    hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(kFinThreads), 0, s, partial, nb, VEC_MAX_BLOCKS, out,
                        ops);
   }
 }
@@ -1093,7 +1080,7 @@ void check_signal(const double* sig, const uint8_t* obs, long long n, double* pa
   const int nb = vec_blocks(n);
   hipLaunchKernelGGL(k_check_signal, VB, sig, obs, n, partial);
   RedOps<2> ops{{RED_SUM, RED_SUM}};
-  hipLaunchKernelGGL((k_fin_reduce<2>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out2, ops);
+  hipLaunchKernelGGL((k_fin_reduce<2>), dim3(1), dim3(kFinThreads), 0, s, partial, nb, VEC_MAX_BLOCKS, out2, ops);
 }
 void zero_fill(const double* sig, const uint8_t* obs, double* out, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_fill, VB, sig, obs, out, n);
@@ -1109,7 +1096,7 @@ void absmax(const double* a, long long n, double* partial, double* out, hipStrea
   const int nb = vec_blocks(n);
   hipLaunchKernelGGL(k_absmax, VB, a, n, partial);
   RedOps<1> ops{{RED_MAX}};
-  hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(256), 0, s, partial, nb, VEC_MAX_BLOCKS, out, ops);
+  hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(kFinThreads), 0, s, partial, nb, VEC_MAX_BLOCKS, out, ops);
 }
 void diag_h(const double* bm_ext, double* out_ext, int n1, int n2, int n3, double mfrac, hipStream_t s) {
   const long long n = (long long)n1 * n2 * n3;
@@ -1123,10 +1110,9 @@ void diag_h(const double* bm_ext, double* out_ext, int n1, int n2, int n3, doubl
                              const T*, const float*, const double*, const int*, long long, double*, bool,      \
                              hipStream_t);                                                                     \
   template void newton_init<T>(const double*, const double*, const double*, const double*, const double*,     \
-                               const double*, double, double, double*, double*, double*, double*, T*, T*,      \
+                               double, double, double*, double*, double*, double*, T*, T*,                     \
                                const float*, T*, T*, T*, T*, T*, T*, long long, double*, hipStream_t,          \
                                const double*, const double*);                                                  \
-  template void cg_pupdate<T>(T*, T*, const T*, const T*, const double*, const int*, long long, hipStream_t);  \
   template void cr_dir<T>(T*, T*, T*, T*, const T*, const T*, const T*, const T*, const T*, const T*,         \
                           const float*, const double*, const int*, long long, double*, bool, hipStream_t);   \
   template void car_dir<T>(T*, T*, T*, T*, T*, T*, const T*, const T*, const T*, const T*, const T*, const T*,  \
