@@ -98,6 +98,15 @@ def kernel_bytes(name, shape, learned):
         # beta, z, nu1, nu2, G, direction, H d_beta source (beta part) in; state and G out
         "ipm_advance+fin": 104 * n,
         "ipm_advance_d32+fin": 92 * n,
+        # the same with the next Newton system built from the new iterate:
+        # FP32 Sigma, r, p (ni32), also FP64 Sigma and h (ni32r), or FP64
+        # Sigma, r, p (ni64)
+        "ipm_advance_ni32+fin": 128 * n,
+        "ipm_advance_ni32r+fin": 160 * n,
+        "ipm_advance_ni64+fin": 152 * n,
+        "ipm_advance_d32_ni32+fin": 116 * n,
+        "ipm_advance_d32_ni32r+fin": 148 * n,
+        "ipm_advance_d32_ni64+fin": 140 * n,
         # beta, z, nu1, nu2, H beta, xi in, G = H beta - xi out (after a full H-apply)
         "ipm_resid+fin": 56 * n,
         "set_f2d": 24 * n,

@@ -633,9 +633,12 @@ enum HdSource {
 
 csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, double eta, const float* pcc,
                           int& cg_iters, int& refine_steps, bool& converged, bool capture, HdSource& src,
-                          const double* dab = nullptr, const double* daz = nullptr) {
+                          const double* dab = nullptr, const double* daz = nullptr, bool prebuilt = false) {
   const long long n = c->g.n;
   const int nbv = vec_blocks(n);
+  // a system built by the previous iterate update (prebuilt) left its r.z
+  // and h.P^{-1}h partials after the residual quantities
+  double* const part0 = prebuilt ? c->partV + (size_t)NRESID_Q * VEC_MAX_BLOCKS : c->partV;
   cg_iters = 0;
   refine_steps = 0;
   converged = false;
@@ -643,12 +646,13 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
   // CG starts from p = z and overwrites z before reading it
   const bool cg = o.krylov == CSIPM_KRYLOV_CG;
   if (o.precision == CSIPM_FP64) {
-    KT(c, "newton_init.f64",
-       newton_init<double>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->lambda, smu, c->sig1, c->sig2, nullptr,
-                           nullptr, nullptr, nullptr, pcc, c->rb, c->rz, cg ? nullptr : c->zb, c->zz, c->pb, c->pz,
-                           n, c->partV, c->s, dab, daz));
+    if (!prebuilt)
+      KT(c, "newton_init.f64",
+         newton_init<double>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->lambda, smu, c->sig1, c->sig2, nullptr,
+                             nullptr, nullptr, nullptr, pcc, c->rb, c->rz, cg ? nullptr : c->zb, c->zz, c->pb, c->pz,
+                             n, c->partV, c->s, dab, daz));
     KT(c, "fin_cg_start",
-       fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, eta, o.cg_atol, o.cg_max, -1, -1, c->s));
+       fin_cg_start(part0, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, eta, o.cg_atol, o.cg_max, -1, -1, c->s));
     PcgOut po;
     csipm_status st = krylov<double>(c, o.krylov, c->dxb, c->dxz, c->sig1, c->sig2, pcc, po, capture);
     cg_iters = po.iters;
@@ -665,18 +669,18 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
   const bool trusted = o.refine_trust > 0.0 && eta >= o.refine_trust;
   // (an unrefined system stores no FP64 Sigma or h: nothing reads them,
   // except the features of a capture)
-  KT(c, trusted ? "newton_init_noh.f32" : "newton_init.f32",
-     newton_init<float>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->lambda, smu,
-                        trusted && !capture ? nullptr : c->sig1, trusted && !capture ? nullptr : c->sig2,
-                        trusted ? nullptr : c->rhb, trusted ? nullptr : c->rhz,
-                        c->sig1f, c->sig2f, pcc, c->frb,
-                        c->frz, cg ? nullptr : c->fzb, c->fzz, c->fpb, c->fpz, n, c->partV, c->s, dab, daz));
+  if (!prebuilt)
+    KT(c, trusted ? "newton_init_noh.f32" : "newton_init.f32",
+       newton_init<float>(c->beta, c->z, c->nu1, c->nu2, c->hb, c->lambda, smu,
+                          trusted && !capture ? nullptr : c->sig1, trusted && !capture ? nullptr : c->sig2,
+                          trusted ? nullptr : c->rhb, trusted ? nullptr : c->rhz, c->sig1f, c->sig2f, pcc, c->frb,
+                          c->frz, cg ? nullptr : c->fzb, c->fzz, c->fpb, c->fpz, n, c->partV, c->s, dab, daz));
   // inner tolerance: half the remaining reduction, at most 1e-2, at least
   // refine_inner_rtol (what FP32 PCG can still reach)
   double inner = std::max(o.refine_inner_rtol, std::min(1e-2, 0.5 * eta));
   if (trusted) {
     KT(c, "fin_cg_start",
-       fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, inner, 0.0, o.cg_max, -1, -1, c->s));
+       fin_cg_start(part0, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, inner, 0.0, o.cg_max, -1, -1, c->s));
     PcgOut po;
     csipm_status st = krylov<float>(c, o.krylov, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, po, capture);
     if (st != CSIPM_OK) return st;
@@ -687,7 +691,7 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
   }
   src = HD_DIRECT;
   KT(c, "fin_cg_start",
-     fin_cg_start(c->partV, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, inner, 0.0, o.cg_max, S_REF0, -1, c->s));
+     fin_cg_start(part0, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, inner, 0.0, o.cg_max, S_REF0, -1, c->s));
   double target = 0.0, rnorm = 0.0;
   double prev_rnorm = INFINITY, prev_rinf = INFINITY;
   int first_iters = 0;
@@ -848,6 +852,12 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   inf.xi_inf = c->xi_inf;
   csipm_status result = CSIPM_NOT_CONVERGED;
   int prev_cg = 0;
+  // the Newton system the last iterate update built for the next iteration
+  // (see the step below): none, FP32 without / with the FP64 refinement
+  // arrays, or FP64
+  enum { NEXT_NONE = 0, NEXT_F32 = 1, NEXT_F32_REF = 2, NEXT_F64 = 3 };
+  int next_kind = NEXT_NONE;
+  double prev_rel = INFINITY;
   for (int it = 0;; ++it) {
     auto rel_of = [&](const Resid& q) { return std::max(std::max(q.fb, q.fz), q.cmax) / (1.0 + c->xi_inf); };
     double rel = rel_of(r);
@@ -862,6 +872,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       carried = 0;
       carry_err = 0.0;
       rel = rel_of(r);
+      next_kind = NEXT_NONE;   // built from the carried G
     }
     // a step along an inexact direction (the Newton solve stopped at its
     // precision floor or budget) that raised rel_kkt is undone, and the solve
@@ -922,6 +933,15 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     // iterate)
     const double relevant = learned ? r.relevant / (double)n : -1.0;
     const bool use_learned = learned && prev_cg >= o.pc_min_cg && relevant <= o.pc_max_relevant;
+    // the system the last update built applies when it was built for this
+    // precision and preconditioner
+    const bool trusted_now = o.refine_trust > 0.0 && eta >= o.refine_trust;
+    const bool prebuilt = !use_learned && !o.mehrotra &&
+                          (next_kind == NEXT_F64   ? o.precision == CSIPM_FP64
+                           : next_kind == NEXT_F32_REF ? o.precision == CSIPM_FP32
+                           : next_kind == NEXT_F32     ? o.precision == CSIPM_FP32 && trusted_now
+                                                       : false);
+    next_kind = NEXT_NONE;
     if (use_learned) {
       st = learned_correction(c, true);
       if (st != CSIPM_OK) return st;
@@ -949,7 +969,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
           ++inf.fallbacks;
         }
       } else {
-        e = newton_solve(c, o, tmu, eta, pc_fixed, a, b, conv, cap, src, dab, daz);
+        e = newton_solve(c, o, tmu, eta, pc_fixed, a, b, conv, cap, src, dab, daz, prebuilt);
         if (e != CSIPM_OK) return e;
         cgi += a;
         ref += b;
@@ -957,6 +977,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       return CSIPM_OK;
     };
     double smu = o.sigma * mu;
+    if (prebuilt) smu = c->hscal[S_SMU];   // the target the system was built for
     const double* dab = nullptr;
     const double* daz = nullptr;
     bool pred_conv = true;
@@ -1007,16 +1028,59 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     inf.cg_iters_total += cgi;
     inf.cg_iters_max = std::max(inf.cg_iters_max, cgi);
     inf.refine_steps_total += ref;
+    // The update also builds the next iteration's Newton system from the new
+    // iterate (saving newton_init's pass over the state) when that system is
+    // predictable: standard steps, CG, no capture, a converged solve (else
+    // the next iteration recomputes G first), the learned correction not
+    // expected (the relevant fraction of this iterate stands in for the
+    // next), and in FP32 the refinement expected or not from the last
+    // reduction of rel_kkt.  Its target sigma mu+ comes from the step's sums.
+    // A system the next iteration cannot use (another precision, a
+    // recomputed G, the correction after all) is rebuilt by newton_init.
+    int fuse_kind = NEXT_NONE;
+    if (!o.mehrotra && o.krylov == CSIPM_KRYLOV_CG && !c->cap_enable && conv && it + 1 < o.max_iter &&
+        carried + 1 < kExactEvery) {
+      const bool pred_learned = learned && cgi >= o.pc_min_cg && relevant <= o.pc_max_relevant;
+      const double rel_pred = rel * std::min(1.0, rel / prev_rel);
+      if (!pred_learned && rel_pred > o.tol) {
+        if (o.precision == CSIPM_FP64) {
+          fuse_kind = NEXT_F64;
+        } else if (o.refine_trust > 0.0 && std::min(o.cg_rtol, 0.1 * rel_pred) >= o.refine_trust) {
+          fuse_kind = NEXT_F32;
+        } else if (!approx && src != HD_RRES32) {   // (after an unrefined step G is recomputed first)
+          fuse_kind = NEXT_F32_REF;
+        }
+      }
+    }
+    NewtonOut<float> n32{};
+    NewtonOut<double> n64{};
+    NextSystem nx{nullptr, nullptr, pc_fixed};
+    if (fuse_kind == NEXT_F64) {
+      n64 = NewtonOut<double>{c->sig1, c->sig2, nullptr, nullptr, nullptr, nullptr,
+                              c->rb, c->rz, nullptr, nullptr, c->pb, c->pz};
+      nx.out64 = &n64;
+    } else if (fuse_kind != NEXT_NONE) {
+      const bool ref64 = fuse_kind == NEXT_F32_REF;
+      n32 = NewtonOut<float>{ref64 ? c->sig1 : nullptr, ref64 ? c->sig2 : nullptr, ref64 ? c->rhb : nullptr,
+                             ref64 ? c->rhz : nullptr, c->sig1f, c->sig2f, c->frb, c->frz, nullptr, nullptr,
+                             c->fpb, c->fpz};
+      nx.out32 = &n32;
+    }
     KT(c, d32b ? "ipm_ratio_d32+fin" : "ipm_ratio+fin",
        ipm_step(c->beta, c->z, c->nu1, c->nu2, c->dxb, c->dxz, d32b, d32z, smu, o.tau, n, c->partV, c->scal, c->s,
-                dab, daz));
-    KT(c, d32b ? "ipm_advance_d32+fin" : "ipm_advance+fin",
+                dab, daz, nullptr, fuse_kind != NEXT_NONE, r.csum, o.sigma));
+    static const char* const kAdvName[2][4] = {
+        {"ipm_advance+fin", "ipm_advance_ni32+fin", "ipm_advance_ni32r+fin", "ipm_advance_ni64+fin"},
+        {"ipm_advance_d32+fin", "ipm_advance_d32_ni32+fin", "ipm_advance_d32_ni32r+fin", "ipm_advance_d32_ni64+fin"}};
+    KT(c, kAdvName[d32b ? 1 : 0][fuse_kind],
        ipm_advance(c->beta, c->z, c->nu1, c->nu2, c->hb, c->dxb, c->dxz, d32b, d32z,
                    src == HD_DIRECT ? c->rb : nullptr, c->rb, src == HD_RRES32 ? c->frb : nullptr, lam, smu, c->scal, n,
-                   c->partV, learned, c->s, dab, daz));
+                   c->partV, learned, c->s, dab, daz, fuse_kind != NEXT_NONE ? &nx : nullptr));
     st = sync_scalars(c, "advance");
     if (st != CSIPM_OK) return st;
     r = read_resid(c);
+    next_kind = fuse_kind;
+    prev_rel = rel;
     exact = false;
     approx = approx || src == HD_RRES32;
     if (src == HD_RRES64) carry_err += 2.0 * DBL_EPSILON * c->hscal[S_ALPHA_IPM] * r.dscale;

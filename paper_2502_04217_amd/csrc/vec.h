@@ -31,6 +31,7 @@ enum ScalarSlot {
   S_REFRZ = 12,    // refinement: r32.P^{-1}r32, start of the next inner PCG
   S_REFINF = 13,   // refinement: max |r| of the FP64 residual
   S_DSDN = 14,     // predictor-corrector: sum ds.dnu of the affine direction
+  S_SMU = 15,      // target sigma mu of the next Newton system built with the step
   S_RESID = 16,    // IPM residual block, 10 values (k_ipm_resid order)
   S_SIG = 28,      // signal check: non-finite count, observed count
   S_MISC = 32,     // free scratch (32 values)
@@ -77,6 +78,24 @@ void fin_cg_start(const double* partial, int nb, int stride, double* scal, int* 
 // Newton system of the iterate: Sigma, h, r = h and p = z = P_c^{-1} r (z
 // skipped when zb is null: CG never reads it before its first update), the
 // sums r.z and h.P^{-1}h
+// Where a Newton system build writes: FP64 Sigma and h (each pair nullable),
+// Sigma in the Krylov precision TC (FP32 only), r = h, z = P_c^{-1} r (zb
+// nullable) and p = z.
+template <typename TC>
+struct NewtonOut {
+  double *sig1, *sig2, *hb_out, *hz_out;
+  TC *sig1c, *sig2c, *rb, *rz, *zb, *zz, *pb, *pz;
+};
+// the next Newton system built by ipm_advance: in FP32 (out32) or FP64
+// (out64) Krylov precision, with correction c (null: none)
+struct NextSystem {
+  const NewtonOut<float>* out32;
+  const NewtonOut<double>* out64;
+  const float* c;
+};
+// quantities reduced by ipm_advance (its partials of the next system follow)
+constexpr int NRESID_Q = 10;
+
 template <typename TC>
 void newton_init(const double* beta, const double* z, const double* nu1, const double* nu2, const double* hb,
                  double lam, double smu, double* sig1, double* sig2, double* hb_out,
@@ -99,19 +118,25 @@ void ipm_resid(const double* beta, const double* z, const double* nu1, const dou
 // (the direction is read from db32/dz32 when set, else from db/dz)
 // (dab, daz: the affine direction of a predictor-corrector step, for the
 // corrector's dnu; dsdn: where to put sum ds.dnu of this direction)
+// (next_smu: also scal[S_SMU] = sigma mu+, mu+ the duality measure after the
+// step from s0 = sum s.nu now and the sums of the ratio pass)
 void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* db,
               const double* dz, const float* db32, const float* dz32, double smu, double tau, long long n,
               double* partial, double* scal, hipStream_t s, const double* dab = nullptr, const double* daz = nullptr,
-              double* dsdn = nullptr);
-// iterate update with H beta carried along (H d_beta from hd when set, else
+              double* dsdn = nullptr, bool next_smu = false, double s0 = 0.0, double sigma = 0.0);
+// iterate update with G carried along (H d_beta from hd when set, else
 // from the Krylov residual: rres32 when set, else rres), and the new residual
 // parts -> scal[S_RESID..]; with rres, scal[S_RESID + 9] = max (S1 + S2)
 // (|d_beta| + |d_z|), which times the FP64 epsilon bounds the rounding error
 // of the recovered H d_beta
-void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* db, const double* dz, const float* db32, const float* dz32, const double* hd,
+// (next: also build the next Newton system from the new iterate at target
+// scal[S_SMU], as newton_init would with correction next->c; its r.z and
+// h.P^{-1}h partials stay in quantities NRESID_Q and NRESID_Q + 1 of partial)
+void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* db,
+                 const double* dz, const float* db32, const float* dz32, const double* hd,
                  const double* rres, const float* rres32, double lam, double smu, double* scal, long long n,
                  double* partial, bool logsum, hipStream_t s, const double* dab = nullptr,
-                 const double* daz = nullptr);
+                 const double* daz = nullptr, const NextSystem* next = nullptr);
 
 void add_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s);
 // FP32 restart of a further inner solve from H d_beta (hd): r32, z32 = p32 =

@@ -415,9 +415,11 @@ k_ipm_init(double* __restrict__ beta, double* __restrict__ z, double* __restrict
 // complementarity: [max|F_b|, max|F_z|, max s.nu, sum s.nu, max|beta|,
 // min(s, nu), count of non-finite values, sum log(S1 + S2) (when logsum is
 // set: the centring of the learned correction's first feature)].
-constexpr int NRESID = 10;
+constexpr int NRESID = NRESID_Q;
 #define CSIPM_RESID_OPS \
   {RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM, RED_SUM, RED_SUM, RED_MAX}
+#define CSIPM_RESID_OPS_NI \
+  {RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_MAX, RED_MIN, RED_SUM, RED_SUM, RED_SUM, RED_MAX, RED_SUM, RED_SUM}
 
 __device__ __forceinline__ void resid_accumulate(double* v, double b, double s1, double s2, double a1, double a2,
                                                  double fb, double fz, int logsum) {
@@ -504,6 +506,70 @@ __device__ __forceinline__ void corr_terms(double b, double zz, double a1, doubl
   c2 = d.ds2 * d.dn2;
 }
 
+// The Newton system at pair j from the state (b, z, nu1, nu2, G) of its two
+// coefficients: Sigma_j = nu_j / s_j, h (with the corrector terms c1, c2
+// when corr), r = h in TC, z = P_c^{-1} r in TC; adds r.z and h.P_c^{-1}h
+// (FP64) to acc[0], acc[1].
+template <typename TC>
+__device__ __forceinline__ void newton_pair(const NewtonOut<TC>& o, long long j, const double* bb, const double* zz2,
+                                            const double* n1, const double* n2, const double* hv, const double* cv,
+                                            double lam, double smu, bool corr, const double* c1v, const double* c2v,
+                                            double* acc) {
+  using D2 = cx<double>;
+  using V = cx<TC>;
+  double g1o[2], g2o[2], h1o[2], h2o[2];
+  TC r1o[2], r2o[2], w1o[2], w2o[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double s1 = zz2[k] + bb[k], s2 = zz2[k] - bb[k];
+    const double i1 = 1.0 / s1, i2 = 1.0 / s2;
+    const double g1 = n1[k] * i1, g2 = n2[k] * i2;
+    double h1, h2;
+    if (corr) {   // corrector of a predictor-corrector step
+      const double u1 = (smu - c1v[k]) * i1, u2 = (smu - c2v[k]) * i2;
+      h1 = -hv[k] + (u1 - u2);
+      h2 = -lam + (u1 + u2);
+    } else {
+      h1 = -hv[k] + smu * (i1 - i2);
+      h2 = -lam + smu * (i1 + i2);
+    }
+    double u1, u2;
+    pinv_block<double>(h1, h2, g1, g2, cv[k], u1, u2);
+    acc[1] += h1 * u1 + h2 * u2;
+    const TC r1 = (TC)h1, r2 = (TC)h2;
+    TC w1, w2;
+    if constexpr (std::is_same<TC, double>::value) {
+      w1 = u1;
+      w2 = u2;
+    } else {
+      pinv_block<TC>(r1, r2, (TC)g1, (TC)g2, cv[k], w1, w2);
+    }
+    acc[0] += (double)r1 * (double)w1 + (double)r2 * (double)w2;
+    g1o[k] = g1; g2o[k] = g2; h1o[k] = h1; h2o[k] = h2;
+    r1o[k] = r1; r2o[k] = r2; w1o[k] = w1; w2o[k] = w2;
+  }
+  if (o.sig1) {
+    ((D2*)o.sig1)[j] = {g1o[0], g1o[1]};
+    ((D2*)o.sig2)[j] = {g2o[0], g2o[1]};
+  }
+  if (o.hb_out) {
+    ((D2*)o.hb_out)[j] = {h1o[0], h1o[1]};
+    ((D2*)o.hz_out)[j] = {h2o[0], h2o[1]};
+  }
+  if constexpr (!std::is_same<TC, double>::value) {
+    ((V*)o.sig1c)[j] = {(TC)g1o[0], (TC)g1o[1]};
+    ((V*)o.sig2c)[j] = {(TC)g2o[0], (TC)g2o[1]};
+  }
+  ((V*)o.rb)[j] = {r1o[0], r1o[1]};
+  ((V*)o.rz)[j] = {r2o[0], r2o[1]};
+  if (o.zb) {
+    ((V*)o.zb)[j] = {w1o[0], w1o[1]};
+    ((V*)o.zz)[j] = {w2o[0], w2o[1]};
+  }
+  ((V*)o.pb)[j] = {w1o[0], w1o[1]};
+  ((V*)o.pz)[j] = {w2o[0], w2o[1]};
+}
+
 // Newton system and PCG start in one pass: Sigma_j = nu_j / s_j (FP64 when
 // sig1 is set, and in TC when sig1c is set), the right-hand side h (written
 // only when hb_out is set), r = h, z = P_c^{-1} r, p = z in the Krylov precision TC, and the
@@ -532,69 +598,22 @@ k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, con
 
   double acc[2] = {0.0, 0.0};
   using D2 = cx<double>;
-  using V = cx<TC>;
   const D2 *BE = (const D2*)beta, *ZV = (const D2*)z, *N1 = (const D2*)nu1, *N2 = (const D2*)nu2,
            *HB = (const D2*)hb;
   const float2* C2 = (const float2*)c;
+  const NewtonOut<TC> o{sig1, sig2, hb_out, hz_out, sig1c, sig2c, rb, rz, zb, zz, pb, pz};
   for (long long j = gtid(); j < n / 2; j += gstride()) {
     const D2 b2 = BE[j], z2 = ZV[j], a1 = N1[j], a2 = N2[j], hh = HB[j];
     const float2 cc = C2 ? C2[j] : make_float2(1.0f, 1.0f);
     const double bb[2] = {b2.re, b2.im}, zz2[2] = {z2.re, z2.im}, n1[2] = {a1.re, a1.im},
                  n2[2] = {a2.re, a2.im}, hv[2] = {hh.re, hh.im}, cv[2] = {(double)cc.x, (double)cc.y};
-    double g1o[2], g2o[2], h1o[2], h2o[2];
-    TC r1o[2], r2o[2], w1o[2], w2o[2];
+    double c1v[2] = {0.0, 0.0}, c2v[2] = {0.0, 0.0};
+    if (dab) {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const double s1 = zz2[k] + bb[k], s2 = zz2[k] - bb[k];
-      const double i1 = 1.0 / s1, i2 = 1.0 / s2;
-      const double g1 = n1[k] * i1, g2 = n2[k] * i2;
-      double h1, h2;
-      if (dab) {   // corrector of a predictor-corrector step
-        double c1, c2;
-        corr_terms(bb[k], zz2[k], n1[k], n2[k], k ? dab[2 * j + 1] : dab[2 * j], k ? daz[2 * j + 1] : daz[2 * j],
-                   c1, c2);
-        const double u1 = (smu - c1) * i1, u2 = (smu - c2) * i2;
-        h1 = -hv[k] + (u1 - u2);
-        h2 = -lam + (u1 + u2);
-      } else {
-        h1 = -hv[k] + smu * (i1 - i2);
-        h2 = -lam + smu * (i1 + i2);
-      }
-      double u1, u2;
-      pinv_block<double>(h1, h2, g1, g2, cv[k], u1, u2);
-      acc[1] += h1 * u1 + h2 * u2;
-      const TC r1 = (TC)h1, r2 = (TC)h2;
-      TC w1, w2;
-      if constexpr (std::is_same<TC, double>::value) {
-        w1 = u1;
-        w2 = u2;
-      } else {
-        pinv_block<TC>(r1, r2, (TC)g1, (TC)g2, cv[k], w1, w2);
-      }
-      acc[0] += (double)r1 * (double)w1 + (double)r2 * (double)w2;
-      g1o[k] = g1; g2o[k] = g2; h1o[k] = h1; h2o[k] = h2;
-      r1o[k] = r1; r2o[k] = r2; w1o[k] = w1; w2o[k] = w2;
+      for (int k = 0; k < 2; ++k)
+        corr_terms(bb[k], zz2[k], n1[k], n2[k], dab[2 * j + k], daz[2 * j + k], c1v[k], c2v[k]);
     }
-    if (sig1) {
-      ((D2*)sig1)[j] = {g1o[0], g1o[1]};
-      ((D2*)sig2)[j] = {g2o[0], g2o[1]};
-    }
-    if (hb_out) {
-      ((D2*)hb_out)[j] = {h1o[0], h1o[1]};
-      ((D2*)hz_out)[j] = {h2o[0], h2o[1]};
-    }
-    if constexpr (!std::is_same<TC, double>::value) {
-      ((V*)sig1c)[j] = {(TC)g1o[0], (TC)g1o[1]};
-      ((V*)sig2c)[j] = {(TC)g2o[0], (TC)g2o[1]};
-    }
-    ((V*)rb)[j] = {r1o[0], r1o[1]};
-    ((V*)rz)[j] = {r2o[0], r2o[1]};
-    if (zb) {
-      ((V*)zb)[j] = {w1o[0], w1o[1]};
-      ((V*)zz)[j] = {w2o[0], w2o[1]};
-    }
-    ((V*)pb)[j] = {w1o[0], w1o[1]};
-    ((V*)pz)[j] = {w2o[0], w2o[1]};
+    newton_pair<TC>(o, j, bb, zz2, n1, n2, hv, cv, lam, smu, dab != nullptr, c1v, c2v, acc);
   }
   const int ops[2] = {RED_SUM, RED_SUM};
   block_reduce_store<2>(acc, ops, partial, VEC_MAX_BLOCKS);
@@ -619,8 +638,8 @@ __global__ void __launch_bounds__(256)
 k_ipm_ratio(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
             const double* __restrict__ nu2, const double* __restrict__ db, const double* __restrict__ dz,
             const float* __restrict__ db32, const float* __restrict__ dz32, double smu, long long n,
-            double* partial, const double* __restrict__ dab, const double* __restrict__ daz, int dsdn) {
-  double v[2] = {INFINITY, 0.0};
+            double* partial, const double* __restrict__ dab, const double* __restrict__ daz, int dsdn, int musum) {
+  double v[4] = {INFINITY, 0.0, 0.0, 0.0};
   using D2 = cx<double>;
   for (long long j = gtid(); j < n / 2; j += gstride()) {
     const D2 b2 = ((const D2*)beta)[j], z2 = ((const D2*)z)[j], a1 = ((const D2*)nu1)[j], a2 = ((const D2*)nu2)[j],
@@ -641,9 +660,16 @@ k_ipm_ratio(const double* __restrict__ beta, const double* __restrict__ z, const
       if (d.dn1 < 0.0) v[0] = fmin(v[0], -n1[k] / d.dn1);
       if (d.dn2 < 0.0) v[0] = fmin(v[0], -n2[k] / d.dn2);
       if (dsdn) v[1] += d.ds1 * d.dn1 + d.ds2 * d.dn2;
+      if (musum) {   // s.nu after a step alpha: s.nu + alpha (s.dnu + nu.ds) + alpha^2 ds.dnu
+        v[2] += d.s1 * d.dn1 + n1[k] * d.ds1 + d.s2 * d.dn2 + n2[k] * d.ds2;
+        v[3] += d.ds1 * d.dn1 + d.ds2 * d.dn2;
+      }
     }
   }
-  if (dsdn) {
+  if (musum) {
+    const int ops[4] = {RED_MIN, RED_SUM, RED_SUM, RED_SUM};
+    block_reduce_store<4>(v, ops, partial, VEC_MAX_BLOCKS);
+  } else if (dsdn) {
     const int ops[2] = {RED_MIN, RED_SUM};
     block_reduce_store<2>(v, ops, partial, VEC_MAX_BLOCKS);
   } else {
@@ -652,18 +678,40 @@ k_ipm_ratio(const double* __restrict__ beta, const double* __restrict__ z, const
   }
 }
 
+// Step length: scal[S_AMAX] and scal[S_ALPHA_IPM].  With musum (quantities 2
+// and 3 of the ratio pass) also the next target scal[S_SMU] = sigma mu+ with
+// mu+ = (s0 + alpha s1 + alpha^2 s2) / (2n) the duality measure after the step.
 __global__ void __launch_bounds__(256)
-k_fin_step(const double* partial, int nb, double tau, double* scal) {
-  double a = INFINITY;
-  for (int i = threadIdx.x; i < nb; i += 256) a = fmin(a, partial[i]);
+k_fin_step(const double* partial, int nb, double tau, double* scal, int musum, double s0, double sigma,
+           double inv2n) {
+  double a = INFINITY, m1 = 0.0, m2 = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    a = fmin(a, partial[i]);
+    if (musum) {
+      m1 += partial[2 * VEC_MAX_BLOCKS + i];
+      m2 += partial[3 * VEC_MAX_BLOCKS + i];
+    }
+  }
   a = wave_min(a);
-  __shared__ double red[4];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  m1 = wave_sum(m1);
+  m2 = wave_sum(m2);
+  __shared__ double red[3][4];
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = m1;
+    red[2][threadIdx.x >> 6] = m2;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double amax = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+    const double amax = fmin(fmin(red[0][0], red[0][1]), fmin(red[0][2], red[0][3]));
+    const double alpha = fmin(1.0, tau * amax);
     scal[S_AMAX] = amax;
-    scal[S_ALPHA_IPM] = fmin(1.0, tau * amax);
+    scal[S_ALPHA_IPM] = alpha;
+    if (musum) {
+      const double s1 = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+      const double s2 = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
+      scal[S_SMU] = sigma * fmax(0.0, s0 + alpha * s1 + alpha * alpha * s2) * inv2n;
+    }
   }
 }
 
@@ -674,16 +722,22 @@ k_fin_step(const double* partial, int nb, double tau, double* scal) {
 // FP64, or rres32 from an FP32 solve taken without refinement),
 //   H d_beta = h_beta - r_beta - Sigma_1 (d_beta + d_z) - Sigma_2 (d_beta - d_z)
 // (the beta row of K in Sigma form).  The same pass reduces the residual parts
-// of the new iterate in k_ipm_resid's order.
+// of the new iterate in k_ipm_resid's order.  With NI it also builds the
+// next Newton system from the new iterate (newton_pair, target scal[S_SMU],
+// correction cn or none) and stores its r.z and h.P^{-1}h partials as
+// quantities NRESID and NRESID + 1.
+template <typename TC, bool NI>
 __global__ void __launch_bounds__(256)
 k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restrict__ nu1, double* __restrict__ nu2,
               double* __restrict__ hbeta, const double* __restrict__ db,
-              const double* __restrict__ dz, const double* __restrict__ hd, const double* __restrict__ rres,
-              const float* __restrict__ rres32, const float* __restrict__ db32, const float* __restrict__ dz32,
+              const double* __restrict__ dz, const double* __restrict__ hd, const double* rres,
+              const float* rres32, const float* __restrict__ db32, const float* __restrict__ dz32,
               double lam, double smu, const double* __restrict__ scal, long long n, double* partial, int stride,
-              int logsum, const double* __restrict__ dab, const double* __restrict__ daz) {
+              int logsum, const double* __restrict__ dab, const double* __restrict__ daz, NewtonOut<TC> no,
+              const float* __restrict__ cn) {
   const double a = scal[S_ALPHA_IPM];
-  double v[NRESID] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0, 0.0};
+  const double smu_next = NI ? scal[S_SMU] : 0.0;
+  double v[NRESID + 2] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   using D2 = cx<double>;
   D2 *BE = (D2*)beta, *ZV = (D2*)z, *N1 = (D2*)nu1, *N2 = (D2*)nu2, *HBV = (D2*)hbeta;
   const D2 *DB = (const D2*)db, *DZ = (const D2*)dz, *W = (const D2*)(hd ? hd : rres);
@@ -732,9 +786,20 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
     N1[j] = {n1o[0], n1o[1]};
     N2[j] = {n2o[0], n2o[1]};
     HBV[j] = {ho[0], ho[1]};
+    if constexpr (NI) {
+      const float2 cc = cn ? reinterpret_cast<const float2*>(cn)[j] : make_float2(1.0f, 1.0f);
+      const double cv[2] = {(double)cc.x, (double)cc.y}, zero[2] = {0.0, 0.0};
+      // (the r written here may be rres / rres32 itself: pair j was read above)
+      newton_pair<TC>(no, j, bo, zo, n1o, n2o, ho, cv, lam, smu_next, false, zero, zero, v + NRESID);
+    }
   }
-  const int ops[NRESID] = CSIPM_RESID_OPS;
-  block_reduce_store<NRESID>(v, ops, partial, stride);
+  if constexpr (NI) {
+    const int ops[NRESID + 2] = CSIPM_RESID_OPS_NI;
+    block_reduce_store<NRESID + 2>(v, ops, partial, stride);
+  } else {
+    const int ops[NRESID] = CSIPM_RESID_OPS;
+    block_reduce_store<NRESID>(v, ops, partial, stride);
+  }
 }
 
 // Generic multi-value finalize: out[q] = op_q over partial[q*stride + 0..nb);
@@ -1027,23 +1092,37 @@ void ipm_resid(const double* beta, const double* z, const double* nu1, const dou
 }
 void ipm_step(const double* beta, const double* z, const double* nu1, const double* nu2, const double* db,
               const double* dz, const float* db32, const float* dz32, double smu, double tau, long long n,
-              double* partial, double* scal, hipStream_t s, const double* dab, const double* daz, double* dsdn) {
+              double* partial, double* scal, hipStream_t s, const double* dab, const double* daz, double* dsdn,
+              bool next_smu, double s0, double sigma) {
   const int nb = vec_blocks(n);
   hipLaunchKernelGGL(k_ipm_ratio, VB, beta, z, nu1, nu2, db, dz, db32, dz32, smu, n, partial, dab, daz,
-                     dsdn ? 1 : 0);
-  hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(256), 0, s, partial, nb, tau, scal);
+                     dsdn ? 1 : 0, next_smu ? 1 : 0);
+  hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(256), 0, s, partial, nb, tau, scal, next_smu ? 1 : 0, s0, sigma,
+                     0.5 / (double)n);
   if (dsdn) {
     RedOps<1> ops{{RED_SUM}};
     hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(kFinThreads), 0, s, partial + VEC_MAX_BLOCKS, nb, VEC_MAX_BLOCKS,
                        dsdn, ops);
   }
 }
-void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* db, const double* dz, const float* db32, const float* dz32, const double* hd,
-                 const double* rres, const float* rres32, double lam, double smu, double* scal, long long n,
-                 double* partial, bool logsum, hipStream_t s, const double* dab, const double* daz) {
+void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* db, const double* dz,
+                 const float* db32, const float* dz32, const double* hd, const double* rres, const float* rres32,
+                 double lam, double smu, double* scal, long long n, double* partial, bool logsum, hipStream_t s,
+                 const double* dab, const double* daz, const NextSystem* next) {
   const int nb = vec_blocks(n);
-  hipLaunchKernelGGL(k_ipm_advance, VB, beta, z, nu1, nu2, hbeta, db, dz, hd, rres, rres32, db32, dz32, lam, smu,
-                     scal, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0, dab, daz);
+  if (next && next->out32) {
+    hipLaunchKernelGGL((k_ipm_advance<float, true>), VB, beta, z, nu1, nu2, hbeta, db, dz, hd, rres, rres32, db32,
+                       dz32, lam, smu, scal, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0, dab, daz, *next->out32,
+                       next->c);
+  } else if (next && next->out64) {
+    hipLaunchKernelGGL((k_ipm_advance<double, true>), VB, beta, z, nu1, nu2, hbeta, db, dz, hd, rres, rres32, db32,
+                       dz32, lam, smu, scal, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0, dab, daz, *next->out64,
+                       next->c);
+  } else {
+    hipLaunchKernelGGL((k_ipm_advance<float, false>), VB, beta, z, nu1, nu2, hbeta, db, dz, hd, rres, rres32, db32,
+                       dz32, lam, smu, scal, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0, dab, daz,
+                       NewtonOut<float>{}, nullptr);
+  }
   hipLaunchKernelGGL((k_fin_reduce<NRESID>), dim3(1), dim3(kFinThreads), 0, s, partial, nb, VEC_MAX_BLOCKS, scal + S_RESID,
                      kResidRedOps);
 }
