@@ -146,6 +146,15 @@ typedef struct {
                           Not from the paper, which leaves the barrier update
                           to its solver; Mehrotra's scheme on the condensed K
                           (eq. condensedkkt) with the rows of eq. kktmu. */
+  int build_next;      /* 1 (default): the iterate update of a standard CG
+                          step also builds the next Newton system (Sigma,
+                          h, r, p) from the new iterate, at the target sigma
+                          mu+ formed from the step's sums, when that system's
+                          precision and preconditioner can be foreseen; a
+                          system the next iteration cannot use is rebuilt.
+                          0: every system is built by its own pass.  Saves
+                          a pass over the state per iteration; the result
+                          differs from 0 only by rounding. */
 } csipm_options;
 
 typedef struct {

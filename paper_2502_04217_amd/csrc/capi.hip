@@ -504,6 +504,7 @@ void csipm_default_options(csipm_options* o) {
   o->pc_rho = 0.0;
   o->pc_max_relevant = 0.5;
   o->mehrotra = 0;
+  o->build_next = 1;
 }
 
 size_t csipm_workspace_bytes(int n1, int n2, int n3) {
@@ -815,6 +816,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       (o.pc != CSIPM_PC_PLAIN && o.pc != CSIPM_PC_LEARNED && o.pc != CSIPM_PC_SCALED) ||
       (o.krylov != CSIPM_KRYLOV_CG && o.krylov != CSIPM_KRYLOV_CR && o.krylov != CSIPM_KRYLOV_CAR) || !(o.pc_rho >= 0.0) ||
       !(o.pc_max_relevant >= 0.0 && o.pc_max_relevant <= 1.0) || (o.mehrotra != 0 && o.mehrotra != 1) ||
+      (o.build_next != 0 && o.build_next != 1) ||
       !(o.refine_trust >= 0.0 && o.refine_trust <= 1.0) || !(o.refine_inner_rtol > 0.0) || o.pc_min_cg < 0)
     return fail(c, CSIPM_EINVAL, "invalid options");
   if (o.pc == CSIPM_PC_LEARNED && !c->have_params) return fail(c, CSIPM_ESTATE, "learned preconditioner has no parameters");
@@ -1038,7 +1040,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     // A system the next iteration cannot use (another precision, a
     // recomputed G, the correction after all) is rebuilt by newton_init.
     int fuse_kind = NEXT_NONE;
-    if (!o.mehrotra && o.krylov == CSIPM_KRYLOV_CG && !c->cap_enable && conv && it + 1 < o.max_iter &&
+    if (o.build_next && !o.mehrotra && o.krylov == CSIPM_KRYLOV_CG && !c->cap_enable && conv && it + 1 < o.max_iter &&
         carried + 1 < kExactEvery) {
       const bool pred_learned = learned && cgi >= o.pc_min_cg && relevant <= o.pc_max_relevant;
       const double rel_pred = rel * std::min(1.0, rel / prev_rel);

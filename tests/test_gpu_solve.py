@@ -399,3 +399,45 @@ def test_predictor_corrector_parity(grid, precision):
         assert info["ipm_iters"] == ref.iters
         for a, b in zip(log[:4], ref.log[:4]):
             assert a["cg_iters"] == b["cg"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_next_system_build_matches_separate_pass(precision):
+    """The Newton system built by the iterate update (build_next = 1, target
+    sigma mu+ from the step's sums) against every system built by its own
+    pass (build_next = 0): the same interior-point count and solution up to
+    rounding, and in FP64 the same Krylov counts.  (In FP32 the last
+    systems are solved at the FP32 precision floor, where a rounding-level
+    change of the FP64 right-hand side moves the inner iteration counts;
+    the counts agree up to there.)  The timing records show that built
+    systems were used in the first case and none in the second."""
+    need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid64(1)
+    lam = ipm.lambda_rule(w.signal, w.observed)
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.set_lambda(lam)
+    out = {}
+    for bn in (1, 0):
+        pr.timing(True)
+        info = pr.solve(tol=PARITY_TOL, precision=precision, build_next=bn)
+        rep = {r["name"]: r["calls"] for r in pr.timing_report(0.0)}
+        pr.timing(False)
+        built = sum(c for nm, c in rep.items() if nm.startswith("ipm_advance") and "_ni" in nm)
+        ninit = sum(c for nm, c in rep.items() if nm.startswith("newton_init"))
+        out[bn] = (info, [r["cg_iters"] for r in pr.log()], pr.get(csipm.BETA).cpu().numpy(), built, ninit)
+        say("  build_next", bn, info["status_name"], info["ipm_iters"], out[bn][1], "built", built, "newton_init", ninit)
+    (i1, cg1, b1, built1, ninit1), (i0, cg0, b0, built0, ninit0) = out[1], out[0]
+    assert i1["status"] == 0 and i0["status"] == 0
+    assert i1["ipm_iters"] == i0["ipm_iters"]
+    if precision == 0:
+        assert cg1 == cg0
+    else:
+        assert cg1[:8] == cg0[:8]
+    assert built0 == 0 and ninit0 == i0["ipm_iters"]
+    assert built1 > 0 and ninit1 < i1["ipm_iters"] and ninit1 + built1 >= i1["ipm_iters"]
+    err = rel2(b1, b0)
+    say("  rel diff", err)
+    assert err <= (1e-12 if precision == 0 else 1e-7)
+    with pytest.raises(csipm.CsipmError):
+        pr.solve(tol=1e-6, build_next=2)
