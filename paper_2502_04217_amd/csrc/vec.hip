@@ -574,7 +574,7 @@ __device__ __forceinline__ void newton_pair(const NewtonOut<TC>& o, long long j,
 // sig1 is set, and in TC when sig1c is set), the right-hand side h (written
 // only when hb_out is set), r = h, z = P_c^{-1} r, p = z in the Krylov precision TC, and the
 // partial sums r.z (in TC) and h.P_c^{-1}h (in FP64).  x0 = 0 is implicit.
-template <typename TC>
+template <typename TC, bool CORR>
 __global__ void __launch_bounds__(256)
 k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
               const double* __restrict__ nu2, const double* __restrict__ hb, double lam, double smu,
@@ -608,12 +608,12 @@ k_newton_init(const double* __restrict__ beta, const double* __restrict__ z, con
     const double bb[2] = {b2.re, b2.im}, zz2[2] = {z2.re, z2.im}, n1[2] = {a1.re, a1.im},
                  n2[2] = {a2.re, a2.im}, hv[2] = {hh.re, hh.im}, cv[2] = {(double)cc.x, (double)cc.y};
     double c1v[2] = {0.0, 0.0}, c2v[2] = {0.0, 0.0};
-    if (dab) {
+    if constexpr (CORR) {
 #pragma unroll
       for (int k = 0; k < 2; ++k)
         corr_terms(bb[k], zz2[k], n1[k], n2[k], dab[2 * j + k], daz[2 * j + k], c1v[k], c2v[k]);
     }
-    newton_pair<TC>(o, j, bb, zz2, n1, n2, hv, cv, lam, smu, dab != nullptr, c1v, c2v, acc);
+    newton_pair<TC>(o, j, bb, zz2, n1, n2, hv, cv, lam, smu, CORR, c1v, c2v, acc);
   }
   const int ops[2] = {RED_SUM, RED_SUM};
   block_reduce_store<2>(acc, ops, partial, VEC_MAX_BLOCKS);
@@ -630,46 +630,48 @@ __device__ __forceinline__ cx<double> ld_dir(const cx<double>* d64, const float*
 }
 
 // Largest step keeping s and nu positive along (db, dz, dnu1, dnu2); with
-// dab set (a corrector) dnu carries the affine direction's second-order
-// terms; with dsdn set, also sum ds.dnu (quantity 1 of the partials: for the
-// affine direction, mu at its step alpha is ((1 - alpha) s.nu + alpha^2
-// ds.dnu) / 2n).
+// CORR (a corrector) dnu carries the affine direction's second-order terms;
+// with DSDN also sum ds.dnu (quantity 1 of the partials: for the affine
+// direction, mu at its step alpha is ((1 - alpha) s.nu + alpha^2 ds.dnu) /
+// 2n); with MUSUM the sums s.dnu + nu.ds and ds.dnu (quantities 2 and 3)
+// that give mu after the step.  (D32: the direction is read in FP32.)
+template <bool D32, bool CORR, bool DSDN, bool MUSUM>
 __global__ void __launch_bounds__(256)
 k_ipm_ratio(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
             const double* __restrict__ nu2, const double* __restrict__ db, const double* __restrict__ dz,
             const float* __restrict__ db32, const float* __restrict__ dz32, double smu, long long n,
-            double* partial, const double* __restrict__ dab, const double* __restrict__ daz, int dsdn, int musum) {
+            double* partial, const double* __restrict__ dab, const double* __restrict__ daz) {
   double v[4] = {INFINITY, 0.0, 0.0, 0.0};
   using D2 = cx<double>;
   for (long long j = gtid(); j < n / 2; j += gstride()) {
     const D2 b2 = ((const D2*)beta)[j], z2 = ((const D2*)z)[j], a1 = ((const D2*)nu1)[j], a2 = ((const D2*)nu2)[j],
-             d1 = ld_dir((const D2*)db, db32, j), d2 = ld_dir((const D2*)dz, dz32, j);
+             d1 = ld_dir((const D2*)db, D32 ? db32 : nullptr, j), d2 = ld_dir((const D2*)dz, D32 ? dz32 : nullptr, j);
     const double bb[2] = {b2.re, b2.im}, zv[2] = {z2.re, z2.im}, n1[2] = {a1.re, a1.im}, n2[2] = {a2.re, a2.im},
                  dbv[2] = {d1.re, d1.im}, dzv[2] = {d2.re, d2.im};
     double c1[2] = {0.0, 0.0}, c2[2] = {0.0, 0.0};
-    if (dab) {
+    if constexpr (CORR) {
       const D2 e1 = ((const D2*)dab)[j], e2 = ((const D2*)daz)[j];
       corr_terms(bb[0], zv[0], n1[0], n2[0], e1.re, e2.re, c1[0], c2[0]);
       corr_terms(bb[1], zv[1], n1[1], n2[1], e1.im, e2.im, c1[1], c2[1]);
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const IpmDir d = ipm_dir(bb[k], zv[k], n1[k], n2[k], dbv[k], dzv[k], smu, c1[k], c2[k], dab != nullptr);
+      const IpmDir d = ipm_dir(bb[k], zv[k], n1[k], n2[k], dbv[k], dzv[k], smu, c1[k], c2[k], CORR);
       if (d.ds1 < 0.0) v[0] = fmin(v[0], -d.s1 / d.ds1);
       if (d.ds2 < 0.0) v[0] = fmin(v[0], -d.s2 / d.ds2);
       if (d.dn1 < 0.0) v[0] = fmin(v[0], -n1[k] / d.dn1);
       if (d.dn2 < 0.0) v[0] = fmin(v[0], -n2[k] / d.dn2);
-      if (dsdn) v[1] += d.ds1 * d.dn1 + d.ds2 * d.dn2;
-      if (musum) {   // s.nu after a step alpha: s.nu + alpha (s.dnu + nu.ds) + alpha^2 ds.dnu
+      if constexpr (DSDN) v[1] += d.ds1 * d.dn1 + d.ds2 * d.dn2;
+      if constexpr (MUSUM) {   // s.nu after a step alpha: s.nu + alpha (s.dnu + nu.ds) + alpha^2 ds.dnu
         v[2] += d.s1 * d.dn1 + n1[k] * d.ds1 + d.s2 * d.dn2 + n2[k] * d.ds2;
         v[3] += d.ds1 * d.dn1 + d.ds2 * d.dn2;
       }
     }
   }
-  if (musum) {
+  if constexpr (MUSUM) {
     const int ops[4] = {RED_MIN, RED_SUM, RED_SUM, RED_SUM};
     block_reduce_store<4>(v, ops, partial, VEC_MAX_BLOCKS);
-  } else if (dsdn) {
+  } else if constexpr (DSDN) {
     const int ops[2] = {RED_MIN, RED_SUM};
     block_reduce_store<2>(v, ops, partial, VEC_MAX_BLOCKS);
   } else {
@@ -725,8 +727,12 @@ k_fin_step(const double* partial, int nb, double tau, double* scal, int musum, d
 // of the new iterate in k_ipm_resid's order.  With NI it also builds the
 // next Newton system from the new iterate (newton_pair, target scal[S_SMU],
 // correction cn or none) and stores its r.z and h.P^{-1}h partials as
-// quantities NRESID and NRESID + 1.
-template <typename TC, bool NI>
+// quantities NRESID and NRESID + 1.  HDM selects the source of H d_beta:
+// ADV_RRES64 (the FP64 Krylov residual), ADV_DIRECT (hd) or ADV_RRES32 (the
+// FP32 residual, with the direction read in FP32); CORR adds the corrector
+// terms of a predictor-corrector step.
+enum { ADV_RRES64 = 0, ADV_DIRECT = 1, ADV_RRES32 = 2 };
+template <typename TC, bool NI, int HDM, bool CORR>
 __global__ void __launch_bounds__(256)
 k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restrict__ nu1, double* __restrict__ nu2,
               double* __restrict__ hbeta, const double* __restrict__ db,
@@ -740,13 +746,14 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
   double v[NRESID + 2] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   using D2 = cx<double>;
   D2 *BE = (D2*)beta, *ZV = (D2*)z, *N1 = (D2*)nu1, *N2 = (D2*)nu2, *HBV = (D2*)hbeta;
-  const D2 *DB = (const D2*)db, *DZ = (const D2*)dz, *W = (const D2*)(hd ? hd : rres);
+  const D2 *DB = (const D2*)db, *DZ = (const D2*)dz, *W = (const D2*)(HDM == ADV_DIRECT ? hd : rres);
   const float2* W32 = (const float2*)rres32;
+  constexpr bool d32 = HDM == ADV_RRES32;
   for (long long j = gtid(); j < n / 2; j += gstride()) {
     const D2 b2 = BE[j], z2 = ZV[j], a1 = N1[j], a2 = N2[j], h2 = HBV[j];
-    const D2 d1 = ld_dir(DB, db32, j), d2 = ld_dir(DZ, dz32, j);
+    const D2 d1 = ld_dir(DB, d32 ? db32 : nullptr, j), d2 = ld_dir(DZ, d32 ? dz32 : nullptr, j);
     D2 w2;
-    if (W32) {
+    if constexpr (d32) {
       const float2 f = W32[j];
       w2 = {(double)f.x, (double)f.y};
     } else {
@@ -757,19 +764,19 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
                  dzv[2] = {d2.re, d2.im}, wv[2] = {w2.re, w2.im};
     double bo[2], zo[2], n1o[2], n2o[2], ho[2];
     double c1[2] = {0.0, 0.0}, c2[2] = {0.0, 0.0};
-    if (dab) {
+    if constexpr (CORR) {
       const D2 e1 = ((const D2*)dab)[j], e2 = ((const D2*)daz)[j];
       corr_terms(bb[0], zv[0], n1[0], n2[0], e1.re, e2.re, c1[0], c2[0]);
       corr_terms(bb[1], zv[1], n1[1], n2[1], e1.im, e2.im, c1[1], c2[1]);
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const IpmDir d = ipm_dir(bb[k], zv[k], n1[k], n2[k], dbv[k], dzv[k], smu, c1[k], c2[k], dab != nullptr);
+      const IpmDir d = ipm_dir(bb[k], zv[k], n1[k], n2[k], dbv[k], dzv[k], smu, c1[k], c2[k], CORR);
       double u;
-      if (hd) {
+      if constexpr (HDM == ADV_DIRECT) {
         u = wv[k];
       } else {
-        const double hrhs = dab ? -hv[k] + ((smu - c1[k]) * d.i1 - (smu - c2[k]) * d.i2) : -hv[k] + smu * (d.i1 - d.i2);
+        const double hrhs = CORR ? -hv[k] + ((smu - c1[k]) * d.i1 - (smu - c2[k]) * d.i2) : -hv[k] + smu * (d.i1 - d.i2);
         u = (hrhs - wv[k]) - (d.g1 * (dbv[k] + dzv[k]) + d.g2 * (dbv[k] - dzv[k]));
         // rounding of the Sigma terms, here and in the Krylov recurrence
         // that produced r, scales like eps (S1 + S2)(|d_beta| + |d_z|)
@@ -1036,8 +1043,12 @@ void newton_init(const double* beta, const double* z, const double* nu1, const d
                  double lam, double smu, double* sig1, double* sig2, double* hb_out,
                  double* hz_out, TC* sig1c, TC* sig2c, const float* c, TC* rb, TC* rz, TC* zb, TC* zz, TC* pb,
                  TC* pz, long long n, double* partial, hipStream_t s, const double* dab, const double* daz) {
-  hipLaunchKernelGGL((k_newton_init<TC>), VB, beta, z, nu1, nu2, hb, lam, smu, sig1, sig2, hb_out, hz_out,
-                     sig1c, sig2c, c, rb, rz, zb, zz, pb, pz, n, partial, dab, daz);
+  if (dab)   // corrector of a predictor-corrector step
+    hipLaunchKernelGGL((k_newton_init<TC, true>), VB, beta, z, nu1, nu2, hb, lam, smu, sig1, sig2, hb_out, hz_out,
+                       sig1c, sig2c, c, rb, rz, zb, zz, pb, pz, n, partial, dab, daz);
+  else
+    hipLaunchKernelGGL((k_newton_init<TC, false>), VB, beta, z, nu1, nu2, hb, lam, smu, sig1, sig2, hb_out, hz_out,
+                       sig1c, sig2c, c, rb, rz, zb, zz, pb, pz, n, partial, dab, daz);
 }
 void set_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_set_f2d, VB, db, dz, eb, ez, n);
@@ -1095,8 +1106,25 @@ void ipm_step(const double* beta, const double* z, const double* nu1, const doub
               double* partial, double* scal, hipStream_t s, const double* dab, const double* daz, double* dsdn,
               bool next_smu, double s0, double sigma) {
   const int nb = vec_blocks(n);
-  hipLaunchKernelGGL(k_ipm_ratio, VB, beta, z, nu1, nu2, db, dz, db32, dz32, smu, n, partial, dab, daz,
-                     dsdn ? 1 : 0, next_smu ? 1 : 0);
+  const bool d32 = db32 != nullptr, corr = dab != nullptr;
+#define CSIPM_RATIO(B, C, D)                                                                                     \
+  do {                                                                                                           \
+    if (d32)                                                                                                     \
+      hipLaunchKernelGGL((k_ipm_ratio<true, B, C, D>), VB, beta, z, nu1, nu2, db, dz, db32, dz32, smu, n, partial, \
+                         dab, daz);                                                                              \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_ipm_ratio<false, B, C, D>), VB, beta, z, nu1, nu2, db, dz, db32, dz32, smu, n,        \
+                         partial, dab, daz);                                                                     \
+  } while (0)
+  if (next_smu)   // (standard steps only)
+    CSIPM_RATIO(false, false, true);
+  else if (dsdn)  // (the affine direction of a predictor-corrector step)
+    CSIPM_RATIO(false, true, false);
+  else if (corr)
+    CSIPM_RATIO(true, false, false);
+  else
+    CSIPM_RATIO(false, false, false);
+#undef CSIPM_RATIO
   hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(256), 0, s, partial, nb, tau, scal, next_smu ? 1 : 0, s0, sigma,
                      0.5 / (double)n);
   if (dsdn) {
@@ -1110,19 +1138,35 @@ void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbet
                  double lam, double smu, double* scal, long long n, double* partial, bool logsum, hipStream_t s,
                  const double* dab, const double* daz, const NextSystem* next) {
   const int nb = vec_blocks(n);
-  if (next && next->out32) {
-    hipLaunchKernelGGL((k_ipm_advance<float, true>), VB, beta, z, nu1, nu2, hbeta, db, dz, hd, rres, rres32, db32,
-                       dz32, lam, smu, scal, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0, dab, daz, *next->out32,
-                       next->c);
+  const int hdm = hd ? ADV_DIRECT : rres32 ? ADV_RRES32 : ADV_RRES64;
+  // (an FP32 direction comes only with the FP32 residual)
+  const int ls = logsum ? 1 : 0;
+#define CSIPM_ADV(TC, NI, HDM, CORR, NO, CN)                                                                        \
+  hipLaunchKernelGGL((k_ipm_advance<TC, NI, HDM, CORR>), VB, beta, z, nu1, nu2, hbeta, db, dz, hd, rres, rres32,    \
+                     db32, dz32, lam, smu, scal, n, partial, VEC_MAX_BLOCKS, ls, dab, daz, NO, CN)
+  if (next && next->out32) {   // (standard steps: no corrector terms)
+    if (hdm == ADV_DIRECT)
+      CSIPM_ADV(float, true, ADV_DIRECT, false, *next->out32, next->c);
+    else
+      CSIPM_ADV(float, true, ADV_RRES32, false, *next->out32, next->c);
   } else if (next && next->out64) {
-    hipLaunchKernelGGL((k_ipm_advance<double, true>), VB, beta, z, nu1, nu2, hbeta, db, dz, hd, rres, rres32, db32,
-                       dz32, lam, smu, scal, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0, dab, daz, *next->out64,
-                       next->c);
+    CSIPM_ADV(double, true, ADV_RRES64, false, *next->out64, next->c);
+  } else if (dab) {
+    if (hdm == ADV_DIRECT)
+      CSIPM_ADV(float, false, ADV_DIRECT, true, NewtonOut<float>{}, nullptr);
+    else if (hdm == ADV_RRES32)
+      CSIPM_ADV(float, false, ADV_RRES32, true, NewtonOut<float>{}, nullptr);
+    else
+      CSIPM_ADV(float, false, ADV_RRES64, true, NewtonOut<float>{}, nullptr);
   } else {
-    hipLaunchKernelGGL((k_ipm_advance<float, false>), VB, beta, z, nu1, nu2, hbeta, db, dz, hd, rres, rres32, db32,
-                       dz32, lam, smu, scal, n, partial, VEC_MAX_BLOCKS, logsum ? 1 : 0, dab, daz,
-                       NewtonOut<float>{}, nullptr);
+    if (hdm == ADV_DIRECT)
+      CSIPM_ADV(float, false, ADV_DIRECT, false, NewtonOut<float>{}, nullptr);
+    else if (hdm == ADV_RRES32)
+      CSIPM_ADV(float, false, ADV_RRES32, false, NewtonOut<float>{}, nullptr);
+    else
+      CSIPM_ADV(float, false, ADV_RRES64, false, NewtonOut<float>{}, nullptr);
   }
+#undef CSIPM_ADV
   hipLaunchKernelGGL((k_fin_reduce<NRESID>), dim3(1), dim3(kFinThreads), 0, s, partial, nb, VEC_MAX_BLOCKS, scal + S_RESID,
                      kResidRedOps);
 }
