@@ -422,11 +422,13 @@ struct StridedGeom {
 // 64 KB for axis 2.  Pencils with odd factors take mixed_e elements.
 constexpr int strided_e(int w, int L, int axis, int dir) {
   if (odd_part(L) != 1) return mixed_e(L);
-  const int e = ((w == 16 && axis == 2) || (w == 8 && axis == 1 && dir < 0)) ? 8 : 16;
+  const int e = ((w == 16 && axis == 2) || (w == 8 && axis == 1 && dir < 0) ||
+                   (w == 16 && axis == 1 && dir > 0 && L >= 512))
+                    ? 8 : 16;
   return L < e ? L : e;
 }
-constexpr int strided_lds(int w, int axis, int dir) {
-  return axis == 2 ? 65536 : (w == 16 && dir > 0 ? 65536 : 131072);
+constexpr int strided_lds(int w, int axis, int dir, int L) {
+  return axis == 2 ? 65536 : (w == 16 && dir > 0 && L < 512 ? 65536 : 131072);
 }
 // TM is the power of two that the LDS budget gives (at most 64), raised
 // until each access is a run of at least 128 contiguous bytes (a whole
@@ -434,7 +436,7 @@ constexpr int strided_lds(int w, int axis, int dir) {
 // 160 KB of LDS and 1024 threads.
 constexpr int strided_tm(int w, int L, int axis, int dir) {
   const int nt = L / strided_e(w, L, axis, dir);
-  int tm = strided_lds(w, axis, dir) / (L * w);
+  int tm = strided_lds(w, axis, dir, L) / (L * w);
   if (tm > 64) tm = 64;
   if (tm < 1) tm = 1;
   int p = 1;
