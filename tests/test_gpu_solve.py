@@ -401,8 +401,9 @@ def test_predictor_corrector_parity(grid, precision):
             assert a["cg_iters"] == b["cg"]
 
 
+@pytest.mark.parametrize("pc", ["plain", "scaled"])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_next_system_build_matches_separate_pass(precision):
+def test_next_system_build_matches_separate_pass(precision, pc):
     """The Newton system built by the iterate update (build_next = 1, target
     sigma mu+ from the step's sums) against every system built by its own
     pass (build_next = 0): the same interior-point count and solution up to
@@ -420,13 +421,14 @@ def test_next_system_build_matches_separate_pass(precision):
     out = {}
     for bn in (1, 0):
         pr.timing(True)
-        info = pr.solve(tol=PARITY_TOL, precision=precision, build_next=bn)
+        info = pr.solve(tol=PARITY_TOL, precision=precision, build_next=bn,
+                        pc=csipm.PC_SCALED if pc == "scaled" else csipm.PC_PLAIN)
         rep = {r["name"]: r["calls"] for r in pr.timing_report(0.0)}
         pr.timing(False)
         built = sum(c for nm, c in rep.items() if nm.startswith("ipm_advance") and "_ni" in nm)
         ninit = sum(c for nm, c in rep.items() if nm.startswith("newton_init"))
         out[bn] = (info, [r["cg_iters"] for r in pr.log()], pr.get(csipm.BETA).cpu().numpy(), built, ninit)
-        say("  build_next", bn, info["status_name"], info["ipm_iters"], out[bn][1], "built", built, "newton_init", ninit)
+        say("  build_next", pc, bn, info["status_name"], info["ipm_iters"], out[bn][1], "built", built, "newton_init", ninit)
     (i1, cg1, b1, built1, ninit1), (i0, cg0, b0, built0, ninit0) = out[1], out[0]
     assert i1["status"] == 0 and i0["status"] == 0
     assert i1["ipm_iters"] == i0["ipm_iters"]
@@ -441,3 +443,28 @@ def test_next_system_build_matches_separate_pass(precision):
     assert err <= (1e-12 if precision == 0 else 1e-7)
     with pytest.raises(csipm.CsipmError):
         pr.solve(tol=1e-6, build_next=2)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_ignores_prior_memory_contents(precision):
+    """A solve reads nothing it did not write: the same FP32 / FP64 solve on a
+    fresh problem whose device memory first held NaN (through torch's caching
+    allocator) gives bit-identical iterates, counts and residuals."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid64(1)
+    lam = ipm.lambda_rule(w.signal, w.observed)
+    runs = []
+    for fill in (0.0, float("nan")):
+        # occupy and poison the memory the next problem's workspace is carved from
+        junk = torch.full((64 << 20,), fill, dtype=torch.float64, device="cuda")
+        del junk
+        pr = csipm.Problem(w.signal, w.observed)
+        pr.set_lambda(lam)
+        info = pr.solve(tol=PARITY_TOL, precision=precision)
+        runs.append((info, [r["cg_iters"] for r in pr.log()], pr.get(csipm.BETA).cpu(), pr.get(csipm.NU1).cpu()))
+        say("  memory", fill, info["status_name"], info["ipm_iters"], runs[-1][1])
+        pr.close()
+    (i0, c0, b0, n0), (i1, c1, b1, n1) = runs
+    assert c0 == c1 and i0["ipm_iters"] == i1["ipm_iters"] and i0["rel_kkt"] == i1["rel_kkt"]
+    assert torch.equal(b0, b1) and torch.equal(n0, n1)
