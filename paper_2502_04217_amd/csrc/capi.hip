@@ -92,6 +92,17 @@ struct csipm_ctx {
   std::vector<hipEvent_t> kt_ev;
   std::vector<std::pair<const char*, size_t>> kt_rec;
   long long kt_dropped = 0;
+  // PCG chunks recorded as HIP graphs (pcg), keyed by precision, chunk
+  // length, whether the chunk starts the solve, and the correction pointer;
+  // recorded on a private stream, replayed on s
+  struct PcgGraph {
+    int wbytes, chunk;
+    bool first;
+    const float* pcc;
+    hipGraphExec_t exec;
+  };
+  std::vector<PcgGraph> graphs;
+  hipStream_t cap_s = nullptr;
 };
 
 namespace {
@@ -337,36 +348,88 @@ struct PcgOut {
 
 // Preconditioned CG (Hestenes-Stiefel) on K x = h, x0 = 0, stopping on
 // sqrt(r.P^{-1}r) <= max(atol, eta sqrt(r0.P^{-1}r0)).  The caller has put
-// r = h, z = P^{-1}r and p = z into the precision-T Krylov vectors and
-// finalised the start (k_fin_cg_init).  x0 = 0 is never stored: the first
-// update writes x = alpha p.  On return r holds the recursive residual of x.  Iterations are queued in growing
-// batches; finished iterations turn the rest of a batch into no-ops through
-// the device flag, so the host only synchronises once per batch.  If
-// `capture` is set, p_0 and q_0 = K p_0 go to the capture hook.
+// r = h and p = P^{-1}r into the precision-T Krylov vectors and finalised
+// the start (k_fin_cg_init).  x0 = 0 is never stored: the first update
+// writes x = alpha p.  On return r holds the recursive residual of x.
+//
+// One chunk of PCG iterations queued on c->s: K-apply of p (with the fused
+// direction update after the solve's first iteration), alpha, the update of
+// x, r, z and beta.  Finished iterations turn the rest of a chunk into
+// no-ops through the device flag, so the host only synchronises once per
+// chunk.  If `capture` is set, p_0 and q_0 = K p_0 go to the capture hook.
 template <typename T>
-csipm_status pcg(csipm_ctx* c, T* xb, T* xz, const T* s1, const T* s2, const float* pcc, PcgOut& out,
-                 bool capture) {
+void pcg_chunk(csipm_ctx* c, int chunk, bool first, T* xb, T* xz, const T* s1, const T* s2, const float* pcc,
+               bool capture) {
   const long long n = c->g.n;
   PcgSet v = pcg_set<T>(c);
   T *rb = (T*)v.rb, *rz = (T*)v.rz, *zb = (T*)v.zb, *zz = (T*)v.zz, *pb = (T*)v.pb, *pz = (T*)v.pz,
     *qb = (T*)v.qb, *qz = (T*)v.qz, *work = (T*)v.work;
   const int nbv = vec_blocks(n);
   const int* skip = c->flags + F_DONE;
-  int chunk = 2;
-  bool first = true;
   // after the first iteration, p <- z + beta p is applied by the K-apply of
   // the new p as it reads p (PUpd), not by a separate pass
   const PUpd<T> upd{pb, pz, zb, zz, c->scal + S_BETA};
+  for (int k = 0; k < chunk; ++k) {
+    const int nbk = op_K<T>(c, pb, pz, s1, s2, qb, qz, work, skip, first ? nullptr : &upd);
+    if (first && capture) KT(c, "capture", capture_pair<T>(c, pb, pz, qb, qz, s1, s2));
+    KT(c, "fin_alpha", fin_alpha(c->partK, nbk, c->scal, c->flags, c->s));
+    KT(c, PN(T, "cg_update"), cg_update<T>(xb, xz, pb, pz, qb, qz, rb, rz, zb, zz, s1, s2, pcc, c->scal, c->flags,
+                                          n, c->partV, first, c->s));
+    first = false;
+    KT(c, "fin_rz", fin_rz(c->partV, nbv, c->scal, c->flags, c->s));
+  }
+}
+
+// The chunk as a replayable HIP graph (recorded on first use; null when the
+// runtime refuses, and the caller then queues the chunk directly).  The
+// kernels and their arguments are the same as those pcg_chunk queues, so a
+// replay computes exactly what the direct launches compute.
+template <typename T>
+hipGraphExec_t pcg_graph(csipm_ctx* c, int chunk, bool first, T* xb, T* xz, const T* s1, const T* s2,
+                         const float* pcc) {
+  for (const auto& gr : c->graphs)
+    if (gr.wbytes == (int)sizeof(T) && gr.chunk == chunk && gr.first == first && gr.pcc == pcc) return gr.exec;
+  if (!c->cap_s && hipStreamCreateWithFlags(&c->cap_s, hipStreamNonBlocking) != hipSuccess) {
+    c->cap_s = nullptr;
+    return nullptr;
+  }
+  hipStream_t s0 = c->s;
+  c->s = c->cap_s;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ok = hipStreamBeginCapture(c->cap_s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    pcg_chunk<T>(c, chunk, first, xb, xz, s1, s2, pcc, false);
+    ok = hipStreamEndCapture(c->cap_s, &graph) == hipSuccess && graph;
+  }
+  c->s = s0;
+  if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (graph) (void)hipGraphDestroy(graph);
+  if (!ok) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  c->graphs.push_back({(int)sizeof(T), chunk, first, pcc, exec});
+  return exec;
+}
+
+// PCG: chunks of 2, 4, 8 and 16 iterations between host reads of the
+// stopping flag; with graphs (no timing, no capture) each chunk is one graph
+// launch.
+template <typename T>
+csipm_status pcg(csipm_ctx* c, T* xb, T* xz, const T* s1, const T* s2, const float* pcc, PcgOut& out,
+                 bool capture, bool graphs) {
+  int chunk = 2;
+  bool first = true;
+  const bool use_graphs = graphs && !capture && !c->kt_on;
   for (;;) {
-    for (int k = 0; k < chunk; ++k) {
-      const int nbk = op_K<T>(c, pb, pz, s1, s2, qb, qz, work, skip, first ? nullptr : &upd);
-      if (first && capture) KT(c, "capture", capture_pair<T>(c, pb, pz, qb, qz, s1, s2));
-      KT(c, "fin_alpha", fin_alpha(c->partK, nbk, c->scal, c->flags, c->s));
-      KT(c, PN(T, "cg_update"), cg_update<T>(xb, xz, pb, pz, qb, qz, rb, rz, zb, zz, s1, s2, pcc, c->scal, c->flags,
-                                            n, c->partV, first, c->s));
-      first = false;
-      KT(c, "fin_rz", fin_rz(c->partV, nbv, c->scal, c->flags, c->s));
+    hipGraphExec_t ex = use_graphs ? pcg_graph<T>(c, chunk, first, xb, xz, s1, s2, pcc) : nullptr;
+    if (ex) {
+      if (hipGraphLaunch(ex, c->s) != hipSuccess) return fail(c, CSIPM_EHIP, "pcg: graph launch failed");
+    } else {
+      pcg_chunk<T>(c, chunk, first, xb, xz, s1, s2, pcc, capture);
     }
+    first = false;
     csipm_status st = sync_scalars(c, "pcg");
     if (st != CSIPM_OK) return st;
     if (c->hflags[F_DONE]) break;
@@ -474,10 +537,10 @@ csipm_status pcar(csipm_ctx* c, T* xb, T* xz, const T* s1, const T* s2, const fl
 // The Newton systems' Krylov method (options.krylov); capture needs CG.
 template <typename T>
 csipm_status krylov(csipm_ctx* c, int method, T* xb, T* xz, const T* s1, const T* s2, const float* pcc, PcgOut& out,
-                    bool capture) {
+                    bool capture, bool graphs) {
   if (method == CSIPM_KRYLOV_CR) return pcr<T>(c, xb, xz, s1, s2, pcc, out);
   if (method == CSIPM_KRYLOV_CAR) return pcar<T>(c, xb, xz, s1, s2, pcc, out);
-  return pcg<T>(c, xb, xz, s1, s2, pcc, out, capture);
+  return pcg<T>(c, xb, xz, s1, s2, pcc, out, capture, graphs);
 }
 
 }  // namespace
@@ -505,6 +568,7 @@ void csipm_default_options(csipm_options* o) {
   o->pc_max_relevant = 0.5;
   o->mehrotra = 0;
   o->build_next = 1;
+  o->graphs = 1;
 }
 
 size_t csipm_workspace_bytes(int n1, int n2, int n3) {
@@ -655,7 +719,7 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
     KT(c, "fin_cg_start",
        fin_cg_start(part0, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, eta, o.cg_atol, o.cg_max, -1, -1, c->s));
     PcgOut po;
-    csipm_status st = krylov<double>(c, o.krylov, c->dxb, c->dxz, c->sig1, c->sig2, pcc, po, capture);
+    csipm_status st = krylov<double>(c, o.krylov, c->dxb, c->dxz, c->sig1, c->sig2, pcc, po, capture, o.graphs != 0);
     cg_iters = po.iters;
     converged = po.converged;
     return st;
@@ -683,7 +747,7 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
     KT(c, "fin_cg_start",
        fin_cg_start(part0, nbv, VEC_MAX_BLOCKS, c->scal, c->flags, inner, 0.0, o.cg_max, -1, -1, c->s));
     PcgOut po;
-    csipm_status st = krylov<float>(c, o.krylov, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, po, capture);
+    csipm_status st = krylov<float>(c, o.krylov, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, po, capture, o.graphs != 0);
     if (st != CSIPM_OK) return st;
     cg_iters = po.iters;
     converged = po.converged;
@@ -704,7 +768,8 @@ csipm_status newton_solve(csipm_ctx* c, const csipm_options& o, double smu, doub
       KT(c, "fin_cg_start",
          fin_cg_start(nullptr, 0, 0, c->scal, c->flags, inner, 0.0, inner_max, -1, S_REFRZ, c->s));
     PcgOut po;
-    csipm_status st = krylov<float>(c, o.krylov, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, po, capture && step == 0);
+    csipm_status st =
+        krylov<float>(c, o.krylov, c->fxb, c->fxz, c->sig1f, c->sig2f, pcc, po, capture && step == 0, o.graphs != 0);
     if (st != CSIPM_OK) return st;
     cg_iters += po.iters;
     if (step == 0)
@@ -816,7 +881,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       (o.pc != CSIPM_PC_PLAIN && o.pc != CSIPM_PC_LEARNED && o.pc != CSIPM_PC_SCALED) ||
       (o.krylov != CSIPM_KRYLOV_CG && o.krylov != CSIPM_KRYLOV_CR && o.krylov != CSIPM_KRYLOV_CAR) || !(o.pc_rho >= 0.0) ||
       !(o.pc_max_relevant >= 0.0 && o.pc_max_relevant <= 1.0) || (o.mehrotra != 0 && o.mehrotra != 1) ||
-      (o.build_next != 0 && o.build_next != 1) ||
+      (o.build_next != 0 && o.build_next != 1) || (o.graphs != 0 && o.graphs != 1) ||
       !(o.refine_trust >= 0.0 && o.refine_trust <= 1.0) || !(o.refine_inner_rtol > 0.0) || o.pc_min_cg < 0)
     return fail(c, CSIPM_EINVAL, "invalid options");
   if (o.pc == CSIPM_PC_LEARNED && !c->have_params) return fail(c, CSIPM_ESTATE, "learned preconditioner has no parameters");
@@ -1449,6 +1514,8 @@ csipm_status csipm_timing_report(csipm_ctx* c, double min_us, csipm_kernel_time*
 csipm_status csipm_destroy(csipm_ctx* c) {
   if (!c) return CSIPM_EINVAL;
   for (hipEvent_t ev : c->kt_ev) (void)hipEventDestroy(ev);
+  for (auto& gr : c->graphs) (void)hipGraphExecDestroy(gr.exec);
+  if (c->cap_s) (void)hipStreamDestroy(c->cap_s);
   if (c->hscal) (void)hipHostFree(c->hscal);
   delete c;
   return CSIPM_OK;

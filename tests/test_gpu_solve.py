@@ -468,3 +468,28 @@ def test_solve_ignores_prior_memory_contents(precision):
     (i0, c0, b0, n0), (i1, c1, b1, n1) = runs
     assert c0 == c1 and i0["ipm_iters"] == i1["ipm_iters"] and i0["rel_kkt"] == i1["rel_kkt"]
     assert torch.equal(b0, b1) and torch.equal(n0, n1)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_direct_launches(precision):
+    """PCG chunks replayed from HIP graphs (graphs = 1, the default) against
+    the same kernels launched one by one (graphs = 0), alternating on one
+    problem so that every replay follows direct work: bit-identical
+    solutions and counts."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid64(2)
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.lambda_rule(0.05)
+    res = {}
+    for g in (1, 0, 1, 0):
+        info = pr.solve(tol=PARITY_TOL, precision=precision, graphs=g)
+        out = (info["ipm_iters"], info["cg_iters_total"], info["rel_kkt"], [r["cg_iters"] for r in pr.log()],
+               pr.get(csipm.BETA).cpu(), pr.get(csipm.NU2).cpu())
+        say("  graphs", g, info["status_name"], out[0], out[1], out[3])
+        assert info["status"] == 0
+        if g in res:
+            assert out[:4] == res[g][:4] and torch.equal(out[4], res[g][4]) and torch.equal(out[5], res[g][5])
+        res[g] = out
+    assert res[1][:4] == res[0][:4]
+    assert torch.equal(res[1][4], res[0][4]) and torch.equal(res[1][5], res[0][5])
