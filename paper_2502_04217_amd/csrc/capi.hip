@@ -387,6 +387,7 @@ void pcg_chunk(csipm_ctx* c, int chunk, bool first, T* xb, T* xz, const T* s1, c
 template <typename T>
 hipGraphExec_t pcg_graph(csipm_ctx* c, int chunk, bool first, T* xb, T* xz, const T* s1, const T* s2,
                          const float* pcc) {
+  // (a key whose recording failed is kept with a null exec: not retried)
   for (const auto& gr : c->graphs)
     if (gr.wbytes == (int)sizeof(T) && gr.chunk == chunk && gr.first == first && gr.pcc == pcc) return gr.exec;
   if (!c->cap_s && hipStreamCreateWithFlags(&c->cap_s, hipStreamNonBlocking) != hipSuccess) {
@@ -406,8 +407,9 @@ hipGraphExec_t pcg_graph(csipm_ctx* c, int chunk, bool first, T* xb, T* xz, cons
   if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
   if (graph) (void)hipGraphDestroy(graph);
   if (!ok) {
-    (void)hipGetLastError();
-    return nullptr;
+    const hipError_t e = hipGetLastError();
+    c->err = std::string("pcg: graph recording failed, chunks are launched directly: ") + hipGetErrorString(e);
+    exec = nullptr;
   }
   c->graphs.push_back({(int)sizeof(T), chunk, first, pcc, exec});
   return exec;

@@ -493,3 +493,25 @@ def test_graph_replay_matches_direct_launches(precision):
         res[g] = out
     assert res[1][:4] == res[0][:4]
     assert torch.equal(res[1][4], res[0][4]) and torch.equal(res[1][5], res[0][5])
+
+
+def test_graph_recording_with_large_workgroup_memory():
+    """At 128^3 the FP64 axis-1 pass sets its workgroup-memory limit above
+    64 KB when it is launched; recording those launches into graphs succeeds
+    (no recording failure is reported) and the replayed solve equals the
+    direct one bit for bit, in FP64 and FP32."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid128_family(10000)
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.lambda_rule(0.05)
+    for precision in (0, 1):
+        out = {}
+        for g in (1, 0):
+            info = pr.solve(tol=1e-8, precision=precision, graphs=g)
+            out[g] = ([r["cg_iters"] for r in pr.log()], info["rel_kkt"], pr.get(csipm.BETA).cpu())
+            msg = (csipm.lib().csipm_last_error(pr._ctx) or b"").decode()
+            say("  128^3 graphs", g, precision, info["status_name"], out[g][0], repr(msg))
+            assert info["status"] == 0
+            assert "graph recording failed" not in msg
+        assert out[1][:2] == out[0][:2] and torch.equal(out[1][2], out[0][2])
