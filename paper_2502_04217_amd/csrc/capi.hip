@@ -86,7 +86,8 @@ struct csipm_ctx {
   float *cap_feat = nullptr, *cap_rec = nullptr;
   unsigned long long cap_seed = 0;
   std::vector<int> cap_cg;
-  int last_cg = 0;
+  // iterations of the last PCG solve: the first chunk of the next one
+  int pcg_hint = 0;
   // kernel timing: an event pair per launch while kt_on
   bool kt_on = false;
   std::vector<hipEvent_t> kt_ev;
@@ -421,7 +422,11 @@ hipGraphExec_t pcg_graph(csipm_ctx* c, int chunk, bool first, T* xb, T* xz, cons
 template <typename T>
 csipm_status pcg(csipm_ctx* c, T* xb, T* xz, const T* s1, const T* s2, const float* pcc, PcgOut& out,
                  bool capture, bool graphs) {
+  // the first chunk covers as many iterations as the last solve needed (a
+  // power of two in [2, 16]), so that most systems need one host read;
+  // queued iterations past convergence return at once
   int chunk = 2;
+  while (chunk < c->pcg_hint && chunk < 16) chunk *= 2;
   bool first = true;
   const bool use_graphs = graphs && !capture && !c->kt_on;
   for (;;) {
@@ -442,6 +447,7 @@ csipm_status pcg(csipm_ctx* c, T* xb, T* xz, const T* s1, const T* s2, const flo
   out.res0 = std::sqrt(std::max(c->hscal[S_RZ0], 0.0));
   out.res = c->hscal[S_RES];
   out.converged = out.res <= c->hscal[S_TOL];
+  c->pcg_hint = out.iters;
   return CSIPM_OK;
 }
 
