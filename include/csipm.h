@@ -155,13 +155,14 @@ typedef struct {
                           0: every system is built by its own pass.  Saves
                           a pass over the state per iteration; the result
                           differs from 0 only by rounding. */
-  int graphs;          /* 1 (default): PCG chunks are recorded once per
-                          context as HIP graphs and replayed (one launch per
-                          chunk of 2-16 iterations instead of about ten per
-                          iteration; what small grids gain).  0: every
-                          kernel is launched directly.  Not used while
-                          kernel timing or sample capture is on.  Same
-                          kernels and arguments, so the same results. */
+  int graphs;          /* 1 (default): from a context's second solve on,
+                          PCG chunks are recorded once per context as HIP
+                          graphs and replayed (one launch per chunk of 2-16
+                          iterations instead of about ten per iteration;
+                          what small grids gain).  0: every kernel is
+                          launched directly.  Not used while kernel timing
+                          or sample capture is on.  Same kernels and
+                          arguments, so the same results. */
 } csipm_options;
 
 typedef struct {

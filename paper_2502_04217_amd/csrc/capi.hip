@@ -104,6 +104,7 @@ struct csipm_ctx {
   };
   std::vector<PcgGraph> graphs;
   hipStream_t cap_s = nullptr;
+  long long solves = 0;   // csipm_solve calls that returned (graphs from the second on)
 };
 
 namespace {
@@ -428,7 +429,9 @@ csipm_status pcg(csipm_ctx* c, T* xb, T* xz, const T* s1, const T* s2, const flo
   int chunk = 2;
   while (chunk < c->pcg_hint && chunk < 16) chunk *= 2;
   bool first = true;
-  const bool use_graphs = graphs && !capture && !c->kt_on;
+  // (a context's first solve launches directly: recording and first
+  // replays cost more than one solve of a small grid gains)
+  const bool use_graphs = graphs && !capture && !c->kt_on && c->solves > 0;
   for (;;) {
     hipGraphExec_t ex = use_graphs ? pcg_graph<T>(c, chunk, first, xb, xz, s1, s2, pcc) : nullptr;
     if (ex) {
@@ -1165,6 +1168,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   }
   inf.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   inf.status = result;
+  ++c->solves;
   if (info) *info = inf;
   return result;
 }

@@ -472,10 +472,10 @@ def test_solve_ignores_prior_memory_contents(precision):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_graph_replay_matches_direct_launches(precision):
-    """PCG chunks replayed from HIP graphs (graphs = 1, the default) against
-    the same kernels launched one by one (graphs = 0), alternating on one
-    problem so that every replay follows direct work: bit-identical
-    solutions and counts."""
+    """PCG chunks replayed from HIP graphs (graphs = 1, the default; from a
+    context's second solve on) against the same kernels launched one by one
+    (graphs = 0), alternating on one problem so that every replay follows
+    direct work: bit-identical solutions and counts."""
     torch = need_gpu()
     from paper_2502_04217_amd import csipm
     w = wl.grid64(2)
@@ -505,6 +505,7 @@ def test_graph_recording_with_large_workgroup_memory():
     w = wl.grid128_family(10000)
     pr = csipm.Problem(w.signal, w.observed)
     pr.lambda_rule(0.05)
+    pr.solve(tol=1e-6)   # (a context's first solve launches directly)
     for precision in (0, 1):
         out = {}
         for g in (1, 0):
