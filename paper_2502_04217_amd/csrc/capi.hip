@@ -139,12 +139,12 @@ size_t kt_begin(csipm_ctx* c, const char* name) {
     }
     c->kt_ev.push_back(ev);
   }
-  hipEventRecord(c->kt_ev[e], c->s);
+  (void)hipEventRecord(c->kt_ev[e], c->s);
   c->kt_rec.emplace_back(name, e);
   return e;
 }
 void kt_end(csipm_ctx* c, size_t e) {
-  if (e != SIZE_MAX) hipEventRecord(c->kt_ev[e + 1], c->s);
+  if (e != SIZE_MAX) (void)hipEventRecord(c->kt_ev[e + 1], c->s);
 }
 #define KT(c, name, launch)                 \
   do {                                      \
@@ -1450,7 +1450,7 @@ csipm_status csipm_profile_kapply(csipm_ctx* c, int precision, int reps, double*
     const T* s2 = std::is_same<T, double>::value ? (const T*)c->sig2 : (const T*)c->sig2f;
     const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>), -1);
     const int ps = (int)k_partials(g.n1, g.n2, g.n3);
-    EpiArgs<T> ka{KArgs<T>{pb, pz, s1, s2, qb, qz}, RArgs{}, c->partK, ps};
+    EpiArgs<T> ka{KArgs<T>{pb, pz, s1, s2, qb, qz, PUpd<T>{}}, RArgs{}, c->partK, ps};
     EpiArgs<T> kb = ka;
     kb.partial = c->partK + nb5;
     for (int r = 0; r < reps; ++r) {

@@ -456,6 +456,7 @@ __global__ void __launch_bounds__(256)
 k_capture(const T* __restrict__ pb, const T* __restrict__ pz, const T* __restrict__ qb, const T* __restrict__ qz,
           const T* __restrict__ s1, const T* __restrict__ s2, const float* __restrict__ feat_all, long long n,
           int npick, unsigned long long seed, float* __restrict__ of, float* __restrict__ orc, double* partial) {
+  (void)qz;   // (H p) is the beta row of q less its Sigma terms; q_z is not needed
   double acc = 0.0;
   for (long long j = gtid(); j < npick; j += gstride()) {
     const long long i = (long long)(splitmix64(seed + (unsigned long long)j) % (unsigned long long)n);
