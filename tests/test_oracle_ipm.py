@@ -462,3 +462,45 @@ def test_cr_and_scaled_preconditioner_reach_the_lasso_solution():
     assert car9.converged and car9.iters == cg9.iters
     err = np.linalg.norm(car9.state.beta - cg9.state.beta) / np.linalg.norm(cg9.state.beta)
     assert err < 1e-8, err
+
+
+def test_duality_measure_after_step_from_step_sums():
+    """The duality measure after a step of length alpha along a Newton
+    direction is (s.nu + alpha (s.dnu + nu.ds) + alpha^2 ds.dnu) / 2n, with
+    s_j dnu_j + nu_j ds_j = sigma mu - s_j nu_j elementwise (the
+    linearised complementarity rows of equation "kktmu").  The iterate
+    update that also builds the next Newton system takes its target from
+    these sums; here they are checked against the product of the stepped
+    iterate."""
+    shape = (4, 4, 6)
+    n = 96
+    w = wl.make_workload(shape, n_freq=5, amplitude="normal", snr_db=10.0,
+                         half_width=0, period=2, seed=5)
+    obs = w.observed.astype(np.float64)
+    xi = dft3.xi(w.signal, obs)
+    lam = 0.1 * float(np.abs(xi).max())
+    rng = np.random.default_rng(11)
+    beta = 0.3 * rng.standard_normal(shape)
+    z = np.abs(beta) + rng.uniform(0.1, 1.0, shape)
+    nu1 = rng.uniform(0.1, 1.0, shape) * lam
+    nu2 = rng.uniform(0.1, 1.0, shape) * lam
+    st = ipm.IPMState(beta, z, nu1, nu2)
+    s1, s2 = z + beta, z - beta
+    sig1, sig2 = nu1 / s1, nu2 / s2
+    sigma = 0.1
+    mu = float((s1 * nu1).sum() + (s2 * nu2).sum()) / (2 * n)
+    rb, rz = ipm.newton_rhs(st, dft3.apply_H(beta, obs), xi, lam, sigma, mu)
+    res = ipm.pcg(lambda pb, pz: ipm.K_apply(pb, pz, sig1, sig2, obs),
+                  lambda qb, qz: ipm.Pinv_apply(qb, qz, sig1, sig2), rb, rz, rtol=1e-13, maxit=400)
+    ds1, ds2, dnu1, dnu2 = ipm.recover_dnu(st, res.xb, res.xz, sig1, sig2, sigma, mu)
+    assert np.allclose(s1 * dnu1 + nu1 * ds1, sigma * mu - s1 * nu1, rtol=0, atol=1e-12 * lam)
+    assert np.allclose(s2 * dnu2 + nu2 * ds2, sigma * mu - s2 * nu2, rtol=0, atol=1e-12 * lam)
+    amax = min(ipm.max_step(s1, ds1), ipm.max_step(s2, ds2), ipm.max_step(nu1, dnu1), ipm.max_step(nu2, dnu2))
+    S0 = float((s1 * nu1).sum() + (s2 * nu2).sum())
+    S1 = float((s1 * dnu1 + nu1 * ds1).sum() + (s2 * dnu2 + nu2 * ds2).sum())
+    S2 = float((ds1 * dnu1).sum() + (ds2 * dnu2).sum())
+    for alpha in (0.0, 0.3, min(1.0, 0.99 * amax)):
+        direct = float(((s1 + alpha * ds1) * (nu1 + alpha * dnu1)).sum()
+                       + ((s2 + alpha * ds2) * (nu2 + alpha * dnu2)).sum()) / (2 * n)
+        from_sums = (S0 + alpha * S1 + alpha * alpha * S2) / (2 * n)
+        assert abs(from_sums - direct) <= 1e-13 * S0 / (2 * n)
