@@ -386,6 +386,13 @@ def main():
                      "launches": top["calls"], "working_launches": top["working_calls"],
                      "avg_ms": top["total_ms"] / max(1, top["calls"]),
                      "bytes_per_launch": top["bytes_per_launch"]},
+        # summed kernel durations of the event-timed solve of each form, beside
+        # the untimed wall time: the difference is time the device sat idle
+        # (host synchronisation and launch latency between kernels)
+        "kernel_busy_ms_per_solve": {"chosen": round(sum(r["total_ms"] for r in kern), 3),
+                                     "chosen_wall": round(chosen_s * 1e3, 3),
+                                     "plain_fp64": round(sum(r["total_ms"] for r in kern64), 3),
+                                     "plain_fp64_wall": round(plain_s * 1e3, 3)},
         "kernels_ms_per_solve": {r["name"]: round(r["total_ms"], 3) for r in kern[:10]},
         "kernels_ms_per_solve_fp64": {r["name"]: round(r["total_ms"], 3) for r in kern64[:8]},
         "kapply": kapply,

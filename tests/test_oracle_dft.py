@@ -62,6 +62,48 @@ def test_1d_matches_paper_formula(N):
     assert np.abs(ours[:, perm] - Ap).max() < 1e-14
 
 
+GOLDEN = __import__("pathlib").Path(__file__).parent / "golden"
+
+
+def _read_paper_1d_A():
+    """The hand-worked matrices of tests/golden/paper_1d_map_A.txt, as
+    {n: A} with A in the paper's ordering of beta (equation "beta")."""
+    value = {"0": 0.0, "1": 1.0, "r2": math.sqrt(2), "r2/2": math.sqrt(2) / 2, "r6/2": math.sqrt(6) / 2}
+    out, rows, n = {}, [], None
+    for line in (GOLDEN / "paper_1d_map_A.txt").read_text().splitlines():
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.startswith("n "):
+            if n is not None:
+                out[n] = np.array(rows) / math.sqrt(n)
+            n, rows = int(line.split()[1]), []
+            continue
+        rows.append([-value[t[1:]] if t.startswith("-") else value[t] for t in line.split()])
+    out[n] = np.array(rows) / math.sqrt(n)
+    return out
+
+
+def test_1d_map_matches_hand_worked_golden():
+    """The oracle's A for a 1D grid (N1 = N2 = 1) equals the hand-evaluated
+    matrices of the paper's 1D map at n = 4 and n = 6 (derivation "map"),
+    after the permutation from the paper's ordering of beta to ours."""
+    golden = _read_paper_1d_A()
+    assert sorted(golden) == [4, 6]
+    for n, Ap in golden.items():
+        assert Ap.shape == (n, n)
+        h = n // 2
+        perm = np.empty(n, dtype=int)          # perm[paper index] = our index
+        perm[0], perm[1] = 0, h
+        for j in range(1, h):
+            perm[j + 1] = j
+            perm[j + h] = n - j
+        ours = dft3.dense_A((1, 1, n))
+        assert np.abs(ours[:, perm] - Ap).max() < 1e-15
+        # the fixture itself is orthogonal, so a mistyped entry shows here too
+        assert np.abs(Ap.T @ Ap - np.eye(n)).max() < 1e-15
+
+
 def test_synthesised_waves_match_A():
     """numpy's irfftn synthesis of plane waves equals A applied to the beta
     the oracle derives from the wave list (two independent routes)."""
