@@ -19,7 +19,7 @@ iterations, wall time and the true final KKT residual.
     python -m paper_2502_04217_amd.learn --eval-only --eval 50
 
 writes paper_2502_04217_amd/pc_params.json (not with --eval-only) and
-gpurun_out/learn_eval.json.
+learn_eval.json (or the path given by --out).
 """
 from __future__ import annotations
 
@@ -157,7 +157,7 @@ def main():
     ap.add_argument("--eval", type=int, default=50)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--out", default=os.path.join("gpurun_out", "learn_eval.json"))
+    ap.add_argument("--out", default="learn_eval.json")
     ap.add_argument("--eval-only", action="store_true", help="evaluate the stored parameters, no training")
     args = ap.parse_args()
     log = lambda *a: print(*a, flush=True)

@@ -4,7 +4,7 @@ only (longer than --min-us; Krylov iterations are queued ahead in batches and
 the ones past convergence return at once, in a few microseconds), plus the
 per-dispatch mean of any collected counters (FETCH_SIZE, WRITE_SIZE in KiB).
 
-    python -m paper_2502_04217_amd.rocprof_summary gpurun_out/prof/x_results.db [--top 25] [--min-us 8]
+    python -m paper_2502_04217_amd.rocprof_summary prof/x_results.db [--top 25] [--min-us 8]
 """
 from __future__ import annotations
 
