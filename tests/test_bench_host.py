@@ -1,0 +1,49 @@
+"""Host logic of bench.py that needs no GPU: the one-GPU guard and the
+algorithmic byte counts behind the roofline figure (K-apply 15 n w + n/8
+bytes plus the m = 0 plane passes; one CG update 16 n w)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 256), (512, 512, 512), (560, 560, 560), (64, 32, 16)])
+@pytest.mark.parametrize("w", [4, 8])
+def test_kapply_pass_bytes_sum_to_model(shape, w):
+    """Five volume passes move the work array once each way (10 n w), the
+    K epilogue reads T, p_beta, p_z, Sigma_1, Sigma_2 and writes q_beta, q_z
+    (5 n w more), the axis-3 pass reads the n-bit mask, and the two m = 0
+    plane passes touch 2 N1 N2 reals per array (2 + 7 arrays)."""
+    n1, n2, n3 = shape
+    n = n1 * n2 * n3
+    plane = 2 * n1 * n2
+    by = bench.pass_bytes(shape, w)
+    assert len(by) == len(bench.PASS_NAMES) == 7
+    assert sum(by) == 15 * n * w + n // 8 + 9 * plane * w
+
+
+def test_kernel_bytes_of_the_roofline_kernels():
+    shape = (256, 256, 256)
+    n = 256 ** 3
+    # x, p, q, r, Sigma (2 each) in; x, r, z (2 each) out: 16 arrays
+    assert bench.kernel_bytes("cg_update.f32", shape, False) == 16 * n * 4
+    assert bench.kernel_bytes("cg_update.f64", shape, False) == 16 * n * 8
+    # the learned correction adds one FP32 n-array to every P_c^{-1} apply
+    assert bench.kernel_bytes("cg_update.f32", shape, True) == 16 * n * 4 + 4 * n
+    assert bench.kernel_bytes("axis1_fwd_K.f64", shape, False) == 7 * n * 8
+    assert bench.kernel_bytes("axis3.f32", shape, False) == 2 * n * 4 + n // 8
+    # the finalize kernels carry no byte count
+    assert bench.kernel_bytes("fin_alpha", shape, False) is None
