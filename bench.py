@@ -12,16 +12,26 @@ resident in HBM and the problem created (xi, diag H) outside the timed region.
 
 The chosen form (FP32 Krylov with FP64 refinement, learned preconditioner
 correction when trained parameters are present) gives `value`; the plain FP64
-form is timed alongside.  One more solve of each form runs with per-kernel
-event timing (csipm_timing); `roofline` covers the HBM-bound kernel with the
-largest share of the chosen form's solve time (`dominant` says whether it is
-also the largest overall), with its algorithmic bytes per launch over its
-average launch time.  `traffic` is the calibrated rocprofv3 counter total of
-that kernel from a committed profile record taken on the current kernel
-sources (null otherwise).  `kapply` times the seven K-apply kernels alone
-(the matvec rate).  `cpu_baseline` times the CPU oracle on one K-apply of the
-same problem and scales it by the number of operator applies of the FP64
-solve.
+form is timed alongside.  Every form reports the LASSO certificate the
+library computes with the solve (relative duality gap, natural residual).
+
+`roofline` is the metric's matvec: one K-apply (the seven kernels of
+q = K p) in the chosen form's precision, FP32, timed with HIP events on the
+library's stream (csipm_profile_kapply, at the last solve's barrier
+diagonals), against its design bytes 15 n w + n/8 (five volume passes that
+each read and write the work array, the K epilogue's inputs and outputs,
+the mask bits); `frac_minimum` uses the least bytes any K-apply must move,
+6 n w + n/8 (read p and the two diagonals, write q).  `traffic` is the
+calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE of the same kernels from a
+committed profile record taken on the current kernel sources (null
+otherwise).  `roofline.fp64` is the FP64 K-apply, `roofline.secondary` the
+largest HBM-bound kernel of the chosen form's event-timed solve
+(csipm_timing), and `kapply_in_solve` the FP32 K-apply kernels of that solve.
+
+`cpu_baseline` times the CPU oracle on one K-apply of the same problem and
+scales it by the number of operator applies of the FP64 solve; the same leg
+certifies the chosen form's solution with the oracle (two naive transforms)
+and times whole oracle solves of the 16^3 and 64^3 workloads beside the GPU's.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--grid 256]
 """
@@ -118,9 +128,15 @@ def kernel_bytes(name, shape, learned):
 
 def kernel_breakdown(pr, opts, shape, learned, info):
     """One extra solve with per-kernel event timing; returns the per-kernel
-    records (ms per solve) with algorithmic bytes attached."""
+    records (ms per solve) with algorithmic bytes attached, and the wall time
+    of that same solve (event recording included)."""
+    import torch
     pr.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     pr.solve(**opts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     rep = pr.timing_report(8.0)
     pr.timing(False)
     # launches of cg_update that start a PCG solve read no x: 2nw fewer bytes
@@ -136,7 +152,29 @@ def kernel_breakdown(pr, opts, shape, learned, info):
         r["bytes_per_launch"] = b
         out.append(r)
     out.sort(key=lambda r: -r["total_ms"])
-    return out
+    return out, wall
+
+
+# the K-apply kernels of a PCG iteration as csipm_timing names them (with the
+# fused direction update: *_P, *_KP)
+KAPPLY_NAMES = ("premix", "premix_P", "axis1_inv", "axis1_inv_P", "axis2_inv", "axis3", "axis2_fwd",
+                "axis1_fwd_K", "axis1_fwd_KP", "postmix_K", "postmix_KP")
+
+
+def kapply_in_solve(kern, prec, shape):
+    """Algorithmic bytes over time of the precision-`prec` K-apply kernels
+    of an event-timed solve (working launches: those queued past a Krylov
+    solve's convergence return at once)."""
+    n = shape[0] * shape[1] * shape[2]
+    w = 4 if prec == "f32" else 8
+    b = t = 0.0
+    for r in kern:
+        base, _, p = r["name"].partition(".")
+        if p == prec and base in KAPPLY_NAMES and r["bytes_per_launch"] is not None:
+            b += r["bytes_per_launch"] * r["working_calls"]
+            t += r["working_ms"] * 1e-3
+    napply = b / (15 * n * w + n // 8) if b else 0.0
+    return {"GBps": b / t / 1e9 if t else None, "ms": t * 1e3, "applies_equiv": round(napply, 2)}
 
 
 PROFILE_RECORDS = os.path.join(ROOT, "profiles")
@@ -171,17 +209,22 @@ def load_params(torch):
     return torch.tensor(d["params"], dtype=torch.float32, device="cuda")
 
 
-def cpu_baseline(w, lam, info64, sig_for_k):
+def cpu_baseline(w, lam, info64, sig_for_k, beta_chosen, gpu_small):
     """Oracle (numpy float64, naive separable DFT) on a bounded sample: one
     K-apply of this problem, scaled by the operator-apply count of the GPU
-    FP64 solve (PCG K-applies + one H-apply per interior-point iteration)."""
+    FP64 solve (PCG K-applies + one H-apply per interior-point iteration);
+    the oracle's LASSO certificate of the chosen form's solution; whole
+    oracle solves of the 16^3 and 64^3 workloads (gpu_small: the GPU's
+    times on the same problems)."""
     import numpy as np
     from oracle import ipm
+    from paper_2502_04217_amd import workload as wl
+    host_cpus = os.cpu_count() or 1
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
-        threads = os.cpu_count() or 1
+        threads = host_cpus
     rng = np.random.default_rng(0)
     pb = rng.standard_normal(w.shape)
     pz = rng.standard_normal(w.shape)
@@ -191,9 +234,25 @@ def cpu_baseline(w, lam, info64, sig_for_k):
     ipm.K_apply(pb, pz, s1, s2, obs)
     t_apply = time.perf_counter() - t0
     applies = int(info64["cg_iters_total"]) + int(info64["ipm_iters"]) + 1
+    t0 = time.perf_counter()
+    cert = ipm.lasso_certificate(beta_chosen, w.signal, w.observed, lam)
+    t_cert = time.perf_counter() - t0
+    small = {}
+    for name, make in (("grid16", lambda: wl.grid16(1)), ("grid64", lambda: wl.grid64(1))):
+        ws = make()
+        lam_s = ipm.lambda_rule(ws.signal, ws.observed)
+        t0 = time.perf_counter()
+        ref = ipm.ipm_solve(ws.signal, ws.observed, lam_s, ipm.IPMOptions(tol=1e-6))
+        small[name] = {"oracle_s": time.perf_counter() - t0, "oracle_ipm_iters": ref.iters,
+                       "gpu_fp64_s": gpu_small.get(name)}
     return {"value": t_apply * applies, "unit": "s", "cores": int(threads), "kind": "oracle",
+            "host_cpus": int(host_cpus), "blas_threads": int(threads),
             "sample": f"one oracle K-apply at {w.shape[0]}^3 ({t_apply:.2f} s) x {applies} operator applies "
-                      f"of the GPU FP64 solve (extrapolated time-to-solve)"}
+                      f"of the GPU FP64 solve (extrapolated time-to-solve)",
+            "oracle_certificate_chosen": {"rel_dual_gap": cert.rel_gap, "natural_residual": cert.natural_residual,
+                                          "max_offsupport_ratio": cert.max_offsupport_ratio,
+                                          "max_onsupport_dev": cert.max_onsupport_dev, "seconds": t_cert},
+            "oracle_full_solves_tol_1e-6": small}
 
 
 def main():
@@ -292,13 +351,14 @@ def main():
         torch.cuda.synchronize()
         alternatives[name] = {"seconds": (time.perf_counter() - t0) / args.steps, "ipm_iters": ia[-1]["ipm_iters"],
                               "krylov_iters_total": ia[-1]["cg_iters_total"], "rel_kkt": ia[-1]["rel_kkt"],
-                              "status": ia[-1]["status_name"]}
+                              "status": ia[-1]["status_name"], "rel_dual_gap": ia[-1]["rel_dual_gap"],
+                              "natural_residual": ia[-1]["natural_residual"]}
 
-    # per-kernel event timing of one more solve of each form; the dominant
-    # kernel of the chosen form is the roofline kernel
+    # per-kernel event timing of one more solve of each form; the largest
+    # HBM-bound kernel of the chosen form is the secondary roofline entry
     n = int(np.prod(w.shape))
-    kern = kernel_breakdown(pr, chosen, w.shape, learned, infos[-1])
-    kern64 = kernel_breakdown(pr, plain, w.shape, False, infos64[-1])
+    kern, kern_wall = kernel_breakdown(pr, chosen, w.shape, learned, infos[-1])
+    kern64, kern64_wall = kernel_breakdown(pr, plain, w.shape, False, infos64[-1])
     top = next(r for r in kern if r["bytes_per_launch"] is not None)
     dominant_is_top = top is kern[0]
 
@@ -317,10 +377,29 @@ def main():
     kapply = {}
     for name, wsz in (("fp32", 4), ("fp64", 8)):
         t = sum(prof[name]["ms"]) * 1e-3
-        kapply[name] = {"ms": t * 1e3,
-                        "design_GBps": (15 * n * wsz + n // 8) / t / 1e9,
-                        "minimum_GBps": (6 * n * wsz + n // 8) / t / 1e9,
+        design = 15 * n * wsz + n // 8
+        minimum = 6 * n * wsz + n // 8
+        krec = traffic_record("kapply." + ("f32" if wsz == 4 else "f64"), w.shape[0])
+        kapply[name] = {"ms": t * 1e3, "design_bytes": design, "minimum_bytes": minimum,
+                        "design_GBps": design / t / 1e9,
+                        "minimum_GBps": minimum / t / 1e9,
+                        "traffic": (krec["read_bytes"] + krec["write_bytes"]) if krec else None,
                         "per_kernel_ms": dict(zip(PASS_NAMES, [round(v, 5) for v in prof[name]["ms"]]))}
+    roofline = {"bound": "hbm", "kernel": "K-apply q = K p (7 kernels), fp32",
+                "achieved": kapply["fp32"]["design_GBps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                "frac": kapply["fp32"]["design_GBps"] / PEAK_HBM_GBPS, "traffic": kapply["fp32"]["traffic"],
+                "bytes_per_launch": kapply["fp32"]["design_bytes"], "avg_ms": kapply["fp32"]["ms"],
+                "frac_minimum": kapply["fp32"]["minimum_GBps"] / PEAK_HBM_GBPS,
+                "fp64": {"achieved": kapply["fp64"]["design_GBps"],
+                         "frac": kapply["fp64"]["design_GBps"] / PEAK_HBM_GBPS,
+                         "frac_minimum": kapply["fp64"]["minimum_GBps"] / PEAK_HBM_GBPS,
+                         "traffic": kapply["fp64"]["traffic"], "avg_ms": kapply["fp64"]["ms"],
+                         "bytes_per_launch": kapply["fp64"]["design_bytes"]},
+                "secondary": {"kernel": top["name"], "achieved": achieved, "frac": achieved / PEAK_HBM_GBPS,
+                              "traffic": traffic, "dominant": dominant_is_top, "launches": top["calls"],
+                              "working_launches": top["working_calls"],
+                              "avg_ms": top["total_ms"] / max(1, top["calls"]),
+                              "bytes_per_launch": top["bytes_per_launch"]}}
 
     # learned-correction inference on every coefficient (the network's two
     # dense layers on the matrix cores): 2 (4*32 + 32*32) MFMA flops per coefficient
@@ -344,9 +423,27 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        # the GPU's FP64 solve times of the small workloads the oracle solves whole
+        gpu_small = {}
+        for name, make in (("grid16", lambda: wl.grid16(1)), ("grid64", lambda: wl.grid64(1))):
+            ws = make()
+            ps = csipm.Problem(ws.signal, ws.observed)
+            ps.lambda_rule(0.05)
+            ps.solve(tol=1e-6)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                ps.solve(tol=1e-6)
+            torch.cuda.synchronize()
+            gpu_small[name] = (time.perf_counter() - t0) / 3
+            ps.close()
         sig1, sig2 = wl.random_barrier(w.shape, 1, spread=3.0)
-        cpu = cpu_baseline(w, lam, infos64[-1], (sig1, sig2))
+        cpu = cpu_baseline(w, lam, infos64[-1], (sig1, sig2), beta_chosen.cpu().numpy(), gpu_small)
         print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
+
+    def cert_of(i):
+        return {"rel_dual_gap": i["rel_dual_gap"], "natural_residual": i["natural_residual"],
+                "objective": i["objective"]}
 
     last = infos[-1]
     out = {
@@ -370,29 +467,28 @@ def main():
                   "cg_per_iter": [r["cg_iters"] for r in chosen_log],
                   "learned_per_iter": [r["learned"] for r in chosen_log],
                   "refine_steps": last["refine_steps_total"], "fallbacks": last["fallbacks"],
-                  "rel_kkt": last["rel_kkt"], "rel_diff_vs_fp64": rel_diff},
+                  "rel_kkt": last["rel_kkt"], "rel_diff_vs_fp64": rel_diff, "certificate": cert_of(last)},
         "plain_fp64": {"seconds": plain_s, "ipm_iters": infos64[-1]["ipm_iters"],
-                       "cg_iters_total": infos64[-1]["cg_iters_total"], "rel_kkt": infos64[-1]["rel_kkt"]},
+                       "cg_iters_total": infos64[-1]["cg_iters_total"], "rel_kkt": infos64[-1]["rel_kkt"],
+                       "certificate": cert_of(infos64[-1])},
         "fp32_plain_pc": {"seconds": fp32_plain_s, "ipm_iters": infos32[-1]["ipm_iters"],
                           "cg_per_iter": [r["cg_iters"] for r in fp32_plain_log],
                           "cg_iters_total": infos32[-1]["cg_iters_total"], "rel_kkt": infos32[-1]["rel_kkt"],
-                          "refine_steps": infos32[-1]["refine_steps_total"]},
+                          "refine_steps": infos32[-1]["refine_steps_total"], "certificate": cert_of(infos32[-1])},
         "alternatives_fp64": alternatives,
         "correction_inference": corr,
         "setup_seconds": setup_s,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic,
-                     "kernel": top["name"], "dominant": dominant_is_top,
-                     "launches": top["calls"], "working_launches": top["working_calls"],
-                     "avg_ms": top["total_ms"] / max(1, top["calls"]),
-                     "bytes_per_launch": top["bytes_per_launch"]},
+        "setup_seconds_library": last["setup_seconds"],
+        "roofline": roofline,
+        "kapply_in_solve": {"fp32": kapply_in_solve(kern, "f32", w.shape),
+                            "fp64": kapply_in_solve(kern64, "f64", w.shape)},
         # summed kernel durations of the event-timed solve of each form, beside
-        # the untimed wall time: the difference is time the device sat idle
-        # (host synchronisation and launch latency between kernels)
+        # the wall time of that same solve: the difference is time the device
+        # sat idle (host synchronisation, launch latency and event recording)
         "kernel_busy_ms_per_solve": {"chosen": round(sum(r["total_ms"] for r in kern), 3),
-                                     "chosen_wall": round(chosen_s * 1e3, 3),
+                                     "chosen_same_solve_wall": round(kern_wall * 1e3, 3),
                                      "plain_fp64": round(sum(r["total_ms"] for r in kern64), 3),
-                                     "plain_fp64_wall": round(plain_s * 1e3, 3)},
+                                     "plain_fp64_same_solve_wall": round(kern64_wall * 1e3, 3)},
         "kernels_ms_per_solve": {r["name"]: round(r["total_ms"], 3) for r in kern[:10]},
         "kernels_ms_per_solve_fp64": {r["name"]: round(r["total_ms"], 3) for r in kern64[:8]},
         "kapply": kapply,

@@ -178,6 +178,26 @@ typedef struct {
   double lambda;
   double xi_inf;
   double solve_seconds;
+  /* LASSO certificate of the returned beta (equation "realopt" and its
+   * dual max b^T theta - 1/2 ||theta||^2 s.t. ||M_perp^T theta||_inf <=
+   * lambda), from g = M_perp^T (b - M_perp beta) = xi - H beta evaluated by
+   * an FP64 apply of H; M_perp^T is an isometry on the observed samples,
+   * so ||b - M_perp beta|| = ||g||:
+   *   objective     P = 1/2 ||b - M_perp beta||^2 + lambda ||beta||_1
+   *   dual_objective D = s b^T r - s^2 ||r||^2 / 2 at theta = s r,
+   *                 r = b - M_perp beta, s = min(1, lambda / ||g||_inf)
+   *   rel_dual_gap  (P - D) / |P|, with P - D summed termwise as
+   *                 (1 - s)^2 ||r||^2 / 2 + sum_i (lambda |beta_i| -
+   *                 s beta_i g_i)
+   *   natural_residual ||beta - soft(beta + g, lambda)||_inf / max(1,
+   *                 ||beta||_inf)  (0 exactly at the LASSO solution)
+   *   g_inf         ||g||_inf  (<= lambda at the solution)            */
+  double objective;
+  double dual_objective;
+  double rel_dual_gap;
+  double natural_residual;
+  double g_inf;
+  double setup_seconds;     /* wall time of csipm_create for this context  */
 } csipm_info;
 
 /* One record per interior-point iteration (csipm_get_log). */
@@ -214,9 +234,17 @@ csipm_status csipm_set_lambda(csipm_ctx* ctx, double lambda);
 /* Sets lambda = frac * ||M_perp^T b||_inf and returns it (frac > 0). */
 csipm_status csipm_lambda_rule(csipm_ctx* ctx, double frac, double* lambda_out);
 
-/* Runs the interior-point method from the standard starting point
- * (beta = 0, z = ||xi||_inf, nu1 = nu2 = lambda/2).  `info` may be NULL.
- * Returns OK, NOT_CONVERGED, STALLED or FELL_BACK, or an error. */
+/* Runs the primal-dual interior-point method (paper: section "Primal-dual
+ * interior-point method", the KKT system of equation "kkt", Newton steps on
+ * equation "kktmu" condensed to equation "condensedkkt" and solved by a
+ * Krylov method with the preconditioner of equation "precond1") from the
+ * standard starting point (beta = 0, z = ||xi||_inf, nu1 = nu2 =
+ * lambda/2) until rel_kkt <= opts->tol.  The iterate stays in the
+ * context's workspace (csipm_get_iterate).  `info` may be NULL; it also
+ * receives the LASSO certificate of the returned beta (one more FP64 pass
+ * over beta and H beta).  Returns OK, NOT_CONVERGED, STALLED or FELL_BACK,
+ * or an error (EINVAL bad options, ESTATE no lambda or no parameters for
+ * the learned form, ENONFINITE non-finite iterate, EHIP). */
 csipm_status csipm_solve(csipm_ctx* ctx, const csipm_options* opts, csipm_info* info);
 
 /* Solves `count` independent problems concurrently (the "next" item of
@@ -235,7 +263,13 @@ csipm_status csipm_solve_batch(csipm_ctx* const* ctxs, int count, const csipm_op
  * layout). */
 csipm_status csipm_get_iterate(csipm_ctx* ctx, int which, double* d_dst);
 
-/* KKT residual parts of the current iterate (one FP64 apply of H). */
+/* KKT residual parts of the current iterate (paper, equation "kkt": the
+ * rows F_beta = H beta - xi - nu1 + nu2 and F_z = lambda - nu1 - nu2 and
+ * the complementarity s_j nu_j, with the slacks s1 = z + beta, s2 = z -
+ * beta eliminated) from one FP64 apply of H, and the LASSO certificate of
+ * beta (the certificate fields of csipm_info); solve_seconds and the
+ * iteration counts are 0.  Synchronises.  Errors: EINVAL, ESTATE (no
+ * lambda), EHIP. */
 csipm_status csipm_get_residuals(csipm_ctx* ctx, csipm_info* out);
 
 /* Copies up to max_records per-iteration records of the last solve. */
@@ -251,9 +285,9 @@ csipm_status csipm_get_log(csipm_ctx* ctx, csipm_iter_log* host_buf, int max_rec
  *   apply_K    : [qb; qz] = K [pb; pz], K = [[H + L1, L2], [L2, L1]],
  *                L1 = S1 + S2, L2 = S1 - S2 (equation "condensedkkt"),
  *                with the barrier diagonals of csipm_set_barrier
- *   apply_Pinv : [zb; zz] = P_c^{-1} [rb; rz], P_c = [[C + L1, L2], [L2, L1]]
- *                (equation "invprecond1"; C = I unless a learned correction
- *                is active) */
+ *   apply_Pinv : [zb; zz] = P^{-1} [rb; rz], P = [[I + L1, L2], [L2, L1]]
+ *                (equation "invprecond1": the paper's preconditioner,
+ *                whatever correction or scaling the last solve used) */
 csipm_status csipm_apply_A(csipm_ctx* ctx, const void* d_beta, void* d_x, int precision);
 csipm_status csipm_apply_At(csipm_ctx* ctx, const void* d_x, void* d_beta, int precision);
 csipm_status csipm_apply_H(csipm_ctx* ctx, const void* d_beta, void* d_y, int precision);
@@ -297,6 +331,14 @@ csipm_status csipm_mlp_loss_grad(const float* d_params, const float* d_feat, con
                                  void* hip_stream);
 csipm_status csipm_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, int t, float lr,
                             void* hip_stream);
+/* One training step of the network on n_rec records: loss_grad at the
+ * current parameters (loss to d_loss_out, gradient to d_grad), then adam
+ * with step count t on d_params, d_m, d_v; the same kernels as those two
+ * calls, queued in that order.  The moments are two arrays (m, v) and the
+ * step count is the caller's; d_scratch is as for loss_grad. */
+csipm_status csipm_mlp_train_step(float* d_params, float* d_m, float* d_v, int t, float lr, const float* d_feat,
+                                  const float* d_rec, int n_rec, double* d_loss_out, float* d_grad, void* d_scratch,
+                                  size_t scratch_bytes, void* hip_stream);
 
 /* Training-record capture during csipm_solve with the paper's
  * preconditioner.  At every interior-point iteration (up to max_iters), the

@@ -45,7 +45,9 @@ class Info(C.Structure):
                 ("cg_iters_total", C.c_longlong), ("refine_steps_total", C.c_int), ("fallbacks", C.c_int),
                 ("rel_kkt", C.c_double), ("res_beta_inf", C.c_double), ("res_z_inf", C.c_double),
                 ("compl_max", C.c_double), ("mu", C.c_double), ("lambda_", C.c_double), ("xi_inf", C.c_double),
-                ("solve_seconds", C.c_double)]
+                ("solve_seconds", C.c_double), ("objective", C.c_double), ("dual_objective", C.c_double),
+                ("rel_dual_gap", C.c_double), ("natural_residual", C.c_double), ("g_inf", C.c_double),
+                ("setup_seconds", C.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -91,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "csipm_mlp_backward": (I, [P, P, P, P, I, P, S, P]),
         "csipm_mlp_loss_grad": (I, [P, P, P, I, P, P, P, S, P]),
         "csipm_mlp_adam": (I, [P, P, P, P, I, F, P]),
+        "csipm_mlp_train_step": (I, [P, P, P, I, F, P, P, I, P, P, P, S, P]),
         "csipm_capture": (I, [P, I, P, P, I, I, C.c_ulonglong]),
         "csipm_captured": (I, [P, C.POINTER(I), P, I]),
         "csipm_features": (I, [P, P]),
@@ -378,6 +381,19 @@ def mlp_loss_grad(params, feat, rec, scratch=None):
     sc, nb = scratch if scratch is not None else _scratch(n, feat.device)
     _check(lib().csipm_mlp_loss_grad(_ptr(params), _ptr(feat), _ptr(rec), n, _ptr(loss), _ptr(g), _ptr(sc), nb,
                                      _stream()), "mlp_loss_grad")
+    return loss, g
+
+
+def mlp_train_step(params, m, v, t, lr, feat, rec, scratch=None):
+    """csipm_mlp_train_step: loss and gradient at params, then one Adam step
+    (params, m, v updated in place); returns (loss, grad)."""
+    import torch
+    n = feat.shape[0]
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feat.device)
+    loss = torch.empty(1, dtype=torch.float64, device=feat.device)
+    sc, nb = scratch if scratch is not None else _scratch(n, feat.device)
+    _check(lib().csipm_mlp_train_step(_ptr(params), _ptr(m), _ptr(v), int(t), float(lr), _ptr(feat), _ptr(rec), n,
+                                      _ptr(loss), _ptr(g), _ptr(sc), nb, _stream()), "mlp_train_step")
     return loss, g
 
 

@@ -80,6 +80,7 @@ struct csipm_ctx {
   bool have_params = false;
   double xi_inf = 0.0;
   long long nobs = 0;
+  double setup_s = 0.0;   // wall time of csipm_create
   std::vector<csipm_iter_log> log;
   // capture of training records
   int cap_enable = 0, cap_per_iter = 0, cap_max = 0, cap_count = 0;
@@ -598,6 +599,7 @@ csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double*
   if ((reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0) return CSIPM_EINVAL;
   const size_t need = csipm_workspace_bytes(n1, n2, n3);
   if (workspace_bytes < need) return CSIPM_ENOMEM;
+  const auto t_create = std::chrono::steady_clock::now();
   csipm_ctx* c = new (std::nothrow) csipm_ctx();
   if (!c) return CSIPM_ENOMEM;
   c->g = Grid{n1, n2, n3, n3 / 2, (long long)n1 * n2 * n3};
@@ -670,8 +672,9 @@ csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double*
   fill<double>(c->sig2, 1.0, n, c->s);
   fill<float>(c->sig1f, 1.0f, n, c->s);
   fill<float>(c->sig2f, 1.0f, n, c->s);
-  st = hip_check(c, "create");
+  st = sync_scalars(c, "create");
   if (st != CSIPM_OK) { csipm_destroy(c); return st; }
+  c->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_create).count();
   *out = c;
   return CSIPM_OK;
 }
@@ -860,6 +863,29 @@ csipm_status residuals(csipm_ctx* c, Resid& r, bool logsum) {
   csipm_status st = sync_scalars(c, "residuals");
   if (st != CSIPM_OK) return st;
   r = read_resid(c);
+  return CSIPM_OK;
+}
+
+// LASSO certificate of beta from G = H beta - xi (which must be exact: an
+// FP64 H-apply, not the carried value) into the certificate fields of inf;
+// synchronises.
+csipm_status certificate(csipm_ctx* c, csipm_info& inf) {
+  KT(c, "lasso_cert+fin", lasso_cert(c->beta, c->hb, c->lambda, c->g.n, c->partV, c->scal + S_CERT, c->s));
+  csipm_status st = sync_scalars(c, "certificate");
+  if (st != CSIPM_OK) return st;
+  const double* q = c->hscal + S_CERT;
+  const double rr = q[0], l1 = q[1], termwise = q[2], bG = q[3], ginf = q[4], nat = q[5], bmax = q[6];
+  const double lam = c->lambda;
+  // dual point theta = s r, scaled into ||M_perp^T theta||_inf <= lambda
+  const double sc = ginf > lam ? lam / ginf : 1.0;
+  const double bg = -bG;   // beta.g with g = -G
+  inf.objective = 0.5 * rr + lam * l1;
+  inf.dual_objective = sc * (rr + bg) - 0.5 * sc * sc * rr;
+  const double gap = 0.5 * (1.0 - sc) * (1.0 - sc) * rr + termwise + (1.0 - sc) * bg;
+  inf.rel_dual_gap = gap / std::max(std::fabs(inf.objective), 1e-300);
+  inf.natural_residual = nat / std::max(1.0, bmax);
+  inf.g_inf = ginf;
+  inf.setup_seconds = c->setup_s;
   return CSIPM_OK;
 }
 
@@ -1166,6 +1192,9 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     c->log.push_back(csipm_iter_log{it, cgi, ref, fell ? 1 : 0, use_learned ? 1 : 0, mu, rel, 0.0, relevant});
     inf.ipm_iters = it + 1;
   }
+  // (every exit of the loop above follows an FP64 recomputation of G)
+  st = certificate(c, inf);
+  if (st != CSIPM_OK) return st;
   inf.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   inf.status = result;
   ++c->solves;
@@ -1235,7 +1264,7 @@ csipm_status csipm_get_residuals(csipm_ctx* c, csipm_info* out) {
   out->rel_kkt = std::max(std::max(r.fb, r.fz), r.cmax) / (1.0 + c->xi_inf);
   out->lambda = c->lambda;
   out->xi_inf = c->xi_inf;
-  return CSIPM_OK;
+  return certificate(c, *out);
 }
 
 csipm_status csipm_get_log(csipm_ctx* c, csipm_iter_log* host_buf, int max_records, int* n_records) {
@@ -1316,13 +1345,13 @@ csipm_status csipm_apply_Pinv(csipm_ctx* c, const void* d_rb, const void* d_rz, 
   if (precision == CSIPM_FP64) {
     launch_to_internal<double, double>(c->g, (const double*)d_rb, c->rb, c->s);
     launch_to_internal<double, double>(c->g, (const double*)d_rz, c->rz, c->s);
-    pinv_apply<double>(c->rb, c->rz, c->zb, c->zz, c->sig1, c->sig2, c->pc_c, c->g.n, c->partV, nullptr, c->s);
+    pinv_apply<double>(c->rb, c->rz, c->zb, c->zz, c->sig1, c->sig2, nullptr, c->g.n, c->partV, nullptr, c->s);
     launch_to_external<double, double>(c->g, c->zb, (double*)d_zb, c->s);
     launch_to_external<double, double>(c->g, c->zz, (double*)d_zz, c->s);
   } else if (precision == CSIPM_FP32) {
     launch_to_internal<float, float>(c->g, (const float*)d_rb, c->frb, c->s);
     launch_to_internal<float, float>(c->g, (const float*)d_rz, c->frz, c->s);
-    pinv_apply<float>(c->frb, c->frz, c->fzb, c->fzz, c->sig1f, c->sig2f, c->pc_c, c->g.n, c->partV, nullptr,
+    pinv_apply<float>(c->frb, c->frz, c->fzb, c->fzz, c->sig1f, c->sig2f, nullptr, c->g.n, c->partV, nullptr,
                       c->s);
     launch_to_external<float, float>(c->g, c->fzb, (float*)d_zb, c->s);
     launch_to_external<float, float>(c->g, c->fzz, (float*)d_zz, c->s);
@@ -1387,6 +1416,16 @@ csipm_status csipm_mlp_adam(float* d_params, const float* d_grad, float* d_m, fl
   if (!d_params || !d_grad || !d_m || !d_v || t < 1 || !(lr > 0.0f)) return CSIPM_EINVAL;
   mlp_adam(d_params, d_grad, d_m, d_v, t, lr, reinterpret_cast<hipStream_t>(hip_stream));
   return hipGetLastError() == hipSuccess ? CSIPM_OK : CSIPM_EHIP;
+}
+
+csipm_status csipm_mlp_train_step(float* d_params, float* d_m, float* d_v, int t, float lr, const float* d_feat,
+                                  const float* d_rec, int n_rec, double* d_loss_out, float* d_grad, void* d_scratch,
+                                  size_t scratch_bytes, void* hip_stream) {
+  if (!d_params || !d_m || !d_v || t < 1 || !(lr > 0.0f)) return CSIPM_EINVAL;
+  const csipm_status st =
+      csipm_mlp_loss_grad(d_params, d_feat, d_rec, n_rec, d_loss_out, d_grad, d_scratch, scratch_bytes, hip_stream);
+  if (st != CSIPM_OK) return st;
+  return csipm_mlp_adam(d_params, d_grad, d_m, d_v, t, lr, hip_stream);
 }
 
 csipm_status csipm_capture(csipm_ctx* c, int enable, float* d_feat, float* d_rec, int n_per_iter, int max_iters,

@@ -34,7 +34,8 @@ enum ScalarSlot {
   S_SMU = 15,      // target sigma mu of the next Newton system built with the step
   S_RESID = 16,    // IPM residual block, 10 values (k_ipm_resid order)
   S_SIG = 28,      // signal check: non-finite count, observed count
-  S_MISC = 32,     // free scratch (32 values)
+  S_MISC = 32,     // free scratch (8 values)
+  S_CERT = 40,     // LASSO certificate sums of lasso_cert (NCERT_Q values)
   S_COUNT = 64
 };
 // int slots of the device flag block
@@ -159,5 +160,15 @@ template <typename T>
 void fill(T* a, T v, long long n, hipStream_t s);
 void absmax(const double* a, long long n, double* partial, double* out, hipStream_t s);
 void diag_h(const double* bm_ext, double* out_ext, int n1, int n2, int n3, double mfrac, hipStream_t s);
+
+// LASSO optimality and duality gap of beta (equation "realopt" and its dual)
+// from G = H beta - xi = -M_perp^T r, r = b - M_perp beta (M_perp^T is an
+// isometry on the observed samples, so ||r|| = ||G||).  out[0..NCERT_Q):
+//   sum G^2 (= ||r||^2), sum |beta|, sum (lam |beta_i| + beta_i G_i)
+//   (= lam ||beta||_1 - beta.g, summed termwise), sum beta_i G_i,
+//   max |G| (= ||g||_inf), max |beta - soft(beta - G, lam)|, max |beta|
+constexpr int NCERT_Q = 7;
+void lasso_cert(const double* beta, const double* g, double lam, long long n, double* partial, double* out,
+                hipStream_t s);
 
 }  // namespace csipm

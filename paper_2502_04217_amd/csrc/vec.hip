@@ -1015,6 +1015,29 @@ k_diag_h(const double* __restrict__ bm, double* __restrict__ out, int n1, int n2
   }
 }
 
+// Certificate sums of the LASSO solution beta (lasso_cert in vec.h); the
+// natural residual uses g = -G: soft(beta + g, lam) = soft(beta - G, lam).
+__global__ void __launch_bounds__(256)
+k_lasso_cert(const double* __restrict__ beta, const double* __restrict__ g, double lam, long long n,
+             double* partial) {
+  double v[NCERT_Q] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (long long i = gtid(); i < n; i += gstride()) {
+    const double b = beta[i], G = g[i];
+    const double ab = fabs(b);
+    v[0] += G * G;
+    v[1] += ab;
+    v[2] += lam * ab + b * G;
+    v[3] += b * G;
+    v[4] = fmax(v[4], fabs(G));
+    const double x = b - G;
+    const double sx = x > lam ? x - lam : (x < -lam ? x + lam : 0.0);
+    v[5] = fmax(v[5], fabs(b - sx));
+    v[6] = fmax(v[6], ab);
+  }
+  const int ops[NCERT_Q] = {RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_MAX, RED_MAX, RED_MAX};
+  block_reduce_store<NCERT_Q>(v, ops, partial, VEC_MAX_BLOCKS);
+}
+
 }  // namespace
 
 int vec_blocks(long long n) {
@@ -1220,6 +1243,14 @@ void absmax(const double* a, long long n, double* partial, double* out, hipStrea
   hipLaunchKernelGGL(k_absmax, VB, a, n, partial);
   RedOps<1> ops{{RED_MAX}};
   hipLaunchKernelGGL((k_fin_reduce<1>), dim3(1), dim3(kFinThreads), 0, s, partial, nb, VEC_MAX_BLOCKS, out, ops);
+}
+void lasso_cert(const double* beta, const double* g, double lam, long long n, double* partial, double* out,
+                hipStream_t s) {
+  const int nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_lasso_cert, VB, beta, g, lam, n, partial);
+  RedOps<NCERT_Q> ops{{RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_MAX, RED_MAX, RED_MAX}};
+  hipLaunchKernelGGL((k_fin_reduce<NCERT_Q>), dim3(1), dim3(kFinThreads), 0, s, partial, nb, VEC_MAX_BLOCKS, out,
+                     ops);
 }
 void diag_h(const double* bm_ext, double* out_ext, int n1, int n2, int n3, double mfrac, hipStream_t s) {
   const long long n = (long long)n1 * n2 * n3;

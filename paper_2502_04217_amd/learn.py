@@ -8,7 +8,7 @@ the Newton solve to `n_per_iter` records (features + loss terms) at
 pseudo-random coefficients, weighted by that system's PCG count.
 
 Training: Adam on the records with the library's forward/backward kernels
-(csipm_mlp_loss_grad, csipm_mlp_adam); each step uses the records of one
+(csipm_mlp_train_step: loss_grad, then adam); each step uses the records of one
 captured iteration, iterations visited in a seeded random order.
 
 Evaluation: held-out seeds solved with the paper's preconditioner and with
@@ -97,10 +97,9 @@ def train(feats, recs, epochs=20, lr=2e-3, seed=0, log=print):
         tot = 0.0
         losses = []
         for i in order:
-            loss, g = csipm.mlp_loss_grad(params, feats[i], recs[i], scratch)
             t += 1
             lr_t = lr * 0.5 * (1 + math.cos(math.pi * min(1.0, t / (epochs * len(order)))))
-            csipm.mlp_adam(params, g, m, v, t, max(lr_t, 1e-5))
+            loss, _ = csipm.mlp_train_step(params, m, v, t, max(lr_t, 1e-5), feats[i], recs[i], scratch)
             losses.append(loss)
         tot = float(torch.cat(losses).sum().item())
         hist.append(tot)

@@ -96,6 +96,9 @@ def main(argv=None):
     ap.add_argument("--record", nargs=3, metavar=("KERNEL", "NAME", "GRID"),
                     help="print a traffic-record line for the rocprof kernel KERNEL (short name), timed as NAME "
                          "by csipm_timing, at GRID^3, stamped with the current kernel-source digest")
+    ap.add_argument("--record-group", nargs="+", metavar="ARG",
+                    help="NAME GRID KERNEL [KERNEL ...]: a traffic-record line for the sum of one working "
+                         "dispatch of each listed rocprof kernel (short names), e.g. the kernels of one K-apply")
     a = ap.parse_args(argv)
     if a.fetch_db and a.write_db:
         tr, (ff, fw) = calibrated_traffic(a.fetch_db, a.write_db, a.calib_bytes)
@@ -110,6 +113,16 @@ def main(argv=None):
             kern, name, grid = a.record
             fe, wr = tr[kern]
             print("traffic-record: " + json.dumps({"kernel": name, "rocprof_kernel": kern, "grid": int(grid),
+                                                   "read_bytes": round(fe), "write_bytes": round(wr),
+                                                   "fetch_factor": round(ff, 4), "write_factor": round(fw, 4),
+                                                   "source_sha256": source_digest()}))
+        if a.record_group:
+            import json
+            from .build import source_digest
+            name, grid, kerns = a.record_group[0], a.record_group[1], a.record_group[2:]
+            fe = sum(tr[k][0] for k in kerns)
+            wr = sum(tr[k][1] for k in kerns)
+            print("traffic-record: " + json.dumps({"kernel": name, "rocprof_kernels": kerns, "grid": int(grid),
                                                    "read_bytes": round(fe), "write_bytes": round(wr),
                                                    "fetch_factor": round(ff, 4), "write_factor": round(fw, 4),
                                                    "source_sha256": source_digest()}))

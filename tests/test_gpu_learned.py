@@ -75,6 +75,26 @@ def test_adam_matches_oracle():
     assert np.abs(tp.cpu().numpy() - pr).max() <= 1e-6
 
 
+def test_train_step_equals_loss_grad_then_adam():
+    """csipm_mlp_train_step queues the loss_grad and adam kernels in that
+    order: parameters, moments, loss and gradient equal (bit for bit) those of
+    the two separate calls, over three steps."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    f, r = _records(3000, 21)
+    tf, tr = torch.tensor(f, device="cuda"), torch.tensor(r, device="cuda")
+    p0 = torch.tensor(_params(5), device="cuda")
+    pa, ma, va = p0.clone(), torch.zeros_like(p0), torch.zeros_like(p0)
+    pb, mb, vb = p0.clone(), torch.zeros_like(p0), torch.zeros_like(p0)
+    for t in (1, 2, 3):
+        la, ga = csipm.mlp_train_step(pa, ma, va, t, 1e-3, tf, tr)
+        lb, gb = csipm.mlp_loss_grad(pb, tf, tr)
+        csipm.mlp_adam(pb, gb, mb, vb, t, 1e-3)
+        assert torch.equal(la, lb) and torch.equal(ga, gb)
+        assert torch.equal(pa, pb) and torch.equal(ma, mb) and torch.equal(va, vb)
+    assert not torch.equal(pa, p0)
+
+
 def test_features_of_iterate():
     torch = need_gpu()
     from paper_2502_04217_amd import csipm

@@ -23,6 +23,13 @@ MIXED_SHAPES = [(_MIXED[i], _MIXED[(i + 1) % 8], _MIXED[(i + 2) % 8]) for i in r
 LOWDIM_SHAPES = [(1, 64, 64), (1, 1, 256), (2, 96, 40), (1, 560, 12), (64, 1, 32), (2, 2, 8), (1, 1, 4)]
 # odd extents on axes 1 and 2 (no Nyquist index there)
 ODD_SHAPES = [(3, 5, 8), (7, 9, 12), (15, 21, 16), (35, 45, 20), (45, 35, 64), (1, 21, 28), (5, 1, 40), (9, 7, 96)]
+# the pencil lengths of the full-size workloads: 256 and 512 on the strided
+# axes (the axis-1 inverse tile of 16 pencils at 8 values per thread in FP64
+# from 512, the K epilogue at 256), N3 = 256 and 512 in 3D grids (the
+# axis-3 pass at half lengths 128 and 256, c2r + mask + r2c), and one grid
+# that fills several workgroups of each pass at L = 256
+BENCH_SHAPES = [(256, 16, 8), (16, 256, 8), (8, 8, 256), (512, 4, 8), (4, 512, 8), (4, 4, 512), (256, 64, 16),
+                (16, 32, 256)]
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
@@ -35,7 +42,7 @@ def _problem(shape, seed=0):
     return torch, csipm, csipm.Problem(sig, obs), sig, obs
 
 
-@pytest.mark.parametrize("shape", SHAPES + MIXED_SHAPES + LOWDIM_SHAPES + ODD_SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + BENCH_SHAPES + MIXED_SHAPES + LOWDIM_SHAPES + ODD_SHAPES)
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_operator_parity(shape, prec):
     torch, csipm, pr, sig, obs = _problem(shape, 1)

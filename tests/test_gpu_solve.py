@@ -4,6 +4,9 @@ relative (both sides stopped at rel_kkt 1e-11), identical support above
 64^3 workloads, in FP64 and FP32-with-refinement; closed forms (nothing
 missing -> soft threshold, lambda >= ||xi||_inf -> 0); the LASSO certificate
 at 256^3 computed by the oracle from the GPU solution."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -20,17 +23,26 @@ pytestmark = pytest.mark.gpu
 # solution); at 1e-11 every workload here is within 1e-9 of it, and the FP32
 # form stays above its precision floor (mu ~ 1e-14 on 64^3).
 PARITY_TOL = 1e-11
+PARAMS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2502_04217_amd",
+                      "pc_params.json")
 
 
-def _supports_match(bg, bo, rel=1e-6):
+def _supports_match(bg, bo, rel=1e-6, max_amb_frac=0.01):
     """Identical support above rel*max|beta|; coordinates of either side in
-    the band [0.1 rel, 10 rel] max|beta| are reported ambiguous, not compared."""
+    the band [0.1 rel, 10 rel] max|beta| are reported ambiguous, not compared,
+    and there may be at most max(1, max_amb_frac * |support|) of them (on
+    every parity workload the oracle's own solution has none), so a wide
+    band cannot make the comparison vacuous."""
     m = max(np.abs(bo).max(), 1e-300)
     sg = np.abs(bg) > rel * m
     so = np.abs(bo) > rel * m
     amb = ((np.abs(bo) > 0.1 * rel * m) & (np.abs(bo) < 10 * rel * m)) | \
           ((np.abs(bg) > 0.1 * rel * m) & (np.abs(bg) < 10 * rel * m))
-    return bool(np.all((sg == so) | amb)), int(amb.sum())
+    n_amb = int(amb.sum())
+    bound = max(1, int(max_amb_frac * int(so.sum())))
+    if n_amb:
+        say("  ambiguous support coordinates", n_amb, "of", int(so.sum()), "bound", bound)
+    return bool(np.all((sg == so) | amb)) and n_amb <= bound, n_amb
 
 
 def _gpu_solve(w, lam, **opts):
@@ -199,10 +211,30 @@ def test_iteration_limit_status():
     assert info["status"] == 1 and info["ipm_iters"] == 3
 
 
-def test_grid256_certificate_fp64_and_fp32():
-    """256^3 at the metric's tolerance (1e-6): the oracle certifies the GPU
-    solutions (optimality conditions and duality gap from two naive
-    transforms), and the FP32+refinement solution matches the FP64 one."""
+def _certify(label, beta, info, w, lam):
+    """Oracle certificate of a GPU solution at the metric's tolerance
+    (rel_kkt 1e-6): off-support |g_i| <= lambda (1 + 1e-4), relative duality
+    gap <= 1e-4, and the library's own certificate fields equal the
+    oracle's (gap to 1e-10, natural residual to 1e-9, objective to 1e-12
+    relative)."""
+    cert = ipm.lasso_certificate(beta, w.signal, w.observed, lam)
+    say(f"  {label} oracle certificate: off-support {cert.max_offsupport_ratio:.8f} gap {cert.rel_gap:.3e} "
+        f"natural residual {cert.natural_residual:.3e}; library gap {info['rel_dual_gap']:.3e} "
+        f"natural residual {info['natural_residual']:.3e}")
+    assert cert.max_offsupport_ratio <= 1.0 + 1e-4
+    assert cert.rel_gap <= 1e-4
+    assert abs(info["rel_dual_gap"] - cert.rel_gap) <= 1e-10
+    assert abs(info["natural_residual"] - cert.natural_residual) <= 1e-9
+    assert abs(info["objective"] - cert.primal) <= 1e-12 * abs(cert.primal)
+    return cert
+
+
+def test_grid256_certificate_chosen_form_and_fp64():
+    """256^3 (the benchmark workload) at the metric's tolerance (1e-6): the
+    oracle certifies the plain FP64 solution and the chosen form's (FP32
+    Krylov with FP64 refinement and the learned correction) from two naive
+    transforms each, and the two solutions agree to 1e-4 (near-support
+    coordinates still move like mu at rel_kkt 1e-6)."""
     torch = need_gpu()
     from paper_2502_04217_amd import csipm
     w = wl.grid256(1)
@@ -212,17 +244,66 @@ def test_grid256_certificate_fp64_and_fp32():
     i64 = pr.solve(tol=1e-6, precision=0)
     b64 = pr.get(csipm.BETA).cpu().numpy()
     say("  ", i64)
-    say("256^3 FP32+refine solve")
-    i32 = pr.solve(tol=1e-6, precision=1)
+    pc = csipm.PC_PLAIN
+    if os.path.exists(PARAMS):
+        with open(PARAMS) as fh:
+            pr.set_pc_params(torch.tensor(json.load(fh)["params"], dtype=torch.float32, device="cuda"))
+        pc = csipm.PC_LEARNED
+    say("256^3 chosen form (FP32 + refinement, pc", pc, ")")
+    i32 = pr.solve(tol=1e-6, precision=1, pc=pc)
     b32 = pr.get(csipm.BETA).cpu().numpy()
     say("  ", i32)
-    assert i64["status"] == 0 and i32["status"] == 0
-    say("  rel diff fp32 vs fp64", rel2(b32, b64))
+    assert i64["status"] == 0 and i32["status"] in (0, 3)
+    say("  rel diff chosen vs fp64", rel2(b32, b64))
     assert rel2(b32, b64) <= 1e-4
-    cert = ipm.lasso_certificate(b64, w.signal, w.observed, lam)
-    say("  certificate", cert.natural_residual, cert.rel_gap, cert.max_offsupport_ratio)
-    assert cert.max_offsupport_ratio <= 1.0 + 1e-4
-    assert cert.rel_gap <= 1e-4
+    _certify("fp64", b64, i64, w, lam)
+    _certify("chosen", b32, i32, w, lam)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_certificate_fields_match_oracle(precision):
+    """csipm_info's LASSO certificate (objective, dual objective, relative
+    duality gap, natural residual, ||g||_inf) equals the oracle's
+    lasso_certificate of the same beta at 64^3, after the solve and from
+    csipm_get_residuals; the gap to 1e-10 (the oracle forms it as a
+    difference of two objectives, the library termwise)."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid64(1)
+    pr = csipm.Problem(w.signal, w.observed)
+    lam = pr.lambda_rule(0.05)
+    info = pr.solve(tol=1e-8, precision=precision)
+    beta = pr.get(csipm.BETA).cpu().numpy()
+    cert = ipm.lasso_certificate(beta, w.signal, w.observed, lam)
+    res = pr.residuals()
+    say("  certificate", precision, info["rel_dual_gap"], cert.rel_gap, info["natural_residual"],
+        cert.natural_residual, info["setup_seconds"])
+    assert info["setup_seconds"] > 0
+    for d in (info, res):
+        assert abs(d["objective"] - cert.primal) <= 1e-12 * abs(cert.primal)
+        assert abs(d["dual_objective"] - cert.dual) <= 1e-10 * abs(cert.primal)
+        assert abs(d["rel_dual_gap"] - cert.rel_gap) <= 1e-10
+        assert abs(d["natural_residual"] - cert.natural_residual) <= 1e-10
+        assert abs(d["g_inf"] - float(np.abs(cert.g).max())) <= 1e-12 * float(np.abs(cert.g).max())
+    assert 0 <= info["rel_dual_gap"] <= 1e-6
+
+
+def test_apply_pinv_is_the_papers_preconditioner_after_any_solve():
+    """apply_Pinv applies the paper's P (C = I) even after a solve with the
+    scaled identity, whose rho is kept in the correction buffer."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid16(2)
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.lambda_rule(0.05)
+    pr.solve(tol=1e-8, pc=csipm.PC_SCALED)
+    s1, s2 = wl.random_barrier(w.shape, 3, spread=3.0)
+    pr.set_barrier(torch.tensor(s1, device="cuda"), torch.tensor(s2, device="cuda"))
+    rng = np.random.default_rng(4)
+    rb, rz = rng.standard_normal(w.shape), rng.standard_normal(w.shape)
+    zb, zz = pr.apply_Pinv(torch.tensor(rb, device="cuda"), torch.tensor(rz, device="cuda"))
+    ob, oz = ipm.Pinv_apply(rb, rz, s1, s2)
+    assert rel2(zb.cpu().numpy(), ob) <= 1e-13 and rel2(zz.cpu().numpy(), oz) <= 1e-13
 
 
 def test_kernel_timing_records():
@@ -263,32 +344,58 @@ def test_kernel_timing_records():
     assert pr.timing_report(0.0) == rep
 
 
-def test_grid512_fp32_tracks_fp64():
-    """512^3 (the full-size workload): the FP32 form with the paper's P
-    follows the FP64 form iteration by iteration and converges with it.
+@pytest.mark.timeout(900)
+def test_grid512_chosen_form_certified():
+    """512^3, the full chosen form against plain FP64: the FP32 form with the
+    paper's P follows the FP64 form iteration by iteration, the chosen form
+    (FP32 + refinement + the learned correction) converges to the same
+    solution within 1e-4, and the oracle certifies the chosen form's
+    solution (two naive 512^3 transforms on the host, about a minute): the
+    LASSO optimality conditions, the duality gap, and the library's own
+    certificate fields.
     Regression: a refinement test on the preconditioned norm alone let FP32
     solutions through whose d_beta + d_z was misrepresented where one slack
     is tiny; the single large residual components then grew rel_kkt from
     7e-6 back to 1e-1 and the solve never converged."""
     torch = need_gpu()
     from paper_2502_04217_amd import csipm
+    say("512^3 workload")
     w = wl.grid512(1)
     pr = csipm.Problem(w.signal, w.observed)
-    pr.lambda_rule(0.05)
+    lam = pr.lambda_rule(0.05)
     i64 = pr.solve(tol=1e-6, precision=0, max_iter=30)
     log64 = pr.log()
     b64 = pr.get(csipm.BETA)
+    say("512^3 fp64", i64["ipm_iters"], i64["rel_kkt"], i64["rel_dual_gap"], i64["solve_seconds"])
     i32 = pr.solve(tol=1e-6, precision=1, pc=0, max_iter=30)
     log32 = pr.log()
     b32 = pr.get(csipm.BETA)
-    say("512^3 fp64", i64["ipm_iters"], i64["rel_kkt"], "fp32", i32["ipm_iters"], i32["rel_kkt"])
+    say("512^3 fp32 paper P", i32["ipm_iters"], i32["rel_kkt"], i32["rel_dual_gap"], i32["solve_seconds"])
     assert i64["status"] == 0 and i32["status"] == 0
     assert i32["ipm_iters"] <= i64["ipm_iters"] + 1
     for a, b in zip(log32, log64):
         assert abs(a["rel_kkt"] - b["rel_kkt"]) <= 0.05 * b["rel_kkt"]
     assert float((b32 - b64).norm() / b64.norm()) <= 1e-4
-    del pr
+    del b32
+    pc = csipm.PC_PLAIN
+    if os.path.exists(PARAMS):
+        with open(PARAMS) as fh:
+            pr.set_pc_params(torch.tensor(json.load(fh)["params"], dtype=torch.float32, device="cuda"))
+        pc = csipm.PC_LEARNED
+    ic = pr.solve(tol=1e-6, precision=1, pc=pc, max_iter=30)
+    bc = pr.get(csipm.BETA)
+    say("512^3 chosen form (pc", pc, ")", ic["ipm_iters"], ic["rel_kkt"], ic["rel_dual_gap"], ic["solve_seconds"],
+        [r["learned"] for r in pr.log()])
+    assert ic["status"] in (0, 3)
+    say("  rel diff chosen vs fp64", float((bc - b64).norm() / b64.norm()))
+    assert float((bc - b64).norm() / b64.norm()) <= 1e-4
+    for info in (i64, i32, ic):
+        assert info["rel_dual_gap"] <= 1e-4 and info["g_inf"] <= lam * (1 + 1e-4)
+    beta = bc.cpu().numpy()
+    del pr, bc, b64
     torch.cuda.empty_cache()
+    say("  oracle certificate of the chosen form (512^3, two naive transforms)")
+    _certify("chosen", beta, ic, w, lam)
 
 
 @pytest.mark.parametrize("krylov,scaled", [(1, False), (0, True), (1, True)])
@@ -318,29 +425,37 @@ def test_cr_and_scaled_pc_parity(krylov, scaled, precision):
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("grid,tol", [("grid16", 1e-9), ("grid64", 1e-7)])
 def test_car_parity(grid, tol, precision):
-    """Conjugate A-residuals against the oracle's pcar, both stopped at the
-    same tolerance: the residual of CAr stops decreasing near 1e-9 relative
-    on late interior-point systems (at 64^3 the oracle's CAr solve breaks
-    down below 1e-7).  FP64 follows the oracle's iterates (same Krylov
-    counts over the first iterations, beta within 1e-7); FP32 with
-    refinement stops at a different iterate of the same path, within 1e-7 at
-    1e-9 and 1e-5 at 1e-7 (near-support coordinates converge like mu)."""
+    """Conjugate A-residuals against the oracle: the residual of CAr stops
+    decreasing near 1e-9 relative on late interior-point systems (at 64^3
+    the oracle's FP64 CAr breaks down below 1e-7, and so does the library's:
+    its FP64 form stalls at rel_kkt 2.9e-8).  FP64 follows the oracle's pcar
+    iterates, both stopped at the same tolerance (same Krylov counts over
+    the first iterations, beta within 1e-7).  The FP32 form with FP64
+    refinement is not limited by that floor (the refinement residual is
+    FP64): at 16^3 it is compared with the oracle's pcar at 1e-9, and at
+    64^3 it solves to 1e-9 (it reaches 3e-11) and is compared with the
+    oracle's LASSO solution (CG, 1e-11), the unique minimiser both converge
+    to; the bar is 1e-7 in every case."""
     from paper_2502_04217_amd import csipm
     w = wl.grid16(4) if grid == "grid16" else wl.grid64(1)
     lam = ipm.lambda_rule(w.signal, w.observed)
-    ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=tol, krylov="car"))
+    gpu_tol = tol if (precision == 0 or grid == "grid16") else 1e-9
+    if precision == 1 and grid == "grid64":
+        ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=PARITY_TOL))
+    else:
+        ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=tol, krylov="car"))
     assert ref.converged
-    pr, info, beta = _gpu_solve(w, lam, tol=tol, precision=precision, krylov=csipm.KRYLOV_CAR)
+    pr, info, beta = _gpu_solve(w, lam, tol=gpu_tol, precision=precision, krylov=csipm.KRYLOV_CAR)
     say("  car", grid, precision, info["status_name"], info["ipm_iters"], info["cg_iters_total"],
         [r["cg_iters"] for r in pr.log()], "oracle", ref.iters, ref.cg_iters)
     assert info["status"] == 0
-    bar = 1e-7 if (precision == 0 or tol <= 1e-9) else 1e-5
+    assert info["rel_kkt"] <= gpu_tol
     err = rel2(beta, ref.state.beta)
     say("  rel err vs oracle", err)
-    assert err <= bar
+    assert err <= 1e-7
+    ok, amb = _supports_match(beta, ref.state.beta)
+    assert ok
     if precision == 0:
-        ok, amb = _supports_match(beta, ref.state.beta)
-        assert ok
         for a, b in zip(pr.log()[:6], ref.log[:6]):
             assert a["cg_iters"] == b["cg"]
 

@@ -118,3 +118,97 @@ def test_features_shape_and_ranges():
     assert np.all(np.abs(f[:, 1]) < 1)
     assert f[:, 2].max() < 1e-11
     assert np.allclose(f[:, 3], 1.0)
+
+
+# --- features and gate pinned by values worked out by hand -------------------
+# Three coefficients with barrier diagonals chosen so that L1 = S1 + S2 and
+# L2 = S1 - S2 are small integers:
+#   S1 = (1, 2, 0.5), S2 = (1, 6, 1.5)  ->  L1 = (2, 8, 2), L2 = (0, -4, -1).
+# log L1 = (ln 2, 3 ln 2, ln 2) has mean (5/3) ln 2, so
+#   f1 = (-2/3 ln 2, 4/3 ln 2, -2/3 ln 2),   f2 = L2/L1 = (0, -1/2, -1/2).
+# beta = (0, -3, 1.5), max|beta| = 3:
+#   f3 = (ln 1e-12, ln(1 + 1e-12), ln(1/2 + 1e-12)).
+# A feature formed from log S1 (mean 0: f1 = (0, ln 2, -ln 2)) or from
+# S1/L1 = (1/2, 1/4, 1/4) differs from these in every coefficient.
+_HAND_S1 = np.array([1.0, 2.0, 0.5])
+_HAND_S2 = np.array([1.0, 6.0, 1.5])
+_HAND_BETA = np.array([0.0, -3.0, 1.5])
+_HAND_DIAG = np.array([0.25, 0.5, 0.96875])
+_LN2 = 0.6931471805599453
+_HAND_F = np.array([[-2.0 / 3.0 * _LN2, 0.0, -27.631021115928547, 0.25],
+                    [4.0 / 3.0 * _LN2, -0.5, 9.999778782798785e-13, 0.5],
+                    [-2.0 / 3.0 * _LN2, -0.5, -0.6931471805579453, 0.96875]])
+
+
+def test_features_hand_values():
+    f = mlp.features(_HAND_S1, _HAND_S2, _HAND_BETA, _HAND_DIAG)
+    assert f.shape == (3, 4)
+    assert np.abs(f - _HAND_F).max() <= 1e-15 * 30
+
+
+def _one_path(feature):
+    """Parameters of a network whose output is o = tanh(tanh(x_feature)):
+    W1[0][feature] = 1, W2[0][0] = 1, w3[0] = 1, every other weight and
+    bias 0; the correction is then c = ln(1 + e^o) + 1e-6."""
+    W1 = np.zeros((mlp.H1, mlp.NIN))
+    W1[0, feature] = 1.0
+    W2 = np.zeros((mlp.H2, mlp.H1))
+    W2[0, 0] = 1.0
+    w3 = np.zeros(mlp.H2)
+    w3[0] = 1.0
+    return mlp.pack(W1, np.zeros(mlp.H1), W2, np.zeros(mlp.H2), w3, 0.0)
+
+
+@pytest.mark.parametrize("feature", [0, 1, 2, 3])
+def test_forward_one_path_network_hand_values(feature):
+    """Each feature routed alone through one hidden unit per layer: the
+    output is ln(1 + exp(tanh(tanh(f)))) + 1e-6, written out here for the
+    hand-evaluated features above.  A network that reads its inputs in
+    another order, drops a layer or uses another output map fails."""
+    import math
+    c, _ = mlp.forward(_one_path(feature), _HAND_F)
+    want = [math.log1p(math.exp(math.tanh(math.tanh(f)))) + 1e-6 for f in _HAND_F[:, feature]]
+    assert np.abs(c - np.array(want)).max() <= 1e-15
+
+
+def _gate_state(s1, s2):
+    """An iterate with beta = 0 and z = 1 (so both slacks are 1) whose
+    barrier diagonals are S1 = nu1, S2 = nu2."""
+    k = len(s1)
+    return np.zeros(k), np.ones(k), np.asarray(s1, float), np.asarray(s2, float)
+
+
+def test_relevance_gate_either_side_of_threshold():
+    """The correction acts where L1 >= 1e-3 (L1 + 4 S1 S2).  With S1 = S2 = s
+    that is 2s >= 1e-3 (2s + 4s^2), i.e. s <= 499.5; with S1 = 1e4, S2 = 1 it
+    is 10001 >= 1e-3 * 50001 (relevant), with S1 = S2 = 1e4 it is
+    2e4 >= 1e-3 * 4.00002e8 (not).  s = 600 separates the reading 4 S1 S2
+    from 2 S1 S2 (threshold s <= 999), and s = 499.4 / 499.6 sit either side
+    of the true one."""
+    s1 = [499.4, 499.6, 600.0, 1e4, 1e4, 1e-3]
+    s2 = [499.4, 499.6, 600.0, 1.0, 1e4, 1e-3]
+    want = np.array([True, False, False, True, False, True])
+    beta, z, nu1, nu2 = _gate_state(s1, s2)
+    diag = np.full(len(s1), 0.5)
+    params = mlp.init_params(0, out_scale=0.0)
+    params[-1] = 0.0      # c = ln 2 + 1e-6 wherever the network runs
+    c, act = mlp.correction(params, beta, z, nu1, nu2, diag)
+    assert np.array_equal(act, want)
+    assert np.allclose(c[want], np.log(2.0) + 1e-6, rtol=0, atol=1e-15)
+    assert np.all(c[~want] == 1.0)
+
+
+def test_correction_features_come_from_the_iterate():
+    """correction() forms S_j = nu_j / s_j with s1 = z + beta, s2 = z - beta:
+    for beta = (0, -3, 1.5), z = 4 the slacks are s1 = (4, 1, 5.5),
+    s2 = (4, 7, 2.5); nu1 = S1 s1 and nu2 = S2 s2 give back the hand
+    diagonals above, so the one-path network on f2 returns the values of
+    the hand features (all three coefficients relevant)."""
+    import math
+    z = np.full(3, 4.0)
+    s1, s2 = z + _HAND_BETA, z - _HAND_BETA
+    nu1, nu2 = _HAND_S1 * s1, _HAND_S2 * s2
+    c, act = mlp.correction(_one_path(1), _HAND_BETA, z, nu1, nu2, _HAND_DIAG)
+    assert np.all(act)
+    want = [math.log1p(math.exp(math.tanh(math.tanh(f)))) + 1e-6 for f in _HAND_F[:, 1]]
+    assert np.abs(c - np.array(want)).max() <= 1e-15
