@@ -340,6 +340,21 @@ csipm_status csipm_mlp_train_step(float* d_params, float* d_m, float* d_v, int t
                                   const float* d_rec, int n_rec, double* d_loss_out, float* d_grad, void* d_scratch,
                                   size_t scratch_bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training loops, hosts that forbid allocation):
+ * csipm_mlp_loss_grad without the workspace.  The gradient partials live in
+ * a fixed device array of the library, sized for CSIPM_MLP_NOALLOC_MAX_REC
+ * records (9.8 MiB), that every GPU the library runs on keeps until the
+ * process ends; the call itself allocates nothing.  n_rec above the maximum
+ * returns ENOMEM and queues nothing.  Calls that overlap on one GPU share
+ * the array and race.  The kernels and their reduction order are those of
+ * csipm_mlp_loss_grad, so the results are the same bit for bit.
+ * Errors: EINVAL, ENOMEM, EHIP; csipm_last_error(NULL) gives the message of
+ * the last failed call on the calling thread. */
+#define CSIPM_MLP_NOALLOC_MAX_REC 65536
+csipm_status csipm_mlp_loss_grad_noalloc(const float* d_params, const float* d_feat, const float* d_rec, int n_rec,
+                                         double* d_loss_out, float* d_grad, void* hip_stream);
+
 /* Training-record capture during csipm_solve with the paper's
  * preconditioner.  At every interior-point iteration (up to max_iters), the
  * first Krylov direction p = P^{-1} r_0 of the Newton solve and q = K p are
@@ -401,6 +416,8 @@ csipm_status csipm_timing_report(csipm_ctx* ctx, double min_us, csipm_kernel_tim
 
 csipm_status csipm_destroy(csipm_ctx* ctx);
 const char* csipm_status_string(int status);
+/* Message of the last failure on ctx; with ctx NULL, that of the last
+ * failed context-free call (csipm_mlp_loss_grad_noalloc) on this thread. */
 const char* csipm_last_error(const csipm_ctx* ctx);
 
 #ifdef __cplusplus

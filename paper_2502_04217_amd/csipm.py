@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "csipm_mlp_loss_grad": (I, [P, P, P, I, P, P, P, S, P]),
         "csipm_mlp_adam": (I, [P, P, P, P, I, F, P]),
         "csipm_mlp_train_step": (I, [P, P, P, I, F, P, P, I, P, P, P, S, P]),
+        "csipm_mlp_loss_grad_noalloc": (I, [P, P, P, I, P, P, P]),
         "csipm_capture": (I, [P, I, P, P, I, I, C.c_ulonglong]),
         "csipm_captured": (I, [P, C.POINTER(I), P, I]),
         "csipm_features": (I, [P, P]),
@@ -382,6 +383,19 @@ def mlp_loss_grad(params, feat, rec, scratch=None):
     _check(lib().csipm_mlp_loss_grad(_ptr(params), _ptr(feat), _ptr(rec), n, _ptr(loss), _ptr(g), _ptr(sc), nb,
                                      _stream()), "mlp_loss_grad")
     return loss, g
+
+
+NOALLOC_MAX_REC = 65536
+
+
+def mlp_loss_grad_noalloc(params, feat, rec, loss, grad):
+    """csipm_mlp_loss_grad_noalloc into caller-given loss (1 double) and grad
+    (1249 floats) tensors: nothing is allocated on the device by the call."""
+    st = lib().csipm_mlp_loss_grad_noalloc(_ptr(params), _ptr(feat), _ptr(rec), int(feat.shape[0]), _ptr(loss),
+                                           _ptr(grad), _stream())
+    if st != 0:
+        msg = lib().csipm_last_error(None)
+        raise CsipmError(st, f"mlp_loss_grad_noalloc: {msg.decode() if msg else ''}")
 
 
 def mlp_train_step(params, m, v, t, lr, feat, rec, scratch=None):

@@ -1588,6 +1588,6 @@ const char* csipm_status_string(int st) {
   return "unknown status";
 }
 
-const char* csipm_last_error(const csipm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* csipm_last_error(const csipm_ctx* c) { return c ? c->err.c_str() : noctx_last_error(); }
 
 }  // extern "C"

@@ -233,6 +233,9 @@ int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir);
 bool fft_extent_supported(int N, int axis);
 int postmix_blocks(const Grid& g);
 
+// message of the last failed context-free call on this thread (noalloc.hip)
+const char* noctx_last_error();
+
 // permutation between the external beta layout and the internal one
 template <typename Te, typename Ti>
 void launch_to_internal(const Grid& g, const Te* ext, Ti* in, hipStream_t s);

@@ -18,7 +18,7 @@ namespace csipm {
 
 constexpr int MLP_NP = 1249;
 constexpr int MLP_REC = 6;
-constexpr int MLP_BLOCK = 128;   // records per training workgroup
+constexpr int MLP_REC_PER_BLOCK = 64;   // records per training workgroup (one gradient partial each)
 
 // mean of log(S1 + S2) over n coefficients -> *out (device), via partials
 void mlp_mean_log_l1(const double* s1, const double* s2, long long n, double* partial, double* out, hipStream_t s);

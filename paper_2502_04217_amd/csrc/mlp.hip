@@ -13,7 +13,7 @@ namespace {
 constexpr int H1 = 32, H2 = 32, NIN = 4;
 constexpr int OW1 = 0, OB1 = OW1 + H1 * NIN, OW2 = OB1 + H1, OB2 = OW2 + H2 * H1, OW3 = OB2 + H2, OB3 = OW3 + H2;
 static_assert(OB3 + 1 == MLP_NP, "parameter layout");
-constexpr int RB = 64;          // records per training workgroup
+constexpr int RB = MLP_REC_PER_BLOCK;   // records per training workgroup
 constexpr int RP = RB + 1;      // padded LDS row
 
 __device__ __forceinline__ long long gtid() { return blockIdx.x * (long long)blockDim.x + threadIdx.x; }
