@@ -15,10 +15,10 @@ correction when trained parameters are present) gives `value`; the plain FP64
 form is timed alongside.  Every form reports the LASSO certificate the
 library computes with the solve (relative duality gap, natural residual).
 
-`roofline` is the metric's matvec: one K-apply (the seven kernels of
+`roofline` is the metric's matvec: one K-apply (the five kernels of
 q = K p) in the chosen form's precision, FP32, timed with HIP events on the
-library's stream (csipm_profile_kapply, at the last solve's barrier
-diagonals), against its design bytes 15 n w + n/8 (five volume passes that
+library's stream around K-applies queued back to back (csipm_profile_kapply,
+at the last solve's barrier diagonals), against its design bytes 15 n w + n/8 (five volume passes that
 each read and write the work array, the K epilogue's inputs and outputs,
 the mask bits); `frac_minimum` uses the least bytes any K-apply must move,
 6 n w + n/8 (read p and the two diagonals, write q).  `traffic` is the
@@ -49,21 +49,8 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-solve at rel KKT res 1e-6, plain vs FP32+learned-PC; matvec HBM GB/s"
 PEAK_HBM_GBPS = 8000.0
-PASS_NAMES = ["premix", "axis1_inverse", "axis2_inverse", "axis3_c2r_mask_r2c", "axis2_forward",
-              "axis1_forward_K_epilogue", "postmix"]
+from paper_2502_04217_amd.profile_kapply import PASS_NAMES, pass_bytes  # noqa: E402
 PARAMS_FILE = os.path.join(ROOT, "paper_2502_04217_amd", "pc_params.json")
-
-
-def pass_bytes(shape, w):
-    """Algorithmic HBM bytes of each K-apply kernel: every volume pass reads
-    and writes the n-real work array once; the axis-3 pass also reads the
-    n-bit mask; the last pass also reads p_beta, p_z, Sigma_1, Sigma_2 and
-    writes q_beta, q_z; the m = 0 plane passes touch 2 N1 N2 reals per
-    array."""
-    n1, n2, n3 = shape
-    n = n1 * n2 * n3
-    plane = 2 * n1 * n2
-    return [2 * plane * w, 2 * n * w, 2 * n * w, 2 * n * w + n // 8, 2 * n * w, 7 * n * w, 7 * plane * w]
 
 
 def kernel_bytes(name, shape, learned):
@@ -75,26 +62,19 @@ def kernel_bytes(name, shape, learned):
     as 8n bytes and each FP32 array as 4n."""
     n1, n2, n3 = shape
     n = n1 * n2 * n3
-    plane = 2 * n1 * n2
     base, _, prec = name.partition(".")
     w = 8 if prec == "f64" else 4
     c = 4 if learned else 0   # FP32 correction read by P_c^{-1}
     table = {
-        "premix": 2 * plane * w,
         "axis1_inv": 2 * n * w, "axis2_inv": 2 * n * w, "axis2_fwd": 2 * n * w, "axis1_fwd": 2 * n * w,
         "axis3": 2 * n * w + n // 8,
-        "postmix": 2 * plane * w,
         "axis1_fwd_K": 7 * n * w,
-        "postmix_K": 7 * plane * w,
         # the K-apply of a CG direction with p <- z + beta p fused in: z read and
         # p written back by the passes that first read p
-        "premix_P": 4 * plane * w,
         "axis1_inv_P": 4 * n * w,
         "axis1_fwd_KP": 9 * n * w,
-        "postmix_KP": 9 * plane * w,
         # T, d (2), Sigma (2), h (2) in FP64, c; H d_beta out
         "axis1_fwd_R": (64 + c) * n,
-        "postmix_R": (64 + c) * plane,
         # h, d, Sigma (2 each), H d_beta in FP64, c; r32, z32, p32 (2 each, FP32) out
         "ref_restart+fin": (56 + c + 24) * n,
         # x, p, q, r, Sigma (2 each) in, x, r, z out (the first update of a solve skips reading x)
@@ -157,8 +137,7 @@ def kernel_breakdown(pr, opts, shape, learned, info):
 
 # the K-apply kernels of a PCG iteration as csipm_timing names them (with the
 # fused direction update: *_P, *_KP)
-KAPPLY_NAMES = ("premix", "premix_P", "axis1_inv", "axis1_inv_P", "axis2_inv", "axis3", "axis2_fwd",
-                "axis1_fwd_K", "axis1_fwd_KP", "postmix_K", "postmix_KP")
+KAPPLY_NAMES = ("axis1_inv", "axis1_inv_P", "axis2_inv", "axis3", "axis2_fwd", "axis1_fwd_K", "axis1_fwd_KP")
 
 
 def kapply_in_solve(kern, prec, shape):
@@ -365,9 +344,10 @@ def main():
     # per-kernel timing of the K-apply at the last Newton system's barrier diagonals
     prof = {}
     for name, prec, wsz in (("fp32", csipm.FP32, 4), ("fp64", csipm.FP64, 8)):
-        ms = pr.profile_kapply(prec, args.profile_reps)
+        pr.profile_kapply(prec, 3)
+        ms, whole = pr.profile_kapply(prec, args.profile_reps)
         by = pass_bytes(w.shape, wsz)
-        prof[name] = {"ms": ms, "bytes": by}
+        prof[name] = {"ms": ms, "whole_ms": whole, "bytes": by}
     k_bytes = top["bytes_per_launch"] * top["working_calls"]
     achieved = k_bytes / (top["total_ms"] * 1e-3) / 1e9
     rec = traffic_record(top["name"], w.shape[0])
@@ -376,7 +356,9 @@ def main():
         traffic = rec["read_bytes"] + rec["write_bytes"]
     kapply = {}
     for name, wsz in (("fp32", 4), ("fp64", 8)):
-        t = sum(prof[name]["ms"]) * 1e-3
+        # one K-apply among applies queued back to back (one event pair around
+        # them all); the per-kernel times below carry an event pair each
+        t = prof[name]["whole_ms"] * 1e-3
         design = 15 * n * wsz + n // 8
         minimum = 6 * n * wsz + n // 8
         krec = traffic_record("kapply." + ("f32" if wsz == 4 else "f64"), w.shape[0])
@@ -384,8 +366,9 @@ def main():
                         "design_GBps": design / t / 1e9,
                         "minimum_GBps": minimum / t / 1e9,
                         "traffic": (krec["read_bytes"] + krec["write_bytes"]) if krec else None,
-                        "per_kernel_ms": dict(zip(PASS_NAMES, [round(v, 5) for v in prof[name]["ms"]]))}
-    roofline = {"bound": "hbm", "kernel": "K-apply q = K p (7 kernels), fp32",
+                        "per_kernel_ms": dict(zip(PASS_NAMES, [round(v, 5) for v in prof[name]["ms"]])),
+                        "per_kernel_sum_ms": round(sum(prof[name]["ms"]), 5)}
+    roofline = {"bound": "hbm", "kernel": "K-apply q = K p (5 kernels), fp32",
                 "achieved": kapply["fp32"]["design_GBps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                 "frac": kapply["fp32"]["design_GBps"] / PEAK_HBM_GBPS, "traffic": kapply["fp32"]["traffic"],
                 "bytes_per_launch": kapply["fp32"]["design_bytes"], "avg_ms": kapply["fp32"]["ms"],

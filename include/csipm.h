@@ -382,11 +382,15 @@ csipm_status csipm_pc_correction(csipm_ctx* ctx, double* d_c);
 
 /* Instrumentation: runs `reps` K-applies (apply_K's kernels on the
  * internal vectors, with the current barrier diagonals) and returns in
- * ms_out[0..6] the average duration of each of its seven kernels, timed
- * with HIP events on the context's stream, in launch order: premix,
- * axis-1 inverse, axis-2 inverse, axis-3 c2r/mask/r2c, axis-2 forward,
- * axis-1 forward with the K epilogue, postmix.  Synchronises. */
-#define CSIPM_KAPPLY_PASSES 7
+ * ms_out[0..4] the average duration of each of its five kernels, timed with
+ * HIP events on the context's stream around each kernel, in launch order:
+ * axis-1 inverse (with the m = 0 plane's mixing), axis-2 inverse, axis-3
+ * c2r/mask/r2c, axis-2 forward, axis-1 forward with the m = 0 unmixing and
+ * the K epilogue; and in ms_out[5] the average time of one K-apply over
+ * `reps` more applies queued back to back between a single event pair
+ * (no events between its kernels).  ms_out holds CSIPM_KAPPLY_PASSES + 1
+ * values.  Synchronises. */
+#define CSIPM_KAPPLY_PASSES 5
 csipm_status csipm_profile_kapply(csipm_ctx* ctx, int precision, int reps, double* ms_out);
 
 /* Instrumentation: per-kernel timing of everything the context launches.
@@ -417,7 +421,8 @@ csipm_status csipm_timing_report(csipm_ctx* ctx, double min_us, csipm_kernel_tim
 csipm_status csipm_destroy(csipm_ctx* ctx);
 const char* csipm_status_string(int status);
 /* Message of the last failure on ctx; with ctx NULL, that of the last
- * failed context-free call (csipm_mlp_loss_grad_noalloc) on this thread. */
+ * failed call without a context on this thread (csipm_create,
+ * csipm_mlp_loss_grad_noalloc). */
 const char* csipm_last_error(const csipm_ctx* ctx);
 
 #ifdef __cplusplus

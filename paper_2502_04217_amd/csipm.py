@@ -15,6 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcsipm.so")
 MLP_PARAMS = 1249
+KAPPLY_PASSES = 5
 
 FP64, FP32 = 0, 1
 PC_PLAIN, PC_LEARNED, PC_SCALED = 0, 1, 2
@@ -69,6 +70,10 @@ class IterLog(C.Structure):
 def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_2502_04217_amd.build`")
+    # torch first: it brings its own HIP runtime, which the library must share
+    # (loaded the other way round, the process can hold two runtimes and
+    # torch's device memory is then invalid for the library's calls)
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P, I, D, S, F = C.c_void_p, C.c_int, C.c_double, C.c_size_t, C.c_float
     sig = {
@@ -195,7 +200,8 @@ class Problem:
         st = lib().csipm_create(C.byref(self._ctx), *self.shape, _ptr(self.signal), _ptr(self.observed),
                                 self._ws_ptr, nbytes, handle)
         if st != 0:
-            raise CsipmError(st, "csipm_create")
+            msg = lib().csipm_last_error(None)
+            raise CsipmError(st, f"csipm_create: {msg.decode() if msg else ''}")
 
     # -- helpers
     def _check(self, st, what):
@@ -315,11 +321,13 @@ class Problem:
         self._check(lib().csipm_captured(self._ctx, C.byref(n), cg, max_iters), "captured")
         return n.value, list(cg[:n.value])
 
-    def profile_kapply(self, precision: int, reps: int = 20) -> list:
-        """Average per-kernel milliseconds of the seven K-apply kernels."""
-        out = (C.c_double * 7)()
+    def profile_kapply(self, precision: int, reps: int = 20):
+        """Average milliseconds of each of the KAPPLY_PASSES K-apply kernels
+        (events around each), and of one whole K-apply among `reps` queued back
+        to back (one event pair): (list, float)."""
+        out = (C.c_double * (KAPPLY_PASSES + 1))()
         self._check(lib().csipm_profile_kapply(self._ctx, precision, reps, out), "profile_kapply")
-        return list(out)
+        return list(out[:KAPPLY_PASSES]), out[KAPPLY_PASSES]
 
     def timing(self, enable: bool):
         """Start (clearing earlier records) or stop per-kernel event timing."""

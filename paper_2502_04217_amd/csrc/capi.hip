@@ -166,10 +166,10 @@ csipm_status sync_scalars(csipm_ctx* c, const char* where) {
   return CSIPM_OK;
 }
 
-// partial sums of one K-apply: axis-1 forward blocks plus postmix blocks
+// partial sums of one K-apply: one per workgroup of the axis-1 forward pass
 size_t k_partials(int n1, int n2, int n3) {
   const Grid g{n1, n2, n3, n3 / 2, (long long)n1 * n2 * n3};
-  return (size_t)std::max(axis12_blocks(g, 1, 16, -1), axis12_blocks(g, 1, 8, -1)) + postmix_blocks(g) + 64;
+  return (size_t)std::max(axis12_blocks(g, 1, 16, -1), axis12_blocks(g, 1, 8, -1)) + 64;
 }
 
 size_t layout(Carver& cv, csipm_ctx* c, int n1, int n2, int n3) {
@@ -204,26 +204,24 @@ const Twiddles<double>& tw<double>(csipm_ctx* c) { return c->T64; }
 template <>
 const Twiddles<float>& tw<float>(csipm_ctx* c) { return c->T32; }
 
-// out = H in (internal layout), work = FFT scratch; out may equal in.
+// out = H in (internal layout), work = FFT scratch; out may not equal in
+// (the axis-1 inverse pass reads the mirror rows of the m = 0 plane).
 template <typename T>
 void op_H(csipm_ctx* c, const T* in, T* out, T* work) {
   const Grid& g = c->g;
-  KT(c, PN(T, "premix"), launch_premix<T>(g, in, work, nullptr, c->s));
-  KT(c, PN(T, "axis1_inv"), launch_axis12<T>(g, 1, +1, in, work, tw<T>(c), EPI_NONE, nullptr, true, nullptr, c->s));
-  KT(c, PN(T, "axis2_inv"), launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s));
+  KT(c, PN(T, "axis1_inv"), launch_axis12<T>(g, 1, +1, in, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s));
+  KT(c, PN(T, "axis2_inv"), launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s));
   KT(c, PN(T, "axis3"), launch_axis3<T>(g, A3_FULL, work, work, c->mask, tw<T>(c), nullptr, c->s));
-  KT(c, PN(T, "axis2_fwd"), launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s));
-  KT(c, PN(T, "axis1_fwd"), launch_axis12<T>(g, 1, -1, work, out, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s));
-  KT(c, PN(T, "postmix"), launch_postmix<T>(g, out, out, EPI_NONE, nullptr, nullptr, c->s));
+  KT(c, PN(T, "axis2_fwd"), launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s));
+  KT(c, PN(T, "axis1_fwd"), launch_axis12<T>(g, 1, -1, work, out, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s));
 }
 
 // x = A in (real grid, row-major), work = FFT scratch (must differ from x).
 template <typename T>
 void op_A(csipm_ctx* c, const T* in, T* x, T* work) {
   const Grid& g = c->g;
-  launch_premix<T>(g, in, work, nullptr, c->s);
-  launch_axis12<T>(g, 1, +1, in, work, tw<T>(c), EPI_NONE, nullptr, true, nullptr, c->s);
-  launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
+  launch_axis12<T>(g, 1, +1, in, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s);
+  launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s);
   launch_axis3<T>(g, A3_C2R, work, x, nullptr, tw<T>(c), nullptr, c->s);
 }
 
@@ -232,9 +230,8 @@ template <typename T>
 void op_At(csipm_ctx* c, const T* x, T* out, T* work) {
   const Grid& g = c->g;
   launch_axis3<T>(g, A3_R2C, x, work, nullptr, tw<T>(c), nullptr, c->s);
-  launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
-  launch_axis12<T>(g, 1, -1, work, out, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
-  launch_postmix<T>(g, out, out, EPI_NONE, nullptr, nullptr, c->s);
+  launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s);
+  launch_axis12<T>(g, 1, -1, work, out, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s);
 }
 
 size_t k_partials(int n1, int n2, int n3);
@@ -247,19 +244,15 @@ int op_K(csipm_ctx* c, const T* pb, const T* pz, const T* s1, const T* s2, T* qb
   const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>), -1);
   const int ps = (int)k_partials(g.n1, g.n2, g.n3);
   EpiArgs<T> ka{KArgs<T>{pb, pz, s1, s2, qb, qz, u ? *u : PUpd<T>{}}, RArgs{}, c->partK, ps};
-  EpiArgs<T> kb = ka;
-  kb.partial = c->partK + nb5;
   // (the passes that apply the direction update are timed under their own names)
-  KT(c, u ? PN(T, "premix_P") : PN(T, "premix"), launch_premix<T>(g, pb, work, skip, c->s, u));
   KT(c, u ? PN(T, "axis1_inv_P") : PN(T, "axis1_inv"),
-     launch_axis12<T>(g, 1, +1, pb, work, tw<T>(c), EPI_NONE, u ? &ka : nullptr, true, skip, c->s));
-  KT(c, PN(T, "axis2_inv"), launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, skip, c->s));
+     launch_axis12<T>(g, 1, +1, pb, work, tw<T>(c), EPI_NONE, u ? &ka : nullptr, skip, c->s));
+  KT(c, PN(T, "axis2_inv"), launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, skip, c->s));
   KT(c, PN(T, "axis3"), launch_axis3<T>(g, A3_FULL, work, work, c->mask, tw<T>(c), skip, c->s));
-  KT(c, PN(T, "axis2_fwd"), launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, skip, c->s));
+  KT(c, PN(T, "axis2_fwd"), launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, skip, c->s));
   KT(c, u ? PN(T, "axis1_fwd_KP") : PN(T, "axis1_fwd_K"),
-     launch_axis12<T>(g, 1, -1, work, work, tw<T>(c), EPI_K, &ka, false, skip, c->s));
-  KT(c, u ? PN(T, "postmix_KP") : PN(T, "postmix_K"), launch_postmix<T>(g, work, nullptr, EPI_K, &kb, skip, c->s));
-  return nb5 + postmix_blocks(g);
+     launch_axis12<T>(g, 1, -1, work, work, tw<T>(c), EPI_K, &ka, skip, c->s));
+  return nb5;
 }
 
 // FP64 refinement residual r = h - K d, fused into the K-apply of d: writes
@@ -272,19 +265,14 @@ void op_Kr(csipm_ctx* c, const float* pcc) {
   // H d_beta goes to rb: the FP64 Krylov vectors are idle in the FP32 form
   RArgs ra{c->dxb, c->dxz, c->sig1, c->sig2, c->rhb, c->rhz, pcc, c->rb};
   EpiArgs<double> ea{KArgs<double>{}, ra, c->partK, ps};
-  EpiArgs<double> eb = ea;
-  eb.partial = c->partK + nb5;
   double* work = c->work;
-  KT(c, "premix.f64", launch_premix<double>(g, c->dxb, work, nullptr, c->s));
-  KT(c, "axis1_inv.f64",
-     launch_axis12<double>(g, 1, +1, c->dxb, work, c->T64, EPI_NONE, nullptr, true, nullptr, c->s));
-  KT(c, "axis2_inv.f64", launch_axis12<double>(g, 2, +1, work, work, c->T64, EPI_NONE, nullptr, false, nullptr, c->s));
+  KT(c, "axis1_inv.f64", launch_axis12<double>(g, 1, +1, c->dxb, work, c->T64, EPI_NONE, nullptr, nullptr, c->s));
+  KT(c, "axis2_inv.f64", launch_axis12<double>(g, 2, +1, work, work, c->T64, EPI_NONE, nullptr, nullptr, c->s));
   KT(c, "axis3.f64", launch_axis3<double>(g, A3_FULL, work, work, c->mask, c->T64, nullptr, c->s));
-  KT(c, "axis2_fwd.f64", launch_axis12<double>(g, 2, -1, work, work, c->T64, EPI_NONE, nullptr, false, nullptr, c->s));
-  KT(c, "axis1_fwd_R.f64", launch_axis12<double>(g, 1, -1, work, work, c->T64, EPI_R, &ea, false, nullptr, c->s));
-  KT(c, "postmix_R.f64", launch_postmix<double>(g, work, nullptr, EPI_R, &eb, nullptr, c->s));
-  KT(c, "fin_sum", fin_sum(c->partK, nb5 + postmix_blocks(g), c->scal + S_REF, c->s));
-  KT(c, "fin_max", fin_max(c->partK + ps, nb5 + postmix_blocks(g), c->scal + S_REFINF, c->s));
+  KT(c, "axis2_fwd.f64", launch_axis12<double>(g, 2, -1, work, work, c->T64, EPI_NONE, nullptr, nullptr, c->s));
+  KT(c, "axis1_fwd_R.f64", launch_axis12<double>(g, 1, -1, work, work, c->T64, EPI_R, &ea, nullptr, c->s));
+  KT(c, "fin_sum", fin_sum(c->partK, nb5, c->scal + S_REF, c->s));
+  KT(c, "fin_max", fin_max(c->partK + ps, nb5, c->scal + S_REFINF, c->s));
 }
 
 // ------------------------------------------------- learned correction --
@@ -634,6 +622,7 @@ csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double*
     e = hipMemcpyAsync(c->tw32, h32.data(), h32.size() * sizeof(cx<float>), hipMemcpyHostToDevice, c->s);
   if (e == hipSuccess) e = hipStreamSynchronize(c->s);
   if (e != hipSuccess) {
+    noctx_set_error(std::string("create: twiddle tables: ") + hipGetErrorString(e));
     (void)hipHostFree(c->hscal);
     delete c;
     return CSIPM_EHIP;
@@ -647,7 +636,7 @@ csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double*
   // input checks: finite observed samples, at least one observed
   check_signal(d_signal, d_observed, n, c->partV, c->scal + S_SIG, c->s);
   csipm_status st = sync_scalars(c, "create");
-  if (st != CSIPM_OK) { csipm_destroy(c); return st; }
+  if (st != CSIPM_OK) { noctx_set_error("create: " + c->err); csipm_destroy(c); return st; }
   if (c->hscal[S_SIG] > 0) { csipm_destroy(c); return CSIPM_ENONFINITE; }
   c->nobs = (long long)c->hscal[S_SIG + 1];
   if (c->nobs == 0) { csipm_destroy(c); return CSIPM_EINVAL; }
@@ -665,7 +654,7 @@ csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double*
   launch_to_internal<double, double>(g, c->rz, c->diagH, c->s);
   fill<float>(c->pc_c, 1.0f, n, c->s);
   st = sync_scalars(c, "create");
-  if (st != CSIPM_OK) { csipm_destroy(c); return st; }
+  if (st != CSIPM_OK) { noctx_set_error("create: " + c->err); csipm_destroy(c); return st; }
   c->xi_inf = c->hscal[S_MISC];
   // barrier diagonals default to 1 so apply_K / apply_Pinv are defined
   fill<double>(c->sig1, 1.0, n, c->s);
@@ -673,7 +662,7 @@ csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double*
   fill<float>(c->sig1f, 1.0f, n, c->s);
   fill<float>(c->sig2f, 1.0f, n, c->s);
   st = sync_scalars(c, "create");
-  if (st != CSIPM_OK) { csipm_destroy(c); return st; }
+  if (st != CSIPM_OK) { noctx_set_error("create: " + c->err); csipm_destroy(c); return st; }
   c->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_create).count();
   *out = c;
   return CSIPM_OK;
@@ -1481,44 +1470,47 @@ csipm_status csipm_profile_kapply(csipm_ctx* c, int precision, int reps, double*
   for (auto& e : ev)
     if (hipEventCreate(&e) != hipSuccess) return fail(c, CSIPM_EHIP, "hipEventCreate");
   double acc[CSIPM_KAPPLY_PASSES] = {0};
+  double whole = 0.0;
   auto run = [&](auto tag) {
     using T = decltype(tag);
     PcgSet v = pcg_set<T>(c);
     T *pb = (T*)v.pb, *pz = (T*)v.pz, *qb = (T*)v.qb, *qz = (T*)v.qz, *work = (T*)v.work;
     const T* s1 = std::is_same<T, double>::value ? (const T*)c->sig1 : (const T*)c->sig1f;
     const T* s2 = std::is_same<T, double>::value ? (const T*)c->sig2 : (const T*)c->sig2f;
-    const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>), -1);
     const int ps = (int)k_partials(g.n1, g.n2, g.n3);
     EpiArgs<T> ka{KArgs<T>{pb, pz, s1, s2, qb, qz, PUpd<T>{}}, RArgs{}, c->partK, ps};
-    EpiArgs<T> kb = ka;
-    kb.partial = c->partK + nb5;
     for (int r = 0; r < reps; ++r) {
       (void)hipEventRecord(ev[0], c->s);
-      launch_premix<T>(g, pb, work, nullptr, c->s);
+      launch_axis12<T>(g, 1, +1, pb, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s);
       (void)hipEventRecord(ev[1], c->s);
-      launch_axis12<T>(g, 1, +1, pb, work, tw<T>(c), EPI_NONE, nullptr, true, nullptr, c->s);
+      launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s);
       (void)hipEventRecord(ev[2], c->s);
-      launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
-      (void)hipEventRecord(ev[3], c->s);
       launch_axis3<T>(g, A3_FULL, work, work, c->mask, tw<T>(c), nullptr, c->s);
+      (void)hipEventRecord(ev[3], c->s);
+      launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s);
       (void)hipEventRecord(ev[4], c->s);
-      launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, false, nullptr, c->s);
+      launch_axis12<T>(g, 1, -1, work, work, tw<T>(c), EPI_K, &ka, nullptr, c->s);
       (void)hipEventRecord(ev[5], c->s);
-      launch_axis12<T>(g, 1, -1, work, work, tw<T>(c), EPI_K, &ka, false, nullptr, c->s);
-      (void)hipEventRecord(ev[6], c->s);
-      launch_postmix<T>(g, work, nullptr, EPI_K, &kb, nullptr, c->s);
-      (void)hipEventRecord(ev[7], c->s);
-      (void)hipEventSynchronize(ev[7]);
+      (void)hipEventSynchronize(ev[5]);
       for (int k = 0; k < CSIPM_KAPPLY_PASSES; ++k) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
         acc[k] += ms;
       }
     }
+    // the same K-apply back to back, one event pair around all reps
+    (void)hipEventRecord(ev[0], c->s);
+    for (int r = 0; r < reps; ++r) (void)op_K<T>(c, pb, pz, s1, s2, qb, qz, work, nullptr);
+    (void)hipEventRecord(ev[1], c->s);
+    (void)hipEventSynchronize(ev[1]);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    whole = (double)ms / reps;
   };
   if (precision == CSIPM_FP64) run(double{}); else run(float{});
   for (auto& e : ev) (void)hipEventDestroy(e);
   for (int k = 0; k < CSIPM_KAPPLY_PASSES; ++k) ms_out[k] = acc[k] / reps;
+  ms_out[CSIPM_KAPPLY_PASSES] = whole;
   return hip_check(c, "profile_kapply");
 }
 

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 namespace csipm {
 
@@ -121,7 +122,7 @@ struct Grid {
 // Selects what the axis-3 pass does.
 enum Axis3Mode { A3_C2R = 1, A3_R2C = 2, A3_FULL = 3 };
 
-// Epilogue of the last forward pass (axis 1) and of the m = 0 postmix pass.
+// Epilogue of the last forward pass (axis 1).
 enum EpiMode {
   EPI_NONE = 0,   // write the transform result (A^T x or H p), m = 0 left raw
   EPI_K = 1,      // q = K p with the barrier diagonals, plus p.q partials
@@ -134,8 +135,8 @@ constexpr double kPcRelevance = 1e-3;
 
 // CG direction update p <- z + beta p fused into the K-apply of the new p
 // (zb null: none).  The passes that first read p apply it and write p back:
-// the premix (m = 0) and the axis-1 inverse pass (m >= 1) to p_beta, the K
-// epilogues to p_z.  Every element is updated exactly once.
+// the axis-1 inverse pass to p_beta, the K epilogue to p_z.  Every element
+// is updated exactly once.
 template <typename T>
 struct PUpd {
   T* pb;
@@ -209,32 +210,29 @@ __device__ __forceinline__ void p_block(T zb, T zz, T s1, T s2, double c, double
 // FFT driver entry points (fft.hip).  All work is queued on `s`.
 // `skip` (nullable device int): when nonzero at launch time the kernel
 // returns at once; lets a batch of Krylov iterations be queued ahead.
-template <typename T>
-void launch_premix(const Grid& g, const T* src, T* work, const int* skip, hipStream_t s,
-                   const PUpd<T>* u = nullptr);
-// (the axis-1 inverse pass applies the direction update ea->k.u when ea is
-// set and ea->k.u.zb is not null)
+// The axis-1 passes also map the m = 0 plane between the real
+// parametrisation and the spectrum (inverse: on input; forward: on output,
+// before the epilogue); the axis-1 inverse pass applies the direction update
+// ea->k.u when ea is set and ea->k.u.zb is not null.
 template <typename T>
 void launch_axis12(const Grid& g, int axis, int dir, const T* src, T* dst, const Twiddles<T>& tw,
-                   int epi, const EpiArgs<T>* ea, bool m0_from_dst, const int* skip, hipStream_t s);
+                   int epi, const EpiArgs<T>* ea, const int* skip, hipStream_t s);
 template <typename T>
 void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t* maskbits,
                   const Twiddles<T>& tw, const int* skip, hipStream_t s);
-template <typename T>
-void launch_postmix(const Grid& g, const T* work, T* out, int epi, const EpiArgs<T>* ea,
-                    const int* skip, hipStream_t s);
 // workgroups of a strided pass (axis 1 or 2, complex size elem_bytes, dir +1
-// inverse / -1 forward); for the axis-1 forward pass also its partial count
+// inverse / -1 forward), those of the m = 0 plane included; for the axis-1
+// forward pass also its partial count
 int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir);
 // whether the FFT passes have kernels for extent N on `axis` (1, 2: pencils
 // of length N; 3: half length N/2): powers of two in [4, 1024], the extents
 // with odd factors that fft_mixed_f64/f32.hip instantiate, and on axes 1
 // and 2 also 1 and 2 (2D and 1D grids) and the odd extents 3-45
 bool fft_extent_supported(int N, int axis);
-int postmix_blocks(const Grid& g);
 
 // message of the last failed context-free call on this thread (noalloc.hip)
 const char* noctx_last_error();
+void noctx_set_error(const std::string& msg);
 
 // permutation between the external beta layout and the internal one
 template <typename Te, typename Ti>

@@ -2,18 +2,17 @@
 // the condensed KKT operator K (paper: "Matrix-free operators" and equation
 // "condensedkkt").  gfx950, wave64.
 //
-// One apply of H is five volume passes over the n-real internal array plus
-// two small passes over the plane m = 0:
-//   premix   : m = 0 plane, real parametrisation -> spectrum (pairs k, -k)
-//   axis 1   : inverse complex FFT along k1 (strided pencils)
+// One apply of H is five volume passes over the n-real internal array:
+//   axis 1   : inverse complex FFT along k1 (strided pencils); the leading
+//              workgroups take the m = 0 plane, whose real parametrisation
+//              pairs (k1, k2) with (-k1, -k2), and mix the pairs on input
 //   axis 2   : inverse complex FFT along k2 (strided pencils)
 //   axis 3   : c2r along k3, mask, r2c along k3 (contiguous pencils), using
 //              a half-length complex FFT with the DC/Nyquist pair packed in
 //              slot 0
 //   axis 2   : forward complex FFT along k2
-//   axis 1   : forward complex FFT along k1, fused with the K epilogue
-//              q = K p and the p.q partial sums
-//   postmix  : m = 0 plane, spectrum -> real parametrisation, K epilogue
+//   axis 1   : forward complex FFT along k1, unmixing the m = 0 pairs, fused
+//              with the K epilogue q = K p and the p.q partial sums
 // The pencil FFT kernels (Stockham stages, fft_kernels.h) are instantiated
 // here for power-of-two lengths and in fft_mixed_f64/f32.hip for lengths with odd
 // factors.  Strided passes map consecutive lanes to consecutive pencils, so
@@ -34,97 +33,6 @@ CSIPM_MIXED_INST12(extern, double, 1, -1, EpiR)
 using namespace fftk;
 
 namespace {
-
-// --------------------------------------------------------- m = 0 mixing --
-// 2D class of (k1, k2) in the m = 0 plane: 0 self-conjugate, 1 canonical,
-// 2 mirror of a canonical index.
-__device__ __forceinline__ int cls2(int k1, int k2, int n1, int n2) {
-  const bool e1 = (2 * k1 == n1) || k1 == 0;
-  const bool e2 = (2 * k2 == n2) || k2 == 0;
-  if (e1 && e2) return 0;
-  if (2 * k2 < n2 && k2 >= 1) return 1;
-  if (e2 && k1 >= 1 && 2 * k1 < n1) return 1;
-  return 2;
-}
-
-// (pw, z, beta: the fused CG direction update of the m = 0 column, src = pw;
-// z null: none)
-template <typename T>
-__global__ void k_premix(const cx<T>* src, cx<T>* __restrict__ dst, int n1, int n2, int m, const int* skip,
-                         cx<T>* pw, const cx<T>* __restrict__ z, const double* __restrict__ beta) {
-  if (skip && *skip) return;
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= n1 * n2) return;
-  const int k1 = id / n2, k2 = id % n2;
-  const int c = cls2(k1, k2, n1, n2);
-  if (c == 2) return;
-  const T be = z ? (T)*beta : T(0);
-  auto load = [&](long long i) {
-    cx<T> x = src[i];
-    if (z) {
-      const cx<T> zv = z[i];
-      x = {zv.re + be * x.re, zv.im + be * x.im};
-      pw[i] = x;
-    }
-    return x;
-  };
-  const long long ia = ((long long)k1 * n2 + k2) * m;
-  if (c == 0) {
-    dst[ia] = load(ia);
-    return;
-  }
-  const int q1 = (n1 - k1) % n1, q2 = (n2 - k2) % n2;
-  const long long ib = ((long long)q1 * n2 + q2) * m;
-  const T r = T(0.70710678118654752440);
-  const cx<T> a = load(ia), b = load(ib);
-  // U[k] = (W[k] + i W[-k]) / sqrt2,  U[-k] = (W[k] - i W[-k]) / sqrt2
-  const cx<T> ib_ = cmul_i<1>(b);
-  dst[ia] = cscale(cadd(a, ib_), r);
-  dst[ib] = cscale(csub(a, ib_), r);
-}
-
-template <typename T, class Epi>
-__global__ void __launch_bounds__(256)
-k_postmix(const cx<T>* work, cx<T>* out, int n1, int n2, int m, Epi epi, const int* skip) {
-  if (skip && *skip) return;
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  double acc[Epi::NRED > 0 ? Epi::NRED : 1];
-#pragma unroll
-  for (int q = 0; q < (Epi::NRED > 0 ? Epi::NRED : 1); ++q) acc[q] = 0.0;
-  if (id < n1 * n2) {
-    const int k1 = id / n2, k2 = id % n2;
-    const int c = cls2(k1, k2, n1, n2);
-    if (c != 2) {
-      const long long ia = ((long long)k1 * n2 + k2) * m;
-      const int q1 = (n1 - k1) % n1, q2 = (n2 - k2) % n2;
-      const long long ib = ((long long)q1 * n2 + q2) * m;
-      cx<T> ha, hb;
-      int cnt;
-      if (c == 0) {
-        ha = work[ia];
-        cnt = 1;
-      } else {
-        const T r = T(0.70710678118654752440);
-        const cx<T> a = work[ia], b = work[ib];
-        // W[k] = (U[k] + U[-k]) / sqrt2,  W[-k] = i (U[-k] - U[k]) / sqrt2
-        ha = cscale(cadd(a, b), r);
-        hb = cscale(cmul_i<1>(csub(b, a)), r);
-        cnt = 2;
-      }
-      if constexpr (Epi::NRED > 0) {
-        epi(ia, ha, acc);
-        if (cnt == 2) epi(ib, hb, acc);
-      } else {
-        out[ia] = ha;
-        if (cnt == 2) out[ib] = hb;
-      }
-    }
-  }
-  if constexpr (Epi::NRED > 0) {
-    __shared__ double red[4 * Epi::NRED];
-    block_sums_store<256, Epi::NRED, Epi::NMAX>(acc, epi.partial, epi.pstride, red);
-  }
-}
 
 // ----------------------------------------------------- layout conversion --
 // internal real index r = ((k1*N2 + k2)*M + m)*2 + part
@@ -190,10 +98,10 @@ int grid_for(long long n, int block) {
 
 template <typename T, int AX, int DIR, class Epi>
 void launch_axis12_L(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* tw,
-                     int m, int m0, Epi epi, const int* skip, hipStream_t s) {
+                     int m, int n2, Epi epi, const int* skip, hipStream_t s) {
 #define CSIPM_A12(LL)                                                                     \
   case LL:                                                                                \
-    launch_axis12_at<T, LL, AX, DIR, Epi>(grid, src, dst, geo, tw, m, m0, epi, skip, s); \
+    launch_axis12_at<T, LL, AX, DIR, Epi>(grid, src, dst, geo, tw, m, n2, epi, skip, s); \
     break;
   switch (L) {
     CSIPM_A12(1)
@@ -208,7 +116,7 @@ void launch_axis12_L(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom
     CSIPM_A12(512)
     CSIPM_A12(1024)
     default:
-      (void)launch_axis12_mixed<T, AX, DIR, Epi>(L, grid, src, dst, geo, tw, m, m0, epi, skip, s);
+      (void)launch_axis12_mixed<T, AX, DIR, Epi>(L, grid, src, dst, geo, tw, m, n2, epi, skip, s);
       break;
   }
 #undef CSIPM_A12
@@ -233,11 +141,19 @@ StridedGeom<T> geom(const Grid& g, int axis) {
 
 }  // namespace
 
-int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir) {
+// the workgroups of the pencil tiles alone (the launch adds those of the
+// m = 0 plane in front of them on axis 1)
+int axis12_tiles(const Grid& g, int axis, int elem_bytes, int dir) {
   const int L = axis == 1 ? g.n1 : g.n2;
   const int batch = axis == 1 ? g.n2 * g.m : g.n1 * g.m;
   const int tm = strided_tm(elem_bytes, L, axis, dir);
   return (batch + tm - 1) / tm;
+}
+
+int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir) {
+  const int L = axis == 1 ? g.n1 : g.n2;
+  const int tm = strided_tm(elem_bytes, L, axis, dir);
+  return axis12_tiles(g, axis, elem_bytes, dir) + (axis == 1 ? plane0_groups(g.n2, tm) : 0);
 }
 
 bool fft_extent_supported(int N, int axis) {
@@ -252,25 +168,13 @@ bool fft_extent_supported(int N, int axis) {
   return false;
 }
 
-int postmix_blocks(const Grid& g) { return (g.n1 * g.n2 + 255) / 256; }
-
-template <typename T>
-void launch_premix(const Grid& g, const T* src, T* work, const int* skip, hipStream_t s, const PUpd<T>* u) {
-  const int tot = g.n1 * g.n2;
-  const bool up = u && u->zb;
-  hipLaunchKernelGGL((k_premix<T>), dim3((tot + 255) / 256), dim3(256), 0, s,
-                     reinterpret_cast<const cx<T>*>(src), reinterpret_cast<cx<T>*>(work), g.n1, g.n2, g.m, skip,
-                     up ? reinterpret_cast<cx<T>*>(u->pb) : nullptr,
-                     up ? reinterpret_cast<const cx<T>*>(u->zb) : nullptr, up ? u->beta : nullptr);
-}
-
 template <typename T>
 void launch_axis12(const Grid& g, int axis, int dir, const T* src, T* dst, const Twiddles<T>& tw, int epi,
-                   const EpiArgs<T>* ea, bool m0_from_dst, const int* skip, hipStream_t s) {
+                   const EpiArgs<T>* ea, const int* skip, hipStream_t s) {
   const int L = axis == 1 ? g.n1 : g.n2;
   const cx<T>* twp = axis == 1 ? tw.t1 : tw.t2;
   StridedGeom<T> geo = geom<T>(g, axis);
-  dim3 grid(axis12_blocks(g, axis, (int)sizeof(cx<T>), dir));
+  dim3 grid(axis12_tiles(g, axis, (int)sizeof(cx<T>), dir));
   const cx<T>* cs = reinterpret_cast<const cx<T>*>(src);
   cx<T>* cd = reinterpret_cast<cx<T>*>(dst);
   if (axis == 1) {
@@ -278,20 +182,22 @@ void launch_axis12(const Grid& g, int axis, int dir, const T* src, T* dst, const
       const bool up = ea && ea->k.u.zb;
       EpiP<T> pro{up ? reinterpret_cast<cx<T>*>(ea->k.u.pb) : nullptr,
                   up ? reinterpret_cast<const cx<T>*>(ea->k.u.zb) : nullptr, up ? ea->k.u.beta : nullptr};
-      launch_axis12_L<T, 1, +1>(L, grid, cs, cd, geo, twp, g.m, m0_from_dst ? 1 : 0, pro, skip, s);
+      launch_axis12_L<T, 1, +1>(L, grid, cs, cd, geo, twp, g.m, g.n2, pro, skip, s);
     } else if (epi == EPI_K) {
-      launch_axis12_L<T, 1, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiK<T>{ea->k, ea->partial, ea->pstride}, skip, s);
+      launch_axis12_L<T, 1, -1>(L, grid, cs, cd, geo, twp, g.m, g.n2, EpiK<T>{ea->k, ea->partial, ea->pstride}, skip,
+                                s);
     } else if (epi == EPI_R) {
       if constexpr (std::is_same<T, double>::value)
-        launch_axis12_L<T, 1, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiR{ea->r, ea->partial, ea->pstride}, skip, s);
+        launch_axis12_L<T, 1, -1>(L, grid, cs, cd, geo, twp, g.m, g.n2, EpiR{ea->r, ea->partial, ea->pstride}, skip,
+                                  s);
     } else {
-      launch_axis12_L<T, 1, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiNone{}, skip, s);
+      launch_axis12_L<T, 1, -1>(L, grid, cs, cd, geo, twp, g.m, g.n2, EpiNone{}, skip, s);
     }
   } else {
     if (dir > 0)
-      launch_axis12_L<T, 2, +1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiNone{}, skip, s);
+      launch_axis12_L<T, 2, +1>(L, grid, cs, cd, geo, twp, g.m, g.n2, EpiNone{}, skip, s);
     else
-      launch_axis12_L<T, 2, -1>(L, grid, cs, cd, geo, twp, g.m, 0, EpiNone{}, skip, s);
+      launch_axis12_L<T, 2, -1>(L, grid, cs, cd, geo, twp, g.m, g.n2, EpiNone{}, skip, s);
   }
 }
 
@@ -306,9 +212,12 @@ void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t*
   const T sc_ac = (T)(rn * std::sqrt(2.0));
   const cx<T>* cs = reinterpret_cast<const cx<T>*>(src);
   cx<T>* cd = reinterpret_cast<cx<T>*>(dst);
-#define CSIPM_A3(LL)                                                                                      \
-  case LL:                                                                                                \
-    launch_axis3_at<T, LL>(mode, np, cs, cd, maskbits, tw.tm, tw.t3, sc_c2r, sc_dc, sc_ac, skip, s); \
+#define CSIPM_A3(LL)                                                                                        \
+  case LL:                                                                                                  \
+    if constexpr (a3t_ok<T, LL>())                                                                          \
+      launch_axis3t_at<T, LL>(mode, np, cs, cd, maskbits, tw.tm, tw.t3, sc_c2r, sc_dc, sc_ac, skip, s);     \
+    else                                                                                                    \
+      launch_axis3_at<T, LL>(mode, np, cs, cd, maskbits, tw.tm, tw.t3, sc_c2r, sc_dc, sc_ac, skip, s);      \
     break;
   switch (L) {
     CSIPM_A3(2)
@@ -325,24 +234,6 @@ void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t*
       break;
   }
 #undef CSIPM_A3
-}
-
-template <typename T>
-void launch_postmix(const Grid& g, const T* work, T* out, int epi, const EpiArgs<T>* ea, const int* skip,
-                    hipStream_t s) {
-  dim3 grid(postmix_blocks(g));
-  const cx<T>* w = reinterpret_cast<const cx<T>*>(work);
-  cx<T>* o = reinterpret_cast<cx<T>*>(out);
-  if (epi == EPI_K) {
-    hipLaunchKernelGGL((k_postmix<T, EpiK<T>>), grid, dim3(256), 0, s, w, o, g.n1, g.n2, g.m,
-                       EpiK<T>{ea->k, ea->partial, ea->pstride}, skip);
-  } else if (epi == EPI_R) {
-    if constexpr (std::is_same<T, double>::value)
-      hipLaunchKernelGGL((k_postmix<T, EpiR>), grid, dim3(256), 0, s, w, o, g.n1, g.n2, g.m,
-                         EpiR{ea->r, ea->partial, ea->pstride}, skip);
-  } else {
-    hipLaunchKernelGGL((k_postmix<T, EpiNone>), grid, dim3(256), 0, s, w, o, g.n1, g.n2, g.m, EpiNone{}, skip);
-  }
 }
 
 template <typename Te, typename Ti>
@@ -366,12 +257,10 @@ void launch_pack_mask(const Grid& g, const uint8_t* obs, uint32_t* bits, hipStre
 }
 
 #define CSIPM_INST(T)                                                                                          \
-  template void launch_premix<T>(const Grid&, const T*, T*, const int*, hipStream_t, const PUpd<T>*);          \
   template void launch_axis12<T>(const Grid&, int, int, const T*, T*, const Twiddles<T>&, int,                 \
-                                 const EpiArgs<T>*, bool, const int*, hipStream_t);                            \
+                                 const EpiArgs<T>*, const int*, hipStream_t);                                  \
   template void launch_axis3<T>(const Grid&, int, const T*, T*, const uint32_t*, const Twiddles<T>&,           \
                                 const int*, hipStream_t);                                                      \
-  template void launch_postmix<T>(const Grid&, const T*, T*, int, const EpiArgs<T>*, const int*, hipStream_t); \
   template void launch_to_internal<double, T>(const Grid&, const double*, T*, hipStream_t);                   \
   template void launch_to_internal<float, T>(const Grid&, const float*, T*, hipStream_t);                     \
   template void launch_to_external<T, double>(const Grid&, const T*, double*, hipStream_t);                   \

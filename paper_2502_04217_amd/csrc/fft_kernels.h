@@ -316,7 +316,7 @@ __device__ __forceinline__ void block_sums_store(const double* v, double* out, i
 
 // ------------------------------------------------------------ epilogues --
 // Applied to each output element h = (H p)[idx] of the last forward pass
-// (m >= 1 there, the m = 0 plane in the postmix pass).
+// (the m = 0 plane by the workgroups that unmix it).
 struct EpiNone {
   static constexpr int NRED = 0;
   static constexpr int NMAX = 0;
@@ -326,8 +326,9 @@ struct EpiNone {
 };
 
 // Plain output with the fused CG direction update on input (axis-1 inverse
-// pass of K p): p <- z + beta p as p is loaded, written back to p, except in
-// the m = 0 column that the premix already updated.  z null: no update.
+// pass of K p): p <- z + beta p as p is loaded, written back to p (in the
+// m = 0 plane only once the workgroup has read the mirror values).  z null:
+// no update.
 template <typename T>
 struct EpiP {
   static constexpr int NRED = 0;
@@ -453,82 +454,198 @@ constexpr int strided_threads() {
   return strided_tm(w, L, AX, DIR) * (L / strided_e(w, L, AX, DIR));
 }
 
+// ------------------------------------------------ the m = 0 plane (axis 1) --
+// In the m = 0 plane the internal layout holds the two self-paired planes
+// k3 = 0 and k3 = N3/2 of the real parametrisation, whose coefficients pair
+// (k1, k2) with (-k1, -k2) (derivation "map"): the spectrum U the inverse
+// transform needs at (k1, k2, 0) mixes the stored values W of both, and the
+// forward transform's output H is unmixed the same way.  An axis-1 pencil
+// (k2, m = 0) therefore also reads the pencil of row (N2 - k2) mod N2.  The
+// first `ndedicated` workgroups of an axis-1 pass take the m = 0 pencils and
+// the other workgroups leave their m = 0 lane idle.
+//   inverse: U = W on self-conjugate (k1, k2), (W + i W(-k)) / sqrt2 on a
+//            canonical one, (W(-k) - i W) / sqrt2 on its mirror, formed as
+//            the two rows are read;
+//   forward: with F the FFT along k1 and R the reversal j1 -> -j1 (so that
+//            F(R b)(k1) = F(b)(-k1)), the unmixed output of a canonical row
+//            a paired with row b is F((a + R b) / sqrt2) and that of the
+//            mirror row b is F(i (b - R a) / sqrt2): the unmixing is applied
+//            to the inputs.  A self-paired row (k2 = 0 or N2/2) takes two
+//            lanes, one transforming (a + R a) / sqrt2 and writing its
+//            canonical and (scaled by 1/sqrt2) self-conjugate elements, the
+//            other i (a - R a) / sqrt2 and writing its mirror elements.
+// 2D class of (k1, k2): 0 self-conjugate, 1 canonical, 2 the mirror of a
+// canonical index.
+__host__ __device__ __forceinline__ int cls2(int k1, int k2, int n1, int n2) {
+  const bool e1 = (2 * k1 == n1) || k1 == 0;
+  const bool e2 = (2 * k2 == n2) || k2 == 0;
+  if (e1 && e2) return 0;
+  if (2 * k2 < n2 && k2 >= 1) return 1;
+  if (e2 && k1 >= 1 && 2 * k1 < n1) return 1;
+  return 2;
+}
+// Row k2 of entry li of the m = 0 pencil list: entries 0, 1 take row 0 and
+// entries 2, 3 row N2/2 (when N2 is even); then the pairs (1, N2 - 1),
+// (2, N2 - 2), ...; -1 for an empty entry.  Even entries have the canonical
+// role, odd entries the mirror role; a pair never straddles two workgroups
+// of an even number of lanes.
+__host__ __device__ __forceinline__ int plane0_row(int li, int n2) {
+  if (li < 2) return 0;
+  if (li < 4) return (n2 % 2 == 0 && n2 >= 2) ? n2 / 2 : -1;
+  const int j = (li - 4) / 2 + 1;
+  if (2 * j >= n2) return -1;
+  return ((li - 4) % 2 == 0) ? j : n2 - j;
+}
+constexpr int plane0_entries(int n2) { return 4 + 2 * ((n2 - 1) / 2); }
+struct Plane0 {
+  int n2;           // N2
+  int ndedicated;   // workgroups at the front of the grid that take the m = 0 pencils
+};
+
 template <typename T, int L, int AX, int DIR, class Epi>
 __global__ void __launch_bounds__((strided_threads<T, L, AX, DIR>()))
 k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
-         const cx<T>* __restrict__ tw, int m, int m0_from_dst, Epi epi, const int* skip) {
+         const cx<T>* __restrict__ tw, int m, Plane0 pl, Epi epi, const int* skip) {
   if (skip && *skip) return;
   constexpr int E = strided_e(int(sizeof(cx<T>)), L, AX, DIR);
   constexpr int TM = strided_tm(int(sizeof(cx<T>)), L, AX, DIR);
   constexpr int NT = L / E;
   constexpr int VM = Radix<L, E>::VMAX;
   constexpr int SL = last_stage<L, E>();
+  constexpr bool MIX = AX == 1;
+  static_assert(!MIX || TM % 2 == 0, "mirror pairs of the m = 0 plane take two lanes");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int p = threadIdx.x % TM;
   const int t = threadIdx.x / TM;
-  const int qpen = blockIdx.x * TM + p;
-  const bool active = qpen < geo.batch;
+  const T rs2 = T(0.70710678118654752440);
+  // a workgroup of the m = 0 plane (uniform per workgroup)
+  const bool ded = MIX && (int)blockIdx.x < pl.ndedicated;
+  int k2 = 0;
+  bool canon = true, active;
+  long long mbase = 0;
+  int qpen;
+  if (MIX && ded) {
+    const int li = (int)blockIdx.x * TM + p;
+    k2 = plane0_row(li, pl.n2);
+    canon = (li & 1) == 0;
+    // (the inverse transform of a self-paired row needs one lane)
+    active = k2 >= 0 && (DIR < 0 || canon || li >= 4);
+    qpen = active ? k2 * m : 0;
+    mbase = active ? (long long)((pl.n2 - k2) % pl.n2) * m : 0;
+  } else {
+    qpen = ((int)blockIdx.x - (MIX ? pl.ndedicated : 0)) * TM + p;
+    active = qpen < geo.batch && !(MIX && qpen % m == 0);
+  }
   const long long base = active ? (long long)(qpen / geo.inner) * geo.outer + (qpen % geo.inner) : 0;
-  const bool is_m0 = (qpen % m) == 0;
-  const cx<T>* in = (m0_from_dst && is_m0) ? dst : src;
 
   cx<T> v[VM];
   bool upd = false;
   T be = T(0);
   if constexpr (Epi::PRO) {
-    upd = epi.z != nullptr && !(m0_from_dst && is_m0);
+    upd = epi.z != nullptr;
     if (upd) be = (T)*epi.beta;
   }
-  for_stage_io<L, E, 0>(t, [&](int s, int e) {
-    const long long idx = base + (long long)e * geo.estride;
-    cx<T> x = active ? in[idx] : cx<T>{T(0), T(0)};
+  if (MIX && ded) {
+    // element e of this row and element -e of the partner row
+    for_stage_io<L, E, 0>(t, [&](int s, int e) {
+      cx<T> x = {T(0), T(0)};
+      if (active) {
+        const long long i0 = base + (long long)e * geo.estride;
+        const long long i1 = mbase + (long long)((L - e) % L) * geo.estride;
+        cx<T> a = src[i0], b = src[i1];
+        if constexpr (Epi::PRO) {
+          if (upd) {
+            const cx<T> za = epi.z[i0], zb = epi.z[i1];
+            a = {za.re + be * a.re, za.im + be * a.im};
+            b = {zb.re + be * b.re, zb.im + be * b.im};
+          }
+        }
+        if constexpr (DIR > 0) {
+          const int c = cls2(e, k2, L, pl.n2);
+          x = c == 0 ? a : (c == 1 ? cscale(cadd(a, cmul_i<1>(b)), rs2) : cscale(csub(b, cmul_i<1>(a)), rs2));
+        } else {
+          x = canon ? cscale(cadd(a, b), rs2) : cscale(cmul_i<1>(csub(a, b)), rs2);
+        }
+      }
+      v[s] = x;
+    });
     if constexpr (Epi::PRO) {
-      if (upd && active) {
-        const cx<T> zv = epi.z[idx];
-        x = {zv.re + be * x.re, zv.im + be * x.im};
-        epi.p[idx] = x;
+      if (upd) {
+        // every partner value of the workgroup is read before any is replaced
+        __syncthreads();
+        for_stage_io<L, E, 0>(t, [&](int s, int e) {
+          if (active) {
+            const long long i0 = base + (long long)e * geo.estride;
+            const cx<T> pv = src[i0], zv = epi.z[i0];
+            epi.p[i0] = {zv.re + be * pv.re, zv.im + be * pv.im};
+          }
+        });
       }
     }
-    v[s] = x;
-  });
+  } else {
+    for_stage_io<L, E, 0>(t, [&](int s, int e) {
+      const long long idx = base + (long long)e * geo.estride;
+      cx<T> x = active ? src[idx] : cx<T>{T(0), T(0)};
+      if constexpr (Epi::PRO) {
+        if (upd && active) {
+          const cx<T> zv = epi.z[idx];
+          x = {zv.re + be * x.re, zv.im + be * x.im};
+          epi.p[idx] = x;
+        }
+      }
+      v[s] = x;
+    });
+  }
   auto lidx = [p](int e) { return e * TM + p; };
   fft_stages<T, L, E, DIR, 0>(v, t, lds, lidx, tw);
 
+  // which output elements this lane writes: all of them, except on the
+  // forward m = 0 lanes (their class) where self-conjugate ones are scaled
+  auto keep = [&](int e, cx<T>& h) {
+    if (!(MIX && DIR < 0 && ded)) return true;
+    const int c = cls2(e, k2, L, pl.n2);
+    if (c == 0 && canon) h = cscale(h, rs2);
+    return canon ? c != 2 : c == 2;
+  };
   if constexpr (Epi::NRED > 0) {
     double acc[Epi::NRED];
 #pragma unroll
     for (int q = 0; q < Epi::NRED; ++q) acc[q] = 0.0;
     if (active) {
       for_stage_io<L, E, SL>(t, [&](int s, int e) {
-        const long long idx = base + (long long)e * geo.estride;
-        if (is_m0)
-          dst[idx] = v[s];   // finished by the postmix pass
-        else
-          epi(idx, v[s], acc);
+        cx<T> h = v[s];
+        if (keep(e, h)) epi(base + (long long)e * geo.estride, h, acc);
       });
     }
     block_sums_store<TM * NT, Epi::NRED, Epi::NMAX>(acc, epi.partial, epi.pstride,
                                                     reinterpret_cast<double*>(smem_raw));
   } else {
     if (active) {
-      for_stage_io<L, E, SL>(t, [&](int s, int e) { dst[base + (long long)e * geo.estride] = v[s]; });
+      for_stage_io<L, E, SL>(t, [&](int s, int e) {
+        cx<T> h = v[s];
+        if (keep(e, h)) dst[base + (long long)e * geo.estride] = h;
+      });
     }
   }
 }
 
+// workgroups of the m = 0 plane that lead an axis-1 grid of tile width tm
+inline int plane0_groups(int n2, int tm) { return (plane0_entries(n2) + tm - 1) / tm; }
+
 template <typename T, int L, int AX, int DIR, class Epi>
 void launch_axis12_at(dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* tw, int m,
-                      int m0, Epi epi, const int* skip, hipStream_t s) {
+                      int n2, Epi epi, const int* skip, hipStream_t s) {
   constexpr int TM = strided_tm(int(sizeof(cx<T>)), L, AX, DIR);
   constexpr int NT = L / strided_e(int(sizeof(cx<T>)), L, AX, DIR);
   static_assert((TM * NT) % 64 == 0 && TM * NT <= 1024, "strided tile must be whole waves");
   static_assert((size_t)TM * L * sizeof(cx<T>) <= 163840, "strided tile exceeds the LDS of a CU");
   const size_t shm = (size_t)TM * L * sizeof(cx<T>);
+  const Plane0 pl{n2, AX == 1 ? plane0_groups(n2, TM) : 0};
   auto kern = k_axis12<T, L, AX, DIR, Epi>;
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL(kern, grid, dim3(TM * NT), shm, s, src, dst, geo, tw, m, m0, epi, skip);
+  hipLaunchKernelGGL(kern, dim3(grid.x + pl.ndedicated), dim3(TM * NT), shm, s, src, dst, geo, tw, m, pl, epi, skip);
 }
 
 // ------------------------------------------------------ axis-3 (c2r/r2c) --
@@ -699,6 +816,209 @@ void launch_axis3_at(int mode, int np, const cx<T>* cs, cx<T>* cd, const uint32_
                        sc_dc, sc_ac, skip);
 }
 
+// ------------------------------------- axis-3 (c2r/r2c), transposed tiles --
+// TM whole pencils per workgroup, staged in LDS transposed ([element][pencil],
+// pencil fastest) with the pencil index XOR-swizzled by the element index:
+//   slot(e, p) = e TM + (p ^ (e mod TM)),  TM sizeof(cx) = 256 bytes,
+// so that one element row spans the 64 banks once.  Every LDS access of the
+// pass is then free of bank conflicts: in the FFT stages and in the pairing
+// of element e with L - e, the lanes of one bank pass hold the same element
+// of different pencils (distinct columns); in the coalesced tile loads and
+// stores they hold consecutive elements of one pencil (distinct swizzles).
+// Thread (p, t) = (tid mod TM, tid / TM) transforms pencil p with NT = L/E
+// threads of E values.  The stage plan is exact (NT divides every stage's
+// butterfly count), so the last inverse stage leaves a thread the elements
+// t + NT k (k < E) that the first forward stage reads: the FULL mode goes
+// from the inverse to the forward transform by a register permutation.
+template <typename T>
+constexpr int a3t_tm() { return 256 / int(sizeof(cx<T>)); }
+template <typename T, int L>
+constexpr int a3t_e() { return L >= 64 ? 16 : 8; }
+template <int L, int E>
+constexpr bool plan_exact() {
+  for (int s = 0; s < Radix<L, E>::NSTAGES; ++s)
+    if (!Radix<L, E>::exact(s) || Radix<L, E>::nb(s) * Radix<L, E>::radix(s) != E) return false;
+  return true;
+}
+// whether the transposed tile serves half length L (else the pencil-tile
+// k_axis3 does): power-of-two L from 16 with whole-wave workgroups of at
+// most 512 threads (the FULL mode needs more than 128 VGPRs) and <= 128 KB
+// of LDS
+template <typename T, int L>
+constexpr bool a3t_ok() {
+  constexpr int E = a3t_e<T, L>();
+  constexpr int TM = a3t_tm<T>();
+  // (pencil rows of the mask bits start on 32-bit words from L = 16 on)
+  if constexpr (odd_part(L) != 1 || L < 16 || L % E != 0) {
+    return false;
+  } else {
+    return ((TM * (L / E)) % 64) == 0 && TM * (L / E) <= 512 && TM * L * int(sizeof(cx<T>)) <= 131072 &&
+           plan_exact<L, E>();
+  }
+}
+template <typename T, int L>
+constexpr int a3t_threads() { return a3t_tm<T>() * (L / a3t_e<T, L>()); }
+// mask words of one pencil row (N3 = 2L bits) and their padded LDS stride
+template <int L>
+constexpr int a3t_mwords() { return (2 * L + 31) / 32; }
+template <int L>
+constexpr int a3t_mstride() { return a3t_mwords<L>() | 1; }
+
+template <typename T, int L, int MODE>
+__global__ void __launch_bounds__((a3t_threads<T, L>()))
+k_axis3t(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask, const cx<T>* __restrict__ twm,
+         const cx<T>* __restrict__ tw3, int npencils, T sc_c2r, T sc_r2c_dc, T sc_r2c, const int* skip) {
+  if (skip && *skip) return;
+  constexpr int E = a3t_e<T, L>();
+  constexpr int NT = L / E;
+  constexpr int TM = a3t_tm<T>();
+  constexpr int NTHR = TM * NT;
+  constexpr int N3 = 2 * L;
+  constexpr int SL = last_stage<L, E>();
+  constexpr int MW = a3t_mwords<L>();
+  constexpr int MS = a3t_mstride<L>();
+  static_assert(plan_exact<L, E>(), "transposed axis-3 tiles need an exact stage plan");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  uint32_t* mlds = reinterpret_cast<uint32_t*>(smem_raw + (size_t)TM * L * sizeof(cx<T>));
+  const int tid = threadIdx.x;
+  const int p = tid % TM;
+  const int t = tid / TM;
+  const int pen0 = blockIdx.x * TM;
+  const int valid = npencils - pen0 < TM ? npencils - pen0 : TM;
+  const long long base = (long long)pen0 * L;
+  auto slot = [](int e, int q) { return e * TM + (q ^ (e & (TM - 1))); };
+  auto lidx = [p, slot](int e) { return slot(e, p); };
+  const T rs2 = T(0.70710678118654752440);
+
+  // coalesced tile load: consecutive lanes take consecutive elements of a pencil
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int c = tid + k * NTHR;
+    const int q = c / L, e = c % L;
+    lds[slot(e, q)] = q < valid ? src[base + c] : cx<T>{T(0), T(0)};
+  }
+  if constexpr (MODE == A3_FULL) {
+    for (int i = tid; i < TM * MW; i += NTHR) {
+      const int q = i / MW, wd = i % MW;
+      mlds[q * MS + wd] = q < valid ? mask[(long long)(pen0 + q) * MW + wd] : 0u;
+    }
+  }
+  __syncthreads();
+
+  cx<T> v[E];
+  if constexpr (MODE & A3_C2R) {
+    // Z_e from X_e and X_{L-e} of the packed half spectrum
+    for_stage_io<L, E, 0>(t, [&](int s, int e) {
+      cx<T> z;
+      if (e == 0) {
+        const cx<T> x0 = lds[slot(0, p)];   // (DC, Nyquist)
+        z = {x0.re + x0.im, x0.re - x0.im};
+      } else {
+        const cx<T> a = cscale(lds[slot(e, p)], rs2);
+        const cx<T> b = cconj(cscale(lds[slot(L - e, p)], rs2));
+        const cx<T> sm = cadd(a, b);
+        const cx<T> d = csub(a, b);
+        cx<T> w = tw3[e];          // exp(-2 pi i e / N3)
+        w.im = -w.im;              // exp(+2 pi i e / N3)
+        z = cadd(sm, cmul_i<1>(cmul(w, d)));
+      }
+      v[s] = z;
+    });
+    fft_stages<T, L, E, +1, 0>(v, t, lds, lidx, twm);
+    // z_e = x[2e] + i x[2e+1]: scale, and in FULL mode the mask
+    for_stage_io<L, E, SL>(t, [&](int s, int e) {
+      cx<T> z = cscale(v[s], sc_c2r);
+      if constexpr (MODE == A3_FULL) {
+        const int bit = 2 * e;
+        const uint32_t wd = mlds[p * MS + (bit >> 5)];
+        const int sh = bit & 31;
+        if (!((wd >> sh) & 1u)) z.re = T(0);
+        if (!((wd >> (sh + 1)) & 1u)) z.im = T(0);
+      }
+      v[s] = z;
+    });
+    if constexpr (MODE == A3_C2R) {
+      // through LDS to a coalesced store of the real pencils
+      __syncthreads();
+      for_stage_io<L, E, SL>(t, [&](int s, int e) { lds[slot(e, p)] = v[s]; });
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int c = tid + k * NTHR;
+        const int q = c / L, e = c % L;
+        if (q < valid) dst[base + c] = lds[slot(e, q)];
+      }
+      return;
+    } else {
+      // last-stage slot i r + q holds element t + NT (i + NB q): the
+      // first-stage slot of that element is i + NB q
+      constexpr int R = Radix<L, E>::radix(SL);
+      constexpr int NB = Radix<L, E>::nb(SL);
+      cx<T> u[E];
+#pragma unroll
+      for (int s = 0; s < E; ++s) u[(s / R) + NB * (s % R)] = v[s];
+#pragma unroll
+      for (int s = 0; s < E; ++s) v[s] = u[s];
+    }
+  } else {
+    for_stage_io<L, E, 0>(t, [&](int s, int e) { v[s] = lds[slot(e, p)]; });
+  }
+
+  // forward half-length FFT, then the r2c post-processing in the store
+  // pattern (consecutive lanes on consecutive elements of one pencil)
+  fft_stages<T, L, E, -1, 0>(v, t, lds, lidx, twm);
+  __syncthreads();
+  for_stage_io<L, E, SL>(t, [&](int s, int e) { lds[slot(e, p)] = v[s]; });
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int c = tid + k * NTHR;
+    const int q = c / L, e = c % L;
+    cx<T> xo;
+    if (e == 0) {
+      const cx<T> z0 = lds[slot(0, q)];
+      xo = {(z0.re + z0.im) * sc_r2c_dc, (z0.re - z0.im) * sc_r2c_dc};
+    } else {
+      const cx<T> a = lds[slot(e, q)];
+      const cx<T> b = cconj(lds[slot(L - e, q)]);
+      const cx<T> ev = cscale(cadd(a, b), T(0.5));
+      const cx<T> od = cscale(csub(a, b), T(0.5));
+      const cx<T> w = tw3[e];        // exp(-2 pi i e / N3)
+      xo = cscale(cadd(ev, cmul_i<-1>(cmul(w, od))), sc_r2c);
+    }
+    if (q < valid) dst[base + c] = xo;
+  }
+}
+
+template <typename T, int L>
+void launch_axis3t_at(int mode, int np, const cx<T>* cs, cx<T>* cd, const uint32_t* maskbits,
+                      const cx<T>* twm, const cx<T>* tw3, T sc_c2r, T sc_dc, T sc_ac, const int* skip,
+                      hipStream_t s) {
+  constexpr int TM = a3t_tm<T>();
+  constexpr int NTHR = a3t_threads<T, L>();
+  const size_t shm = (size_t)TM * L * sizeof(cx<T>) +
+                     (mode == A3_FULL ? (size_t)TM * a3t_mstride<L>() * sizeof(uint32_t) : 0);
+  dim3 grid((np + TM - 1) / TM), block(NTHR);
+  if (shm > 65536) {
+    (void)hipFuncSetAttribute((const void*)k_axis3t<T, L, A3_FULL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shm);
+    (void)hipFuncSetAttribute((const void*)k_axis3t<T, L, A3_C2R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shm);
+    (void)hipFuncSetAttribute((const void*)k_axis3t<T, L, A3_R2C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shm);
+  }
+  if (mode == A3_FULL)
+    hipLaunchKernelGGL((k_axis3t<T, L, A3_FULL>), grid, block, shm, s, cs, cd, maskbits, twm, tw3, np, sc_c2r,
+                       sc_dc, sc_ac, skip);
+  else if (mode == A3_C2R)
+    hipLaunchKernelGGL((k_axis3t<T, L, A3_C2R>), grid, block, shm, s, cs, cd, maskbits, twm, tw3, np, sc_c2r,
+                       sc_dc, sc_ac, skip);
+  else
+    hipLaunchKernelGGL((k_axis3t<T, L, A3_R2C>), grid, block, shm, s, cs, cd, maskbits, twm, tw3, np, sc_c2r,
+                       sc_dc, sc_ac, skip);
+}
+
 // ------------------------------------------------------- length dispatch --
 // Grid extents with odd factors that have kernels (each as an axis-1/2
 // pencil length N, and N/2 as the axis-3 half length): small grids that
@@ -715,10 +1035,10 @@ void launch_axis3_at(int mode, int np, const cx<T>* cs, cx<T>* cd, const uint32_
 // fft_mixed_f64.hip and for FP32 in fft_mixed_f32.hip.
 template <typename T, int AX, int DIR, class Epi>
 bool launch_axis12_mixed(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* tw,
-                         int m, int m0, Epi epi, const int* skip, hipStream_t s) {
+                         int m, int n2, Epi epi, const int* skip, hipStream_t s) {
 #define CSIPM_A12(LL)                                                                     \
   case LL:                                                                                \
-    launch_axis12_at<T, LL, AX, DIR, Epi>(grid, src, dst, geo, tw, m, m0, epi, skip, s); \
+    launch_axis12_at<T, LL, AX, DIR, Epi>(grid, src, dst, geo, tw, m, n2, epi, skip, s); \
     return true;
   switch (L) {
     CSIPM_MIXED_LENGTHS(CSIPM_A12)

@@ -62,6 +62,7 @@ csipm_status fail(csipm_status st, const std::string& msg) {
 }  // namespace
 
 const char* noctx_last_error() { return g_err.c_str(); }
+void noctx_set_error(const std::string& msg) { g_err = msg; }
 
 }  // namespace csipm
 

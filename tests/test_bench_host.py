@@ -1,6 +1,6 @@
 """Host logic of bench.py that needs no GPU: the one-GPU guard and the
 algorithmic byte counts behind the roofline figure (K-apply 15 n w + n/8
-bytes plus the m = 0 plane passes; one CG update 16 n w)."""
+bytes; one CG update 16 n w)."""
 import os
 import subprocess
 import sys
@@ -25,14 +25,13 @@ def test_more_than_one_gpu_is_refused():
 def test_kapply_pass_bytes_sum_to_model(shape, w):
     """Five volume passes move the work array once each way (10 n w), the
     K epilogue reads T, p_beta, p_z, Sigma_1, Sigma_2 and writes q_beta, q_z
-    (5 n w more), the axis-3 pass reads the n-bit mask, and the two m = 0
-    plane passes touch 2 N1 N2 reals per array (2 + 7 arrays)."""
+    instead of the work array (5 n w more), and the axis-3 pass reads the
+    n-bit mask: 15 n w + n/8 in all."""
     n1, n2, n3 = shape
     n = n1 * n2 * n3
-    plane = 2 * n1 * n2
     by = bench.pass_bytes(shape, w)
-    assert len(by) == len(bench.PASS_NAMES) == 7
-    assert sum(by) == 15 * n * w + n // 8 + 9 * plane * w
+    assert len(by) == len(bench.PASS_NAMES) == 5
+    assert sum(by) == 15 * n * w + n // 8
 
 
 def test_kernel_bytes_of_the_roofline_kernels():
