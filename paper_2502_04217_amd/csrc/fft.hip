@@ -3,9 +3,9 @@
 // "condensedkkt").  gfx950, wave64.
 //
 // One apply of H is five volume passes over the n-real internal array:
-//   axis 1   : inverse complex FFT along k1 (strided pencils); the leading
-//              workgroups take the m = 0 plane, whose real parametrisation
-//              pairs (k1, k2) with (-k1, -k2), and mix the pairs on input
+//   axis 1   : inverse complex FFT along k1 (strided pencils); the lanes of
+//              the m = 0 plane, whose real parametrisation pairs (k1, k2)
+//              with (-k1, -k2), mix the pairs on input
 //   axis 2   : inverse complex FFT along k2 (strided pencils)
 //   axis 3   : c2r along k3, mask, r2c along k3 (contiguous pencils), using
 //              a half-length complex FFT with the DC/Nyquist pair packed in
@@ -151,9 +151,7 @@ int axis12_tiles(const Grid& g, int axis, int elem_bytes, int dir) {
 }
 
 int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir) {
-  const int L = axis == 1 ? g.n1 : g.n2;
-  const int tm = strided_tm(elem_bytes, L, axis, dir);
-  return axis12_tiles(g, axis, elem_bytes, dir) + (axis == 1 ? plane0_groups(g.n2, tm) : 0);
+  return axis12_tiles(g, axis, elem_bytes, dir) + (axis == 1 ? plane0_groups(dir) : 0);
 }
 
 bool fft_extent_supported(int N, int axis) {
@@ -212,12 +210,9 @@ void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t*
   const T sc_ac = (T)(rn * std::sqrt(2.0));
   const cx<T>* cs = reinterpret_cast<const cx<T>*>(src);
   cx<T>* cd = reinterpret_cast<cx<T>*>(dst);
-#define CSIPM_A3(LL)                                                                                        \
-  case LL:                                                                                                  \
-    if constexpr (a3t_ok<T, LL>())                                                                          \
-      launch_axis3t_at<T, LL>(mode, np, cs, cd, maskbits, tw.tm, tw.t3, sc_c2r, sc_dc, sc_ac, skip, s);     \
-    else                                                                                                    \
-      launch_axis3_at<T, LL>(mode, np, cs, cd, maskbits, tw.tm, tw.t3, sc_c2r, sc_dc, sc_ac, skip, s);      \
+#define CSIPM_A3(LL)                                                                                      \
+  case LL:                                                                                                \
+    launch_axis3_at<T, LL>(mode, np, cs, cd, maskbits, tw.tm, tw.t3, sc_c2r, sc_dc, sc_ac, skip, s); \
     break;
   switch (L) {
     CSIPM_A3(2)

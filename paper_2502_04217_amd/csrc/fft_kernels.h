@@ -326,9 +326,8 @@ struct EpiNone {
 };
 
 // Plain output with the fused CG direction update on input (axis-1 inverse
-// pass of K p): p <- z + beta p as p is loaded, written back to p (in the
-// m = 0 plane only once the workgroup has read the mirror values).  z null:
-// no update.
+// pass of K p): p <- z + beta p as p is loaded, written back to p outside
+// the m = 0 plane (there the K epilogue writes it).  z null: no update.
 template <typename T>
 struct EpiP {
   static constexpr int NRED = 0;
@@ -350,11 +349,18 @@ struct EpiK {
   KArgs<T> a;
   double* partial;
   int pstride;
-  __device__ __forceinline__ void operator()(long long idx, cx<T> h, double* acc) const {
-    const cx<T> pb = reinterpret_cast<const cx<T>*>(a.pb)[idx];
+  // (m0: an element of the m = 0 plane, whose p_beta the inverse pass did
+  // not update)
+  __device__ __forceinline__ void operator()(long long idx, cx<T> h, double* acc, bool m0) const {
+    cx<T> pb = reinterpret_cast<const cx<T>*>(a.pb)[idx];
     cx<T> pz = reinterpret_cast<const cx<T>*>(a.pz)[idx];
     if (a.u.zb) {   // fused direction update of p_z (p_beta was updated on input)
       const T be = (T)*a.u.beta;
+      if (m0) {
+        const cx<T> zb = reinterpret_cast<const cx<T>*>(a.u.zb)[idx];
+        pb = {zb.re + be * pb.re, zb.im + be * pb.im};
+        reinterpret_cast<cx<T>*>(a.u.pb)[idx] = pb;
+      }
       const cx<T> zz = reinterpret_cast<const cx<T>*>(a.u.zz)[idx];
       pz = {zz.re + be * pz.re, zz.im + be * pz.im};
       reinterpret_cast<cx<T>*>(a.u.pz)[idx] = pz;
@@ -382,7 +388,7 @@ struct EpiR {
   RArgs a;
   double* partial;
   int pstride;
-  __device__ __forceinline__ void operator()(long long idx, cx<double> h, double* acc) const {
+  __device__ __forceinline__ void operator()(long long idx, cx<double> h, double* acc, bool) const {
     using D2 = cx<double>;
     const D2 db = reinterpret_cast<const D2*>(a.db)[idx], dz = reinterpret_cast<const D2*>(a.dz)[idx];
     const D2 s1 = reinterpret_cast<const D2*>(a.sig1)[idx], s2 = reinterpret_cast<const D2*>(a.sig2)[idx];
@@ -459,10 +465,9 @@ constexpr int strided_threads() {
 // k3 = 0 and k3 = N3/2 of the real parametrisation, whose coefficients pair
 // (k1, k2) with (-k1, -k2) (derivation "map"): the spectrum U the inverse
 // transform needs at (k1, k2, 0) mixes the stored values W of both, and the
-// forward transform's output H is unmixed the same way.  An axis-1 pencil
-// (k2, m = 0) therefore also reads the pencil of row (N2 - k2) mod N2.  The
-// first `ndedicated` workgroups of an axis-1 pass take the m = 0 pencils and
-// the other workgroups leave their m = 0 lane idle.
+// forward transform's output H is unmixed the same way.  In an axis-1 pass
+// the lane of pencil (k2, m = 0) also reads the pencil of the partner row
+// (N2 - k2) mod N2 at the reversed index -k1:
 //   inverse: U = W on self-conjugate (k1, k2), (W + i W(-k)) / sqrt2 on a
 //            canonical one, (W(-k) - i W) / sqrt2 on its mirror, formed as
 //            the two rows are read;
@@ -470,10 +475,14 @@ constexpr int strided_threads() {
 //            F(R b)(k1) = F(b)(-k1)), the unmixed output of a canonical row
 //            a paired with row b is F((a + R b) / sqrt2) and that of the
 //            mirror row b is F(i (b - R a) / sqrt2): the unmixing is applied
-//            to the inputs.  A self-paired row (k2 = 0 or N2/2) takes two
-//            lanes, one transforming (a + R a) / sqrt2 and writing its
-//            canonical and (scaled by 1/sqrt2) self-conjugate elements, the
-//            other i (a - R a) / sqrt2 and writing its mirror elements.
+//            to the inputs.  A self-paired row (k2 = 0 or N2/2) is both, so
+//            the forward pass gives it two lanes of one workgroup at the
+//            front of the grid: one transforms (a + R a) / sqrt2 and writes
+//            the canonical and (scaled by 1/sqrt2) self-conjugate elements,
+//            the other i (a - R a) / sqrt2 and writes the mirror elements.
+// With the fused CG direction update the m = 0 lanes of the inverse pass
+// read p but do not write it back (a partner row may still need the old
+// value); the forward pass's K epilogue updates p_beta there instead.
 // 2D class of (k1, k2): 0 self-conjugate, 1 canonical, 2 the mirror of a
 // canonical index.
 __host__ __device__ __forceinline__ int cls2(int k1, int k2, int n1, int n2) {
@@ -484,22 +493,17 @@ __host__ __device__ __forceinline__ int cls2(int k1, int k2, int n1, int n2) {
   if (e2 && k1 >= 1 && 2 * k1 < n1) return 1;
   return 2;
 }
-// Row k2 of entry li of the m = 0 pencil list: entries 0, 1 take row 0 and
-// entries 2, 3 row N2/2 (when N2 is even); then the pairs (1, N2 - 1),
-// (2, N2 - 2), ...; -1 for an empty entry.  Even entries have the canonical
-// role, odd entries the mirror role; a pair never straddles two workgroups
-// of an even number of lanes.
-__host__ __device__ __forceinline__ int plane0_row(int li, int n2) {
+__host__ __device__ __forceinline__ bool self_paired_row(int k2, int n2) { return k2 == 0 || 2 * k2 == n2; }
+// lane li of the forward pass's first workgroup: the two self-paired rows,
+// each on a canonical (even li) and a mirror (odd li) lane; -1: idle
+__host__ __device__ __forceinline__ int plane0_self_row(int li, int n2) {
   if (li < 2) return 0;
   if (li < 4) return (n2 % 2 == 0 && n2 >= 2) ? n2 / 2 : -1;
-  const int j = (li - 4) / 2 + 1;
-  if (2 * j >= n2) return -1;
-  return ((li - 4) % 2 == 0) ? j : n2 - j;
+  return -1;
 }
-constexpr int plane0_entries(int n2) { return 4 + 2 * ((n2 - 1) / 2); }
 struct Plane0 {
   int n2;           // N2
-  int ndedicated;   // workgroups at the front of the grid that take the m = 0 pencils
+  int ndedicated;   // workgroups in front of the tiles (forward axis-1 pass: 1)
 };
 
 template <typename T, int L, int AX, int DIR, class Epi>
@@ -513,29 +517,32 @@ k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
   constexpr int VM = Radix<L, E>::VMAX;
   constexpr int SL = last_stage<L, E>();
   constexpr bool MIX = AX == 1;
-  static_assert(!MIX || TM % 2 == 0, "mirror pairs of the m = 0 plane take two lanes");
+  static_assert(!MIX || TM >= 4, "the self-paired rows take four lanes of one workgroup");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int p = threadIdx.x % TM;
   const int t = threadIdx.x / TM;
   const T rs2 = T(0.70710678118654752440);
-  // a workgroup of the m = 0 plane (uniform per workgroup)
-  const bool ded = MIX && (int)blockIdx.x < pl.ndedicated;
+  // the forward pass's workgroup of the self-paired rows (uniform per workgroup)
+  const bool ded = MIX && DIR < 0 && (int)blockIdx.x < pl.ndedicated;
   int k2 = 0;
-  bool canon = true, active;
-  long long mbase = 0;
+  bool canon = true, m0 = false, active;
   int qpen;
   if (MIX && ded) {
-    const int li = (int)blockIdx.x * TM + p;
-    k2 = plane0_row(li, pl.n2);
-    canon = (li & 1) == 0;
-    // (the inverse transform of a self-paired row needs one lane)
-    active = k2 >= 0 && (DIR < 0 || canon || li >= 4);
+    k2 = plane0_self_row(p, pl.n2);
+    active = k2 >= 0;
+    m0 = true;
+    canon = (p & 1) == 0;
     qpen = active ? k2 * m : 0;
-    mbase = active ? (long long)((pl.n2 - k2) % pl.n2) * m : 0;
   } else {
     qpen = ((int)blockIdx.x - (MIX ? pl.ndedicated : 0)) * TM + p;
-    active = qpen < geo.batch && !(MIX && qpen % m == 0);
+    active = qpen < geo.batch;
+    if (MIX && active && qpen % m == 0) {
+      m0 = true;
+      k2 = qpen / m;
+      canon = 2 * k2 < pl.n2;
+      if (DIR < 0 && self_paired_row(k2, pl.n2)) active = false;   // (taken by the first workgroup)
+    }
   }
   const long long base = active ? (long long)(qpen / geo.inner) * geo.outer + (qpen % geo.inner) : 0;
 
@@ -546,62 +553,79 @@ k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
     upd = epi.z != nullptr;
     if (upd) be = (T)*epi.beta;
   }
-  if (MIX && ded) {
-    // element e of this row and element -e of the partner row
-    for_stage_io<L, E, 0>(t, [&](int s, int e) {
-      cx<T> x = {T(0), T(0)};
-      if (active) {
-        const long long i0 = base + (long long)e * geo.estride;
-        const long long i1 = mbase + (long long)((L - e) % L) * geo.estride;
-        cx<T> a = src[i0], b = src[i1];
-        if constexpr (Epi::PRO) {
-          if (upd) {
-            const cx<T> za = epi.z[i0], zb = epi.z[i1];
-            a = {za.re + be * a.re, za.im + be * a.im};
-            b = {zb.re + be * b.re, zb.im + be * b.im};
+  for_stage_io<L, E, 0>(t, [&](int s, int e) {
+    const long long idx = base + (long long)e * geo.estride;
+    cx<T> x = active ? src[idx] : cx<T>{T(0), T(0)};
+    if constexpr (Epi::PRO) {
+      // (an m = 0 lane does not write p back: its partner row may still
+      // need the old value; the forward pass's K epilogue writes it)
+      if (upd && active) {
+        const cx<T> zv = epi.z[idx];
+        x = {zv.re + be * x.re, zv.im + be * x.im};
+        if (!(MIX && m0)) epi.p[idx] = x;
+      }
+    }
+    v[s] = x;
+  });
+  // The partner rows of the workgroup's m = 0 lanes, reversed (element e of
+  // slot r holds element -e of slot r's partner row; with the direction
+  // update applied), are staged in the tile's LDS, which the FFT stages do
+  // not use before their first exchange: every thread loads at most a few
+  // of them while its own loads are in flight, instead of the m = 0 lanes
+  // each waiting on a row of scattered loads; the m = 0 lanes then mix.
+  // Slot r holds the partner of row first + r, for the rows whose m = 0
+  // pencil falls in the tile (pencils q0 .. q0 + TM - 1); in the forward
+  // pass's first workgroup lanes 0-3 are the slots (partner = own row).
+  if constexpr (MIX) {
+    const int q0 = ded ? 0 : ((int)blockIdx.x - pl.ndedicated) * TM;
+    const int first = ded ? 0 : (q0 + m - 1) / m;
+    const int nslot = ded ? 4 : (q0 + TM - 1) / m + 1 - first;
+    if (nslot > 0) {
+      constexpr int NTHR = TM * NT;
+      for (int j = threadIdx.x; j < nslot * L; j += NTHR) {
+        const int r = j / L, i = j % L;
+        int row;
+        if (ded) {
+          row = plane0_self_row(r, pl.n2);
+        } else {
+          row = first + r;
+          if (row >= pl.n2 || (DIR < 0 && self_paired_row(row, pl.n2))) row = -1;
+        }
+        cx<T> y = {T(0), T(0)};
+        if (row >= 0) {
+          const int prow = ded ? row : (pl.n2 - row) % pl.n2;
+          const long long i1 = (long long)prow * m + (long long)((L - i) % L) * geo.estride;
+          y = src[i1];
+          if constexpr (Epi::PRO) {
+            if (upd) {
+              const cx<T> zb = epi.z[i1];
+              y = {zb.re + be * y.re, zb.im + be * y.im};
+            }
           }
         }
-        if constexpr (DIR > 0) {
-          const int c = cls2(e, k2, L, pl.n2);
-          x = c == 0 ? a : (c == 1 ? cscale(cadd(a, cmul_i<1>(b)), rs2) : cscale(csub(b, cmul_i<1>(a)), rs2));
-        } else {
-          x = canon ? cscale(cadd(a, b), rs2) : cscale(cmul_i<1>(csub(a, b)), rs2);
-        }
+        lds[j] = y;
       }
-      v[s] = x;
-    });
-    if constexpr (Epi::PRO) {
-      if (upd) {
-        // every partner value of the workgroup is read before any is replaced
-        __syncthreads();
+      __syncthreads();
+      if (m0 && active) {
+        const int slot = ded ? p : (q0 + p) / m - first;
         for_stage_io<L, E, 0>(t, [&](int s, int e) {
-          if (active) {
-            const long long i0 = base + (long long)e * geo.estride;
-            const cx<T> pv = src[i0], zv = epi.z[i0];
-            epi.p[i0] = {zv.re + be * pv.re, zv.im + be * pv.im};
+          const cx<T> x = v[s];
+          const cx<T> y = lds[slot * L + e];
+          if constexpr (DIR > 0) {
+            const int c = cls2(e, k2, L, pl.n2);
+            v[s] = c == 0 ? x
+                          : (c == 1 ? cscale(cadd(x, cmul_i<1>(y)), rs2) : cscale(csub(y, cmul_i<1>(x)), rs2));
+          } else {
+            v[s] = canon ? cscale(cadd(x, y), rs2) : cscale(cmul_i<1>(csub(x, y)), rs2);
           }
         });
       }
     }
-  } else {
-    for_stage_io<L, E, 0>(t, [&](int s, int e) {
-      const long long idx = base + (long long)e * geo.estride;
-      cx<T> x = active ? src[idx] : cx<T>{T(0), T(0)};
-      if constexpr (Epi::PRO) {
-        if (upd && active) {
-          const cx<T> zv = epi.z[idx];
-          x = {zv.re + be * x.re, zv.im + be * x.im};
-          epi.p[idx] = x;
-        }
-      }
-      v[s] = x;
-    });
   }
   auto lidx = [p](int e) { return e * TM + p; };
   fft_stages<T, L, E, DIR, 0>(v, t, lds, lidx, tw);
 
-  // which output elements this lane writes: all of them, except on the
-  // forward m = 0 lanes (their class) where self-conjugate ones are scaled
+  // the self-paired rows' lanes write the elements of their class
   auto keep = [&](int e, cx<T>& h) {
     if (!(MIX && DIR < 0 && ded)) return true;
     const int c = cls2(e, k2, L, pl.n2);
@@ -615,7 +639,7 @@ k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
     if (active) {
       for_stage_io<L, E, SL>(t, [&](int s, int e) {
         cx<T> h = v[s];
-        if (keep(e, h)) epi(base + (long long)e * geo.estride, h, acc);
+        if (keep(e, h)) epi(base + (long long)e * geo.estride, h, acc, MIX && m0);
       });
     }
     block_sums_store<TM * NT, Epi::NRED, Epi::NMAX>(acc, epi.partial, epi.pstride,
@@ -630,8 +654,9 @@ k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
   }
 }
 
-// workgroups of the m = 0 plane that lead an axis-1 grid of tile width tm
-inline int plane0_groups(int n2, int tm) { return (plane0_entries(n2) + tm - 1) / tm; }
+// workgroups in front of the tiles of an axis-1 pass (the forward pass's
+// workgroup of the self-paired rows)
+inline int plane0_groups(int dir) { return dir < 0 ? 1 : 0; }
 
 template <typename T, int L, int AX, int DIR, class Epi>
 void launch_axis12_at(dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* tw, int m,
@@ -641,7 +666,7 @@ void launch_axis12_at(dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> ge
   static_assert((TM * NT) % 64 == 0 && TM * NT <= 1024, "strided tile must be whole waves");
   static_assert((size_t)TM * L * sizeof(cx<T>) <= 163840, "strided tile exceeds the LDS of a CU");
   const size_t shm = (size_t)TM * L * sizeof(cx<T>);
-  const Plane0 pl{n2, AX == 1 ? plane0_groups(n2, TM) : 0};
+  const Plane0 pl{n2, AX == 1 ? plane0_groups(DIR) : 0};
   auto kern = k_axis12<T, L, AX, DIR, Epi>;
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -813,209 +838,6 @@ void launch_axis3_at(int mode, int np, const cx<T>* cs, cx<T>* cd, const uint32_
                        sc_dc, sc_ac, skip);
   else
     hipLaunchKernelGGL((k_axis3<T, L, A3_R2C>), grid, block, shm, s, cs, cd, maskbits, twm, tw3, np, sc_c2r,
-                       sc_dc, sc_ac, skip);
-}
-
-// ------------------------------------- axis-3 (c2r/r2c), transposed tiles --
-// TM whole pencils per workgroup, staged in LDS transposed ([element][pencil],
-// pencil fastest) with the pencil index XOR-swizzled by the element index:
-//   slot(e, p) = e TM + (p ^ (e mod TM)),  TM sizeof(cx) = 256 bytes,
-// so that one element row spans the 64 banks once.  Every LDS access of the
-// pass is then free of bank conflicts: in the FFT stages and in the pairing
-// of element e with L - e, the lanes of one bank pass hold the same element
-// of different pencils (distinct columns); in the coalesced tile loads and
-// stores they hold consecutive elements of one pencil (distinct swizzles).
-// Thread (p, t) = (tid mod TM, tid / TM) transforms pencil p with NT = L/E
-// threads of E values.  The stage plan is exact (NT divides every stage's
-// butterfly count), so the last inverse stage leaves a thread the elements
-// t + NT k (k < E) that the first forward stage reads: the FULL mode goes
-// from the inverse to the forward transform by a register permutation.
-template <typename T>
-constexpr int a3t_tm() { return 256 / int(sizeof(cx<T>)); }
-template <typename T, int L>
-constexpr int a3t_e() { return L >= 64 ? 16 : 8; }
-template <int L, int E>
-constexpr bool plan_exact() {
-  for (int s = 0; s < Radix<L, E>::NSTAGES; ++s)
-    if (!Radix<L, E>::exact(s) || Radix<L, E>::nb(s) * Radix<L, E>::radix(s) != E) return false;
-  return true;
-}
-// whether the transposed tile serves half length L (else the pencil-tile
-// k_axis3 does): power-of-two L from 16 with whole-wave workgroups of at
-// most 512 threads (the FULL mode needs more than 128 VGPRs) and <= 128 KB
-// of LDS
-template <typename T, int L>
-constexpr bool a3t_ok() {
-  constexpr int E = a3t_e<T, L>();
-  constexpr int TM = a3t_tm<T>();
-  // (pencil rows of the mask bits start on 32-bit words from L = 16 on)
-  if constexpr (odd_part(L) != 1 || L < 16 || L % E != 0) {
-    return false;
-  } else {
-    return ((TM * (L / E)) % 64) == 0 && TM * (L / E) <= 512 && TM * L * int(sizeof(cx<T>)) <= 131072 &&
-           plan_exact<L, E>();
-  }
-}
-template <typename T, int L>
-constexpr int a3t_threads() { return a3t_tm<T>() * (L / a3t_e<T, L>()); }
-// mask words of one pencil row (N3 = 2L bits) and their padded LDS stride
-template <int L>
-constexpr int a3t_mwords() { return (2 * L + 31) / 32; }
-template <int L>
-constexpr int a3t_mstride() { return a3t_mwords<L>() | 1; }
-
-template <typename T, int L, int MODE>
-__global__ void __launch_bounds__((a3t_threads<T, L>()))
-k_axis3t(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask, const cx<T>* __restrict__ twm,
-         const cx<T>* __restrict__ tw3, int npencils, T sc_c2r, T sc_r2c_dc, T sc_r2c, const int* skip) {
-  if (skip && *skip) return;
-  constexpr int E = a3t_e<T, L>();
-  constexpr int NT = L / E;
-  constexpr int TM = a3t_tm<T>();
-  constexpr int NTHR = TM * NT;
-  constexpr int N3 = 2 * L;
-  constexpr int SL = last_stage<L, E>();
-  constexpr int MW = a3t_mwords<L>();
-  constexpr int MS = a3t_mstride<L>();
-  static_assert(plan_exact<L, E>(), "transposed axis-3 tiles need an exact stage plan");
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  uint32_t* mlds = reinterpret_cast<uint32_t*>(smem_raw + (size_t)TM * L * sizeof(cx<T>));
-  const int tid = threadIdx.x;
-  const int p = tid % TM;
-  const int t = tid / TM;
-  const int pen0 = blockIdx.x * TM;
-  const int valid = npencils - pen0 < TM ? npencils - pen0 : TM;
-  const long long base = (long long)pen0 * L;
-  auto slot = [](int e, int q) { return e * TM + (q ^ (e & (TM - 1))); };
-  auto lidx = [p, slot](int e) { return slot(e, p); };
-  const T rs2 = T(0.70710678118654752440);
-
-  // coalesced tile load: consecutive lanes take consecutive elements of a pencil
-#pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const int c = tid + k * NTHR;
-    const int q = c / L, e = c % L;
-    lds[slot(e, q)] = q < valid ? src[base + c] : cx<T>{T(0), T(0)};
-  }
-  if constexpr (MODE == A3_FULL) {
-    for (int i = tid; i < TM * MW; i += NTHR) {
-      const int q = i / MW, wd = i % MW;
-      mlds[q * MS + wd] = q < valid ? mask[(long long)(pen0 + q) * MW + wd] : 0u;
-    }
-  }
-  __syncthreads();
-
-  cx<T> v[E];
-  if constexpr (MODE & A3_C2R) {
-    // Z_e from X_e and X_{L-e} of the packed half spectrum
-    for_stage_io<L, E, 0>(t, [&](int s, int e) {
-      cx<T> z;
-      if (e == 0) {
-        const cx<T> x0 = lds[slot(0, p)];   // (DC, Nyquist)
-        z = {x0.re + x0.im, x0.re - x0.im};
-      } else {
-        const cx<T> a = cscale(lds[slot(e, p)], rs2);
-        const cx<T> b = cconj(cscale(lds[slot(L - e, p)], rs2));
-        const cx<T> sm = cadd(a, b);
-        const cx<T> d = csub(a, b);
-        cx<T> w = tw3[e];          // exp(-2 pi i e / N3)
-        w.im = -w.im;              // exp(+2 pi i e / N3)
-        z = cadd(sm, cmul_i<1>(cmul(w, d)));
-      }
-      v[s] = z;
-    });
-    fft_stages<T, L, E, +1, 0>(v, t, lds, lidx, twm);
-    // z_e = x[2e] + i x[2e+1]: scale, and in FULL mode the mask
-    for_stage_io<L, E, SL>(t, [&](int s, int e) {
-      cx<T> z = cscale(v[s], sc_c2r);
-      if constexpr (MODE == A3_FULL) {
-        const int bit = 2 * e;
-        const uint32_t wd = mlds[p * MS + (bit >> 5)];
-        const int sh = bit & 31;
-        if (!((wd >> sh) & 1u)) z.re = T(0);
-        if (!((wd >> (sh + 1)) & 1u)) z.im = T(0);
-      }
-      v[s] = z;
-    });
-    if constexpr (MODE == A3_C2R) {
-      // through LDS to a coalesced store of the real pencils
-      __syncthreads();
-      for_stage_io<L, E, SL>(t, [&](int s, int e) { lds[slot(e, p)] = v[s]; });
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const int c = tid + k * NTHR;
-        const int q = c / L, e = c % L;
-        if (q < valid) dst[base + c] = lds[slot(e, q)];
-      }
-      return;
-    } else {
-      // last-stage slot i r + q holds element t + NT (i + NB q): the
-      // first-stage slot of that element is i + NB q
-      constexpr int R = Radix<L, E>::radix(SL);
-      constexpr int NB = Radix<L, E>::nb(SL);
-      cx<T> u[E];
-#pragma unroll
-      for (int s = 0; s < E; ++s) u[(s / R) + NB * (s % R)] = v[s];
-#pragma unroll
-      for (int s = 0; s < E; ++s) v[s] = u[s];
-    }
-  } else {
-    for_stage_io<L, E, 0>(t, [&](int s, int e) { v[s] = lds[slot(e, p)]; });
-  }
-
-  // forward half-length FFT, then the r2c post-processing in the store
-  // pattern (consecutive lanes on consecutive elements of one pencil)
-  fft_stages<T, L, E, -1, 0>(v, t, lds, lidx, twm);
-  __syncthreads();
-  for_stage_io<L, E, SL>(t, [&](int s, int e) { lds[slot(e, p)] = v[s]; });
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const int c = tid + k * NTHR;
-    const int q = c / L, e = c % L;
-    cx<T> xo;
-    if (e == 0) {
-      const cx<T> z0 = lds[slot(0, q)];
-      xo = {(z0.re + z0.im) * sc_r2c_dc, (z0.re - z0.im) * sc_r2c_dc};
-    } else {
-      const cx<T> a = lds[slot(e, q)];
-      const cx<T> b = cconj(lds[slot(L - e, q)]);
-      const cx<T> ev = cscale(cadd(a, b), T(0.5));
-      const cx<T> od = cscale(csub(a, b), T(0.5));
-      const cx<T> w = tw3[e];        // exp(-2 pi i e / N3)
-      xo = cscale(cadd(ev, cmul_i<-1>(cmul(w, od))), sc_r2c);
-    }
-    if (q < valid) dst[base + c] = xo;
-  }
-}
-
-template <typename T, int L>
-void launch_axis3t_at(int mode, int np, const cx<T>* cs, cx<T>* cd, const uint32_t* maskbits,
-                      const cx<T>* twm, const cx<T>* tw3, T sc_c2r, T sc_dc, T sc_ac, const int* skip,
-                      hipStream_t s) {
-  constexpr int TM = a3t_tm<T>();
-  constexpr int NTHR = a3t_threads<T, L>();
-  const size_t shm = (size_t)TM * L * sizeof(cx<T>) +
-                     (mode == A3_FULL ? (size_t)TM * a3t_mstride<L>() * sizeof(uint32_t) : 0);
-  dim3 grid((np + TM - 1) / TM), block(NTHR);
-  if (shm > 65536) {
-    (void)hipFuncSetAttribute((const void*)k_axis3t<T, L, A3_FULL>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)shm);
-    (void)hipFuncSetAttribute((const void*)k_axis3t<T, L, A3_C2R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)shm);
-    (void)hipFuncSetAttribute((const void*)k_axis3t<T, L, A3_R2C>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)shm);
-  }
-  if (mode == A3_FULL)
-    hipLaunchKernelGGL((k_axis3t<T, L, A3_FULL>), grid, block, shm, s, cs, cd, maskbits, twm, tw3, np, sc_c2r,
-                       sc_dc, sc_ac, skip);
-  else if (mode == A3_C2R)
-    hipLaunchKernelGGL((k_axis3t<T, L, A3_C2R>), grid, block, shm, s, cs, cd, maskbits, twm, tw3, np, sc_c2r,
-                       sc_dc, sc_ac, skip);
-  else
-    hipLaunchKernelGGL((k_axis3t<T, L, A3_R2C>), grid, block, shm, s, cs, cd, maskbits, twm, tw3, np, sc_c2r,
                        sc_dc, sc_ac, skip);
 }
 
