@@ -106,24 +106,39 @@ def kernel_bytes(name, shape, learned):
     return table.get(base)
 
 
-def kernel_breakdown(pr, opts, shape, learned, info):
+def working_min_us(shape):
+    """Least duration of a launch that does its work: every volume kernel
+    moves at least 2 n FP32 words, which takes 2 n 4 / 8 TB/s at the HBM peak
+    (13.4 us at 256^3 with a 20 % margin).  Launches queued past a Krylov
+    solve's convergence only read the device flag and return; with an event
+    pair around each they still last several microseconds, so a fixed 8 us
+    cut counts some of them as working."""
+    n = shape[0] * shape[1] * shape[2]
+    return max(8.0, 0.8 * 2 * n * 4 / (PEAK_HBM_GBPS * 1e9) * 1e6)
+
+
+def kernel_breakdown(pr, opts, shape, learned):
     """One extra solve with per-kernel event timing; returns the per-kernel
     records (ms per solve) with algorithmic bytes attached, and the wall time
-    of that same solve (event recording included)."""
+    of that same solve (event recording included).  A PCG iteration launches
+    cg_update once, so its working launches are at most the solve's PCG
+    iterations."""
     import torch
     pr.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pr.solve(**opts)
+    info_k = pr.solve(**opts)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    rep = pr.timing_report(8.0)
+    rep = pr.timing_report(working_min_us(shape))
     pr.timing(False)
     # launches of cg_update that start a PCG solve read no x: 2nw fewer bytes
-    starts = int(info["refine_steps_total"]) if opts["precision"] == 1 else int(info["ipm_iters"])
+    starts = int(info_k["refine_steps_total"]) if opts["precision"] == 1 else int(info_k["ipm_iters"])
     out = []
     for r in rep:
         b = kernel_bytes(r["name"], shape, learned)
+        if r["name"].startswith("cg_update"):
+            r["working_calls"] = min(r["working_calls"], int(info_k["cg_iters_total"]))
         if b is not None and r["name"].startswith("cg_update"):
             n = shape[0] * shape[1] * shape[2]
             w = 8 if r["name"].endswith("f64") else 4
@@ -336,8 +351,8 @@ def main():
     # per-kernel event timing of one more solve of each form; the largest
     # HBM-bound kernel of the chosen form is the secondary roofline entry
     n = int(np.prod(w.shape))
-    kern, kern_wall = kernel_breakdown(pr, chosen, w.shape, learned, infos[-1])
-    kern64, kern64_wall = kernel_breakdown(pr, plain, w.shape, False, infos64[-1])
+    kern, kern_wall = kernel_breakdown(pr, chosen, w.shape, learned)
+    kern64, kern64_wall = kernel_breakdown(pr, plain, w.shape, False)
     top = next(r for r in kern if r["bytes_per_launch"] is not None)
     dominant_is_top = top is kern[0]
 

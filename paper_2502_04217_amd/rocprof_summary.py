@@ -93,11 +93,13 @@ def main(argv=None):
     ap.add_argument("--fetch-db")
     ap.add_argument("--write-db")
     ap.add_argument("--calib-bytes", type=int, default=1 << 30)
-    ap.add_argument("--record", nargs=3, metavar=("KERNEL", "NAME", "GRID"),
-                    help="print a traffic-record line for the rocprof kernel KERNEL (short name), timed as NAME "
+    ap.add_argument("--record", nargs=3, metavar=("KERNEL", "NAME", "GRID"), action="append", default=[],
+                    help="(repeatable) "
+                         "print a traffic-record line for the rocprof kernel KERNEL (short name), timed as NAME "
                          "by csipm_timing, at GRID^3, stamped with the current kernel-source digest")
-    ap.add_argument("--record-group", nargs="+", metavar="ARG",
-                    help="NAME GRID KERNEL [KERNEL ...]: a traffic-record line for the sum of one working "
+    ap.add_argument("--record-group", nargs="+", metavar="ARG", action="append", default=[],
+                    help="(repeatable) "
+                         "NAME GRID KERNEL [KERNEL ...]: a traffic-record line for the sum of one working "
                          "dispatch of each listed rocprof kernel (short names), e.g. the kernels of one K-apply")
     a = ap.parse_args(argv)
     if a.fetch_db and a.write_db:
@@ -107,25 +109,23 @@ def main(argv=None):
             fe, wr = tr[k]
             if fe + wr > 1e6:
                 print(f"{k[:60]:60s} read {fe / 1e6:10.2f} MB  write {wr / 1e6:10.2f} MB")
-        if a.record:
-            import json
-            from .build import source_digest
-            kern, name, grid = a.record
+        import json
+        from .build import source_digest
+        digest = source_digest()
+        for kern, name, grid in a.record:
             fe, wr = tr[kern]
             print("traffic-record: " + json.dumps({"kernel": name, "rocprof_kernel": kern, "grid": int(grid),
                                                    "read_bytes": round(fe), "write_bytes": round(wr),
                                                    "fetch_factor": round(ff, 4), "write_factor": round(fw, 4),
-                                                   "source_sha256": source_digest()}))
-        if a.record_group:
-            import json
-            from .build import source_digest
-            name, grid, kerns = a.record_group[0], a.record_group[1], a.record_group[2:]
+                                                   "source_sha256": digest}))
+        for group in a.record_group:
+            name, grid, kerns = group[0], group[1], group[2:]
             fe = sum(tr[k][0] for k in kerns)
             wr = sum(tr[k][1] for k in kerns)
             print("traffic-record: " + json.dumps({"kernel": name, "rocprof_kernels": kerns, "grid": int(grid),
                                                    "read_bytes": round(fe), "write_bytes": round(wr),
                                                    "fetch_factor": round(ff, 4), "write_factor": round(fw, 4),
-                                                   "source_sha256": source_digest()}))
+                                                   "source_sha256": digest}))
     out, counters, total_us = summarize(a.db, a.top, a.min_us)
     print(f"# kernel time total {total_us:.1f} us; working = dispatches >= {a.min_us} us")
     print(f"{'kernel':60s} {'calls':>6s} {'total_us':>11s} {'avg_us':>9s} {'pct':>6s} {'work':>5s} {'work_avg_us':>11s}")

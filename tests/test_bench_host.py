@@ -46,3 +46,11 @@ def test_kernel_bytes_of_the_roofline_kernels():
     assert bench.kernel_bytes("axis3.f32", shape, False) == 2 * n * 4 + n // 8
     # the finalize kernels carry no byte count
     assert bench.kernel_bytes("fin_alpha", shape, False) is None
+
+
+def test_working_launch_threshold():
+    """A working launch moves at least 2 n FP32 words; at 8 TB/s that is
+    16.8 us at 256^3, taken with a 20 % margin; small grids keep 8 us."""
+    assert bench.working_min_us((256, 256, 256)) == pytest.approx(0.8 * 2 * 256 ** 3 * 4 / 8e12 * 1e6)
+    assert 13.0 < bench.working_min_us((256, 256, 256)) < 14.0
+    assert bench.working_min_us((64, 64, 64)) == 8.0
