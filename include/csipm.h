@@ -364,6 +364,14 @@ csipm_status csipm_mlp_loss_grad_noalloc(const float* d_params, const float* d_f
  * [max_iters][n_per_iter][6] records {u = (H p_beta)_i, p_beta_i, L1, L2,
  * 4 S1 S2, w}, with w = (PCG iterations of that Newton system) /
  * sum_j (p_beta_j^2 + p_z_j^2).  enable = 0 turns capture off.
+ * enable = 2 captures as the learned correction is used: only at the
+ * iterations where the learned form would apply it (the previous Newton
+ * system needed at least opts->pc_min_cg PCG iterations, at most
+ * opts->pc_max_relevant of the coefficients are relevant, and at least one
+ * is), and with idx_j = a[splitmix64(seed + it * n_per_iter + j) mod m],
+ * where a lists in increasing order the m coefficients at which
+ * L1 / (L1 + 4 S1 S2) >= 1e-3 (where c can act on P_c^{-1}).  Other values
+ * of enable return CSIPM_EINVAL.
  * csipm_captured returns how many iterations were captured by the last solve
  * and their PCG counts (cg_counts_host may be NULL). */
 csipm_status csipm_capture(csipm_ctx* ctx, int enable, float* d_feat, float* d_rec, int n_per_iter,

@@ -307,10 +307,12 @@ class Problem:
         self._check(lib().csipm_set_pc_params(self._ctx, _ptr(self._params), self._params.numel()),
                     "set_pc_params")
 
-    def capture(self, feat, rec, n_per_iter: int, max_iters: int, seed: int = 0):
+    def capture(self, feat, rec, n_per_iter: int, max_iters: int, seed: int = 0, policy: bool = False):
+        """csipm_capture; policy=True is mode 2 (iterations and coefficients
+        where the learned form applies the correction)."""
         self._cap = (feat, rec)
-        self._check(lib().csipm_capture(self._ctx, 1, _ptr(feat), _ptr(rec), n_per_iter, max_iters, seed),
-                    "capture")
+        self._check(lib().csipm_capture(self._ctx, 2 if policy else 1, _ptr(feat), _ptr(rec), n_per_iter,
+                                        max_iters, seed), "capture")
 
     def capture_off(self):
         self._check(lib().csipm_capture(self._ctx, 0, None, None, 0, 0, 0), "capture")

@@ -308,9 +308,12 @@ template <typename T>
 void capture_pair(csipm_ctx* c, const T* pb, const T* pz, const T* qb, const T* qz, const T* s1, const T* s2) {
   compute_features(c);
   const size_t off = (size_t)c->cap_count * c->cap_per_iter;
+  // policy capture draws among the coefficients where the correction acts;
+  // their list goes to fwb (an FP32 n-array only the CR and CAr solvers use)
   mlp_capture<T>(pb, pz, qb, qz, s1, s2, c->feat, c->g.n, c->cap_per_iter,
                  c->cap_seed + (unsigned long long)c->cap_count * (unsigned long long)c->cap_per_iter,
-                 c->cap_feat + off * 4, c->cap_rec + off * MLP_REC, c->partV, c->s);
+                 c->cap_feat + off * 4, c->cap_rec + off * MLP_REC, c->partV,
+                 c->cap_enable == 2 ? reinterpret_cast<int*>(c->fwb) : nullptr, kPcRelevance, c->s);
 }
 
 // ------------------------------------------------------------------- PCG --
@@ -855,6 +858,34 @@ csipm_status residuals(csipm_ctx* c, Resid& r, bool logsum) {
   return CSIPM_OK;
 }
 
+// The learned correction of the current iterate when the last iterate update
+// has built its Newton system with the paper's P (in FP64, or in FP32 with
+// or without the FP64 h and Sigma of a refined solve): c from the state (as learned_correction forms
+// it), and the PCG start and its sums rewritten to those of P_c, so that no
+// newton_init pass rebuilds the system.  The update's residual reduction has
+// left the centring sum and max |beta| of this iterate.
+csipm_status correction_patch(csipm_ctx* c, bool f64, bool ref64) {
+  const long long n = c->g.n;
+  const int nbv = vec_blocks(n);
+  double* const part = c->partV + (size_t)NRESID_Q * VEC_MAX_BLOCKS;
+  const double* ml = c->scal + S_RESID + 7;
+  const double* bmax = c->scal + S_RESID + 4;
+  const double mscale = 1.0 / (double)n;
+  if (f64) {
+    KT(c, "correction_patch.f64",
+       mlp_correction_patch<double>(c->beta, c->z, c->nu1, c->nu2, c->diagH, ml, mscale, bmax, c->mlp_params, c->pc_c,
+                                    n, kPcRelevance, c->sig1, c->sig2, c->rb, c->rz, c->pb, c->pz, nullptr, nullptr,
+                                    nullptr, nullptr, part, VEC_MAX_BLOCKS, nbv, c->s));
+  } else {
+    KT(c, "correction_patch.f32",
+       mlp_correction_patch<float>(c->beta, c->z, c->nu1, c->nu2, c->diagH, ml, mscale, bmax, c->mlp_params, c->pc_c,
+                                   n, kPcRelevance, c->sig1f, c->sig2f, c->frb, c->frz, c->fpb, c->fpz,
+                                   ref64 ? c->sig1 : nullptr, ref64 ? c->sig2 : nullptr, ref64 ? c->rhb : nullptr,
+                                   ref64 ? c->rhz : nullptr, part, VEC_MAX_BLOCKS, nbv, c->s));
+  }
+  return hip_check(c, "correction_patch");
+}
+
 // LASSO certificate of beta from G = H beta - xi (which must be exact: an
 // FP64 H-apply, not the carried value) into the certificate fields of inf;
 // synchronises.
@@ -919,6 +950,10 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   c->cap_cg.clear();
   const double z0 = c->xi_inf > 0 ? c->xi_inf : 1.0;
   const bool learned = o.pc == CSIPM_PC_LEARNED;
+  // the residual passes count the coefficients where the correction can act
+  // (and sum the centring of its first feature) for the learned form and for
+  // a capture that follows the correction's policy
+  const bool need_rel = learned || c->cap_enable == 2;
   // scaled identity: c = rho everywhere, rho = m/n unless given
   const float* pc_fixed = nullptr;
   if (o.pc == CSIPM_PC_SCALED) {
@@ -929,7 +964,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   // the start beta = 0 has H beta = 0 exactly: G = -xi
   KT(c, "ipm_init", ipm_init(c->beta, c->z, c->nu1, c->nu2, c->hb, c->xi, n, z0, lam, c->s));
   KT(c, "ipm_resid+fin",
-     ipm_resid(c->beta, c->z, c->nu1, c->nu2, c->hb, nullptr, lam, n, c->partV, c->scal + S_RESID, learned, c->s));
+     ipm_resid(c->beta, c->z, c->nu1, c->nu2, c->hb, nullptr, lam, n, c->partV, c->scal + S_RESID, need_rel, c->s));
   csipm_status st = sync_scalars(c, "solve start");
   if (st != CSIPM_OK) return st;
   Resid r = read_resid(c);
@@ -958,7 +993,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     if (!exact && (rel <= o.tol || it >= o.max_iter || carried >= kExactEvery || leaving_trust || have_snap ||
                    carry_err > kCarryFrac * rel * (1.0 + c->xi_inf) || rel > kStallFactor * best_rel ||
                    !std::isfinite(rel))) {
-      st = residuals(c, r, learned);
+      st = residuals(c, r, need_rel);
       if (st != CSIPM_OK) return st;
       exact = true;
       approx = false;
@@ -972,7 +1007,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     // ends there with the better iterate
     if (have_snap && !(rel <= snap_rel)) {
       restore_state(c);
-      st = residuals(c, r, learned);
+      st = residuals(c, r, need_rel);
       if (st != CSIPM_OK) return st;
       rel = rel_of(r);
       result = CSIPM_STALLED;
@@ -1017,26 +1052,33 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     int cgi = 0, ref = 0;
     bool conv = false, fell = false;
     HdSource src = HD_RRES64;
-    const bool capture =
-        c->cap_enable && o.pc == CSIPM_PC_PLAIN && o.krylov == CSIPM_KRYLOV_CG && c->cap_count < c->cap_max;
+    // (a policy capture takes only the iterations where the learned form
+    // would apply the correction: see use_learned below)
+    const bool capture = c->cap_enable && o.pc == CSIPM_PC_PLAIN && o.krylov == CSIPM_KRYLOV_CG &&
+                         c->cap_count < c->cap_max &&
+                         (c->cap_enable != 2 || (prev_cg >= o.pc_min_cg && r.relevant >= 1.0 &&
+                                                 r.relevant / (double)n <= o.pc_max_relevant));
     // the correction is applied once a Newton system has needed more than
     // pc_min_cg - 1 PCG iterations (a system the paper's P solves in one
     // iteration leaves nothing to gain) and while at most pc_max_relevant of
     // the coefficients are relevant (reduced with the residual of the
     // iterate)
-    const double relevant = learned ? r.relevant / (double)n : -1.0;
+    const double relevant = need_rel ? r.relevant / (double)n : -1.0;
     const bool use_learned = learned && prev_cg >= o.pc_min_cg && relevant <= o.pc_max_relevant;
     // the system the last update built applies when it was built for this
     // precision and preconditioner
     const bool trusted_now = o.refine_trust > 0.0 && eta >= o.refine_trust;
-    const bool prebuilt = !use_learned && !o.mehrotra &&
+    // (built with the paper's P: with the correction it is patched in place)
+    const bool prebuilt = !o.mehrotra &&
                           (next_kind == NEXT_F64   ? o.precision == CSIPM_FP64
                            : next_kind == NEXT_F32_REF ? o.precision == CSIPM_FP32
                            : next_kind == NEXT_F32     ? o.precision == CSIPM_FP32 && trusted_now
                                                        : false);
+    const int built_kind = next_kind;
     next_kind = NEXT_NONE;
     if (use_learned) {
-      st = learned_correction(c, true);
+      st = prebuilt ? correction_patch(c, built_kind == NEXT_F64, built_kind == NEXT_F32_REF)
+                    : learned_correction(c, true);
       if (st != CSIPM_OK) return st;
     }
     // one Newton system at target tmu (with the corrector terms of the affine
@@ -1049,11 +1091,11 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
         csipm_options ol = o;
         const int budget = prev_cg > 0 ? std::min(o.cg_max, std::max(8, (prev_cg * 3) / 2)) : o.cg_max;
         ol.cg_max = budget;
-        e = newton_solve(c, ol, tmu, eta, c->pc_c, a, b, conv, false, src, dab, daz);
+        e = newton_solve(c, ol, tmu, eta, c->pc_c, a, b, conv, false, src, dab, daz, prebuilt);
         if (e != CSIPM_OK) return e;
         cgi += a;
         ref += b;
-        if (!conv) {
+        if (!conv) {   // (rebuilt with the paper's P)
           e = newton_solve(c, o, tmu, eta, nullptr, a, b, conv, false, src, dab, daz);
           if (e != CSIPM_OK) return e;
           cgi += a;
@@ -1124,18 +1166,18 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     // The update also builds the next iteration's Newton system from the new
     // iterate (saving newton_init's pass over the state) when that system is
     // predictable: standard steps, CG, no capture, a converged solve (else
-    // the next iteration recomputes G first), the learned correction not
-    // expected (the relevant fraction of this iterate stands in for the
-    // next), and in FP32 the refinement expected or not from the last
-    // reduction of rel_kkt.  Its target sigma mu+ comes from the step's sums.
-    // A system the next iteration cannot use (another precision, a
-    // recomputed G, the correction after all) is rebuilt by newton_init.
+    // the next iteration recomputes G first), and in FP32 the refinement
+    // expected or not from the last reduction of rel_kkt.  Its target
+    // sigma mu+ comes from the step's sums.  It is built with the paper's P;
+    // if the next iteration applies the learned correction, correction_patch
+    // turns it into the corrected system.  A system the next iteration
+    // cannot use (another precision, a recomputed G) is rebuilt by
+    // newton_init.
     int fuse_kind = NEXT_NONE;
     if (o.build_next && !o.mehrotra && o.krylov == CSIPM_KRYLOV_CG && !c->cap_enable && conv && it + 1 < o.max_iter &&
         carried + 1 < kExactEvery) {
-      const bool pred_learned = learned && cgi >= o.pc_min_cg && relevant <= o.pc_max_relevant;
       const double rel_pred = rel * std::min(1.0, rel / prev_rel);
-      if (!pred_learned && rel_pred > o.tol) {
+      if (rel_pred > o.tol) {
         if (o.precision == CSIPM_FP64) {
           fuse_kind = NEXT_F64;
         } else if (o.refine_trust > 0.0 && std::min(o.cg_rtol, 0.1 * rel_pred) >= o.refine_trust) {
@@ -1168,7 +1210,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     KT(c, kAdvName[d32b ? 1 : 0][fuse_kind],
        ipm_advance(c->beta, c->z, c->nu1, c->nu2, c->hb, c->dxb, c->dxz, d32b, d32z,
                    src == HD_DIRECT ? c->rb : nullptr, c->rb, src == HD_RRES32 ? c->frb : nullptr, lam, smu, c->scal, n,
-                   c->partV, learned, c->s, dab, daz, fuse_kind != NEXT_NONE ? &nx : nullptr));
+                   c->partV, need_rel, c->s, dab, daz, fuse_kind != NEXT_NONE ? &nx : nullptr));
     st = sync_scalars(c, "advance");
     if (st != CSIPM_OK) return st;
     r = read_resid(c);
@@ -1425,7 +1467,8 @@ csipm_status csipm_capture(csipm_ctx* c, int enable, float* d_feat, float* d_rec
     return CSIPM_OK;
   }
   if (!d_feat || !d_rec || n_per_iter < 1 || max_iters < 1) return fail(c, CSIPM_EINVAL, "capture buffers");
-  c->cap_enable = 1;
+  if (enable != 1 && enable != 2) return fail(c, CSIPM_EINVAL, "capture mode");
+  c->cap_enable = enable;
   c->cap_feat = d_feat;
   c->cap_rec = d_rec;
   c->cap_per_iter = n_per_iter;

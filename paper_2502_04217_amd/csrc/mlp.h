@@ -38,6 +38,19 @@ void mlp_mean_log_l1_state(const double* beta, const double* z, const double* nu
 void mlp_correction_state(const double* beta, const double* z, const double* nu1, const double* nu2,
                           const double* diagH, const double* meanlog, double mscale, const double* bmax,
                           const float* params, float* c, long long n, double rmin, hipStream_t s);
+// c of the interior-point state as mlp_correction_state forms it, for an
+// iterate whose Newton system (Sigma s1c/s2c, r = rb/rz, p = pb/pz in TC;
+// for TC = float also the FP64 Sigma s164/s264 and h hb64/hz64, or null)
+// was built with c = 1: p is rewritten to P_c^{-1} r where c acts, and the
+// change of r.P^{-1}r (and h.P^{-1}h) is added to partial[b] (and
+// partial[stride + b]) for workgroup b < max_blocks
+template <typename TC>
+void mlp_correction_patch(const double* beta, const double* z, const double* nu1, const double* nu2,
+                          const double* diagH, const double* meanlog, double mscale, const double* bmax,
+                          const float* params, float* c, long long n, double rmin, const TC* s1c, const TC* s2c,
+                          const TC* rb, const TC* rz, TC* pb, TC* pz, const double* s164, const double* s264,
+                          const double* hb64, const double* hz64, double* partial, int stride, int max_blocks,
+                          hipStream_t s);
 // c = softplus(MLP(feat)) + 1e-6 for n records (matrix-core inference)
 void mlp_forward(const float* params, const float* feat, float* c, long long n, hipStream_t s);
 // gradient of sum_i dc_i c_i, accumulated into grad (float, 1249)
@@ -52,10 +65,13 @@ void mlp_adam(float* params, const float* grad, float* m, float* v, int t, float
 // Capture: records at coefficients idx_j = splitmix64(seed + j) mod n,
 // j < npick, from (p, q = K p) and the barrier diagonals; feat_all is the
 // full [n][4] feature array of the iterate.  w_j = 1 / sum_j (pb^2 + pz^2).
+// With gate_idx (n ints of scratch) the coefficients are drawn only among
+// those where L1 / (L1 + 4 S1 S2) >= rmin; partial must then hold
+// 8192 + 1024 doubles.
 template <typename T>
 void mlp_capture(const T* pb, const T* pz, const T* qb, const T* qz, const T* s1, const T* s2,
                  const float* feat_all, long long n, int npick, unsigned long long seed, float* out_feat,
-                 float* out_rec, double* partial, hipStream_t s);
+                 float* out_rec, double* partial, int* gate_idx, double rmin, hipStream_t s);
 void mlp_scale_weights(float* rec, int npick, float factor, hipStream_t s);
 
 }  // namespace csipm

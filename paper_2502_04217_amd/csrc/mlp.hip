@@ -4,7 +4,9 @@
 // (I -> diag(c), c > 0 keeps every 2x2 block positive definite).
 #include "mlp.h"
 
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace csipm {
 
@@ -15,6 +17,7 @@ constexpr int OW1 = 0, OB1 = OW1 + H1 * NIN, OW2 = OB1 + H1, OB2 = OW2 + H2 * H1
 static_assert(OB3 + 1 == MLP_NP, "parameter layout");
 constexpr int RB = MLP_REC_PER_BLOCK;   // records per training workgroup
 constexpr int RP = RB + 1;      // padded LDS row
+constexpr int kGateBlocks = 1024;   // workgroups listing the coefficients where the correction acts
 
 __device__ __forceinline__ long long gtid() { return blockIdx.x * (long long)blockDim.x + threadIdx.x; }
 __device__ __forceinline__ long long gstride() { return (long long)gridDim.x * blockDim.x; }
@@ -399,6 +402,32 @@ k_features_state(const double* __restrict__ beta, const double* __restrict__ z, 
 }
 
 
+// Gate and features of coefficient i of the interior-point state.  The
+// slacks are formed in FP64 (z and |beta| nearly cancel late in the solve);
+// the gate L1 / (L1 + 4 S1 S2) >= rmin is multiplied through by s1 s2 > 0:
+// (nu1 s2 + nu2 s1) >= rmin (nu1 s2 + nu2 s1 + 4 nu1 nu2), no division.
+// The features are FP32 from the FP64 slacks.  diagH is read only where
+// the gate passes: the network maps each coefficient's features to its own
+// output (a column of every layer's product), so an inactive lane's
+// features, whose output is discarded, need not be exact.
+__device__ __forceinline__ bool state_features(const double* __restrict__ beta, const double* __restrict__ z,
+                                               const double* __restrict__ nu1, const double* __restrict__ nu2,
+                                               const double* __restrict__ diagH, double ml, double ibm, double rmin,
+                                               long long i, float x[NIN]) {
+  const double b = beta[i], a1 = nu1[i], a2 = nu2[i];
+  const double s1 = z[i] + b, s2 = z[i] - b;
+  const double num = a1 * s2 + a2 * s1;
+  const bool act = num >= rmin * (num + 4.0 * a1 * a2);
+  const float g1 = (float)a1 * __builtin_amdgcn_rcpf((float)s1);
+  const float g2 = (float)a2 * __builtin_amdgcn_rcpf((float)s2);
+  const float L1 = g1 + g2;
+  x[0] = __logf(L1) - (float)ml;
+  x[1] = (g1 - g2) * __builtin_amdgcn_rcpf(L1);
+  x[2] = __logf((float)(fabs(b) * ibm) + 1e-12f);
+  x[3] = act ? (float)diagH[i] : 0.0f;
+  return act;
+}
+
 // Correction of the interior-point state in one pass: Sigma_j = nu_j / s_j,
 // the four features, and c = softplus(MLP) + 1e-6 only where c can act on
 // P_c^{-1}, i.e. where L1 / (L1 + 4 S1 S2) >= rmin; elsewhere c = 1 (the
@@ -420,27 +449,92 @@ k_correction_state(const double* __restrict__ beta, const double* __restrict__ z
   for (long long ch = blockIdx.x * (long long)kNetWaves + wv; ch < nch; ch += (long long)gridDim.x * kNetWaves) {
     const long long i = ch * 64 + l;
     float x[NIN] = {0.0f, 0.0f, 0.0f, 0.0f};
-    bool act = false;
-    if (i < n) {
-      // slacks in FP64 (z and |beta| nearly cancel late in the solve); the
-      // gate L1 / (L1 + 4 S1 S2) >= rmin multiplied through by s1 s2 > 0:
-      // (nu1 s2 + nu2 s1) >= rmin (nu1 s2 + nu2 s1 + 4 nu1 nu2), no division
-      const double b = beta[i], a1 = nu1[i], a2 = nu2[i];
-      const double s1 = z[i] + b, s2 = z[i] - b;
-      const double num = a1 * s2 + a2 * s1;
-      act = num >= rmin * (num + 4.0 * a1 * a2);
-      // features in FP32 from the FP64 slacks
-      const float g1 = (float)a1 * __builtin_amdgcn_rcpf((float)s1);
-      const float g2 = (float)a2 * __builtin_amdgcn_rcpf((float)s2);
-      const float L1 = g1 + g2;
-      x[0] = __logf(L1) - (float)ml;
-      x[1] = (g1 - g2) * __builtin_amdgcn_rcpf(L1);
-      x[2] = __logf((float)(fabs(b) * ibm) + 1e-12f);
-      x[3] = (float)diagH[i];
-    }
+    const bool act = i < n && state_features(beta, z, nu1, nu2, diagH, ml, ibm, rmin, i, x);
     float o = 0.0f;
     if (__ballot(act)) o = net_chunk<kNetTiles>(w, lds[wv], x);   // chunks without an active coefficient skip the network
     if (i < n) c[i] = act ? softplusf(o) + 1e-6f : 1.0f;
+  }
+}
+
+// The correction of an iterate whose Newton system the iterate update has
+// already built with the paper's P (c = 1): c as k_correction_state forms
+// it, and, at each coefficient where c acts, the PCG start patched in place
+// to p = P_c^{-1} r, by the same arithmetic as the Newton build with c.
+// Each workgroup adds what the patch changes in r.P^{-1}r (quantity 0, in
+// the Krylov precision TC, summed in FP64) and in h.P^{-1}h (quantity 1,
+// FP64; only when h64 is given) to its own partial of the update's
+// reduction, so the start sums become those of the corrected system.  The
+// grid must not exceed the update's workgroup count.  For TC = double, r is
+// h and the FP64 Sigma is s1c/s2c; for TC = float the FP64 h and Sigma are
+// hb64/hz64 and s164/s264 (null for a system solved without refinement,
+// whose h.P^{-1}h is not used).
+template <typename TC>
+__global__ void __launch_bounds__(64 * kNetWaves)
+k_correction_patch(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
+                   const double* __restrict__ nu2, const double* __restrict__ diagH,
+                   const double* __restrict__ meanlog, double mscale, const double* __restrict__ bmax,
+                   const float* __restrict__ P, float* __restrict__ c, long long n, double rmin,
+                   const TC* __restrict__ s1c, const TC* __restrict__ s2c, const TC* __restrict__ rb,
+                   const TC* __restrict__ rz, TC* __restrict__ pb, TC* __restrict__ pz,
+                   const double* __restrict__ s164, const double* __restrict__ s264,
+                   const double* __restrict__ hb64, const double* __restrict__ hz64, double* partial, int stride) {
+  constexpr bool F64 = std::is_same<TC, double>::value;
+  __shared__ float lds[kNetWaves][64 * NIN];
+  __shared__ double red[2][kNetWaves];
+  MfmaNet w;
+  load_net(P, w);
+  const double ml = *meanlog * mscale;
+  const double ibm = *bmax > 0.0 ? 1.0 / *bmax : 1.0;
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long long nch = (n + 63) / 64;
+  const bool h64 = F64 || hb64 != nullptr;
+  double d0 = 0.0, d1 = 0.0;
+  for (long long ch = blockIdx.x * (long long)kNetWaves + wv; ch < nch; ch += (long long)gridDim.x * kNetWaves) {
+    const long long i = ch * 64 + l;
+    float x[NIN] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const bool act = i < n && state_features(beta, z, nu1, nu2, diagH, ml, ibm, rmin, i, x);
+    if (!__ballot(act)) {
+      if (i < n) c[i] = 1.0f;
+      continue;
+    }
+    const float o = net_chunk<kNetTiles>(w, lds[wv], x);
+    const float ci = act ? softplusf(o) + 1e-6f : 1.0f;
+    if (i < n) c[i] = ci;
+    if (act) {
+      const double cv = (double)ci;
+      const TC r1 = rb[i], r2 = rz[i], g1 = s1c[i], g2 = s2c[i];
+      TC w1, w2, v1, v2;
+      pinv_block<TC>(r1, r2, g1, g2, cv, w1, w2);
+      pinv_block<TC>(r1, r2, g1, g2, 1.0, v1, v2);
+      pb[i] = w1;
+      pz[i] = w2;
+      d0 += ((double)r1 * (double)w1 + (double)r2 * (double)w2) - ((double)r1 * (double)v1 + (double)r2 * (double)v2);
+      if constexpr (F64) {
+        d1 += (r1 * w1 + r2 * w2) - (r1 * v1 + r2 * v2);
+      } else if (h64) {
+        const double h1 = hb64[i], h2 = hz64[i], G1 = s164[i], G2 = s264[i];
+        double u1, u2, q1, q2;
+        pinv_block<double>(h1, h2, G1, G2, cv, u1, u2);
+        pinv_block<double>(h1, h2, G1, G2, 1.0, q1, q2);
+        d1 += (h1 * u1 + h2 * u2) - (h1 * q1 + h2 * q2);
+      }
+    }
+  }
+  d0 = wave_sum(d0);
+  d1 = wave_sum(d1);
+  if (l == 0) {
+    red[0][wv] = d0;
+    red[1][wv] = d1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int k = 0; k < kNetWaves; ++k) {
+      a0 += red[0][k];
+      a1 += red[1][k];
+    }
+    partial[blockIdx.x] += a0;
+    if (h64) partial[stride + blockIdx.x] += a1;
   }
 }
 
@@ -451,18 +545,30 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
   return x ^ (x >> 31);
 }
 
+// Records at coefficients i_j, j < npick: i_j = splitmix64(seed + j) mod n,
+// or, with a list of the m = *count coefficients where the correction can
+// act (idx), i_j = idx[splitmix64(seed + j) mod m]; with an empty list every
+// record has p = 0 and carries no weight.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_capture(const T* __restrict__ pb, const T* __restrict__ pz, const T* __restrict__ qb, const T* __restrict__ qz,
           const T* __restrict__ s1, const T* __restrict__ s2, const float* __restrict__ feat_all, long long n,
-          int npick, unsigned long long seed, float* __restrict__ of, float* __restrict__ orc, double* partial) {
+          int npick, unsigned long long seed, const int* __restrict__ idx, const long long* __restrict__ count,
+          float* __restrict__ of, float* __restrict__ orc, double* partial) {
   (void)qz;   // (H p) is the beta row of q less its Sigma terms; q_z is not needed
+  const long long m = idx ? *count : n;
   double acc = 0.0;
   for (long long j = gtid(); j < npick; j += gstride()) {
-    const long long i = (long long)(splitmix64(seed + (unsigned long long)j) % (unsigned long long)n);
+    float* rc = orc + j * MLP_REC;
+    if (m == 0) {
+      rc[0] = 0.0f; rc[1] = 0.0f; rc[2] = 1.0f; rc[3] = 0.0f; rc[4] = 0.0f; rc[5] = 1.0f;
+      reinterpret_cast<float4*>(of)[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      continue;
+    }
+    const long long h = (long long)(splitmix64(seed + (unsigned long long)j) % (unsigned long long)m);
+    const long long i = idx ? (long long)idx[h] : h;
     const double b = pb[i], z = pz[i], g1 = s1[i], g2 = s2[i];
     const double u = (double)qb[i] - g1 * (b + z) - g2 * (b - z);
-    float* rc = orc + j * MLP_REC;
     rc[0] = (float)u;
     rc[1] = (float)b;
     rc[2] = (float)(g1 + g2);
@@ -477,6 +583,74 @@ k_capture(const T* __restrict__ pb, const T* __restrict__ pz, const T* __restric
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// The coefficients where the correction can act, L1 / (L1 + 4 S1 S2) >= rmin
+// from the barrier diagonals, listed in increasing order: each of nb
+// workgroups counts its contiguous range, one workgroup turns the counts into
+// offsets, and each range is written out in order (wave ballots for the
+// order within a round of 256).
+template <typename T>
+__device__ __forceinline__ bool sigma_gate(const T* s1, const T* s2, long long i, double rmin) {
+  const double g1 = s1[i], g2 = s2[i], L1 = g1 + g2;
+  return L1 >= rmin * (L1 + 4.0 * g1 * g2);
+}
+
+__device__ __forceinline__ void gate_range(long long n, long long& lo, long long& hi) {
+  const long long per = (n + gridDim.x - 1) / gridDim.x;
+  lo = blockIdx.x * per;
+  hi = lo + per < n ? lo + per : n;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_gate_count(const T* __restrict__ s1, const T* __restrict__ s2, long long n, double rmin, int* __restrict__ counts) {
+  long long lo, hi;
+  gate_range(n, lo, hi);
+  int k = 0;
+  for (long long i = lo + threadIdx.x; i < hi; i += 256) k += sigma_gate(s1, s2, i, rmin) ? 1 : 0;
+  __shared__ int red[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = k;
+  __syncthreads();
+  if (threadIdx.x == 0) counts[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(64)
+k_gate_scan(int* __restrict__ counts, int nb, long long* __restrict__ total) {
+  if (threadIdx.x != 0) return;
+  long long acc = 0;
+  for (int b = 0; b < nb; ++b) {
+    const int k = counts[b];
+    counts[b] = (int)acc;
+    acc += k;
+  }
+  *total = acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_gate_compact(const T* __restrict__ s1, const T* __restrict__ s2, long long n, double rmin,
+               const int* __restrict__ offsets, int* __restrict__ idx) {
+  long long lo, hi;
+  gate_range(n, lo, hi);
+  __shared__ int wsum[4];
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  long long base = offsets[blockIdx.x];
+  for (long long r = lo; r < hi; r += 256) {
+    const long long i = r + threadIdx.x;
+    const bool act = i < hi && sigma_gate(s1, s2, i, rmin);
+    const unsigned long long m = __ballot(act);
+    if (l == 0) wsum[wv] = __popcll(m);
+    __syncthreads();
+    int before = 0;
+    for (int k = 0; k < wv; ++k) before += wsum[k];
+    const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (act) idx[base + before + __popcll(m & ((1ull << l) - 1ull))] = (int)i;
+    base += total;
+    __syncthreads();
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -544,6 +718,29 @@ void mlp_correction_state(const double* beta, const double* z, const double* nu1
                      meanlog, mscale, bmax, params, c, n, rmin);
 }
 
+template <typename TC>
+void mlp_correction_patch(const double* beta, const double* z, const double* nu1, const double* nu2,
+                          const double* diagH, const double* meanlog, double mscale, const double* bmax,
+                          const float* params, float* c, long long n, double rmin, const TC* s1c, const TC* s2c,
+                          const TC* rb, const TC* rz, TC* pb, TC* pz, const double* s164, const double* s264,
+                          const double* hb64, const double* hz64, double* partial, int stride, int max_blocks,
+                          hipStream_t s) {
+  const int nb = std::max(1, std::min(net_blocks(n), max_blocks));
+  hipLaunchKernelGGL(k_correction_patch<TC>, dim3(nb), dim3(64 * kNetWaves), 0, s, beta, z, nu1, nu2, diagH, meanlog,
+                     mscale, bmax, params, c, n, rmin, s1c, s2c, rb, rz, pb, pz, s164, s264, hb64, hz64, partial,
+                     stride);
+}
+template void mlp_correction_patch<float>(const double*, const double*, const double*, const double*, const double*,
+                                          const double*, double, const double*, const float*, float*, long long,
+                                          double, const float*, const float*, const float*, const float*, float*,
+                                          float*, const double*, const double*, const double*, const double*,
+                                          double*, int, int, hipStream_t);
+template void mlp_correction_patch<double>(const double*, const double*, const double*, const double*, const double*,
+                                           const double*, double, const double*, const float*, float*, long long,
+                                           double, const double*, const double*, const double*, const double*,
+                                           double*, double*, const double*, const double*, const double*,
+                                           const double*, double*, int, int, hipStream_t);
+
 void mlp_forward(const float* params, const float* feat, float* c, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_forward, dim3(net_blocks(n)), dim3(64 * kNetWaves), 0, s, params, feat, c, n);
 }
@@ -572,10 +769,22 @@ void mlp_adam(float* params, const float* grad, float* m, float* v, int t, float
 template <typename T>
 void mlp_capture(const T* pb, const T* pz, const T* qb, const T* qz, const T* s1, const T* s2, const float* feat_all,
                  long long n, int npick, unsigned long long seed, float* out_feat, float* out_rec, double* partial,
-                 hipStream_t s) {
+                 int* gate_idx, double rmin, hipStream_t s) {
+  const int* idx = nullptr;
+  long long* count = nullptr;
+  if (gate_idx) {
+    // the counts and their total sit past the capture's own partials
+    int* counts = reinterpret_cast<int*>(partial + 8192);
+    count = reinterpret_cast<long long*>(partial + 8192 + kGateBlocks / 2);
+    const int gb = (int)std::max(1LL, std::min<long long>(kGateBlocks, (n + 255) / 256));
+    hipLaunchKernelGGL((k_gate_count<T>), dim3(gb), dim3(256), 0, s, s1, s2, n, rmin, counts);
+    hipLaunchKernelGGL(k_gate_scan, dim3(1), dim3(64), 0, s, counts, gb, count);
+    hipLaunchKernelGGL((k_gate_compact<T>), dim3(gb), dim3(256), 0, s, s1, s2, n, rmin, (const int*)counts, gate_idx);
+    idx = gate_idx;
+  }
   const int nb = blocks_for(npick);
   hipLaunchKernelGGL((k_capture<T>), dim3(nb), dim3(256), 0, s, pb, pz, qb, qz, s1, s2, feat_all, n, npick, seed,
-                     out_feat, out_rec, partial);
+                     idx, (const long long*)count, out_feat, out_rec, partial);
   double* total = partial + 4096;
   hipLaunchKernelGGL(k_fin_mean, dim3(1), dim3(256), 0, s, partial, nb, 1.0, total);
   hipLaunchKernelGGL(k_set_weights, dim3(blocks_for(npick)), dim3(256), 0, s, out_rec, npick, (const double*)total);
@@ -587,9 +796,9 @@ void mlp_scale_weights(float* rec, int npick, float factor, hipStream_t s) {
 
 template void mlp_capture<double>(const double*, const double*, const double*, const double*, const double*,
                                   const double*, const float*, long long, int, unsigned long long, float*, float*,
-                                  double*, hipStream_t);
+                                  double*, int*, double, hipStream_t);
 template void mlp_capture<float>(const float*, const float*, const float*, const float*, const float*, const float*,
-                                 const float*, long long, int, unsigned long long, float*, float*, double*,
-                                 hipStream_t);
+                                 const float*, long long, int, unsigned long long, float*, float*, double*, int*,
+                                 double, hipStream_t);
 
 }  // namespace csipm

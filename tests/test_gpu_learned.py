@@ -178,6 +178,52 @@ def test_learned_solve_same_solution_and_fallback():
     assert np.all(c > 0)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_corrected_system_patched_in_place_matches_separate_build(precision):
+    """With the correction on every system, the systems the iterate update
+    builds with the paper's P are turned into corrected ones in place
+    (correction_patch: c, p = P_c^{-1} r where c acts, the start sums) instead
+    of the correction pass plus a newton_init rebuild; against build_next = 0
+    the solve takes the same interior-point count and reaches the same
+    solution up to rounding (FP64: the same Krylov counts)."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid64(1)
+    lam = ipm.lambda_rule(w.signal, w.observed)
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.set_lambda(lam)
+    pr.set_pc_params(torch.tensor(_params(3), device="cuda"))
+    out = {}
+    for bn in (1, 0):
+        pr.timing(True)
+        info = pr.solve(tol=1e-11, precision=precision, pc=csipm.PC_LEARNED, pc_min_cg=0, pc_max_relevant=1.0,
+                        build_next=bn)
+        rep = {r["name"]: r["calls"] for r in pr.timing_report(0.0)}
+        pr.timing(False)
+        patched = sum(c for nm, c in rep.items() if nm.startswith("correction_patch"))
+        separate = rep.get("correction", 0)
+        ninit = sum(c for nm, c in rep.items() if nm.startswith("newton_init"))
+        log = pr.log()
+        out[bn] = (info, [r["cg_iters"] for r in log], pr.get(csipm.BETA).cpu().numpy(), patched, separate, ninit)
+        say("  build_next", bn, info["status_name"], info["ipm_iters"], out[bn][1], "fallbacks", info["fallbacks"],
+            "patched", patched, "separate", separate, "newton_init", ninit)
+        assert all(r["learned"] == 1 for r in log)
+    (i1, cg1, b1, p1, s1, n1), (i0, cg0, b0, p0, s0, n0) = out[1], out[0]
+    assert i1["status"] in (0, 3) and i0["status"] in (0, 3)
+    assert i1["ipm_iters"] == i0["ipm_iters"]
+    if precision == 0:
+        assert cg1 == cg0
+    else:
+        assert cg1[:8] == cg0[:8]
+    assert p0 == 0 and s0 == i0["ipm_iters"]
+    assert p1 > 0 and p1 + s1 == i1["ipm_iters"] and n1 < n0
+    err = rel2(b1, b0)
+    say("  rel diff", err)
+    assert err <= (1e-12 if precision == 0 else 1e-7)
+    ref = ipm.ipm_solve(w.signal, w.observed, lam, ipm.IPMOptions(tol=1e-11))
+    assert rel2(b1, ref.state.beta) <= 1e-7
+
+
 def test_capture_records_consistent():
     torch = need_gpu()
     from paper_2502_04217_amd import csipm
@@ -198,6 +244,44 @@ def test_capture_records_consistent():
     for i in range(k):
         wsum = r[i * per:(i + 1) * per, 5]
         assert np.allclose(wsum, wsum[0]) and wsum[0] > 0
+    pr.capture_off()
+
+
+def test_policy_capture_records():
+    """Capture mode 2 (csipm_capture): only at the iterations where the
+    learned form would apply the correction (previous system >= pc_min_cg
+    PCG iterations, 1 <= relevant coefficients <= pc_max_relevant of them),
+    and only at coefficients where the correction can act."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid64(1)
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.lambda_rule(0.05)
+    n = w.signal.size
+    per, mx = 512, 40
+    feat = torch.zeros((per * mx, 4), dtype=torch.float32, device="cuda")
+    rec = torch.zeros((per * mx, 6), dtype=torch.float32, device="cuda")
+    pr.capture(feat, rec, per, mx, seed=7, policy=True)
+    info = pr.solve(tol=1e-8, precision=csipm.FP64, pc=csipm.PC_PLAIN, pc_min_cg=2, pc_max_relevant=0.5)
+    k, cg = pr.captured()
+    log = pr.log()
+    prev = [0] + [r["cg_iters"] for r in log[:-1]]
+    want = [i for i, (p, r) in enumerate(zip(prev, log))
+            if p >= 2 and r["relevant"] * n >= 0.5 and r["relevant"] <= 0.5]
+    say("policy capture", info["ipm_iters"], "iterations, captured", k, "expected at", want,
+        "relevant", [round(r["relevant"], 5) for r in log])
+    assert k == len(want) and k >= 1
+    assert cg == [log[i]["cg_iters"] for i in want]
+    r = rec[:k * per].cpu().numpy().astype(np.float64)
+    L1, q4 = r[:, 2], r[:, 4]
+    assert np.all(L1 >= 1e-3 * (L1 + q4) * (1 - 1e-5))
+    assert np.all(r[:, 5] > 0)
+    f = feat[:k * per].cpu().numpy()
+    assert np.allclose(f[:, 1], r[:, 3] / r[:, 2], rtol=1e-4, atol=1e-6)
+    # the same solve without the policy captures every iteration
+    pr.capture(feat, rec, per, mx, seed=7)
+    info2 = pr.solve(tol=1e-8, precision=csipm.FP64, pc=csipm.PC_PLAIN)
+    assert pr.captured()[0] == info2["ipm_iters"]
     pr.capture_off()
 
 
