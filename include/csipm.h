@@ -15,10 +15,13 @@
  *    extents with odd factors 12, 20, 24, 28, 40, 48, 56, 70, 96, 192, 384,
  *    560 (the FFT passes have radix-3, -5 and -7 stages); N1 and N2 may
  *    also be 1 or 2, so a 2D problem is the grid 1 x N2 x N3 and a 1D one
- *    1 x 1 x N3, or odd: 3, 5, 7, 9, 15, 21, 35, 45 (the odd-N case of the
- *    parametrisation, section "Problem formulation": no Nyquist index on
- *    that axis); N3 is even.  n = N1*N2*N3.  Other extents return
- *    CSIPM_EUNSUPPORTED.
+ *    1 x 1 x N3.  Any axis may be odd: 3, 5, 7, 9, 15, 21, 35, 45 (the
+ *    odd-N case of the parametrisation, section "Problem formulation": no
+ *    Nyquist index on that axis; an odd N3 runs the transforms on the whole
+ *    spectrum, with twice the bytes of the half-spectrum passes, and when
+ *    N1*N2*N3 is odd the library adds internally one coordinate with no data,
+ *    a zero column of A, which the solution sets to 0).  n = N1*N2*N3.
+ *    Other extents return CSIPM_EUNSUPPORTED.
  *  - Real-space arrays are row-major [N1][N2][N3] (index j3 fastest).
  *  - beta-space arrays ("external beta layout") are row-major [N1][N2][N3]
  *    indexed by the frequency k: beta[k] = v_k for self-conjugate k
@@ -397,7 +400,8 @@ csipm_status csipm_pc_correction(csipm_ctx* ctx, double* d_c);
  * the K epilogue; and in ms_out[5] the average time of one K-apply over
  * `reps` more applies queued back to back between a single event pair
  * (no events between its kernels).  ms_out holds CSIPM_KAPPLY_PASSES + 1
- * values.  Synchronises. */
+ * values.  Synchronises.  CSIPM_EUNSUPPORTED for an odd N3 (whose K-apply
+ * is the full-spectrum transforms). */
 #define CSIPM_KAPPLY_PASSES 5
 csipm_status csipm_profile_kapply(csipm_ctx* ctx, int precision, int reps, double* ms_out);
 

@@ -65,6 +65,11 @@ struct csipm_ctx {
   float *fyb, *fyz;    // CAr: y (FP32)
   // learned correction
   float *pc_c, *feat, *mlp_params;
+  // per 64-coefficient chunk: the correction's gate passes somewhere in the
+  // last updated iterate (written by the update), and c may differ from 1
+  // there (pc_set; valid while pc_tracked: otherwise c may differ anywhere)
+  uint32_t *pc_act, *pc_set;
+  bool pc_tracked = false;
   uint32_t* mask;
   cx<double>* tw64;
   cx<float>* tw32;
@@ -167,26 +172,34 @@ csipm_status sync_scalars(csipm_ctx* c, const char* where) {
 }
 
 // partial sums of one K-apply: one per workgroup of the axis-1 forward pass
+// (of the unmap pass for an odd N3)
 size_t k_partials(int n1, int n2, int n3) {
-  const Grid g{n1, n2, n3, n3 / 2, (long long)n1 * n2 * n3};
+  const Grid g = make_grid(n1, n2, n3);
+  if (g.odd3()) return (size_t)cp_blocks(g) + 64;
   return (size_t)std::max(axis12_blocks(g, 1, 16, -1), axis12_blocks(g, 1, 8, -1)) + 64;
 }
 
 size_t layout(Carver& cv, csipm_ctx* c, int n1, int n2, int n3) {
-  const size_t n = (size_t)n1 * n2 * n3;
+  const Grid g = make_grid(n1, n2, n3);
+  const size_t n = (size_t)g.n;
+  // FFT scratch: the half spectrum (n reals), or the whole spectrum for an odd N3
+  const size_t nw = g.odd3() ? std::max(n, (size_t)(2 * g.nr)) : n;
   const size_t ntw = (size_t)n1 + n2 + n3 / 2 + n3;
   double** d64[] = {&c->beta, &c->z, &c->nu1, &c->nu2, &c->xi, &c->hb, &c->sig1, &c->sig2, &c->rhb, &c->rhz,
                     &c->dxb, &c->dxz, &c->diagH, &c->rb, &c->rz, &c->zb, &c->zz, &c->pb, &c->pz, &c->qb,
-                    &c->qz, &c->work, &c->yb64, &c->yz64, &c->dab, &c->daz};
+                    &c->qz, &c->yb64, &c->yz64, &c->dab, &c->daz};
   for (double** p : d64) *p = cv.take<double>(n);
+  c->work = cv.take<double>(nw);
   c->snap = cv.take<double>(4 * n);
-  float** f32[] = {&c->sig1f, &c->sig2f, &c->frb, &c->frz, &c->fzb,   &c->fzz,  &c->fpb, &c->fpz,
-                   &c->fqb,   &c->fqz,   &c->fxb, &c->fxz, &c->fwork, &c->pc_c, &c->fwb, &c->fwz,
-                   &c->fyb,   &c->fyz};
+  float** f32[] = {&c->sig1f, &c->sig2f, &c->frb, &c->frz, &c->fzb, &c->fzz, &c->fpb, &c->fpz, &c->fqb,
+                   &c->fqz,   &c->fxb,   &c->fxz, &c->pc_c, &c->fwb, &c->fwz, &c->fyb, &c->fyz};
   for (float** p : f32) *p = cv.take<float>(n);
+  c->fwork = cv.take<float>(nw);
   c->feat = cv.take<float>(4 * n);
   c->mlp_params = cv.take<float>(CSIPM_MLP_PARAMS);
   c->mask = cv.take<uint32_t>((n + 31) / 32);
+  c->pc_act = cv.take<uint32_t>((n + kPcChunk - 1) / kPcChunk);
+  c->pc_set = cv.take<uint32_t>((n + kPcChunk - 1) / kPcChunk);
   c->tw64 = cv.take<cx<double>>(ntw);
   c->tw32 = cv.take<cx<float>>(ntw);
   c->partK = cv.take<double>(2 * k_partials(n1, n2, n3));   // up to two quantities
@@ -209,6 +222,14 @@ const Twiddles<float>& tw<float>(csipm_ctx* c) { return c->T32; }
 template <typename T>
 void op_H(csipm_ctx* c, const T* in, T* out, T* work) {
   const Grid& g = c->g;
+  if (g.odd3()) {
+    KT(c, PN(T, "cp_map"), cp_map<T>(g, in, work, nullptr, c->s));
+    KT(c, PN(T, "cp_inv"), cp_passes<T>(g, +1, work, tw<T>(c), nullptr, c->s));
+    KT(c, PN(T, "cp_mask"), cp_mask<T>(g, work, c->mask, nullptr, c->s));
+    KT(c, PN(T, "cp_fwd"), cp_passes<T>(g, -1, work, tw<T>(c), nullptr, c->s));
+    KT(c, PN(T, "cp_unmap"), cp_unmap<T>(g, work, out, EPI_NONE, nullptr, nullptr, c->s));
+    return;
+  }
   KT(c, PN(T, "axis1_inv"), launch_axis12<T>(g, 1, +1, in, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s));
   KT(c, PN(T, "axis2_inv"), launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s));
   KT(c, PN(T, "axis3"), launch_axis3<T>(g, A3_FULL, work, work, c->mask, tw<T>(c), nullptr, c->s));
@@ -220,6 +241,12 @@ void op_H(csipm_ctx* c, const T* in, T* out, T* work) {
 template <typename T>
 void op_A(csipm_ctx* c, const T* in, T* x, T* work) {
   const Grid& g = c->g;
+  if (g.odd3()) {
+    cp_map<T>(g, in, work, nullptr, c->s);
+    cp_passes<T>(g, +1, work, tw<T>(c), nullptr, c->s);
+    cp_real<T>(g, work, x, c->s);
+    return;
+  }
   launch_axis12<T>(g, 1, +1, in, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s);
   launch_axis12<T>(g, 2, +1, work, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s);
   launch_axis3<T>(g, A3_C2R, work, x, nullptr, tw<T>(c), nullptr, c->s);
@@ -229,6 +256,12 @@ void op_A(csipm_ctx* c, const T* in, T* x, T* work) {
 template <typename T>
 void op_At(csipm_ctx* c, const T* x, T* out, T* work) {
   const Grid& g = c->g;
+  if (g.odd3()) {
+    cp_cplx<T>(g, x, work, c->s);
+    cp_passes<T>(g, -1, work, tw<T>(c), nullptr, c->s);
+    (void)cp_unmap<T>(g, work, out, EPI_NONE, nullptr, nullptr, c->s);
+    return;
+  }
   launch_axis3<T>(g, A3_R2C, x, work, nullptr, tw<T>(c), nullptr, c->s);
   launch_axis12<T>(g, 2, -1, work, work, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s);
   launch_axis12<T>(g, 1, -1, work, out, tw<T>(c), EPI_NONE, nullptr, nullptr, c->s);
@@ -241,9 +274,21 @@ template <typename T>
 int op_K(csipm_ctx* c, const T* pb, const T* pz, const T* s1, const T* s2, T* qb, T* qz, T* work,
          const int* skip, const PUpd<T>* u = nullptr) {
   const Grid& g = c->g;
-  const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>), -1);
   const int ps = (int)k_partials(g.n1, g.n2, g.n3);
   EpiArgs<T> ka{KArgs<T>{pb, pz, s1, s2, qb, qz, u ? *u : PUpd<T>{}}, RArgs{}, c->partK, ps};
+  if (g.odd3()) {
+    if (u)
+      KT(c, PN(T, "cp_pupd"),
+         cp_pupdate<T>(g, u->pb, u->pz, u->zb, u->zz, u->beta, skip, c->s));
+    KT(c, PN(T, "cp_map"), cp_map<T>(g, pb, work, skip, c->s));
+    KT(c, PN(T, "cp_inv"), cp_passes<T>(g, +1, work, tw<T>(c), skip, c->s));
+    KT(c, PN(T, "cp_mask"), cp_mask<T>(g, work, c->mask, skip, c->s));
+    KT(c, PN(T, "cp_fwd"), cp_passes<T>(g, -1, work, tw<T>(c), skip, c->s));
+    int nb = 0;
+    KT(c, PN(T, "cp_unmap_K"), nb = cp_unmap<T>(g, work, nullptr, EPI_K, &ka, skip, c->s));
+    return nb;
+  }
+  const int nb5 = axis12_blocks(g, 1, (int)sizeof(cx<T>), -1);
   // (the passes that apply the direction update are timed under their own names)
   KT(c, u ? PN(T, "axis1_inv_P") : PN(T, "axis1_inv"),
      launch_axis12<T>(g, 1, +1, pb, work, tw<T>(c), EPI_NONE, u ? &ka : nullptr, skip, c->s));
@@ -260,12 +305,23 @@ int op_K(csipm_ctx* c, const T* pb, const T* pz, const T* s1, const T* s2, T* qb
 // scal[S_REFINF].
 void op_Kr(csipm_ctx* c, const float* pcc) {
   const Grid& g = c->g;
-  const int nb5 = axis12_blocks(g, 1, 16, -1);
   const int ps = (int)k_partials(g.n1, g.n2, g.n3);
   // H d_beta goes to rb: the FP64 Krylov vectors are idle in the FP32 form
   RArgs ra{c->dxb, c->dxz, c->sig1, c->sig2, c->rhb, c->rhz, pcc, c->rb};
   EpiArgs<double> ea{KArgs<double>{}, ra, c->partK, ps};
   double* work = c->work;
+  if (g.odd3()) {
+    int nb = 0;
+    KT(c, "cp_map.f64", cp_map<double>(g, c->dxb, work, nullptr, c->s));
+    KT(c, "cp_inv.f64", cp_passes<double>(g, +1, work, c->T64, nullptr, c->s));
+    KT(c, "cp_mask.f64", cp_mask<double>(g, work, c->mask, nullptr, c->s));
+    KT(c, "cp_fwd.f64", cp_passes<double>(g, -1, work, c->T64, nullptr, c->s));
+    KT(c, "cp_unmap_R.f64", nb = cp_unmap<double>(g, work, nullptr, EPI_R, &ea, nullptr, c->s));
+    KT(c, "fin_sum", fin_sum(c->partK, nb, c->scal + S_REF, c->s));
+    KT(c, "fin_max", fin_max(c->partK + ps, nb, c->scal + S_REFINF, c->s));
+    return;
+  }
+  const int nb5 = axis12_blocks(g, 1, 16, -1);
   KT(c, "axis1_inv.f64", launch_axis12<double>(g, 1, +1, c->dxb, work, c->T64, EPI_NONE, nullptr, nullptr, c->s));
   KT(c, "axis2_inv.f64", launch_axis12<double>(g, 2, +1, work, work, c->T64, EPI_NONE, nullptr, nullptr, c->s));
   KT(c, "axis3.f64", launch_axis3<double>(g, A3_FULL, work, work, c->mask, c->T64, nullptr, c->s));
@@ -300,7 +356,8 @@ csipm_status learned_correction(csipm_ctx* c, bool have_logsum) {
   }
   KT(c, "correction",
      mlp_correction_state(c->beta, c->z, c->nu1, c->nu2, c->diagH, ml, mscale, c->scal + S_RESID + 4, c->mlp_params,
-                          c->pc_c, c->g.n, kPcRelevance, c->s));
+                          c->pc_c, c->g.n, c->pc_set, c->s));
+  c->pc_tracked = true;
   return hip_check(c, "learned_correction");
 }
 
@@ -593,7 +650,7 @@ csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double*
   const auto t_create = std::chrono::steady_clock::now();
   csipm_ctx* c = new (std::nothrow) csipm_ctx();
   if (!c) return CSIPM_ENOMEM;
-  c->g = Grid{n1, n2, n3, n3 / 2, (long long)n1 * n2 * n3};
+  c->g = make_grid(n1, n2, n3);
   c->s = reinterpret_cast<hipStream_t>(hip_stream);
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
@@ -637,7 +694,8 @@ csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double*
   c->T64.t3 = c->tw64 + o; c->T32.t3 = c->tw32 + o;
 
   // input checks: finite observed samples, at least one observed
-  check_signal(d_signal, d_observed, n, c->partV, c->scal + S_SIG, c->s);
+  const long long nr = g.nr;   // real-space samples (n beta coordinates)
+  check_signal(d_signal, d_observed, nr, c->partV, c->scal + S_SIG, c->s);
   csipm_status st = sync_scalars(c, "create");
   if (st != CSIPM_OK) { noctx_set_error("create: " + c->err); csipm_destroy(c); return st; }
   if (c->hscal[S_SIG] > 0) { csipm_destroy(c); return CSIPM_ENONFINITE; }
@@ -646,14 +704,15 @@ csipm_status csipm_create(csipm_ctx** out, int n1, int n2, int n3, const double*
 
   launch_pack_mask(g, d_observed, c->mask, c->s);
   // xi = A^T b_hat (b_hat: zero-filled signal, staged in rb as a real grid)
-  zero_fill(d_signal, d_observed, c->rb, n, c->s);
+  zero_fill(d_signal, d_observed, c->rb, nr, c->s);
   op_At<double>(c, c->rb, c->xi, c->work);
   absmax(c->xi, n, c->partV, c->scal + S_MISC, c->s);
-  // diag(M_perp^T M_perp) from A^T(mask), through the external layout
-  obs_to_double(d_observed, c->rb, n, c->s);
+  // diag(M_perp^T M_perp) from A^T(mask), through the external layout (the
+  // coordinate without data, if any, gets 0)
+  obs_to_double(d_observed, c->rb, nr, c->s);
   op_At<double>(c, c->rb, c->zb, c->work);
   launch_to_external<double, double>(g, c->zb, c->zz, c->s);
-  diag_h(c->zz, c->rz, n1, n2, n3, (double)c->nobs / (double)n, c->s);
+  diag_h(c->zz, c->rz, n1, n2, n3, (double)c->nobs / (double)nr, c->s);
   launch_to_internal<double, double>(g, c->rz, c->diagH, c->s);
   fill<float>(c->pc_c, 1.0f, n, c->s);
   st = sync_scalars(c, "create");
@@ -863,7 +922,9 @@ csipm_status residuals(csipm_ctx* c, Resid& r, bool logsum) {
 // or without the FP64 h and Sigma of a refined solve): c from the state (as learned_correction forms
 // it), and the PCG start and its sums rewritten to those of P_c, so that no
 // newton_init pass rebuilds the system.  The update's residual reduction has
-// left the centring sum and max |beta| of this iterate.
+// left the centring sum and max |beta| of this iterate, and its activity
+// flags the chunks where the correction's gate passes: only those chunks,
+// and those where c was last set, are visited.
 csipm_status correction_patch(csipm_ctx* c, bool f64, bool ref64) {
   const long long n = c->g.n;
   const int nbv = vec_blocks(n);
@@ -874,15 +935,17 @@ csipm_status correction_patch(csipm_ctx* c, bool f64, bool ref64) {
   if (f64) {
     KT(c, "correction_patch.f64",
        mlp_correction_patch<double>(c->beta, c->z, c->nu1, c->nu2, c->diagH, ml, mscale, bmax, c->mlp_params, c->pc_c,
-                                    n, kPcRelevance, c->sig1, c->sig2, c->rb, c->rz, c->pb, c->pz, nullptr, nullptr,
-                                    nullptr, nullptr, part, VEC_MAX_BLOCKS, nbv, c->s));
+                                    n, c->pc_act, c->pc_set, c->pc_tracked, c->sig1, c->sig2, c->rb, c->rz, c->pb,
+                                    c->pz, nullptr, nullptr, nullptr, nullptr, part, VEC_MAX_BLOCKS, nbv, c->s));
   } else {
     KT(c, "correction_patch.f32",
        mlp_correction_patch<float>(c->beta, c->z, c->nu1, c->nu2, c->diagH, ml, mscale, bmax, c->mlp_params, c->pc_c,
-                                   n, kPcRelevance, c->sig1f, c->sig2f, c->frb, c->frz, c->fpb, c->fpz,
-                                   ref64 ? c->sig1 : nullptr, ref64 ? c->sig2 : nullptr, ref64 ? c->rhb : nullptr,
-                                   ref64 ? c->rhz : nullptr, part, VEC_MAX_BLOCKS, nbv, c->s));
+                                   n, c->pc_act, c->pc_set, c->pc_tracked, c->sig1f, c->sig2f, c->frb, c->frz, c->fpb,
+                                   c->fpz, ref64 ? c->sig1 : nullptr, ref64 ? c->sig2 : nullptr,
+                                   ref64 ? c->rhb : nullptr, ref64 ? c->rhz : nullptr, part, VEC_MAX_BLOCKS, nbv,
+                                   c->s));
   }
+  c->pc_tracked = true;
   return hip_check(c, "correction_patch");
 }
 
@@ -959,6 +1022,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   if (o.pc == CSIPM_PC_SCALED) {
     const double rho = o.pc_rho > 0.0 ? o.pc_rho : (double)c->nobs / (double)n;
     KT(c, "fill", fill<float>(c->pc_c, (float)rho, n, c->s));
+    c->pc_tracked = false;
     pc_fixed = c->pc_c;
   }
   // the start beta = 0 has H beta = 0 exactly: G = -xi
@@ -1210,7 +1274,8 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     KT(c, kAdvName[d32b ? 1 : 0][fuse_kind],
        ipm_advance(c->beta, c->z, c->nu1, c->nu2, c->hb, c->dxb, c->dxz, d32b, d32z,
                    src == HD_DIRECT ? c->rb : nullptr, c->rb, src == HD_RRES32 ? c->frb : nullptr, lam, smu, c->scal, n,
-                   c->partV, need_rel, c->s, dab, daz, fuse_kind != NEXT_NONE ? &nx : nullptr));
+                   c->partV, need_rel, c->s, dab, daz, fuse_kind != NEXT_NONE ? &nx : nullptr,
+                   learned ? c->pc_act : nullptr));
     st = sync_scalars(c, "advance");
     if (st != CSIPM_OK) return st;
     r = read_resid(c);
@@ -1398,6 +1463,12 @@ csipm_status csipm_set_barrier(csipm_ctx* c, const double* d_sigma1, const doubl
   launch_to_internal<double, double>(c->g, d_sigma2, c->sig2, c->s);
   launch_to_internal<double, float>(c->g, d_sigma1, c->sig1f, c->s);
   launch_to_internal<double, float>(c->g, d_sigma2, c->sig2f, c->s);
+  if (c->g.n > c->g.nr) {   // the coordinate without data keeps Sigma = 1 (P stays invertible there)
+    fill<double>(c->sig1 + c->g.nr, 1.0, 1, c->s);
+    fill<double>(c->sig2 + c->g.nr, 1.0, 1, c->s);
+    fill<float>(c->sig1f + c->g.nr, 1.0f, 1, c->s);
+    fill<float>(c->sig2f + c->g.nr, 1.0f, 1, c->s);
+  }
   return hip_check(c, "set_barrier");
 }
 
@@ -1509,6 +1580,7 @@ csipm_status csipm_profile_kapply(csipm_ctx* c, int precision, int reps, double*
   if (!c || !ms_out || reps < 1) return CSIPM_EINVAL;
   if (precision != CSIPM_FP64 && precision != CSIPM_FP32) return fail(c, CSIPM_EINVAL, "precision");
   const Grid& g = c->g;
+  if (g.odd3()) return fail(c, CSIPM_EUNSUPPORTED, "profile_kapply: the five-pass K-apply needs an even N3");
   hipEvent_t ev[CSIPM_KAPPLY_PASSES + 1];
   for (auto& e : ev)
     if (hipEventCreate(&e) != hipSuccess) return fail(c, CSIPM_EHIP, "hipEventCreate");

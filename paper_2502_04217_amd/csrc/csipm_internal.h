@@ -114,10 +114,34 @@ struct Twiddles {
   const cx<T>* t3;   // length N3
 };
 
+// An even N3 gives the half-spectrum layout (n = n1*n2*n3 reals = n1*n2*m
+// complex).  An odd N3 has no Nyquist plane to pack beside the DC plane, so
+// its beta-space vectors keep the external order, the transforms run on the
+// full Hermitian spectrum (n1*n2*n3 complex), and when n1*n2*n3 is odd one
+// more coordinate with no data (a zero column of A) makes the vector length
+// n even for the pairwise kernels; the LASSO sets it to 0.
 struct Grid {
-  int n1, n2, n3, m;   // m = n3/2
-  long long n;         // n1*n2*n3 reals = n1*n2*m complex
+  int n1, n2, n3, m;   // m = n3/2 (even N3)
+  long long n;         // beta-space length: nr, or nr + 1 when nr is odd
+  long long nr;        // real-space samples n1*n2*n3
+  bool odd3() const { return (n3 & 1) != 0; }
 };
+inline Grid make_grid(int n1, int n2, int n3) {
+  Grid g{n1, n2, n3, n3 / 2, 0, (long long)n1 * n2 * n3};
+  g.n = g.nr + (g.nr & 1);
+  return g;
+}
+
+// 3D class of a frequency under the parametrisation's choice of
+// representatives: 0 self-conjugate, 1 canonical, 2 mirror of one.
+__device__ __forceinline__ int cls3(int k1, int k2, int k3, int n1, int n2, int n3) {
+  const bool e1 = k1 == 0 || 2 * k1 == n1, e2 = k2 == 0 || 2 * k2 == n2, e3 = k3 == 0 || 2 * k3 == n3;
+  if (e1 && e2 && e3) return 0;
+  if (k3 >= 1 && 2 * k3 < n3) return 1;
+  if (e3 && k2 >= 1 && 2 * k2 < n2) return 1;
+  if (e3 && e2 && k1 >= 1 && 2 * k1 < n1) return 1;
+  return 2;
+}
 
 // Selects what the axis-3 pass does.
 enum Axis3Mode { A3_C2R = 1, A3_R2C = 2, A3_FULL = 3 };
@@ -132,6 +156,20 @@ enum EpiMode {
 // the learned correction is evaluated where L1 / (L1 + 4 S1 S2) >= this
 // (elsewhere the 2x2 block of P_c does not depend on c to this precision)
 constexpr double kPcRelevance = 1e-3;
+// coefficients per activity flag of the correction (one wave's chunk)
+constexpr int kPcChunk = 64;
+
+// The correction's gate at a coefficient with multipliers a1, a2 and slacks
+// s1, s2 > 0: L1 / (L1 + 4 S1 S2) >= kPcRelevance with S_j = a_j / s_j,
+// multiplied through by s1 s2.  Every operation is rounded on its own (no
+// contraction into fused multiply-adds), so that the kernels that evaluate
+// it (the residual count, the update's activity flags, the correction)
+// decide alike on the same values.
+__device__ __forceinline__ bool pc_gate(double a1, double a2, double s1, double s2) {
+  const double num = __dadd_rn(__dmul_rn(a1, s2), __dmul_rn(a2, s1));
+  const double den = __dadd_rn(num, __dmul_rn(4.0, __dmul_rn(a1, a2)));
+  return num >= __dmul_rn(kPcRelevance, den);
+}
 
 // CG direction update p <- z + beta p fused into the K-apply of the new p
 // (zb null: none).  The passes that first read p apply it and write p back:
@@ -225,10 +263,44 @@ void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t*
 // forward pass also its partial count
 int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir);
 // whether the FFT passes have kernels for extent N on `axis` (1, 2: pencils
-// of length N; 3: half length N/2): powers of two in [4, 1024], the extents
-// with odd factors that fft_mixed_f64/f32.hip instantiate, and on axes 1
-// and 2 also 1 and 2 (2D and 1D grids) and the odd extents 3-45
+// of length N; 3: half length N/2 for an even N): powers of two in
+// [4, 1024], the extents with odd factors that fft_mixed_f64/f32.hip
+// instantiate, the odd extents 3-45 on every axis (an odd N3 takes the
+// full-spectrum transforms), and on axes 1 and 2 also 1 and 2 (2D and 1D
+// grids)
 bool fft_extent_supported(int N, int axis);
+
+// Full-spectrum transforms of a grid with an odd N3 (Grid::odd3): beta in
+// external order, work holds n1*n2*n3 complex values.  Each launch returns at
+// once when *skip is set.
+constexpr int kCpMaxBlocks = 1024;
+// workgroups (and partials) of cp_unmap
+int cp_blocks(const Grid& g);
+// work = B^H beta (the Hermitian spectrum of the real parametrisation)
+template <typename T>
+void cp_map(const Grid& g, const T* beta, T* work, const int* skip, hipStream_t s);
+// p <- z + beta p (both halves; the CG direction update before a K-apply)
+template <typename T>
+void cp_pupdate(const Grid& g, T* pb, T* pz, const T* zb, const T* zz, const double* beta, const int* skip,
+                hipStream_t s);
+// unnormalised complex FFT of work along axes 1, 2, 3 (dir +1: inverse,
+// exp(+); dir -1: forward, along 3, 2, 1)
+template <typename T>
+void cp_passes(const Grid& g, int dir, T* work, const Twiddles<T>& tw, const int* skip, hipStream_t s);
+// work = mask * Re(work) / nr (the normalisations of an inverse and a
+// forward unitary transform), imaginary part 0
+template <typename T>
+void cp_mask(const Grid& g, T* work, const uint32_t* bits, const int* skip, hipStream_t s);
+// x = Re(work) / sqrt(nr); work = x / sqrt(nr)
+template <typename T>
+void cp_real(const Grid& g, const T* work, T* x, hipStream_t s);
+template <typename T>
+void cp_cplx(const Grid& g, const T* x, T* work, hipStream_t s);
+// the real parametrisation of the spectrum in work: written to out
+// (EPI_NONE) or handed to the K / refinement epilogue of ea (EPI_K, EPI_R;
+// ea->k.u is ignored, cp_pupdate applies it); returns the partial count
+template <typename T>
+int cp_unmap(const Grid& g, const T* work, T* out, int epi, const EpiArgs<T>* ea, const int* skip, hipStream_t s);
 
 // message of the last failed context-free call on this thread (noalloc.hip)
 const char* noctx_last_error();

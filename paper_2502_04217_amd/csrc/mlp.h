@@ -33,24 +33,28 @@ void mlp_features_state(const double* beta, const double* z, const double* nu1, 
 void mlp_mean_log_l1_state(const double* beta, const double* z, const double* nu1, const double* nu2, long long n,
                            double* partial, double* meanlog, hipStream_t s);
 // c of the interior-point state, network evaluated (on the matrix cores) only
-// where L1 / (L1 + 4 S1 S2) >= rmin (c = 1 elsewhere); the centring of the
-// first feature is *meanlog * mscale, and meanlog, bmax are device scalars
+// where pc_gate passes (c = 1 elsewhere); the centring of the first feature
+// is *meanlog * mscale, and meanlog, bmax are device scalars; set[k] = 1 for
+// the 64-coefficient chunks k where c may differ from 1, else 0
 void mlp_correction_state(const double* beta, const double* z, const double* nu1, const double* nu2,
                           const double* diagH, const double* meanlog, double mscale, const double* bmax,
-                          const float* params, float* c, long long n, double rmin, hipStream_t s);
+                          const float* params, float* c, long long n, uint32_t* set, hipStream_t s);
 // c of the interior-point state as mlp_correction_state forms it, for an
 // iterate whose Newton system (Sigma s1c/s2c, r = rb/rz, p = pb/pz in TC;
 // for TC = float also the FP64 Sigma s164/s264 and h hb64/hz64, or null)
-// was built with c = 1: p is rewritten to P_c^{-1} r where c acts, and the
-// change of r.P^{-1}r (and h.P^{-1}h) is added to partial[b] (and
-// partial[stride + b]) for workgroup b < max_blocks
+// was built with c = 1 and whose chunks the update flagged in act: p is
+// rewritten to P_c^{-1} r where c acts, and the change of r.P^{-1}r (and
+// h.P^{-1}h) is added to partial[b] (and partial[stride + b]) for workgroup
+// b < max_blocks.  Only flagged chunks and those set marks are visited
+// (with tracked false, every chunk: c may then differ from 1 anywhere);
+// set is updated.
 template <typename TC>
 void mlp_correction_patch(const double* beta, const double* z, const double* nu1, const double* nu2,
                           const double* diagH, const double* meanlog, double mscale, const double* bmax,
-                          const float* params, float* c, long long n, double rmin, const TC* s1c, const TC* s2c,
-                          const TC* rb, const TC* rz, TC* pb, TC* pz, const double* s164, const double* s264,
-                          const double* hb64, const double* hz64, double* partial, int stride, int max_blocks,
-                          hipStream_t s);
+                          const float* params, float* c, long long n, const uint32_t* act, uint32_t* set,
+                          bool tracked, const TC* s1c, const TC* s2c, const TC* rb, const TC* rz, TC* pb, TC* pz,
+                          const double* s164, const double* s264, const double* hb64, const double* hz64,
+                          double* partial, int stride, int max_blocks, hipStream_t s);
 // c = softplus(MLP(feat)) + 1e-6 for n records (matrix-core inference)
 void mlp_forward(const float* params, const float* feat, float* c, long long n, hipStream_t s);
 // gradient of sum_i dc_i c_i, accumulated into grad (float, 1249)

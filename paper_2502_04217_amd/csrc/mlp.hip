@@ -404,20 +404,18 @@ k_features_state(const double* __restrict__ beta, const double* __restrict__ z, 
 
 // Gate and features of coefficient i of the interior-point state.  The
 // slacks are formed in FP64 (z and |beta| nearly cancel late in the solve);
-// the gate L1 / (L1 + 4 S1 S2) >= rmin is multiplied through by s1 s2 > 0:
-// (nu1 s2 + nu2 s1) >= rmin (nu1 s2 + nu2 s1 + 4 nu1 nu2), no division.
-// The features are FP32 from the FP64 slacks.  diagH is read only where
-// the gate passes: the network maps each coefficient's features to its own
-// output (a column of every layer's product), so an inactive lane's
-// features, whose output is discarded, need not be exact.
+// the gate is pc_gate (no division).  The features are FP32 from the FP64
+// slacks.  diagH is read only where the gate passes: the network maps each
+// coefficient's features to its own output (a column of every layer's
+// product), so an inactive lane's features, whose output is discarded, need
+// not be exact.
 __device__ __forceinline__ bool state_features(const double* __restrict__ beta, const double* __restrict__ z,
                                                const double* __restrict__ nu1, const double* __restrict__ nu2,
-                                               const double* __restrict__ diagH, double ml, double ibm, double rmin,
+                                               const double* __restrict__ diagH, double ml, double ibm,
                                                long long i, float x[NIN]) {
   const double b = beta[i], a1 = nu1[i], a2 = nu2[i];
   const double s1 = z[i] + b, s2 = z[i] - b;
-  const double num = a1 * s2 + a2 * s1;
-  const bool act = num >= rmin * (num + 4.0 * a1 * a2);
+  const bool act = pc_gate(a1, a2, s1, s2);
   const float g1 = (float)a1 * __builtin_amdgcn_rcpf((float)s1);
   const float g2 = (float)a2 * __builtin_amdgcn_rcpf((float)s2);
   const float L1 = g1 + g2;
@@ -430,15 +428,16 @@ __device__ __forceinline__ bool state_features(const double* __restrict__ beta, 
 
 // Correction of the interior-point state in one pass: Sigma_j = nu_j / s_j,
 // the four features, and c = softplus(MLP) + 1e-6 only where c can act on
-// P_c^{-1}, i.e. where L1 / (L1 + 4 S1 S2) >= rmin; elsewhere c = 1 (the
-// paper's P, from which P_c^{-1} then differs by less than rmin relative).
-// The network runs on the matrix cores for every 64-coefficient chunk that
-// holds an active coefficient.
+// P_c^{-1}, i.e. where L1 / (L1 + 4 S1 S2) >= kPcRelevance; elsewhere c = 1
+// (the paper's P, from which P_c^{-1} then differs by less than that
+// relative).  The network runs on the matrix cores for every 64-coefficient
+// chunk that holds an active coefficient; set[chunk] records which chunks
+// those are (where c may differ from 1).
 __global__ void __launch_bounds__(64 * kNetWaves)
 k_correction_state(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
                    const double* __restrict__ nu2, const double* __restrict__ diagH,
                    const double* __restrict__ meanlog, double mscale, const double* __restrict__ bmax,
-                   const float* __restrict__ P, float* __restrict__ c, long long n, double rmin) {
+                   const float* __restrict__ P, float* __restrict__ c, long long n, uint32_t* __restrict__ set) {
   __shared__ float lds[kNetWaves][64 * NIN];
   MfmaNet w;
   load_net(P, w);
@@ -449,10 +448,54 @@ k_correction_state(const double* __restrict__ beta, const double* __restrict__ z
   for (long long ch = blockIdx.x * (long long)kNetWaves + wv; ch < nch; ch += (long long)gridDim.x * kNetWaves) {
     const long long i = ch * 64 + l;
     float x[NIN] = {0.0f, 0.0f, 0.0f, 0.0f};
-    const bool act = i < n && state_features(beta, z, nu1, nu2, diagH, ml, ibm, rmin, i, x);
+    const bool act = i < n && state_features(beta, z, nu1, nu2, diagH, ml, ibm, i, x);
     float o = 0.0f;
-    if (__ballot(act)) o = net_chunk<kNetTiles>(w, lds[wv], x);   // chunks without an active coefficient skip the network
+    const bool any = __ballot(act) != 0;
+    if (any) o = net_chunk<kNetTiles>(w, lds[wv], x);   // chunks without an active coefficient skip the network
     if (i < n) c[i] = act ? softplusf(o) + 1e-6f : 1.0f;
+    if (l == 0) set[ch] = any ? 1u : 0u;
+  }
+}
+
+// One active chunk of k_correction_patch: c of its 64 coefficients, the
+// patched PCG start where c acts, and the changes of the start sums.
+template <typename TC>
+__device__ __forceinline__ void patch_chunk(const MfmaNet& w, float* lds, const double* __restrict__ beta,
+                                            const double* __restrict__ z, const double* __restrict__ nu1,
+                                            const double* __restrict__ nu2, const double* __restrict__ diagH,
+                                            double ml, double ibm, float* __restrict__ c, uint32_t* __restrict__ set,
+                                            long long n, long long ch, int l, bool h64, const TC* __restrict__ s1c,
+                                            const TC* __restrict__ s2c, const TC* __restrict__ rb,
+                                            const TC* __restrict__ rz, TC* __restrict__ pb, TC* __restrict__ pz,
+                                            const double* __restrict__ s164, const double* __restrict__ s264,
+                                            const double* __restrict__ hb64, const double* __restrict__ hz64,
+                                            double& d0, double& d1) {
+  constexpr bool F64 = std::is_same<TC, double>::value;
+  const long long i = ch * kPcChunk + l;
+  float x[NIN] = {0.0f, 0.0f, 0.0f, 0.0f};
+  const bool a = i < n && state_features(beta, z, nu1, nu2, diagH, ml, ibm, i, x);
+  const float o = net_chunk<kNetTiles>(w, lds, x);
+  const float ci = a ? softplusf(o) + 1e-6f : 1.0f;
+  if (i < n) c[i] = ci;
+  if (l == 0) set[ch] = 1u;
+  if (a) {
+    const double cv = (double)ci;
+    const TC r1 = rb[i], r2 = rz[i], g1 = s1c[i], g2 = s2c[i];
+    TC w1, w2, v1, v2;
+    pinv_block<TC>(r1, r2, g1, g2, cv, w1, w2);
+    pinv_block<TC>(r1, r2, g1, g2, 1.0, v1, v2);
+    pb[i] = w1;
+    pz[i] = w2;
+    d0 += ((double)r1 * (double)w1 + (double)r2 * (double)w2) - ((double)r1 * (double)v1 + (double)r2 * (double)v2);
+    if constexpr (F64) {
+      d1 += (r1 * w1 + r2 * w2) - (r1 * v1 + r2 * v2);
+    } else if (h64) {
+      const double h1 = hb64[i], h2 = hz64[i], G1 = s164[i], G2 = s264[i];
+      double u1, u2, q1, q2;
+      pinv_block<double>(h1, h2, G1, G2, cv, u1, u2);
+      pinv_block<double>(h1, h2, G1, G2, 1.0, q1, q2);
+      d1 += (h1 * u1 + h2 * u2) - (h1 * q1 + h2 * q2);
+    }
   }
 }
 
@@ -460,20 +503,23 @@ k_correction_state(const double* __restrict__ beta, const double* __restrict__ z
 // already built with the paper's P (c = 1): c as k_correction_state forms
 // it, and, at each coefficient where c acts, the PCG start patched in place
 // to p = P_c^{-1} r, by the same arithmetic as the Newton build with c.
-// Each workgroup adds what the patch changes in r.P^{-1}r (quantity 0, in
-// the Krylov precision TC, summed in FP64) and in h.P^{-1}h (quantity 1,
-// FP64; only when h64 is given) to its own partial of the update's
-// reduction, so the start sums become those of the corrected system.  The
-// grid must not exceed the update's workgroup count.  For TC = double, r is
-// h and the FP64 Sigma is s1c/s2c; for TC = float the FP64 h and Sigma are
-// hb64/hz64 and s164/s264 (null for a system solved without refinement,
-// whose h.P^{-1}h is not used).
+// Only chunks are visited that the update flagged active (act) or where c
+// was last set (set; every chunk when c is not known to be 1 outside them,
+// !tracked); set is brought up to date.  Each workgroup adds what the patch
+// changes in r.P^{-1}r (quantity 0, in the Krylov precision TC, summed in
+// FP64) and in h.P^{-1}h (quantity 1, FP64; only when h64 is given) to its
+// own partial of the update's reduction, so the start sums become those of
+// the corrected system.  The grid must not exceed the update's workgroup
+// count.  For TC = double, r is h and the FP64 Sigma is s1c/s2c; for TC =
+// float the FP64 h and Sigma are hb64/hz64 and s164/s264 (null for a system
+// solved without refinement, whose h.P^{-1}h is not used).
 template <typename TC>
 __global__ void __launch_bounds__(64 * kNetWaves)
 k_correction_patch(const double* __restrict__ beta, const double* __restrict__ z, const double* __restrict__ nu1,
                    const double* __restrict__ nu2, const double* __restrict__ diagH,
                    const double* __restrict__ meanlog, double mscale, const double* __restrict__ bmax,
-                   const float* __restrict__ P, float* __restrict__ c, long long n, double rmin,
+                   const float* __restrict__ P, float* __restrict__ c, long long n,
+                   const uint32_t* __restrict__ act, uint32_t* __restrict__ set, int tracked,
                    const TC* __restrict__ s1c, const TC* __restrict__ s2c, const TC* __restrict__ rb,
                    const TC* __restrict__ rz, TC* __restrict__ pb, TC* __restrict__ pz,
                    const double* __restrict__ s164, const double* __restrict__ s264,
@@ -482,42 +528,44 @@ k_correction_patch(const double* __restrict__ beta, const double* __restrict__ z
   __shared__ float lds[kNetWaves][64 * NIN];
   __shared__ double red[2][kNetWaves];
   MfmaNet w;
-  load_net(P, w);
+  bool loaded = false;
   const double ml = *meanlog * mscale;
   const double ibm = *bmax > 0.0 ? 1.0 / *bmax : 1.0;
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const long long nch = (n + 63) / 64;
+  const long long nch = (n + kPcChunk - 1) / kPcChunk;
   const bool h64 = F64 || hb64 != nullptr;
   double d0 = 0.0, d1 = 0.0;
-  for (long long ch = blockIdx.x * (long long)kNetWaves + wv; ch < nch; ch += (long long)gridDim.x * kNetWaves) {
-    const long long i = ch * 64 + l;
-    float x[NIN] = {0.0f, 0.0f, 0.0f, 0.0f};
-    const bool act = i < n && state_features(beta, z, nu1, nu2, diagH, ml, ibm, rmin, i, x);
-    if (!__ballot(act)) {
-      if (i < n) c[i] = 1.0f;
-      continue;
+  // wave v takes the chunks v, v + W, v + 2W, ... (W waves in the grid);
+  // lane l reads the flags of the wave's chunk 64 g + l of that sequence, so
+  // one load serves 64 of its chunks, and the wave visits those that need
+  // work (the ballot and the visit order are uniform across the wave)
+  const long long nwaves = (long long)gridDim.x * kNetWaves;
+  const long long first = blockIdx.x * (long long)kNetWaves + wv;
+  for (long long g0 = 0; first + g0 * nwaves < nch; g0 += 64) {
+    const long long mine = first + (g0 + l) * nwaves;
+    bool isact = false, need = false;
+    if (mine < nch) {
+      isact = act[mine] != 0u;
+      need = isact || !tracked || set[mine] != 0u;
     }
-    const float o = net_chunk<kNetTiles>(w, lds[wv], x);
-    const float ci = act ? softplusf(o) + 1e-6f : 1.0f;
-    if (i < n) c[i] = ci;
-    if (act) {
-      const double cv = (double)ci;
-      const TC r1 = rb[i], r2 = rz[i], g1 = s1c[i], g2 = s2c[i];
-      TC w1, w2, v1, v2;
-      pinv_block<TC>(r1, r2, g1, g2, cv, w1, w2);
-      pinv_block<TC>(r1, r2, g1, g2, 1.0, v1, v2);
-      pb[i] = w1;
-      pz[i] = w2;
-      d0 += ((double)r1 * (double)w1 + (double)r2 * (double)w2) - ((double)r1 * (double)v1 + (double)r2 * (double)v2);
-      if constexpr (F64) {
-        d1 += (r1 * w1 + r2 * w2) - (r1 * v1 + r2 * v2);
-      } else if (h64) {
-        const double h1 = hb64[i], h2 = hz64[i], G1 = s164[i], G2 = s264[i];
-        double u1, u2, q1, q2;
-        pinv_block<double>(h1, h2, G1, G2, cv, u1, u2);
-        pinv_block<double>(h1, h2, G1, G2, 1.0, q1, q2);
-        d1 += (h1 * u1 + h2 * u2) - (h1 * q1 + h2 * q2);
+    unsigned long long todo = __ballot(need);
+    const unsigned long long acts = __ballot(isact);
+    while (todo) {
+      const int b = __ffsll((long long)todo) - 1;
+      todo &= todo - 1ull;
+      const long long ch = first + (g0 + b) * nwaves;
+      const long long i = ch * kPcChunk + l;
+      if (!((acts >> b) & 1ull)) {
+        if (i < n) c[i] = 1.0f;
+        if (l == 0) set[ch] = 0u;
+        continue;
       }
+      if (!loaded) {
+        load_net(P, w);
+        loaded = true;
+      }
+      patch_chunk<TC>(w, lds[wv], beta, z, nu1, nu2, diagH, ml, ibm, c, set, n, ch, l, h64, s1c, s2c, rb, rz, pb,
+                      pz, s164, s264, hb64, hz64, d0, d1);
     }
   }
   d0 = wave_sum(d0);
@@ -713,33 +761,34 @@ void mlp_mean_log_l1_state(const double* beta, const double* z, const double* nu
 
 void mlp_correction_state(const double* beta, const double* z, const double* nu1, const double* nu2,
                           const double* diagH, const double* meanlog, double mscale, const double* bmax,
-                          const float* params, float* c, long long n, double rmin, hipStream_t s) {
+                          const float* params, float* c, long long n, uint32_t* set, hipStream_t s) {
   hipLaunchKernelGGL(k_correction_state, dim3(net_blocks(n)), dim3(64 * kNetWaves), 0, s, beta, z, nu1, nu2, diagH,
-                     meanlog, mscale, bmax, params, c, n, rmin);
+                     meanlog, mscale, bmax, params, c, n, set);
 }
 
 template <typename TC>
 void mlp_correction_patch(const double* beta, const double* z, const double* nu1, const double* nu2,
                           const double* diagH, const double* meanlog, double mscale, const double* bmax,
-                          const float* params, float* c, long long n, double rmin, const TC* s1c, const TC* s2c,
-                          const TC* rb, const TC* rz, TC* pb, TC* pz, const double* s164, const double* s264,
-                          const double* hb64, const double* hz64, double* partial, int stride, int max_blocks,
-                          hipStream_t s) {
+                          const float* params, float* c, long long n, const uint32_t* act, uint32_t* set,
+                          bool tracked, const TC* s1c, const TC* s2c, const TC* rb, const TC* rz, TC* pb, TC* pz,
+                          const double* s164, const double* s264, const double* hb64, const double* hz64,
+                          double* partial, int stride, int max_blocks, hipStream_t s) {
   const int nb = std::max(1, std::min(net_blocks(n), max_blocks));
   hipLaunchKernelGGL(k_correction_patch<TC>, dim3(nb), dim3(64 * kNetWaves), 0, s, beta, z, nu1, nu2, diagH, meanlog,
-                     mscale, bmax, params, c, n, rmin, s1c, s2c, rb, rz, pb, pz, s164, s264, hb64, hz64, partial,
-                     stride);
+                     mscale, bmax, params, c, n, act, set, tracked ? 1 : 0, s1c, s2c, rb, rz, pb, pz, s164, s264,
+                     hb64, hz64, partial, stride);
 }
 template void mlp_correction_patch<float>(const double*, const double*, const double*, const double*, const double*,
                                           const double*, double, const double*, const float*, float*, long long,
-                                          double, const float*, const float*, const float*, const float*, float*,
-                                          float*, const double*, const double*, const double*, const double*,
-                                          double*, int, int, hipStream_t);
+                                          const uint32_t*, uint32_t*, bool, const float*, const float*, const float*,
+                                          const float*, float*, float*, const double*, const double*, const double*,
+                                          const double*, double*, int, int, hipStream_t);
 template void mlp_correction_patch<double>(const double*, const double*, const double*, const double*, const double*,
                                            const double*, double, const double*, const float*, float*, long long,
-                                           double, const double*, const double*, const double*, const double*,
-                                           double*, double*, const double*, const double*, const double*,
-                                           const double*, double*, int, int, hipStream_t);
+                                           const uint32_t*, uint32_t*, bool, const double*, const double*,
+                                           const double*, const double*, double*, double*, const double*,
+                                           const double*, const double*, const double*, double*, int, int,
+                                           hipStream_t);
 
 void mlp_forward(const float* params, const float* feat, float* c, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_forward, dim3(net_blocks(n)), dim3(64 * kNetWaves), 0, s, params, feat, c, n);

@@ -133,11 +133,14 @@ void ipm_step(const double* beta, const double* z, const double* nu1, const doub
 // (next: also build the next Newton system from the new iterate at target
 // scal[S_SMU], as newton_init would with correction next->c; its r.z and
 // h.P^{-1}h partials stay in quantities NRESID_Q and NRESID_Q + 1 of partial)
+// (act: also act[c] = 1 where chunk c (coefficients 64c .. 64c + 63) of the
+// new iterate holds one where the correction's gate passes, else 0; the
+// launch covers n / 2 pairs in waves of 64 consecutive pairs)
 void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* db,
                  const double* dz, const float* db32, const float* dz32, const double* hd,
                  const double* rres, const float* rres32, double lam, double smu, double* scal, long long n,
                  double* partial, bool logsum, hipStream_t s, const double* dab = nullptr,
-                 const double* daz = nullptr, const NextSystem* next = nullptr);
+                 const double* daz = nullptr, const NextSystem* next = nullptr, uint32_t* act = nullptr);
 
 void add_f2d(double* db, double* dz, const float* eb, const float* ez, long long n, hipStream_t s);
 // FP32 restart of a further inner solve from H d_beta (hd): r32, z32 = p32 =

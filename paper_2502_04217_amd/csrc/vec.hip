@@ -433,10 +433,8 @@ __device__ __forceinline__ void resid_accumulate(double* v, double b, double s1,
   if (!isfinite(fb) || !isfinite(c1) || !isfinite(c2)) v[6] += 1.0;
   if (logsum) {
     v[7] += log(a1 / s1 + a2 / s2);
-    // coefficients where the learned correction can matter: L1 / (L1 +
-    // 4 S1 S2) >= kPcRelevance, multiplied through by s1 s2 > 0
-    const double num = a1 * s2 + a2 * s1;
-    v[8] += num >= kPcRelevance * (num + 4.0 * a1 * a2) ? 1.0 : 0.0;
+    // coefficients where the learned correction can matter
+    v[8] += pc_gate(a1, a2, s1, s2) ? 1.0 : 0.0;
   }
 }
 __global__ void __launch_bounds__(256)
@@ -740,7 +738,7 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
               const float* rres32, const float* __restrict__ db32, const float* __restrict__ dz32,
               double lam, double smu, const double* __restrict__ scal, long long n, double* partial, int stride,
               int logsum, const double* __restrict__ dab, const double* __restrict__ daz, NewtonOut<TC> no,
-              const float* __restrict__ cn) {
+              const float* __restrict__ cn, uint32_t* __restrict__ act) {
   const double a = scal[S_ALPHA_IPM];
   const double smu_next = NI ? scal[S_SMU] : 0.0;
   double v[NRESID + 2] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -793,6 +791,16 @@ k_ipm_advance(double* __restrict__ beta, double* __restrict__ z, double* __restr
     N1[j] = {n1o[0], n1o[1]};
     N2[j] = {n2o[0], n2o[1]};
     HBV[j] = {ho[0], ho[1]};
+    if (act) {
+      // activity flags of the correction, one per 64 coefficients: the 64
+      // lanes of a wave hold 64 consecutive pairs, i.e. two chunks
+      const bool a = pc_gate(n1o[0], n2o[0], zo[0] + bo[0], zo[0] - bo[0]) ||
+                     pc_gate(n1o[1], n2o[1], zo[1] + bo[1], zo[1] - bo[1]);
+      const unsigned long long m = __ballot(a);
+      const int lane = threadIdx.x & 63;
+      if (lane == 0) act[j >> 5] = (m & 0xffffffffull) ? 1u : 0u;
+      if (lane == 32) act[j >> 5] = (m >> 32) ? 1u : 0u;
+    }
     if constexpr (NI) {
       const float2 cc = cn ? reinterpret_cast<const float2*>(cn)[j] : make_float2(1.0f, 1.0f);
       const double cv[2] = {(double)cc.x, (double)cc.y}, zero[2] = {0.0, 0.0};
@@ -975,16 +983,6 @@ k_absmax(const double* __restrict__ a, long long n, double* partial) {
   block_reduce_store<1>(&v, &op, partial, 0);
 }
 
-// 3D class of a frequency: 0 self-conjugate, 1 canonical, 2 mirror of one.
-__device__ __forceinline__ int cls3(int k1, int k2, int k3, int n1, int n2, int n3) {
-  const bool e1 = k1 == 0 || 2 * k1 == n1, e2 = k2 == 0 || 2 * k2 == n2, e3 = k3 == 0 || 2 * k3 == n3;
-  if (e1 && e2 && e3) return 0;
-  if (k3 >= 1 && 2 * k3 < n3) return 1;
-  if (e3 && k2 >= 1 && 2 * k2 < n2) return 1;
-  if (e3 && e2 && k1 >= 1 && 2 * k1 < n1) return 1;
-  return 2;
-}
-
 // diag(M_perp^T M_perp) in the external beta layout from bm = A^T(mask):
 // column i of A squared is (1/n)(1 + s_i cos(2 theta)), so
 // H_ii = m/n + s_i Re(v_{2k}) / sqrt(n) with v the unitary DFT of the mask
@@ -1159,14 +1157,14 @@ void ipm_step(const double* beta, const double* z, const double* nu1, const doub
 void ipm_advance(double* beta, double* z, double* nu1, double* nu2, double* hbeta, const double* db, const double* dz,
                  const float* db32, const float* dz32, const double* hd, const double* rres, const float* rres32,
                  double lam, double smu, double* scal, long long n, double* partial, bool logsum, hipStream_t s,
-                 const double* dab, const double* daz, const NextSystem* next) {
+                 const double* dab, const double* daz, const NextSystem* next, uint32_t* act) {
   const int nb = vec_blocks(n);
   const int hdm = hd ? ADV_DIRECT : rres32 ? ADV_RRES32 : ADV_RRES64;
   // (an FP32 direction comes only with the FP32 residual)
   const int ls = logsum ? 1 : 0;
 #define CSIPM_ADV(TC, NI, HDM, CORR, NO, CN)                                                                        \
   hipLaunchKernelGGL((k_ipm_advance<TC, NI, HDM, CORR>), VB, beta, z, nu1, nu2, hbeta, db, dz, hd, rres, rres32,    \
-                     db32, dz32, lam, smu, scal, n, partial, VEC_MAX_BLOCKS, ls, dab, daz, NO, CN)
+                     db32, dz32, lam, smu, scal, n, partial, VEC_MAX_BLOCKS, ls, dab, daz, NO, CN, act)
   if (next && next->out32) {   // (standard steps: no corrector terms)
     if (hdm == ADV_DIRECT)
       CSIPM_ADV(float, true, ADV_DIRECT, false, *next->out32, next->c);

@@ -105,8 +105,9 @@ def synthesize(shape, wave_k: np.ndarray, wave_c: np.ndarray) -> np.ndarray:
     numpy's irfftn computes (1/n) sum over the full Hermitian spectrum, using
     only bins with k3 <= N3/2.  A wave placed as c at k and conj(c) at -k
     contributes (2/n) Re(c e^{i theta}); bins with k3 > N3/2 are written at -k
-    (conjugated), and in the planes k3 in {0, N3/2} both k and -k are written
-    because irfftn keeps only the real part of those planes' 2D inverse."""
+    (conjugated), and in the self-paired planes (k3 = 0, and k3 = N3/2 for an
+    even N3) both k and -k are written because irfftn keeps only the real
+    part of those planes' 2D inverse."""
     N1, N2, N3 = shape
     n = N1 * N2 * N3
     half = N3 // 2
@@ -117,12 +118,13 @@ def synthesize(shape, wave_k: np.ndarray, wave_c: np.ndarray) -> np.ndarray:
         cs = c * scale
         mk = (-kv) % Nv
         k3 = int(kv[2])
-        if 0 < k3 < half:                          # strictly inside the half
+        paired = k3 == 0 or (N3 % 2 == 0 and k3 == half)
+        if paired:                                 # a self-paired plane: both bins
             S[kv[0], kv[1], k3] += cs
-        elif k3 > half:                            # mirror lies inside the half
             S[mk[0], mk[1], mk[2]] += np.conj(cs)
-        else:                                      # k3 in {0, N3/2}: both bins
+        elif k3 <= half:                           # inside the stored half
             S[kv[0], kv[1], k3] += cs
+        else:                                      # mirror lies inside the half
             S[mk[0], mk[1], mk[2]] += np.conj(cs)
     return np.fft.irfftn(S, s=shape, axes=(0, 1, 2))
 

@@ -40,7 +40,9 @@ def test_host_only_calls():
     assert csipm.workspace_bytes((8, 8, 2)) == 0
     assert csipm.workspace_bytes((1, 8, 8)) > 0
     assert csipm.workspace_bytes((15, 21, 8)) > 0
-    assert csipm.workspace_bytes((8, 8, 15)) == 0
+    assert csipm.workspace_bytes((8, 8, 15)) > 0      # odd N3: the full-spectrum transforms
+    assert csipm.workspace_bytes((45, 45, 45)) > 0
+    assert csipm.workspace_bytes((8, 8, 11)) == 0
     o = csipm.default_options()
     assert o.tol == 1e-6 and o.sigma == 0.1 and o.tau == 0.99
     assert csipm.lib().csipm_status_string(-5) == b"unsupported grid"

@@ -291,16 +291,24 @@ PARAMS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 @pytest.mark.skipif(not os.path.exists(PARAMS), reason="no trained parameters committed")
 def test_trained_network_on_held_out_problems():
-    """Held-out 128^3 problems: the trained correction reaches the same true
-    KKT residual as the paper's preconditioner; its PCG iteration total is
-    reported against the plain one and may not exceed it by more than 10%."""
+    """Held-out 128^3 problems (the first 8 of the 50 in
+    profiles/learned_eval_128cubed.md): the trained correction reaches the
+    same true KKT residual as the paper's preconditioner with no more PCG
+    iterations in either form (the 50-seed record: 0.984x in FP64, 0.963x in
+    FP32), and no slowdown beyond 10 % (the record: 1.02x and 1.01x the time;
+    at 128^3 the inference on the last systems costs about what the saved
+    iterations gain, while at 256^3 the chosen form is the faster one)."""
     torch = need_gpu()
     from paper_2502_04217_amd import csipm, learn
     with open(PARAMS) as fh:
         params = torch.tensor(json.load(fh)["params"], dtype=torch.float32, device="cuda")
-    rows = learn.evaluate(params, [10000, 10001, 10002], log=say)
+    rows = learn.evaluate(params, list(range(10000, 10008)), log=say)
     s = learn.summarize(rows)
     say("held-out summary", json.dumps(s))
     assert s["fp64_learned"]["max_true_rel_kkt"] <= 1e-6
     assert s["fp32_learned"]["max_true_rel_kkt"] <= 1e-6
-    assert s["cg_ratio_fp64"] <= 1.10
+    assert s["fp64_learned"]["fallbacks"] == 0 and s["fp32_learned"]["fallbacks"] == 0
+    assert s["cg_ratio_fp64"] <= 1.0
+    assert s["cg_ratio_fp32"] <= 1.0
+    assert s["time_ratio_fp64"] <= 1.10
+    assert s["time_ratio_fp32"] <= 1.10

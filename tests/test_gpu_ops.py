@@ -23,6 +23,10 @@ MIXED_SHAPES = [(_MIXED[i], _MIXED[(i + 1) % 8], _MIXED[(i + 2) % 8]) for i in r
 LOWDIM_SHAPES = [(1, 64, 64), (1, 1, 256), (2, 96, 40), (1, 560, 12), (64, 1, 32), (2, 2, 8), (1, 1, 4)]
 # odd extents on axes 1 and 2 (no Nyquist index there)
 ODD_SHAPES = [(3, 5, 8), (7, 9, 12), (15, 21, 16), (35, 45, 20), (45, 35, 64), (1, 21, 28), (5, 1, 40), (9, 7, 96)]
+# odd N3 (the full-spectrum transforms), with an even and an odd number of
+# samples (the latter adds a coordinate without data inside the library)
+ODD3_SHAPES = [(8, 8, 15), (15, 21, 35), (45, 45, 45), (3, 5, 7), (1, 1, 9), (1, 16, 21), (12, 20, 5), (2, 4, 3),
+               (64, 32, 9)]
 # the pencil lengths of the full-size workloads: 256 and 512 on the strided
 # axes (the axis-1 inverse tile of 16 pencils at 8 values per thread in FP64
 # from 512, the K epilogue at 256), N3 = 256 and 512 in 3D grids (the
@@ -42,7 +46,8 @@ def _problem(shape, seed=0):
     return torch, csipm, csipm.Problem(sig, obs), sig, obs
 
 
-@pytest.mark.parametrize("shape", SHAPES + BENCH_SHAPES + MIXED_SHAPES + LOWDIM_SHAPES + ODD_SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + BENCH_SHAPES + MIXED_SHAPES + LOWDIM_SHAPES + ODD_SHAPES + ODD3_SHAPES,
+                         ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_operator_parity(shape, prec):
     torch, csipm, pr, sig, obs = _problem(shape, 1)
@@ -183,8 +188,8 @@ def test_errors():
     with pytest.raises(csipm.CsipmError) as e:
         csipm.Problem(np.zeros((8, 18, 8)), np.ones((8, 18, 8), np.uint8))
     assert e.value.status == -5
-    with pytest.raises(csipm.CsipmError) as e:     # odd N3
-        csipm.Problem(np.zeros((8, 8, 15)), np.ones((8, 8, 15), np.uint8))
+    with pytest.raises(csipm.CsipmError) as e:     # an odd extent without kernels
+        csipm.Problem(np.zeros((8, 8, 11)), np.ones((8, 8, 11), np.uint8))
     assert e.value.status == -5
     pr = csipm.Problem(np.random.default_rng(0).standard_normal((8, 8, 8)), obs)
     with pytest.raises(csipm.CsipmError) as e:

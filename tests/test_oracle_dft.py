@@ -104,16 +104,19 @@ def test_1d_map_matches_hand_worked_golden():
         assert np.abs(Ap.T @ Ap - np.eye(n)).max() < 1e-15
 
 
-def test_synthesised_waves_match_A():
+@pytest.mark.parametrize("shape", [(8, 6, 10), (5, 6, 7), (4, 9, 15), (3, 5, 3)])
+def test_synthesised_waves_match_A(shape):
     """numpy's irfftn synthesis of plane waves equals A applied to the beta
-    the oracle derives from the wave list (two independent routes)."""
-    w = wl.make_workload((8, 6, 10), n_freq=14, amplitude="normal", snr_db=np.inf,
+    the oracle derives from the wave list (two independent routes), with an
+    even N3 and with odd ones (no Nyquist plane: k3 = floor(N3/2) is an
+    interior bin)."""
+    w = wl.make_workload(shape, n_freq=14, amplitude="normal", snr_db=np.inf,
                          half_width=-1, period=2, seed=7)
     beta = dft3.waves_to_beta(w.shape, w.wave_k, w.wave_c)
     assert np.count_nonzero(beta) == 14
     assert np.abs(dft3.apply_A(beta) - w.clean).max() < 1e-14
     # and the naive DFT agrees with numpy's FFT
-    x = np.random.default_rng(3).standard_normal((8, 6, 10))
+    x = np.random.default_rng(3).standard_normal(shape)
     assert np.abs(dft3.dft3(x) - np.fft.fftn(x, norm="ortho")).max() < 1e-13
 
 
