@@ -262,6 +262,38 @@ csipm_status csipm_solve(csipm_ctx* ctx, const csipm_options* opts, csipm_info* 
 csipm_status csipm_solve_batch(csipm_ctx* const* ctxs, int count, const csipm_options* opts, csipm_info* infos,
                                int* statuses, int max_threads);
 
+/* Batches of small problems in one launch (the learned correction's
+ * training throughput; no context, no host round trip until the batch is
+ * done).  `count` problems of one N1 x N2 x N3 grid, each extent in
+ * [1, 64] (any length, odd or even; n = N1*N2*N3), are solved by one kernel,
+ * one workgroup per problem, each to rel_kkt <= opts->tol with the standard
+ * interior-point steps in FP64 and PCG with the paper's preconditioner
+ * (section "Primal-dual interior-point method", equations "kkt", "kktmu",
+ * "condensedkkt", "invprecond1"; the readings of csipm_solve: starting
+ * point, fixed centring sigma, step tau, PCG tolerance min(cg_rtol,
+ * 0.1 rel_kkt) with floor cg_atol).  H beta is recomputed at every iterate.
+ *   d_signals   [count][n] doubles, d_observed [count][n] bytes (0 missing)
+ *   d_lambdas   [count] doubles > 0, or NULL: lambda = lambda_frac *
+ *               ||M_perp^T b||_inf per problem (lambda_frac > 0)
+ *   d_beta_out  [count][n] doubles, the solutions (external beta layout)
+ *   d_info      [count][CSIPM_SMALL_INFO] doubles: status (0 converged,
+ *               1 iteration limit, -2 non-finite iterate), interior-point
+ *               iterations, PCG iterations, rel_kkt, mu, lambda
+ *   d_workspace csipm_small_workspace_bytes(n1, n2, n3, count) bytes,
+ *               256-byte aligned, owned by the caller
+ * Reads tol, max_iter, cg_max, cg_rtol, cg_atol, sigma, tau of opts (the
+ * others are ignored).  A problem's result does not depend on the rest of
+ * its batch.  Copies the twiddle tables into the workspace and
+ * synchronises hip_stream once before the launch; the solve itself is
+ * asynchronous on it.  Errors: EINVAL, EUNSUPPORTED (an extent outside
+ * [1, 64]), ENOMEM (workspace too small), EHIP. */
+#define CSIPM_SMALL_INFO 6
+size_t csipm_small_workspace_bytes(int n1, int n2, int n3, int count);
+csipm_status csipm_solve_small_batch(int n1, int n2, int n3, int count, const double* d_signals,
+                                     const uint8_t* d_observed, const double* d_lambdas, double lambda_frac,
+                                     const csipm_options* opts, double* d_beta_out, double* d_info,
+                                     void* d_workspace, size_t workspace_bytes, void* hip_stream);
+
 /* Copies an iterate or a fixed vector to d_dst (n doubles, external beta
  * layout). */
 csipm_status csipm_get_iterate(csipm_ctx* ctx, int which, double* d_dst);

@@ -1,6 +1,8 @@
 """Throughput of many small independent solves: one after another against
 csipm_solve_batch (each problem on its own stream, solves on a pool of host
-threads).  The paper's synthetic problem at a small grid, seeds 0..count-1.
+threads) and against csipm_solve_small_batch (one kernel, one workgroup per
+problem).  The paper's synthetic problem at a small grid, seeds
+0..count-1.
 
     python -m paper_2502_04217_amd.batch_throughput [--grid 16] [--count 64] [--threads 1 2 4 8]
 
@@ -52,6 +54,22 @@ def main(argv=None):
         ok = all(i["status"] >= 0 for i in infos)
         print(json.dumps({"grid": a.grid, "count": a.count, "mode": "batch", "threads": nt, "seconds": dt,
                           "solves_per_s": a.count / dt, "speedup": seq / dt, "all_ok": ok}), flush=True)
+    # one launch: the same problems in one kernel (signals and masks already
+    # on the device, as for the contexts above)
+    import numpy as np
+    ws = [wl.paper_synthetic(a.grid, seed) for seed in range(a.count)]
+    sig = torch.tensor(np.stack([w.signal for w in ws]), device="cuda")
+    obs = torch.tensor(np.stack([w.observed for w in ws]).astype(np.uint8), device="cuda")
+    csipm.solve_small_batch(sig, obs, lambda_frac=0.05, tol=a.tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    beta, info = csipm.solve_small_batch(sig, obs, lambda_frac=0.05, tol=a.tol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"grid": a.grid, "count": a.count, "mode": "one_launch", "seconds": dt,
+                      "solves_per_s": a.count / dt, "speedup": seq / dt, "all_ok": bool((info[:, 0] == 0).all()),
+                      "ipm_iters_mean": float(info[:, 1].mean()), "pcg_iters_mean": float(info[:, 2].mean())}),
+          flush=True)
     return 0
 
 

@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH):
         "csipm_destroy": (I, [P]),
         "csipm_status_string": (C.c_char_p, [I]),
         "csipm_last_error": (C.c_char_p, [P]),
+        "csipm_small_workspace_bytes": (S, [I, I, I, I]),
+        "csipm_solve_small_batch": (I, [I, I, I, I, P, P, P, D, C.POINTER(Options), P, P, P, S, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -166,6 +168,51 @@ def solve_batch(problems, opts: Options | None = None, max_threads: int = 0, **k
         d["status_name"] = STATUS.get(sts[i], "?")
         out.append(d)
     return out
+
+
+SMALL_INFO = 6
+SMALL_STATUS = {0: "OK", 1: "NOT_CONVERGED", -2: "NONFINITE"}
+
+
+def small_workspace_bytes(shape, count: int) -> int:
+    return int(lib().csipm_small_workspace_bytes(*[int(s) for s in shape], int(count)))
+
+
+def solve_small_batch(signals, observed, lambdas=None, lambda_frac: float = 0.05, opts: Options | None = None,
+                      **kw):
+    """csipm_solve_small_batch: count problems of one small grid (each
+    extent <= 64) solved by one kernel, one workgroup per problem.
+    signals: [count, N1, N2, N3] float64, observed: the same shape, nonzero =
+    observed (numpy or torch); lambdas: [count] or None (lambda_frac times
+    ||M_perp^T b||_inf).  Returns (beta [count, N1, N2, N3] float64 on the
+    device, info [count, SMALL_INFO] on the host: status, interior-point
+    iterations, PCG iterations, rel_kkt, mu, lambda)."""
+    import torch
+    o = opts if opts is not None else default_options(**kw)
+    sig = torch.as_tensor(signals, dtype=torch.float64).to("cuda").contiguous()
+    obs = (torch.as_tensor(observed) != 0).to(torch.uint8).to("cuda").contiguous()
+    if sig.dim() != 4 or obs.shape != sig.shape:
+        raise ValueError("signals and observed must be [count, N1, N2, N3]")
+    count, shape = sig.shape[0], tuple(sig.shape[1:])
+    lam = None
+    if lambdas is not None:
+        lam = torch.as_tensor(lambdas, dtype=torch.float64).to("cuda").contiguous()
+    beta = torch.empty_like(sig)
+    info = torch.empty((count, SMALL_INFO), dtype=torch.float64, device="cuda")
+    nb = small_workspace_bytes(shape, count)
+    if nb == 0:
+        raise CsipmError(-5, "solve_small_batch: extents must lie in [1, 64]")
+    ws = torch.empty(nb // 8 + 64, dtype=torch.float64, device="cuda")
+    base = ws.data_ptr()
+    off = (-base) % 256
+    st = lib().csipm_solve_small_batch(*[int(v) for v in shape], int(count), _ptr(sig), _ptr(obs),
+                                       _ptr(lam) if lam is not None else None, float(lambda_frac), C.byref(o),
+                                       _ptr(beta), _ptr(info), C.c_void_p(base + off), nb, _stream())
+    if st < 0:
+        msg = lib().csipm_last_error(None)
+        raise CsipmError(st, f"solve_small_batch: {msg.decode() if msg else ''}")
+    torch.cuda.current_stream().synchronize()
+    return beta, info.cpu().numpy()
 
 
 def workspace_bytes(shape) -> int:
