@@ -7,8 +7,9 @@ namespace csipm {
 
 // the largest extent of a small problem (direct DFTs: L^2 work per pencil)
 constexpr int kSmallMaxExtent = 64;
-// grids up to this many points keep their two spectra in LDS (2 x 64 KB)
-constexpr long long kSmallLdsPoints = 4096;
+// the spectrum buffers (one, or two when an extent takes the direct DFT) of
+// a grid sit in LDS when they take at most this many bytes
+constexpr long long kSmallLdsBytes = 131072;
 
 // the options the small solver reads (those of csipm_options it uses)
 struct SmallOpts {

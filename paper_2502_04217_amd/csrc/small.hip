@@ -8,12 +8,13 @@
 // The steps are those of the library's standard form in FP64 (the readings
 // of the barrier strategy, right-hand side and stopping rules), on the
 // simplest data path: H beta is recomputed by a full H-apply at every
-// iterate, and the operators run on the whole Hermitian spectrum with
-// direct DFTs along each axis (L^2 work per pencil, any extent up to
-// kSmallMaxExtent, odd or even).  The spectrum is double-buffered in LDS when
-// it fits (n <= kSmallLdsPoints), else in the problem's workspace.  A
-// problem's result does not depend on the others in the batch: a batch of
-// one gives the same bits.
+// iterate, and the operators run on the whole Hermitian spectrum, one axis
+// at a time, in place: a pencil of power-of-two length up to 32 is
+// transformed by one thread in registers (radix 2), any other length up to
+// kSmallMaxExtent by direct DFTs (L^2 work per pencil) through a second
+// buffer.  The spectrum sits in LDS when it fits (kSmallLdsBytes), else in
+// the problem's workspace.  A problem's result does not depend on the
+// others in the batch: a batch of one gives the same bits.
 #include "small.h"
 
 #include "../../include/csipm.h"
@@ -104,6 +105,89 @@ __device__ void dft_pass(const cx<double>* src, cx<double>* dst, const SmallDims
   __syncthreads();
 }
 
+constexpr int bitrev(int j, int L) {
+  int r = 0;
+  for (int b = 1; b < L; b <<= 1) {
+    r = (r << 1) | (j & 1);
+    j >>= 1;
+  }
+  return r;
+}
+
+// pencils of length L (a power of two) transformed in place, one per
+// thread: loaded in bit-reversed order, radix-2 butterflies in registers
+// (span len, twiddles tw[k L / len]), written back in order
+template <int L>
+__device__ void reg_pass(cx<double>* w, const SmallDims& d, int axis, int dir, const cx<double>* tw) {
+  const long long st = axis == 1 ? (long long)d.n2 * d.n3 : axis == 2 ? d.n3 : 1;
+  const long long npen = d.n / L;
+  for (long long P = threadIdx.x; P < npen; P += kSmallThreads) {
+    const long long base =
+        axis == 1 ? P : axis == 2 ? (P / d.n3) * ((long long)d.n2 * d.n3) + P % d.n3 : P * (long long)d.n3;
+    cx<double> v[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) v[bitrev(j, L)] = w[base + (long long)j * st];
+#pragma unroll
+    for (int len = 2; len <= L; len <<= 1) {
+      const int half = len >> 1, step = L / len;
+#pragma unroll
+      for (int i = 0; i < L; i += len)
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+          const cx<double> t0 = tw[k * step];
+          const double wr = t0.re, wi = dir > 0 ? -t0.im : t0.im;
+          const cx<double> a = v[i + k], b = v[i + k + half];
+          const double tr = b.re * wr - b.im * wi, ti = b.re * wi + b.im * wr;
+          v[i + k] = {a.re + tr, a.im + ti};
+          v[i + k + half] = {a.re - tr, a.im - ti};
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < L; ++j) w[base + (long long)j * st] = v[j];
+  }
+  __syncthreads();
+}
+
+// whether an extent takes the register pass (else the direct DFT)
+__host__ __device__ constexpr bool reg_length(int L) { return L == 2 || L == 4 || L == 8 || L == 16 || L == 32; }
+
+// one axis of the full-spectrum transform of w, in place (scr: n complex of
+// scratch for the direct DFT of other lengths).  RMAX is the longest
+// register pencil the kernel instance holds (32 takes about twice the
+// registers of 16, so grids without a 32-point axis use the 16 instance).
+template <int RMAX>
+__device__ void axis_pass(cx<double>* w, cx<double>* scr, const SmallDims& d, int axis, int dir,
+                          const cx<double>* tw) {
+  const int L = axis == 1 ? d.n1 : axis == 2 ? d.n2 : d.n3;
+  if constexpr (RMAX >= 32) {
+    if (L == 32) {
+      reg_pass<32>(w, d, axis, dir, tw);
+      return;
+    }
+  }
+  switch (L) {
+    case 1:
+      return;
+    case 2:
+      reg_pass<2>(w, d, axis, dir, tw);
+      return;
+    case 4:
+      reg_pass<4>(w, d, axis, dir, tw);
+      return;
+    case 8:
+      reg_pass<8>(w, d, axis, dir, tw);
+      return;
+    case 16:
+      reg_pass<16>(w, d, axis, dir, tw);
+      return;
+    default:
+      dft_pass(w, scr, d, axis, dir, tw);
+      for (long long f = threadIdx.x; f < d.n; f += kSmallThreads) w[f] = scr[f];
+      __syncthreads();
+      return;
+  }
+}
+
 struct SmallTw {
   const cx<double>* t1;
   const cx<double>* t2;
@@ -111,9 +195,10 @@ struct SmallTw {
 };
 
 // y = H beta = A^T D A beta (beta and y in the external parametrisation of
-// derivation "map"); w0, w1 hold n complex values each.
+// derivation "map"); w0 holds the n-point spectrum, scr n complex of scratch.
+template <int RMAX>
 __device__ void h_apply(const double* beta, double* y, const uint8_t* obs, const SmallDims& d, const SmallTw& tw,
-                        cx<double>* w0, cx<double>* w1) {
+                        cx<double>* w0, cx<double>* scr) {
   const double rs2 = 0.70710678118654752440, sq2 = 1.41421356237309504880;
   for (long long f = threadIdx.x; f < d.n; f += kSmallThreads) {
     int k1, k2, k3;
@@ -128,40 +213,41 @@ __device__ void h_apply(const double* beta, double* y, const uint8_t* obs, const
     }
   }
   __syncthreads();
-  dft_pass(w0, w1, d, 1, +1, tw.t1);
-  dft_pass(w1, w0, d, 2, +1, tw.t2);
-  dft_pass(w0, w1, d, 3, +1, tw.t3);
+  axis_pass<RMAX>(w0, scr, d, 1, +1, tw.t1);
+  axis_pass<RMAX>(w0, scr, d, 2, +1, tw.t2);
+  axis_pass<RMAX>(w0, scr, d, 3, +1, tw.t3);
   const double sc = 1.0 / (double)d.n;   // both unitary normalisations
-  for (long long f = threadIdx.x; f < d.n; f += kSmallThreads) w0[f] = {obs[f] ? w1[f].re * sc : 0.0, 0.0};
+  for (long long f = threadIdx.x; f < d.n; f += kSmallThreads) w0[f] = {obs[f] ? w0[f].re * sc : 0.0, 0.0};
   __syncthreads();
-  dft_pass(w0, w1, d, 3, -1, tw.t3);
-  dft_pass(w1, w0, d, 2, -1, tw.t2);
-  dft_pass(w0, w1, d, 1, -1, tw.t1);
+  axis_pass<RMAX>(w0, scr, d, 3, -1, tw.t3);
+  axis_pass<RMAX>(w0, scr, d, 2, -1, tw.t2);
+  axis_pass<RMAX>(w0, scr, d, 1, -1, tw.t1);
   for (long long f = threadIdx.x; f < d.n; f += kSmallThreads) {
     int k1, k2, k3;
     unravel(f, d, k1, k2, k3);
     const int c = cls3(k1, k2, k3, d.n1, d.n2, d.n3);
-    const cx<double> h = w1[f];
+    const cx<double> h = w0[f];
     y[f] = c == 0 ? h.re : (c == 1 ? sq2 * h.re : -sq2 * h.im);
   }
   __syncthreads();
 }
 
 // xi = A^T b_hat = B DFT(b_hat) (the adjoint of A, reading "adjoint")
+template <int RMAX>
 __device__ void at_apply(const double* x, const uint8_t* obs, double* out, const SmallDims& d, const SmallTw& tw,
-                         cx<double>* w0, cx<double>* w1) {
+                         cx<double>* w0, cx<double>* scr) {
   const double sq2 = 1.41421356237309504880;
   const double sc = 1.0 / sqrt((double)d.n);
   for (long long f = threadIdx.x; f < d.n; f += kSmallThreads) w0[f] = {obs[f] ? x[f] * sc : 0.0, 0.0};
   __syncthreads();
-  dft_pass(w0, w1, d, 3, -1, tw.t3);
-  dft_pass(w1, w0, d, 2, -1, tw.t2);
-  dft_pass(w0, w1, d, 1, -1, tw.t1);
+  axis_pass<RMAX>(w0, scr, d, 3, -1, tw.t3);
+  axis_pass<RMAX>(w0, scr, d, 2, -1, tw.t2);
+  axis_pass<RMAX>(w0, scr, d, 1, -1, tw.t1);
   for (long long f = threadIdx.x; f < d.n; f += kSmallThreads) {
     int k1, k2, k3;
     unravel(f, d, k1, k2, k3);
     const int c = cls3(k1, k2, k3, d.n1, d.n2, d.n3);
-    const cx<double> h = w1[f];
+    const cx<double> h = w0[f];
     out[f] = c == 0 ? h.re : (c == 1 ? sq2 * h.re : -sq2 * h.im);
   }
   __syncthreads();
@@ -184,6 +270,7 @@ enum SmallVec {
   SV_COUNT
 };
 
+template <int RMAX>
 __global__ void __launch_bounds__(kSmallThreads)
 k_small_solve(int n1, int n2, int n3, const double* __restrict__ signals, const uint8_t* __restrict__ observed,
               const double* __restrict__ lambdas, double lambda_frac, double* __restrict__ beta_out,
@@ -197,15 +284,10 @@ k_small_solve(int n1, int n2, int n3, const double* __restrict__ signals, const 
   const double* sig = signals + (long long)p * n;
   const uint8_t* obs = observed + (long long)p * n;
   double* v = reinterpret_cast<double*>(ws + (long long)p * ws_stride);
-  cx<double>* w0;
-  cx<double>* w1;
-  if (lds_spectrum) {
-    w0 = reinterpret_cast<cx<double>*>(smem);
-    w1 = w0 + n;
-  } else {
-    w0 = reinterpret_cast<cx<double>*>(v + (long long)SV_COUNT * n);
-    w1 = w0 + n;
-  }
+  // the spectrum and, for a length without the register pass, its scratch
+  cx<double>* w0 = lds_spectrum ? reinterpret_cast<cx<double>*>(smem)
+                                : reinterpret_cast<cx<double>*>(v + (long long)SV_COUNT * n);
+  cx<double>* w1 = w0 + n;
   const SmallTw T{tw, tw + n1, tw + n1 + n2};
   double *xi = v + SV_XI * n, *be = v + SV_B * n, *zv = v + SV_Z * n, *nu1 = v + SV_N1 * n,
          *nu2 = v + SV_N2 * n, *hb = v + SV_HB * n, *g1 = v + SV_S1 * n, *g2 = v + SV_S2 * n, *xb = v + SV_XB * n,
@@ -214,7 +296,7 @@ k_small_solve(int n1, int n2, int n3, const double* __restrict__ signals, const 
 
   // xi = A^T b_hat, lambda, the starting point beta = 0, z = |xi|_inf (1 if 0),
   // nu = lambda / 2 (reading "barrier strategy")
-  at_apply(sig, obs, xi, d, T, w0, w1);
+  at_apply<RMAX>(sig, obs, xi, d, T, w0, w1);
   double xinf = 0.0;
   for (long long f = threadIdx.x; f < n; f += kSmallThreads) xinf = fmax(xinf, fabs(xi[f]));
   xinf = block_reduce(xinf, 1, red);
@@ -232,7 +314,7 @@ k_small_solve(int n1, int n2, int n3, const double* __restrict__ signals, const 
   double rel = INFINITY, mu = 0.0;
   for (;; ++it) {
     // residual of the iterate (equation "kkt") and its relative size
-    h_apply(be, hb, obs, d, T, w0, w1);
+    h_apply<RMAX>(be, hb, obs, d, T, w0, w1);
     double fb = 0.0, fz = 0.0, cmax = 0.0, csum = 0.0;
     bool bad = false;
     for (long long f = threadIdx.x; f < n; f += kSmallThreads) {
@@ -292,7 +374,7 @@ k_small_solve(int n1, int n2, int n3, const double* __restrict__ signals, const 
     int cg = 0;
     while (sqrt(fmax(rho, 0.0)) > tol && cg < o.cg_max) {
       // q = K p (H p_beta plus the Sigma terms)
-      h_apply(pb, qb, obs, d, T, w0, w1);
+      h_apply<RMAX>(pb, qb, obs, d, T, w0, w1);
       double pq = 0.0;
       for (long long f = threadIdx.x; f < n; f += kSmallThreads) {
         const double L1 = g1[f] + g2[f], L2 = g1[f] - g2[f];
@@ -369,11 +451,25 @@ bool small_supported(int n1, int n2, int n3) {
          n3 <= kSmallMaxExtent;
 }
 
+namespace {
+// complex buffers of the transforms: the spectrum, and a scratch copy when
+// an extent has no register pass
+int spectrum_buffers(int n1, int n2, int n3) {
+  const auto reg = [](int L) { return L == 1 || reg_length(L); };
+  return reg(n1) && reg(n2) && reg(n3) ? 1 : 2;
+}
+bool spectrum_in_lds(int n1, int n2, int n3) {
+  const long long n = (long long)n1 * n2 * n3;
+  return (long long)spectrum_buffers(n1, n2, n3) * n * (long long)sizeof(cx<double>) <= kSmallLdsBytes;
+}
+}  // namespace
+
 size_t small_problem_bytes(int n1, int n2, int n3) {
   const long long n = (long long)n1 * n2 * n3;
-  const bool lds = n <= kSmallLdsPoints;
-  // SV_COUNT real arrays, and the two spectra when they do not sit in LDS
-  size_t b = sizeof(double) * (size_t)n * (size_t)SV_COUNT + (lds ? 0 : 2 * sizeof(cx<double>) * (size_t)n);
+  const bool lds = spectrum_in_lds(n1, n2, n3);
+  // SV_COUNT real arrays, and the spectrum buffers when they do not sit in LDS
+  size_t b = sizeof(double) * (size_t)n * (size_t)SV_COUNT +
+             (lds ? 0 : (size_t)spectrum_buffers(n1, n2, n3) * sizeof(cx<double>) * (size_t)n);
   return (b + 255) & ~(size_t)255;
 }
 
@@ -381,16 +477,21 @@ hipError_t small_launch(int n1, int n2, int n3, int count, const double* signals
                         const double* lambdas, double lambda_frac, double* beta_out, double* info, char* ws,
                         const cx<double>* tw, const SmallOpts& o, hipStream_t s) {
   const long long n = (long long)n1 * n2 * n3;
-  const bool lds = n <= kSmallLdsPoints;
-  const size_t shm = lds ? 2 * sizeof(cx<double>) * (size_t)n : 0;
+  const bool lds = spectrum_in_lds(n1, n2, n3);
+  const size_t shm = lds ? (size_t)spectrum_buffers(n1, n2, n3) * sizeof(cx<double>) * (size_t)n : 0;
+  const bool has32 = n1 == 32 || n2 == 32 || n3 == 32;
+  const void* kern = has32 ? (const void*)k_small_solve<32> : (const void*)k_small_solve<16>;
   if (shm > 65536) {
-    const hipError_t e =
-        hipFuncSetAttribute((const void*)k_small_solve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    const hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_small_solve, dim3(count), dim3(kSmallThreads), shm, s, n1, n2, n3, signals, observed, lambdas,
-                     lambda_frac, beta_out, info, ws, (long long)small_problem_bytes(n1, n2, n3), tw, o,
-                     lds ? 1 : 0);
+  const long long stride = (long long)small_problem_bytes(n1, n2, n3);
+  if (has32)
+    hipLaunchKernelGGL(k_small_solve<32>, dim3(count), dim3(kSmallThreads), shm, s, n1, n2, n3, signals, observed,
+                       lambdas, lambda_frac, beta_out, info, ws, stride, tw, o, lds ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_small_solve<16>, dim3(count), dim3(kSmallThreads), shm, s, n1, n2, n3, signals, observed,
+                       lambdas, lambda_frac, beta_out, info, ws, stride, tw, o, lds ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -21,13 +21,15 @@ def _batch(ws, lams=None, **kw):
     return csipm.solve_small_batch(sig, obs, lambdas=lams, **kw)
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 16), (9, 15, 7), (1, 16, 24), (8, 6, 5), (16, 16, 32)],
+@pytest.mark.parametrize("shape", [(16, 16, 16), (9, 15, 7), (1, 16, 24), (8, 6, 5), (16, 16, 32), (32, 8, 9),
+                                   (32, 32, 32), (24, 40, 12)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_small_batch_matches_oracle(shape):
     """Each problem of a batch reaches the oracle's LASSO solution (both
     stopped at rel_kkt 1e-11) with the oracle's interior-point iteration
-    count up to one; 16 x 16 x 32 keeps its spectra in the workspace
-    instead of LDS."""
+    count up to one.  The shapes cover the register pencils (2 to 32), the
+    direct DFTs of other lengths (with their scratch buffer), spectra in
+    LDS (up to 128 KB) and in the workspace (32^3, 24 x 40 x 12)."""
     if shape == (16, 16, 16):
         ws = [wl.grid16(s) for s in (1, 2, 3)]
     else:
