@@ -429,10 +429,12 @@ csipm_status csipm_pc_correction(csipm_ctx* ctx, double* d_c);
  * HIP events on the context's stream around each kernel, in launch order:
  * axis-1 inverse (with the m = 0 plane's mixing), axis-2 inverse, axis-3
  * c2r/mask/r2c, axis-2 forward, axis-1 forward with the m = 0 unmixing and
- * the K epilogue; and in ms_out[5] the average time of one K-apply over
- * `reps` more applies queued back to back between a single event pair
- * (no events between its kernels).  ms_out holds CSIPM_KAPPLY_PASSES + 1
- * values.  Synchronises.  CSIPM_EUNSUPPORTED for an odd N3 (whose K-apply
+ * the K epilogue; in ms_out[5] the average time of one K-apply over `reps`
+ * more applies replayed from one HIP graph between a single event pair (as
+ * a solve launches its PCG iterations; the direct-launch time when the
+ * graph cannot be recorded), and in ms_out[6] the same with the applies
+ * launched directly.  ms_out holds CSIPM_KAPPLY_PASSES + 2 values.
+ * Synchronises.  CSIPM_EUNSUPPORTED for an odd N3 (whose K-apply
  * is the full-spectrum transforms). */
 #define CSIPM_KAPPLY_PASSES 5
 csipm_status csipm_profile_kapply(csipm_ctx* ctx, int precision, int reps, double* ms_out);

@@ -370,13 +370,20 @@ class Problem:
         self._check(lib().csipm_captured(self._ctx, C.byref(n), cg, max_iters), "captured")
         return n.value, list(cg[:n.value])
 
-    def profile_kapply(self, precision: int, reps: int = 20):
+    def profile_kapply(self, precision: int, reps: int = 20, direct: bool = False):
         """Average milliseconds of each of the KAPPLY_PASSES K-apply kernels
-        (events around each), and of one whole K-apply among `reps` queued back
-        to back (one event pair): (list, float)."""
-        out = (C.c_double * (KAPPLY_PASSES + 1))()
+        (events around each), and of one whole K-apply among `reps` back to
+        back (one event pair; replayed from a HIP graph, or launched directly
+        with direct=True): (list, float)."""
+        ms, graph, launched = self.profile_kapply_all(precision, reps)
+        return ms, launched if direct else graph
+
+    def profile_kapply_all(self, precision: int, reps: int = 20):
+        """csipm_profile_kapply: (per-kernel ms, whole K-apply from a graph
+        replay, whole K-apply launched directly)."""
+        out = (C.c_double * (KAPPLY_PASSES + 2))()
         self._check(lib().csipm_profile_kapply(self._ctx, precision, reps, out), "profile_kapply")
-        return list(out[:KAPPLY_PASSES]), out[KAPPLY_PASSES]
+        return list(out[:KAPPLY_PASSES]), out[KAPPLY_PASSES], out[KAPPLY_PASSES + 1]
 
     def timing(self, enable: bool):
         """Start (clearing earlier records) or stop per-kernel event timing."""

@@ -1585,7 +1585,7 @@ csipm_status csipm_profile_kapply(csipm_ctx* c, int precision, int reps, double*
   for (auto& e : ev)
     if (hipEventCreate(&e) != hipSuccess) return fail(c, CSIPM_EHIP, "hipEventCreate");
   double acc[CSIPM_KAPPLY_PASSES] = {0};
-  double whole = 0.0;
+  double whole = 0.0, direct = 0.0;
   auto run = [&](auto tag) {
     using T = decltype(tag);
     PcgSet v = pcg_set<T>(c);
@@ -1613,19 +1613,51 @@ csipm_status csipm_profile_kapply(csipm_ctx* c, int precision, int reps, double*
         acc[k] += ms;
       }
     }
-    // the same K-apply back to back, one event pair around all reps
+    // the same K-apply back to back, one event pair around all reps:
+    // launched directly, and replayed from a HIP graph of the reps applies
+    // (as a solve launches its PCG iterations)
     (void)hipEventRecord(ev[0], c->s);
     for (int r = 0; r < reps; ++r) (void)op_K<T>(c, pb, pz, s1, s2, qb, qz, work, nullptr);
     (void)hipEventRecord(ev[1], c->s);
     (void)hipEventSynchronize(ev[1]);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
-    whole = (double)ms / reps;
+    direct = (double)ms / reps;
+    whole = direct;
+    if (!c->cap_s && hipStreamCreateWithFlags(&c->cap_s, hipStreamNonBlocking) != hipSuccess) c->cap_s = nullptr;
+    if (c->cap_s) {
+      hipStream_t s0 = c->s;
+      c->s = c->cap_s;
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      bool ok = hipStreamBeginCapture(c->cap_s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        for (int r = 0; r < reps; ++r) (void)op_K<T>(c, pb, pz, s1, s2, qb, qz, work, nullptr);
+        ok = hipStreamEndCapture(c->cap_s, &graph) == hipSuccess && graph;
+      }
+      c->s = s0;
+      if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      if (graph) (void)hipGraphDestroy(graph);
+      if (ok) {
+        (void)hipGraphLaunch(exec, c->s);   // (first replay uploads the graph)
+        (void)hipEventRecord(ev[0], c->s);
+        (void)hipGraphLaunch(exec, c->s);
+        (void)hipEventRecord(ev[1], c->s);
+        (void)hipEventSynchronize(ev[1]);
+        ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+        whole = (double)ms / reps;
+      } else {
+        (void)hipGetLastError();
+      }
+      if (exec) (void)hipGraphExecDestroy(exec);
+    }
   };
   if (precision == CSIPM_FP64) run(double{}); else run(float{});
   for (auto& e : ev) (void)hipEventDestroy(e);
   for (int k = 0; k < CSIPM_KAPPLY_PASSES; ++k) ms_out[k] = acc[k] / reps;
   ms_out[CSIPM_KAPPLY_PASSES] = whole;
+  ms_out[CSIPM_KAPPLY_PASSES + 1] = direct;
   return hip_check(c, "profile_kapply");
 }
 

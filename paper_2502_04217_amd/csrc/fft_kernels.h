@@ -276,16 +276,6 @@ constexpr int mixed_e(int L) {
 constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 
 // ------------------------------------------------------- block reduction --
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 // Block sums of NQ values; thread 0 writes out[q * stride + blockIdx.x].
 // `red` is LDS scratch of at least NQ * NTHREADS/64 doubles; it may alias the

@@ -22,11 +22,6 @@ constexpr int kGateBlocks = 1024;   // workgroups listing the coefficients where
 __device__ __forceinline__ long long gtid() { return blockIdx.x * (long long)blockDim.x + threadIdx.x; }
 __device__ __forceinline__ long long gstride() { return (long long)gridDim.x * blockDim.x; }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // tanh in float32 to ~2e-7 relative: an odd polynomial (least-squares fit
 // of tanh(x)/x in x^2 on [0, 0.55]) below 0.55, 1 - 2/(exp(2|x|) + 1) above.

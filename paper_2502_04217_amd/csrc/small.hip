@@ -38,24 +38,9 @@ struct SmallDims {
 
 // ------------------------------------------------------- block reductions --
 // (every thread of the workgroup calls these; red holds kSmallWaves doubles)
-__device__ __forceinline__ double wave_sum_s(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max_s(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_min_s(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
 // op 0: sum, 1: max, 2: min; the waves' values combined in wave order
 __device__ double block_reduce(double v, int op, double* red) {
-  v = op == 0 ? wave_sum_s(v) : op == 1 ? wave_max_s(v) : wave_min_s(v);
+  v = op == 0 ? wave_sum(v) : op == 1 ? wave_max(v) : wave_min(v);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) red[wv] = v;

@@ -201,3 +201,19 @@ def test_errors():
     with pytest.raises(csipm.CsipmError) as e:
         pr.solve(tau=1.5)
     assert e.value.status in (-1, -6)
+
+
+def test_profile_kapply_times():
+    """csipm_profile_kapply: five positive per-kernel times, the graph-replayed
+    and directly launched whole K-apply, and EUNSUPPORTED for an odd N3."""
+    torch, csipm, pr, sig, obs = _problem((64, 64, 64), 4)
+    for prec in (csipm.FP64, csipm.FP32):
+        ms, graph, launched = pr.profile_kapply_all(prec, 4)
+        say("profile_kapply", prec, ms, graph, launched)
+        assert len(ms) == 5 and all(m > 0 for m in ms)
+        assert graph > 0 and launched > 0
+        assert graph <= 1.5 * launched
+    _, _, pr3, _, _ = _problem((8, 8, 15), 4)
+    with pytest.raises(csipm.CsipmError) as e:
+        pr3.profile_kapply_all(csipm.FP32, 2)
+    assert e.value.status == -5
