@@ -65,12 +65,12 @@ def init_params(seed: int = 0, out_scale: float = 0.01):
     return p.astype(np.float32)
 
 
-def collect(seeds, n_per_iter=4096, max_iters=80, policy=True, log=print):
+def collect(seeds, n_per_iter=4096, max_iters=80, policy=True, periods=(8, 16, 32), log=print):
     import torch
     feats, recs = [], []
     t0 = time.time()
     for s in seeds:
-        w = wl.grid128_family(s)
+        w = wl.grid128_family(s, periods)
         pr = csipm.Problem(w.signal, w.observed)
         pr.lambda_rule(0.05)
         feat = torch.empty((max_iters * n_per_iter, 4), dtype=torch.float32, device="cuda")
@@ -210,6 +210,8 @@ def main():
     ap.add_argument("--params-in", default=PARAMS_FILE, help="parameters evaluated by --eval-only")
     ap.add_argument("--params-out", default=PARAMS_FILE)
     ap.add_argument("--md", help="also write the per-seed evaluation as markdown to this path")
+    ap.add_argument("--periods", type=int, nargs="+", default=[8, 16, 32],
+                    help="lattice periods of the training problems (the evaluation family keeps 8, 16, 32)")
     args = ap.parse_args()
     command = "python -m paper_2502_04217_amd.learn " + " ".join(sys.argv[1:])
     log = lambda *a: print(*a, flush=True)
@@ -232,7 +234,8 @@ def main():
                 f.write(markdown(rows, summ, command, note))
         return 0
     t0 = time.time()
-    feats, recs = collect(list(TRAIN_SEEDS)[:args.train], policy=not args.all_iterations, log=log)
+    feats, recs = collect(list(TRAIN_SEEDS)[:args.train], policy=not args.all_iterations,
+                          periods=tuple(args.periods), log=log)
     log(f"[collect] {len(feats)} record groups in {time.time() - t0:.0f} s")
     l0 = baseline_loss(feats, recs)
     t1 = time.time()
@@ -242,7 +245,7 @@ def main():
     with open(args.params_out, "w") as f:
         json.dump({"params": params.cpu().tolist(), "train_seeds": [0, args.train], "epochs": args.epochs,
                    "lr": args.lr, "loss_untrained": l0, "loss_trained": hist[-1],
-                   "capture": "all iterations" if args.all_iterations else "policy",
+                   "capture": "all iterations" if args.all_iterations else "policy", "periods": args.periods,
                    "record_groups": len(feats), "command": command}, f)
     rows = evaluate(params, list(EVAL_SEEDS)[:args.eval], log=log)
     summ = summarize(rows)

@@ -195,14 +195,15 @@ def grid256(seed: int = 1) -> Workload:
                          name=f"grid256-s{seed}")
 
 
-def grid128_family(seed: int) -> Workload:
+def grid128_family(seed: int, periods=(8, 16, 32)) -> Workload:
     """128^3 training/evaluation family: sparsity log-uniform in [0.05%, 0.5%]
     of the DFT bins, SNR uniform in [5, 20] dB, lattice period drawn from
-    {8, 16, 32} with cube half-width log2(P) - 2, N(0,1) parts."""
+    `periods` ({8, 16, 32} for the evaluation family) with cube half-width
+    log2(P) - 2, N(0,1) parts."""
     rng = np.random.default_rng(10_000_019 + seed)
     frac = math.exp(rng.uniform(math.log(5e-4), math.log(5e-3)))
     snr = float(rng.uniform(5.0, 20.0))
-    period = int(rng.choice([8, 16, 32]))
+    period = int(rng.choice(list(periods)))
     hw = int(math.log2(period)) - 2
     shape = (128, 128, 128)
     return make_workload(shape, n_freq=int(round(frac * 128 ** 3)), amplitude="normal",
