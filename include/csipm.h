@@ -11,16 +11,18 @@
  * formulation", equations "beta", "v", derivation "map").
  *
  * Conventions shared by every entry point
- *  - Grid: N1 x N2 x N3, each a power of two in [4, 1024] or one of the
- *    extents with odd factors 12, 20, 24, 28, 40, 48, 56, 70, 96, 192, 384,
- *    560 (the FFT passes have radix-3, -5 and -7 stages); N1 and N2 may
- *    also be 1 or 2, so a 2D problem is the grid 1 x N2 x N3 and a 1D one
- *    1 x 1 x N3.  Any axis may be odd: 3, 5, 7, 9, 15, 21, 35, 45 (the
- *    odd-N case of the parametrisation, section "Problem formulation": no
- *    Nyquist index on that axis; an odd N3 runs the transforms on the whole
- *    spectrum, with twice the bytes of the half-spectrum passes, and when
- *    N1*N2*N3 is odd the library adds internally one coordinate with no data,
- *    a zero column of A, which the solution sets to 0).  n = N1*N2*N3.
+ *  - Grid: N1 x N2 x N3, each a product 2^a 3^b 5^c 7^d in [3, 1024] (the
+ *    FFT passes have radix-2^k, -3, -5 and -7 stages: register-resident
+ *    kernels for the powers of two, the paper's sizes 96, 192, 384, 560 and
+ *    the small extents 12-70, 3-45 that have them; kernels holding the
+ *    pencils in LDS, with a radix plan computed at launch, for the rest);
+ *    N1 and N2 may also be 1 or 2, so a 2D problem is the grid 1 x N2 x N3
+ *    and a 1D one 1 x 1 x N3.  Any axis may be odd (the odd-N case of the
+ *    parametrisation, section "Problem formulation": no Nyquist index on
+ *    that axis; an odd N3 runs the transforms on the whole spectrum, with
+ *    twice the bytes of the half-spectrum passes, and when N1*N2*N3 is odd
+ *    the library adds internally one coordinate with no data, a zero column
+ *    of A, which the solution sets to 0).  n = N1*N2*N3.
  *    Other extents return CSIPM_EUNSUPPORTED.
  *  - Real-space arrays are row-major [N1][N2][N3] (index j3 fastest).
  *  - beta-space arrays ("external beta layout") are row-major [N1][N2][N3]

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcsipm.so")
-SOURCES = ["fft.hip", "fft_mixed_f64.hip", "fft_mixed_f32.hip", "vec.hip", "mlp.hip", "capi.hip", "noalloc.hip", "small.hip"]
+SOURCES = ["fft.hip", "fft_mixed_f64.hip", "fft_mixed_f32.hip", "fft_any.hip", "vec.hip", "mlp.hip", "capi.hip", "noalloc.hip", "small.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]

@@ -280,10 +280,11 @@ void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t*
 // forward pass also its partial count
 int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir);
 // whether the FFT passes have kernels for extent N on `axis` (1, 2: pencils
-// of length N; 3: half length N/2 for an even N): powers of two in
-// [4, 1024], the extents with odd factors that fft_mixed_f64/f32.hip
-// instantiate, the odd extents 3-45 on every axis (an odd N3 takes the
-// full-spectrum transforms), and on axes 1 and 2 also 1 and 2 (2D and 1D
+// of length N; 3: half length N/2 for an even N, full length for an odd N,
+// which takes the full-spectrum transforms): every N = 2^a 3^b 5^c 7^d in
+// [3, 1024] (instantiated register-resident kernels for the powers of two
+// and the lengths fft_mixed_f64/f32.hip list, the LDS-resident kernels of
+// fft_any.hip for the rest), and on axes 1 and 2 also 1 and 2 (2D and 1D
 // grids)
 bool fft_extent_supported(int N, int axis);
 

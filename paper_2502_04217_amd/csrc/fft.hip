@@ -15,7 +15,7 @@
 //              with the K epilogue q = K p and the p.q partial sums
 // The pencil FFT kernels (Stockham stages, fft_kernels.h) are instantiated
 // here for power-of-two lengths and in fft_mixed_f64/f32.hip for lengths with odd
-// factors.  Strided passes map consecutive lanes to consecutive pencils, so
+// factors; fft_any.hip serves the other 7-smooth lengths.  Strided passes map consecutive lanes to consecutive pencils, so
 // every global access is a run of TM contiguous complex numbers.
 #include "fft_kernels.h"
 
@@ -123,7 +123,8 @@ void launch_axis12_L(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom
     CSIPM_A12(512)
     CSIPM_A12(1024)
     default:
-      (void)launch_axis12_mixed<T, AX, DIR, Epi>(L, grid, src, dst, geo, tw, m, n2, epi, skip, s);
+      if (!launch_axis12_mixed<T, AX, DIR, Epi>(L, grid, src, dst, geo, tw, m, n2, epi, skip, s))
+        (void)launch_axis12_any<T, AX, DIR, Epi>(L, grid, src, dst, geo, tw, m, n2, epi, skip, s);
       break;
   }
 #undef CSIPM_A12
@@ -275,7 +276,7 @@ void cp_pass(int L, int inner, long long outer, long long estride, int batch, cx
   geo.outer = outer;
   geo.estride = estride;
   geo.batch = batch;
-  const int tm = strided_tm(int(sizeof(cx<T>)), L, 2, DIR);
+  const int tm = pass_tm(int(sizeof(cx<T>)), L, 2, DIR);
   launch_axis12_L<T, 2, DIR>(L, dim3((batch + tm - 1) / tm), w, w, geo, tw, 1, 1, EpiNone{}, skip, s);
 }
 
@@ -286,7 +287,7 @@ void cp_pass(int L, int inner, long long outer, long long estride, int batch, cx
 int axis12_tiles(const Grid& g, int axis, int elem_bytes, int dir) {
   const int L = axis == 1 ? g.n1 : g.n2;
   const int batch = axis == 1 ? g.n2 * g.m : g.n1 * g.m;
-  const int tm = strided_tm(elem_bytes, L, axis, dir);
+  const int tm = pass_tm(elem_bytes, L, axis, dir);
   return (batch + tm - 1) / tm;
 }
 
@@ -295,15 +296,13 @@ int axis12_blocks(const Grid& g, int axis, int elem_bytes, int dir) {
 }
 
 bool fft_extent_supported(int N, int axis) {
-  if (axis != 3 && (N == 1 || N == 2)) return true;
-#define CSIPM_IS_ODD(NN) if (N == NN) return true;
-  CSIPM_ODD_LENGTHS(CSIPM_IS_ODD)
-#undef CSIPM_IS_ODD
-  if (N >= 4 && N <= 1024 && (N & (N - 1)) == 0) return true;
-#define CSIPM_IS(NN) if (N == NN) return true;
-  CSIPM_MIXED_LENGTHS(CSIPM_IS)
-#undef CSIPM_IS
-  return false;
+  AnyPlan pl;
+  if (N > kAnyMaxLen) return false;
+  if (axis != 3) return N >= 1 && (templated12(N) || any_plan(N, pl));
+  // an odd N3 takes full-length complex pencils, an even one half-length
+  // pencils of the real transforms
+  if (N % 2 == 1) return N >= 3 && (templated12(N) || any_plan(N, pl));
+  return N >= 4 && (templated3(N / 2) || any_plan(N / 2, pl));
 }
 
 template <typename T>
@@ -365,7 +364,8 @@ void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t*
     CSIPM_A3(256)
     CSIPM_A3(512)
     default:
-      (void)launch_axis3_mixed<T>(L, mode, np, cs, cd, maskbits, tw.tm, tw.t3, sc_c2r, sc_dc, sc_ac, skip, s);
+      if (!launch_axis3_mixed<T>(L, mode, np, cs, cd, maskbits, tw.tm, tw.t3, sc_c2r, sc_dc, sc_ac, skip, s))
+        (void)launch_axis3_any<T>(L, mode, np, cs, cd, maskbits, tw.tm, tw.t3, sc_c2r, sc_dc, sc_ac, skip, s);
       break;
   }
 #undef CSIPM_A3

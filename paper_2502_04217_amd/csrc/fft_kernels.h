@@ -2,7 +2,9 @@
 // instantiates them for power-of-two pencil lengths, fft_mixed_f64.hip and
 // fft_mixed_f32.hip for lengths with odd factors 3, 5 and 7 (the
 // non-power-of-two grids of the paper's synthetic size table, small grids
-// that exercise each radix, and odd extents on axes 1 and 2).
+// that exercise each radix, and odd extents on axes 1 and 2); fft_any.hip
+// serves the other lengths 2^a 3^b 5^c 7^d up to 1024 through the same
+// helpers.
 //
 // Each pencil FFT is a Stockham sequence of radix-r stages: the first stage
 // reads its inputs straight from global memory into registers, intermediate
@@ -496,6 +498,134 @@ struct Plane0 {
   int ndedicated;   // workgroups in front of the tiles (forward axis-1 pass: 1)
 };
 
+// The pencil a lane of a strided pass transforms (pencil p of the
+// workgroup's TM) and its part in the m = 0 plane (axis 1).
+struct Lane12 {
+  long long base;   // offset of the pencil's element 0
+  int k2;           // row of an m = 0 lane
+  bool active;      // the lane has a pencil
+  bool m0;          // the pencil lies in the m = 0 plane
+  bool canon;       // an m = 0 lane of a canonical row (or the even lane of a self-paired one)
+  bool ded;         // the workgroup of the self-paired rows (forward axis-1 pass)
+};
+template <int AX, int DIR, typename T>
+__device__ __forceinline__ Lane12 lane12(int p, int TM, const StridedGeom<T>& geo, int m, const Plane0& pl) {
+  constexpr bool MIX = AX == 1;
+  Lane12 ln;
+  ln.ded = MIX && DIR < 0 && (int)blockIdx.x < pl.ndedicated;
+  ln.k2 = 0;
+  ln.canon = true;
+  ln.m0 = false;
+  int qpen;
+  if (MIX && ln.ded) {
+    ln.k2 = plane0_self_row(p, pl.n2);
+    ln.active = ln.k2 >= 0;
+    ln.m0 = true;
+    ln.canon = (p & 1) == 0;
+    qpen = ln.active ? ln.k2 * m : 0;
+  } else {
+    qpen = ((int)blockIdx.x - (MIX ? pl.ndedicated : 0)) * TM + p;
+    ln.active = qpen < geo.batch;
+    if (MIX && ln.active && qpen % m == 0) {
+      ln.m0 = true;
+      ln.k2 = qpen / m;
+      ln.canon = 2 * ln.k2 < pl.n2;
+      if (DIR < 0 && self_paired_row(ln.k2, pl.n2)) ln.active = false;   // (taken by the first workgroup)
+    }
+  }
+  ln.base = ln.active ? (long long)(qpen / geo.inner) * geo.outer + (qpen % geo.inner) : 0;
+  return ln;
+}
+
+// The partner rows of the workgroup's m = 0 lanes, reversed (element e of
+// slot r holds element -e of slot r's partner row; with the direction
+// update applied), staged in lds by all nthr threads, so that each thread
+// loads at most a few of them instead of the m = 0 lanes each waiting on a
+// row of scattered loads.  Slot r holds the partner of row first + r, for
+// the rows whose m = 0 pencil falls in the tile (pencils q0 .. q0 + TM - 1);
+// in the forward pass's first workgroup lanes 0-3 are the slots (partner =
+// own row).  Returns the slot count (uniform over the workgroup; 0: no
+// m = 0 lane, nothing staged and no barrier) and the lane's slot.
+template <typename T, int DIR, class Epi>
+__device__ __forceinline__ int stage_partners(cx<T>* lds, const cx<T>* src, int L, int TM, int nthr,
+                                              const StridedGeom<T>& geo, int m, const Plane0& pl, const Epi& epi,
+                                              bool upd, T be, bool ded, int p, int& slot) {
+  const int q0 = ded ? 0 : ((int)blockIdx.x - pl.ndedicated) * TM;
+  const int first = ded ? 0 : (q0 + m - 1) / m;
+  const int nslot = ded ? 4 : (q0 + TM - 1) / m + 1 - first;
+  slot = ded ? p : (q0 + p) / m - first;
+  if (nslot <= 0) return nslot;
+  for (int j = threadIdx.x; j < nslot * L; j += nthr) {
+    const int r = j / L, i = j % L;
+    int row;
+    if (ded) {
+      row = plane0_self_row(r, pl.n2);
+    } else {
+      row = first + r;
+      if (row >= pl.n2 || (DIR < 0 && self_paired_row(row, pl.n2))) row = -1;
+    }
+    // (each branch stores its own value: a value merged across the branches
+    // was kept in scratch memory)
+    if (row >= 0) {
+      const int prow = ded ? row : (pl.n2 - row) % pl.n2;
+      const long long i1 = (long long)prow * m + (long long)((L - i) % L) * geo.estride;
+      cx<T> y = src[i1];
+      if constexpr (Epi::PRO) {
+        if (upd) {
+          const cx<T> zb = epi.z[i1];
+          y = {zb.re + be * y.re, zb.im + be * y.im};
+        }
+      }
+      lds[j] = y;
+    } else {
+      lds[j] = cx<T>{T(0), T(0)};
+    }
+  }
+  __syncthreads();
+  return nslot;
+}
+
+// Element e of an m = 0 lane's pencil x mixed with its staged partner y:
+// on the inverse pass's input (U from the stored W), or the forward pass's
+// unmixing applied to its input.
+template <typename T, int DIR>
+__device__ __forceinline__ cx<T> plane0_mix(cx<T> x, cx<T> y, int e, const Lane12& ln, int L, int n2) {
+  const T rs2 = T(0.70710678118654752440);
+  if constexpr (DIR > 0) {
+    const int c = cls2(e, ln.k2, L, n2);
+    return c == 0 ? x : (c == 1 ? cscale(cadd(x, cmul_i<1>(y)), rs2) : cscale(csub(y, cmul_i<1>(x)), rs2));
+  } else {
+    return ln.canon ? cscale(cadd(x, y), rs2) : cscale(cmul_i<1>(csub(x, y)), rs2);
+  }
+}
+
+// Whether the lane writes output element e: the self-paired rows' lanes
+// write the elements of their class (the self-conjugate ones scaled).
+template <int AX, int DIR, typename T>
+__device__ __forceinline__ bool plane0_keep(int e, cx<T>& h, const Lane12& ln, int L, int n2) {
+  if (!(AX == 1 && DIR < 0 && ln.ded)) return true;
+  const int c = cls2(e, ln.k2, L, n2);
+  if (c == 0 && ln.canon) h = cscale(h, T(0.70710678118654752440));
+  return ln.canon ? c != 2 : c == 2;
+}
+
+// Element idx of the input, with the fused direction update p <- z + beta p
+// (written back outside the m = 0 plane: a partner row may still need the
+// old value; the forward pass's K epilogue writes it).
+template <typename T, class Epi>
+__device__ __forceinline__ cx<T> load_input(const cx<T>* src, long long idx, bool active, bool upd, T be,
+                                            const Epi& epi, bool keep_p) {
+  cx<T> x = active ? src[idx] : cx<T>{T(0), T(0)};
+  if constexpr (Epi::PRO) {
+    if (upd && active) {
+      const cx<T> zv = epi.z[idx];
+      x = {zv.re + be * x.re, zv.im + be * x.im};
+      if (!keep_p) epi.p[idx] = x;
+    }
+  }
+  return x;
+}
+
 template <typename T, int L, int AX, int DIR, class Epi>
 __global__ void __launch_bounds__((strided_threads<T, L, AX, DIR>()))
 k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
@@ -512,29 +642,7 @@ k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int p = threadIdx.x % TM;
   const int t = threadIdx.x / TM;
-  const T rs2 = T(0.70710678118654752440);
-  // the forward pass's workgroup of the self-paired rows (uniform per workgroup)
-  const bool ded = MIX && DIR < 0 && (int)blockIdx.x < pl.ndedicated;
-  int k2 = 0;
-  bool canon = true, m0 = false, active;
-  int qpen;
-  if (MIX && ded) {
-    k2 = plane0_self_row(p, pl.n2);
-    active = k2 >= 0;
-    m0 = true;
-    canon = (p & 1) == 0;
-    qpen = active ? k2 * m : 0;
-  } else {
-    qpen = ((int)blockIdx.x - (MIX ? pl.ndedicated : 0)) * TM + p;
-    active = qpen < geo.batch;
-    if (MIX && active && qpen % m == 0) {
-      m0 = true;
-      k2 = qpen / m;
-      canon = 2 * k2 < pl.n2;
-      if (DIR < 0 && self_paired_row(k2, pl.n2)) active = false;   // (taken by the first workgroup)
-    }
-  }
-  const long long base = active ? (long long)(qpen / geo.inner) * geo.outer + (qpen % geo.inner) : 0;
+  const Lane12 ln = lane12<AX, DIR>(p, TM, geo, m, pl);
 
   cx<T> v[VM];
   bool upd = false;
@@ -544,101 +652,39 @@ k_axis12(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo,
     if (upd) be = (T)*epi.beta;
   }
   for_stage_io<L, E, 0>(t, [&](int s, int e) {
-    const long long idx = base + (long long)e * geo.estride;
-    cx<T> x = active ? src[idx] : cx<T>{T(0), T(0)};
-    if constexpr (Epi::PRO) {
-      // (an m = 0 lane does not write p back: its partner row may still
-      // need the old value; the forward pass's K epilogue writes it)
-      if (upd && active) {
-        const cx<T> zv = epi.z[idx];
-        x = {zv.re + be * x.re, zv.im + be * x.im};
-        if (!(MIX && m0)) epi.p[idx] = x;
-      }
-    }
-    v[s] = x;
+    v[s] = load_input(src, ln.base + (long long)e * geo.estride, ln.active, upd, be, epi, MIX && ln.m0);
   });
-  // The partner rows of the workgroup's m = 0 lanes, reversed (element e of
-  // slot r holds element -e of slot r's partner row; with the direction
-  // update applied), are staged in the tile's LDS, which the FFT stages do
-  // not use before their first exchange: every thread loads at most a few
-  // of them while its own loads are in flight, instead of the m = 0 lanes
-  // each waiting on a row of scattered loads; the m = 0 lanes then mix.
-  // Slot r holds the partner of row first + r, for the rows whose m = 0
-  // pencil falls in the tile (pencils q0 .. q0 + TM - 1); in the forward
-  // pass's first workgroup lanes 0-3 are the slots (partner = own row).
+  // (the partner rows go to the tile's LDS, which the FFT stages do not use
+  // before their first exchange, while the lanes' own loads are in flight)
   if constexpr (MIX) {
-    const int q0 = ded ? 0 : ((int)blockIdx.x - pl.ndedicated) * TM;
-    const int first = ded ? 0 : (q0 + m - 1) / m;
-    const int nslot = ded ? 4 : (q0 + TM - 1) / m + 1 - first;
-    if (nslot > 0) {
-      constexpr int NTHR = TM * NT;
-      for (int j = threadIdx.x; j < nslot * L; j += NTHR) {
-        const int r = j / L, i = j % L;
-        int row;
-        if (ded) {
-          row = plane0_self_row(r, pl.n2);
-        } else {
-          row = first + r;
-          if (row >= pl.n2 || (DIR < 0 && self_paired_row(row, pl.n2))) row = -1;
-        }
-        cx<T> y = {T(0), T(0)};
-        if (row >= 0) {
-          const int prow = ded ? row : (pl.n2 - row) % pl.n2;
-          const long long i1 = (long long)prow * m + (long long)((L - i) % L) * geo.estride;
-          y = src[i1];
-          if constexpr (Epi::PRO) {
-            if (upd) {
-              const cx<T> zb = epi.z[i1];
-              y = {zb.re + be * y.re, zb.im + be * y.im};
-            }
-          }
-        }
-        lds[j] = y;
-      }
-      __syncthreads();
-      if (m0 && active) {
-        const int slot = ded ? p : (q0 + p) / m - first;
-        for_stage_io<L, E, 0>(t, [&](int s, int e) {
-          const cx<T> x = v[s];
-          const cx<T> y = lds[slot * L + e];
-          if constexpr (DIR > 0) {
-            const int c = cls2(e, k2, L, pl.n2);
-            v[s] = c == 0 ? x
-                          : (c == 1 ? cscale(cadd(x, cmul_i<1>(y)), rs2) : cscale(csub(y, cmul_i<1>(x)), rs2));
-          } else {
-            v[s] = canon ? cscale(cadd(x, y), rs2) : cscale(cmul_i<1>(csub(x, y)), rs2);
-          }
-        });
-      }
+    int slot;
+    if (stage_partners<T, DIR>(lds, src, L, TM, TM * NT, geo, m, pl, epi, upd, be, ln.ded, p, slot) > 0 &&
+        ln.m0 && ln.active) {
+      for_stage_io<L, E, 0>(t, [&](int s, int e) {
+        v[s] = plane0_mix<T, DIR>(v[s], lds[slot * L + e], e, ln, L, pl.n2);
+      });
     }
   }
   auto lidx = [p](int e) { return e * TM + p; };
   fft_stages<T, L, E, DIR, 0>(v, t, lds, lidx, tw);
 
-  // the self-paired rows' lanes write the elements of their class
-  auto keep = [&](int e, cx<T>& h) {
-    if (!(MIX && DIR < 0 && ded)) return true;
-    const int c = cls2(e, k2, L, pl.n2);
-    if (c == 0 && canon) h = cscale(h, rs2);
-    return canon ? c != 2 : c == 2;
-  };
   if constexpr (Epi::NRED > 0) {
     double acc[Epi::NRED];
 #pragma unroll
     for (int q = 0; q < Epi::NRED; ++q) acc[q] = 0.0;
-    if (active) {
+    if (ln.active) {
       for_stage_io<L, E, SL>(t, [&](int s, int e) {
         cx<T> h = v[s];
-        if (keep(e, h)) epi(base + (long long)e * geo.estride, h, acc, MIX && m0);
+        if (plane0_keep<AX, DIR>(e, h, ln, L, pl.n2)) epi(ln.base + (long long)e * geo.estride, h, acc, MIX && ln.m0);
       });
     }
     block_sums_store<TM * NT, Epi::NRED, Epi::NMAX>(acc, epi.partial, epi.pstride,
                                                     reinterpret_cast<double*>(smem_raw));
   } else {
-    if (active) {
+    if (ln.active) {
       for_stage_io<L, E, SL>(t, [&](int s, int e) {
         cx<T> h = v[s];
-        if (keep(e, h)) dst[base + (long long)e * geo.estride] = h;
+        if (plane0_keep<AX, DIR>(e, h, ln, L, pl.n2)) dst[ln.base + (long long)e * geo.estride] = h;
       });
     }
   }
@@ -693,6 +739,45 @@ constexpr int a3_pp(int L) {
   return pp;
 }
 
+// The real transforms of length N3 = 2L through a half-length complex FFT
+// (z_e = x[2e] + i x[2e+1]).  With the half spectrum X_e (e < L; X_0 packs
+// the DC and Nyquist values as (re, im)) and w = exp(-2 pi i e / N3):
+// the inverse transform's input Z_e = A + conj(B) + i w* (A - conj(B)) with
+// A = X_e / sqrt2, B = X_{L-e} / sqrt2, and Z_0 = (X_0.re + X_0.im,
+// X_0.re - X_0.im); the forward transform's output from its half-length
+// result Z: X_e = ((Z_e + conj Z_{L-e}) - i w (Z_e - conj Z_{L-e})) / 2,
+// X_0 = (Z_0.re + Z_0.im, Z_0.re - Z_0.im); each scaled.
+template <typename T>
+__device__ __forceinline__ cx<T> c2r_dc(cx<T> x0) { return {x0.re + x0.im, x0.re - x0.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> c2r_pack(cx<T> xe, cx<T> xle, cx<T> w) {
+  const T rs2 = T(0.70710678118654752440);
+  const cx<T> a = cscale(xe, rs2);
+  const cx<T> b = cconj(cscale(xle, rs2));
+  const cx<T> sm = cadd(a, b);
+  const cx<T> d = csub(a, b);
+  w.im = -w.im;   // exp(+2 pi i e / N3)
+  return cadd(sm, cmul_i<1>(cmul(w, d)));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> r2c_dc(cx<T> z0, T sc) { return {(z0.re + z0.im) * sc, (z0.re - z0.im) * sc}; }
+template <typename T>
+__device__ __forceinline__ cx<T> r2c_unpack(cx<T> a, cx<T> zle, cx<T> w, T sc) {
+  const cx<T> b = cconj(zle);
+  const cx<T> ev = cscale(cadd(a, b), T(0.5));
+  const cx<T> od = cscale(csub(a, b), T(0.5));
+  return cscale(cadd(ev, cmul_i<-1>(cmul(w, od))), sc);
+}
+// z = (x[2e], x[2e+1]) with the unobserved samples zeroed: bits sh and
+// sh + 1 of the mask word wd (the flat bit index of x[2e] is even, so both
+// samples share a word)
+template <typename T>
+__device__ __forceinline__ cx<T> mask_pair(cx<T> z, uint32_t wd, int sh) {
+  if (!((wd >> sh) & 1u)) z.re = T(0);
+  if (!((wd >> (sh + 1)) & 1u)) z.im = T(0);
+  return z;
+}
+
 // L = M = N3/2 complex values per pencil; pencil = (j1, j2).
 template <typename T, int L, int MODE>
 __global__ void __launch_bounds__(kA3Threads)
@@ -717,7 +802,6 @@ k_axis3(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask,
   const long long base = (long long)pen * L;
   cx<T>* lds = ldsall + p * LP;
   auto lidx = [](int e) { return e + (e >> 4); };
-  const T rs2 = T(0.70710678118654752440);
 
   cx<T> v[VM];
   if constexpr (MODE & A3_C2R) {
@@ -729,21 +813,7 @@ k_axis3(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask,
     }
     __syncthreads();
     for_stage_io<L, E, 0>(t, [&](int s, int e) {
-      cx<T> z;
-      if (e == 0) {
-        const cx<T> x0 = lds[lidx(0)];   // (DC, Nyquist)
-        z = {x0.re + x0.im, x0.re - x0.im};
-      } else {
-        const cx<T> a = cscale(lds[lidx(e)], rs2);
-        const cx<T> b = cconj(cscale(lds[lidx(L - e)], rs2));
-        const cx<T> sm = cadd(a, b);
-        const cx<T> d = csub(a, b);
-        cx<T> w = tw3[e];          // exp(-2 pi i e / N3)
-        w.im = -w.im;              // exp(+2 pi i e / N3)
-        const cx<T> id = cmul_i<1>(cmul(w, d));
-        z = cadd(sm, id);
-      }
-      v[s] = z;
+      v[s] = e == 0 ? c2r_dc(lds[lidx(0)]) : c2r_pack(lds[lidx(e)], lds[lidx(L - e)], tw3[e]);
     });
     fft_stages<T, L, E, +1, 0>(v, t, lds, lidx, twm);
     // z_e = x[2e] + i x[2e+1]
@@ -751,10 +821,7 @@ k_axis3(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask,
       cx<T> z = cscale(v[s], sc_c2r);
       if constexpr (MODE == A3_FULL) {
         const long long bit = (long long)pen * N3 + 2 * e;
-        const uint32_t wd = active ? mask[bit >> 5] : 0u;
-        const int sh = (int)(bit & 31);
-        if (!((wd >> sh) & 1u)) z.re = T(0);
-        if (!((wd >> (sh + 1)) & 1u)) z.im = T(0);
+        z = mask_pair(z, active ? mask[bit >> 5] : 0u, (int)(bit & 31));
       }
       v[s] = z;
     });
@@ -787,20 +854,7 @@ k_axis3(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask,
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int e = tf + q * NT;
-    cx<T> xo;
-    if (e == 0) {
-      const cx<T> z0 = lds[lidx(0)];
-      xo = {(z0.re + z0.im) * sc_r2c_dc, (z0.re - z0.im) * sc_r2c_dc};
-    } else {
-      const cx<T> a = lds[lidx(e)];
-      const cx<T> b = cconj(lds[lidx(L - e)]);
-      const cx<T> ev = cscale(cadd(a, b), T(0.5));
-      const cx<T> od = cscale(csub(a, b), T(0.5));
-      const cx<T> w = tw3[e];        // exp(-2 pi i e / N3)
-      const cx<T> t2 = cmul_i<-1>(cmul(w, od));
-      xo = cscale(cadd(ev, t2), sc_r2c);
-    }
-    dst[base + e] = xo;
+    dst[base + e] = e == 0 ? r2c_dc(lds[lidx(0)], sc_r2c_dc) : r2c_unpack(lds[lidx(e)], lds[lidx(L - e)], tw3[e], sc_r2c);
   }
 }
 
@@ -875,6 +929,48 @@ bool launch_axis3_mixed(int L, int mode, int np, const cx<T>* cs, cx<T>* cd, con
       return false;
   }
 #undef CSIPM_A3
+}
+
+// Lengths with instantiated kernels: strided pencils (axes 1 and 2, and
+// every axis of the odd-N3 transforms) and axis-3 half lengths.
+inline bool templated12(int L) {
+  if (L == 1 || L == 2 || (L >= 4 && L <= 1024 && (L & (L - 1)) == 0)) return true;
+#define CSIPM_IS(NN) if (L == NN) return true;
+  CSIPM_MIXED_LENGTHS(CSIPM_IS)
+  CSIPM_ODD_LENGTHS(CSIPM_IS)
+#undef CSIPM_IS
+  return false;
+}
+inline bool templated3(int L) {
+  if (L >= 2 && L <= 512 && (L & (L - 1)) == 0) return true;
+#define CSIPM_IS(NN) if (2 * L == NN) return true;
+  CSIPM_MIXED_LENGTHS(CSIPM_IS)
+#undef CSIPM_IS
+  return false;
+}
+
+// Every other length 2^a 3^b 5^c 7^d up to kAnyMaxLen: the passes with the
+// pencils in LDS and a radix plan computed at launch (fft_any.hip).
+constexpr int kAnyMaxLen = 1024;
+struct AnyPlan {
+  int L;        // pencil length
+  int nst;      // stages
+  int r[12];    // radix of each stage: 8, then 4 or 2, then 3, 5, 7
+};
+// false when L has a prime factor above 7 or lies outside [1, kAnyMaxLen]
+bool any_plan(int L, AnyPlan& pl);
+// pencils per 256-thread workgroup
+int any_tm(int L);
+template <typename T, int AX, int DIR, class Epi>
+bool launch_axis12_any(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* tw, int m,
+                       int n2, Epi epi, const int* skip, hipStream_t s);
+template <typename T>
+bool launch_axis3_any(int L, int mode, int np, const cx<T>* cs, cx<T>* cd, const uint32_t* maskbits,
+                      const cx<T>* twm, const cx<T>* tw3, T sc_c2r, T sc_dc, T sc_ac, const int* skip,
+                      hipStream_t s);
+// pencils per workgroup of the strided pass that serves length L
+inline int pass_tm(int w, int L, int axis, int dir) {
+  return templated12(L) ? strided_tm(w, L, axis, dir) : any_tm(L);
 }
 
 // The instances used: PREFIX is empty where they are compiled and `extern`

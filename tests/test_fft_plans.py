@@ -1,0 +1,179 @@
+"""The Stockham stage plans of the pencil FFT kernels, restated on the CPU
+(no GPU): for every length the register-resident kernels are instantiated
+at (csrc/fft_kernels.h: Radix<L, E> with the elements per thread of each
+pass) and every length 2^a 3^b 5^c 7^d up to 1024 of the LDS-resident passes
+(csrc/fft_any.hip: the plan computed at launch, TM pencils of NT threads),
+the stages, run in numpy with the kernels' butterfly indexing, give numpy's
+FFT in both directions; each stage's butterflies are all taken by some
+thread, and its outputs write every element exactly once."""
+import numpy as np
+import pytest
+
+
+def odd_part(x):
+    while x > 0 and x % 2 == 0:
+        x //= 2
+    return x
+
+
+def smallest_odd_factor(x):
+    p = 3
+    while p <= x:
+        if x % p == 0:
+            return p
+        p += 2
+    return x
+
+
+def odd_factors(F):
+    out = []
+    while F > 1:
+        p = smallest_odd_factor(F)
+        out.append(p)
+        F //= p
+    return out
+
+
+def radix_plan(L, E):
+    """Radix<L, E>: power-of-two stages of radix P2 (the power-of-two part of
+    E; 4 when E is odd), one remainder stage, then the odd prime factors."""
+    if L == 1:
+        return [1]
+    LP = L // odd_part(L)
+    P2 = E // odd_part(E) if E // odd_part(E) > 1 else min(LP, 4)
+    st, r = [], LP
+    while P2 > 1 and r >= P2:
+        st.append(P2)
+        r //= P2
+    if r > 1:
+        st.append(r)
+    return st + odd_factors(odd_part(L))
+
+
+def any_plan(L):
+    """The LDS-resident passes' plan: radix 8, then one 4 or 2, then 3, 5, 7."""
+    a, r = 0, L
+    while r % 2 == 0:
+        r //= 2
+        a += 1
+    st = [8] * (a // 3) + ([1 << (a % 3)] if a % 3 else [])
+    for f in (3, 5, 7):
+        while r % f == 0:
+            st.append(f)
+            r //= f
+    return st if r == 1 else None
+
+
+def any_tm(L):
+    tm = 256
+    while tm > 1 and tm * L > 4096:
+        tm //= 2
+    return tm
+
+
+def run_stages(x, plan, nthreads, nb_of, direction):
+    """The Stockham stages with the kernels' indexing: stage radix R, Ns the
+    product of the earlier radices; butterfly j (taken by thread j % nthreads
+    in round j // nthreads) reads elements j + q L/R, multiplies input q by
+    w^(jm q L/(Ns R)) (jm = j mod Ns, w = exp(-+2 pi i / L)), and writes its
+    DFT output q to (j - jm) R + jm + q Ns."""
+    L = len(x)
+    a = x.astype(np.complex128)
+    tw = np.exp(-2j * np.pi * np.arange(L) / L)
+    if direction > 0:
+        tw = tw.conj()
+    ns = 1
+    for R in plan:
+        nbf = L // R
+        assert nbf * R == L
+        # every butterfly has a thread in one of the stage's rounds
+        assert nb_of(R) * nthreads >= nbf, (L, R)
+        j = np.arange(nbf)
+        jm = j % ns
+        q = np.arange(R)
+        v = a[j[:, None] + q[None, :] * nbf]
+        v = v * tw[(jm[:, None] * q[None, :] * (L // (ns * R))) % L]
+        dft = np.exp(direction * 2j * np.pi * np.outer(q, q) / R)
+        y = v @ dft
+        dst = (j - jm)[:, None] * R + jm[:, None] + q[None, :] * ns
+        assert dst.min() >= 0 and dst.max() < L
+        assert np.array_equal(np.sort(dst.ravel()), np.arange(L)), "each element written once"
+        out = np.empty_like(a)
+        out[dst.ravel()] = y.ravel()
+        a = out
+        ns *= R
+    assert ns == L
+    return a
+
+
+def check_fft(L, plan, nthreads, nb_of):
+    rng = np.random.default_rng(L)
+    x = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+    scale = np.abs(np.fft.fft(x)).max()
+    assert np.abs(run_stages(x, plan, nthreads, nb_of, -1) - np.fft.fft(x)).max() <= 1e-12 * scale
+    assert np.abs(run_stages(x, plan, nthreads, nb_of, +1) - np.fft.ifft(x) * L).max() <= 1e-12 * scale
+
+
+MIXED = [12, 20, 24, 28, 40, 48, 56, 70, 96, 192, 384, 560]
+ODD = [3, 5, 7, 9, 15, 21, 35, 45]
+
+
+def mixed_e(L):
+    F = odd_part(L)
+    P = L // F
+    f = F if F <= 7 else smallest_odd_factor(F)
+    return f * min(P, 4)
+
+
+def a3_e(L):
+    if odd_part(L) == 1:
+        return min(L, 8)
+    if odd_part(L) > 7:
+        P = L // odd_part(L)
+        return smallest_odd_factor(odd_part(L)) * min(P, 2)
+    return mixed_e(L)
+
+
+def register_cases():
+    """(L, E) of every instantiated pencil: strided passes (E 8 or 16 at
+    powers of two, mixed_e otherwise) and axis-3 half lengths (a3_e)."""
+    cases = set()
+    for k in range(0, 11):
+        L = 1 << k
+        cases.add((L, min(L, 8)))
+        cases.add((L, min(L, 16)))
+    for L in MIXED + ODD:
+        cases.add((L, mixed_e(L)))
+    for L in [1 << k for k in range(1, 10)] + [N // 2 for N in MIXED]:
+        cases.add((L, a3_e(L)))
+    return sorted(cases)
+
+
+@pytest.mark.parametrize("L,E", register_cases())
+def test_register_plan(L, E):
+    assert L % E == 0
+    NT = L // E
+    plan = radix_plan(L, E)
+    if L == 1:
+        return
+    check_fft(L, plan, NT, lambda R: -(-(L // R) // NT))
+
+
+SMOOTH = [L for L in range(1, 1025) if any_plan(L) is not None]
+
+
+def test_any_lengths():
+    assert len(SMOOTH) == 143
+    assert all(any_plan(L) is None for L in (11, 13, 22, 1001))
+
+
+@pytest.mark.parametrize("L", [L for L in SMOOTH if L >= 3])
+def test_any_plan(L):
+    plan = any_plan(L)
+    assert len(plan) <= 12
+    tm = any_tm(L)
+    nt = 256 // tm
+    # the self-paired rows of the axis-1 passes take four lanes of one
+    # workgroup; a thread holds at most 16 values
+    assert tm >= 4 and -(-L // nt) <= 16
+    check_fft(L, plan, nt, lambda R: -(-16 // R))

@@ -184,8 +184,11 @@ def test_corrected_system_patched_in_place_matches_separate_build(precision):
     builds with the paper's P are turned into corrected ones in place
     (correction_patch: c, p = P_c^{-1} r where c acts, the start sums) instead
     of the correction pass plus a newton_init rebuild; against build_next = 0
-    the solve takes the same interior-point count and reaches the same
-    solution up to rounding (FP64: the same Krylov counts)."""
+    the solve reaches the same solution up to rounding.  FP64: the same
+    interior-point and Krylov counts.  FP32 (stopped at 1e-11, near its
+    floor, with the correction on every system): the two roundings agree on
+    the first Krylov counts and then drift, and the last system can exceed
+    its budget and fall back, so the interior-point counts may differ by one."""
     torch = need_gpu()
     from paper_2502_04217_amd import csipm
     w = wl.grid64(1)
@@ -210,10 +213,11 @@ def test_corrected_system_patched_in_place_matches_separate_build(precision):
         assert all(r["learned"] == 1 for r in log)
     (i1, cg1, b1, p1, s1, n1), (i0, cg0, b0, p0, s0, n0) = out[1], out[0]
     assert i1["status"] in (0, 3) and i0["status"] in (0, 3)
-    assert i1["ipm_iters"] == i0["ipm_iters"]
     if precision == 0:
+        assert i1["ipm_iters"] == i0["ipm_iters"]
         assert cg1 == cg0
     else:
+        assert abs(i1["ipm_iters"] - i0["ipm_iters"]) <= 1
         assert cg1[:8] == cg0[:8]
     assert p0 == 0 and s0 == i0["ipm_iters"]
     assert p1 > 0 and p1 + s1 == i1["ipm_iters"] and n1 < n0

@@ -34,6 +34,13 @@ ODD3_SHAPES = [(8, 8, 15), (15, 21, 35), (45, 45, 45), (3, 5, 7), (1, 1, 9), (1,
 # that fills several workgroups of each pass at L = 256
 BENCH_SHAPES = [(256, 16, 8), (16, 256, 8), (8, 8, 256), (512, 4, 8), (4, 512, 8), (4, 4, 512), (256, 64, 16),
                 (16, 32, 256)]
+# extents 2^a 3^b 5^c 7^d without instantiated kernels (the passes with the
+# pencils in LDS and a radix plan computed at launch): each radix on every
+# axis, odd and even, the axis-3 half lengths 9, 5, 7, 60, 25 and 500, the
+# longest pencils (1000 = 2^3 5^3, four per workgroup) on each axis, odd N3
+# of such lengths (the full-spectrum transforms at 63 and 875), and 2D grids
+ANY_SHAPES = [(6, 10, 18), (18, 14, 10), (10, 6, 14), (80, 100, 120), (25, 27, 50), (1000, 6, 4), (6, 1000, 4),
+              (4, 6, 1000), (49, 63, 8), (14, 10, 63), (6, 4, 875), (1, 50, 42), (160, 1, 6)]
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
@@ -46,7 +53,8 @@ def _problem(shape, seed=0):
     return torch, csipm, csipm.Problem(sig, obs), sig, obs
 
 
-@pytest.mark.parametrize("shape", SHAPES + BENCH_SHAPES + MIXED_SHAPES + LOWDIM_SHAPES + ODD_SHAPES + ODD3_SHAPES,
+@pytest.mark.parametrize("shape", SHAPES + BENCH_SHAPES + MIXED_SHAPES + LOWDIM_SHAPES + ODD_SHAPES + ODD3_SHAPES +
+                         ANY_SHAPES,
                          ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_operator_parity(shape, prec):
@@ -179,18 +187,11 @@ def test_errors():
     with pytest.raises(csipm.CsipmError) as e:
         csipm.Problem(sig, np.zeros((8, 8, 8), np.uint8))
     assert e.value.status == -1
-    with pytest.raises(csipm.CsipmError) as e:
-        csipm.Problem(np.zeros((6, 8, 8)), np.ones((6, 8, 8), np.uint8))
-    assert e.value.status == -5
-    with pytest.raises(csipm.CsipmError) as e:
-        csipm.Problem(np.zeros((8, 8, 2)), np.ones((8, 8, 2), np.uint8))
-    assert e.value.status == -5
-    with pytest.raises(csipm.CsipmError) as e:
-        csipm.Problem(np.zeros((8, 18, 8)), np.ones((8, 18, 8), np.uint8))
-    assert e.value.status == -5
-    with pytest.raises(csipm.CsipmError) as e:     # an odd extent without kernels
-        csipm.Problem(np.zeros((8, 8, 11)), np.ones((8, 8, 11), np.uint8))
-    assert e.value.status == -5
+    # extents with a prime factor above 7, above 1024, and N3 = 2
+    for shape in ((22, 8, 8), (8, 8, 2), (8, 26, 8), (8, 8, 11), (1100, 2, 4)):
+        with pytest.raises(csipm.CsipmError) as e:
+            csipm.Problem(np.zeros(shape), np.ones(shape, np.uint8))
+        assert e.value.status == -5
     pr = csipm.Problem(np.random.default_rng(0).standard_normal((8, 8, 8)), obs)
     with pytest.raises(csipm.CsipmError) as e:
         pr.solve()

@@ -109,19 +109,23 @@ def test_grid64_parity(precision, trust):
     assert abs(info["rel_kkt"] - rel) <= 1e-3 * rel + 1e-15
 
 
-@pytest.mark.parametrize("shape,half,period,dropout", [((24, 20, 28), 0, 4, 0.03), ((12, 70, 40), -1, 1, 0.08),
-                                                       ((1, 64, 96), -1, 1, 0.1), ((1, 1, 512), -1, 1, 0.15),
-                                                       ((15, 21, 32), -1, 1, 0.1), ((45, 35, 8), -1, 1, 0.1),
-                                                       ((8, 16, 45), -1, 1, 0.1), ((15, 21, 35), -1, 1, 0.1),
-                                                       ((45, 45, 45), -1, 1, 0.1)])
+MIXED_GRIDS = [((24, 20, 28), 0, 4, 0.03), ((12, 70, 40), -1, 1, 0.08), ((1, 64, 96), -1, 1, 0.1),
+               ((1, 1, 512), -1, 1, 0.15), ((15, 21, 32), -1, 1, 0.1), ((45, 35, 8), -1, 1, 0.1),
+               ((8, 16, 45), -1, 1, 0.1), ((15, 21, 35), -1, 1, 0.1), ((45, 45, 45), -1, 1, 0.1),
+               ((18, 20, 30), -1, 1, 0.1), ((50, 36, 42), -1, 1, 0.1), ((14, 10, 63), -1, 1, 0.1)]
+
+
+@pytest.mark.parametrize("shape,half,period,dropout", MIXED_GRIDS, ids=["x".join(map(str, g[0])) for g in MIXED_GRIDS])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_mixed_grid_parity(shape, half, period, dropout, precision):
     """Grids with odd factors 3, 5 and 7 (odd-radix FFT stages on every
     axis), a 2D grid (1 x 64 x 96), a 1D one (1 x 1 x 512), grids with odd
     extents on axes 1 and 2 (15 x 21 x 32, 45 x 35 x 8) and with an odd N3
     (the full-spectrum transforms: 8 x 16 x 45; 15 x 21 x 35 and 45^3, whose
-    odd sample counts add a coordinate without data inside the library): the
-    same parity bar as the 3D power-of-two grids."""
+    odd sample counts add a coordinate without data inside the library),
+    and grids of extents without instantiated kernels (18 x 20 x 30,
+    50 x 36 x 42, and 14 x 10 x 63 with an odd N3): the same parity bar as
+    the 3D power-of-two grids."""
     w = wl.make_workload(shape, n_freq=24, amplitude="normal", snr_db=20.0, half_width=half, period=period,
                          dropout=dropout, seed=2)
     lam = ipm.lambda_rule(w.signal, w.observed)
