@@ -8,10 +8,12 @@
 // computed at launch (radix 8, then one 4 or 2, for the power-of-two part;
 // 3, 5 and 7 for the odd part), so that one kernel serves every length.
 //
-// A 256-thread workgroup holds TM pencils (a power of two, TM L <= 4096
-// elements: at most 64 KB of FP64 tile) with NT = 256 / TM threads each, at
-// most 16 elements per thread.  A stage loads every butterfly of the thread
-// into registers, synchronises, and writes its outputs back in place.
+// A workgroup holds TM pencils (a power of two, TM L <= 4096 elements: at
+// most 64 KB of FP64 tile) with NT = threads / TM threads each (512 threads
+// of at most 8 elements in FP32, 256 of at most 16 in FP64), and the pencil
+// length's twiddle table.  A
+// stage loads every butterfly of the thread into registers, synchronises,
+// and writes its outputs back in place.
 #include "fft_kernels.h"
 
 #include <algorithm>
@@ -21,15 +23,20 @@ namespace fftk {
 
 namespace {
 
-constexpr int kAnyThreads = 256;
-constexpr int kAnyMaxE = 16;   // elements per thread at most
+// threads per workgroup and elements per thread at most (TM L <= 4096):
+// FP32 on 512 threads of at most 8 values, FP64 on 256 threads of at most
+// 16 (each the faster of the two shapes measured in its precision)
+template <typename T>
+constexpr int any_threads() { return sizeof(T) == 4 ? 512 : 256; }
+template <typename T>
+constexpr int any_max_e() { return 4096 / any_threads<T>(); }
 
 // Applies one radix-R stage (Ns: product of the earlier radices) to the
 // pencil at a (element e at a[e * es]), in place; thread t of nt.
 template <typename T, int R, int DIR>
 __device__ __forceinline__ void any_stage(cx<T>* a, int es, int L, int Ns, int t, int nt,
                                           const cx<T>* __restrict__ tw) {
-  constexpr int NB = (kAnyMaxE + R - 1) / R;
+  constexpr int NB = (any_max_e<T>() + R - 1) / R;
   const int nbf = L / R;
   const int step = L / (Ns * R);
   cx<T> v[NB][R];
@@ -86,19 +93,23 @@ __device__ __forceinline__ void any_fft(cx<T>* a, int es, const AnyPlan& pl, int
 // of the workgroup at element stride TM, then (axis 1) the partner rows of
 // the m = 0 lanes.
 template <typename T, int AX, int DIR, class Epi>
-__global__ void __launch_bounds__(kAnyThreads)
+__global__ void __launch_bounds__(any_threads<T>())
 k_axis12_any(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* __restrict__ tw, int m, Plane0 pl,
-             Epi epi, const int* skip, AnyPlan plan, int TM) {
+             Epi epi, const int* skip, AnyPlan plan, int TM, int rows) {
   if (skip && *skip) return;
   constexpr bool MIX = AX == 1;
   const int L = plan.L;
-  const int NT = kAnyThreads / TM;
+  const int NT = any_threads<T>() / TM;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tile = reinterpret_cast<cx<T>*>(smem_raw);
   const int p = threadIdx.x % TM;
   const int t = threadIdx.x / TM;
   const Lane12 ln = lane12<AX, DIR>(p, TM, geo, m, pl);
   cx<T>* a = tile + p;
+  // the twiddle table, after the tile and the partner rows (the stages read
+  // it after their first barrier)
+  cx<T>* twl = tile + (size_t)rows * L;
+  for (int i = threadIdx.x; i < L; i += any_threads<T>()) twl[i] = tw[i];
 
   bool upd = false;
   T be = T(0);
@@ -111,12 +122,12 @@ k_axis12_any(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* __re
   if constexpr (MIX) {
     cx<T>* stg = tile + TM * L;
     int slot;
-    if (stage_partners<T, DIR>(stg, src, L, TM, kAnyThreads, geo, m, pl, epi, upd, be, ln.ded, p, slot) > 0 &&
+    if (stage_partners<T, DIR>(stg, src, L, TM, any_threads<T>(), geo, m, pl, epi, upd, be, ln.ded, p, slot) > 0 &&
         ln.m0 && ln.active) {
       for (int e = t; e < L; e += NT) a[e * TM] = plane0_mix<T, DIR>(a[e * TM], stg[slot * L + e], e, ln, L, pl.n2);
     }
   }
-  any_fft<T, DIR>(a, TM, plan, t, NT, tw);
+  any_fft<T, DIR>(a, TM, plan, t, NT, twl);
 
   if constexpr (Epi::NRED > 0) {
     double acc[Epi::NRED];
@@ -128,7 +139,7 @@ k_axis12_any(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* __re
         if (plane0_keep<AX, DIR>(e, h, ln, L, pl.n2)) epi(ln.base + (long long)e * geo.estride, h, acc, MIX && ln.m0);
       }
     }
-    block_sums_store<kAnyThreads, Epi::NRED, Epi::NMAX>(acc, epi.partial, epi.pstride,
+    block_sums_store<any_threads<T>(), Epi::NRED, Epi::NMAX>(acc, epi.partial, epi.pstride,
                                                        reinterpret_cast<double*>(smem_raw));
   } else {
     if (ln.active) {
@@ -144,13 +155,13 @@ k_axis12_any(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* __re
 // pencils in LDS: pencil p at offset p (L + 1), element stride 1; the NT
 // threads of a pencil are consecutive lanes.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kAnyThreads)
+__global__ void __launch_bounds__(any_threads<T>())
 k_axis3_any(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask, const cx<T>* __restrict__ twm,
             const cx<T>* __restrict__ tw3, int npencils, T sc_c2r, T sc_r2c_dc, T sc_r2c, const int* skip,
             AnyPlan plan, int TM) {
   if (skip && *skip) return;
   const int L = plan.L;
-  const int NT = kAnyThreads / TM;
+  const int NT = any_threads<T>() / TM;
   const int N3 = 2 * L;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int p = threadIdx.x / NT;
@@ -159,24 +170,27 @@ k_axis3_any(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask, con
   const bool active = pen < npencils;
   const long long base = (long long)pen * L;
   cx<T>* a = reinterpret_cast<cx<T>*>(smem_raw) + p * (L + 1);
+  // the half-length transform's twiddles, after the tile
+  cx<T>* twl = reinterpret_cast<cx<T>*>(smem_raw) + (size_t)TM * (L + 1);
+  for (int i = threadIdx.x; i < L; i += any_threads<T>()) twl[i] = twm[i];
 
   for (int e = t; e < L; e += NT) a[e] = active ? src[base + e] : cx<T>{T(0), T(0)};
   if constexpr ((MODE & A3_C2R) != 0) {
     // Z_e needs X_e and X_{L-e}: all of X is read before any Z is written
-    cx<T> z[kAnyMaxE];
+    cx<T> z[any_max_e<T>()];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kAnyMaxE; ++i) {
+    for (int i = 0; i < any_max_e<T>(); ++i) {
       const int e = t + i * NT;
       if (e < L) z[i] = e == 0 ? c2r_dc(a[0]) : c2r_pack(a[e], a[L - e], tw3[e]);
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kAnyMaxE; ++i) {
+    for (int i = 0; i < any_max_e<T>(); ++i) {
       const int e = t + i * NT;
       if (e < L) a[e] = z[i];
     }
-    any_fft<T, +1>(a, 1, plan, t, NT, twm);
+    any_fft<T, +1>(a, 1, plan, t, NT, twl);
     for (int e = t; e < L; e += NT) {
       cx<T> v = cscale(a[e], sc_c2r);
       if constexpr (MODE == A3_FULL) {
@@ -191,7 +205,7 @@ k_axis3_any(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask, con
       return;
     }
   }
-  any_fft<T, -1>(a, 1, plan, t, NT, twm);
+  any_fft<T, -1>(a, 1, plan, t, NT, twl);
   if (!active) return;
   for (int e = t; e < L; e += NT)
     dst[base + e] = e == 0 ? r2c_dc(a[0], sc_r2c_dc) : r2c_unpack(a[e], a[L - e], tw3[e], sc_r2c);
@@ -215,8 +229,8 @@ bool any_plan(int L, AnyPlan& pl) {
   return r == 1;
 }
 
-int any_tm(int L) {
-  int tm = kAnyThreads;
+int any_tm(int w, int L) {
+  int tm = w == (int)sizeof(cx<float>) ? any_threads<float>() : any_threads<double>();
   while (tm > 1 && tm * L > 4096) tm >>= 1;
   return tm;
 }
@@ -226,17 +240,17 @@ bool launch_axis12_any(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGe
                        int n2, Epi epi, const int* skip, hipStream_t s) {
   AnyPlan plan;
   if (!any_plan(L, plan)) return false;
-  const int tm = any_tm(L);
+  const int tm = any_tm((int)sizeof(cx<T>), L);
   const Plane0 pl{n2, AX == 1 ? plane0_groups(DIR) : 0};
   // the tile, and on axis 1 the partner-row slots (at most 4 in the
   // first workgroup of the forward pass, (TM - 1) / m + 1 in a tile)
   const int rows = tm + (AX == 1 ? std::max(4, (tm - 1) / m + 1) : 0);
-  const size_t shm = (size_t)rows * L * sizeof(cx<T>);
+  const size_t shm = (size_t)(rows + 1) * L * sizeof(cx<T>);   // (and the twiddles)
   auto kern = k_axis12_any<T, AX, DIR, Epi>;
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL(kern, dim3(grid.x + pl.ndedicated), dim3(kAnyThreads), shm, s, src, dst, geo, tw, m, pl, epi,
-                     skip, plan, tm);
+  hipLaunchKernelGGL(kern, dim3(grid.x + pl.ndedicated), dim3(any_threads<T>()), shm, s, src, dst, geo, tw, m, pl, epi,
+                     skip, plan, tm, rows);
   return true;
 }
 
@@ -246,9 +260,14 @@ bool launch_axis3_any(int L, int mode, int np, const cx<T>* cs, cx<T>* cd, const
                       hipStream_t s) {
   AnyPlan plan;
   if (!any_plan(L, plan)) return false;
-  const int tm = any_tm(L);
-  const size_t shm = (size_t)tm * (L + 1) * sizeof(cx<T>);
-  const dim3 grid((np + tm - 1) / tm), block(kAnyThreads);
+  const int tm = any_tm((int)sizeof(cx<T>), L);
+  const size_t shm = ((size_t)tm * (L + 1) + L) * sizeof(cx<T>);   // (the tile and the twiddles)
+  const dim3 grid((np + tm - 1) / tm), block(any_threads<T>());
+  if (shm > 65536) {
+    (void)hipFuncSetAttribute((const void*)k_axis3_any<T, A3_FULL>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    (void)hipFuncSetAttribute((const void*)k_axis3_any<T, A3_C2R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    (void)hipFuncSetAttribute((const void*)k_axis3_any<T, A3_R2C>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  }
   if (mode == A3_FULL)
     hipLaunchKernelGGL((k_axis3_any<T, A3_FULL>), grid, block, shm, s, cs, cd, maskbits, twm, tw3, np, sc_c2r, sc_dc,
                        sc_ac, skip, plan, tm);

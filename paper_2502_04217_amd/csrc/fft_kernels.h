@@ -959,8 +959,8 @@ struct AnyPlan {
 };
 // false when L has a prime factor above 7 or lies outside [1, kAnyMaxLen]
 bool any_plan(int L, AnyPlan& pl);
-// pencils per 256-thread workgroup
-int any_tm(int L);
+// pencils per workgroup at complex size w
+int any_tm(int w, int L);
 template <typename T, int AX, int DIR, class Epi>
 bool launch_axis12_any(int L, dim3 grid, const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* tw, int m,
                        int n2, Epi epi, const int* skip, hipStream_t s);
@@ -970,7 +970,7 @@ bool launch_axis3_any(int L, int mode, int np, const cx<T>* cs, cx<T>* cd, const
                       hipStream_t s);
 // pencils per workgroup of the strided pass that serves length L
 inline int pass_tm(int w, int L, int axis, int dir) {
-  return templated12(L) ? strided_tm(w, L, axis, dir) : any_tm(L);
+  return templated12(L) ? strided_tm(w, L, axis, dir) : any_tm(w, L);
 }
 
 // The instances used: PREFIX is empty where they are compiled and `extern`

@@ -2,7 +2,8 @@
 (no GPU): for every length the register-resident kernels are instantiated
 at (csrc/fft_kernels.h: Radix<L, E> with the elements per thread of each
 pass) and every length 2^a 3^b 5^c 7^d up to 1024 of the LDS-resident passes
-(csrc/fft_any.hip: the plan computed at launch, TM pencils of NT threads),
+(csrc/fft_any.hip: the plan computed at launch, TM pencils of NT threads,
+in both precisions' workgroup shapes),
 the stages, run in numpy with the kernels' butterfly indexing, give numpy's
 FFT in both directions; each stage's butterflies are all taken by some
 thread, and its outputs write every element exactly once."""
@@ -64,8 +65,12 @@ def any_plan(L):
     return st if r == 1 else None
 
 
-def any_tm(L):
-    tm = 256
+# threads per workgroup of the LDS-resident passes: FP32 512, FP64 256
+ANY_THREADS = {"f32": 512, "f64": 256}
+
+
+def any_tm(threads, L):
+    tm = threads
     while tm > 1 and tm * L > 4096:
         tm //= 2
     return tm
@@ -167,13 +172,16 @@ def test_any_lengths():
     assert all(any_plan(L) is None for L in (11, 13, 22, 1001))
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("L", [L for L in SMOOTH if L >= 3])
-def test_any_plan(L):
+def test_any_plan(L, prec):
     plan = any_plan(L)
     assert len(plan) <= 12
-    tm = any_tm(L)
-    nt = 256 // tm
+    threads = ANY_THREADS[prec]
+    emax = 4096 // threads
+    tm = any_tm(threads, L)
+    nt = threads // tm
     # the self-paired rows of the axis-1 passes take four lanes of one
-    # workgroup; a thread holds at most 16 values
-    assert tm >= 4 and -(-L // nt) <= 16
-    check_fft(L, plan, nt, lambda R: -(-16 // R))
+    # workgroup; a thread holds at most emax values (8 in FP32, 16 in FP64)
+    assert tm >= 4 and -(-L // nt) <= emax
+    check_fft(L, plan, nt, lambda R: -(-emax // R))
