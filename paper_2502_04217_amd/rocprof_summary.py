@@ -16,7 +16,7 @@ import sys
 
 
 def short(name: str) -> str:
-    name = re.sub(r"csipm::\(anonymous namespace\)::", "", name)
+    name = re.sub(r"\(anonymous namespace\)::", "", name)
     name = re.sub(r"(csipm|fftk)::", "", name)
     m = re.match(r"(void )?([A-Za-z_0-9]+(<[^()]*>)?)", name)
     return m.group(2) if m else name[:80]
