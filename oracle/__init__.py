@@ -22,5 +22,5 @@ Modules
 Parity status: every function is pinned by a test in tests/test_oracle_*.py
 against a closed form, an invariant, an independent library routine or brute
 force, except the training outcome of the learned correction, which is parity
-unpinned (judged only by iteration counts at equal true KKT residual).
+unpinned (assessed only by iteration counts at equal true KKT residual).
 """
