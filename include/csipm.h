@@ -168,6 +168,16 @@ typedef struct {
                           launched directly.  Not used while kernel timing
                           or sample capture is on.  Same kernels and
                           arguments, so the same results. */
+  double pc_min_missing; /* learned correction: used only when at least this
+                          fraction of the samples is missing (default 0.01,
+                          the least in the training family of the shipped
+                          parameters: lattice period 32, cubes of half-width
+                          3, 1.05 %).  Below it the paper's P is nearly K
+                          itself and the network would act outside the range
+                          it was trained on, so the solve runs with the
+                          paper's P, exactly as CSIPM_PC_PLAIN.  0 = no limit.
+                          A policy capture (csipm_capture mode 2) follows the
+                          same rule. */
 } csipm_options;
 
 typedef struct {

@@ -38,7 +38,7 @@ class Options(C.Structure):
                 ("pc", C.c_int), ("refine_max", C.c_int), ("refine_inner_rtol", C.c_double),
                 ("refine_trust", C.c_double), ("pc_min_cg", C.c_int), ("krylov", C.c_int),
                 ("pc_rho", C.c_double), ("pc_max_relevant", C.c_double), ("mehrotra", C.c_int),
-                ("build_next", C.c_int), ("graphs", C.c_int)]
+                ("build_next", C.c_int), ("graphs", C.c_int), ("pc_min_missing", C.c_double)]
 
 
 class Info(C.Structure):

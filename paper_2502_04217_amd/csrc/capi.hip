@@ -629,6 +629,7 @@ void csipm_default_options(csipm_options* o) {
   o->mehrotra = 0;
   o->build_next = 1;
   o->graphs = 1;
+  o->pc_min_missing = 0.01;
 }
 
 size_t csipm_workspace_bytes(int n1, int n2, int n3) {
@@ -1002,7 +1003,8 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       (o.krylov != CSIPM_KRYLOV_CG && o.krylov != CSIPM_KRYLOV_CR && o.krylov != CSIPM_KRYLOV_CAR) || !(o.pc_rho >= 0.0) ||
       !(o.pc_max_relevant >= 0.0 && o.pc_max_relevant <= 1.0) || (o.mehrotra != 0 && o.mehrotra != 1) ||
       (o.build_next != 0 && o.build_next != 1) || (o.graphs != 0 && o.graphs != 1) ||
-      !(o.refine_trust >= 0.0 && o.refine_trust <= 1.0) || !(o.refine_inner_rtol > 0.0) || o.pc_min_cg < 0)
+      !(o.refine_trust >= 0.0 && o.refine_trust <= 1.0) || !(o.refine_inner_rtol > 0.0) || o.pc_min_cg < 0 ||
+      !(o.pc_min_missing >= 0.0 && o.pc_min_missing <= 1.0))
     return fail(c, CSIPM_EINVAL, "invalid options");
   if (o.pc == CSIPM_PC_LEARNED && !c->have_params) return fail(c, CSIPM_ESTATE, "learned preconditioner has no parameters");
   const auto t0 = std::chrono::steady_clock::now();
@@ -1012,11 +1014,15 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   c->cap_count = 0;
   c->cap_cg.clear();
   const double z0 = c->xi_inf > 0 ? c->xi_inf : 1.0;
-  const bool learned = o.pc == CSIPM_PC_LEARNED;
+  // the learned form acts only within the missing fractions its network
+  // was trained on; below pc_min_missing it is the paper's P throughout
+  const double missing = 1.0 - (double)c->nobs / (double)c->g.nr;
+  const bool in_domain = missing >= o.pc_min_missing;
+  const bool learned = o.pc == CSIPM_PC_LEARNED && in_domain;
   // the residual passes count the coefficients where the correction can act
   // (and sum the centring of its first feature) for the learned form and for
   // a capture that follows the correction's policy
-  const bool need_rel = learned || c->cap_enable == 2;
+  const bool need_rel = learned || (c->cap_enable == 2 && in_domain);
   // scaled identity: c = rho everywhere, rho = m/n unless given
   const float* pc_fixed = nullptr;
   if (o.pc == CSIPM_PC_SCALED) {
@@ -1120,7 +1126,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     // would apply the correction: see use_learned below)
     const bool capture = c->cap_enable && o.pc == CSIPM_PC_PLAIN && o.krylov == CSIPM_KRYLOV_CG &&
                          c->cap_count < c->cap_max &&
-                         (c->cap_enable != 2 || (prev_cg >= o.pc_min_cg && r.relevant >= 1.0 &&
+                         (c->cap_enable != 2 || (in_domain && prev_cg >= o.pc_min_cg && r.relevant >= 1.0 &&
                                                  r.relevant / (double)n <= o.pc_max_relevant));
     // the correction is applied once a Newton system has needed more than
     // pc_min_cg - 1 PCG iterations (a system the paper's P solves in one

@@ -122,10 +122,30 @@ def baseline_loss(feats, recs):
     return float(sum(csipm.mlp_loss_grad(p0, f, r, scratch)[0].item() for f, r in zip(feats, recs)))
 
 
-def evaluate(params, seeds, log=print):
+# evaluation workloads by grid: the 128^3 family (held-out seeds) and the
+# 256^3 and 512^3 recipes of the full-size runs (seeds 1, 2, ...; the network
+# never sees these grids in training)
+EVAL_FAMILIES = {
+    128: (wl.grid128_family, "the 128^3 family (sparsity log-uniform in [0.05 %, 0.5 %], SNR uniform in "
+                             "[5, 20] dB, lattice period in {8, 16, 32})"),
+    256: (wl.grid256, "the 256^3 recipe (0.1 % of the bins, N(0,1) exp(-|k|/32) parts, SNR 10 dB, cubes of "
+                      "half-width 3 on a period-32 lattice plus 2 % dropouts)"),
+    512: (wl.grid512, "the 512^3 recipe (0.02 % of the bins, N(0,1) parts, SNR 10 dB, cubes of half-width 4 on "
+                      "a period-64 lattice)"),
+}
+
+
+def eval_seeds(grid, count):
+    return list(EVAL_SEEDS)[:count] if grid == 128 else list(range(1, 1 + count))
+
+
+def evaluate(params, seeds, log=print, grid=128, **solve_kw):
+    """Each problem solved in the four forms; solve_kw adds solve options
+    (e.g. pc_min_missing) to every solve."""
     out = []
+    family = EVAL_FAMILIES[grid][0]
     for s in seeds:
-        w = wl.grid128_family(s)
+        w = family(s)
         pr = csipm.Problem(w.signal, w.observed)
         pr.lambda_rule(0.05)
         pr.set_pc_params(params)
@@ -134,9 +154,9 @@ def evaluate(params, seeds, log=print):
                               ("fp32_plain", csipm.FP32, csipm.PC_PLAIN), ("fp32_learned", csipm.FP32, csipm.PC_LEARNED)):
             # the first solve of a form on a context records its HIP graphs;
             # the time is the faster of the next two (the counts do not change)
-            pr.solve(tol=1e-6, precision=prec, pc=pc)
-            info = pr.solve(tol=1e-6, precision=prec, pc=pc)
-            again = pr.solve(tol=1e-6, precision=prec, pc=pc)
+            pr.solve(tol=1e-6, precision=prec, pc=pc, **solve_kw)
+            info = pr.solve(tol=1e-6, precision=prec, pc=pc, **solve_kw)
+            again = pr.solve(tol=1e-6, precision=prec, pc=pc, **solve_kw)
             info["solve_seconds"] = min(info["solve_seconds"], again["solve_seconds"])
             true = pr.residuals()
             row[tag] = {"cg": info["cg_iters_total"], "ipm": info["ipm_iters"], "s": info["solve_seconds"],
@@ -162,12 +182,13 @@ def summarize(rows):
     return s
 
 
-def markdown(rows, summ, command, params_note):
+def markdown(rows, summ, command, params_note, grid=128):
     """The per-seed evaluation as a markdown record."""
-    head = ["# Learned preconditioner correction on held-out 128^3 problems", "",
-            "Workload: the 128^3 family (sparsity log-uniform in [0.05 %, 0.5 %], SNR uniform in [5, 20] dB, "
-            "lattice period in {8, 16, 32}), seeds " + f"{rows[0]['seed']}-{rows[-1]['seed']}" + " (held out: "
-            "training uses seeds 0-199), lambda = 0.05 |M^T b|_inf, each solved to rel_kkt 1e-6 with the "
+    held = (" (held out: training uses seeds 0-199 of the 128^3 family)" if grid == 128 else
+            " (training sees only 128^3 problems)")
+    head = [f"# Learned preconditioner correction on held-out {grid}^3 problems", "",
+            "Workload: " + EVAL_FAMILIES[grid][1] + ", seeds " + f"{rows[0]['seed']}-{rows[-1]['seed']}" + held +
+            ", lambda = 0.05 |M^T b|_inf, each solved to rel_kkt 1e-6 with the "
             "paper's P and with the learned correction, in FP64 and in FP32 with FP64 refinement.", "",
             "Parameters: " + params_note, "", "Command:", "", "    " + command, "",
             "PCG: total PCG iterations of the solve; ms: solve wall time (the faster `solve_seconds` of the second "
@@ -212,15 +233,20 @@ def main():
     ap.add_argument("--md", help="also write the per-seed evaluation as markdown to this path")
     ap.add_argument("--periods", type=int, nargs="+", default=[8, 16, 32],
                     help="lattice periods of the training problems (the evaluation family keeps 8, 16, 32)")
+    ap.add_argument("--eval-grid", type=int, choices=sorted(EVAL_FAMILIES), default=128,
+                    help="evaluation workloads: the 128^3 family, or seeds 1.. of the 256^3 or 512^3 recipe")
+    ap.add_argument("--pc-min-missing", type=float, default=None,
+                    help="the solve option pc_min_missing in the evaluation (default: the library's, 0.01)")
     args = ap.parse_args()
     command = "python -m paper_2502_04217_amd.learn " + " ".join(sys.argv[1:])
+    solve_kw = {} if args.pc_min_missing is None else {"pc_min_missing": args.pc_min_missing}
     log = lambda *a: print(*a, flush=True)
     if args.eval_only:
         import torch
         with open(args.params_in) as f:
             stored = json.load(f)
         params = torch.tensor(stored["params"], dtype=torch.float32, device="cuda")
-        rows = evaluate(params, list(EVAL_SEEDS)[:args.eval], log=log)
+        rows = evaluate(params, eval_seeds(args.eval_grid, args.eval), log=log, grid=args.eval_grid, **solve_kw)
         summ = summarize(rows)
         log(json.dumps(summ))
         os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
@@ -231,7 +257,7 @@ def main():
                     f"`{stored.get('command', '?')}` (training loss {stored.get('loss_untrained', float('nan')):.4g} "
                     f"with c = 1, {stored.get('loss_trained', float('nan')):.4g} trained).")
             with open(args.md, "w") as f:
-                f.write(markdown(rows, summ, command, note))
+                f.write(markdown(rows, summ, command, note, grid=args.eval_grid))
         return 0
     t0 = time.time()
     feats, recs = collect(list(TRAIN_SEEDS)[:args.train], policy=not args.all_iterations,
@@ -247,7 +273,7 @@ def main():
                    "lr": args.lr, "loss_untrained": l0, "loss_trained": hist[-1],
                    "capture": "all iterations" if args.all_iterations else "policy", "periods": args.periods,
                    "record_groups": len(feats), "command": command}, f)
-    rows = evaluate(params, list(EVAL_SEEDS)[:args.eval], log=log)
+    rows = evaluate(params, eval_seeds(args.eval_grid, args.eval), log=log, grid=args.eval_grid, **solve_kw)
     summ = summarize(rows)
     log(json.dumps(summ))
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
@@ -257,7 +283,7 @@ def main():
         note = (f"trained by this command on {len(feats)} captured iterations (training loss {l0:.4g} with c = 1, "
                 f"{hist[-1]:.4g} trained).")
         with open(args.md, "w") as f:
-            f.write(markdown(rows, summ, command, note))
+            f.write(markdown(rows, summ, command, note, grid=args.eval_grid))
 
 
 if __name__ == "__main__":
