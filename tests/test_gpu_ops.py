@@ -41,6 +41,12 @@ BENCH_SHAPES = [(256, 16, 8), (16, 256, 8), (8, 8, 256), (512, 4, 8), (4, 512, 8
 # of such lengths (the full-spectrum transforms at 63 and 875), and 2D grids
 ANY_SHAPES = [(6, 10, 18), (18, 14, 10), (10, 6, 14), (80, 100, 120), (25, 27, 50), (1000, 6, 4), (6, 1000, 4),
               (4, 6, 1000), (49, 63, 8), (14, 10, 63), (6, 4, 875), (1, 50, 42), (160, 1, 6)]
+# 16 shapes drawn (numpy default_rng(20261203)) from the 7-smooth extents 3-64 on every axis: register-
+# and LDS-resident lengths mixed within one grid, odd N3 (the full-spectrum transforms) and even N3
+# with odd half lengths
+RANDOM_SHAPES = [(64, 50, 48), (32, 35, 9), (24, 18, 12), (28, 35, 4), (9, 3, 20), (60, 42, 27), (24, 36, 64),
+                 (27, 21, 14), (48, 21, 20), (12, 30, 45), (60, 25, 5), (4, 27, 36), (27, 5, 12), (60, 27, 4),
+                 (54, 18, 27), (48, 35, 28)]
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
@@ -54,7 +60,7 @@ def _problem(shape, seed=0):
 
 
 @pytest.mark.parametrize("shape", SHAPES + BENCH_SHAPES + MIXED_SHAPES + LOWDIM_SHAPES + ODD_SHAPES + ODD3_SHAPES +
-                         ANY_SHAPES,
+                         ANY_SHAPES + RANDOM_SHAPES,
                          ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_operator_parity(shape, prec):

@@ -112,7 +112,8 @@ def test_grid64_parity(precision, trust):
 MIXED_GRIDS = [((24, 20, 28), 0, 4, 0.03), ((12, 70, 40), -1, 1, 0.08), ((1, 64, 96), -1, 1, 0.1),
                ((1, 1, 512), -1, 1, 0.15), ((15, 21, 32), -1, 1, 0.1), ((45, 35, 8), -1, 1, 0.1),
                ((8, 16, 45), -1, 1, 0.1), ((15, 21, 35), -1, 1, 0.1), ((45, 45, 45), -1, 1, 0.1),
-               ((18, 20, 30), -1, 1, 0.1), ((50, 36, 42), -1, 1, 0.1), ((14, 10, 63), -1, 1, 0.1)]
+               ((18, 20, 30), -1, 1, 0.1), ((50, 36, 42), -1, 1, 0.1), ((14, 10, 63), -1, 1, 0.1),
+               ((27, 21, 14), -1, 1, 0.1), ((12, 30, 45), -1, 1, 0.1)]
 
 
 @pytest.mark.parametrize("shape,half,period,dropout", MIXED_GRIDS, ids=["x".join(map(str, g[0])) for g in MIXED_GRIDS])
@@ -124,8 +125,8 @@ def test_mixed_grid_parity(shape, half, period, dropout, precision):
     (the full-spectrum transforms: 8 x 16 x 45; 15 x 21 x 35 and 45^3, whose
     odd sample counts add a coordinate without data inside the library),
     and grids of extents without instantiated kernels (18 x 20 x 30,
-    50 x 36 x 42, and 14 x 10 x 63 with an odd N3): the same parity bar as
-    the 3D power-of-two grids."""
+    50 x 36 x 42, 27 x 21 x 14, and 14 x 10 x 63 and 12 x 30 x 45 with an odd
+    N3): the same parity bar as the 3D power-of-two grids."""
     w = wl.make_workload(shape, n_freq=24, amplitude="normal", snr_db=20.0, half_width=half, period=period,
                          dropout=dropout, seed=2)
     lam = ipm.lambda_rule(w.signal, w.observed)
