@@ -113,13 +113,19 @@ typedef struct {
                                PCG solve (default 1e-5); each inner solve aims at
                                half the remaining reduction, at most 1e-2     */
   double refine_trust; /* FP32: Newton systems whose tolerance min(cg_rtol,
-                          0.1 rel_kkt) is at least this (default 1e-5) take
+                          0.1 rel_kkt) is at least this (default 2e-6) take
                           the FP32 solution (inner tolerance half of it)
                           without an FP64 residual pass; the residual of the
                           iterate then carries FP32-level error until it is
                           recomputed in FP64, which happens before every
                           stopping test and before the first system below
-                          the threshold.  0 = always refine.               */
+                          the threshold.  The first time the solve would
+                          stall after such a step (a step that raised
+                          rel_kkt, or rel_kkt 10x above its best), the
+                          trust is revoked for the rest of the solve: the
+                          step is undone where a snapshot holds the iterate
+                          before it, and every later system is refined.
+                          0 = always refine.                              */
   int pc_min_cg;       /* learned correction: applied to a Newton system only
                           when the previous system took at least this many
                           PCG iterations (default 2; the first system and

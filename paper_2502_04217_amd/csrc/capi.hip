@@ -621,7 +621,7 @@ void csipm_default_options(csipm_options* o) {
   o->pc = CSIPM_PC_PLAIN;
   o->refine_max = 8;
   o->refine_inner_rtol = 1e-5;
-  o->refine_trust = 1e-5;
+  o->refine_trust = 2e-6;
   o->pc_min_cg = 2;
   o->krylov = CSIPM_KRYLOV_CG;
   o->pc_rho = 0.0;
@@ -1045,6 +1045,18 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
   double best_rel = INFINITY;
   bool have_snap = false;
   double snap_rel = INFINITY;
+  // FP32 steps taken without refinement (refine_trust) are revoked for the
+  // rest of the solve the first time the solve would stall after one: the
+  // step is undone (or the solve goes on from the current iterate) and every
+  // later Newton system is refined
+  int unrefined_steps = 0;
+  bool trust_revoked = false;
+  auto revoke_trust = [&]() {
+    if (trust_revoked || unrefined_steps == 0 || !(o.refine_trust > 0.0)) return false;
+    o.refine_trust = 0.0;
+    trust_revoked = true;
+    return true;
+  };
   csipm_info inf{};
   inf.lambda = lam;
   inf.xi_inf = c->xi_inf;
@@ -1080,19 +1092,26 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
       st = residuals(c, r, need_rel);
       if (st != CSIPM_OK) return st;
       rel = rel_of(r);
-      result = CSIPM_STALLED;
-      inf.rel_kkt = rel;
-      inf.res_beta_inf = r.fb;
-      inf.res_z_inf = r.fz;
-      inf.compl_max = r.cmax;
-      inf.mu = r.csum / (2.0 * (double)n);
-      break;
+      exact = true;
+      approx = false;
+      carried = 0;
+      carry_err = 0.0;
+      next_kind = NEXT_NONE;   // (built from the undone iterate)
+      if (!revoke_trust()) {
+        result = CSIPM_STALLED;
+        inf.rel_kkt = rel;
+        inf.res_beta_inf = r.fb;
+        inf.res_z_inf = r.fz;
+        inf.compl_max = r.cmax;
+        inf.mu = r.csum / (2.0 * (double)n);
+        break;
+      }
     }
     have_snap = false;
     if (r.nonfinite > 0 || !std::isfinite(r.fb)) return fail(c, CSIPM_ENONFINITE, "non-finite interior-point iterate");
     // past the precision floor the Newton steps stop reducing the residual
     // and start raising it: stop there rather than run into overflow
-    if (rel > kStallFactor * best_rel) {
+    if (rel > kStallFactor * best_rel && !revoke_trust()) {
       result = CSIPM_STALLED;
       inf.rel_kkt = rel;
       inf.res_beta_inf = r.fb;
@@ -1289,6 +1308,7 @@ csipm_status csipm_solve(csipm_ctx* c, const csipm_options* opts, csipm_info* in
     prev_rel = rel;
     exact = false;
     approx = approx || src == HD_RRES32;
+    if (src == HD_RRES32) ++unrefined_steps;
     if (src == HD_RRES64) carry_err += 2.0 * DBL_EPSILON * c->hscal[S_ALPHA_IPM] * r.dscale;
     ++carried;
     c->log.push_back(csipm_iter_log{it, cgi, ref, fell ? 1 : 0, use_learned ? 1 : 0, mu, rel, 0.0, relevant});

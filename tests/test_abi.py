@@ -67,5 +67,6 @@ def test_supported_extents_are_the_7_smooth_ones():
     o = csipm.default_options()
     assert o.tol == 1e-6 and o.sigma == 0.1 and o.tau == 0.99
     assert o.pc_min_missing == 0.01 and o.pc_min_cg == 2 and o.pc_max_relevant == 0.5
+    assert o.refine_trust == 2e-6
     assert csipm.lib().csipm_status_string(-5) == b"unsupported grid"
     assert csipm.lib().csipm_mlp_scratch_bytes(65) == 2 * 1250 * 8
