@@ -298,8 +298,8 @@ def test_trained_network_on_held_out_problems():
     """Held-out 128^3 problems (the first 8 of the 50 in
     profiles/learned_eval_128cubed.md): the trained correction reaches the
     same true KKT residual as the paper's preconditioner with no more PCG
-    iterations in either form (the 50-seed record: 0.984x in FP64, 0.963x in
-    FP32), and no slowdown beyond 10 % (the record: 1.02x and 1.01x the time;
+    iterations in either form (the 50-seed record: 0.984x in FP64, 0.970x in
+    FP32), and no slowdown beyond 10 % (the record: 1.025x and 1.020x the time;
     at 128^3 the inference on the last systems costs about what the saved
     iterations gain; at 256^3 it pays, test_trained_network_gains_at_256)."""
     torch = need_gpu()
@@ -323,7 +323,7 @@ def test_trained_network_gains_at_256():
     """Problems of the 256^3 recipe the network never saw (it trains on 128^3
     problems only; seeds 1-3 of the 8 in profiles/learned_eval_256cubed.md,
     whose totals are 0.938x (FP64) and 0.881x (FP32) the PCG iterations and
-    0.965x and 0.945x the time of the paper's preconditioner): on every seed
+    0.964x and 0.948x the time of the paper's preconditioner): on every seed
     and in both forms the trained correction takes fewer PCG iterations than
     the paper's P, reaches the same true KKT residual with no fallback, and the
     FP32 form, the chosen one, takes less time in total."""
