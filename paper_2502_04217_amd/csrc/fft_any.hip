@@ -152,63 +152,95 @@ k_axis12_any(const cx<T>* src, cx<T>* dst, StridedGeom<T> geo, const cx<T>* __re
 }
 
 // Axis-3 pass of k_axis3 (half length L = N3/2, contiguous pencils) with the
-// pencils in LDS: pencil p at offset p (L + 1), element stride 1; the NT
-// threads of a pencil are consecutive lanes.
+// pencils in LDS.  The transform work uses the strided passes' tile layout,
+// element e of pencil p at e (TM + 1) + p with the pencils in consecutive
+// lanes, on which every stage access is free of bank conflicts (a tile of
+// whole pencils conflicts on the strided Stockham writes); the workgroup's TM
+// pencils, one contiguous run of TM L values in memory, are loaded and stored
+// through the same tile with consecutive lanes on consecutive values.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(any_threads<T>())
 k_axis3_any(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask, const cx<T>* __restrict__ twm,
             const cx<T>* __restrict__ tw3, int npencils, T sc_c2r, T sc_r2c_dc, T sc_r2c, const int* skip,
             AnyPlan plan, int TM) {
   if (skip && *skip) return;
+  constexpr int NTHR = any_threads<T>();
+  constexpr int EM = any_max_e<T>();
   const int L = plan.L;
-  const int NT = any_threads<T>() / TM;
+  const int NT = NTHR / TM;
   const int N3 = 2 * L;
+  const int ES = TM + 1;   // element row stride
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int p = threadIdx.x / NT;
-  const int t = threadIdx.x % NT;
+  cx<T>* tile = reinterpret_cast<cx<T>*>(smem_raw);
+  const int p = threadIdx.x % TM;
+  const int t = threadIdx.x / TM;
   const int pen = blockIdx.x * TM + p;
   const bool active = pen < npencils;
-  const long long base = (long long)pen * L;
-  cx<T>* a = reinterpret_cast<cx<T>*>(smem_raw) + p * (L + 1);
+  cx<T>* a = tile + p;
   // the half-length transform's twiddles, after the tile
-  cx<T>* twl = reinterpret_cast<cx<T>*>(smem_raw) + (size_t)TM * (L + 1);
-  for (int i = threadIdx.x; i < L; i += any_threads<T>()) twl[i] = twm[i];
-
-  for (int e = t; e < L; e += NT) a[e] = active ? src[base + e] : cx<T>{T(0), T(0)};
+  cx<T>* twl = tile + (size_t)L * ES;
+  for (int i = threadIdx.x; i < L; i += NTHR) twl[i] = twm[i];
+  // the workgroup's pencils: values [run, run + nval) of the array
+  const long long run = (long long)blockIdx.x * TM * L;
+  const int nval = min(TM, npencils - (int)blockIdx.x * TM) * L;
+  for (int i = threadIdx.x; i < TM * L; i += NTHR) {
+    const int pp = i / L, e = i - pp * L;
+    tile[e * ES + pp] = i < nval ? src[run + i] : cx<T>{T(0), T(0)};
+  }
+  __syncthreads();
   if constexpr ((MODE & A3_C2R) != 0) {
     // Z_e needs X_e and X_{L-e}: all of X is read before any Z is written
-    cx<T> z[any_max_e<T>()];
-    __syncthreads();
+    cx<T> z[EM];
 #pragma unroll
-    for (int i = 0; i < any_max_e<T>(); ++i) {
+    for (int i = 0; i < EM; ++i) {
       const int e = t + i * NT;
-      if (e < L) z[i] = e == 0 ? c2r_dc(a[0]) : c2r_pack(a[e], a[L - e], tw3[e]);
+      if (e < L) z[i] = e == 0 ? c2r_dc(a[0]) : c2r_pack(a[e * ES], a[(L - e) * ES], tw3[e]);
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < any_max_e<T>(); ++i) {
+    for (int i = 0; i < EM; ++i) {
       const int e = t + i * NT;
-      if (e < L) a[e] = z[i];
+      if (e < L) a[e * ES] = z[i];
     }
-    any_fft<T, +1>(a, 1, plan, t, NT, twl);
+    any_fft<T, +1>(a, ES, plan, t, NT, twl);
     for (int e = t; e < L; e += NT) {
-      cx<T> v = cscale(a[e], sc_c2r);
+      cx<T> v = cscale(a[e * ES], sc_c2r);
       if constexpr (MODE == A3_FULL) {
         const long long bit = (long long)pen * N3 + 2 * e;
         v = mask_pair(v, active ? mask[bit >> 5] : 0u, (int)(bit & 31));
       }
-      a[e] = v;
+      a[e * ES] = v;
     }
     if constexpr (MODE == A3_C2R) {
-      if (active)
-        for (int e = t; e < L; e += NT) dst[base + e] = a[e];
+      __syncthreads();
+      for (int i = threadIdx.x; i < nval; i += NTHR) {
+        const int pp = i / L, e = i - pp * L;
+        dst[run + i] = tile[e * ES + pp];
+      }
       return;
     }
   }
-  any_fft<T, -1>(a, 1, plan, t, NT, twl);
-  if (!active) return;
-  for (int e = t; e < L; e += NT)
-    dst[base + e] = e == 0 ? r2c_dc(a[0], sc_r2c_dc) : r2c_unpack(a[e], a[L - e], tw3[e], sc_r2c);
+  any_fft<T, -1>(a, ES, plan, t, NT, twl);
+  {
+    // X_e needs Z_e and Z_{L-e}: all of Z is read before any X is written
+    cx<T> x[EM];
+#pragma unroll
+    for (int i = 0; i < EM; ++i) {
+      const int e = t + i * NT;
+      if (e < L) x[i] = e == 0 ? r2c_dc(a[0], sc_r2c_dc) : r2c_unpack(a[e * ES], a[(L - e) * ES], tw3[e], sc_r2c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < EM; ++i) {
+      const int e = t + i * NT;
+      if (e < L) a[e * ES] = x[i];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nval; i += NTHR) {
+    const int pp = i / L, e = i - pp * L;
+    dst[run + i] = tile[e * ES + pp];
+  }
 }
 
 }  // namespace
@@ -261,7 +293,7 @@ bool launch_axis3_any(int L, int mode, int np, const cx<T>* cs, cx<T>* cd, const
   AnyPlan plan;
   if (!any_plan(L, plan)) return false;
   const int tm = any_tm((int)sizeof(cx<T>), L);
-  const size_t shm = ((size_t)tm * (L + 1) + L) * sizeof(cx<T>);   // (the tile and the twiddles)
+  const size_t shm = ((size_t)L * (tm + 1) + L) * sizeof(cx<T>);   // (the tile and the twiddles)
   const dim3 grid((np + tm - 1) / tm), block(any_threads<T>());
   if (shm > 65536) {
     (void)hipFuncSetAttribute((const void*)k_axis3_any<T, A3_FULL>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
