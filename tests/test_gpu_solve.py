@@ -213,6 +213,32 @@ def test_precision_floor_stops_cleanly():
     assert rel2(beta, ref.state.beta) <= 1e-6
 
 
+def test_trusted_fp32_steps_revoked_instead_of_stalling():
+    """128^3 family seed 10002 with refine_trust = 1e-6: its unrefined FP32
+    steps stop making progress (before the revocation the solve ended STALLED
+    at rel_kkt 3.7e-4 with no system refined).  The trust is revoked, later
+    systems are refined, and the solve reaches rel_kkt 1e-6, the true residual
+    recomputed in FP64 included, at the solution of the always-refined solve."""
+    torch = need_gpu()
+    from paper_2502_04217_amd import csipm
+    w = wl.grid128_family(10002)
+    pr = csipm.Problem(w.signal, w.observed)
+    pr.lambda_rule(0.05)
+    ref = pr.solve(tol=1e-6, precision=1, refine_trust=0.0)
+    bref = pr.get(csipm.BETA).cpu().numpy()
+    info = pr.solve(tol=1e-6, precision=1, refine_trust=1e-6)
+    log = pr.log()
+    say("  trust 1e-6", info["status_name"], info["ipm_iters"], [r["refine_steps"] for r in log], "always refined",
+        ref["ipm_iters"])
+    assert info["status"] == 0 and info["rel_kkt"] <= 1e-6
+    assert pr.residuals()["rel_kkt"] <= 1e-6
+    # unrefined systems first, refined ones after the revocation
+    refined = [r["refine_steps"] > 0 for r in log]
+    assert not refined[0] and any(refined)
+    assert refined[refined.index(True):] == [True] * (len(refined) - refined.index(True))
+    assert rel2(pr.get(csipm.BETA).cpu().numpy(), bref) <= 1e-3
+
+
 def test_iteration_limit_status():
     w = wl.grid16(1)
     lam = ipm.lambda_rule(w.signal, w.observed)
