@@ -343,10 +343,14 @@ void launch_axis3(const Grid& g, int mode, const T* src, T* dst, const uint32_t*
                   const int* skip, hipStream_t s) {
   const int L = g.m;
   const int np = g.n1 * g.n2;
-  const double rn = 1.0 / std::sqrt((double)g.n);
-  const T sc_c2r = (T)rn;
-  const T sc_dc = (T)rn;
-  const T sc_ac = (T)(rn * std::sqrt(2.0));
+  // the packing helpers leave sqrt2 (inverse input) and 2 (forward output;
+  // DC and Nyquist 1) to these scales with the 1/sqrt(n) of each transform;
+  // a full pass carries the inverse's factors into its forward output
+  const double rn = 1.0 / std::sqrt((double)g.n), r2 = std::sqrt(2.0);
+  const bool full = mode == A3_FULL;
+  const T sc_c2r = (T)(rn / r2);
+  const T sc_dc = (T)(full ? rn * rn / r2 : rn);
+  const T sc_ac = (T)(full ? rn * rn / 2.0 : rn / r2);
   const cx<T>* cs = reinterpret_cast<const cx<T>*>(src);
   cx<T>* cd = reinterpret_cast<cx<T>*>(dst);
 #define CSIPM_A3(LL)                                                                                      \

@@ -204,12 +204,12 @@ k_axis3_any(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask, con
     }
     any_fft<T, +1>(a, ES, plan, t, NT, twl);
     for (int e = t; e < L; e += NT) {
-      cx<T> v = cscale(a[e * ES], sc_c2r);
       if constexpr (MODE == A3_FULL) {
         const long long bit = (long long)pen * N3 + 2 * e;
-        v = mask_pair(v, active ? mask[bit >> 5] : 0u, (int)(bit & 31));
+        a[e * ES] = mask_pair(a[e * ES], active ? mask[bit >> 5] : 0u, (int)(bit & 31));
+      } else {
+        a[e * ES] = cscale(a[e * ES], sc_c2r);
       }
-      a[e * ES] = v;
     }
     if constexpr (MODE == A3_C2R) {
       __syncthreads();

@@ -198,6 +198,7 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* tw) 
   constexpr int NT = RP::NT;
   constexpr int NB = RP::nb(S);
   constexpr bool EX = RP::exact(S);
+  cx<T> wt{T(1), T(0)};
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int j = t + i * NT;
@@ -216,10 +217,29 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* tw) 
             v[i * r + q] = cmul(v[i * r + q], wq);
           }
         } else {
-#pragma unroll
-          for (int q = 1; q < r; ++q) {
-            v[i * r + q] = cmul(v[i * r + q], twiddle<T>(tw, jm * q * (L / (Ns * r)), DIR));
+          // power-of-two radices: one table load per butterfly, the higher
+          // twiddles w^q as products of lower powers (w^2 = w w, w^3 = w w^2,
+          // w^4 = w^2 w^2, ...; depth log2 r).  Where every butterfly of the
+          // thread has jm = j = t + i NT (the stages with L / r <= Ns),
+          // w^(j TS) = w^(t TS) w^(i NT TS): one load per thread and a
+          // uniform factor (a scalar load) per further butterfly.  Loads of
+          // the table were the pencil passes' most frequent vector-memory
+          // instruction and held the most registers.
+          constexpr int TS = L / (Ns * r);
+          cx<T> wq[r];
+          if constexpr (NB > 1 && L / r <= Ns) {
+            if (i == 0) wt = twiddle<T>(tw, t * TS, DIR);
+            wq[1] = i == 0 ? wt : cmul(wt, twiddle<T>(tw, i * NT * TS, DIR));
+          } else {
+            wq[1] = twiddle<T>(tw, jm * TS, DIR);
           }
+#pragma unroll
+          for (int q = 2; q < r; ++q) {
+            const int hb = 1 << (31 - __builtin_clz(q));
+            wq[q] = q == hb ? cmul(wq[hb / 2], wq[hb / 2]) : cmul(wq[q - hb], wq[hb]);
+          }
+#pragma unroll
+          for (int q = 1; q < r; ++q) v[i * r + q] = cmul(v[i * r + q], wq[q]);
         }
       }
       dft_any<r, DIR, T>(&v[i * r]);
@@ -741,21 +761,26 @@ constexpr int a3_pp(int L) {
 
 // The real transforms of length N3 = 2L through a half-length complex FFT
 // (z_e = x[2e] + i x[2e+1]).  With the half spectrum X_e (e < L; X_0 packs
-// the DC and Nyquist values as (re, im)) and w = exp(-2 pi i e / N3):
-// the inverse transform's input Z_e = A + conj(B) + i w* (A - conj(B)) with
-// A = X_e / sqrt2, B = X_{L-e} / sqrt2, and Z_0 = (X_0.re + X_0.im,
-// X_0.re - X_0.im); the forward transform's output from its half-length
-// result Z: X_e = ((Z_e + conj Z_{L-e}) - i w (Z_e - conj Z_{L-e})) / 2,
-// X_0 = (Z_0.re + Z_0.im, Z_0.re - Z_0.im); each scaled.
+// the DC and Nyquist values as (re, im); the other coefficients carry the
+// sqrt2 of the real parametrisation) and w = exp(-2 pi i e / N3):
+// sqrt2 times the inverse transform's input is
+// Z_e = X_e + conj X_{L-e} + i w* (X_e - conj X_{L-e}), with
+// Z_0 = sqrt2 (X_0.re + X_0.im, X_0.re - X_0.im); from the forward half-length
+// result Y, twice the half spectrum (the DC and Nyquist values once) is
+// X_e = (Y_e + conj Y_{L-e}) - i w (Y_e - conj Y_{L-e}), with
+// X_0 = (Y_0.re + Y_0.im, Y_0.re - Y_0.im).  These factors and the 1/sqrt(n)
+// of each orthonormal transform are left to the one scale per output kind
+// that the launch passes: a pass running both transforms multiplies once.
 template <typename T>
-__device__ __forceinline__ cx<T> c2r_dc(cx<T> x0) { return {x0.re + x0.im, x0.re - x0.im}; }
+__device__ __forceinline__ cx<T> c2r_dc(cx<T> x0) {
+  const T s2 = T(1.41421356237309504880);
+  return {(x0.re + x0.im) * s2, (x0.re - x0.im) * s2};
+}
 template <typename T>
 __device__ __forceinline__ cx<T> c2r_pack(cx<T> xe, cx<T> xle, cx<T> w) {
-  const T rs2 = T(0.70710678118654752440);
-  const cx<T> a = cscale(xe, rs2);
-  const cx<T> b = cconj(cscale(xle, rs2));
-  const cx<T> sm = cadd(a, b);
-  const cx<T> d = csub(a, b);
+  const cx<T> b = cconj(xle);
+  const cx<T> sm = cadd(xe, b);
+  const cx<T> d = csub(xe, b);
   w.im = -w.im;   // exp(+2 pi i e / N3)
   return cadd(sm, cmul_i<1>(cmul(w, d)));
 }
@@ -764,9 +789,7 @@ __device__ __forceinline__ cx<T> r2c_dc(cx<T> z0, T sc) { return {(z0.re + z0.im
 template <typename T>
 __device__ __forceinline__ cx<T> r2c_unpack(cx<T> a, cx<T> zle, cx<T> w, T sc) {
   const cx<T> b = cconj(zle);
-  const cx<T> ev = cscale(cadd(a, b), T(0.5));
-  const cx<T> od = cscale(csub(a, b), T(0.5));
-  return cscale(cadd(ev, cmul_i<-1>(cmul(w, od))), sc);
+  return cscale(cadd(cadd(a, b), cmul_i<-1>(cmul(w, csub(a, b)))), sc);
 }
 // z = (x[2e], x[2e+1]) with the unobserved samples zeroed: bits sh and
 // sh + 1 of the mask word wd (the flat bit index of x[2e] is even, so both
@@ -812,18 +835,24 @@ k_axis3(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask,
       lds[lidx(e)] = active ? src[base + e] : cx<T>{T(0), T(0)};
     }
     __syncthreads();
+    // exp(-2 pi i e / N3) for e = t + k, k fixed by the unrolled slot:
+    // tw3[t] (one load) times the uniform tw3[k] (a scalar load)
+    const cx<T> w3t = tw3[t];
     for_stage_io<L, E, 0>(t, [&](int s, int e) {
-      v[s] = e == 0 ? c2r_dc(lds[lidx(0)]) : c2r_pack(lds[lidx(e)], lds[lidx(L - e)], tw3[e]);
+      const int k = e - t;
+      v[s] = e == 0 ? c2r_dc(lds[lidx(0)])
+                    : c2r_pack(lds[lidx(e)], lds[lidx(L - e)], k == 0 ? w3t : cmul(w3t, tw3[k]));
     });
     fft_stages<T, L, E, +1, 0>(v, t, lds, lidx, twm);
     // z_e = x[2e] + i x[2e+1]
+    // (a full pass leaves the inverse's scale to the forward output)
     for_stage_io<L, E, SL>(t, [&](int s, int e) {
-      cx<T> z = cscale(v[s], sc_c2r);
       if constexpr (MODE == A3_FULL) {
         const long long bit = (long long)pen * N3 + 2 * e;
-        z = mask_pair(z, active ? mask[bit >> 5] : 0u, (int)(bit & 31));
+        v[s] = mask_pair(v[s], active ? mask[bit >> 5] : 0u, (int)(bit & 31));
+      } else {
+        v[s] = cscale(v[s], sc_c2r);
       }
-      v[s] = z;
     });
     if constexpr (MODE == A3_C2R) {
       if (active) for_stage_io<L, E, SL>(t, [&](int s, int e) { dst[base + e] = v[s]; });
@@ -851,11 +880,12 @@ k_axis3(const cx<T>* src, cx<T>* dst, const uint32_t* __restrict__ mask,
   for_stage_io<L, E, SL>(tf, [&](int s, int e) { lds[lidx(e)] = v[s]; });
   __syncthreads();
   if (!active) return;
-#pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const int e = tf + q * NT;
-    dst[base + e] = e == 0 ? r2c_dc(lds[lidx(0)], sc_r2c_dc) : r2c_unpack(lds[lidx(e)], lds[lidx(L - e)], tw3[e], sc_r2c);
-  }
+  const cx<T> w3f = tw3[tf];
+  for_stage_io<L, E, 0>(tf, [&](int s, int e) {
+    const int k = e - tf;
+    dst[base + e] = e == 0 ? r2c_dc(lds[lidx(0)], sc_r2c_dc)
+                           : r2c_unpack(lds[lidx(e)], lds[lidx(L - e)], k == 0 ? w3f : cmul(w3f, tw3[k]), sc_r2c);
+  });
 }
 
 template <typename T, int L>
