@@ -6,7 +6,11 @@ pass) and every length 2^a 3^b 5^c 7^d up to 1024 of the LDS-resident passes
 in both precisions' workgroup shapes),
 the stages, run in numpy with the kernels' butterfly indexing, give numpy's
 FFT in both directions; each stage's butterflies are all taken by some
-thread, and its outputs write every element exactly once."""
+thread, and its outputs write every element exactly once.  The twiddles of
+the power-of-two stages, formed from one table entry per butterfly (or one
+per thread times a uniform entry) by products, equal the table's powers, and
+every index read stays in the table; the axis-3 packing twiddle of element
+t + k is the product of the entries t and k with k below L."""
 import numpy as np
 import pytest
 
@@ -185,3 +189,96 @@ def test_any_plan(L, prec):
     # workgroup; a thread holds at most emax values (8 in FP32, 16 in FP64)
     assert tm >= 4 and -(-L // nt) <= emax
     check_fft(L, plan, nt, lambda R: -(-emax // R))
+
+
+def product_twiddles(w1, r):
+    """w^q for q < r from w^1 by the kernels' product tree: w^q = (w^(q/2))^2
+    for q a power of two, else w^(q - hb) w^hb (hb the highest power of two
+    below q)."""
+    wq = [1.0 + 0j, w1]
+    for q in range(2, r):
+        hb = 1 << (q.bit_length() - 1)
+        wq.append(wq[hb // 2] * wq[hb // 2] if q == hb else wq[q - hb] * wq[hb])
+    return wq
+
+
+def kernel_stage_twiddles(L, E, stage_radices, s, t, i, NT, direction):
+    """The twiddles w^(jm q TS) of butterfly j = t + i NT of stage s, formed as
+    the power-of-two stages form them: the table entry of jm TS, or, where
+    every butterfly of the thread has jm = j (L / r <= Ns and several
+    butterflies per thread), the entry of t TS times the uniform entry of
+    i NT TS; then the product tree.  Returns (powers, table indices read)."""
+    r = stage_radices[s]
+    ns = int(np.prod(stage_radices[:s]))
+    TS = L // (ns * r)
+    NB = -(-(L // r) // NT)
+    tab = np.exp(-2j * np.pi * np.arange(L) / L)
+    if direction > 0:
+        tab = tab.conj()
+    j = t + i * NT
+    if NB > 1 and L // r <= ns:
+        idx = [t * TS, i * NT * TS]
+        w1 = tab[idx[0]] * (tab[idx[1]] if i else 1.0)
+    else:
+        idx = [(j % ns) * TS]
+        w1 = tab[idx[0]]
+    return product_twiddles(w1, r), idx
+
+
+@pytest.mark.parametrize("L,E", [c for c in register_cases() if odd_part(c[0]) == 1 and c[0] >= 4])
+def test_product_twiddles_match_table(L, E):
+    """Every power-of-two pencil the register-resident kernels instantiate:
+    the stages whose thread shares one table load have table stride 1, every
+    index read stays inside the length-L table, and the product-formed
+    twiddles equal w^(jm q TS) to rounding."""
+    plan = radix_plan(L, E)
+    NT = L // E
+    for s, r in enumerate(plan):
+        ns = int(np.prod(plan[:s]))
+        if ns == 1:
+            continue
+        TS = L // (ns * r)
+        NB = -(-(L // r) // NT)
+        if NB > 1 and L // r <= ns:
+            assert TS == 1
+        for direction in (-1, 1):
+            for t in range(NT):
+                for i in range(NB):
+                    j = t + i * NT
+                    if j >= L // r:
+                        continue
+                    wq, idx = kernel_stage_twiddles(L, E, plan, s, t, i, NT, direction)
+                    assert all(0 <= x < L for x in idx)
+                    jm = j % ns
+                    want = np.exp(direction * 2j * np.pi * jm * TS * np.arange(r) / L)
+                    assert np.abs(np.array(wq) - want).max() < 1e-13
+
+
+@pytest.mark.parametrize("L", [1 << k for k in range(1, 10)] + [N // 2 for N in MIXED])
+def test_packing_twiddle_offsets(L):
+    """The c2r/r2c packing twiddle exp(-2 pi i e / N3) of element e = t + k
+    of the first-stage pattern is tw3[t] tw3[k]: k = e - t is fixed by the
+    unrolled slot (the same for every thread) and stays below L, the table's
+    first L entries."""
+    E = a3_e(L)
+    NT = L // E
+    plan = radix_plan(L, E)
+    r0 = plan[0]
+    N3 = 2 * L
+    offsets = None
+    for t in range(NT):
+        ks = []
+        for i in range(-(-(L // r0) // NT)):
+            j = t + i * NT
+            if j >= L // r0:
+                continue
+            for q in range(r0):
+                e = j + q * (L // r0)
+                k = e - t
+                assert 0 <= k < L
+                assert abs(np.exp(-2j * np.pi * t / N3) * np.exp(-2j * np.pi * k / N3) - np.exp(-2j * np.pi * e / N3)) < 1e-14
+                ks.append((i, q, k))
+        if offsets is None:
+            offsets = ks
+        elif len(ks) == len(offsets):
+            assert ks == offsets
