@@ -198,46 +198,48 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* tw) 
   constexpr int NT = RP::NT;
   constexpr int NB = RP::nb(S);
   constexpr bool EX = RP::exact(S);
+  // Twiddles w^(jm q TS), jm = j mod Ns, of butterfly j = t + i NT: one
+  // table load per butterfly, the higher powers w^q as products of lower
+  // ones (w^2 = w w, w^3 = w w^2, w^4 = w^2 w^2, ...; depth log2 r).  Where
+  // NT is a multiple of Ns every butterfly of the thread has jm = t mod Ns,
+  // and one set serves them all; where L / r <= Ns every one has jm = j, and
+  // w^(j TS) = w^(t TS) w^(i NT TS): one load per thread and a uniform factor
+  // (a scalar load) per further butterfly.  Table loads were the pencil
+  // passes' most frequent vector-memory instruction and held the most
+  // registers.
+  constexpr int TS = L / (Ns * r);
+  constexpr bool SHARED = Ns > 1 && NB > 1 && NT % Ns == 0;
+  constexpr bool LASTJ = Ns > 1 && NB > 1 && !SHARED && L / r <= Ns;
+  auto powers = [](cx<T>* wq) {
+#pragma unroll
+    for (int q = 2; q < r; ++q) {
+      const int hb = 1 << (31 - __builtin_clz(q));
+      wq[q] = q == hb ? cmul(wq[hb / 2], wq[hb / 2]) : cmul(wq[q - hb], wq[hb]);
+    }
+  };
+  cx<T> ws[SHARED ? r : 1];
+  if constexpr (SHARED) {
+    ws[1] = twiddle<T>(tw, (t % Ns) * TS, DIR);
+    powers(ws);
+  }
   cx<T> wt{T(1), T(0)};
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int j = t + i * NT;
     if (EX || j < L / r) {
       if constexpr (Ns > 1) {
-        const int jm = j % Ns;
-        if constexpr (odd_part(L) > 1) {
-          // lengths with odd factors: one table load per butterfly, the
-          // higher twiddles w^q as powers of w (at most 6 products)
-          const cx<T> w1 = twiddle<T>(tw, jm * (L / (Ns * r)), DIR);
-          cx<T> wq = w1;
-          v[i * r + 1] = cmul(v[i * r + 1], w1);
+        if constexpr (SHARED) {
 #pragma unroll
-          for (int q = 2; q < r; ++q) {
-            wq = cmul(wq, w1);
-            v[i * r + q] = cmul(v[i * r + q], wq);
-          }
+          for (int q = 1; q < r; ++q) v[i * r + q] = cmul(v[i * r + q], ws[q]);
         } else {
-          // power-of-two radices: one table load per butterfly, the higher
-          // twiddles w^q as products of lower powers (w^2 = w w, w^3 = w w^2,
-          // w^4 = w^2 w^2, ...; depth log2 r).  Where every butterfly of the
-          // thread has jm = j = t + i NT (the stages with L / r <= Ns),
-          // w^(j TS) = w^(t TS) w^(i NT TS): one load per thread and a
-          // uniform factor (a scalar load) per further butterfly.  Loads of
-          // the table were the pencil passes' most frequent vector-memory
-          // instruction and held the most registers.
-          constexpr int TS = L / (Ns * r);
           cx<T> wq[r];
-          if constexpr (NB > 1 && L / r <= Ns) {
+          if constexpr (LASTJ) {
             if (i == 0) wt = twiddle<T>(tw, t * TS, DIR);
             wq[1] = i == 0 ? wt : cmul(wt, twiddle<T>(tw, i * NT * TS, DIR));
           } else {
-            wq[1] = twiddle<T>(tw, jm * TS, DIR);
+            wq[1] = twiddle<T>(tw, (j % Ns) * TS, DIR);
           }
-#pragma unroll
-          for (int q = 2; q < r; ++q) {
-            const int hb = 1 << (31 - __builtin_clz(q));
-            wq[q] = q == hb ? cmul(wq[hb / 2], wq[hb / 2]) : cmul(wq[q - hb], wq[hb]);
-          }
+          powers(wq);
 #pragma unroll
           for (int q = 1; q < r; ++q) v[i * r + q] = cmul(v[i * r + q], wq[q]);
         }

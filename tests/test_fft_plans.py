@@ -6,10 +6,10 @@ pass) and every length 2^a 3^b 5^c 7^d up to 1024 of the LDS-resident passes
 in both precisions' workgroup shapes),
 the stages, run in numpy with the kernels' butterfly indexing, give numpy's
 FFT in both directions; each stage's butterflies are all taken by some
-thread, and its outputs write every element exactly once.  The twiddles of
-the power-of-two stages, formed from one table entry per butterfly (or one
-per thread times a uniform entry) by products, equal the table's powers, and
-every index read stays in the table; the axis-3 packing twiddle of element
+thread, and its outputs write every element exactly once.  The stage
+twiddles, formed from one table entry per butterfly (one per thread where
+its butterflies share it, or one per thread times a uniform entry) by
+products, equal the table's powers, and every index read stays in the table; the axis-3 packing twiddle of element
 t + k is the product of the entries t and k with k below L."""
 import numpy as np
 import pytest
@@ -202,12 +202,13 @@ def product_twiddles(w1, r):
     return wq
 
 
-def kernel_stage_twiddles(L, E, stage_radices, s, t, i, NT, direction):
-    """The twiddles w^(jm q TS) of butterfly j = t + i NT of stage s, formed as
-    the power-of-two stages form them: the table entry of jm TS, or, where
-    every butterfly of the thread has jm = j (L / r <= Ns and several
-    butterflies per thread), the entry of t TS times the uniform entry of
-    i NT TS; then the product tree.  Returns (powers, table indices read)."""
+def kernel_stage_twiddles(L, stage_radices, s, t, i, NT, direction):
+    """The twiddles w^(jm q TS) of butterfly j = t + i NT of stage s as the
+    kernels form them: where NT is a multiple of Ns (several butterflies per
+    thread) the entry of (t mod Ns) TS, shared by the thread's butterflies;
+    else, where every butterfly of the thread has jm = j (L / r <= Ns), the
+    entry of t TS times the uniform entry of i NT TS; else the entry of
+    jm TS; then the product tree.  Returns (powers, table indices read)."""
     r = stage_radices[s]
     ns = int(np.prod(stage_radices[:s]))
     TS = L // (ns * r)
@@ -216,7 +217,10 @@ def kernel_stage_twiddles(L, E, stage_radices, s, t, i, NT, direction):
     if direction > 0:
         tab = tab.conj()
     j = t + i * NT
-    if NB > 1 and L // r <= ns:
+    if NB > 1 and NT % ns == 0:
+        idx = [(t % ns) * TS]
+        w1 = tab[idx[0]]
+    elif NB > 1 and L // r <= ns:
         idx = [t * TS, i * NT * TS]
         w1 = tab[idx[0]] * (tab[idx[1]] if i else 1.0)
     else:
@@ -225,12 +229,13 @@ def kernel_stage_twiddles(L, E, stage_radices, s, t, i, NT, direction):
     return product_twiddles(w1, r), idx
 
 
-@pytest.mark.parametrize("L,E", [c for c in register_cases() if odd_part(c[0]) == 1 and c[0] >= 4])
+@pytest.mark.parametrize("L,E", [c for c in register_cases() if c[0] >= 3])
 def test_product_twiddles_match_table(L, E):
-    """Every power-of-two pencil the register-resident kernels instantiate:
-    the stages whose thread shares one table load have table stride 1, every
-    index read stays inside the length-L table, and the product-formed
-    twiddles equal w^(jm q TS) to rounding."""
+    """Every pencil the register-resident kernels instantiate: in the stages
+    whose thread shares one load (by jm = t mod Ns or by jm = j), the shared
+    index is the butterfly's own up to the uniform factor, every index read
+    stays inside the length-L table, and the product-formed twiddles equal
+    w^(jm q TS) to rounding."""
     plan = radix_plan(L, E)
     NT = L // E
     for s, r in enumerate(plan):
@@ -239,7 +244,7 @@ def test_product_twiddles_match_table(L, E):
             continue
         TS = L // (ns * r)
         NB = -(-(L // r) // NT)
-        if NB > 1 and L // r <= ns:
+        if NB > 1 and NT % ns != 0 and L // r <= ns:
             assert TS == 1
         for direction in (-1, 1):
             for t in range(NT):
@@ -247,7 +252,7 @@ def test_product_twiddles_match_table(L, E):
                     j = t + i * NT
                     if j >= L // r:
                         continue
-                    wq, idx = kernel_stage_twiddles(L, E, plan, s, t, i, NT, direction)
+                    wq, idx = kernel_stage_twiddles(L, plan, s, t, i, NT, direction)
                     assert all(0 <= x < L for x in idx)
                     jm = j % ns
                     want = np.exp(direction * 2j * np.pi * jm * TS * np.arange(r) / L)
