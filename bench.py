@@ -260,7 +260,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is single-device "
-              f"and this build has no multi-GPU path", file=sys.stderr)
+              f"and the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
