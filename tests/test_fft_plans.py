@@ -10,7 +10,9 @@ thread, and its outputs write every element exactly once.  The stage
 twiddles, formed from one table entry per butterfly (one per thread where
 its butterflies share it, or one per thread times a uniform entry) by
 products, equal the table's powers, and every index read stays in the table; the axis-3 packing twiddle of element
-t + k is the product of the entries t and k with k below L."""
+t + k is the product of the entries t and k with k below L.  The axis-3
+packing algebra and the scale the launch passes per mode reproduce numpy's
+orthonormal rfft/irfft."""
 import numpy as np
 import pytest
 
@@ -287,3 +289,60 @@ def test_packing_twiddle_offsets(L):
             offsets = ks
         elif len(ks) == len(offsets):
             assert ks == offsets
+
+
+def _axis3_model(X, L, mode, mask=None):
+    """The axis-3 pass of one pencil as the kernels compute it, in numpy:
+    the unscaled packing (sqrt2 times the inverse input; twice the half
+    spectrum, DC and Nyquist once) and the one scale per output kind that the
+    launch passes for each mode (n = N3 here: a single pencil)."""
+    N3 = 2 * L
+    rn, r2 = 1.0 / np.sqrt(N3), np.sqrt(2.0)
+    w = np.exp(-2j * np.pi * np.arange(L) / N3)
+    if mode == "r2c":
+        z = X
+    else:
+        Z = np.empty(L, complex)
+        Z[0] = r2 * complex(X[0].real + X[0].imag, X[0].real - X[0].imag)
+        e = np.arange(1, L)
+        a, b = X[e], np.conj(X[L - e])
+        Z[e] = (a + b) + 1j * np.conj(w[e]) * (a - b)
+        z = np.fft.ifft(Z) * L                       # unnormalised inverse
+        if mode == "c2r":
+            return z * (rn / r2)
+        z = z.real * mask[0::2] + 1j * z.imag * mask[1::2]
+    full = mode == "full"
+    sc_dc = rn * rn / r2 if full else rn
+    sc_ac = rn * rn / 2 if full else rn / r2
+    Y = np.fft.fft(z)                                # unnormalised forward
+    out = np.empty(L, complex)
+    out[0] = sc_dc * complex(Y[0].real + Y[0].imag, Y[0].real - Y[0].imag)
+    e = np.arange(1, L)
+    a, b = Y[e], np.conj(Y[L - e])
+    out[e] = sc_ac * ((a + b) - 1j * w[e] * (a - b))
+    return out
+
+
+@pytest.mark.parametrize("L", [2, 4, 8, 12, 64, 128, 280])
+def test_axis3_packing_and_scales(L):
+    """Against numpy's orthonormal rfft/irfft of a length-2L pencil, with the
+    half spectrum in the kernels' layout (slot 0 = (DC, Nyquist), the other
+    coefficients times sqrt2): the c2r and r2c modes with their scales are
+    the orthonormal transforms, and the full pass (no scale between its two
+    transforms) equals r2c(mask(c2r(.)))."""
+    N3 = 2 * L
+    rng = np.random.default_rng(L)
+    x = rng.standard_normal(N3)
+    F = np.fft.rfft(x, norm="ortho")                 # F_0 .. F_L
+    X = np.sqrt(2.0) * F[:L].copy()
+    X[0] = complex(F[0].real, F[L].real)
+    z = _axis3_model(X, L, "c2r")
+    assert np.abs(np.concatenate([[v.real, v.imag] for v in z]) - x).max() < 1e-12
+    pairs = x[0::2] + 1j * x[1::2]
+    assert np.abs(_axis3_model(pairs, L, "r2c") - X).max() < 1e-12
+    mask = (rng.random(N3) < 0.7).astype(float)
+    xm = np.fft.irfft(F, n=N3, norm="ortho") * mask
+    Fm = np.fft.rfft(xm, norm="ortho")
+    Xm = np.sqrt(2.0) * Fm[:L].copy()
+    Xm[0] = complex(Fm[0].real, Fm[L].real)
+    assert np.abs(_axis3_model(X, L, "full", mask) - Xm).max() < 1e-12
